@@ -1,0 +1,158 @@
+"""FP64 oracle of 3DGS registration as keyframe localisation (paper Sec. 3.2).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+Readings (the paper leaves these open):
+  R18 optimiser: Adam with beta1 = 0.9, beta2 = 0.999, eps = 1e-8 and bias
+      correction; the rotation (unnormalised quaternion) and the translation
+      get their own learning rates (supplement, loop-closure hyper-parameter
+      table: 0.003 / 0.001 synthetic-like, 0.015 / 0.005 real-like)
+  R19 iteration count: a parameter (200 in the single-pair workload)
+  R20 residual eps_i: the L1 loss at the final pose, from one extra forward
+  R21 weight 1 / max(eps_i, 1e-12)
+  R22 translation: weighted mean of the P->Q translations, the Q->P
+      estimates inverted first
+
+Per-view problem (Sec. 3.2, keyframe localisation).  For keyframe i of P with
+camera-to-world pose T_i (in P's frame) and measurements (I, D)_i, the
+submap Q is rendered with world-to-camera Delta o T_i^-1 and Delta (starting
+at identity) is optimised with Q held fixed.  The keyframe's pose in Q is
+T_i^q = T_i Delta^-1, so the estimate of T_{P->Q} = T_i^q T_i^-1 is
+E_i = T_i Delta^-1 T_i^-1.  Keyframes of Q rendering P give estimates of
+T_{Q->P} the same way.
+
+Fusion (Eq. 7): R_bar = argmin_R sum_i w_i ||R - R~_i||_F^2 with R~_i = R_i
+for P->Q estimates and R_i^-1 for Q->P ones.  Its closed form is the
+projection of M = sum_i w_i R~_i onto SO(3): M = U S V^T,
+R_bar = U diag(1, 1, det(U V^T)) V^T.
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import raster
+
+F64 = torch.float64
+
+
+def adam_step(param, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update in place on float64 tensors; `step` counts from 1."""
+    with torch.no_grad():
+        m.mul_(beta1).add_((1 - beta1) * grad)
+        v.mul_(beta2).add_((1 - beta2) * grad * grad)
+        m_hat = m / (1 - beta1 ** step)
+        v_hat = v / (1 - beta2 ** step)
+        param.sub_(lr * m_hat / (torch.sqrt(v_hat) + eps))
+
+
+def pose_matrix(pose7) -> np.ndarray:
+    """4x4 rigid transform of a pose 7-vector (q_w, q_x, q_y, q_z, t)."""
+    p = torch.as_tensor(np.asarray(pose7, np.float64))
+    out = np.eye(4)
+    out[:3, :3] = raster.quat_to_rotmat(p[:4]).numpy()
+    out[:3, 3] = p[4:7].numpy()
+    return out
+
+
+def inv_rigid(t: np.ndarray) -> np.ndarray:
+    out = np.eye(4)
+    out[:3, :3] = t[:3, :3].T
+    out[:3, 3] = -t[:3, :3].T @ t[:3, 3]
+    return out
+
+
+def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt_depth, iters: int,
+                  lr_rot: float, lr_trans: float, beta1=0.9, beta2=0.999, eps=1e-8):
+    """Optimise the camera-frame correction Delta of one keyframe (R18-R20).
+
+    gauss: the *other* submap (float64 tensors, held fixed); c2w: the
+    keyframe's camera-to-world pose in its own submap; targets [3,H,W], [H,W].
+    Returns (Delta as a pose 7-vector, residual eps, loss history).
+    """
+    w2c = torch.as_tensor(inv_rigid(np.asarray(c2w, np.float64))[:3, :])
+    fixed = {k: v.detach() for k, v in gauss.items()}
+    q = torch.tensor([1.0, 0.0, 0.0, 0.0], dtype=F64, requires_grad=True)
+    t = torch.zeros(3, dtype=F64, requires_grad=True)
+    mq, vq = torch.zeros(4, dtype=F64), torch.zeros(4, dtype=F64)
+    mt, vt = torch.zeros(3, dtype=F64), torch.zeros(3, dtype=F64)
+    tgt_rgb = torch.as_tensor(np.asarray(tgt_rgb, np.float64))
+    tgt_depth = torch.as_tensor(np.asarray(tgt_depth, np.float64))
+    hist = []
+    for it in range(1, iters + 1):
+        out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
+        loss = raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth)
+        gq, gt = torch.autograd.grad(loss, [q, t], allow_unused=True)
+        gq = torch.zeros(4, dtype=F64) if gq is None else gq
+        gt = torch.zeros(3, dtype=F64) if gt is None else gt
+        adam_step(q, gq, mq, vq, it, lr_rot, beta1, beta2, eps)
+        adam_step(t, gt, mt, vt, it, lr_trans, beta1, beta2, eps)
+        hist.append(float(loss.detach()))
+    with torch.no_grad():
+        out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
+        resid = float(raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth))
+    return torch.cat([q, t]).detach().numpy(), resid, hist
+
+
+def view_estimate(c2w: np.ndarray, delta7) -> np.ndarray:
+    """E = T_i Delta^-1 T_i^-1: the source-to-target transform implied by one
+    keyframe localisation (Sec. 3.2, T_{P->Q} = T_i^q T_i^-1)."""
+    c2w = np.asarray(c2w, np.float64)
+    return c2w @ inv_rigid(pose_matrix(delta7)) @ inv_rigid(c2w)
+
+
+def fuse(estimates, residuals, reverse) -> np.ndarray:
+    """Weighted rotation averaging (Eq. 7) and weighted translation mean.
+
+    estimates: list of 4x4 transforms; residuals: eps_i; reverse[i] True for
+    a Q->P estimate (inverted before averaging).  Returns the 4x4 T_bar.
+    """
+    m = np.zeros((3, 3))
+    tsum = np.zeros(3)
+    wsum = 0.0
+    for e, r, rev in zip(estimates, residuals, reverse):
+        w = 1.0 / max(float(r), 1e-12)
+        e = inv_rigid(e) if rev else np.asarray(e, np.float64)
+        m += w * e[:3, :3]
+        tsum += w * e[:3, 3]
+        wsum += w
+    u, _, vt = np.linalg.svd(m)
+    d = np.sign(np.linalg.det(u @ vt))
+    out = np.eye(4)
+    out[:3, :3] = u @ np.diag([1.0, 1.0, d]) @ vt
+    out[:3, 3] = tsum / wsum
+    return out
+
+
+def register_pair(P: dict, Q: dict, views_p, views_q, cam: raster.Camera, iters: int, lr_rot: float,
+                  lr_trans: float):
+    """Full pair registration: every keyframe of P localised in Q and every
+    keyframe of Q in P, then fused (Sec. 3.2).
+
+    P, Q: float64 Gaussian dicts; views_*: lists of (c2w 4x4, rgb [3,H,W],
+    depth [H,W]).  Returns (T_bar 4x4, per-view estimates, residuals).
+    """
+    ests, res, rev = [], [], []
+    for c2w, rgb, dep in views_p:
+        d, r, _ = localise_view(Q, cam, c2w, rgb, dep, iters, lr_rot, lr_trans)
+        ests.append(view_estimate(c2w, d))
+        res.append(r)
+        rev.append(False)
+    for c2w, rgb, dep in views_q:
+        d, r, _ = localise_view(P, cam, c2w, rgb, dep, iters, lr_rot, lr_trans)
+        ests.append(view_estimate(c2w, d))
+        res.append(r)
+        rev.append(True)
+    return fuse(ests, res, rev), ests, res
+
+
+def rotation_error_deg(r: np.ndarray, r_gt: np.ndarray) -> float:
+    c = (np.trace(np.asarray(r)[:3, :3] @ np.asarray(r_gt)[:3, :3].T) - 1.0) / 2.0
+    return math.degrees(math.acos(min(1.0, max(-1.0, c))))
+
+
+def translation_error_cm(t: np.ndarray, t_gt: np.ndarray) -> float:
+    return 100.0 * float(np.linalg.norm(np.asarray(t, np.float64) - np.asarray(t_gt, np.float64)))

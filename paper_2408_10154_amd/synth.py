@@ -1,0 +1,262 @@
+"""Seeded synthetic inputs shaped like the paper's RGB-D workloads.
+
+This module only draws random numbers and lays them out; it holds none of the
+rendering or registration arithmetic, so both the GPU path and the CPU oracle
+can take their inputs from it.  Every array is float32, structure-of-arrays:
+mean [3,N], log_scale [3,N], quat [4,N] (w, x, y, z, unnormalised),
+opacity_logit [N], rgb [3,N].
+
+The paper's datasets (Replica, TUM-RGBD, ScanNet, ScanNet++) are not used;
+these generators stand in for them with the Gaussian counts the paper reports
+(about 0.2-0.33 M per scene, supplement table of Gaussian counts) and its
+per-frame motion scale (supplement table of average frame motion).
+"""
+
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+
+def camera(fx, fy, cx, cy, width, height) -> dict:
+    return dict(fx=float(fx), fy=float(fy), cx=float(cx), cy=float(cy), width=int(width), height=int(height))
+
+
+def identity_w2c() -> np.ndarray:
+    return np.concatenate([np.eye(3), np.zeros((3, 1))], 1).astype(np.float32)
+
+
+def identity_pose() -> np.ndarray:
+    return np.array([1, 0, 0, 0, 0, 0, 0], np.float32)
+
+
+def gaussians_in_box(rng: np.random.Generator, n: int, lo, hi, log_scale_mu=math.log(0.02),
+                     log_scale_sd=0.3) -> dict:
+    """N Gaussians with means uniform in the box [lo, hi] (metres), log-scales
+    N(log 0.02, 0.3), random unit quaternions (normalised N(0, I4) draws),
+    opacity logits N(0, 1) and RGB U[0, 1]."""
+    lo = np.asarray(lo, np.float64)
+    hi = np.asarray(hi, np.float64)
+    mean = lo[:, None] + (hi - lo)[:, None] * rng.random((3, n))
+    log_scale = rng.normal(log_scale_mu, log_scale_sd, (3, n))
+    q = rng.normal(0.0, 1.0, (4, n))
+    q /= np.linalg.norm(q, axis=0, keepdims=True)
+    opacity_logit = rng.normal(0.0, 1.0, n)
+    rgb = rng.random((3, n))
+    return dict(
+        mean=mean.astype(np.float32), log_scale=log_scale.astype(np.float32), quat=q.astype(np.float32),
+        opacity_logit=opacity_logit.astype(np.float32), rgb=rgb.astype(np.float32),
+    )
+
+
+def random_axis(rng: np.random.Generator) -> np.ndarray:
+    a = rng.normal(0.0, 1.0, 3)
+    return a / np.linalg.norm(a)
+
+
+def axis_angle_pose(axis, angle_rad: float, trans) -> np.ndarray:
+    """Pose 7-vector (q_w, q_x, q_y, q_z, t_x, t_y, t_z) of a rotation by
+    `angle_rad` about the unit `axis` and a translation."""
+    axis = np.asarray(axis, np.float64)
+    h = 0.5 * angle_rad
+    q = np.concatenate([[math.cos(h)], math.sin(h) * axis])
+    return np.concatenate([q, np.asarray(trans, np.float64)]).astype(np.float32)
+
+
+def perturbation(rng: np.random.Generator, deg: float, metres: float) -> np.ndarray:
+    """A rotation of `deg` degrees about a random axis plus a translation of
+    `metres` in a random direction, as a pose 7-vector."""
+    return axis_angle_pose(random_axis(rng), math.radians(deg), metres * random_axis(rng))
+
+
+def scene_small(seed: int = 0, n: int = 4096) -> dict:
+    """Plain single-view workload: 4,096 Gaussians in a 2 m cube centred
+    2.5 m in front of an identity camera, 160x120 pinhole, f = 150, and a
+    target pose perturbed by 2 deg / 3 cm."""
+    rng = np.random.default_rng(seed)
+    g = gaussians_in_box(rng, n, (-1.0, -1.0, 1.5), (1.0, 1.0, 3.5))
+    return dict(gauss=g, cam=camera(150, 150, 80, 60, 160, 120), w2c=identity_w2c(),
+                target_pose=perturbation(rng, 2.0, 0.03))
+
+
+def scene_room_volume(seed: int = 1, n: int = 200_000) -> dict:
+    """Tracking/mapping-shaped workload: 200k Gaussians in a 6 x 3 x 4 m
+    room-shaped box in front of the camera (x in [-3, 3], y in [-1.5, 1.5],
+    z in [0.5, 4.5]), 1200x680 pinhole, f = 600, target pose 2 deg / 3 cm."""
+    rng = np.random.default_rng(seed)
+    g = gaussians_in_box(rng, n, (-3.0, -1.5, 0.5), (3.0, 1.5, 4.5))
+    return dict(gauss=g, cam=camera(600, 600, 600, 340, 1200, 680), w2c=identity_w2c(),
+                target_pose=perturbation(rng, 2.0, 0.03))
+
+
+def scene_tiny(seed: int, n: int, width: int, height: int, f: float, depth_range=(1.5, 3.0),
+               half_extent=0.8, log_scale_mu=math.log(0.05)) -> dict:
+    """Small scene for brute-force and finite-difference checks."""
+    rng = np.random.default_rng(seed)
+    zc = 0.5 * (depth_range[0] + depth_range[1])
+    hz = 0.5 * (depth_range[1] - depth_range[0])
+    g = gaussians_in_box(rng, n, (-half_extent, -half_extent, zc - hz), (half_extent, half_extent, zc + hz),
+                         log_scale_mu=log_scale_mu)
+    return dict(gauss=g, cam=camera(f, f, width / 2, height / 2, width, height), w2c=identity_w2c(),
+                target_pose=perturbation(rng, 2.0, 0.03))
+
+
+def random_image_grads(rng: np.random.Generator, n_pix: int, scale=1.0) -> dict:
+    """Upstream gradients dL/d(rgb [3,P], depth [P], alpha [P]) for backward tests."""
+    return dict(
+        rgb=(scale * rng.normal(0.0, 1.0, (3, n_pix))).astype(np.float32),
+        depth=(scale * rng.normal(0.0, 1.0, n_pix)).astype(np.float32),
+        alpha=(scale * rng.normal(0.0, 1.0, n_pix)).astype(np.float32),
+    )
+
+
+def look_at_c2w(position, target, up=(0.0, 1.0, 0.0)) -> np.ndarray:
+    """Camera-to-world 4x4 of a camera at `position` looking at `target`
+    (camera axes: x right, y down, z forward; world y up)."""
+    position = np.asarray(position, np.float64)
+    z = np.asarray(target, np.float64) - position
+    z /= np.linalg.norm(z)
+    x = np.cross(z, np.asarray(up, np.float64))
+    x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    out = np.eye(4)
+    out[:3, 0], out[:3, 1], out[:3, 2], out[:3, 3] = x, y, z, position
+    return out
+
+
+def _smooth_colour(rng: np.random.Generator, pts: np.ndarray, n_waves=8, wl=(0.3, 2.0), noise=0.05):
+    """RGB from a sum of random plane waves (wavelengths `wl` metres) plus
+    N(0, noise) per Gaussian; pts [3,N]."""
+    out = np.zeros((3, pts.shape[1]))
+    for ch in range(3):
+        acc = np.zeros(pts.shape[1])
+        for _ in range(n_waves):
+            k = random_axis(rng) * (2 * math.pi / rng.uniform(*wl))
+            acc += np.sin(k @ pts + rng.uniform(0, 2 * math.pi))
+        out[ch] = 0.5 + 0.5 * acc / math.sqrt(n_waves)
+    out += rng.normal(0.0, noise, out.shape)
+    return out
+
+
+def room_points(rng: np.random.Generator, n: int, half=(3.0, 1.5, 2.0), boxes=4, jitter=0.01) -> np.ndarray:
+    """Points on the inner shell of a box room (6 x 3 x 4 m by default) plus
+    the surfaces of `boxes` random boxes inside it, jittered along the normal."""
+    half = np.asarray(half, np.float64)
+    faces = []  # (centre, u-axis half, v-axis half, normal)
+    for ax in range(3):
+        for sgn in (-1.0, 1.0):
+            c = np.zeros(3)
+            c[ax] = sgn * half[ax]
+            o = [a for a in range(3) if a != ax]
+            eu = np.zeros(3)
+            eu[o[0]] = half[o[0]]
+            ev = np.zeros(3)
+            ev[o[1]] = half[o[1]]
+            nrm = np.zeros(3)
+            nrm[ax] = 1.0
+            faces.append((c, eu, ev, nrm))
+    for _ in range(boxes):
+        bc = rng.uniform(-0.6, 0.6, 3) * half
+        bc[1] = -half[1] + rng.uniform(0.3, 0.8)
+        bh = rng.uniform(0.2, 0.5, 3)
+        for ax in range(3):
+            for sgn in (-1.0, 1.0):
+                c = bc.copy()
+                c[ax] += sgn * bh[ax]
+                o = [a for a in range(3) if a != ax]
+                eu = np.zeros(3)
+                eu[o[0]] = bh[o[0]]
+                ev = np.zeros(3)
+                ev[o[1]] = bh[o[1]]
+                nrm = np.zeros(3)
+                nrm[ax] = 1.0
+                faces.append((c, eu, ev, nrm))
+    areas = np.array([4 * np.linalg.norm(f[1]) * np.linalg.norm(f[2]) for f in faces])
+    which = rng.choice(len(faces), size=n, p=areas / areas.sum())
+    pts = np.zeros((3, n))
+    for i, (c, eu, ev, nrm) in enumerate(faces):
+        m = which == i
+        k = int(m.sum())
+        a = rng.uniform(-1, 1, k)
+        b = rng.uniform(-1, 1, k)
+        pts[:, m] = (c[:, None] + eu[:, None] * a + ev[:, None] * b + nrm[:, None] * rng.normal(0, jitter, k))
+    return pts
+
+
+def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, views_p: int = 8,
+                      views_q: int = 8, width: int = 640, height: int = 480, f: float = 500.0,
+                      rot_deg_max: float = 10.0, trans_max: float = 0.3, half=(3.0, 1.5, 2.0),
+                      log_scale_mu=math.log(0.02), fixed_gt=None) -> dict:
+    """Two overlapping submaps of one synthetic room and their keyframes.
+
+    The room's Gaussians are ordered along x; the lowest (n_p - S) belong
+    to P only, the highest (n_q - S) to Q only and the S = shared_frac *
+    (n_p + n_q) / 2 in between to both.  P is kept in the world frame; Q is
+    expressed in its own frame through the ground-truth T_gt (rotation about a
+    random axis by U[0, rot_deg_max] deg, translation of length
+    U[0, trans_max] m), so x_Q = T_gt x_P.  Keyframes: `views_*` cameras per
+    submap in a small region near the room centre, each looking at a point of
+    the shared band; their camera-to-world poses are given in the submap's
+    own frame.  Targets (the submaps rendered at their own keyframes) are made
+    by the caller with the renderer.
+    """
+    rng = np.random.default_rng(seed)
+    s = int(round(shared_frac * (n_p + n_q) / 2))
+    s = min(s, n_p, n_q)
+    n_w = n_p + n_q - s
+    pts = room_points(rng, n_w, half=half)
+    order = np.argsort(pts[0], kind="stable")
+    pts = pts[:, order]
+    g = gaussians_in_box(rng, n_w, (0, 0, 0), (1, 1, 1), log_scale_mu=log_scale_mu)
+    g["mean"] = pts.astype(np.float32)
+    g["rgb"] = _smooth_colour(rng, pts).astype(np.float32)
+    idx_p = np.arange(0, n_p)
+    idx_q = np.arange(n_w - n_q, n_w)
+    if fixed_gt is None:
+        ang = math.radians(rng.uniform(0.0, rot_deg_max))
+        gt = axis_angle_pose(random_axis(rng), ang, rng.uniform(0.0, trans_max) * random_axis(rng))
+    else:
+        gt = np.asarray(fixed_gt, np.float32)
+    qn = gt[:4].astype(np.float64) / np.linalg.norm(gt[:4])
+    w, x, y, z = qn
+    rot = np.array([
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ])
+    t_gt = np.eye(4)
+    t_gt[:3, :3] = rot
+    t_gt[:3, 3] = gt[4:7]
+
+    def subset(idx):
+        return {k: v[..., idx].copy() for k, v in g.items()}
+
+    P = subset(idx_p)
+    Q = subset(idx_q)
+    # Q in its own frame: means moved by T_gt, quaternions left-multiplied by q_gt
+    Q["mean"] = (rot @ Q["mean"].astype(np.float64) + t_gt[:3, 3:4]).astype(np.float32)
+    qq = Q["quat"].astype(np.float64)
+    Q["quat"] = np.stack([
+        w * qq[0] - x * qq[1] - y * qq[2] - z * qq[3],
+        w * qq[1] + x * qq[0] + y * qq[3] - z * qq[2],
+        w * qq[2] - x * qq[3] + y * qq[0] + z * qq[1],
+        w * qq[3] + x * qq[2] - y * qq[1] + z * qq[0],
+    ]).astype(np.float32)
+    band = pts[:, n_w - n_q:n_p] if n_p > n_w - n_q else pts
+    half = np.asarray(half)
+
+    def keyframes(k):
+        out = []
+        for _ in range(k):
+            pos = rng.uniform(-0.35, 0.35, 3) * half
+            tgt = band[:, rng.integers(band.shape[1])]
+            if np.linalg.norm(tgt - pos) < 1.0:
+                tgt = pos + (tgt - pos) / max(np.linalg.norm(tgt - pos), 1e-6) * 1.5
+            out.append(look_at_c2w(pos, tgt))
+        return out
+
+    kf_p = keyframes(views_p)
+    kf_q = [t_gt @ c for c in keyframes(views_q)]
+    return dict(P=P, Q=Q, kf_p=np.stack(kf_p).astype(np.float64), kf_q=np.stack(kf_q).astype(np.float64),
+                T_gt=t_gt, cam=camera(f, f, width / 2, height / 2, width, height), shared=s)
