@@ -1,0 +1,258 @@
+/*
+ * loopsplat.h - C ABI of the MI355X (gfx950) Gaussian-splat rasterizer and
+ * 3DGS registration library (libloopsplat.so).
+ *
+ * The operations follow LoopSplat (Zhu et al., "LoopSplat: Loop Closure by
+ * Registering 3D Gaussian Splats"):
+ *   - a submap is a set of 3D Gaussians with mean, covariance, opacity and RGB
+ *     colour (Sec. 3.1, Eq. 1); the covariance is parametrised by per-axis
+ *     scales (Sec. 3.1, Eq. 5) and a rotation quaternion;
+ *   - colour and depth are rendered from a pose and compared with RGB-D
+ *     measurements through L1 losses (Sec. 3.1 tracking loss, Eq. 2; Sec. 3.2
+ *     registration loss);
+ *   - the pose is optimised as a rigid correction applied to the submap in
+ *     the frame of the previous camera (supplement, frame-to-model tracking);
+ *   - registration localises every keyframe of one submap in the other and
+ *     fuses the per-view estimates by weighted rotation averaging (Sec. 3.2,
+ *     Eq. 7).
+ *
+ * Conventions shared by every call
+ *   - Every call returns an ls_status.  Negative values are errors; the detail
+ *     string is available from ls_last_error() (thread-local).  No call
+ *     throws or aborts.
+ *   - All tensor arguments are float32/int32 *device* pointers owned by the
+ *     caller unless stated otherwise; the library never frees them.
+ *   - Device work is enqueued on the given HIP stream and is asynchronous
+ *     unless the call says it blocks.  Calls that share a workspace must be
+ *     ordered on one stream.
+ *   - Gaussians are structure-of-arrays: mean [3][n], log_scale [3][n],
+ *     quat [4][n] = (w, x, y, z) unnormalised, opacity_logit [n], rgb [3][n].
+ *   - A pose is 7 floats (q_w, q_x, q_y, q_z, t_x, t_y, t_z): a rigid
+ *     correction Delta applied in camera coordinates after the job's
+ *     world-to-camera transform, p = R(q/|q|) (R_cw mu + t_cw) + t.
+ *   - Camera axes: x right, y down, z forward; pixel (i, j) is sampled at
+ *     (i + 0.5, j + 0.5).
+ *   - Images of render r are planar: rgb [3][H_r][W_r] starting at float
+ *     offset 3 * pix_off[r]; depth/alpha/T_final/n_last [H_r][W_r] starting
+ *     at pix_off[r], where pix_off is the exclusive prefix sum of H_r * W_r.
+ *   - "Item" i = item_off[r] + g names Gaussian g of render r, item_off being
+ *     the exclusive prefix sum of the jobs' Gaussian counts.
+ */
+#ifndef LOOPSPLAT_H
+#define LOOPSPLAT_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t ls_status;
+#define LS_OK 0
+#define LS_NOT_READY 1
+#define LS_ERR_INVALID (-1)   /* bad argument; nothing was enqueued */
+#define LS_ERR_CAPACITY (-2)  /* a buffer is too small; required size reported */
+#define LS_ERR_BUDGET (-3)    /* request larger than the server's memory budget */
+#define LS_ERR_HIP (-4)       /* a HIP runtime call failed */
+#define LS_ERR_NONFINITE (-5) /* non-finite input or loss */
+
+/* Rasterizer constants (readings of the 3D Gaussian Splatting renderer the
+ * paper builds on; the paper does not restate them). */
+#define LS_TILE 16              /* 16x16-pixel tiles */
+#define LS_NEAR_Z 0.2f          /* cull z <= 0.2 m */
+#define LS_EPS_2D 0.3f          /* 2D low-pass dilation, px^2 */
+#define LS_ALPHA_MIN (1.0f / 255.0f)
+#define LS_ALPHA_MAX 0.99f
+#define LS_T_STOP 1e-4f
+#define LS_REC_FLOATS 12        /* floats per projected record, see ls_projected */
+
+const char* ls_last_error(void);
+/* Library version as major * 10000 + minor * 100 + patch. */
+int32_t ls_version(void);
+/* sizeof of a public struct named by its type name (e.g. "ls_render_job"),
+ * or -1 for an unknown name; lets a binding verify its layouts without a GPU. */
+int64_t ls_struct_size(const char* name);
+
+typedef struct {
+  int32_t n;                  /* number of Gaussians (>= 0) */
+  const float* mean;          /* [3][n] metres, in the job's world frame */
+  const float* log_scale;     /* [3][n] log of the per-axis standard deviations */
+  const float* quat;          /* [4][n] (w, x, y, z), any non-zero length */
+  const float* opacity_logit; /* [n]    opacity = sigmoid(opacity_logit) */
+  const float* rgb;           /* [3][n] colour, used as given (no SH) */
+} ls_gaussians;
+
+typedef struct {
+  float fx, fy, cx, cy; /* pinhole intrinsics in pixels */
+  int32_t width, height;
+} ls_intrinsics;
+
+/* One render: a Gaussian set seen by one camera (Sec. 3.1 renders a submap
+ * at a keyframe pose).  w2c is a row-major 3x4 world-to-camera transform. */
+typedef struct {
+  ls_gaussians g;
+  ls_intrinsics K;
+  float w2c[12];
+} ls_render_job;
+
+/* A batch of R render jobs that share every launch.  Created once (it uploads
+ * the job table to the device), reused across iterations; the Gaussian arrays
+ * the jobs point to must stay allocated (their values may change). */
+typedef struct ls_batch ls_batch;
+
+typedef struct {
+  int32_t renders;        /* R */
+  int64_t items;          /* M = sum of n over jobs */
+  int32_t tiles;          /* total 16x16 tiles over all renders */
+  int64_t pixels;         /* total pixels over all renders */
+  size_t workspace_bytes; /* bytes of ls_bins.work needed for the queried capacity */
+} ls_batch_info;
+
+/* Creates a batch from R >= 1 jobs (host array, copied).  Allocates the
+ * device job table.  Errors: LS_ERR_INVALID for R < 1, n < 0, non-positive
+ * image sizes or focal lengths, or NULL Gaussian arrays with n > 0. */
+ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out);
+ls_status ls_batch_destroy(ls_batch* b);
+/* Sizes of the batch and the workspace needed for `capacity` tile instances. */
+ls_status ls_batch_query(const ls_batch* b, int64_t capacity, ls_batch_info* info);
+/* Host copies of the per-render offsets: item_off, pix_off [R+1] and
+ * tile_off [R+1] (any may be NULL). */
+ls_status ls_batch_offsets(const ls_batch* b, int64_t* item_off, int64_t* pix_off, int32_t* tile_off);
+
+/* Projected splats, one record per item, caller-owned device buffers.
+ *   rec    [M][12]: (u, v, A, B,  C, opacity, z, 0,  r, g, b, 0) where (u, v)
+ *          is the projected centre in pixels, (A, B, C) the conic (inverse
+ *          2D covariance, sigma = A dx^2/2 + B dx dy + C dy^2/2), z the
+ *          camera-space depth.  16-byte aligned.
+ *   radius [M]: ceil(3 sqrt(lambda_max(Sigma_2D))) in pixels, 0 = culled
+ *   tiles  [M]: number of tiles of the item's tile rectangle, 0 = culled */
+typedef struct {
+  float* rec;
+  int32_t* radius;
+  int32_t* tiles;
+} ls_projected;
+
+/* EWA projection of every item (the splatting step the paper's renderer
+ * inherits from 3D Gaussian Splatting; Sec. 3.1 Eq. 1 parameters).
+ *   pose: device [R][7] pose corrections, or NULL for identity.
+ * Per item: Sigma = R(q) diag(s)^2 R(q)^T, camera transform W = R(q_d) R_cw,
+ * Sigma_2D = J W Sigma W^T J^T + 0.3 I with the perspective Jacobian J at the
+ * camera-space mean; culled when z <= 0.2 m, det <= 0 or the tile rectangle
+ * [floor((u-r)/16), floor((u+r)/16)+1) x (same in v), clamped to the image's
+ * tile grid, is empty.  Errors: LS_ERR_INVALID (NULL outputs). */
+ls_status ls_project(const ls_batch* b, const float* pose, const ls_projected* out, hipStream_t s);
+
+/* Tile instance lists, caller-owned device buffers.
+ *   capacity     number of instance slots in tile_of / item
+ *   tile_of [capacity] global tile index (tile_off[r] + ty * tiles_x + tx)
+ *   item    [capacity] item index of each instance
+ *   range   [tiles][2] [start, end) of each tile's list (empty tiles: 0, 0)
+ *   count   [2] int32: {number of instances I, overflow flag}
+ *   work    workspace of ls_batch_info.workspace_bytes (256-byte aligned);
+ *           also used by ls_render_bwd. */
+typedef struct {
+  int64_t capacity;
+  uint32_t* tile_of;
+  int32_t* item;
+  int32_t* range;
+  int32_t* count;
+  void* work;
+} ls_bins;
+
+/* Tile binning: every item with tiles > 0 is listed once in each tile of its
+ * rectangle (recomputed in FP32 from rec.u, rec.v and radius), and the list
+ * is ordered by (tile, FP32 depth bit pattern, item) - depth order with ties
+ * broken by Gaussian index.  Runs entirely on the device (depth radix sort of
+ * the items, scan, emission, tile radix sort).  When I > capacity, count[1]
+ * is set to 1, only the first `capacity` instances are kept and the lists are
+ * not valid; the caller re-runs with a larger capacity.  Errors:
+ * LS_ERR_INVALID (NULL buffers, capacity < 0). */
+ls_status ls_bin_sort(const ls_batch* b, const ls_projected* p, const ls_bins* bins, hipStream_t s);
+
+typedef struct {
+  float* rgb;      /* see image layout above */
+  float* depth;    /* sum_i w_i z_i (not normalised by alpha) */
+  float* alpha;    /* 1 - T_final */
+  float* T_final;  /* final transmittance */
+  int32_t* n_last; /* list entries visited before compositing stopped */
+} ls_image;
+
+/* Front-to-back compositing (RGB, depth, alpha) per 16x16 tile: for each
+ * pixel and each entry of its tile's list in order, alpha = min(0.99,
+ * o exp(-sigma)); entries with sigma < 0 or alpha < 1/255 are skipped; the
+ * loop stops before the entry that would take T below 1e-4; otherwise
+ * w = alpha T, C += w c, D += w z, T *= 1 - alpha.  rgb gets + T bg.
+ * bg: host float[3] or NULL (zero). */
+ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
+                        const ls_image* out, hipStream_t s);
+
+/* Upstream gradients dL/d(image), same layouts as ls_image (any may be NULL
+ * = zero); scale: device [R] per-render factor applied to all three, or NULL. */
+typedef struct {
+  const float* rgb;
+  const float* depth;
+  const float* alpha;
+  const float* scale;
+} ls_image_grad;
+
+/* Gradient outputs (accumulated with +=) for one render's Gaussian set, same
+ * SoA layouts as ls_gaussians; NULL members are not computed. */
+typedef struct {
+  float* mean;
+  float* log_scale;
+  float* quat;
+  float* opacity_logit;
+  float* rgb;
+} ls_gaussian_grads;
+
+/* Backward of ls_project + ls_render_fwd.  Recomputes the per-pixel
+ * transmittance back to front from T_final / n_last (no per-pixel lists are
+ * stored), reduces the per-Gaussian image-space gradients within each tile,
+ * then chains them through the projection.
+ *   grads:     host array [R] of per-render outputs, or NULL (pose only).
+ *              Jobs sharing a Gaussian set may share output arrays.
+ *   pose_grad: device [R][7], accumulated, or NULL.
+ * Errors: LS_ERR_INVALID. */
+ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                        const float* bg, const ls_image* fwd, const ls_image_grad* up,
+                        const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s);
+
+/* Registration / tracking L1 loss (Sec. 3.2: L = L_col + L_depth, both L1;
+ * Sec. 3.1 Eq. 2 without masks): per render
+ *   L_r = (1/|Omega|) sum_{p in Omega} (sum_c |C_c - C*_c| + |D - D*|),
+ * Omega = pixels with target depth > 0.
+ *   loss      device [R] (written), or NULL
+ *   grad_rgb, grad_depth: device, image layout; receive sign(x - x*) on
+ *             Omega and 0 elsewhere (sign(0) = 0)
+ *   grad_scale device [R]: receives 1/|Omega| (0 when Omega is empty), to be
+ *             passed as ls_image_grad.scale. */
+ls_status ls_loss_l1(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
+                     float* loss, float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s);
+
+/* One parameter group of a fused Adam step. */
+typedef struct {
+  float* param;
+  float* grad; /* zeroed after use when zero_grad is set */
+  float* m;
+  float* v;
+  int64_t n;
+  float lr;
+} ls_adam_group;
+
+/* Adam (beta1, beta2, eps; bias correction with step count `step` >= 1)
+ * over up to 16 groups in one launch.  The paper gives learning rates but
+ * does not name the optimiser (supplement hyper-parameter tables). */
+ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2,
+                  float eps, int32_t zero_grad, hipStream_t s);
+
+/* Fills `count` int32 words at `ptr` with `value` (a kernel, never a memset
+ * node, so it is safe inside captured graphs). */
+ls_status ls_fill_i32(int32_t* ptr, int64_t count, int32_t value, hipStream_t s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LOOPSPLAT_H */

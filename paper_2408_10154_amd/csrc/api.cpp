@@ -1,0 +1,394 @@
+// C ABI of libloopsplat.so: argument checking, batch tables, workspace
+// layout and kernel sequencing.  See include/loopsplat.h for the contract.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "kernels.h"
+
+using namespace ls;
+
+namespace {
+
+thread_local std::string g_err;
+
+ls_status fail(ls_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+ls_status fail(ls_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+ls_status hip_check(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return fail(LS_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return LS_OK;
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+}  // namespace
+
+struct ls_batch {
+  int R = 0;
+  int64_t M = 0;
+  int T = 0;
+  int64_t P = 0;
+  int nblk_items = 0;
+  int nblk_pix = 0;
+  int tile_passes = 0;
+  int device = 0;
+  std::vector<JobDev> jobs_h;
+  std::vector<int64_t> item_off, pix_off;
+  std::vector<int32_t> tile_off, blk_off, pblk_off;
+  JobDev* jobs_d = nullptr;
+  int64_t* item_off_d = nullptr;
+  int32_t* tile_off_d = nullptr;
+  int32_t* blk_off_d = nullptr;
+  int32_t* pblk_off_d = nullptr;
+  float* loss_part_d = nullptr;
+  GradDev* grads_d = nullptr;
+  std::vector<GradDev> grads_cached;
+};
+
+namespace {
+
+struct Layout {
+  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, pose_part, total;
+};
+
+Layout layout_of(const ls_batch* b, int64_t cap) {
+  Layout L{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 4));
+    return o;
+  };
+  const int64_t M = b->M;
+  const int64_t nbd = (M + kSortTile - 1) / kSortTile;
+  const int64_t nbt = (cap + kSortTile - 1) / kSortTile;
+  L.dk0 = take(4 * M);
+  L.dv0 = take(4 * M);
+  L.dk1 = take(4 * M);
+  L.dv1 = take(4 * M);
+  L.hist = take(4 * 256 * std::max<int64_t>(std::max(nbd, nbt), 1));
+  L.bsum = take(4 * (nbd + 2));
+  L.tk = take(4 * cap);
+  L.tv = take(4 * cap);
+  L.g2d = take(4 * (size_t)kGrad2D * M);
+  L.pose_part = take(4 * (size_t)kPoseAcc * std::max(b->nblk_items, 1));
+  L.total = off;
+  return L;
+}
+
+template <typename T>
+T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+ls_status ensure_device(const ls_batch* b) {
+  int cur = -1;
+  if (hipGetDevice(&cur) != hipSuccess) return fail(LS_ERR_HIP, "hipGetDevice failed");
+  if (cur != b->device && hipSetDevice(b->device) != hipSuccess) return fail(LS_ERR_HIP, "hipSetDevice failed");
+  return LS_OK;
+}
+
+template <typename T>
+ls_status upload(T** dst, const std::vector<T>& src) {
+  if (hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(src.size() * sizeof(T), 16)) != hipSuccess)
+    return fail(LS_ERR_HIP, "hipMalloc of a batch table failed");
+  if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
+    return fail(LS_ERR_HIP, "upload of a batch table failed");
+  return LS_OK;
+}
+
+ls_status check_projected(const ls_projected* p) {
+  if (!p || !p->rec || !p->radius || !p->tiles) return fail(LS_ERR_INVALID, "ls_projected has NULL members");
+  if (reinterpret_cast<uintptr_t>(p->rec) % 16) return fail(LS_ERR_INVALID, "ls_projected.rec must be 16-byte aligned");
+  return LS_OK;
+}
+
+ls_status check_bins(const ls_batch* b, const ls_bins* bins) {
+  if (!bins || !bins->tile_of || !bins->item || !bins->range || !bins->count || !bins->work)
+    return fail(LS_ERR_INVALID, "ls_bins has NULL members");
+  if (bins->capacity < 0 || bins->capacity > INT32_MAX)
+    return fail(LS_ERR_INVALID, "ls_bins.capacity out of range: %lld", (long long)bins->capacity);
+  if (reinterpret_cast<uintptr_t>(bins->work) % 256) return fail(LS_ERR_INVALID, "ls_bins.work must be 256-byte aligned");
+  (void)b;
+  return LS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* ls_last_error(void) { return g_err.c_str(); }
+
+int32_t ls_version(void) { return 100; }
+
+int64_t ls_struct_size(const char* name) {
+  if (!name) return -1;
+  struct Entry { const char* n; size_t s; };
+  static const Entry table[] = {
+      {"ls_gaussians", sizeof(ls_gaussians)},       {"ls_intrinsics", sizeof(ls_intrinsics)},
+      {"ls_render_job", sizeof(ls_render_job)},     {"ls_batch_info", sizeof(ls_batch_info)},
+      {"ls_projected", sizeof(ls_projected)},       {"ls_bins", sizeof(ls_bins)},
+      {"ls_image", sizeof(ls_image)},               {"ls_image_grad", sizeof(ls_image_grad)},
+      {"ls_gaussian_grads", sizeof(ls_gaussian_grads)}, {"ls_adam_group", sizeof(ls_adam_group)},
+  };
+  for (const Entry& e : table)
+    if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
+  return -1;
+}
+
+ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) {
+  if (!out) return fail(LS_ERR_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!jobs || R < 1) return fail(LS_ERR_INVALID, "need R >= 1 jobs (R = %d)", R);
+  auto* b = new ls_batch();
+  b->R = R;
+  b->item_off.assign(R + 1, 0);
+  b->pix_off.assign(R + 1, 0);
+  b->tile_off.assign(R + 1, 0);
+  b->blk_off.assign(R + 1, 0);
+  b->pblk_off.assign(R + 1, 0);
+  b->jobs_h.resize(R);
+  for (int r = 0; r < R; ++r) {
+    const ls_render_job& j = jobs[r];
+    const ls_intrinsics& K = j.K;
+    if (j.g.n < 0 || K.width <= 0 || K.height <= 0 || !(K.fx > 0.f) || !(K.fy > 0.f) || !std::isfinite(K.cx) ||
+        !std::isfinite(K.cy)) {
+      delete b;
+      return fail(LS_ERR_INVALID, "job %d: bad sizes or intrinsics", r);
+    }
+    if (j.g.n > 0 && (!j.g.mean || !j.g.log_scale || !j.g.quat || !j.g.opacity_logit || !j.g.rgb)) {
+      delete b;
+      return fail(LS_ERR_INVALID, "job %d: NULL Gaussian array", r);
+    }
+    for (int k = 0; k < 12; ++k)
+      if (!std::isfinite(j.w2c[k])) {
+        delete b;
+        return fail(LS_ERR_NONFINITE, "job %d: non-finite w2c", r);
+      }
+    const int TX = (K.width + kTile - 1) / kTile, TY = (K.height + kTile - 1) / kTile;
+    JobDev& d = b->jobs_h[r];
+    d.mean = j.g.mean;
+    d.log_scale = j.g.log_scale;
+    d.quat = j.g.quat;
+    d.opac = j.g.opacity_logit;
+    d.rgb = j.g.rgb;
+    d.fx = K.fx;
+    d.fy = K.fy;
+    d.cx = K.cx;
+    d.cy = K.cy;
+    d.n = j.g.n;
+    d.W = K.width;
+    d.H = K.height;
+    d.TX = TX;
+    d.TY = TY;
+    d.tile_off = b->tile_off[r];
+    d.blk_off = b->blk_off[r];
+    d.item_off = b->item_off[r];
+    d.pix_off = b->pix_off[r];
+    std::memcpy(d.w2c, j.w2c, sizeof(d.w2c));
+    const int64_t hw = (int64_t)K.width * K.height;
+    b->item_off[r + 1] = b->item_off[r] + j.g.n;
+    b->pix_off[r + 1] = b->pix_off[r] + hw;
+    b->tile_off[r + 1] = b->tile_off[r] + TX * TY;
+    b->blk_off[r + 1] = b->blk_off[r] + (j.g.n + 255) / 256;
+    b->pblk_off[r + 1] = b->pblk_off[r] + (int32_t)((hw + 1023) / 1024);
+    if (b->item_off[r + 1] > INT32_MAX || b->tile_off[r + 1] < 0) {
+      delete b;
+      return fail(LS_ERR_INVALID, "batch too large (items or tiles exceed int32)");
+    }
+  }
+  b->M = b->item_off[R];
+  b->P = b->pix_off[R];
+  b->T = b->tile_off[R];
+  b->nblk_items = b->blk_off[R];
+  b->nblk_pix = b->pblk_off[R];
+  int bits = 0;
+  while (bits < 32 && ((int64_t)1 << bits) < (int64_t)b->T) ++bits;
+  b->tile_passes = (bits + 7) / 8;
+  if (hipGetDevice(&b->device) != hipSuccess) {
+    delete b;
+    return fail(LS_ERR_HIP, "hipGetDevice failed");
+  }
+  ls_status st;
+  if ((st = upload(&b->jobs_d, b->jobs_h)) || (st = upload(&b->item_off_d, b->item_off)) ||
+      (st = upload(&b->tile_off_d, b->tile_off)) || (st = upload(&b->blk_off_d, b->blk_off)) ||
+      (st = upload(&b->pblk_off_d, b->pblk_off))) {
+    ls_batch_destroy(b);
+    return st;
+  }
+  if (hipMalloc(reinterpret_cast<void**>(&b->loss_part_d), 8 * std::max(b->nblk_pix, 1)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&b->grads_d), sizeof(GradDev) * R) != hipSuccess) {
+    ls_batch_destroy(b);
+    return fail(LS_ERR_HIP, "hipMalloc of batch scratch failed");
+  }
+  *out = b;
+  return LS_OK;
+}
+
+ls_status ls_batch_destroy(ls_batch* b) {
+  if (!b) return LS_OK;
+  hipFree(b->jobs_d);
+  hipFree(b->item_off_d);
+  hipFree(b->tile_off_d);
+  hipFree(b->blk_off_d);
+  hipFree(b->pblk_off_d);
+  hipFree(b->loss_part_d);
+  hipFree(b->grads_d);
+  delete b;
+  return LS_OK;
+}
+
+ls_status ls_batch_query(const ls_batch* b, int64_t capacity, ls_batch_info* info) {
+  if (!b || !info) return fail(LS_ERR_INVALID, "NULL argument");
+  if (capacity < 0 || capacity > INT32_MAX) return fail(LS_ERR_INVALID, "capacity out of range");
+  info->renders = b->R;
+  info->items = b->M;
+  info->tiles = b->T;
+  info->pixels = b->P;
+  info->workspace_bytes = layout_of(b, capacity).total;
+  return LS_OK;
+}
+
+ls_status ls_batch_offsets(const ls_batch* b, int64_t* item_off, int64_t* pix_off, int32_t* tile_off) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  if (item_off) std::copy(b->item_off.begin(), b->item_off.end(), item_off);
+  if (pix_off) std::copy(b->pix_off.begin(), b->pix_off.end(), pix_off);
+  if (tile_off) std::copy(b->tile_off.begin(), b->tile_off.end(), tile_off);
+  return LS_OK;
+}
+
+ls_status ls_fill_i32(int32_t* ptr, int64_t count, int32_t value, hipStream_t s) {
+  if (count < 0 || (count > 0 && !ptr)) return fail(LS_ERR_INVALID, "bad fill arguments");
+  launch_fill_i32(ptr, count, value, s);
+  return hip_check("ls_fill_i32");
+}
+
+ls_status ls_project(const ls_batch* b, const float* pose, const ls_projected* out, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(out)) || (st = ensure_device(b))) return st;
+  launch_project(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, out->rec, out->radius, out->tiles, s);
+  return hip_check("ls_project");
+}
+
+ls_status ls_bin_sort(const ls_batch* b, const ls_projected* p, const ls_bins* bins, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  const Layout L = layout_of(b, bins->capacity);
+  void* w = bins->work;
+  if (b->M == 0) {
+    launch_fill_i32(bins->count, 2, 0, s);
+    launch_fill_i32(bins->range, 2 * (int64_t)b->T, 0, s);
+    return hip_check("ls_bin_sort");
+  }
+  launch_bin_sort(b->jobs_d, b->item_off_d, b->R, b->M, b->T, b->tile_passes, p->rec, p->radius, p->tiles,
+                  bins->capacity, bins->tile_of, bins->item, bins->range, bins->count, at<uint32_t>(w, L.dk0),
+                  at<uint32_t>(w, L.dv0), at<uint32_t>(w, L.dk1), at<uint32_t>(w, L.dv1), at<uint32_t>(w, L.hist),
+                  at<uint32_t>(w, L.bsum), at<uint32_t>(w, L.tk), at<uint32_t>(w, L.tv), s);
+  return hip_check("ls_bin_sort");
+}
+
+ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
+                        const ls_image* out, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if (!out || !out->rgb || !out->depth || !out->alpha || !out->T_final || !out->n_last)
+    return fail(LS_ERR_INVALID, "ls_image has NULL members");
+  const float zero[3] = {0.f, 0.f, 0.f};
+  launch_composite_fwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
+                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, s);
+  return hip_check("ls_render_fwd");
+}
+
+ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                        const float* bg, const ls_image* fwd, const ls_image_grad* up, const ls_gaussian_grads* grads,
+                        float* pose_grad, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if (!fwd || !fwd->T_final || !fwd->n_last) return fail(LS_ERR_INVALID, "forward state (T_final, n_last) missing");
+  if (!up) return fail(LS_ERR_INVALID, "upstream gradients missing");
+  if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
+  const int want_gauss = grads != nullptr;
+  if (want_gauss) {
+    std::vector<GradDev> gd(b->R);
+    for (int r = 0; r < b->R; ++r) {
+      gd[r].mean = grads[r].mean;
+      gd[r].log_scale = grads[r].log_scale;
+      gd[r].quat = grads[r].quat;
+      gd[r].opac = grads[r].opacity_logit;
+      gd[r].rgb = grads[r].rgb;
+      gd[r].shared = 0;
+      gd[r].pad = 0;
+    }
+    for (int r = 0; r < b->R; ++r)
+      for (int q = 0; q < b->R; ++q) {
+        if (q == r) continue;
+        const float* a[5] = {gd[r].mean, gd[r].log_scale, gd[r].quat, gd[r].opac, gd[r].rgb};
+        const float* c[5] = {gd[q].mean, gd[q].log_scale, gd[q].quat, gd[q].opac, gd[q].rgb};
+        for (int k = 0; k < 5; ++k)
+          if (a[k] && a[k] == c[k]) gd[r].shared = 1;
+      }
+    const bool same = b->grads_cached.size() == gd.size() &&
+                      std::memcmp(b->grads_cached.data(), gd.data(), gd.size() * sizeof(GradDev)) == 0;
+    if (!same) {
+      if (hipMemcpy(b->grads_d, gd.data(), gd.size() * sizeof(GradDev), hipMemcpyHostToDevice) != hipSuccess)
+        return fail(LS_ERR_HIP, "upload of gradient table failed");
+      const_cast<ls_batch*>(b)->grads_cached = gd;
+    }
+  }
+  const Layout L = layout_of(b, bins->capacity);
+  float* g2d = at<float>(bins->work, L.g2d);
+  const float zero[3] = {0.f, 0.f, 0.f};
+  launch_fill_i32(reinterpret_cast<int32_t*>(g2d), (int64_t)kGrad2D * b->M, 0, s);
+  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
+                       fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale, g2d, s);
+  launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, g2d, b->grads_d, want_gauss,
+                     at<float>(bins->work, L.pose_part), pose_grad != nullptr, pose_grad, s);
+  return hip_check("ls_render_bwd");
+}
+
+ls_status ls_loss_l1(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
+                     float* loss, float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  if (!pred || !pred->rgb || !pred->depth || !tgt_rgb || !tgt_depth)
+    return fail(LS_ERR_INVALID, "NULL image arguments");
+  ls_status st;
+  if ((st = ensure_device(b))) return st;
+  launch_loss_l1(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, tgt_rgb, tgt_depth, grad_rgb,
+                 grad_depth, b->loss_part_d, loss, grad_scale, s);
+  return hip_check("ls_loss_l1");
+}
+
+ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2, float eps,
+                  int32_t zero_grad, hipStream_t s) {
+  if (!groups || ngroups < 1 || ngroups > 16) return fail(LS_ERR_INVALID, "need 1..16 Adam groups");
+  if (step < 1) return fail(LS_ERR_INVALID, "Adam step counts from 1");
+  for (int i = 0; i < ngroups; ++i)
+    if (groups[i].n < 0 || (groups[i].n > 0 && (!groups[i].param || !groups[i].grad || !groups[i].m || !groups[i].v)))
+      return fail(LS_ERR_INVALID, "Adam group %d: bad arguments", i);
+  const double bc1 = 1.0 / (1.0 - std::pow((double)beta1, step));
+  const double bc2 = 1.0 / (1.0 - std::pow((double)beta2, step));
+  launch_adam(groups, ngroups, beta1, beta2, eps, (float)bc1, (float)bc2, zero_grad, s);
+  return hip_check("ls_adam");
+}
+
+}  // extern "C"

@@ -1,0 +1,38 @@
+// Host-side launchers of the gfx950 kernels (defined next to each kernel).
+#pragma once
+
+#include "common.h"
+
+namespace ls {
+
+void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
+
+void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
+                    int32_t* radius, int32_t* tiles, hipStream_t s);
+
+void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
+                        const int32_t* radius, const float* g2d, const GradDev* grads, int want_gauss,
+                        float* pose_part, int want_pose, float* pose_grad, hipStream_t s);
+
+void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
+                     const float* rec, const int32_t* radius, const int32_t* tiles, int64_t cap, uint32_t* tile_of,
+                     int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
+                     uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s);
+
+void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
+                          const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
+                          float* alpha, float* Tf, int32_t* nl, hipStream_t s);
+
+void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
+                          const int32_t* items, const int32_t* range, const float* bg, const float* Tf,
+                          const int32_t* nl, const float* up_rgb, const float* up_depth, const float* up_alpha,
+                          const float* up_scale, float* g2d, hipStream_t s);
+
+void launch_loss_l1(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
+                    const float* pred_depth, const float* tgt_rgb, const float* tgt_depth, float* g_rgb,
+                    float* g_depth, float* part, float* loss, float* scale, hipStream_t s);
+
+void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,
+                 int zero_grad, hipStream_t s);
+
+}  // namespace ls

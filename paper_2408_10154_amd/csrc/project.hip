@@ -1,0 +1,296 @@
+// EWA projection of 3D Gaussians (forward) and its backward, gfx950.
+//
+// One thread per item; blocks never straddle two renders (each render owns
+// ceil(n / 256) blocks starting at blk_off), so the per-render pose-gradient
+// partials of the backward can be reduced in a fixed order.
+#include "common.h"
+
+namespace ls {
+
+__global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
+                                                 int R, const float* __restrict__ pose, float4* __restrict__ rec,
+                                                 int32_t* __restrict__ radius_out, int32_t* __restrict__ tiles_out) {
+  const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
+  const JobDev& J = jobs[r];
+  const int g = (blockIdx.x - J.blk_off) * 256 + threadIdx.x;
+  if (g >= J.n) return;
+  const int64_t item = J.item_off + g;
+  const int n = J.n;
+
+  float W[9], t[3];
+  camera_of(J, pose ? pose + 7 * r : nullptr, W, t);
+
+  const float mx = J.mean[g], my = J.mean[n + g], mz = J.mean[2 * n + g];
+  const float px = W[0] * mx + W[1] * my + W[2] * mz + t[0];
+  const float py = W[3] * mx + W[4] * my + W[5] * mz + t[1];
+  const float pz = W[6] * mx + W[7] * my + W[8] * mz + t[2];
+
+  float4* out = rec + item * 3;
+  int rad = 0, ntiles = 0;
+  float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
+  if (pz > LS_NEAR_Z) {
+    // Sigma = M M^T, M = R(q) diag(s)
+    float Rq[9];
+    quat_to_rot(J.quat[g], J.quat[n + g], J.quat[2 * n + g], J.quat[3 * n + g], Rq);
+    const float s0 = __expf(J.log_scale[g]), s1 = __expf(J.log_scale[n + g]), s2 = __expf(J.log_scale[2 * n + g]);
+    float M[9];
+    for (int i = 0; i < 3; ++i) { M[i * 3 + 0] = Rq[i * 3 + 0] * s0; M[i * 3 + 1] = Rq[i * 3 + 1] * s1; M[i * 3 + 2] = Rq[i * 3 + 2] * s2; }
+    // V = W M ; Sigma_c = V V^T
+    float V[9];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) V[i * 3 + k] = W[i * 3 + 0] * M[0 * 3 + k] + W[i * 3 + 1] * M[1 * 3 + k] + W[i * 3 + 2] * M[2 * 3 + k];
+    // J rows: J0 = (fx/z, 0, -fx x/z^2), J1 = (0, fy/z, -fy y/z^2); U = J V (2x3)
+    const float iz = 1.0f / pz;
+    const float j00 = J.fx * iz, j02 = -J.fx * px * iz * iz;
+    const float j11 = J.fy * iz, j12 = -J.fy * py * iz * iz;
+    float U0[3], U1[3];
+    for (int k = 0; k < 3; ++k) { U0[k] = j00 * V[k] + j02 * V[6 + k]; U1[k] = j11 * V[3 + k] + j12 * V[6 + k]; }
+    const float a = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2] + LS_EPS_2D;
+    const float b = U0[0] * U1[0] + U0[1] * U1[1] + U0[2] * U1[2];
+    const float c = U1[0] * U1[0] + U1[1] * U1[1] + U1[2] * U1[2] + LS_EPS_2D;
+    const float det = a * c - b * b;
+    if (det > 0.f) {
+      const float mid = 0.5f * (a + c);
+      const float hd = 0.5f * (a - c);
+      const float lam = mid + sqrtf(hd * hd + b * b);
+      rad = (int)ceilf(3.0f * sqrtf(lam));
+      const float u = J.fx * px * iz + J.cx;
+      const float v = J.fy * py * iz + J.cy;
+      const Rect rc = tile_rect(u, v, rad, J.TX, J.TY);
+      ntiles = max(rc.x1 - rc.x0, 0) * max(rc.y1 - rc.y0, 0);
+      if (ntiles == 0) rad = 0;
+      if (rad > 0) {
+        const float idet = 1.0f / det;
+        const float op = 1.0f / (1.0f + __expf(-J.opac[g]));
+        o0 = make_float4(u, v, c * idet, -b * idet);
+        o1 = make_float4(a * idet, op, pz, 0.f);
+        o2 = make_float4(J.rgb[g], J.rgb[n + g], J.rgb[2 * n + g], 0.f);
+      }
+    }
+  }
+  if (rad == 0) ntiles = 0;
+  out[0] = o0;
+  out[1] = o1;
+  out[2] = o2;
+  radius_out[item] = rad;
+  tiles_out[item] = ntiles;
+}
+
+// d R(q/|q|) / d(q) contracted with G (row-major dL/dR): returns dL/dq for the
+// unnormalised quaternion.
+__device__ __forceinline__ void rot_backward(float w, float x, float y, float z, const float* G, float* dq) {
+  const float n2 = w * w + x * x + y * y + z * z;
+  const float inv = rsqrtf(n2);
+  const float qw = w * inv, qx = x * inv, qy = y * inv, qz = z * inv;
+  // dL/dq_hat
+  const float gw = 2.f * (-qz * G[1] + qy * G[2] + qz * G[3] - qx * G[5] - qy * G[6] + qx * G[7]);
+  const float gx = 2.f * (qy * G[1] + qz * G[2] + qy * G[3] - 2.f * qx * G[4] - qw * G[5] + qz * G[6] + qw * G[7] -
+                          2.f * qx * G[8]);
+  const float gy = 2.f * (-2.f * qy * G[0] + qx * G[1] + qw * G[2] + qx * G[3] + qz * G[5] - qw * G[6] + qz * G[7] -
+                          2.f * qy * G[8]);
+  const float gz = 2.f * (-2.f * qz * G[0] - qw * G[1] + qx * G[2] + qw * G[3] - 2.f * qz * G[4] + qy * G[5] +
+                          qx * G[6] + qy * G[7]);
+  const float dot = qw * gw + qx * gx + qy * gy + qz * gz;
+  dq[0] = (gw - qw * dot) * inv;
+  dq[1] = (gx - qx * dot) * inv;
+  dq[2] = (gy - qy * dot) * inv;
+  dq[3] = (gz - qz * dot) * inv;
+}
+
+__device__ __forceinline__ void store_grad(float* p, float v, bool shared) {
+  if (shared) atomic_add_f32(p, v); else *p += v;
+}
+
+// Chains image-space gradients (du dv dA dB dC dop dz dr dg db per item) to
+// the Gaussian parameters and to the per-render pose correction.
+__global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
+                                                     int R, const float* __restrict__ pose,
+                                                     const int32_t* __restrict__ radius, const float* __restrict__ g2d,
+                                                     const GradDev* __restrict__ grads, int want_gauss,
+                                                     float* __restrict__ pose_part, int want_pose) {
+  const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
+  const JobDev& J = jobs[r];
+  const int g = (blockIdx.x - J.blk_off) * 256 + threadIdx.x;
+  const int n = J.n;
+  float acc[kPoseAcc];
+#pragma unroll
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
+
+  const int64_t item = J.item_off + g;
+  if (g < n && radius[item] > 0) {
+    const float* gi = g2d + item * kGrad2D;
+    const float du = gi[0], dv = gi[1], dA = gi[2], dB = gi[3], dC = gi[4];
+    const float dop = gi[5], dz = gi[6];
+
+    float W[9], t[3];
+    const float* pr = pose ? pose + 7 * r : nullptr;
+    camera_of(J, pr, W, t);
+    const float mx = J.mean[g], my = J.mean[n + g], mz = J.mean[2 * n + g];
+    const float px = W[0] * mx + W[1] * my + W[2] * mz + t[0];
+    const float py = W[3] * mx + W[4] * my + W[5] * mz + t[1];
+    const float pz = W[6] * mx + W[7] * my + W[8] * mz + t[2];
+    const float qw0 = J.quat[g], qx0 = J.quat[n + g], qy0 = J.quat[2 * n + g], qz0 = J.quat[3 * n + g];
+    float Rq[9];
+    quat_to_rot(qw0, qx0, qy0, qz0, Rq);
+    const float s[3] = {__expf(J.log_scale[g]), __expf(J.log_scale[n + g]), __expf(J.log_scale[2 * n + g])};
+    float M[9];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) M[i * 3 + k] = Rq[i * 3 + k] * s[k];
+    float V[9];  // W M
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) V[i * 3 + k] = W[i * 3 + 0] * M[0 * 3 + k] + W[i * 3 + 1] * M[1 * 3 + k] + W[i * 3 + 2] * M[2 * 3 + k];
+    float Sc[9];  // Sigma_c = V V^T
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k) Sc[i * 3 + k] = V[i * 3 + 0] * V[k * 3 + 0] + V[i * 3 + 1] * V[k * 3 + 1] + V[i * 3 + 2] * V[k * 3 + 2];
+    const float iz = 1.0f / pz;
+    const float fx = J.fx, fy = J.fy;
+    const float J0[3] = {fx * iz, 0.f, -fx * px * iz * iz};
+    const float J1[3] = {0.f, fy * iz, -fy * py * iz * iz};
+    float SJ0[3], SJ1[3];  // Sigma_c J0^T, Sigma_c J1^T
+    for (int i = 0; i < 3; ++i) {
+      SJ0[i] = Sc[i * 3 + 0] * J0[0] + Sc[i * 3 + 1] * J0[1] + Sc[i * 3 + 2] * J0[2];
+      SJ1[i] = Sc[i * 3 + 0] * J1[0] + Sc[i * 3 + 1] * J1[1] + Sc[i * 3 + 2] * J1[2];
+    }
+    const float a = J0[0] * SJ0[0] + J0[1] * SJ0[1] + J0[2] * SJ0[2] + LS_EPS_2D;
+    const float b = J0[0] * SJ1[0] + J0[1] * SJ1[1] + J0[2] * SJ1[2];
+    const float c = J1[0] * SJ1[0] + J1[1] * SJ1[1] + J1[2] * SJ1[2] + LS_EPS_2D;
+    const float det = a * c - b * b;
+    const float id2 = 1.0f / (det * det);
+    // conic (A, B, C) = (c, -b, a) / det  ->  gradients of (a, b, c)
+    const float ga = (-c * c * dA + b * c * dB - b * b * dC) * id2;
+    const float gb = (2.f * b * c * dA - (det + 2.f * b * b) * dB + 2.f * a * b * dC) * id2;
+    const float gc = (-b * b * dA + a * b * dB - a * a * dC) * id2;
+    // dL/dSigma_c (symmetric) = ga J0^T J0 + gb (J0^T J1 + J1^T J0)/2 + gc J1^T J1
+    float G[9];
+    for (int i = 0; i < 3; ++i)
+      for (int k = 0; k < 3; ++k)
+        G[i * 3 + k] = ga * J0[i] * J0[k] + 0.5f * gb * (J0[i] * J1[k] + J1[i] * J0[k]) + gc * J1[i] * J1[k];
+    // dL/dJ0 = 2 ga Sigma J0 + gb Sigma J1 ; dL/dJ1 = gb Sigma J0 + 2 gc Sigma J1
+    const float gJ00 = 2.f * ga * SJ0[0] + gb * SJ1[0];
+    const float gJ02 = 2.f * ga * SJ0[2] + gb * SJ1[2];
+    const float gJ11 = gb * SJ0[1] + 2.f * gc * SJ1[1];
+    const float gJ12 = gb * SJ0[2] + 2.f * gc * SJ1[2];
+    const float iz2 = iz * iz, iz3 = iz2 * iz;
+    float dp[3];
+    dp[0] = du * fx * iz - gJ02 * fx * iz2;
+    dp[1] = dv * fy * iz - gJ12 * fy * iz2;
+    dp[2] = -du * fx * px * iz2 - dv * fy * py * iz2 + dz - gJ00 * fx * iz2 + gJ02 * 2.f * fx * px * iz3 -
+            gJ11 * fy * iz2 + gJ12 * 2.f * fy * py * iz3;
+
+    if (want_gauss) {
+      const GradDev& GD = grads[r];
+      const bool sh = GD.shared != 0;
+      if (GD.mean) {
+        for (int k = 0; k < 3; ++k)
+          store_grad(GD.mean + k * n + g, W[0 * 3 + k] * dp[0] + W[1 * 3 + k] * dp[1] + W[2 * 3 + k] * dp[2], sh);
+      }
+      if (GD.log_scale || GD.quat) {
+        // dL/dSigma = W^T G W ; dL/dM = 2 dL/dSigma M
+        float GW[9];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) GW[i * 3 + k] = G[i * 3 + 0] * W[0 * 3 + k] + G[i * 3 + 1] * W[1 * 3 + k] + G[i * 3 + 2] * W[2 * 3 + k];
+        float GS[9];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) GS[i * 3 + k] = W[0 * 3 + i] * GW[0 * 3 + k] + W[1 * 3 + i] * GW[1 * 3 + k] + W[2 * 3 + i] * GW[2 * 3 + k];
+        float GM[9];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) GM[i * 3 + k] = 2.f * (GS[i * 3 + 0] * M[0 * 3 + k] + GS[i * 3 + 1] * M[1 * 3 + k] + GS[i * 3 + 2] * M[2 * 3 + k]);
+        if (GD.log_scale) {
+          for (int k = 0; k < 3; ++k)
+            store_grad(GD.log_scale + k * n + g, s[k] * (GM[0 * 3 + k] * Rq[0 * 3 + k] + GM[1 * 3 + k] * Rq[1 * 3 + k] + GM[2 * 3 + k] * Rq[2 * 3 + k]), sh);
+        }
+        if (GD.quat) {
+          float GR[9];
+          for (int i = 0; i < 3; ++i)
+            for (int k = 0; k < 3; ++k) GR[i * 3 + k] = GM[i * 3 + k] * s[k];
+          float dq[4];
+          rot_backward(qw0, qx0, qy0, qz0, GR, dq);
+          for (int k = 0; k < 4; ++k) store_grad(GD.quat + k * n + g, dq[k], sh);
+        }
+      }
+      if (GD.opac) {
+        const float op = 1.0f / (1.0f + __expf(-J.opac[g]));
+        store_grad(GD.opac + g, dop * op * (1.f - op), sh);
+      }
+      if (GD.rgb) {
+        for (int k = 0; k < 3; ++k) store_grad(GD.rgb + k * n + g, gi[7 + k], sh);
+      }
+    }
+    if (want_pose && pr != nullptr) {
+      // p = R_d p0 + t_d, Sigma_c = R_d Sigma0 R_d^T:
+      // dL/dR_d = dp p0^T + 2 G Sigma_c R_d ; dL/dt_d = dp
+      float Rd[9];
+      quat_to_rot(pr[0], pr[1], pr[2], pr[3], Rd);
+      const float p0[3] = {px - pr[4], py - pr[5], pz - pr[6]};
+      float q0[3];  // R_d^T (p - t_d)
+      for (int k = 0; k < 3; ++k) q0[k] = Rd[0 * 3 + k] * p0[0] + Rd[1 * 3 + k] * p0[1] + Rd[2 * 3 + k] * p0[2];
+      float GSc[9];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k) GSc[i * 3 + k] = G[i * 3 + 0] * Sc[0 * 3 + k] + G[i * 3 + 1] * Sc[1 * 3 + k] + G[i * 3 + 2] * Sc[2 * 3 + k];
+      for (int i = 0; i < 3; ++i)
+        for (int k = 0; k < 3; ++k)
+          acc[i * 3 + k] = dp[i] * q0[k] + 2.f * (GSc[i * 3 + 0] * Rd[0 * 3 + k] + GSc[i * 3 + 1] * Rd[1 * 3 + k] + GSc[i * 3 + 2] * Rd[2 * 3 + k]);
+      acc[9] = dp[0];
+      acc[10] = dp[1];
+      acc[11] = dp[2];
+    }
+  }
+  if (want_pose) {
+    // fixed-order block reduction: wave sums, then the 4 waves in order
+    __shared__ float part[4][kPoseAcc];
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int k = 0; k < kPoseAcc; ++k) {
+      const float s = wave_sum(acc[k]);
+      if (lane == 0) part[w][k] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x < kPoseAcc) {
+      const int k = threadIdx.x;
+      pose_part[(int64_t)blockIdx.x * kPoseAcc + k] = (part[0][k] + part[1][k]) + (part[2][k] + part[3][k]);
+    }
+  }
+}
+
+// Per render: sum the block partials in order, chain dL/dR_d to the
+// quaternion, accumulate into pose_grad [R][7].  One wave per render.
+__global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const float* __restrict__ pose,
+                              const float* __restrict__ pose_part, float* __restrict__ pose_grad) {
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  const JobDev& J = jobs[r];
+  const int nb = (J.n + 255) / 256;
+  const int lane = threadIdx.x;
+  float acc[kPoseAcc];
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
+  for (int b = lane; b < nb; b += 64)
+    for (int k = 0; k < kPoseAcc; ++k) acc[k] += pose_part[(int64_t)(J.blk_off + b) * kPoseAcc + k];
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+    const float* pr = pose + 7 * r;
+    float dq[4];
+    rot_backward(pr[0], pr[1], pr[2], pr[3], acc, dq);
+    float* out = pose_grad + 7 * r;
+    for (int k = 0; k < 4; ++k) out[k] += dq[k];
+    for (int k = 0; k < 3; ++k) out[4 + k] += acc[9 + k];
+  }
+}
+
+}  // namespace ls
+
+namespace ls {
+void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
+                    int32_t* radius, int32_t* tiles, hipStream_t s) {
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, reinterpret_cast<float4*>(rec),
+                       radius, tiles);
+}
+void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
+                        const int32_t* radius, const float* g2d, const GradDev* grads, int want_gauss,
+                        float* pose_part, int want_pose, float* pose_grad, hipStream_t s) {
+  if (nblk > 0)
+    hipLaunchKernelGGL(k_project_bwd, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius, g2d, grads,
+                       want_gauss, pose_part, want_pose);
+  if (want_pose) hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, pose_part, pose_grad);
+}
+}  // namespace ls

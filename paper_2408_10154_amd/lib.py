@@ -1,0 +1,182 @@
+"""ctypes binding of libloopsplat.so (argument marshalling only).
+
+The structures mirror include/loopsplat.h field for field.  `load()` opens the
+in-tree library and raises if it has not been built - there is no fallback
+implementation.  Every `ls_*` function here has the C function's name and
+arguments and raises `LsError` on a negative status.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libloopsplat.so")
+
+LS_OK = 0
+LS_NOT_READY = 1
+LS_ERR_INVALID = -1
+LS_ERR_CAPACITY = -2
+LS_ERR_BUDGET = -3
+LS_ERR_HIP = -4
+LS_ERR_NONFINITE = -5
+REC_FLOATS = 12
+TILE = 16
+
+
+class LsError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"loopsplat status {status}: {msg}")
+        self.status = status
+
+
+class ls_gaussians(C.Structure):
+    _fields_ = [("n", C.c_int32), ("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("rgb", C.c_void_p)]
+
+
+class ls_intrinsics(C.Structure):
+    _fields_ = [("fx", C.c_float), ("fy", C.c_float), ("cx", C.c_float), ("cy", C.c_float),
+                ("width", C.c_int32), ("height", C.c_int32)]
+
+
+class ls_render_job(C.Structure):
+    _fields_ = [("g", ls_gaussians), ("K", ls_intrinsics), ("w2c", C.c_float * 12)]
+
+
+class ls_batch_info(C.Structure):
+    _fields_ = [("renders", C.c_int32), ("items", C.c_int64), ("tiles", C.c_int32), ("pixels", C.c_int64),
+                ("workspace_bytes", C.c_size_t)]
+
+
+class ls_projected(C.Structure):
+    _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles", C.c_void_p)]
+
+
+class ls_bins(C.Structure):
+    _fields_ = [("capacity", C.c_int64), ("tile_of", C.c_void_p), ("item", C.c_void_p), ("range", C.c_void_p),
+                ("count", C.c_void_p), ("work", C.c_void_p)]
+
+
+class ls_image(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("T_final", C.c_void_p),
+                ("n_last", C.c_void_p)]
+
+
+class ls_image_grad(C.Structure):
+    _fields_ = [("rgb", C.c_void_p), ("depth", C.c_void_p), ("alpha", C.c_void_p), ("scale", C.c_void_p)]
+
+
+class ls_gaussian_grads(C.Structure):
+    _fields_ = [("mean", C.c_void_p), ("log_scale", C.c_void_p), ("quat", C.c_void_p),
+                ("opacity_logit", C.c_void_p), ("rgb", C.c_void_p)]
+
+
+class ls_adam_group(C.Structure):
+    _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
+                ("n", C.c_int64), ("lr", C.c_float)]
+
+
+_P = C.c_void_p
+_PROTOS = {
+    "ls_last_error": (C.c_char_p, []),
+    "ls_version": (C.c_int32, []),
+    "ls_struct_size": (C.c_int64, [C.c_char_p]),
+    "ls_batch_create": (C.c_int32, [C.POINTER(ls_render_job), C.c_int32, C.POINTER(_P)]),
+    "ls_batch_destroy": (C.c_int32, [_P]),
+    "ls_batch_query": (C.c_int32, [_P, C.c_int64, C.POINTER(ls_batch_info)]),
+    "ls_batch_offsets": (C.c_int32, [_P, _P, _P, _P]),
+    "ls_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), _P]),
+    "ls_bin_sort": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P]),
+    "ls_render_fwd": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image), _P]),
+    "ls_render_bwd": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
+                                  C.POINTER(ls_image_grad), _P, _P, _P]),
+    "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
+    "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
+                            C.c_int32, _P]),
+    "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
+}
+
+_lib = None
+
+
+def load():
+    """Open libloopsplat.so (once).  Raises if it is missing: build it with
+    `python -m paper_2408_10154_amd.build`."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is not built; run `python -m paper_2408_10154_amd.build`")
+        lib = C.CDLL(LIB_PATH)
+        for name, (res, args) in _PROTOS.items():
+            fn = getattr(lib, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = lib
+    return _lib
+
+
+def declared_functions():
+    return sorted(_PROTOS)
+
+
+def check(status: int) -> int:
+    if status < 0:
+        raise LsError(status, load().ls_last_error().decode(errors="replace"))
+    return status
+
+
+def _call(name, *args):
+    return check(getattr(load(), name)(*args))
+
+
+# Thin wrappers with the C names -------------------------------------------
+
+def ls_batch_create(jobs, R):
+    h = C.c_void_p()
+    _call("ls_batch_create", jobs, R, C.byref(h))
+    return h
+
+
+def ls_batch_destroy(h):
+    return _call("ls_batch_destroy", h)
+
+
+def ls_batch_query(h, capacity):
+    info = ls_batch_info()
+    _call("ls_batch_query", h, capacity, C.byref(info))
+    return info
+
+
+def ls_batch_offsets(h, item_off, pix_off, tile_off):
+    return _call("ls_batch_offsets", h, item_off, pix_off, tile_off)
+
+
+def ls_project(h, pose, proj, stream):
+    return _call("ls_project", h, pose, C.byref(proj), stream)
+
+
+def ls_bin_sort(h, proj, bins, stream):
+    return _call("ls_bin_sort", h, C.byref(proj), C.byref(bins), stream)
+
+
+def ls_render_fwd(h, proj, bins, bg, img, stream):
+    return _call("ls_render_fwd", h, C.byref(proj), C.byref(bins), bg, C.byref(img), stream)
+
+
+def ls_render_bwd(h, pose, proj, bins, bg, fwd, up, grads, pose_grad, stream):
+    return _call("ls_render_bwd", h, pose, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), grads,
+                 pose_grad, stream)
+
+
+def ls_loss_l1(h, pred, tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_scale, stream):
+    return _call("ls_loss_l1", h, C.byref(pred), tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_scale, stream)
+
+
+def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):
+    return _call("ls_adam", groups, ngroups, step, beta1, beta2, eps, zero_grad, stream)
+
+
+def ls_fill_i32(ptr, count, value, stream):
+    return _call("ls_fill_i32", ptr, count, value, stream)

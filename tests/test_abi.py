@@ -1,0 +1,67 @@
+"""The C-ABI library loads on a CPU-only host, exports every function that
+include/loopsplat.h declares, and its struct layouts match the binding.
+No compute call is made (there is no GPU here)."""
+
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_2408_10154_amd import lib as L
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
+
+
+def declared():
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*(ls_[a-z0-9_]+)\s*\(", text, re.M):
+            names.add(m.group(1))
+    return names
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ["ls_project", "ls_bin_sort", "ls_render_fwd", "ls_render_bwd"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = L.load()
+    missing = [n for n in sorted(declared()) if not hasattr(lib, n)]
+    assert not missing, missing
+
+
+def test_binding_covers_the_header():
+    assert set(L.declared_functions()) == declared()
+
+
+@pytest.mark.parametrize("name", ["ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
+                                  "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group"])
+def test_struct_layouts_match(name):
+    lib = L.load()
+    assert lib.ls_struct_size(name.encode()) == C.sizeof(getattr(L, name))
+
+
+def test_invalid_arguments_are_rejected_without_a_device():
+    lib = L.load()
+    h = C.c_void_p()
+    assert lib.ls_batch_create(None, 0, C.byref(h)) == L.LS_ERR_INVALID
+    assert b"R >= 1" in lib.ls_last_error()
+    job = (L.ls_render_job * 1)()
+    job[0].K = L.ls_intrinsics(100.0, 100.0, 8.0, 8.0, 0, 16)  # zero width
+    assert lib.ls_batch_create(job, 1, C.byref(h)) == L.LS_ERR_INVALID
+    job[0].K = L.ls_intrinsics(100.0, 100.0, 8.0, 8.0, 16, 16)
+    job[0].g.n = 5  # n > 0 with NULL arrays
+    assert lib.ls_batch_create(job, 1, C.byref(h)) == L.LS_ERR_INVALID
+    assert lib.ls_adam(None, 0, 1, 0.9, 0.999, 1e-8, 0, None) == L.LS_ERR_INVALID
+    grp = (L.ls_adam_group * 1)()
+    assert lib.ls_adam(grp, 1, 0, 0.9, 0.999, 1e-8, 0, None) == L.LS_ERR_INVALID  # step 0
+    assert lib.ls_fill_i32(None, 4, 0, None) == L.LS_ERR_INVALID
+    assert lib.ls_struct_size(b"no_such_struct") == -1
+    with pytest.raises(L.LsError):
+        L.check(L.LS_ERR_INVALID)
