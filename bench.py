@@ -1,0 +1,216 @@
+#!/usr/bin/env python
+"""Benchmark: differentiable Gaussian-splat render forward + backward on one GPU.
+
+Workload (tracking/mapping-shaped): 200k Gaussians in a 6 x 3 x 4 m room-shaped
+box, 1200 x 680 pinhole (f = 600), L1 RGB + depth loss against a render at a
+pose perturbed by 2 deg / 3 cm.  One step = one optimisation iteration:
+project -> tile binning -> composite forward -> L1 loss -> composite backward
+-> projection backward -> Adam on every Gaussian parameter and on the camera
+pose.  Inputs are resident in HBM before timing; no host sync inside a step.
+
+Prints one JSON line (metric, value in Mpixels/s of fwd+bwd iterations,
+roofline of the dominant kernel measured with HIP events on the launch
+stream, and the FP64 CPU oracle timed on a bounded sample of the same
+workload).
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# algorithmic FP32 operations per (pixel, list entry), counted from the
+# compositing definition (see the design notes): evaluation of an entry
+# (offset, exponent, falloff, opacity, clamp) and the extra work of an entry
+# that is composited.
+FWD_EVAL, FWD_COMP = 14, 11
+BWD_EVAL, BWD_COMP = 14, 53
+PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
+PEAK_HBM_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=30)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-tiles", type=int, default=400, help="tiles in the oracle's timed sample")
+    ap.add_argument("--gaussians", type=int, default=200_000)
+    return ap.parse_args()
+
+
+def cpu_baseline(scene, sample_tiles: int):
+    """The FP64 oracle on a bounded sample of the same workload: projection and
+    binning of all Gaussians, then forward + L1 loss + backward restricted to
+    `sample_tiles` evenly spaced tiles.  The per-image time is extrapolated as
+    t(project + bin) + (tiles / sample_tiles) * t(sampled tiles)."""
+    import numpy as np
+    import torch
+
+    from oracle import raster as R
+
+    cam = R.Camera(**scene["cam"])
+    w2c = torch.as_tensor(np.asarray(scene["w2c"], np.float64))
+    g = R.to_f64(scene["gauss"], requires_grad=True)
+    pose = R.identity_pose().requires_grad_(True)
+    t0 = time.perf_counter()
+    pr = R.project(g["mean"], g["log_scale"], g["quat"], cam, w2c, pose)
+    tile_of, gid, ranges = R.bin_sort(pr["u32"], pr["v32"], pr["z32"], pr["radius"], cam)
+    t1 = time.perf_counter()
+    ntiles = cam.tiles_x * cam.tiles_y
+    subset = np.linspace(0, ntiles - 1, sample_tiles).round().astype(int)
+    out = R.composite(pr["u"], pr["v"], pr["conic"], torch.sigmoid(g["opacity_logit"]), g["rgb"], pr["depth"], gid,
+                      ranges, cam, tiles_subset=subset, with_margins=False)
+    tgt_rgb = out["rgb"].detach() * 0.9
+    tgt_d = out["depth"].detach() * 1.01 + 0.01
+    loss = R.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_d)
+    loss.backward()
+    t2 = time.perf_counter()
+    px_sample = 0
+    for t in subset:
+        ty, tx = divmod(int(t), cam.tiles_x)
+        px_sample += (min(16, cam.height - ty * 16)) * (min(16, cam.width - tx * 16))
+    t_img = (t1 - t0) + (ntiles / len(subset)) * (t2 - t1)
+    pixels = cam.width * cam.height
+    return dict(value=pixels / t_img / 1e6, unit="Mpixels/s", cores=torch.get_num_threads(), kind="oracle",
+                sample=(f"FP64 oracle, one fwd+bwd: project+bin of all {len(pr['radius'])} Gaussians "
+                        f"({t1 - t0:.1f} s), then fwd+L1+bwd on {len(subset)} of {ntiles} tiles ({px_sample} px, "
+                        f"{t2 - t1:.1f} s); per-image time extrapolated by tile count"))
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(independent registration pairs and image-tile bands would shard across GPUs)", file=sys.stderr)
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    from paper_2408_10154_amd import synth
+    from paper_2408_10154_amd import lib as L
+    from paper_2408_10154_amd.render import GaussianSet, RenderBatch, adam
+
+    torch.cuda.set_device(int(os.environ.get("LOCAL_RANK", "0")))
+    scene = synth.scene_room_volume(seed=1, n=args.gaussians)
+    cam = scene["cam"]
+    gs = GaussianSet.from_numpy(scene["gauss"])
+    b = RenderBatch([(gs, cam, scene["w2c"])], auto_grow=True)
+
+    # target: the scene rendered at the perturbed pose (fixed for the run)
+    tpose = torch.as_tensor(scene["target_pose"][None], device="cuda")
+    b.project(tpose)
+    b.bin_sort()
+    b.render_fwd()
+    tgt_rgb, tgt_depth = b.rgb.clone(), b.depth.clone()
+    b._alloc_bins(int(b.instances() * 1.5) + 4096)  # headroom: no host sync inside a step
+    b.auto_grow = False
+
+    pose = torch.as_tensor(synth.identity_pose()[None], device="cuda").contiguous()
+    grads = gs.zeros_like()
+    pose_grad = torch.zeros_like(pose)
+    lr = dict(mean=1.6e-4 * 6.0, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, rgb=2.5e-3)
+    groups = []
+    for name in GaussianSet.FIELDS:
+        p = getattr(gs, name)
+        groups.append((p, getattr(grads, name), torch.zeros_like(p), torch.zeros_like(p), lr[name]))
+    pm, pv = torch.zeros_like(pose), torch.zeros_like(pose)
+    groups.append((pose[0, :4], pose_grad[0, :4], pm[0, :4], pv[0, :4], 2e-3))   # tracking rotation lr
+    groups.append((pose[0, 4:], pose_grad[0, 4:], pm[0, 4:], pv[0, 4:], 1e-2))   # tracking translation lr
+    loss = torch.zeros(1, device="cuda")
+    g_rgb = torch.zeros_like(b.rgb)
+    g_depth = torch.zeros_like(b.depth)
+    g_scale = torch.zeros(1, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev = {k: [] for k in ("fwd", "bwd")}
+    step_no = [0]
+
+    def step(timed: bool):
+        b.project(pose)
+        L.ls_bin_sort(b.h, b.proj, b.bins, L.C.c_void_p(stream.cuda_stream))
+        if timed:
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+        b.render_fwd()
+        if timed:
+            e1.record(stream)
+            ev["fwd"].append((e0, e1))
+        b.loss_l1(tgt_rgb, tgt_depth, loss, g_rgb, g_depth, g_scale)
+        if timed:
+            e2, e3 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e2.record(stream)
+        b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=g_scale)
+        if timed:
+            e3.record(stream)
+            ev["bwd"].append((e2, e3))
+        b.render_bwd_project(grads=[grads], pose=pose, pose_grad=pose_grad)
+        step_no[0] += 1
+        adam(groups, step_no[0])
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    loss0 = float(loss.item())
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    if int(b.count[1].item()) != 0:
+        raise RuntimeError("tile-instance capacity overflowed during the timed steps")
+    loss1 = float(loss.item())
+    dt = (t1 - t0) / args.steps
+    pixels = cam["width"] * cam["height"]
+    value = pixels / dt / 1e6
+
+    kms = {k: sum(a.elapsed_time(c) for a, c in v) / len(v) for k, v in ev.items()}
+    evaluated, composited = b.render_stats()
+    flops = {"fwd": FWD_EVAL * evaluated + FWD_COMP * composited,
+             "bwd": BWD_EVAL * evaluated + BWD_COMP * composited}
+    dom = max(kms, key=kms.get)
+    achieved = flops[dom] / (kms[dom] * 1e-3) / 1e12
+    instances = b.instances()
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(scene, args.cpu_tiles)
+
+    out = {
+        "metric": "fwd+bwd Mpixels/s; batched pair registrations/s + p50/p99 vs plain",
+        "value": round(value, 3),
+        "unit": "Mpixels/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "tracking/mapping render loop: 200k Gaussians (6x3x4 m box), 1200x680 f=600, "
+                               "fwd+bwd+Adam on Gaussians and camera pose",
+                   "gaussians": args.gaussians, "width": cam["width"], "height": cam["height"],
+                   "instances": instances, "parallelism": "single GPU"},
+        "roofline": {"bound": "alu", "kernel": "composite_" + dom, "achieved": round(achieved, 3),
+                     "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
+                     "traffic": None},
+        "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
+        "fragments": {"evaluated": evaluated, "composited": composited},
+        "loss": {"first_timed": round(loss0, 5), "last": round(loss1, 5)},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

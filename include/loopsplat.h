@@ -208,17 +208,39 @@ typedef struct {
   float* rgb;
 } ls_gaussian_grads;
 
-/* Backward of ls_project + ls_render_fwd.  Recomputes the per-pixel
- * transmittance back to front from T_final / n_last (no per-pixel lists are
- * stored), reduces the per-Gaussian image-space gradients within each tile,
- * then chains them through the projection.
+/* Backward of ls_project + ls_render_fwd (= ls_render_bwd_tiles followed by
+ * ls_render_bwd_project).  Recomputes the per-pixel transmittance back to
+ * front from T_final / n_last (no per-pixel lists are stored), reduces the
+ * per-Gaussian image-space gradients within each tile, then chains them
+ * through the projection.
  *   grads:     host array [R] of per-render outputs, or NULL (pose only).
  *              Jobs sharing a Gaussian set may share output arrays.
- *   pose_grad: device [R][7], accumulated, or NULL.
- * Errors: LS_ERR_INVALID. */
+ *   pose_grad: device [R][7], accumulated, or NULL; needs `pose`.
+ * The image-space gradient scratch lives in ls_bins.work: the workspace must
+ * be zero-filled before its first ls_render_bwd_tiles, and
+ * ls_render_bwd_project leaves it zeroed again.  Errors: LS_ERR_INVALID. */
 ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
                         const float* bg, const ls_image* fwd, const ls_image_grad* up,
                         const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s);
+
+/* First half of ls_render_bwd: per tile, back-to-front recomputation and
+ * accumulation of dL/d(u, v, conic, opacity, z, rgb) per item into the
+ * workspace (one kernel). */
+ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
+                              const ls_image* fwd, const ls_image_grad* up, hipStream_t s);
+
+/* Second half of ls_render_bwd: chains the accumulated image-space gradients
+ * through the EWA projection to the Gaussian parameters and the pose, and
+ * clears the accumulator. */
+ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                                const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s);
+
+/* Work statistics of the last forward: stats (device int64 [2], written)
+ * receives {list entries evaluated (every entry up to and including the one
+ * that stopped compositing), entries composited (alpha >= 1/255)} summed
+ * over all pixels. */
+ls_status ls_render_stats(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const ls_image* fwd,
+                          int64_t* stats, hipStream_t s);
 
 /* Registration / tracking L1 loss (Sec. 3.2: L = L_col + L_depth, both L1;
  * Sec. 3.1 Eq. 2 without masks): per render

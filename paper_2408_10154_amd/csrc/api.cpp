@@ -83,7 +83,7 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.dk1 = take(4 * M);
   L.dv1 = take(4 * M);
   L.hist = take(4 * 256 * std::max<int64_t>(std::max(nbd, nbt), 1));
-  L.bsum = take(4 * (nbd + 2));
+  L.bsum = take(4 * (nbd + 8 + 264));  // block sums, their total, then 257 digit bases
   L.tk = take(4 * cap);
   L.tv = take(4 * cap);
   L.g2d = take(4 * (size_t)kGrad2D * M);
@@ -318,14 +318,26 @@ ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins*
   return hip_check("ls_render_fwd");
 }
 
-ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
-                        const float* bg, const ls_image* fwd, const ls_image_grad* up, const ls_gaussian_grads* grads,
-                        float* pose_grad, hipStream_t s) {
+ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
+                              const ls_image* fwd, const ls_image_grad* up, hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");
   ls_status st;
   if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
   if (!fwd || !fwd->T_final || !fwd->n_last) return fail(LS_ERR_INVALID, "forward state (T_final, n_last) missing");
   if (!up) return fail(LS_ERR_INVALID, "upstream gradients missing");
+  const Layout L = layout_of(b, bins->capacity);
+  const float zero[3] = {0.f, 0.f, 0.f};
+  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
+                       fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale,
+                       at<float>(bins->work, L.g2d), s);
+  return hip_check("ls_render_bwd_tiles");
+}
+
+ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                                const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
   if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
   const int want_gauss = grads != nullptr;
   if (want_gauss) {
@@ -350,20 +362,35 @@ ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected
     const bool same = b->grads_cached.size() == gd.size() &&
                       std::memcmp(b->grads_cached.data(), gd.data(), gd.size() * sizeof(GradDev)) == 0;
     if (!same) {
-      if (hipMemcpy(b->grads_d, gd.data(), gd.size() * sizeof(GradDev), hipMemcpyHostToDevice) != hipSuccess)
+      if (hipMemcpyAsync(b->grads_d, gd.data(), gd.size() * sizeof(GradDev), hipMemcpyHostToDevice, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
         return fail(LS_ERR_HIP, "upload of gradient table failed");
       const_cast<ls_batch*>(b)->grads_cached = gd;
     }
   }
   const Layout L = layout_of(b, bins->capacity);
-  float* g2d = at<float>(bins->work, L.g2d);
-  const float zero[3] = {0.f, 0.f, 0.f};
-  launch_fill_i32(reinterpret_cast<int32_t*>(g2d), (int64_t)kGrad2D * b->M, 0, s);
-  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
-                       fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale, g2d, s);
-  launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, g2d, b->grads_d, want_gauss,
-                     at<float>(bins->work, L.pose_part), pose_grad != nullptr, pose_grad, s);
-  return hip_check("ls_render_bwd");
+  launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, at<float>(bins->work, L.g2d),
+                     b->grads_d, want_gauss, at<float>(bins->work, L.pose_part), pose_grad != nullptr, pose_grad, s);
+  return hip_check("ls_render_bwd_project");
+}
+
+ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                        const float* bg, const ls_image* fwd, const ls_image_grad* up, const ls_gaussian_grads* grads,
+                        float* pose_grad, hipStream_t s) {
+  if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
+  ls_status st = ls_render_bwd_tiles(b, p, bins, bg, fwd, up, s);
+  if (st) return st;
+  return ls_render_bwd_project(b, pose, p, bins, grads, pose_grad, s);
+}
+
+ls_status ls_render_stats(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const ls_image* fwd,
+                          int64_t* stats, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if (!fwd || !fwd->n_last || !stats) return fail(LS_ERR_INVALID, "NULL arguments");
+  launch_render_stats(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, fwd->n_last, stats, s);
+  return hip_check("ls_render_stats");
 }
 
 ls_status ls_loss_l1(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,

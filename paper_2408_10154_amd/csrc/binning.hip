@@ -65,34 +65,51 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
   hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
 }
 
-// Exclusive scan of len words in place, one block of 1024 threads.
-// If total_out is given, the total is written there.
-__global__ __launch_bounds__(1024) void k_scan_excl(uint32_t* __restrict__ data, int64_t len,
-                                                    uint32_t* __restrict__ total_out) {
-  __shared__ uint32_t wsum[16];
-  const int tid = threadIdx.x;
-  const int64_t per = (len + 1023) / 1024;
-  const int64_t b = tid * per;
-  const int64_t e = min(b + per, len);
-  uint32_t s = 0;
-  for (int64_t i = b; i < e; ++i) s += data[i];
-  // block exclusive scan of s
-  const int lane = tid & 63, w = tid >> 6;
-  uint32_t x = s;
+// Block-wide exclusive scan of one value per thread (256 threads); returns
+// the exclusive prefix and writes the block total to *total.
+__device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, uint32_t* total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t x = v;
   for (int off = 1; off < 64; off <<= 1) {
     const uint32_t y = __shfl_up(x, off, 64);
     if (lane >= off) x += y;
   }
   if (lane == 63) wsum[w] = x;
   __syncthreads();
-  if (tid == 0) {
-    uint32_t acc = 0;
-    for (int k = 0; k < 16; ++k) { const uint32_t t = wsum[k]; wsum[k] = acc; acc += t; }
-    if (total_out) *total_out = acc;
-  }
+  uint32_t wofs = 0;
+  for (int k = 0; k < w; ++k) wofs += wsum[k];
+  const uint32_t tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   __syncthreads();
-  uint32_t run = x - s + wsum[w];
-  for (int64_t i = b; i < e; ++i) { const uint32_t t = data[i]; data[i] = run; run += t; }
+  *total = tot;
+  return wofs + x - v;
+}
+
+// Exclusive scan of each row of a [rows][len] array in place, one 256-thread
+// block per row; row totals go to totals[row].
+__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, int64_t len,
+                                                   uint32_t* __restrict__ totals) {
+  __shared__ uint32_t wsum[4];
+  uint32_t* row = data + (int64_t)blockIdx.x * len;
+  const int64_t per = (len + 255) / 256;
+  const int64_t b = threadIdx.x * per;
+  const int64_t e = min(b + per, len);
+  uint32_t s = 0;
+  for (int64_t i = b; i < e; ++i) s += row[i];
+  uint32_t tot;
+  uint32_t run = block_excl_scan(s, wsum, &tot);
+  for (int64_t i = b; i < e; ++i) { const uint32_t t = row[i]; row[i] = run; run += t; }
+  if (threadIdx.x == 0) totals[blockIdx.x] = tot;
+}
+
+// Exclusive scan of n <= 256 words in place (one block); the sum goes to
+// data[n].
+__global__ __launch_bounds__(256) void k_scan_small(uint32_t* __restrict__ data, int n) {
+  __shared__ uint32_t wsum[4];
+  const uint32_t v = (int)threadIdx.x < n ? data[threadIdx.x] : 0u;
+  uint32_t tot;
+  const uint32_t x = block_excl_scan(v, wsum, &tot);
+  if ((int)threadIdx.x < n) data[threadIdx.x] = x;
+  if (threadIdx.x == 0) data[n] = tot;
 }
 
 // Stable scatter of one 8-bit digit pass.  Items of a block are taken in
@@ -102,14 +119,15 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                const int32_t* n_dev, int64_t n_static, int64_t cap,
-                                                               int shift, const uint32_t* __restrict__ hist, int nblocks) {
+                                                               int shift, const uint32_t* __restrict__ hist, int nblocks,
+                                                               const uint32_t* __restrict__ digit_base) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[4][256];
   const int n = sort_count(n_dev, n_static, cap);
   const int64_t bbase = (int64_t)blockIdx.x * kSortTile;
   if (bbase >= n) return;  // uniform for the block
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  base[tid] = hist[(int64_t)tid * nblocks + blockIdx.x];
+  base[tid] = digit_base[tid] + hist[(int64_t)tid * nblocks + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int round = 0; round < kSortItems; ++round) {
     const int64_t rbase = bbase + (int64_t)round * kSortThreads;
@@ -151,7 +169,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
   }
 }
 
-// Per-block sums of the tile counts of depth-sorted items.
+// Per-block (4096 items) sums of the tile counts of depth-sorted items.
 __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __restrict__ order,
                                                             const int32_t* __restrict__ tiles, int64_t M,
                                                             uint32_t* __restrict__ bsum) {
@@ -168,60 +186,57 @@ __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __re
   if (threadIdx.x == 0) bsum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// Emission: each thread owns kSortItems consecutive depth-sorted items,
-// scans their counts within the block, and writes (tile key, item) for every
-// tile of each item's rectangle, row by row.  count[0] receives I (from the
-// scan total), count[1] the overflow flag.
-__global__ __launch_bounds__(kSortThreads) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
-                                                       int R, const uint32_t* __restrict__ order,
-                                                       const float4* __restrict__ rec,
-                                                       const int32_t* __restrict__ radius,
-                                                       const int32_t* __restrict__ tiles, int64_t M,
-                                                       const uint32_t* __restrict__ bsum_scanned,
-                                                       const uint32_t* __restrict__ total, int32_t* __restrict__ count,
-                                                       int64_t cap, uint32_t* __restrict__ kout,
-                                                       int32_t* __restrict__ vout) {
+// Exclusive offsets of every depth-sorted item: block offset (scanned bsum)
+// plus the in-block prefix, 16 rounds of 256 items in order.  Also writes
+// count[0] = min(I, cap) and the overflow flag count[1].
+__global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __restrict__ order,
+                                                          const int32_t* __restrict__ tiles, int64_t M,
+                                                          const uint32_t* __restrict__ bsum_scanned, int nbd,
+                                                          uint32_t* __restrict__ offs, int32_t* __restrict__ count,
+                                                          int64_t cap) {
   __shared__ uint32_t wsum[4];
-  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int64_t first = (int64_t)blockIdx.x * kSortTile + (int64_t)tid * kSortItems;
-  uint32_t s = 0;
+  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  uint32_t run = bsum_scanned[blockIdx.x];
   for (int i = 0; i < kSortItems; ++i) {
-    const int64_t k = first + i;
-    if (k < M) s += (uint32_t)tiles[order[k]];
+    const int64_t k = base + i * kSortThreads + threadIdx.x;
+    const uint32_t c = k < M ? (uint32_t)tiles[order[k]] : 0u;
+    uint32_t tot;
+    const uint32_t x = block_excl_scan(c, wsum, &tot);
+    if (k < M) offs[k] = run + x;
+    run += tot;
   }
-  uint32_t x = s;
-  for (int off = 1; off < 64; off <<= 1) {
-    const uint32_t y = __shfl_up(x, off, 64);
-    if (lane >= off) x += y;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    const int64_t I = bsum_scanned[nbd];
+    count[0] = (int32_t)min(I, cap);
+    count[1] = I > cap ? 1 : 0;
   }
-  if (lane == 63) wsum[w] = x;
-  __syncthreads();
-  uint32_t wofs = 0;
-  for (int k = 0; k < w; ++k) wofs += wsum[k];
-  uint64_t pos = (uint64_t)bsum_scanned[blockIdx.x] + wofs + (x - s);
-  if (blockIdx.x == 0 && tid == 0) {
-    const uint32_t I = *total;
-    count[0] = (int32_t)min((int64_t)I, cap);
-    count[1] = (int64_t)I > cap ? 1 : 0;
-  }
-  for (int i = 0; i < kSortItems; ++i) {
-    const int64_t k = first + i;
-    if (k >= M) break;
-    const uint32_t it = order[k];
-    const int nt = tiles[it];
-    if (nt <= 0) continue;
-    const int r = find_segment<int64_t>(item_off, R, (int64_t)it);
-    const JobDev& J = jobs[r];
-    const float4 a = rec[(int64_t)it * 3];
-    const Rect rc = tile_rect(a.x, a.y, radius[it], J.TX, J.TY);
-    for (int ty = rc.y0; ty < rc.y1; ++ty) {
-      for (int tx = rc.x0; tx < rc.x1; ++tx) {
-        if ((int64_t)pos < cap) {
-          kout[pos] = (uint32_t)(J.tile_off + ty * J.TX + tx);
-          vout[pos] = (int32_t)it;
-        }
-        ++pos;
+}
+
+// Emission, one thread per depth-sorted item: writes (tile key, item) for
+// every tile of the item's rectangle, row by row, at its offset.
+__global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
+                                              int R, const uint32_t* __restrict__ order,
+                                              const float4* __restrict__ rec, const int32_t* __restrict__ radius,
+                                              const int32_t* __restrict__ tiles, int64_t M,
+                                              const uint32_t* __restrict__ offs, int64_t cap,
+                                              uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= M) return;
+  const uint32_t it = order[k];
+  const int nt = tiles[it];
+  if (nt <= 0) return;
+  const int r = find_segment<int64_t>(item_off, R, (int64_t)it);
+  const JobDev& J = jobs[r];
+  const float4 a = rec[(int64_t)it * 3];
+  const Rect rc = tile_rect(a.x, a.y, radius[it], J.TX, J.TY);
+  int64_t pos = offs[k];
+  for (int ty = rc.y0; ty < rc.y1; ++ty) {
+    for (int tx = rc.x0; tx < rc.x1; ++tx) {
+      if (pos < cap) {
+        kout[pos] = (uint32_t)(J.tile_off + ty * J.TX + tx);
+        vout[pos] = (int32_t)it;
       }
+      ++pos;
     }
   }
 }
@@ -246,14 +261,16 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
-// One LSD pass: histogram, scan, scatter.
+// One LSD pass: histogram, per-digit row scan, digit-total scan, scatter.
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const int32_t* n_dev,
-                       int64_t n_static, int64_t cap, int shift, uint32_t* hist, int nblocks, hipStream_t s) {
+                       int64_t n_static, int64_t cap, int shift, uint32_t* hist, uint32_t* digit_base, int nblocks,
+                       hipStream_t s) {
   hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift, hist,
                      nblocks);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, hist, (int64_t)256 * nblocks, (uint32_t*)nullptr);
+  hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, s, hist, (int64_t)nblocks, digit_base);
+  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(256), 0, s, digit_base, 256);
   hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_dev, n_static,
-                     cap, shift, (const uint32_t*)hist, nblocks);
+                     cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_base);
 }
 
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
@@ -262,27 +279,30 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s) {
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const int nbd = (int)((M + kSortTile - 1) / kSortTile);
+  uint32_t* digit_base = bsum + nbd + 8;  // 257 words after the block sums
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec4, tiles, M, dk0, dv0);
   uint32_t *ka = dk0, *va = dv0, *kb = dk1, *vb = dv1;
   for (int shift = 0; shift < 32; shift += 8) {
-    radix_pass(ka, va, kb, vb, nullptr, M, M, shift, hist, nbd, s);
+    radix_pass(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, s);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
   const uint32_t* order = va;
+  uint32_t* offs = ka;  // the free key buffer holds the per-item offsets
   hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, bsum);
-  hipLaunchKernelGGL(k_scan_excl, dim3(1), dim3(1024), 0, s, bsum, (int64_t)nbd, bsum + nbd);
+  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, s, bsum, (int64_t)nbd, bsum + nbd);
+  hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const uint32_t*)bsum, nbd,
+                     offs, count, cap);
   // emission lands in the buffer that, after tile_passes ping-pongs, is the output
   uint32_t* ek = (tile_passes & 1) ? tk : tile_of;
   uint32_t* ev = (tile_passes & 1) ? tv : reinterpret_cast<uint32_t*>(item);
   uint32_t* ok = (tile_passes & 1) ? tile_of : tk;
   uint32_t* ov = (tile_passes & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
-  hipLaunchKernelGGL(k_emit, dim3(nbd), dim3(kSortThreads), 0, s, jobs, item_off_d, R, order, rec4, radius, tiles, M,
-                     (const uint32_t*)bsum, (const uint32_t*)(bsum + nbd), count, cap, ek,
-                     reinterpret_cast<int32_t*>(ev));
+  hipLaunchKernelGGL(k_emit, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, jobs, item_off_d, R, order, rec4,
+                     radius, tiles, M, (const uint32_t*)offs, cap, ek, reinterpret_cast<int32_t*>(ev));
   const int nbt = (int)((cap + kSortTile - 1) / kSortTile);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {
-    radix_pass(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, nbt, s);
+    radix_pass(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, digit_base, nbt, s);
     std::swap(ek, ok);
     std::swap(ev, ov);
   }

@@ -5,6 +5,7 @@
 // every lane reads the same record (LDS broadcast).  The forward stops a
 // block's chunk loop once every pixel of the tile has terminated.
 #include "common.h"
+#include "kernels.h"
 
 namespace ls {
 
@@ -224,9 +225,67 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
   }
 }
 
+// Work statistics of a forward pass: entries evaluated and composited.
+__global__ __launch_bounds__(kBlock) void k_render_stats(const JobDev* __restrict__ jobs,
+                                                         const int32_t* __restrict__ tile_off, int R, int T_total,
+                                                         const float4* __restrict__ rec,
+                                                         const int32_t* __restrict__ items,
+                                                         const int32_t* __restrict__ range,
+                                                         const int32_t* __restrict__ fwd_n,
+                                                         unsigned long long* __restrict__ stats) {
+  __shared__ float4 s0[kBlock], s1[kBlock];
+  const int tile = xcd_remap(blockIdx.x, T_total);
+  if (tile >= T_total) return;
+  const TileCtx c = tile_ctx(jobs, tile_off, R, tile);
+  const int start = range[2 * tile], end = range[2 * tile + 1];
+  const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
+  const int nl = c.inside ? fwd_n[c.pix] : 0;
+  unsigned long long visited = c.inside ? (unsigned long long)min(nl + 1, end - start) : 0ull;
+  unsigned long long comp = 0;
+  for (int chunk = start; chunk < end; chunk += kBlock) {
+    const int e = chunk + threadIdx.x;
+    if (e < end) {
+      const int64_t it = items[e];
+      s0[threadIdx.x] = rec[it * 3 + 0];
+      s1[threadIdx.x] = rec[it * 3 + 1];
+    }
+    __syncthreads();
+    const int cnt = min(kBlock, end - chunk);
+    for (int j = 0; j < cnt; ++j) {
+      if (chunk + j - start >= nl) break;
+      const float4 a = s0[j];
+      const float4 b = s1[j];
+      const float dx = fx - a.x, dy = fy - a.y;
+      const float sig = falloff(a.z, a.w, b.x, dx, dy);
+      if (sig < 0.f) continue;
+      const float al = fminf(LS_ALPHA_MAX, b.y * __expf(-sig));
+      if (al >= LS_ALPHA_MIN) ++comp;
+    }
+    __syncthreads();
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    visited += __shfl_xor(visited, off, 64);
+    comp += __shfl_xor(comp, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    atomicAdd(stats, visited);
+    atomicAdd(stats + 1, comp);
+  }
+}
+
 }  // namespace ls
 
 namespace ls {
+void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
+                         const int32_t* items, const int32_t* range, const int32_t* nl, int64_t* stats,
+                         hipStream_t s) {
+  launch_fill_i32(reinterpret_cast<int32_t*>(stats), 4, 0, s);
+  if (T <= 0) return;
+  hipLaunchKernelGGL(k_render_stats, dim3(8 * ((T + 7) / 8)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
+                     reinterpret_cast<const float4*>(rec), items, range, nl,
+                     reinterpret_cast<unsigned long long*>(stats));
+}
+
 static inline int xcd_grid(int total) { return 8 * ((total + 7) / 8); }
 
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,

@@ -11,7 +11,7 @@ void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk,
                     int32_t* radius, int32_t* tiles, hipStream_t s);
 
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
-                        const int32_t* radius, const float* g2d, const GradDev* grads, int want_gauss,
+                        const int32_t* radius, float* g2d, const GradDev* grads, int want_gauss,
                         float* pose_part, int want_pose, float* pose_grad, hipStream_t s);
 
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
@@ -27,6 +27,9 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
                           const int32_t* items, const int32_t* range, const float* bg, const float* Tf,
                           const int32_t* nl, const float* up_rgb, const float* up_depth, const float* up_alpha,
                           const float* up_scale, float* g2d, hipStream_t s);
+
+void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
+                         const int32_t* items, const int32_t* range, const int32_t* nl, int64_t* stats, hipStream_t s);
 
 void launch_loss_l1(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
                     const float* pred_depth, const float* tgt_rgb, const float* tgt_depth, float* g_rgb,

@@ -105,7 +105,7 @@ __device__ __forceinline__ void store_grad(float* p, float v, bool shared) {
 // the Gaussian parameters and to the per-render pose correction.
 __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
                                                      int R, const float* __restrict__ pose,
-                                                     const int32_t* __restrict__ radius, const float* __restrict__ g2d,
+                                                     const int32_t* __restrict__ radius, float* __restrict__ g2d,
                                                      const GradDev* __restrict__ grads, int want_gauss,
                                                      float* __restrict__ pose_part, int want_pose) {
   const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
@@ -118,7 +118,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
 
   const int64_t item = J.item_off + g;
   if (g < n && radius[item] > 0) {
-    const float* gi = g2d + item * kGrad2D;
+    float* gp = g2d + item * kGrad2D;
+    float gi[kGrad2D];
+#pragma unroll
+    for (int q = 0; q < kGrad2D; ++q) {
+      gi[q] = gp[q];
+      gp[q] = 0.f;  // leave the accumulator cleared for the next backward
+    }
     const float du = gi[0], dv = gi[1], dA = gi[2], dB = gi[3], dC = gi[4];
     const float dop = gi[5], dz = gi[6];
 
@@ -286,7 +292,7 @@ void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk,
                        radius, tiles);
 }
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
-                        const int32_t* radius, const float* g2d, const GradDev* grads, int want_gauss,
+                        const int32_t* radius, float* g2d, const GradDev* grads, int want_gauss,
                         float* pose_part, int want_pose, float* pose_grad, hipStream_t s) {
   if (nblk > 0)
     hipLaunchKernelGGL(k_project_bwd, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius, g2d, grads,

@@ -92,6 +92,10 @@ _PROTOS = {
     "ls_render_fwd": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image), _P]),
     "ls_render_bwd": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
                                   C.POINTER(ls_image_grad), _P, _P, _P]),
+    "ls_render_bwd_tiles": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
+                                        C.POINTER(ls_image_grad), _P]),
+    "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, _P]),
+    "ls_render_stats": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), C.POINTER(ls_image), _P, _P]),
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
@@ -168,6 +172,18 @@ def ls_render_fwd(h, proj, bins, bg, img, stream):
 def ls_render_bwd(h, pose, proj, bins, bg, fwd, up, grads, pose_grad, stream):
     return _call("ls_render_bwd", h, pose, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), grads,
                  pose_grad, stream)
+
+
+def ls_render_bwd_tiles(h, proj, bins, bg, fwd, up, stream):
+    return _call("ls_render_bwd_tiles", h, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), stream)
+
+
+def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, stream):
+    return _call("ls_render_bwd_project", h, pose, C.byref(proj), C.byref(bins), grads, pose_grad, stream)
+
+
+def ls_render_stats(h, proj, bins, fwd, stats, stream):
+    return _call("ls_render_stats", h, C.byref(proj), C.byref(bins), C.byref(fwd), stats, stream)
 
 
 def ls_loss_l1(h, pred, tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_scale, stream):

@@ -188,6 +188,32 @@ class RenderBatch:
         L.ls_render_bwd(self.h, _ptr(pose), self.proj, self.bins, bgc, self.image, up, garr, _ptr(pose_grad),
                         _stream())
 
+    def render_bwd_tiles(self, up_rgb=None, up_depth=None, up_alpha=None, scale=None, bg=None):
+        self._check_dev(up_rgb, 3 * self.P, name="up_rgb")
+        self._check_dev(up_depth, self.P, name="up_depth")
+        self._check_dev(up_alpha, self.P, name="up_alpha")
+        self._check_dev(scale, self.R, name="scale")
+        up = L.ls_image_grad(*[None if t is None else t.data_ptr() for t in (up_rgb, up_depth, up_alpha, scale)])
+        bgc = (C.c_float * 3)(*bg) if bg is not None else None
+        L.ls_render_bwd_tiles(self.h, self.proj, self.bins, bgc, self.image, up, _stream())
+
+    def render_bwd_project(self, grads=None, pose=None, pose_grad=None):
+        self._check_pose(pose)
+        self._check_dev(pose_grad, 7 * self.R, name="pose_grad")
+        garr = None
+        if grads is not None:
+            if len(grads) != self.R:
+                raise ValueError("need one gradient set per render")
+            garr = (L.ls_gaussian_grads * self.R)(*[g.grads_c() for g in grads])
+        L.ls_render_bwd_project(self.h, _ptr(pose), self.proj, self.bins, garr, _ptr(pose_grad), _stream())
+
+    def render_stats(self):
+        """(entries evaluated, entries composited) of the last forward (syncs)."""
+        st = torch.zeros(2, dtype=torch.int64, device=self.device)
+        L.ls_render_stats(self.h, self.proj, self.bins, self.image, _ptr(st), _stream())
+        v = st.cpu().numpy()
+        return int(v[0]), int(v[1])
+
     def loss_l1(self, tgt_rgb, tgt_depth, loss=None, grad_rgb=None, grad_depth=None, grad_scale=None):
         dev = self.device
         loss = torch.zeros(self.R, dtype=torch.float32, device=dev) if loss is None else loss
