@@ -212,32 +212,51 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
   }
 }
 
-// Emission, one thread per depth-sorted item: writes (tile key, item) for
-// every tile of the item's rectangle, row by row, at its offset.
+constexpr int kEmitPer = 8;  // instances per emission thread
+
+// Emission, balanced over instances: thread t owns instances
+// [8 t, 8 t + 8) of the output, finds the depth-sorted item that owns the
+// first one by binary search over the item offsets, and walks forward through
+// the items' tile rectangles (row by row).  Output runs are contiguous per
+// thread, so neighbouring threads write neighbouring addresses.
 __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
                                               int R, const uint32_t* __restrict__ order,
                                               const float4* __restrict__ rec, const int32_t* __restrict__ radius,
                                               const int32_t* __restrict__ tiles, int64_t M,
-                                              const uint32_t* __restrict__ offs, int64_t cap,
+                                              const uint32_t* __restrict__ offs, const int32_t* __restrict__ count,
                                               uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (k >= M) return;
-  const uint32_t it = order[k];
-  const int nt = tiles[it];
-  if (nt <= 0) return;
-  const int r = find_segment<int64_t>(item_off, R, (int64_t)it);
-  const JobDev& J = jobs[r];
-  const float4 a = rec[(int64_t)it * 3];
-  const Rect rc = tile_rect(a.x, a.y, radius[it], J.TX, J.TY);
-  int64_t pos = offs[k];
-  for (int ty = rc.y0; ty < rc.y1; ++ty) {
-    for (int tx = rc.x0; tx < rc.x1; ++tx) {
-      if (pos < cap) {
-        kout[pos] = (uint32_t)(J.tile_off + ty * J.TX + tx);
-        vout[pos] = (int32_t)it;
+  const int64_t I = count[0];  // already clamped to the capacity
+  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kEmitPer;
+  if (i0 >= I) return;
+  const int64_t iend = min(i0 + kEmitPer, I);
+  int64_t lo = 0, hi = M - 1;  // largest k with offs[k] <= i0 (that item has tiles > 0)
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if ((int64_t)offs[mid] <= i0) lo = mid; else hi = mid - 1;
+  }
+  int64_t k = lo;
+  int64_t i = i0;
+  while (i < iend && k < M) {
+    const uint32_t it = order[k];
+    const int nt = tiles[it];
+    if (nt > 0) {
+      const int r = find_segment<int64_t>(item_off, R, (int64_t)it);
+      const JobDev& J = jobs[r];
+      const float4 a = rec[(int64_t)it * 3];
+      const Rect rc = tile_rect(a.x, a.y, radius[it], J.TX, J.TY);
+      const int wdt = rc.x1 - rc.x0;
+      int q = (int)(i - (int64_t)offs[k]);
+      int dy = q / wdt, dx = q - dy * wdt;
+      int key = J.tile_off + (rc.y0 + dy) * J.TX + rc.x0 + dx;
+      for (; q < nt && i < iend; ++q, ++i) {
+        kout[i] = (uint32_t)key;
+        vout[i] = (int32_t)it;
+        ++dx;
+        ++key;
+        if (dx == wdt) { dx = 0; key += J.TX - wdt; }
       }
-      ++pos;
     }
+    ++k;
   }
 }
 
@@ -298,8 +317,11 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   uint32_t* ev = (tile_passes & 1) ? tv : reinterpret_cast<uint32_t*>(item);
   uint32_t* ok = (tile_passes & 1) ? tile_of : tk;
   uint32_t* ov = (tile_passes & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
-  hipLaunchKernelGGL(k_emit, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, jobs, item_off_d, R, order, rec4,
-                     radius, tiles, M, (const uint32_t*)offs, cap, ek, reinterpret_cast<int32_t*>(ev));
+  const int64_t emit_threads = (cap + kEmitPer - 1) / kEmitPer;
+  if (emit_threads > 0)
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((emit_threads + 255) / 256)), dim3(256), 0, s, jobs, item_off_d, R, order,
+                       rec4, radius, tiles, M, (const uint32_t*)offs, (const int32_t*)count, ek,
+                       reinterpret_cast<int32_t*>(ev));
   const int nbt = (int)((cap + kSortTile - 1) / kSortTile);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {
     radix_pass(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, digit_base, nbt, s);

@@ -34,6 +34,61 @@ __device__ __forceinline__ TileCtx tile_ctx(const JobDev* jobs, const int32_t* t
   return c;
 }
 
+// Which of the block's four 16x4-pixel wave bands the Gaussian can reach
+// with alpha >= 1/255: the support {o exp(-sigma) >= 1/255} is the ellipse
+// sigma <= ln(255 o), whose bounding box has half-extents
+// sqrt(2 ln(255 o) Sigma_xx) and sqrt(2 ln(255 o) Sigma_yy), Sigma = conic^-1.
+// Widened by 0.1% + 0.02 px so that FP32 rounding never drops a contributor.
+__device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int tile_x0, int tile_y0) {
+  const float o = b.y;
+  if (!(o >= LS_ALPHA_MIN)) return 0u;
+  const float A = a.z, B = a.w, C = b.x;
+  const float dq = A * C - B * B;
+  if (!(dq > 0.f)) return 0xFu;
+  const float st = 2.f * __logf(o * (1.0f / LS_ALPHA_MIN));
+  const float hx = sqrtf(fmaxf(st * C / dq, 0.f)) * 1.001f + 0.02f;
+  const float hy = sqrtf(fmaxf(st * A / dq, 0.f)) * 1.001f + 0.02f;
+  const float x0 = (float)tile_x0 + 0.5f, x1 = (float)tile_x0 + 15.5f;
+  if (a.x + hx < x0 || a.x - hx > x1) return 0u;
+  uint32_t m = 0;
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const float y0 = (float)(tile_y0 + 4 * w) + 0.5f, y1 = y0 + 3.f;
+    if (!(a.y + hy < y0 || a.y - hy > y1)) m |= 1u << w;
+  }
+  return m;
+}
+
+// Order-preserving compaction of the staged entries into one list per wave
+// band: entry e (staged by thread e, e < cnt) goes to the list of every band
+// in mask_e.  Each staging wave counts its entries per band with ballots; the
+// counts are combined in wave order.  Must be called by all threads.
+__device__ __forceinline__ void build_wave_lists(uint32_t mask_e, bool valid, uint8_t (*list)[kBlock],
+                                                 uint32_t (*cnts)[4], uint32_t* wcount) {
+  const int lane = threadIdx.x & 63, sw = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t bal[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    bal[w] = __ballot(valid && ((mask_e >> w) & 1u));
+    if (lane == 0) cnts[sw][w] = (uint32_t)__popcll(bal[w]);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    if (valid && ((mask_e >> w) & 1u)) {
+      uint32_t pos = (uint32_t)__popcll(bal[w] & lt);
+      for (int k = 0; k < sw; ++k) pos += cnts[k][w];
+      list[w][pos] = (uint8_t)threadIdx.x;
+    }
+  }
+  if (threadIdx.x < 4) {
+    const int w = threadIdx.x;
+    wcount[w] = cnts[0][w] + cnts[1][w] + cnts[2][w] + cnts[3][w];
+  }
+  __syncthreads();
+}
+
 __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
@@ -43,11 +98,16 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restri
                                                           float* __restrict__ out_depth, float* __restrict__ out_alpha,
                                                           float* __restrict__ out_T, int32_t* __restrict__ out_n) {
   __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
+  __shared__ uint8_t slist[4][kBlock];
+  __shared__ uint32_t scnt[4][4];
+  __shared__ uint32_t swc[4];
   const int tile = xcd_remap(blockIdx.x, T_total);
   if (tile >= T_total) return;
   const TileCtx c = tile_ctx(jobs, tile_off, R, tile);
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
+  const int w = threadIdx.x >> 6;
+  const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
 
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
   bool done = !c.inside;
@@ -55,16 +115,21 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restri
   for (int chunk = start; chunk < end; chunk += kBlock) {
     if (__syncthreads_count(done) == kBlock) break;
     const int e = chunk + threadIdx.x;
+    uint32_t m = 0;
     if (e < end) {
       const int64_t it = items[e];
-      s0[threadIdx.x] = rec[it * 3 + 0];
-      s1[threadIdx.x] = rec[it * 3 + 1];
+      const float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+      s0[threadIdx.x] = a;
+      s1[threadIdx.x] = b;
       s2[threadIdx.x] = rec[it * 3 + 2];
+      m = wave_mask(a, b, tx0, ty0);
     }
-    __syncthreads();
-    const int cnt = min(kBlock, end - chunk);
-    for (int j = 0; j < cnt; ++j) {
+    build_wave_lists(m, e < end, slist, scnt, swc);
+    const int cw = (int)swc[w];
+    for (int jj = 0; jj < cw; ++jj) {
+      if (__ballot(!done) == 0ull) break;  // whole wave finished
       if (done) continue;
+      const int j = slist[w][jj];
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
@@ -100,14 +165,27 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restri
   out_n[c.pix] = nlast;
 }
 
+// Sum over each 16-lane row of the wave; every lane of a row gets its row sum.
+__device__ __forceinline__ float row_sum16(float v) {
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+  return v;
+}
+
+constexpr int kBwdChunk = 32;   // list entries staged per round
+constexpr int kPartRow = kGrad2D;          // floats per row partial
+constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row partials, padded against bank conflicts
+
 // Backward.  Per pixel, walking the list from n_last - 1 down to 0 with the
 // transmittance recovered as T_i = T_{i+1} / (1 - alpha_i) and the running
 // "behind" value acc = sum_{j>i} alpha_j prod_{i<k<j}(1 - alpha_k) v_j +
 // prod_{k>i}(1 - alpha_k)(bg . gC - gA), where v_j = c_j . gC + z_j gD:
 //   dL/dalpha_i = T_i (v_i - acc_i).
-// The ten image-space gradients of each Gaussian are summed over the wave
-// (DPP), the four wave sums over the block (LDS, fixed order), and added to
-// the item's accumulator with one atomic per value and tile.
+// The ten image-space gradients of each Gaussian are summed over each 16-lane
+// row (DPP), the 16 row sums of the block over LDS in a fixed order, and
+// added to the item's accumulator with one atomic per value and tile.
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
@@ -120,9 +198,13 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
                                                           const float* __restrict__ up_alpha,
                                                           const float* __restrict__ up_scale,
                                                           float* __restrict__ g2d) {
-  __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
-  __shared__ int32_t sit[kBlock];
-  __shared__ float part[kBlock][4][kGrad2D];
+  __shared__ float4 s0[kBwdChunk], s1[kBwdChunk], s2[kBwdChunk];
+  __shared__ int32_t sit[kBwdChunk];
+  __shared__ uint32_t smask[kBwdChunk];
+  __shared__ uint8_t slist[4][kBwdChunk];
+  __shared__ uint32_t swc[4];
+  __shared__ __attribute__((aligned(16))) float part[kBwdChunk * kPartStride];
+  static_assert(kBwdChunk <= 64 && kBlock % kBwdChunk == 0, "chunk must fit one staging wave");
   __shared__ int smax;
   const int tile = xcd_remap(blockIdx.x, T_total);
   if (tile >= T_total) return;
@@ -131,6 +213,8 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = w * 4 + (lane >> 4);  // 0..15, one 16-pixel row of the tile
+  const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
 
   float T = 1.f, gR = 0.f, gG = 0.f, gB = 0.f, gD = 0.f, acc = 0.f;
   int nl = 0;
@@ -151,18 +235,38 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
   __syncthreads();
   const int last = min(start + smax, end);  // exclusive end of the entries any pixel visited
 
-  for (int chunk_end = last; chunk_end > start; chunk_end -= kBlock) {
-    const int chunk = max(start, chunk_end - kBlock);
+  for (int chunk_end = last; chunk_end > start; chunk_end -= kBwdChunk) {
+    const int chunk = max(start, chunk_end - kBwdChunk);
     const int cnt = chunk_end - chunk;
-    if ((int)threadIdx.x < cnt) {
-      const int64_t it = items[chunk + threadIdx.x];
-      sit[threadIdx.x] = (int32_t)it;
-      s0[threadIdx.x] = rec[it * 3 + 0];
-      s1[threadIdx.x] = rec[it * 3 + 1];
-      s2[threadIdx.x] = rec[it * 3 + 2];
+    if (w == 0) {
+      // wave 0 stages the chunk and builds each band's list in list order
+      uint32_t m = 0;
+      const bool valid = lane < cnt;
+      if (valid) {
+        const int64_t it = items[chunk + lane];
+        const float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+        sit[lane] = (int32_t)it;
+        s0[lane] = a;
+        s1[lane] = b;
+        s2[lane] = rec[it * 3 + 2];
+        m = wave_mask(a, b, tx0, ty0);
+        smask[lane] = m;
+      }
+      const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+      for (int b2 = 0; b2 < 4; ++b2) {
+        const bool in = valid && ((m >> b2) & 1u);
+        const uint64_t bal = __ballot(in);
+        if (in) slist[b2][__popcll(bal & lt)] = (uint8_t)lane;
+        if (lane == 0) swc[b2] = (uint32_t)__popcll(bal);
+      }
     }
     __syncthreads();
-    for (int j = cnt - 1; j >= 0; --j) {
+    const int cw = (int)swc[w];
+    for (int jj = cw - 1; jj >= 0; --jj) {
+      const int j = slist[w][jj];
+      float* pj = part + j * kPartStride + row * kPartRow;
+      const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;  // list position
       float g[kGrad2D];
 #pragma unroll
@@ -191,8 +295,8 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
             g[9] = wgt * gB;
             g[6] = wgt * gD;
             const float dG = (G < LS_ALPHA_MAX) ? dal : 0.f;
-            g[5] = dG * ex;                  // dL/d opacity
-            const float ds = -dG * G;        // dL/d sigma
+            g[5] = dG * ex;                      // dL/d opacity
+            const float ds = -dG * G;            // dL/d sigma
             g[0] = -ds * (a.z * dx + a.w * dy);  // dL/du
             g[1] = -ds * (a.w * dx + b.x * dy);  // dL/dv
             g[2] = 0.5f * ds * dx * dx;          // dL/dA
@@ -203,22 +307,33 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
       }
       if (__ballot(act) != 0ull) {
 #pragma unroll
-        for (int q = 0; q < kGrad2D; ++q) {
-          const float s = wave_sum(g[q]);
-          if (lane == 0) part[j][w][q] = s;
+        for (int q = 0; q < kGrad2D; ++q) g[q] = row_sum16(g[q]);
+        if (lead) {
+#pragma unroll
+          for (int q = 0; q < kGrad2D; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(g[q], g[q + 1]);
         }
-      } else if (lane < kGrad2D) {
-        part[j][w][lane] = 0.f;
+      } else if (lead) {
+#pragma unroll
+        for (int q = 0; q < kGrad2D; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(0.f, 0.f);
       }
     }
     __syncthreads();
-    if ((int)threadIdx.x < cnt) {
-      const int j = threadIdx.x;
-      float* dst = g2d + (int64_t)sit[j] * kGrad2D;
+    {
+      // 4 threads per entry; thread (j, t) sums values t, t + 4, t + 8 over the 16 rows in order
+      // rows of bands that did not visit the entry hold stale values: skip them
+      constexpr int kPer = kBlock / kBwdChunk;  // threads per entry
+      const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
+      const uint32_t mj = j < cnt ? smask[j] : 0u;
+      if (mj != 0u) {
+        float* dst = g2d + (int64_t)sit[j] * kGrad2D;
+        const float* pj = part + j * kPartStride;
+        for (int q = t; q < kGrad2D; q += kPer) {
+          float s = 0.f;
 #pragma unroll
-      for (int q = 0; q < kGrad2D; ++q) {
-        const float s = (part[j][0][q] + part[j][1][q]) + (part[j][2][q] + part[j][3][q]);
-        if (s != 0.f) atomic_add_f32(dst + q, s);
+          for (int r2 = 0; r2 < 16; ++r2)
+            if ((mj >> (r2 >> 2)) & 1u) s += pj[r2 * kPartRow + q];
+          if (s != 0.f) atomic_add_f32(dst + q, s);
+        }
       }
     }
     __syncthreads();
