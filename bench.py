@@ -37,6 +37,24 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
 
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if the kernel source changed since the counters were taken."""
+    import hashlib
+
+    src = b"".join(open(os.path.join(ROOT, "paper_2408_10154_amd", "csrc", f), "rb").read()
+                   for f in ("composite.hip", "common.h"))
+    digest = hashlib.sha256(src).hexdigest()[:16]
+    path = os.path.join(ROOT, "profiles", "render_loop_200k_1200x680_hbm_counters.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        f = line.split()
+        if len(f) == 5 and f[0] == "traffic" and f[1] == kernel and f[3] == "source":
+            return int(f[2]) if f[4] == digest else None
+    return None
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -215,7 +233,7 @@ def main():
                    "instances": instances, "parallelism": "single GPU"},
         "roofline": {"bound": "alu", "kernel": "composite_" + dom, "achieved": round(achieved, 3),
                      "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s", "frac": round(achieved / PEAK_FP32_TFLOPS, 4),
-                     "traffic": None},
+                     "traffic": measured_traffic("composite_" + dom)},
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "fragments": {"evaluated": evaluated, "composited": composited},
         "loss": {"first_timed": round(loss0, 5), "last": round(loss1, 5)},
