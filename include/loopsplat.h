@@ -225,9 +225,11 @@ ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected
 
 /* First half of ls_render_bwd: per tile, back-to-front recomputation and
  * accumulation of dL/d(u, v, conic, opacity, z, rgb) per item into the
- * workspace (one kernel). */
+ * workspace (one kernel).  flags: LS_BWD_POSE_ONLY accumulates only the
+ * gradients a pose correction depends on (u, v, conic, z). */
+#define LS_BWD_POSE_ONLY 1u
 ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
-                              const ls_image* fwd, const ls_image_grad* up, hipStream_t s);
+                              const ls_image* fwd, const ls_image_grad* up, uint32_t flags, hipStream_t s);
 
 /* Second half of ls_render_bwd: chains the accumulated image-space gradients
  * through the EWA projection to the Gaussian parameters and the pose, and
@@ -273,6 +275,57 @@ ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, fl
 /* Fills `count` int32 words at `ptr` with `value` (a kernel, never a memset
  * node, so it is safe inside captured graphs). */
 ls_status ls_fill_i32(int32_t* ptr, int64_t count, int32_t value, hipStream_t s);
+
+/* ---------------------------------------------------------------------------
+ * 3DGS registration as keyframe localisation (Sec. 3.2).
+ *
+ * Submaps P and Q are each reconstructed from their own keyframes and are not
+ * aligned; T_{P->Q} maps P's frame into Q's.  Every keyframe i of P (pose T_i
+ * in P's frame, measurements (I, D)_i) is localised in Q: Q is rendered with
+ * world-to-camera Delta_i o T_i^-1 and Delta_i is optimised (Q fixed) for the
+ * L1 colour + depth loss, giving E_i = T_i Delta_i^-1 T_i^-1 ~ T_{P->Q}.
+ * Keyframes of Q are localised in P the same way (estimates of T_{Q->P}).
+ * The 2V estimates are fused by weighted rotation averaging with weights
+ * 1/eps_i (Eq. 7) and a weighted mean of the translations.
+ * ------------------------------------------------------------------------- */
+
+typedef struct {
+  ls_gaussians P, Q;     /* device Gaussian sets, each in its own submap frame */
+  int32_t vP, vQ;        /* keyframes of P and of Q (vP + vQ >= 1) */
+  const float* rgbP;     /* device [vP][3][H][W] measurements of P's keyframes */
+  const float* depthP;   /* device [vP][H][W]; pixels with depth <= 0 are not used */
+  const float* c2wP;     /* host   [vP][12] row-major 3x4 camera-to-world, P's frame */
+  const float* rgbQ;     /* device [vQ][3][H][W] */
+  const float* depthQ;   /* device [vQ][H][W] */
+  const float* c2wQ;     /* host   [vQ][12], Q's frame */
+  ls_intrinsics K;       /* shared by all keyframes */
+} ls_pair;
+
+typedef struct {
+  int32_t iters;            /* Adam iterations per view (>= 1) */
+  float lr_rot, lr_trans;   /* learning rates of the quaternion and the translation */
+  float beta1, beta2, adam_eps;
+} ls_reg_params;
+
+typedef struct {
+  float T_PQ[12];     /* fused T_{P->Q}, row-major 3x4 */
+  float* per_view_T;  /* host [vP + vQ][12] or NULL: E_i (P views: ~T_{P->Q}; Q views: ~T_{Q->P}) */
+  float* residual;    /* host [vP + vQ] or NULL: eps_i, the final L1 loss of each view */
+  int32_t status;     /* LS_OK, or the error of this pair */
+  int32_t iters_done;
+} ls_reg_result;
+
+/* Registers one pair with all 2V views in one launch set per iteration.
+ * Blocks until the result is on the host.  Allocates its device buffers for
+ * the duration of the call.  Errors: LS_ERR_INVALID (bad sizes, NULL
+ * pointers), LS_ERR_NONFINITE (non-finite poses or loss), LS_ERR_HIP. */
+ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg_result* out, hipStream_t s);
+
+/* Host-only fusion of per-view estimates (Eq. 7 + weighted translation mean):
+ * est [n][12] row-major 3x4, resid [n], reverse [n] (1 for a Q->P estimate,
+ * inverted before averaging) -> out [12].  Weights 1/max(eps, 1e-12); the
+ * rotation maximises tr(R^T sum_i w_i R_i) over SO(3).  No GPU needed. */
+ls_status ls_fuse_estimates(const double* est, const double* resid, const int32_t* reverse, int32_t n, double* out);
 
 #ifdef __cplusplus
 }

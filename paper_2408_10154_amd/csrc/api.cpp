@@ -146,6 +146,8 @@ int64_t ls_struct_size(const char* name) {
       {"ls_projected", sizeof(ls_projected)},       {"ls_bins", sizeof(ls_bins)},
       {"ls_image", sizeof(ls_image)},               {"ls_image_grad", sizeof(ls_image_grad)},
       {"ls_gaussian_grads", sizeof(ls_gaussian_grads)}, {"ls_adam_group", sizeof(ls_adam_group)},
+      {"ls_pair", sizeof(ls_pair)},                 {"ls_reg_params", sizeof(ls_reg_params)},
+      {"ls_reg_result", sizeof(ls_reg_result)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -319,7 +321,7 @@ ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins*
 }
 
 ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
-                              const ls_image* fwd, const ls_image_grad* up, hipStream_t s) {
+                              const ls_image* fwd, const ls_image_grad* up, uint32_t flags, hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");
   ls_status st;
   if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
@@ -329,7 +331,7 @@ ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls
   const float zero[3] = {0.f, 0.f, 0.f};
   launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
                        fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale,
-                       at<float>(bins->work, L.g2d), s);
+                       at<float>(bins->work, L.g2d), (flags & LS_BWD_POSE_ONLY) ? 1 : 0, s);
   return hip_check("ls_render_bwd_tiles");
 }
 
@@ -378,7 +380,7 @@ ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected
                         const float* bg, const ls_image* fwd, const ls_image_grad* up, const ls_gaussian_grads* grads,
                         float* pose_grad, hipStream_t s) {
   if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
-  ls_status st = ls_render_bwd_tiles(b, p, bins, bg, fwd, up, s);
+  ls_status st = ls_render_bwd_tiles(b, p, bins, bg, fwd, up, grads ? 0u : LS_BWD_POSE_ONLY, s);
   if (st) return st;
   return ls_render_bwd_project(b, pose, p, bins, grads, pose_grad, s);
 }

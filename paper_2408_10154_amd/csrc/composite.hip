@@ -186,6 +186,9 @@ constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row part
 // The ten image-space gradients of each Gaussian are summed over each 16-lane
 // row (DPP), the 16 row sums of the block over LDS in a fixed order, and
 // added to the item's accumulator with one atomic per value and tile.
+// kPoseOnly: only the gradients a pose correction depends on (u, v, conic,
+// depth) are reduced; opacity and colour gradients are left out.
+template <bool kPoseOnly>
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
@@ -307,7 +310,8 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
       }
       if (__ballot(act) != 0ull) {
 #pragma unroll
-        for (int q = 0; q < kGrad2D; ++q) g[q] = row_sum16(g[q]);
+        for (int q = 0; q < kGrad2D; ++q)
+          if (!kPoseOnly || q <= 4 || q == 6) g[q] = row_sum16(g[q]);
         if (lead) {
 #pragma unroll
           for (int q = 0; q < kGrad2D; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(g[q], g[q + 1]);
@@ -328,6 +332,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
         float* dst = g2d + (int64_t)sit[j] * kGrad2D;
         const float* pj = part + j * kPartStride;
         for (int q = t; q < kGrad2D; q += kPer) {
+          if (kPoseOnly && (q == 5 || q >= 7)) continue;
           float s = 0.f;
 #pragma unroll
           for (int r2 = 0; r2 < 16; ++r2)
@@ -415,10 +420,15 @@ void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, in
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, const float* Tf,
                           const int32_t* nl, const float* up_rgb, const float* up_depth, const float* up_alpha,
-                          const float* up_scale, float* g2d, hipStream_t s) {
+                          const float* up_scale, float* g2d, int pose_only, hipStream_t s) {
   if (T <= 0) return;
-  hipLaunchKernelGGL(k_composite_bwd, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
-                     reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth,
-                     up_alpha, up_scale, g2d);
+  if (pose_only)
+    hipLaunchKernelGGL(k_composite_bwd<true>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
+                       reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb,
+                       up_depth, up_alpha, up_scale, g2d);
+  else
+    hipLaunchKernelGGL(k_composite_bwd<false>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
+                       reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb,
+                       up_depth, up_alpha, up_scale, g2d);
 }
 }  // namespace ls

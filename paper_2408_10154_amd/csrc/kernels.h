@@ -26,7 +26,18 @@ void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, in
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, const float* Tf,
                           const int32_t* nl, const float* up_rgb, const float* up_depth, const float* up_alpha,
-                          const float* up_scale, float* g2d, hipStream_t s);
+                          const float* up_scale, float* g2d, int pose_only, hipStream_t s);
+
+// Registration helpers (reg_kernels.hip).
+struct ViewOpt {
+  float lr_rot, lr_trans;
+  int32_t step;    // Adam steps taken so far
+  int32_t active;  // 0: frozen (no update)
+};
+void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s);
+void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, int R, float beta1, float beta2,
+                      float eps, hipStream_t s);
+void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
 
 void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                          const int32_t* items, const int32_t* range, const int32_t* nl, int64_t* stats, hipStream_t s);

@@ -1,0 +1,428 @@
+// 3DGS registration as keyframe localisation (Sec. 3.2) on top of the
+// rasterizer calls: every keyframe of P localised in Q and every keyframe of
+// Q in P, all views of all pairs of an engine in one launch set per Adam
+// iteration, then the Eq. 7 fusion on the host in double precision.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "kernels.h"
+#include "register_engine.h"
+
+namespace ls {
+
+// ------------------------------------------------------------------ host math
+
+void rot_of_quat(const double* q, double* R) {
+  const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  const double w = q[0] / n, x = q[1] / n, y = q[2] / n, z = q[3] / n;
+  R[0] = 1 - 2 * (y * y + z * z); R[1] = 2 * (x * y - w * z);     R[2] = 2 * (x * z + w * y);
+  R[3] = 2 * (x * y + w * z);     R[4] = 1 - 2 * (x * x + z * z); R[5] = 2 * (y * z - w * x);
+  R[6] = 2 * (x * z - w * y);     R[7] = 2 * (y * z + w * x);     R[8] = 1 - 2 * (x * x + y * y);
+}
+
+// 3x4 rigid transforms, row-major [R | t].
+void rigid_inv(const double* A, double* out) {
+  double o[12];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) o[i * 4 + j] = A[j * 4 + i];
+    o[i * 4 + 3] = -(A[0 * 4 + i] * A[3] + A[1 * 4 + i] * A[7] + A[2 * 4 + i] * A[11]);
+  }
+  std::memcpy(out, o, sizeof(o));
+}
+
+void rigid_mul(const double* A, const double* B, double* out) {
+  double o[12];
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) o[i * 4 + j] = A[i * 4 + 0] * B[0 * 4 + j] + A[i * 4 + 1] * B[1 * 4 + j] + A[i * 4 + 2] * B[2 * 4 + j];
+    o[i * 4 + 3] = A[i * 4 + 0] * B[3] + A[i * 4 + 1] * B[7] + A[i * 4 + 2] * B[11] + A[i * 4 + 3];
+  }
+  std::memcpy(out, o, sizeof(o));
+}
+
+// E = C Delta^-1 C^-1 for a keyframe c2w C and its optimised correction Delta.
+void view_estimate(const double* c2w, const float* pose7, double* E) {
+  const double q[4] = {pose7[0], pose7[1], pose7[2], pose7[3]};
+  double D[12];
+  double R[9];
+  rot_of_quat(q, R);
+  for (int i = 0; i < 3; ++i) {
+    for (int j = 0; j < 3; ++j) D[i * 4 + j] = R[i * 3 + j];
+    D[i * 4 + 3] = pose7[4 + i];
+  }
+  double Di[12], Ci[12], tmp[12];
+  rigid_inv(D, Di);
+  rigid_inv(c2w, Ci);
+  rigid_mul(c2w, Di, tmp);
+  rigid_mul(tmp, Ci, E);
+}
+
+// Eigenvector of the largest eigenvalue of a symmetric 4x4 (cyclic Jacobi).
+static void top_eigvec4(double A[4][4], double* out) {
+  double V[4][4] = {{1, 0, 0, 0}, {0, 1, 0, 0}, {0, 0, 1, 0}, {0, 0, 0, 1}};
+  for (int sweep = 0; sweep < 64; ++sweep) {
+    double off = 0;
+    for (int p = 0; p < 4; ++p)
+      for (int q = p + 1; q < 4; ++q) off += A[p][q] * A[p][q];
+    if (off < 1e-30) break;
+    for (int p = 0; p < 4; ++p)
+      for (int q = p + 1; q < 4; ++q) {
+        if (std::fabs(A[p][q]) < 1e-300) continue;
+        const double theta = (A[q][q] - A[p][p]) / (2 * A[p][q]);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+        const double c = 1 / std::sqrt(t * t + 1), s = t * c;
+        for (int k = 0; k < 4; ++k) {  // A <- J^T A J
+          const double akp = A[k][p], akq = A[k][q];
+          A[k][p] = c * akp - s * akq;
+          A[k][q] = s * akp + c * akq;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double apk = A[p][k], aqk = A[q][k];
+          A[p][k] = c * apk - s * aqk;
+          A[q][k] = s * apk + c * aqk;
+        }
+        for (int k = 0; k < 4; ++k) {
+          const double vkp = V[k][p], vkq = V[k][q];
+          V[k][p] = c * vkp - s * vkq;
+          V[k][q] = s * vkp + c * vkq;
+        }
+      }
+  }
+  int best = 0;
+  for (int k = 1; k < 4; ++k)
+    if (A[k][k] > A[best][best]) best = k;
+  for (int k = 0; k < 4; ++k) out[k] = V[k][best];
+}
+
+int fuse_estimates(const double* est, const double* resid, const int32_t* rev, int n, double* out) {
+  double M[9] = {0}, ts[3] = {0}, wsum = 0;
+  for (int i = 0; i < n; ++i) {
+    double e[12];
+    if (rev[i]) rigid_inv(est + 12 * i, e); else std::memcpy(e, est + 12 * i, sizeof(e));
+    const double w = 1.0 / std::max(resid[i], 1e-12);
+    if (!std::isfinite(w)) return LS_ERR_NONFINITE;
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c) M[r * 3 + c] += w * e[r * 4 + c];
+      ts[r] += w * e[r * 4 + 3];
+    }
+    wsum += w;
+  }
+  // argmax_R tr(R^T M) over SO(3): q maximising q^T N q (N quadratic form of tr(R(q)^T M))
+  double N[4][4] = {
+      {M[0] + M[4] + M[8], M[7] - M[5], M[2] - M[6], M[3] - M[1]},
+      {M[7] - M[5], M[0] - M[4] - M[8], M[1] + M[3], M[2] + M[6]},
+      {M[2] - M[6], M[1] + M[3], -M[0] + M[4] - M[8], M[5] + M[7]},
+      {M[3] - M[1], M[2] + M[6], M[5] + M[7], -M[0] - M[4] + M[8]},
+  };
+  double q[4];
+  top_eigvec4(N, q);
+  double R[9];
+  rot_of_quat(q, R);
+  for (int r = 0; r < 3; ++r) {
+    for (int c = 0; c < 3; ++c) out[r * 4 + c] = R[r * 3 + c];
+    out[r * 4 + 3] = ts[r] / wsum;
+  }
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(out[k])) return LS_ERR_NONFINITE;
+  return LS_OK;
+}
+
+// ------------------------------------------------------------------ engine
+
+RegEngine::~RegEngine() { release(); }
+
+void RegEngine::release() {
+  if (batch) ls_batch_destroy(batch);
+  batch = nullptr;
+  if (arena) hipFree(arena);
+  arena = nullptr;
+  if (bins_mem) hipFree(bins_mem);
+  bins_mem = nullptr;
+}
+
+ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) {
+  release();
+  pairs = pairs_in;
+  std::vector<ls_render_job> jobs;
+  first_view.assign(pairs.size() + 1, 0);
+  views.clear();
+  for (size_t p = 0; p < pairs.size(); ++p) {
+    const ls_pair& pr = pairs[p].pair;
+    first_view[p] = (int)jobs.size();
+    for (int dir = 0; dir < 2; ++dir) {
+      const int nv = dir == 0 ? pr.vP : pr.vQ;
+      for (int i = 0; i < nv; ++i) {
+        View v;
+        v.pair = (int)p;
+        v.reverse = dir == 1;
+        v.index = i;
+        for (int k = 0; k < 12; ++k) v.c2w[k] = (dir == 0 ? pairs[p].c2wP : pairs[p].c2wQ)[12 * i + k];
+        double w2c[12];
+        rigid_inv(v.c2w, w2c);
+        ls_render_job j{};
+        j.g = dir == 0 ? pr.Q : pr.P;  // a keyframe of one submap renders the other
+        j.K = pr.K;
+        for (int k = 0; k < 12; ++k) j.w2c[k] = (float)w2c[k];
+        jobs.push_back(j);
+        views.push_back(v);
+      }
+    }
+  }
+  first_view[pairs.size()] = (int)jobs.size();
+  R = (int)jobs.size();
+  ls_status st = ls_batch_create(jobs.data(), R, &batch);
+  if (st) return st;
+  ls_batch_info info{};
+  ls_batch_query(batch, 0, &info);
+  M = info.items;
+  P = info.pixels;
+  T = info.tiles;
+  pix_off.assign(R + 1, 0);
+  ls_batch_offsets(batch, nullptr, pix_off.data(), nullptr);
+
+  // one arena for everything that does not depend on the instance capacity
+  size_t off = 0;
+  auto take = [&](size_t bytes) { const size_t o = off; off = (off + std::max<size_t>(bytes, 4) + 255) & ~size_t(255); return o; };
+  const size_t o_rec = take(48 * (size_t)std::max<int64_t>(M, 1)), o_rad = take(4 * M), o_til = take(4 * M);
+  const size_t o_rgb = take(12 * P), o_dep = take(4 * P), o_alp = take(4 * P), o_T = take(4 * P), o_nl = take(4 * P);
+  const size_t o_trgb = take(12 * P), o_tdep = take(4 * P), o_grgb = take(12 * P), o_gdep = take(4 * P);
+  const size_t o_scale = take(4 * R), o_loss = take(4 * R), o_pose = take(28 * R), o_pg = take(28 * R);
+  const size_t o_m = take(28 * R), o_v = take(28 * R), o_opt = take(sizeof(ViewOpt) * R), o_range = take(8 * (size_t)T);
+  const size_t o_count = take(8), o_sticky = take(4);
+  if (hipMalloc(&arena, off) != hipSuccess) return LS_ERR_HIP;
+  char* a = static_cast<char*>(arena);
+  proj.rec = reinterpret_cast<float*>(a + o_rec);
+  proj.radius = reinterpret_cast<int32_t*>(a + o_rad);
+  proj.tiles = reinterpret_cast<int32_t*>(a + o_til);
+  img.rgb = reinterpret_cast<float*>(a + o_rgb);
+  img.depth = reinterpret_cast<float*>(a + o_dep);
+  img.alpha = reinterpret_cast<float*>(a + o_alp);
+  img.T_final = reinterpret_cast<float*>(a + o_T);
+  img.n_last = reinterpret_cast<int32_t*>(a + o_nl);
+  tgt_rgb = reinterpret_cast<float*>(a + o_trgb);
+  tgt_depth = reinterpret_cast<float*>(a + o_tdep);
+  g_rgb = reinterpret_cast<float*>(a + o_grgb);
+  g_depth = reinterpret_cast<float*>(a + o_gdep);
+  scale = reinterpret_cast<float*>(a + o_scale);
+  loss = reinterpret_cast<float*>(a + o_loss);
+  pose = reinterpret_cast<float*>(a + o_pose);
+  pose_grad = reinterpret_cast<float*>(a + o_pg);
+  adam_m = reinterpret_cast<float*>(a + o_m);
+  adam_v = reinterpret_cast<float*>(a + o_v);
+  opt = reinterpret_cast<ViewOpt*>(a + o_opt);
+  range = reinterpret_cast<int32_t*>(a + o_range);
+  count = reinterpret_cast<int32_t*>(a + o_count);
+  sticky = reinterpret_cast<int32_t*>(a + o_sticky);
+  if (hipMemsetAsync(arena, 0, off, s) != hipSuccess) return LS_ERR_HIP;
+
+  // targets: each view's measurements, laid out like the batch's images
+  for (int r = 0; r < R; ++r) {
+    const View& v = views[r];
+    const ls_pair& pr = pairs[v.pair].pair;
+    const int64_t hw = (int64_t)pr.K.width * pr.K.height;
+    const float* srgb = (v.reverse ? pr.rgbQ : pr.rgbP) + 3 * hw * v.index;
+    const float* sdep = (v.reverse ? pr.depthQ : pr.depthP) + hw * v.index;
+    if (hipMemcpyAsync(tgt_rgb + 3 * pix_off[r], srgb, 12 * hw, hipMemcpyDeviceToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(tgt_depth + pix_off[r], sdep, 4 * hw, hipMemcpyDeviceToDevice, s) != hipSuccess)
+      return LS_ERR_HIP;
+  }
+  std::vector<ViewOpt> ho(R);
+  for (int r = 0; r < R; ++r) {
+    const ls_reg_params& pm = pairs[views[r].pair].prm;
+    ho[r] = ViewOpt{pm.lr_rot, pm.lr_trans, 0, 1};
+  }
+  if (hipMemcpyAsync(opt, ho.data(), sizeof(ViewOpt) * R, hipMemcpyHostToDevice, s) != hipSuccess) return LS_ERR_HIP;
+  if (hipStreamSynchronize(s) != hipSuccess) return LS_ERR_HIP;
+  launch_pose_init(pose, adam_m, adam_v, opt, R, s);
+  return hip_ok();
+}
+
+ls_status RegEngine::alloc_bins(int64_t cap) {
+  if (bins_mem) hipFree(bins_mem);
+  bins_mem = nullptr;
+  ls_batch_info info{};
+  ls_status st = ls_batch_query(batch, cap, &info);
+  if (st) return st;
+  const size_t o_tile = 0, o_item = (4 * cap + 255) & ~size_t(255);
+  const size_t o_work = (o_item + 4 * cap + 255) & ~size_t(255);
+  const size_t total = o_work + info.workspace_bytes;
+  if (hipMalloc(&bins_mem, total) != hipSuccess) return LS_ERR_HIP;
+  if (hipMemset(bins_mem, 0, total) != hipSuccess) return LS_ERR_HIP;
+  char* b = static_cast<char*>(bins_mem);
+  bins.capacity = cap;
+  bins.tile_of = reinterpret_cast<uint32_t*>(b + o_tile);
+  bins.item = reinterpret_cast<int32_t*>(b + o_item);
+  bins.range = range;
+  bins.count = count;
+  bins.work = b + o_work;
+  capacity = cap;
+  return LS_OK;
+}
+
+ls_status RegEngine::size_capacity(hipStream_t s, double headroom) {
+  ls_status st;
+  int64_t cap = std::max<int64_t>(4096, 12 * M);
+  for (int attempt = 0; attempt < 3; ++attempt) {
+    if ((st = alloc_bins(cap))) return st;
+    if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
+    int32_t hc[2];
+    if (hipMemcpyAsync(hc, count, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return LS_ERR_HIP;
+    if (hc[1] == 0) {
+      const int64_t want = std::max<int64_t>(4096, (int64_t)(hc[0] * headroom));
+      if (want > cap) return alloc_bins(want);
+      return LS_OK;
+    }
+    // overflow: the exact total is the sum of the tile counts; grow generously
+    cap = std::min<int64_t>((int64_t)INT32_MAX, cap * 4);
+  }
+  return LS_ERR_CAPACITY;
+}
+
+ls_status RegEngine::step(hipStream_t s) {
+  ls_status st;
+  const ls_image_grad up{g_rgb, g_depth, nullptr, scale};
+  if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
+  launch_or_flag(count, sticky, s);
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
+      (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)) ||
+      (st = ls_render_bwd_tiles(batch, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
+      (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, s)))
+    return st;
+  const ls_reg_params& pm = pairs[0].prm;
+  launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, R, pm.beta1, pm.beta2, pm.adam_eps, s);
+  return hip_ok();
+}
+
+ls_status RegEngine::final_forward(hipStream_t s) {
+  ls_status st;
+  if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
+  launch_or_flag(count, sticky, s);
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
+      (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)))
+    return st;
+  return hip_ok();
+}
+
+ls_status RegEngine::readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow,
+                              hipStream_t s) {
+  pose_h.resize(7 * R);
+  loss_h.resize(R);
+  if (hipMemcpyAsync(pose_h.data(), pose, 28 * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(loss_h.data(), loss, 4 * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(overflow, sticky, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LS_ERR_HIP;
+  return LS_OK;
+}
+
+ls_status RegEngine::hip_ok() {
+  const hipError_t e = hipGetLastError();
+  return e == hipSuccess ? LS_OK : LS_ERR_HIP;
+}
+
+ls_status RegEngine::fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h,
+                               ls_reg_result* out) {
+  const int v0 = first_view[p], v1 = first_view[p + 1];
+  const int n = v1 - v0;
+  std::vector<double> est(12 * n), res(n);
+  std::vector<int32_t> rev(n);
+  for (int k = 0; k < n; ++k) {
+    const View& v = views[v0 + k];
+    for (int q = 0; q < 7; ++q)
+      if (!std::isfinite(pose_h[7 * (v0 + k) + q])) return LS_ERR_NONFINITE;
+    if (!std::isfinite(loss_h[v0 + k])) return LS_ERR_NONFINITE;
+    view_estimate(v.c2w, &pose_h[7 * (v0 + k)], &est[12 * k]);
+    res[k] = loss_h[v0 + k];
+    rev[k] = v.reverse ? 1 : 0;
+    if (out->per_view_T)
+      for (int q = 0; q < 12; ++q) out->per_view_T[12 * k + q] = (float)est[12 * k + q];
+    if (out->residual) out->residual[k] = loss_h[v0 + k];
+  }
+  double T[12];
+  const int st = fuse_estimates(est.data(), res.data(), rev.data(), n, T);
+  if (st) return st;
+  for (int q = 0; q < 12; ++q) out->T_PQ[q] = (float)T[q];
+  return LS_OK;
+}
+
+ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
+  if (!p || !prm) return LS_ERR_INVALID;
+  if (p->vP < 0 || p->vQ < 0 || p->vP + p->vQ < 1) return LS_ERR_INVALID;
+  if (p->K.width <= 0 || p->K.height <= 0 || !(p->K.fx > 0) || !(p->K.fy > 0)) return LS_ERR_INVALID;
+  if (p->vP > 0 && (!p->rgbP || !p->depthP || !p->c2wP || p->Q.n < 0)) return LS_ERR_INVALID;
+  if (p->vQ > 0 && (!p->rgbQ || !p->depthQ || !p->c2wQ || p->P.n < 0)) return LS_ERR_INVALID;
+  if (prm->iters < 1 || !(prm->lr_rot >= 0) || !(prm->lr_trans >= 0) || !(prm->beta1 >= 0 && prm->beta1 < 1) ||
+      !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0))
+    return LS_ERR_INVALID;
+  for (int i = 0; i < 12 * p->vP; ++i)
+    if (!std::isfinite(p->c2wP[i])) return LS_ERR_NONFINITE;
+  for (int i = 0; i < 12 * p->vQ; ++i)
+    if (!std::isfinite(p->c2wQ[i])) return LS_ERR_NONFINITE;
+  return LS_OK;
+}
+
+RegPair make_reg_pair(const ls_pair* p, const ls_reg_params* prm) {
+  RegPair rp;
+  rp.pair = *p;
+  rp.prm = *prm;
+  rp.c2wP.assign(p->c2wP ? p->c2wP : nullptr, p->c2wP ? p->c2wP + 12 * p->vP : nullptr);
+  rp.c2wQ.assign(p->c2wQ ? p->c2wQ : nullptr, p->c2wQ ? p->c2wQ + 12 * p->vQ : nullptr);
+  rp.pair.c2wP = nullptr;  // host copies above are used from here on
+  rp.pair.c2wQ = nullptr;
+  return rp;
+}
+
+}  // namespace ls
+
+using namespace ls;
+
+extern "C" {
+
+ls_status ls_fuse_estimates(const double* est, const double* resid, const int32_t* reverse, int32_t n, double* out) {
+  if (!est || !resid || !reverse || !out || n < 1) return LS_ERR_INVALID;
+  return fuse_estimates(est, resid, reverse, n, out);
+}
+
+ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg_result* out, hipStream_t s) {
+  if (!out) return LS_ERR_INVALID;
+  ls_status st = validate_pair(pair, prm);
+  out->status = st;
+  out->iters_done = 0;
+  if (st) return st;
+  std::vector<RegPair> v{make_reg_pair(pair, prm)};
+  double headroom = 1.5;
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    RegEngine e;
+    if ((st = e.build(v, s)) || (st = e.size_capacity(s, headroom))) {
+      out->status = st;
+      return st;
+    }
+    for (int it = 0; it < prm->iters; ++it)
+      if ((st = e.step(s))) {
+        out->status = st;
+        return st;
+      }
+    std::vector<float> ph, lh;
+    int32_t ovf = 0;
+    if ((st = e.final_forward(s)) || (st = e.readback(ph, lh, &ovf, s))) {
+      out->status = st;
+      return st;
+    }
+    if (ovf) {  // the instance count outgrew the headroom during optimisation: redo with more
+      headroom *= 2.0;
+      continue;
+    }
+    st = e.fuse_pair(0, ph, lh, out);
+    out->status = st;
+    out->iters_done = prm->iters;
+    return st;
+  }
+  out->status = LS_ERR_CAPACITY;
+  return LS_ERR_CAPACITY;
+}
+
+}  // extern "C"

@@ -1,0 +1,67 @@
+// Registration engine shared by ls_register_pair and the serving loop.
+#pragma once
+
+#include <vector>
+
+#include "kernels.h"
+
+namespace ls {
+
+struct RegPair {
+  ls_pair pair;               // device pointers of the caller; c2w pointers unused (copies below)
+  ls_reg_params prm;
+  std::vector<double> c2wP;   // [vP][12]
+  std::vector<double> c2wQ;   // [vQ][12]
+};
+
+// One localisation problem: a keyframe of one submap rendering the other.
+struct View {
+  int pair;
+  int index;      // keyframe index within its submap
+  bool reverse;   // keyframe of Q localised in P (estimate of T_{Q->P})
+  double c2w[12];
+};
+
+class RegEngine {
+ public:
+  ~RegEngine();
+  ls_status build(const std::vector<RegPair>& pairs, hipStream_t s);
+  ls_status size_capacity(hipStream_t s, double headroom);
+  ls_status alloc_bins(int64_t cap);
+  ls_status step(hipStream_t s);
+  ls_status final_forward(hipStream_t s);
+  ls_status readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow, hipStream_t s);
+  ls_status fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h, ls_reg_result* out);
+  void release();
+
+  std::vector<RegPair> pairs;
+  std::vector<View> views;
+  std::vector<int> first_view;  // [pairs + 1]
+  std::vector<int64_t> pix_off;
+  int R = 0, T = 0;
+  int64_t M = 0, P = 0, capacity = 0;
+  ls_batch* batch = nullptr;
+  void* arena = nullptr;
+  void* bins_mem = nullptr;
+  ls_projected proj{};
+  ls_bins bins{};
+  ls_image img{};
+  float *tgt_rgb = nullptr, *tgt_depth = nullptr, *g_rgb = nullptr, *g_depth = nullptr;
+  float *scale = nullptr, *loss = nullptr, *pose = nullptr, *pose_grad = nullptr, *adam_m = nullptr,
+        *adam_v = nullptr;
+  ViewOpt* opt = nullptr;
+  int32_t *range = nullptr, *count = nullptr, *sticky = nullptr;
+
+ private:
+  static ls_status hip_ok();
+};
+
+void rot_of_quat(const double* q, double* R);
+void rigid_inv(const double* A, double* out);
+void rigid_mul(const double* A, const double* B, double* out);
+void view_estimate(const double* c2w, const float* pose7, double* E);
+int fuse_estimates(const double* est, const double* resid, const int32_t* rev, int n, double* out);
+ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm);
+RegPair make_reg_pair(const ls_pair* p, const ls_reg_params* prm);
+
+}  // namespace ls

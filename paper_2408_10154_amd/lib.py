@@ -22,6 +22,7 @@ LS_ERR_BUDGET = -3
 LS_ERR_HIP = -4
 LS_ERR_NONFINITE = -5
 REC_FLOATS = 12
+BWD_POSE_ONLY = 1
 TILE = 16
 
 
@@ -73,6 +74,22 @@ class ls_gaussian_grads(C.Structure):
                 ("opacity_logit", C.c_void_p), ("rgb", C.c_void_p)]
 
 
+class ls_pair(C.Structure):
+    _fields_ = [("P", ls_gaussians), ("Q", ls_gaussians), ("vP", C.c_int32), ("vQ", C.c_int32),
+                ("rgbP", C.c_void_p), ("depthP", C.c_void_p), ("c2wP", C.c_void_p),
+                ("rgbQ", C.c_void_p), ("depthQ", C.c_void_p), ("c2wQ", C.c_void_p), ("K", ls_intrinsics)]
+
+
+class ls_reg_params(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("lr_rot", C.c_float), ("lr_trans", C.c_float), ("beta1", C.c_float),
+                ("beta2", C.c_float), ("adam_eps", C.c_float)]
+
+
+class ls_reg_result(C.Structure):
+    _fields_ = [("T_PQ", C.c_float * 12), ("per_view_T", C.c_void_p), ("residual", C.c_void_p),
+                ("status", C.c_int32), ("iters_done", C.c_int32)]
+
+
 class ls_adam_group(C.Structure):
     _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
                 ("n", C.c_int64), ("lr", C.c_float)]
@@ -93,13 +110,15 @@ _PROTOS = {
     "ls_render_bwd": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
                                   C.POINTER(ls_image_grad), _P, _P, _P]),
     "ls_render_bwd_tiles": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
-                                        C.POINTER(ls_image_grad), _P]),
+                                        C.POINTER(ls_image_grad), C.c_uint32, _P]),
     "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, _P]),
     "ls_render_stats": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), C.POINTER(ls_image), _P, _P]),
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
+    "ls_register_pair": (C.c_int32, [C.POINTER(ls_pair), C.POINTER(ls_reg_params), C.POINTER(ls_reg_result), _P]),
+    "ls_fuse_estimates": (C.c_int32, [_P, _P, _P, C.c_int32, _P]),
 }
 
 _lib = None
@@ -174,8 +193,8 @@ def ls_render_bwd(h, pose, proj, bins, bg, fwd, up, grads, pose_grad, stream):
                  pose_grad, stream)
 
 
-def ls_render_bwd_tiles(h, proj, bins, bg, fwd, up, stream):
-    return _call("ls_render_bwd_tiles", h, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), stream)
+def ls_render_bwd_tiles(h, proj, bins, bg, fwd, up, flags, stream):
+    return _call("ls_render_bwd_tiles", h, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), flags, stream)
 
 
 def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, stream):
@@ -192,6 +211,14 @@ def ls_loss_l1(h, pred, tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_sca
 
 def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):
     return _call("ls_adam", groups, ngroups, step, beta1, beta2, eps, zero_grad, stream)
+
+
+def ls_register_pair(pair, prm, result, stream):
+    return _call("ls_register_pair", C.byref(pair), C.byref(prm), C.byref(result), stream)
+
+
+def ls_fuse_estimates(est, resid, reverse, n, out):
+    return _call("ls_fuse_estimates", est, resid, reverse, n, out)
 
 
 def ls_fill_i32(ptr, count, value, stream):

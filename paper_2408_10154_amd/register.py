@@ -1,0 +1,103 @@
+"""Pair registration through the C ABI (3DGS registration, Sec. 3.2).
+
+`keyframe_targets` renders a submap at its own keyframes with the rasterizer
+(the synthetic stand-in for the keyframes' RGB-D measurements);
+`register_pair` hands one pair to ls_register_pair and returns the fused
+T_{P->Q}, the per-view estimates and residuals.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import lib as L
+from .render import GaussianSet, RenderBatch, _stream
+
+
+def inv_rigid(t: np.ndarray) -> np.ndarray:
+    out = np.eye(4)
+    out[:3, :3] = t[:3, :3].T
+    out[:3, 3] = -t[:3, :3].T @ t[:3, 3]
+    return out
+
+
+def keyframe_targets(g: GaussianSet, cam: dict, c2ws: np.ndarray):
+    """Renders `g` at each camera-to-world pose: returns rgb [V,3,H,W] and
+    depth [V,H,W] device tensors."""
+    jobs = [(g, cam, inv_rigid(np.asarray(c, np.float64))[:3]) for c in c2ws]
+    b = RenderBatch(jobs)
+    b.project()
+    b.bin_sort()
+    b.render_fwd()
+    H, W = cam["height"], cam["width"]
+    rgb = b.rgb.view(len(jobs), 3, H, W).clone()
+    depth = b.depth.view(len(jobs), H, W).clone()
+    b.close()
+    return rgb, depth
+
+
+def default_params(iters=200, lr_rot=0.015, lr_trans=0.005) -> L.ls_reg_params:
+    return L.ls_reg_params(iters, lr_rot, lr_trans, 0.9, 0.999, 1e-8)
+
+
+def make_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ):
+    """Builds an ls_pair; the returned host arrays must outlive the call."""
+    hp = np.ascontiguousarray(np.asarray(c2w_p, np.float64)[:, :3, :].reshape(-1, 12), np.float32)
+    hq = np.ascontiguousarray(np.asarray(c2w_q, np.float64)[:, :3, :].reshape(-1, 12), np.float32)
+    pair = L.ls_pair()
+    pair.P = P.to_c()
+    pair.Q = Q.to_c()
+    pair.vP, pair.vQ = len(hp), len(hq)
+    pair.rgbP, pair.depthP = rgbP.data_ptr(), depthP.data_ptr()
+    pair.rgbQ, pair.depthQ = rgbQ.data_ptr(), depthQ.data_ptr()
+    pair.c2wP = hp.ctypes.data_as(C.c_void_p)
+    pair.c2wQ = hq.ctypes.data_as(C.c_void_p)
+    pair.K = L.ls_intrinsics(cam["fx"], cam["fy"], cam["cx"], cam["cy"], cam["width"], cam["height"])
+    return pair, (hp, hq, rgbP, depthP, rgbQ, depthQ)
+
+
+def register_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ,
+                  params: L.ls_reg_params | None = None):
+    """Runs ls_register_pair.  Returns dict(T [4,4] float64, per_view [V,4,4],
+    residual [V], status)."""
+    params = params or default_params()
+    pair, keep = make_pair(P, Q, cam, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ)
+    nv = pair.vP + pair.vQ
+    per_view = np.zeros((nv, 12), np.float32)
+    resid = np.zeros(nv, np.float32)
+    res = L.ls_reg_result()
+    res.per_view_T = per_view.ctypes.data_as(C.c_void_p)
+    res.residual = resid.ctypes.data_as(C.c_void_p)
+    L.ls_register_pair(pair, params, res, _stream())
+    T = np.eye(4)
+    T[:3, :] = np.asarray(res.T_PQ, np.float64).reshape(3, 4)
+    pv = np.tile(np.eye(4), (nv, 1, 1))
+    pv[:, :3, :] = per_view.reshape(nv, 3, 4)
+    del keep
+    return dict(T=T, per_view=pv, residual=resid.astype(np.float64), status=res.status, iters=res.iters_done)
+
+
+def fuse_estimates(estimates, residuals, reverse) -> np.ndarray:
+    """Host-only Eq. 7 fusion in the library (no GPU needed)."""
+    n = len(estimates)
+    est = np.ascontiguousarray(np.asarray(estimates, np.float64)[:, :3, :].reshape(n, 12))
+    res = np.ascontiguousarray(np.asarray(residuals, np.float64))
+    rev = np.ascontiguousarray(np.asarray(reverse, np.int32))
+    out = np.zeros(12, np.float64)
+    L.ls_fuse_estimates(est.ctypes.data_as(C.c_void_p), res.ctypes.data_as(C.c_void_p),
+                        rev.ctypes.data_as(C.c_void_p), n, out.ctypes.data_as(C.c_void_p))
+    T = np.eye(4)
+    T[:3, :] = out.reshape(3, 4)
+    return T
+
+
+def rotation_error_deg(R, R_gt) -> float:
+    c = (np.trace(np.asarray(R)[:3, :3] @ np.asarray(R_gt)[:3, :3].T) - 1.0) / 2.0
+    return float(np.degrees(np.arccos(np.clip(c, -1.0, 1.0))))
+
+
+def translation_error_cm(T, T_gt) -> float:
+    return float(100.0 * np.linalg.norm(np.asarray(T)[:3, 3] - np.asarray(T_gt)[:3, 3]))

@@ -188,14 +188,15 @@ class RenderBatch:
         L.ls_render_bwd(self.h, _ptr(pose), self.proj, self.bins, bgc, self.image, up, garr, _ptr(pose_grad),
                         _stream())
 
-    def render_bwd_tiles(self, up_rgb=None, up_depth=None, up_alpha=None, scale=None, bg=None):
+    def render_bwd_tiles(self, up_rgb=None, up_depth=None, up_alpha=None, scale=None, bg=None, pose_only=False):
         self._check_dev(up_rgb, 3 * self.P, name="up_rgb")
         self._check_dev(up_depth, self.P, name="up_depth")
         self._check_dev(up_alpha, self.P, name="up_alpha")
         self._check_dev(scale, self.R, name="scale")
         up = L.ls_image_grad(*[None if t is None else t.data_ptr() for t in (up_rgb, up_depth, up_alpha, scale)])
         bgc = (C.c_float * 3)(*bg) if bg is not None else None
-        L.ls_render_bwd_tiles(self.h, self.proj, self.bins, bgc, self.image, up, _stream())
+        L.ls_render_bwd_tiles(self.h, self.proj, self.bins, bgc, self.image, up, L.BWD_POSE_ONLY if pose_only else 0,
+                              _stream())
 
     def render_bwd_project(self, grads=None, pose=None, pose_grad=None):
         self._check_pose(pose)

@@ -40,7 +40,7 @@ def test_binding_covers_the_header():
     assert set(L.declared_functions()) == declared()
 
 
-@pytest.mark.parametrize("name", ["ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
+@pytest.mark.parametrize("name", ["ls_pair", "ls_reg_params", "ls_reg_result", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
                                   "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group"])
 def test_struct_layouts_match(name):
     lib = L.load()
@@ -65,3 +65,14 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert lib.ls_struct_size(b"no_such_struct") == -1
     with pytest.raises(L.LsError):
         L.check(L.LS_ERR_INVALID)
+
+
+def test_register_pair_rejects_bad_parameters_before_touching_a_device():
+    lib = L.load()
+    pair = L.ls_pair()
+    prm = L.ls_reg_params(0, 0.01, 0.01, 0.9, 0.999, 1e-8)  # iters = 0
+    res = L.ls_reg_result()
+    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+    prm.iters = 10
+    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID  # no views
+    assert lib.ls_fuse_estimates(None, None, None, 0, None) == L.LS_ERR_INVALID
