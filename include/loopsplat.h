@@ -128,11 +128,15 @@ ls_status ls_batch_offsets(const ls_batch* b, int64_t* item_off, int64_t* pix_of
  *          2D covariance, sigma = A dx^2/2 + B dx dy + C dy^2/2), z the
  *          camera-space depth.  16-byte aligned.
  *   radius [M]: ceil(3 sqrt(lambda_max(Sigma_2D))) in pixels, 0 = culled
- *   tiles  [M]: number of tiles of the item's tile rectangle, 0 = culled */
+ *   tiles  [M]: number of tiles of the item's tile rectangle, 0 = culled
+ *   aux    [M][12] or NULL: camera-space mean (x, y, z) and covariance
+ *          (xx, xy, xz, yy, yz, zz), 0, 0, 0 - kept by the forward for the
+ *          backward; required by ls_render_bwd*.  16-byte aligned. */
 typedef struct {
   float* rec;
   int32_t* radius;
   int32_t* tiles;
+  float* aux;
 } ls_projected;
 
 /* EWA projection of every item (the splatting step the paper's renderer
@@ -150,7 +154,8 @@ ls_status ls_project(const ls_batch* b, const float* pose, const ls_projected* o
  *   tile_of [capacity] global tile index (tile_off[r] + ty * tiles_x + tx)
  *   item    [capacity] item index of each instance
  *   range   [tiles][2] [start, end) of each tile's list (empty tiles: 0, 0)
- *   count   [2] int32: {number of instances I, overflow flag}
+ *   count   [4] int32: {instances kept = min(I, capacity), overflow flag,
+ *           instances required I, 0}
  *   work    workspace of ls_batch_info.workspace_bytes (256-byte aligned);
  *           also used by ls_render_bwd. */
 typedef struct {
@@ -168,7 +173,7 @@ typedef struct {
  * broken by Gaussian index.  Runs entirely on the device (depth radix sort of
  * the items, scan, emission, tile radix sort).  When I > capacity, count[1]
  * is set to 1, only the first `capacity` instances are kept and the lists are
- * not valid; the caller re-runs with a larger capacity.  Errors:
+ * not valid; the caller re-runs with capacity >= count[2].  Errors:
  * LS_ERR_INVALID (NULL buffers, capacity < 0). */
 ls_status ls_bin_sort(const ls_batch* b, const ls_projected* p, const ls_bins* bins, hipStream_t s);
 
@@ -216,26 +221,37 @@ typedef struct {
  *   grads:     host array [R] of per-render outputs, or NULL (pose only).
  *              Jobs sharing a Gaussian set may share output arrays.
  *   pose_grad: device [R][7], accumulated, or NULL; needs `pose`.
- * The image-space gradient scratch lives in ls_bins.work: the workspace must
- * be zero-filled before its first ls_render_bwd_tiles, and
- * ls_render_bwd_project leaves it zeroed again.  Errors: LS_ERR_INVALID. */
+ * Two modes:
+ *   - full (grads != NULL): per-tile sums of each Gaussian's image-space
+ *     gradients are added to a per-item accumulator in ls_bins.work (float
+ *     atomics, so reproducible to rounding, not bitwise); the accumulator must
+ *     be zero before the first backward on a workspace and
+ *     ls_render_bwd_project clears it again;
+ *   - pose only (grads == NULL, LS_BWD_POSE_ONLY): each Gaussian's pose
+ *     Jacobian is applied inside the tile and a 12-value partial is written
+ *     per tile, summed per render in a fixed order: no atomics, bit-identical
+ *     results that do not depend on the other renders of the batch.
+ * Errors: LS_ERR_INVALID. */
 ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
                         const float* bg, const ls_image* fwd, const ls_image_grad* up,
                         const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s);
 
-/* First half of ls_render_bwd: per tile, back-to-front recomputation and
- * accumulation of dL/d(u, v, conic, opacity, z, rgb) per item into the
- * workspace (one kernel).  flags: LS_BWD_POSE_ONLY accumulates only the
- * gradients a pose correction depends on (u, v, conic, z). */
+/* First half of ls_render_bwd: per tile, back-to-front recomputation and the
+ * per-(item, tile) sums of dL/d(u, v, conic, opacity, z, rgb) (one kernel).
+ * flags: LS_BWD_POSE_ONLY keeps only what a pose correction depends on (u, v,
+ * conic, z) and turns it into per-tile pose partials (`pose` may be NULL =
+ * identity). */
 #define LS_BWD_POSE_ONLY 1u
-ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
-                              const ls_image* fwd, const ls_image_grad* up, uint32_t flags, hipStream_t s);
+ls_status ls_render_bwd_tiles(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                              const float* bg, const ls_image* fwd, const ls_image_grad* up, uint32_t flags,
+                              hipStream_t s);
 
 /* Second half of ls_render_bwd: chains the accumulated image-space gradients
- * through the EWA projection to the Gaussian parameters and the pose, and
- * clears the accumulator. */
+ * through the EWA projection to the Gaussian parameters and the pose (full
+ * mode), or sums the per-tile pose partials of each render (LS_BWD_POSE_ONLY;
+ * grads must be NULL). */
 ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
-                                const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s);
+                                const ls_gaussian_grads* grads, float* pose_grad, uint32_t flags, hipStream_t s);
 
 /* Work statistics of the last forward: stats (device int64 [2], written)
  * receives {list entries evaluated (every entry up to and including the one
@@ -326,6 +342,67 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg
  * inverted before averaging) -> out [12].  Weights 1/max(eps, 1e-12); the
  * rotation maximises tr(R^T sum_i w_i R_i) over SO(3).  No GPU needed. */
 ls_status ls_fuse_estimates(const double* est, const double* resid, const int32_t* reverse, int32_t n, double* out);
+
+/* ---------------------------------------------------------------------------
+ * Registration serving loop.  Loop edges are requested as submap pairs arrive
+ * (Sec. 3.3: every detected loop is registered before pose-graph
+ * optimisation); the server keeps admitted pairs resident and runs all of
+ * their keyframe localisations together.
+ *   - submit queues a request and returns a ticket (thread-safe);
+ *   - a worker thread admits queued requests first-in first-out while the
+ *     estimated device bytes of the active set stay within the budget and a
+ *     slot is free (continuous batching at iteration granularity: requests
+ *     that arrive while others run join at the next chunk boundary, finished
+ *     ones leave and free their slot);
+ *   - one Adam iteration over every view of every active pair is one launch
+ *     set, captured once per change of the active set as a HIP graph and
+ *     replayed;
+ *   - finished pairs are fused on the host (Eq. 7) and posted to their ticket.
+ * The caller keeps each pair's device buffers alive until its ticket's poll
+ * returns a final status.
+ * ------------------------------------------------------------------------- */
+
+typedef struct ls_server ls_server;
+
+typedef struct {
+  size_t hbm_budget_bytes;  /* device bytes the server may use for resident work */
+  int32_t max_slots;        /* pairs running at once (>= 1) */
+  int32_t chunk_iters;      /* iterations between admission / retirement points (>= 1) */
+  float instance_headroom;  /* tile-instance capacity = headroom x count measured at each rebuild
+                               (>= 0.25; below 1 deliberately undersizes it, which exercises the
+                               overflow-recovery path: the chunk is re-run with more room) */
+  int32_t use_graphs;       /* 1: capture + replay iterations; 0: launch eagerly */
+} ls_server_params;
+
+typedef struct {
+  int64_t submitted, completed, failed;
+  int64_t epochs;            /* active-set changes (batch rebuilds) */
+  int64_t iterations;        /* batched iterations run */
+  int64_t graph_replays;
+  int64_t overflow_retries;  /* chunks re-run after the instance capacity overflowed */
+  int64_t peak_bytes;        /* peak estimated bytes of the active set */
+  int32_t active, waiting;
+} ls_server_stats;
+
+/* Creates a server on the current device with its own worker thread and
+ * stream.  Errors: LS_ERR_INVALID (bad parameters), LS_ERR_HIP. */
+ls_status ls_server_create(const ls_server_params* prm, ls_server** out);
+/* Queues a pair (copied; device pointers referenced).  Errors:
+ * LS_ERR_INVALID (including Adam beta1/beta2/eps different from the first
+ * request the server saw), LS_ERR_NONFINITE (non-finite keyframe poses or
+ * Gaussian parameters; checked on the device before queueing),
+ * LS_ERR_BUDGET (the pair alone exceeds the budget). */
+ls_status ls_register_submit(ls_server* sv, const ls_pair* pair, const ls_reg_params* prm, uint64_t* ticket);
+/* LS_NOT_READY while the ticket runs; otherwise fills `out` (per_view_T and
+ * residual when non-NULL) and `times` (double [3] or NULL: seconds from
+ * submit to admission, admission to completion, submit to completion),
+ * releases the ticket and returns its final status (LS_OK, or e.g.
+ * LS_ERR_NONFINITE when the optimisation diverged). */
+ls_status ls_register_poll(ls_server* sv, uint64_t ticket, ls_reg_result* out, double* times);
+ls_status ls_server_get_stats(ls_server* sv, ls_server_stats* out);
+/* Finishes every submitted request, then stops the worker and frees the
+ * server.  Tickets not yet polled are released. */
+ls_status ls_server_destroy(ls_server* sv);
 
 #ifdef __cplusplus
 }

@@ -10,6 +10,7 @@
 #include <string>
 #include <vector>
 
+#include "batch.h"
 #include "kernels.h"
 
 using namespace ls;
@@ -39,32 +40,12 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 }  // namespace
 
-struct ls_batch {
-  int R = 0;
-  int64_t M = 0;
-  int T = 0;
-  int64_t P = 0;
-  int nblk_items = 0;
-  int nblk_pix = 0;
-  int tile_passes = 0;
-  int device = 0;
-  std::vector<JobDev> jobs_h;
-  std::vector<int64_t> item_off, pix_off;
-  std::vector<int32_t> tile_off, blk_off, pblk_off;
-  JobDev* jobs_d = nullptr;
-  int64_t* item_off_d = nullptr;
-  int32_t* tile_off_d = nullptr;
-  int32_t* blk_off_d = nullptr;
-  int32_t* pblk_off_d = nullptr;
-  float* loss_part_d = nullptr;
-  GradDev* grads_d = nullptr;
-  std::vector<GradDev> grads_cached;
-};
+
 
 namespace {
 
 struct Layout {
-  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, pose_part, total;
+  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, total;
 };
 
 Layout layout_of(const ls_batch* b, int64_t cap) {
@@ -87,6 +68,7 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.tk = take(4 * cap);
   L.tv = take(4 * cap);
   L.g2d = take(4 * (size_t)kGrad2D * M);
+  L.tile_part = take(4 * (size_t)kPoseAcc * std::max(b->T, 1));
   L.pose_part = take(4 * (size_t)kPoseAcc * std::max(b->nblk_items, 1));
   L.total = off;
   return L;
@@ -113,9 +95,12 @@ ls_status upload(T** dst, const std::vector<T>& src) {
   return LS_OK;
 }
 
-ls_status check_projected(const ls_projected* p) {
+ls_status check_projected(const ls_projected* p, bool need_aux = false) {
   if (!p || !p->rec || !p->radius || !p->tiles) return fail(LS_ERR_INVALID, "ls_projected has NULL members");
   if (reinterpret_cast<uintptr_t>(p->rec) % 16) return fail(LS_ERR_INVALID, "ls_projected.rec must be 16-byte aligned");
+  if (need_aux && !p->aux) return fail(LS_ERR_INVALID, "ls_projected.aux is needed by the backward");
+  if (p->aux && reinterpret_cast<uintptr_t>(p->aux) % 16)
+    return fail(LS_ERR_INVALID, "ls_projected.aux must be 16-byte aligned");
   return LS_OK;
 }
 
@@ -130,6 +115,26 @@ ls_status check_bins(const ls_batch* b, const ls_bins* bins) {
 }
 
 }  // namespace
+
+namespace ls {
+ls_status batch_set_targets(ls_batch* b, const std::vector<const float*>& rgb, const std::vector<const float*>& depth) {
+  if (!b || (int)rgb.size() != b->R || (int)depth.size() != b->R) return fail(LS_ERR_INVALID, "one target per render");
+  for (int r = 0; r < b->R; ++r) {
+    b->jobs_h[r].tgt_rgb = rgb[r];
+    b->jobs_h[r].tgt_depth = depth[r];
+  }
+  if (hipMemcpy(b->jobs_d, b->jobs_h.data(), sizeof(JobDev) * b->R, hipMemcpyHostToDevice) != hipSuccess)
+    return fail(LS_ERR_HIP, "job table upload failed");
+  return LS_OK;
+}
+
+ls_status batch_loss_l1(const ls_batch* b, const ls_image* pred, float* loss, float* grad_rgb, float* grad_depth,
+                        float* grad_scale, hipStream_t s) {
+  launch_loss_l1(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, nullptr, nullptr, grad_rgb,
+                 grad_depth, b->loss_part_d, loss, grad_scale, s);
+  return hip_check("loss over per-render targets");
+}
+}  // namespace ls
 
 extern "C" {
 
@@ -147,7 +152,8 @@ int64_t ls_struct_size(const char* name) {
       {"ls_image", sizeof(ls_image)},               {"ls_image_grad", sizeof(ls_image_grad)},
       {"ls_gaussian_grads", sizeof(ls_gaussian_grads)}, {"ls_adam_group", sizeof(ls_adam_group)},
       {"ls_pair", sizeof(ls_pair)},                 {"ls_reg_params", sizeof(ls_reg_params)},
-      {"ls_reg_result", sizeof(ls_reg_result)},
+      {"ls_reg_result", sizeof(ls_reg_result)},     {"ls_server_params", sizeof(ls_server_params)},
+      {"ls_server_stats", sizeof(ls_server_stats)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -204,6 +210,8 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
     d.item_off = b->item_off[r];
     d.pix_off = b->pix_off[r];
     std::memcpy(d.w2c, j.w2c, sizeof(d.w2c));
+    d.tgt_rgb = nullptr;
+    d.tgt_depth = nullptr;
     const int64_t hw = (int64_t)K.width * K.height;
     b->item_off[r + 1] = b->item_off[r] + j.g.n;
     b->pix_off[r + 1] = b->pix_off[r] + hw;
@@ -285,7 +293,7 @@ ls_status ls_project(const ls_batch* b, const float* pose, const ls_projected* o
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");
   ls_status st;
   if ((st = check_projected(out)) || (st = ensure_device(b))) return st;
-  launch_project(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, out->rec, out->radius, out->tiles, s);
+  launch_project(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, out->rec, out->radius, out->tiles, out->aux, s);
   return hip_check("ls_project");
 }
 
@@ -296,7 +304,7 @@ ls_status ls_bin_sort(const ls_batch* b, const ls_projected* p, const ls_bins* b
   const Layout L = layout_of(b, bins->capacity);
   void* w = bins->work;
   if (b->M == 0) {
-    launch_fill_i32(bins->count, 2, 0, s);
+    launch_fill_i32(bins->count, 4, 0, s);
     launch_fill_i32(bins->range, 2 * (int64_t)b->T, 0, s);
     return hip_check("ls_bin_sort");
   }
@@ -320,26 +328,34 @@ ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins*
   return hip_check("ls_render_fwd");
 }
 
-ls_status ls_render_bwd_tiles(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
-                              const ls_image* fwd, const ls_image_grad* up, uint32_t flags, hipStream_t s) {
+ls_status ls_render_bwd_tiles(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                              const float* bg, const ls_image* fwd, const ls_image_grad* up, uint32_t flags,
+                              hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");
   ls_status st;
-  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if ((st = check_projected(p, true)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
   if (!fwd || !fwd->T_final || !fwd->n_last) return fail(LS_ERR_INVALID, "forward state (T_final, n_last) missing");
   if (!up) return fail(LS_ERR_INVALID, "upstream gradients missing");
   const Layout L = layout_of(b, bins->capacity);
   const float zero[3] = {0.f, 0.f, 0.f};
-  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
-                       fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale,
-                       at<float>(bins->work, L.g2d), (flags & LS_BWD_POSE_ONLY) ? 1 : 0, s);
+  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range,
+                       bg ? bg : zero, fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale,
+                       at<float>(bins->work, L.g2d), at<float>(bins->work, L.tile_part),
+                       (flags & LS_BWD_POSE_ONLY) ? 1 : 0, s);
   return hip_check("ls_render_bwd_tiles");
 }
 
 ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
-                                const ls_gaussian_grads* grads, float* pose_grad, hipStream_t s) {
+                                const ls_gaussian_grads* grads, float* pose_grad, uint32_t flags, hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");
   ls_status st;
-  if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if ((st = check_projected(p, true)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  const Layout L = layout_of(b, bins->capacity);
+  if (flags & LS_BWD_POSE_ONLY) {
+    if (grads) return fail(LS_ERR_INVALID, "pose-only backward computes no Gaussian gradients");
+    if (pose_grad) launch_pose_reduce_tiles(b->jobs_d, b->R, pose, at<float>(bins->work, L.tile_part), pose_grad, s);
+    return hip_check("ls_render_bwd_project");
+  }
   if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
   const int want_gauss = grads != nullptr;
   if (want_gauss) {
@@ -370,9 +386,9 @@ ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_p
       const_cast<ls_batch*>(b)->grads_cached = gd;
     }
   }
-  const Layout L = layout_of(b, bins->capacity);
-  launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, at<float>(bins->work, L.g2d),
-                     b->grads_d, want_gauss, at<float>(bins->work, L.pose_part), pose_grad != nullptr, pose_grad, s);
+  launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, p->aux,
+                     at<float>(bins->work, L.g2d), b->grads_d, want_gauss, at<float>(bins->work, L.pose_part),
+                     pose_grad != nullptr, pose_grad, s);
   return hip_check("ls_render_bwd_project");
 }
 
@@ -380,9 +396,10 @@ ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected
                         const float* bg, const ls_image* fwd, const ls_image_grad* up, const ls_gaussian_grads* grads,
                         float* pose_grad, hipStream_t s) {
   if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
-  ls_status st = ls_render_bwd_tiles(b, p, bins, bg, fwd, up, grads ? 0u : LS_BWD_POSE_ONLY, s);
+  const uint32_t flags = grads ? 0u : LS_BWD_POSE_ONLY;
+  ls_status st = ls_render_bwd_tiles(b, pose, p, bins, bg, fwd, up, flags, s);
   if (st) return st;
-  return ls_render_bwd_project(b, pose, p, bins, grads, pose_grad, s);
+  return ls_render_bwd_project(b, pose, p, bins, grads, pose_grad, flags, s);
 }
 
 ls_status ls_render_stats(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const ls_image* fwd,

@@ -1,0 +1,41 @@
+// Internal definition of the opaque ls_batch (shared by the C ABI, the
+// registration engine and the server).
+#pragma once
+
+#include <vector>
+
+#include "kernels.h"
+
+struct ls_batch {
+  using JobDev = ls::JobDev;
+  using GradDev = ls::GradDev;
+  int R = 0;
+  int64_t M = 0;
+  int T = 0;
+  int64_t P = 0;
+  int nblk_items = 0;
+  int nblk_pix = 0;
+  int tile_passes = 0;
+  int device = 0;
+  std::vector<JobDev> jobs_h;
+  std::vector<int64_t> item_off, pix_off;
+  std::vector<int32_t> tile_off, blk_off, pblk_off;
+  JobDev* jobs_d = nullptr;
+  int64_t* item_off_d = nullptr;
+  int32_t* tile_off_d = nullptr;
+  int32_t* blk_off_d = nullptr;
+  int32_t* pblk_off_d = nullptr;
+  float* loss_part_d = nullptr;
+  GradDev* grads_d = nullptr;
+  std::vector<GradDev> grads_cached;
+};
+
+namespace ls {
+// Points every render's loss at its own measurements (device [3][H][W] and
+// [H][W]); re-uploads the job table.  Used by engines that do not lay the
+// targets out contiguously.
+ls_status batch_set_targets(ls_batch* b, const std::vector<const float*>& rgb, const std::vector<const float*>& depth);
+// Loss over per-render targets (see batch_set_targets).
+ls_status batch_loss_l1(const ls_batch* b, const ls_image* pred, float* loss, float* grad_rgb, float* grad_depth,
+                        float* grad_scale, hipStream_t s);
+}  // namespace ls

@@ -209,6 +209,8 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
     const int64_t I = bsum_scanned[nbd];
     count[0] = (int32_t)min(I, cap);
     count[1] = I > cap ? 1 : 0;
+    count[2] = (int32_t)min(I, (int64_t)INT32_MAX);
+    count[3] = 0;
   }
 }
 

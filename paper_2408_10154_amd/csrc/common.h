@@ -15,6 +15,7 @@ constexpr int kSortItems = 16;      // items per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
 constexpr int kGrad2D = 10;         // du dv dA dB dC dop dz dr dg db
 constexpr int kPoseAcc = 12;        // dL/dR (9, row-major) and dL/dt (3)
+constexpr int kAuxFloats = 12;      // per item: camera-space mean (3), covariance (6), 0 x3
 
 // Device view of one render job.
 struct JobDev {
@@ -31,6 +32,8 @@ struct JobDev {
   int64_t item_off;
   int64_t pix_off;
   float w2c[12];
+  const float* tgt_rgb;    // optional per-render measurements [3][H][W] (internal batches)
+  const float* tgt_depth;  // [H][W]
 };
 
 // Gradient pointers of one render, device copy.
@@ -128,6 +131,71 @@ __device__ __forceinline__ int xcd_remap(int b, int total) {
 
 __device__ __forceinline__ void atomic_add_f32(float* p, float v) {
   unsafeAtomicAdd(p, v);
+}
+
+// Image-space gradients of one Gaussian -> gradients w.r.t. its camera-space
+// mean p (dp) and camera-space covariance Sc (G, symmetric 3x3), through
+// u = fx x/z + cx, v = fy y/z + cy, Sigma_2D = J Sc J^T + eps I and the conic
+// (A, B, C) = (c, -b, a) / det.  g = (du, dv, dA, dB, dC, dz).
+__device__ __forceinline__ void camera_space_grads(const float* p, const float* Sc, float fx, float fy,
+                                                   const float* g, float* dp, float* G) {
+  const float px = p[0], py = p[1], pz = p[2];
+  const float du = g[0], dv = g[1], dA = g[2], dB = g[3], dC = g[4], dz = g[5];
+  const float iz = 1.0f / pz;
+  const float J0[3] = {fx * iz, 0.f, -fx * px * iz * iz};
+  const float J1[3] = {0.f, fy * iz, -fy * py * iz * iz};
+  float SJ0[3], SJ1[3];  // Sc J0^T, Sc J1^T
+  for (int i = 0; i < 3; ++i) {
+    SJ0[i] = Sc[i * 3 + 0] * J0[0] + Sc[i * 3 + 1] * J0[1] + Sc[i * 3 + 2] * J0[2];
+    SJ1[i] = Sc[i * 3 + 0] * J1[0] + Sc[i * 3 + 1] * J1[1] + Sc[i * 3 + 2] * J1[2];
+  }
+  const float a = J0[0] * SJ0[0] + J0[1] * SJ0[1] + J0[2] * SJ0[2] + LS_EPS_2D;
+  const float b = J0[0] * SJ1[0] + J0[1] * SJ1[1] + J0[2] * SJ1[2];
+  const float c = J1[0] * SJ1[0] + J1[1] * SJ1[1] + J1[2] * SJ1[2] + LS_EPS_2D;
+  const float det = a * c - b * b;
+  const float id2 = 1.0f / (det * det);
+  const float ga = (-c * c * dA + b * c * dB - b * b * dC) * id2;
+  const float gb = (2.f * b * c * dA - (det + 2.f * b * b) * dB + 2.f * a * b * dC) * id2;
+  const float gc = (-b * b * dA + a * b * dB - a * a * dC) * id2;
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k)
+      G[i * 3 + k] = ga * J0[i] * J0[k] + 0.5f * gb * (J0[i] * J1[k] + J1[i] * J0[k]) + gc * J1[i] * J1[k];
+  const float gJ00 = 2.f * ga * SJ0[0] + gb * SJ1[0];
+  const float gJ02 = 2.f * ga * SJ0[2] + gb * SJ1[2];
+  const float gJ11 = gb * SJ0[1] + 2.f * gc * SJ1[1];
+  const float gJ12 = gb * SJ0[2] + 2.f * gc * SJ1[2];
+  const float iz2 = iz * iz, iz3 = iz2 * iz;
+  dp[0] = du * fx * iz - gJ02 * fx * iz2;
+  dp[1] = dv * fy * iz - gJ12 * fy * iz2;
+  dp[2] = -du * fx * px * iz2 - dv * fy * py * iz2 + dz - gJ00 * fx * iz2 + gJ02 * 2.f * fx * px * iz3 -
+          gJ11 * fy * iz2 + gJ12 * 2.f * fy * py * iz3;
+}
+
+// Contribution of a Gaussian to dL/dR_d (9, row-major) and dL/dt_d (3) of its
+// render's camera-frame correction (R_d, t_d): p = R_d p0 + t_d and
+// Sc = R_d Sc0 R_d^T give dL/dR_d = dp p0^T + 2 G Sc R_d, dL/dt_d = dp, with
+// p0 = R_d^T (p - t_d).  Accumulated into acc[12].
+__device__ __forceinline__ void pose_contrib(const float* p, const float* Sc, const float* Rd, const float* td,
+                                             const float* dp, const float* G, float* acc) {
+  const float d[3] = {p[0] - td[0], p[1] - td[1], p[2] - td[2]};
+  float q0[3];
+  for (int k = 0; k < 3; ++k) q0[k] = Rd[0 * 3 + k] * d[0] + Rd[1 * 3 + k] * d[1] + Rd[2 * 3 + k] * d[2];
+  float GS[9];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k) GS[i * 3 + k] = G[i * 3 + 0] * Sc[0 * 3 + k] + G[i * 3 + 1] * Sc[1 * 3 + k] + G[i * 3 + 2] * Sc[2 * 3 + k];
+  for (int i = 0; i < 3; ++i)
+    for (int k = 0; k < 3; ++k)
+      acc[i * 3 + k] += dp[i] * q0[k] + 2.f * (GS[i * 3 + 0] * Rd[0 * 3 + k] + GS[i * 3 + 1] * Rd[1 * 3 + k] + GS[i * 3 + 2] * Rd[2 * 3 + k]);
+  acc[9] += dp[0];
+  acc[10] += dp[1];
+  acc[11] += dp[2];
+}
+
+// Row-major 3x3 covariance from the 6 stored entries (xx xy xz yy yz zz).
+__device__ __forceinline__ void sym3(const float* s6, float* S) {
+  S[0] = s6[0]; S[1] = s6[1]; S[2] = s6[2];
+  S[3] = s6[1]; S[4] = s6[3]; S[5] = s6[4];
+  S[6] = s6[2]; S[7] = s6[4]; S[8] = s6[5];
 }
 
 }  // namespace ls

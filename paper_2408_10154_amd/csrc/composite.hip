@@ -184,14 +184,19 @@ constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row part
 // prod_{k>i}(1 - alpha_k)(bg . gC - gA), where v_j = c_j . gC + z_j gD:
 //   dL/dalpha_i = T_i (v_i - acc_i).
 // The ten image-space gradients of each Gaussian are summed over each 16-lane
-// row (DPP), the 16 row sums of the block over LDS in a fixed order, and
-// added to the item's accumulator with one atomic per value and tile.
+// row (DPP) and the 16 row sums of the block over LDS in a fixed order.  Full
+// mode adds the result to the item's accumulator (one atomic per value and
+// tile).  Pose-only mode (registration) instead applies the Gaussian's pose
+// Jacobian right here and writes one 12-value partial per tile: no atomics,
+// so the pose gradient is deterministic and independent of the other renders.
 // kPoseOnly: only the gradients a pose correction depends on (u, v, conic,
 // depth) are reduced; opacity and colour gradients are left out.
 template <bool kPoseOnly>
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
+                                                          const float4* __restrict__ aux,
+                                                          const float* __restrict__ pose,
                                                           const int32_t* __restrict__ items,
                                                           const int32_t* __restrict__ range, float bg0, float bg1,
                                                           float bg2, const float* __restrict__ fwd_T,
@@ -200,7 +205,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
                                                           const float* __restrict__ up_depth,
                                                           const float* __restrict__ up_alpha,
                                                           const float* __restrict__ up_scale,
-                                                          float* __restrict__ g2d) {
+                                                          float* __restrict__ g2d, float* __restrict__ tile_part) {
   __shared__ float4 s0[kBwdChunk], s1[kBwdChunk], s2[kBwdChunk];
   __shared__ int32_t sit[kBwdChunk];
   __shared__ uint32_t smask[kBwdChunk];
@@ -237,6 +242,20 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
   if (nl > 0) atomicMax(&smax, nl);
   __syncthreads();
   const int last = min(start + smax, end);  // exclusive end of the entries any pixel visited
+  // pose-only: per-tile accumulation of dL/d(R_d, t_d) by the entry-summing threads
+  float pacc[kPoseAcc];
+  float Rd[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, td[3] = {0.f, 0.f, 0.f};
+  if (kPoseOnly) {
+#pragma unroll
+    for (int k = 0; k < kPoseAcc; ++k) pacc[k] = 0.f;
+    if (pose) {
+      const float* pr = pose + 7 * c.r;
+      quat_to_rot(pr[0], pr[1], pr[2], pr[3], Rd);
+      td[0] = pr[4];
+      td[1] = pr[5];
+      td[2] = pr[6];
+    }
+  }
 
   for (int chunk_end = last; chunk_end > start; chunk_end -= kBwdChunk) {
     const int chunk = max(start, chunk_end - kBwdChunk);
@@ -325,23 +344,60 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
     {
       // 4 threads per entry; thread (j, t) sums values t, t + 4, t + 8 over the 16 rows in order
       // rows of bands that did not visit the entry hold stale values: skip them
-      constexpr int kPer = kBlock / kBwdChunk;  // threads per entry
-      const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
-      const uint32_t mj = j < cnt ? smask[j] : 0u;
-      if (mj != 0u) {
-        float* dst = g2d + (int64_t)sit[j] * kGrad2D;
-        const float* pj = part + j * kPartStride;
-        for (int q = t; q < kGrad2D; q += kPer) {
-          if (kPoseOnly && (q == 5 || q >= 7)) continue;
-          float s = 0.f;
+      if (!kPoseOnly) {
+        constexpr int kPer = kBlock / kBwdChunk;  // threads per entry
+        const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
+        const uint32_t mj = j < cnt ? smask[j] : 0u;
+        if (mj != 0u) {
+          float* dst = g2d + (int64_t)sit[j] * kGrad2D;
+          const float* pj = part + j * kPartStride;
+          for (int q = t; q < kGrad2D; q += kPer) {
+            float s = 0.f;
 #pragma unroll
-          for (int r2 = 0; r2 < 16; ++r2)
-            if ((mj >> (r2 >> 2)) & 1u) s += pj[r2 * kPartRow + q];
-          if (s != 0.f) atomic_add_f32(dst + q, s);
+            for (int r2 = 0; r2 < 16; ++r2)
+              if ((mj >> (r2 >> 2)) & 1u) s += pj[r2 * kPartRow + q];
+            if (s != 0.f) atomic_add_f32(dst + q, s);
+          }
+        }
+      } else if ((int)threadIdx.x < cnt) {
+        // one thread per entry: its image-space sums over the tile, then the
+        // Gaussian's pose Jacobian, accumulated per tile in a fixed order
+        const int j = threadIdx.x;
+        const uint32_t mj = smask[j];
+        if (mj != 0u) {
+          const float* pj = part + j * kPartStride;
+          float g6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+          for (int r2 = 0; r2 < 16; ++r2) {
+            if (!((mj >> (r2 >> 2)) & 1u)) continue;
+            const float* pr2 = pj + r2 * kPartRow;
+            g6[0] += pr2[0];
+            g6[1] += pr2[1];
+            g6[2] += pr2[2];
+            g6[3] += pr2[3];
+            g6[4] += pr2[4];
+            g6[5] += pr2[6];
+          }
+          const int64_t it = sit[j];
+          const float4 a0 = aux[it * 3 + 0], a1 = aux[it * 3 + 1], a2 = aux[it * 3 + 2];
+          const float p[3] = {a0.x, a0.y, a0.z};
+          const float s6[6] = {a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
+          float Sc[9], dp[3], G[9];
+          sym3(s6, Sc);
+          camera_space_grads(p, Sc, J.fx, J.fy, g6, dp, G);
+          pose_contrib(p, Sc, Rd, td, dp, G, pacc);
         }
       }
     }
     __syncthreads();
+  }
+  if (kPoseOnly && w == 0) {
+    // entry threads are all in wave 0: its fixed-order sum is the tile's partial
+#pragma unroll
+    for (int k = 0; k < kPoseAcc; ++k) {
+      const float v = wave_sum(pacc[k]);
+      if (lane == 0) tile_part[(int64_t)tile * kPoseAcc + k] = v;
+    }
   }
 }
 
@@ -418,17 +474,20 @@ void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, in
 }
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
-                          const int32_t* items, const int32_t* range, const float* bg, const float* Tf,
-                          const int32_t* nl, const float* up_rgb, const float* up_depth, const float* up_alpha,
-                          const float* up_scale, float* g2d, int pose_only, hipStream_t s) {
+                          const float* aux, const float* pose, const int32_t* items, const int32_t* range,
+                          const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
+                          const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
+                          float* tile_part, int pose_only, hipStream_t s) {
   if (T <= 0) return;
+  const float4* rec4 = reinterpret_cast<const float4*>(rec);
+  const float4* aux4 = reinterpret_cast<const float4*>(aux);
   if (pose_only)
-    hipLaunchKernelGGL(k_composite_bwd<true>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
-                       reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb,
-                       up_depth, up_alpha, up_scale, g2d);
+    hipLaunchKernelGGL(k_composite_bwd<true>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, aux4,
+                       pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d,
+                       tile_part);
   else
-    hipLaunchKernelGGL(k_composite_bwd<false>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
-                       reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb,
-                       up_depth, up_alpha, up_scale, g2d);
+    hipLaunchKernelGGL(k_composite_bwd<false>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4,
+                       aux4, pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
+                       g2d, tile_part);
 }
 }  // namespace ls

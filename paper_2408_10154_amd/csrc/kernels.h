@@ -8,11 +8,13 @@ namespace ls {
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
-                    int32_t* radius, int32_t* tiles, hipStream_t s);
+                    int32_t* radius, int32_t* tiles, float* aux, hipStream_t s);
 
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
-                        const int32_t* radius, float* g2d, const GradDev* grads, int want_gauss,
+                        const int32_t* radius, const float* aux, float* g2d, const GradDev* grads, int want_gauss,
                         float* pose_part, int want_pose, float* pose_grad, hipStream_t s);
+void launch_pose_reduce_tiles(const JobDev* jobs, int R, const float* pose, const float* tile_part, float* pose_grad,
+                              hipStream_t s);
 
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
                      const float* rec, const int32_t* radius, const int32_t* tiles, int64_t cap, uint32_t* tile_of,
@@ -24,9 +26,10 @@ void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, in
                           float* alpha, float* Tf, int32_t* nl, hipStream_t s);
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
-                          const int32_t* items, const int32_t* range, const float* bg, const float* Tf,
-                          const int32_t* nl, const float* up_rgb, const float* up_depth, const float* up_alpha,
-                          const float* up_scale, float* g2d, int pose_only, hipStream_t s);
+                          const float* aux, const float* pose, const int32_t* items, const int32_t* range,
+                          const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
+                          const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
+                          float* tile_part, int pose_only, hipStream_t s);
 
 // Registration helpers (reg_kernels.hip).
 struct ViewOpt {
@@ -38,6 +41,10 @@ void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipS
 void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, int R, float beta1, float beta2,
                       float eps, hipStream_t s);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
+void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
+                        float* nm, float* nv, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt, int R,
+                        hipStream_t s);
+void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s);
 
 void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                          const int32_t* items, const int32_t* range, const int32_t* nl, int64_t* stats, hipStream_t s);

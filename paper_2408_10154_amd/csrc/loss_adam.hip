@@ -26,14 +26,15 @@ __global__ __launch_bounds__(256) void k_loss_l1(const JobDev* __restrict__ jobs
     if (p >= hw) break;
     const int64_t pi = J.pix_off + p;
     const int64_t ci = 3 * J.pix_off + p;
-    const float td = tgt_depth[pi];
+    const float* trgb = tgt_rgb ? tgt_rgb + ci : J.tgt_rgb + p;  // per-render targets when not batch-laid-out
+    const float td = tgt_depth ? tgt_depth[pi] : J.tgt_depth[p];
     const bool valid = td > 0.f;
     float l = 0.f;
     const float dd = pred_depth[pi] - td;
     l += fabsf(dd);
     if (g_depth) g_depth[pi] = valid ? (dd > 0.f ? 1.f : (dd < 0.f ? -1.f : 0.f)) : 0.f;
     for (int ch = 0; ch < 3; ++ch) {
-      const float dc = pred_rgb[ci + ch * hw] - tgt_rgb[ci + ch * hw];
+      const float dc = pred_rgb[ci + ch * hw] - trgb[ch * hw];
       l += fabsf(dc);
       if (g_rgb) g_rgb[ci + ch * hw] = valid ? (dc > 0.f ? 1.f : (dc < 0.f ? -1.f : 0.f)) : 0.f;
     }

@@ -9,7 +9,8 @@ namespace ls {
 
 __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
                                                  int R, const float* __restrict__ pose, float4* __restrict__ rec,
-                                                 int32_t* __restrict__ radius_out, int32_t* __restrict__ tiles_out) {
+                                                 int32_t* __restrict__ radius_out, int32_t* __restrict__ tiles_out,
+                                                 float4* __restrict__ aux) {
   const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
   const JobDev& J = jobs[r];
   const int g = (blockIdx.x - J.blk_off) * 256 + threadIdx.x;
@@ -28,6 +29,7 @@ __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs
   float4* out = rec + item * 3;
   int rad = 0, ntiles = 0;
   float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
+  float4 x0 = make_float4(px, py, pz, 0.f), x1 = make_float4(0.f, 0.f, 0.f, 0.f), x2 = x1;
   if (pz > LS_NEAR_Z) {
     // Sigma = M M^T, M = R(q) diag(s)
     float Rq[9];
@@ -45,6 +47,13 @@ __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs
     const float j11 = J.fy * iz, j12 = -J.fy * py * iz * iz;
     float U0[3], U1[3];
     for (int k = 0; k < 3; ++k) { U0[k] = j00 * V[k] + j02 * V[6 + k]; U1[k] = j11 * V[3 + k] + j12 * V[6 + k]; }
+    // camera-space covariance V V^T (kept for the pose backward)
+    const float sxx = V[0] * V[0] + V[1] * V[1] + V[2] * V[2], sxy = V[0] * V[3] + V[1] * V[4] + V[2] * V[5];
+    const float sxz = V[0] * V[6] + V[1] * V[7] + V[2] * V[8], syy = V[3] * V[3] + V[4] * V[4] + V[5] * V[5];
+    const float syz = V[3] * V[6] + V[4] * V[7] + V[5] * V[8], szz = V[6] * V[6] + V[7] * V[7] + V[8] * V[8];
+    x0.w = sxx;
+    x1 = make_float4(sxy, sxz, syy, syz);
+    x2 = make_float4(szz, 0.f, 0.f, 0.f);
     const float a = U0[0] * U0[0] + U0[1] * U0[1] + U0[2] * U0[2] + LS_EPS_2D;
     const float b = U0[0] * U1[0] + U0[1] * U1[1] + U0[2] * U1[2];
     const float c = U1[0] * U1[0] + U1[1] * U1[1] + U1[2] * U1[2] + LS_EPS_2D;
@@ -72,6 +81,11 @@ __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs
   out[0] = o0;
   out[1] = o1;
   out[2] = o2;
+  if (aux) {
+    aux[item * 3 + 0] = x0;
+    aux[item * 3 + 1] = x1;
+    aux[item * 3 + 2] = x2;
+  }
   radius_out[item] = rad;
   tiles_out[item] = ntiles;
 }
@@ -101,13 +115,14 @@ __device__ __forceinline__ void store_grad(float* p, float v, bool shared) {
   if (shared) atomic_add_f32(p, v); else *p += v;
 }
 
-// Chains image-space gradients (du dv dA dB dC dop dz dr dg db per item) to
-// the Gaussian parameters and to the per-render pose correction.
+// Chains image-space gradients (du dv dA dB dC dop dz dr dg db, accumulated
+// per item over its tiles) to the Gaussian parameters and to the per-render
+// pose correction, and clears the accumulator for the next backward.
 __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
                                                      int R, const float* __restrict__ pose,
-                                                     const int32_t* __restrict__ radius, float* __restrict__ g2d,
-                                                     const GradDev* __restrict__ grads, int want_gauss,
-                                                     float* __restrict__ pose_part, int want_pose) {
+                                                     const int32_t* __restrict__ radius, const float4* __restrict__ aux,
+                                                     float* __restrict__ g2d, const GradDev* __restrict__ grads,
+                                                     int want_gauss, float* __restrict__ pose_part, int want_pose) {
   const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
   const JobDev& J = jobs[r];
   const int g = (blockIdx.x - J.blk_off) * 256 + threadIdx.x;
@@ -125,65 +140,19 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
       gi[q] = gp[q];
       gp[q] = 0.f;  // leave the accumulator cleared for the next backward
     }
-    const float du = gi[0], dv = gi[1], dA = gi[2], dB = gi[3], dC = gi[4];
-    const float dop = gi[5], dz = gi[6];
-
-    float W[9], t[3];
+    const float4 a0 = aux[item * 3 + 0], a1 = aux[item * 3 + 1], a2 = aux[item * 3 + 2];
+    const float p[3] = {a0.x, a0.y, a0.z};
+    const float s6[6] = {a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
+    float Sc[9];
+    sym3(s6, Sc);
+    const float g6[6] = {gi[0], gi[1], gi[2], gi[3], gi[4], gi[6]};
+    float dp[3], G[9];
+    camera_space_grads(p, Sc, J.fx, J.fy, g6, dp, G);
     const float* pr = pose ? pose + 7 * r : nullptr;
-    camera_of(J, pr, W, t);
-    const float mx = J.mean[g], my = J.mean[n + g], mz = J.mean[2 * n + g];
-    const float px = W[0] * mx + W[1] * my + W[2] * mz + t[0];
-    const float py = W[3] * mx + W[4] * my + W[5] * mz + t[1];
-    const float pz = W[6] * mx + W[7] * my + W[8] * mz + t[2];
-    const float qw0 = J.quat[g], qx0 = J.quat[n + g], qy0 = J.quat[2 * n + g], qz0 = J.quat[3 * n + g];
-    float Rq[9];
-    quat_to_rot(qw0, qx0, qy0, qz0, Rq);
-    const float s[3] = {__expf(J.log_scale[g]), __expf(J.log_scale[n + g]), __expf(J.log_scale[2 * n + g])};
-    float M[9];
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 3; ++k) M[i * 3 + k] = Rq[i * 3 + k] * s[k];
-    float V[9];  // W M
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 3; ++k) V[i * 3 + k] = W[i * 3 + 0] * M[0 * 3 + k] + W[i * 3 + 1] * M[1 * 3 + k] + W[i * 3 + 2] * M[2 * 3 + k];
-    float Sc[9];  // Sigma_c = V V^T
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 3; ++k) Sc[i * 3 + k] = V[i * 3 + 0] * V[k * 3 + 0] + V[i * 3 + 1] * V[k * 3 + 1] + V[i * 3 + 2] * V[k * 3 + 2];
-    const float iz = 1.0f / pz;
-    const float fx = J.fx, fy = J.fy;
-    const float J0[3] = {fx * iz, 0.f, -fx * px * iz * iz};
-    const float J1[3] = {0.f, fy * iz, -fy * py * iz * iz};
-    float SJ0[3], SJ1[3];  // Sigma_c J0^T, Sigma_c J1^T
-    for (int i = 0; i < 3; ++i) {
-      SJ0[i] = Sc[i * 3 + 0] * J0[0] + Sc[i * 3 + 1] * J0[1] + Sc[i * 3 + 2] * J0[2];
-      SJ1[i] = Sc[i * 3 + 0] * J1[0] + Sc[i * 3 + 1] * J1[1] + Sc[i * 3 + 2] * J1[2];
-    }
-    const float a = J0[0] * SJ0[0] + J0[1] * SJ0[1] + J0[2] * SJ0[2] + LS_EPS_2D;
-    const float b = J0[0] * SJ1[0] + J0[1] * SJ1[1] + J0[2] * SJ1[2];
-    const float c = J1[0] * SJ1[0] + J1[1] * SJ1[1] + J1[2] * SJ1[2] + LS_EPS_2D;
-    const float det = a * c - b * b;
-    const float id2 = 1.0f / (det * det);
-    // conic (A, B, C) = (c, -b, a) / det  ->  gradients of (a, b, c)
-    const float ga = (-c * c * dA + b * c * dB - b * b * dC) * id2;
-    const float gb = (2.f * b * c * dA - (det + 2.f * b * b) * dB + 2.f * a * b * dC) * id2;
-    const float gc = (-b * b * dA + a * b * dB - a * a * dC) * id2;
-    // dL/dSigma_c (symmetric) = ga J0^T J0 + gb (J0^T J1 + J1^T J0)/2 + gc J1^T J1
-    float G[9];
-    for (int i = 0; i < 3; ++i)
-      for (int k = 0; k < 3; ++k)
-        G[i * 3 + k] = ga * J0[i] * J0[k] + 0.5f * gb * (J0[i] * J1[k] + J1[i] * J0[k]) + gc * J1[i] * J1[k];
-    // dL/dJ0 = 2 ga Sigma J0 + gb Sigma J1 ; dL/dJ1 = gb Sigma J0 + 2 gc Sigma J1
-    const float gJ00 = 2.f * ga * SJ0[0] + gb * SJ1[0];
-    const float gJ02 = 2.f * ga * SJ0[2] + gb * SJ1[2];
-    const float gJ11 = gb * SJ0[1] + 2.f * gc * SJ1[1];
-    const float gJ12 = gb * SJ0[2] + 2.f * gc * SJ1[2];
-    const float iz2 = iz * iz, iz3 = iz2 * iz;
-    float dp[3];
-    dp[0] = du * fx * iz - gJ02 * fx * iz2;
-    dp[1] = dv * fy * iz - gJ12 * fy * iz2;
-    dp[2] = -du * fx * px * iz2 - dv * fy * py * iz2 + dz - gJ00 * fx * iz2 + gJ02 * 2.f * fx * px * iz3 -
-            gJ11 * fy * iz2 + gJ12 * 2.f * fy * py * iz3;
 
     if (want_gauss) {
+      float W[9], t[3];
+      camera_of(J, pr, W, t);
       const GradDev& GD = grads[r];
       const bool sh = GD.shared != 0;
       if (GD.mean) {
@@ -191,6 +160,13 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
           store_grad(GD.mean + k * n + g, W[0 * 3 + k] * dp[0] + W[1 * 3 + k] * dp[1] + W[2 * 3 + k] * dp[2], sh);
       }
       if (GD.log_scale || GD.quat) {
+        const float qw0 = J.quat[g], qx0 = J.quat[n + g], qy0 = J.quat[2 * n + g], qz0 = J.quat[3 * n + g];
+        float Rq[9];
+        quat_to_rot(qw0, qx0, qy0, qz0, Rq);
+        const float s[3] = {__expf(J.log_scale[g]), __expf(J.log_scale[n + g]), __expf(J.log_scale[2 * n + g])};
+        float M[9];
+        for (int i = 0; i < 3; ++i)
+          for (int k = 0; k < 3; ++k) M[i * 3 + k] = Rq[i * 3 + k] * s[k];
         // dL/dSigma = W^T G W ; dL/dM = 2 dL/dSigma M
         float GW[9];
         for (int i = 0; i < 3; ++i)
@@ -216,29 +192,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
       }
       if (GD.opac) {
         const float op = 1.0f / (1.0f + __expf(-J.opac[g]));
-        store_grad(GD.opac + g, dop * op * (1.f - op), sh);
+        store_grad(GD.opac + g, gi[5] * op * (1.f - op), sh);
       }
       if (GD.rgb) {
         for (int k = 0; k < 3; ++k) store_grad(GD.rgb + k * n + g, gi[7 + k], sh);
       }
     }
     if (want_pose && pr != nullptr) {
-      // p = R_d p0 + t_d, Sigma_c = R_d Sigma0 R_d^T:
-      // dL/dR_d = dp p0^T + 2 G Sigma_c R_d ; dL/dt_d = dp
       float Rd[9];
       quat_to_rot(pr[0], pr[1], pr[2], pr[3], Rd);
-      const float p0[3] = {px - pr[4], py - pr[5], pz - pr[6]};
-      float q0[3];  // R_d^T (p - t_d)
-      for (int k = 0; k < 3; ++k) q0[k] = Rd[0 * 3 + k] * p0[0] + Rd[1 * 3 + k] * p0[1] + Rd[2 * 3 + k] * p0[2];
-      float GSc[9];
-      for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k) GSc[i * 3 + k] = G[i * 3 + 0] * Sc[0 * 3 + k] + G[i * 3 + 1] * Sc[1 * 3 + k] + G[i * 3 + 2] * Sc[2 * 3 + k];
-      for (int i = 0; i < 3; ++i)
-        for (int k = 0; k < 3; ++k)
-          acc[i * 3 + k] = dp[i] * q0[k] + 2.f * (GSc[i * 3 + 0] * Rd[0 * 3 + k] + GSc[i * 3 + 1] * Rd[1 * 3 + k] + GSc[i * 3 + 2] * Rd[2 * 3 + k]);
-      acc[9] = dp[0];
-      acc[10] = dp[1];
-      acc[11] = dp[2];
+      pose_contrib(p, Sc, Rd, pr + 4, dp, G, acc);
     }
   }
   if (want_pose) {
@@ -258,19 +221,21 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
   }
 }
 
-// Per render: sum the block partials in order, chain dL/dR_d to the
-// quaternion, accumulate into pose_grad [R][7].  One wave per render.
+// Per render: sum the partials in order (per 256-item block of the render,
+// or per tile when by_tile is set), chain dL/dR_d to the quaternion,
+// accumulate into pose_grad [R][7].  One wave per render.
 __global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const float* __restrict__ pose,
-                              const float* __restrict__ pose_part, float* __restrict__ pose_grad) {
+                              const float* __restrict__ pose_part, float* __restrict__ pose_grad, int by_tile) {
   const int r = blockIdx.x;
   if (r >= R) return;
   const JobDev& J = jobs[r];
-  const int nb = (J.n + 255) / 256;
+  const int first = by_tile ? J.tile_off : J.blk_off;
+  const int nb = by_tile ? J.TX * J.TY : (J.n + 255) / 256;
   const int lane = threadIdx.x;
   float acc[kPoseAcc];
   for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
   for (int b = lane; b < nb; b += 64)
-    for (int k = 0; k < kPoseAcc; ++k) acc[k] += pose_part[(int64_t)(J.blk_off + b) * kPoseAcc + k];
+    for (int k = 0; k < kPoseAcc; ++k) acc[k] += pose_part[(int64_t)(first + b) * kPoseAcc + k];
   for (int k = 0; k < kPoseAcc; ++k) acc[k] = wave_sum(acc[k]);
   if (lane == 0) {
     const float* pr = pose + 7 * r;
@@ -286,17 +251,23 @@ __global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const floa
 
 namespace ls {
 void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
-                    int32_t* radius, int32_t* tiles, hipStream_t s) {
+                    int32_t* radius, int32_t* tiles, float* aux, hipStream_t s) {
   if (nblk > 0)
     hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, reinterpret_cast<float4*>(rec),
-                       radius, tiles);
+                       radius, tiles, reinterpret_cast<float4*>(aux));
 }
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
-                        const int32_t* radius, float* g2d, const GradDev* grads, int want_gauss,
+                        const int32_t* radius, const float* aux, float* g2d, const GradDev* grads, int want_gauss,
                         float* pose_part, int want_pose, float* pose_grad, hipStream_t s) {
   if (nblk > 0)
-    hipLaunchKernelGGL(k_project_bwd, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius, g2d, grads,
-                       want_gauss, pose_part, want_pose);
-  if (want_pose) hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, pose_part, pose_grad);
+    hipLaunchKernelGGL(k_project_bwd, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius,
+                       reinterpret_cast<const float4*>(aux), g2d, grads, want_gauss, pose_part, want_pose);
+  if (want_pose)
+    hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, (const float*)pose_part, pose_grad, 0);
+}
+
+void launch_pose_reduce_tiles(const JobDev* jobs, int R, const float* pose, const float* tile_part, float* pose_grad,
+                              hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, tile_part, pose_grad, 1);
 }
 }  // namespace ls

@@ -3,6 +3,8 @@
 // an iteration can be captured once in a graph and replayed.
 #include "kernels.h"
 
+#include <algorithm>
+
 namespace ls {
 
 __global__ void k_pose_init(float* __restrict__ pose, float* __restrict__ m, float* __restrict__ v,
@@ -62,6 +64,48 @@ void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt
 
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s) {
   hipLaunchKernelGGL(k_or_flag, dim3(1), dim3(64), 0, s, count, sticky);
+}
+
+}  // namespace ls
+
+namespace ls {
+
+// New epoch's per-view state from the previous epoch's: views that continue
+// (map[r] >= 0) keep pose, Adam moments and step; new views start at the
+// identity with the settings in init_opt.
+__global__ void k_state_remap(const float* __restrict__ opose, const float* __restrict__ om,
+                              const float* __restrict__ ov, const ViewOpt* __restrict__ oopt,
+                              float* __restrict__ npose, float* __restrict__ nm, float* __restrict__ nv,
+                              ViewOpt* __restrict__ nopt, const int32_t* __restrict__ map,
+                              const ViewOpt* __restrict__ init_opt, int R) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  const int o = map[r];
+  for (int k = 0; k < 7; ++k) {
+    npose[7 * r + k] = o >= 0 ? opose[7 * o + k] : (k == 0 ? 1.f : 0.f);
+    nm[7 * r + k] = o >= 0 ? om[7 * o + k] : 0.f;
+    nv[7 * r + k] = o >= 0 ? ov[7 * o + k] : 0.f;
+  }
+  nopt[r] = o >= 0 ? oopt[o] : init_opt[r];
+}
+
+__global__ void k_all_finite(const float* __restrict__ a, int64_t n, int32_t* __restrict__ bad) {
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+    if (!isfinite(a[i])) { *bad = 1; return; }
+}
+
+void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
+                        float* nm, float* nv, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt, int R,
+                        hipStream_t s) {
+  if (R > 0)
+    hipLaunchKernelGGL(k_state_remap, dim3((R + 127) / 128), dim3(128), 0, s, opose, om, ov, oopt, npose, nm, nv, nopt,
+                       map, init_opt, R);
+}
+
+void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s) {
+  if (n <= 0) return;
+  const int64_t blocks = std::min<int64_t>((n + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_all_finite, dim3((unsigned)blocks), dim3(256), 0, s, a, n, bad);
 }
 
 }  // namespace ls

@@ -187,16 +187,18 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off = (off + std::max<size_t>(bytes, 4) + 255) & ~size_t(255); return o; };
   const size_t o_rec = take(48 * (size_t)std::max<int64_t>(M, 1)), o_rad = take(4 * M), o_til = take(4 * M);
+  const size_t o_aux = take(48 * (size_t)std::max<int64_t>(M, 1));
   const size_t o_rgb = take(12 * P), o_dep = take(4 * P), o_alp = take(4 * P), o_T = take(4 * P), o_nl = take(4 * P);
   const size_t o_trgb = take(12 * P), o_tdep = take(4 * P), o_grgb = take(12 * P), o_gdep = take(4 * P);
   const size_t o_scale = take(4 * R), o_loss = take(4 * R), o_pose = take(28 * R), o_pg = take(28 * R);
   const size_t o_m = take(28 * R), o_v = take(28 * R), o_opt = take(sizeof(ViewOpt) * R), o_range = take(8 * (size_t)T);
-  const size_t o_count = take(8), o_sticky = take(4);
+  const size_t o_count = take(16), o_sticky = take(4);
   if (hipMalloc(&arena, off) != hipSuccess) return LS_ERR_HIP;
   char* a = static_cast<char*>(arena);
   proj.rec = reinterpret_cast<float*>(a + o_rec);
   proj.radius = reinterpret_cast<int32_t*>(a + o_rad);
   proj.tiles = reinterpret_cast<int32_t*>(a + o_til);
+  proj.aux = reinterpret_cast<float*>(a + o_aux);
   img.rgb = reinterpret_cast<float*>(a + o_rgb);
   img.depth = reinterpret_cast<float*>(a + o_dep);
   img.alpha = reinterpret_cast<float*>(a + o_alp);
@@ -264,20 +266,16 @@ ls_status RegEngine::alloc_bins(int64_t cap) {
 
 ls_status RegEngine::size_capacity(hipStream_t s, double headroom) {
   ls_status st;
-  int64_t cap = std::max<int64_t>(4096, 12 * M);
+  int64_t cap = std::max<int64_t>(4096, 6 * M);
   for (int attempt = 0; attempt < 3; ++attempt) {
     if ((st = alloc_bins(cap))) return st;
     if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
-    int32_t hc[2];
-    if (hipMemcpyAsync(hc, count, 8, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    int32_t hc[4];
+    if (hipMemcpyAsync(hc, count, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
       return LS_ERR_HIP;
-    if (hc[1] == 0) {
-      const int64_t want = std::max<int64_t>(4096, (int64_t)(hc[0] * headroom));
-      if (want > cap) return alloc_bins(want);
-      return LS_OK;
-    }
-    // overflow: the exact total is the sum of the tile counts; grow generously
-    cap = std::min<int64_t>((int64_t)INT32_MAX, cap * 4);
+    const int64_t want = std::min<int64_t>((int64_t)INT32_MAX, std::max<int64_t>(4096, (int64_t)(hc[2] * headroom)));
+    if (hc[1] == 0) return want > cap ? alloc_bins(want) : LS_OK;
+    cap = want;  // overflow: re-bin with the required count plus headroom
   }
   return LS_ERR_CAPACITY;
 }
@@ -289,8 +287,8 @@ ls_status RegEngine::step(hipStream_t s) {
   launch_or_flag(count, sticky, s);
   if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
       (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)) ||
-      (st = ls_render_bwd_tiles(batch, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
-      (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, s)))
+      (st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
+      (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
     return st;
   const ls_reg_params& pm = pairs[0].prm;
   launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, R, pm.beta1, pm.beta2, pm.adam_eps, s);

@@ -52,7 +52,7 @@ class ls_batch_info(C.Structure):
 
 
 class ls_projected(C.Structure):
-    _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles", C.c_void_p)]
+    _fields_ = [("rec", C.c_void_p), ("radius", C.c_void_p), ("tiles", C.c_void_p), ("aux", C.c_void_p)]
 
 
 class ls_bins(C.Structure):
@@ -90,6 +90,17 @@ class ls_reg_result(C.Structure):
                 ("status", C.c_int32), ("iters_done", C.c_int32)]
 
 
+class ls_server_params(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("chunk_iters", C.c_int32),
+                ("instance_headroom", C.c_float), ("use_graphs", C.c_int32)]
+
+
+class ls_server_stats(C.Structure):
+    _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("epochs", C.c_int64),
+                ("iterations", C.c_int64), ("graph_replays", C.c_int64), ("overflow_retries", C.c_int64),
+                ("peak_bytes", C.c_int64), ("active", C.c_int32), ("waiting", C.c_int32)]
+
+
 class ls_adam_group(C.Structure):
     _fields_ = [("param", C.c_void_p), ("grad", C.c_void_p), ("m", C.c_void_p), ("v", C.c_void_p),
                 ("n", C.c_int64), ("lr", C.c_float)]
@@ -109,9 +120,10 @@ _PROTOS = {
     "ls_render_fwd": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image), _P]),
     "ls_render_bwd": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
                                   C.POINTER(ls_image_grad), _P, _P, _P]),
-    "ls_render_bwd_tiles": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
+    "ls_render_bwd_tiles": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
                                         C.POINTER(ls_image_grad), C.c_uint32, _P]),
-    "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, _P]),
+    "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, C.c_uint32,
+                                          _P]),
     "ls_render_stats": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), C.POINTER(ls_image), _P, _P]),
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
@@ -119,6 +131,11 @@ _PROTOS = {
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
     "ls_register_pair": (C.c_int32, [C.POINTER(ls_pair), C.POINTER(ls_reg_params), C.POINTER(ls_reg_result), _P]),
     "ls_fuse_estimates": (C.c_int32, [_P, _P, _P, C.c_int32, _P]),
+    "ls_server_create": (C.c_int32, [C.POINTER(ls_server_params), C.POINTER(_P)]),
+    "ls_register_submit": (C.c_int32, [_P, C.POINTER(ls_pair), C.POINTER(ls_reg_params), C.POINTER(C.c_uint64)]),
+    "ls_register_poll": (C.c_int32, [_P, C.c_uint64, C.POINTER(ls_reg_result), _P]),
+    "ls_server_get_stats": (C.c_int32, [_P, C.POINTER(ls_server_stats)]),
+    "ls_server_destroy": (C.c_int32, [_P]),
 }
 
 _lib = None
@@ -193,12 +210,13 @@ def ls_render_bwd(h, pose, proj, bins, bg, fwd, up, grads, pose_grad, stream):
                  pose_grad, stream)
 
 
-def ls_render_bwd_tiles(h, proj, bins, bg, fwd, up, flags, stream):
-    return _call("ls_render_bwd_tiles", h, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), flags, stream)
+def ls_render_bwd_tiles(h, pose, proj, bins, bg, fwd, up, flags, stream):
+    return _call("ls_render_bwd_tiles", h, pose, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), flags,
+                 stream)
 
 
-def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, stream):
-    return _call("ls_render_bwd_project", h, pose, C.byref(proj), C.byref(bins), grads, pose_grad, stream)
+def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, flags, stream):
+    return _call("ls_render_bwd_project", h, pose, C.byref(proj), C.byref(bins), grads, pose_grad, flags, stream)
 
 
 def ls_render_stats(h, proj, bins, fwd, stats, stream):

@@ -96,7 +96,9 @@ class RenderBatch:
         self.rec = torch.zeros(max(self.M, 1), L.REC_FLOATS, dtype=torch.float32, device=dev)
         self.radius = torch.zeros(max(self.M, 1), dtype=torch.int32, device=dev)
         self.tiles = torch.zeros(max(self.M, 1), dtype=torch.int32, device=dev)
-        self.proj = L.ls_projected(self.rec.data_ptr(), self.radius.data_ptr(), self.tiles.data_ptr())
+        self.aux = torch.zeros(max(self.M, 1), 12, dtype=torch.float32, device=dev)
+        self.proj = L.ls_projected(self.rec.data_ptr(), self.radius.data_ptr(), self.tiles.data_ptr(),
+                                   self.aux.data_ptr())
         self.rgb = torch.zeros(3 * self.P, dtype=torch.float32, device=dev)
         self.depth = torch.zeros(self.P, dtype=torch.float32, device=dev)
         self.alpha = torch.zeros(self.P, dtype=torch.float32, device=dev)
@@ -104,7 +106,7 @@ class RenderBatch:
         self.n_last = torch.zeros(self.P, dtype=torch.int32, device=dev)
         self.image = L.ls_image(self.rgb.data_ptr(), self.depth.data_ptr(), self.alpha.data_ptr(),
                                 self.T_final.data_ptr(), self.n_last.data_ptr())
-        self.count = torch.zeros(2, dtype=torch.int32, device=dev)
+        self.count = torch.zeros(4, dtype=torch.int32, device=dev)
         self.range = torch.zeros(max(self.T, 1), 2, dtype=torch.int32, device=dev)
         self.auto_grow = auto_grow
         self.capacity = 0
@@ -155,8 +157,7 @@ class RenderBatch:
         if self.auto_grow:
             cnt = self.count.cpu()
             if int(cnt[1]) != 0:
-                need = int(self.tiles[: self.M].sum().item()) if self.M else 0
-                self._alloc_bins(int(need * 1.25) + 1024)
+                self._alloc_bins(int(int(cnt[2]) * 1.25) + 1024)
                 L.ls_bin_sort(self.h, self.proj, self.bins, _stream())
 
     def instances(self) -> int:
@@ -188,17 +189,19 @@ class RenderBatch:
         L.ls_render_bwd(self.h, _ptr(pose), self.proj, self.bins, bgc, self.image, up, garr, _ptr(pose_grad),
                         _stream())
 
-    def render_bwd_tiles(self, up_rgb=None, up_depth=None, up_alpha=None, scale=None, bg=None, pose_only=False):
+    def render_bwd_tiles(self, up_rgb=None, up_depth=None, up_alpha=None, scale=None, bg=None, pose=None,
+                         pose_only=False):
+        self._check_pose(pose)
         self._check_dev(up_rgb, 3 * self.P, name="up_rgb")
         self._check_dev(up_depth, self.P, name="up_depth")
         self._check_dev(up_alpha, self.P, name="up_alpha")
         self._check_dev(scale, self.R, name="scale")
         up = L.ls_image_grad(*[None if t is None else t.data_ptr() for t in (up_rgb, up_depth, up_alpha, scale)])
         bgc = (C.c_float * 3)(*bg) if bg is not None else None
-        L.ls_render_bwd_tiles(self.h, self.proj, self.bins, bgc, self.image, up, L.BWD_POSE_ONLY if pose_only else 0,
-                              _stream())
+        L.ls_render_bwd_tiles(self.h, _ptr(pose), self.proj, self.bins, bgc, self.image, up,
+                              L.BWD_POSE_ONLY if pose_only else 0, _stream())
 
-    def render_bwd_project(self, grads=None, pose=None, pose_grad=None):
+    def render_bwd_project(self, grads=None, pose=None, pose_grad=None, pose_only=False):
         self._check_pose(pose)
         self._check_dev(pose_grad, 7 * self.R, name="pose_grad")
         garr = None
@@ -206,7 +209,8 @@ class RenderBatch:
             if len(grads) != self.R:
                 raise ValueError("need one gradient set per render")
             garr = (L.ls_gaussian_grads * self.R)(*[g.grads_c() for g in grads])
-        L.ls_render_bwd_project(self.h, _ptr(pose), self.proj, self.bins, garr, _ptr(pose_grad), _stream())
+        L.ls_render_bwd_project(self.h, _ptr(pose), self.proj, self.bins, garr, _ptr(pose_grad),
+                                L.BWD_POSE_ONLY if pose_only else 0, _stream())
 
     def render_stats(self):
         """(entries evaluated, entries composited) of the last forward (syncs)."""

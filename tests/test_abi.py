@@ -40,7 +40,7 @@ def test_binding_covers_the_header():
     assert set(L.declared_functions()) == declared()
 
 
-@pytest.mark.parametrize("name", ["ls_pair", "ls_reg_params", "ls_reg_result", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
+@pytest.mark.parametrize("name", ["ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
                                   "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group"])
 def test_struct_layouts_match(name):
     lib = L.load()
@@ -76,3 +76,14 @@ def test_register_pair_rejects_bad_parameters_before_touching_a_device():
     prm.iters = 10
     assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID  # no views
     assert lib.ls_fuse_estimates(None, None, None, 0, None) == L.LS_ERR_INVALID
+
+
+def test_server_rejects_bad_parameters_without_a_device():
+    lib = L.load()
+    h = C.c_void_p()
+    prm = L.ls_server_params(1 << 30, 0, 16, 1.5, 1)  # max_slots = 0
+    assert lib.ls_server_create(C.byref(prm), C.byref(h)) == L.LS_ERR_INVALID
+    prm = L.ls_server_params(1 << 30, 4, 16, 0.1, 1)  # headroom < 0.25
+    assert lib.ls_server_create(C.byref(prm), C.byref(h)) == L.LS_ERR_INVALID
+    assert lib.ls_register_poll(None, 1, None, None) == L.LS_ERR_INVALID
+    assert lib.ls_server_destroy(None) == L.LS_OK
