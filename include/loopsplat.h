@@ -318,9 +318,11 @@ typedef struct {
 } ls_pair;
 
 typedef struct {
-  int32_t iters;            /* Adam iterations per view (>= 1) */
+  int32_t iters;            /* Adam iterations per view (>= 1): the maximum when early exit is on */
   float lr_rot, lr_trans;   /* learning rates of the quaternion and the translation */
   float beta1, beta2, adam_eps;
+  float exit_rel_tol;       /* early exit: a view stops once its loss has not improved on its best */
+  int32_t exit_patience;    /* by more than exit_rel_tol (relative) for exit_patience iterations; 0 = off */
 } ls_reg_params;
 
 typedef struct {
@@ -328,7 +330,7 @@ typedef struct {
   float* per_view_T;  /* host [vP + vQ][12] or NULL: E_i (P views: ~T_{P->Q}; Q views: ~T_{Q->P}) */
   float* residual;    /* host [vP + vQ] or NULL: eps_i, the final L1 loss of each view */
   int32_t status;     /* LS_OK, or the error of this pair */
-  int32_t iters_done;
+  int32_t iters_done; /* Adam steps of the longest-running view */
 } ls_reg_result;
 
 /* Registers one pair with all 2V views in one launch set per iteration.

@@ -36,14 +36,18 @@ struct ViewOpt {
   float lr_rot, lr_trans;
   int32_t step;    // Adam steps taken so far
   int32_t active;  // 0: frozen (no update)
+  float best;      // lowest loss seen (early exit)
+  int32_t stall;   // iterations since the loss last improved on best by more than the tolerance
+  float resid;     // loss at the pose the view froze at
+  int32_t pad;
 };
 void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s);
-void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, int R, float beta1, float beta2,
-                      float eps, hipStream_t s);
+void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
+                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
 void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
-                        float* nm, float* nv, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt, int R,
-                        hipStream_t s);
+                        float* nm, float* nv, float* ngrad, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt,
+                        int R, hipStream_t s);
 void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s);
 
 void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,

@@ -14,34 +14,62 @@ __global__ void k_pose_init(float* __restrict__ pose, float* __restrict__ m, flo
   pose[i] = (i % 7) == 0 ? 1.f : 0.f;
   m[i] = 0.f;
   v[i] = 0.f;
-  if (i < R) opt[i].step = 0;
+  if (i < R) {
+    opt[i].step = 0;
+    opt[i].active = 1;
+    opt[i].stall = 0;
+    opt[i].best = 0.f;
+    opt[i].resid = 0.f;
+  }
 }
 
 // One thread per render: Adam on its 7 pose values (lr_rot for q, lr_trans
 // for t), bias correction from the render's own step count; the gradient is
-// consumed (zeroed).  Frozen renders keep their pose and clear the gradient.
+// consumed (zeroed).  Early exit (exit_patience > 0): a view whose loss has
+// not improved on its best by more than the relative tolerance for
+// exit_patience iterations freezes at its current pose (whose loss is the
+// one just computed) instead of stepping.  Frozen views keep their pose.
 __global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ grad, float* __restrict__ m,
-                            float* __restrict__ v, ViewOpt* __restrict__ opt, int R, float beta1, float beta2,
-                            float eps) {
+                            float* __restrict__ v, ViewOpt* __restrict__ opt, const float* __restrict__ loss, int R,
+                            float beta1, float beta2, float eps, float exit_tol, int exit_patience) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   ViewOpt o = opt[r];
   if (o.active) {
-    const int step = o.step + 1;
-    const float bc1 = 1.f / (1.f - __powf(beta1, (float)step));
-    const float bc2 = 1.f / (1.f - __powf(beta2, (float)step));
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      const int i = 7 * r + k;
-      const float g = grad[i];
-      const float mi = beta1 * m[i] + (1.f - beta1) * g;
-      const float vi = beta2 * v[i] + (1.f - beta2) * g * g;
-      m[i] = mi;
-      v[i] = vi;
-      const float lr = k < 4 ? o.lr_rot : o.lr_trans;
-      pose[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+    bool step_now = true;
+    if (exit_patience > 0) {
+      const float l = loss[r];
+      if (o.step == 0 || l < o.best * (1.f - exit_tol)) {
+        o.best = o.step == 0 ? l : fminf(o.best, l);
+        o.stall = 0;
+      } else {
+        o.best = fminf(o.best, l);
+        ++o.stall;
+      }
+      if (o.stall >= exit_patience) {
+        o.active = 0;
+        o.resid = l;
+        step_now = false;
+      }
     }
-    opt[r].step = step;
+    if (step_now) {
+      const int step = o.step + 1;
+      const float bc1 = 1.f / (1.f - __powf(beta1, (float)step));
+      const float bc2 = 1.f / (1.f - __powf(beta2, (float)step));
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const int i = 7 * r + k;
+        const float g = grad[i];
+        const float mi = beta1 * m[i] + (1.f - beta1) * g;
+        const float vi = beta2 * v[i] + (1.f - beta2) * g * g;
+        m[i] = mi;
+        v[i] = vi;
+        const float lr = k < 4 ? o.lr_rot : o.lr_trans;
+        pose[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+      }
+      o.step = step;
+    }
+    opt[r] = o;
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k) grad[7 * r + k] = 0.f;
@@ -56,10 +84,10 @@ void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipS
   hipLaunchKernelGGL(k_pose_init, dim3((n + 255) / 256), dim3(256), 0, s, pose, m, v, opt, R);
 }
 
-void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, int R, float beta1, float beta2,
-                      float eps, hipStream_t s) {
-  hipLaunchKernelGGL(k_pose_adam, dim3((R + 255) / 256), dim3(256), 0, s, pose, grad, m, v, opt, R, beta1, beta2,
-                     eps);
+void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
+                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s) {
+  hipLaunchKernelGGL(k_pose_adam, dim3((R + 255) / 256), dim3(256), 0, s, pose, grad, m, v, opt, loss, R, beta1, beta2,
+                     eps, exit_tol, exit_patience);
 }
 
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s) {
@@ -76,7 +104,7 @@ namespace ls {
 __global__ void k_state_remap(const float* __restrict__ opose, const float* __restrict__ om,
                               const float* __restrict__ ov, const ViewOpt* __restrict__ oopt,
                               float* __restrict__ npose, float* __restrict__ nm, float* __restrict__ nv,
-                              ViewOpt* __restrict__ nopt, const int32_t* __restrict__ map,
+                              float* __restrict__ ngrad, ViewOpt* __restrict__ nopt, const int32_t* __restrict__ map,
                               const ViewOpt* __restrict__ init_opt, int R) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
@@ -85,6 +113,7 @@ __global__ void k_state_remap(const float* __restrict__ opose, const float* __re
     npose[7 * r + k] = o >= 0 ? opose[7 * o + k] : (k == 0 ? 1.f : 0.f);
     nm[7 * r + k] = o >= 0 ? om[7 * o + k] : 0.f;
     nv[7 * r + k] = o >= 0 ? ov[7 * o + k] : 0.f;
+    ngrad[7 * r + k] = 0.f;  // the backward accumulates into it; Adam consumes it
   }
   nopt[r] = o >= 0 ? oopt[o] : init_opt[r];
 }
@@ -95,11 +124,11 @@ __global__ void k_all_finite(const float* __restrict__ a, int64_t n, int32_t* __
 }
 
 void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
-                        float* nm, float* nv, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt, int R,
-                        hipStream_t s) {
+                        float* nm, float* nv, float* ngrad, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt,
+                        int R, hipStream_t s) {
   if (R > 0)
-    hipLaunchKernelGGL(k_state_remap, dim3((R + 127) / 128), dim3(128), 0, s, opose, om, ov, oopt, npose, nm, nv, nopt,
-                       map, init_opt, R);
+    hipLaunchKernelGGL(k_state_remap, dim3((R + 127) / 128), dim3(128), 0, s, opose, om, ov, oopt, npose, nm, nv,
+                       ngrad, nopt, map, init_opt, R);
 }
 
 void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s) {

@@ -234,7 +234,7 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   std::vector<ViewOpt> ho(R);
   for (int r = 0; r < R; ++r) {
     const ls_reg_params& pm = pairs[views[r].pair].prm;
-    ho[r] = ViewOpt{pm.lr_rot, pm.lr_trans, 0, 1};
+    ho[r] = ViewOpt{pm.lr_rot, pm.lr_trans, 0, 1, 0.f, 0, 0.f, 0};
   }
   if (hipMemcpyAsync(opt, ho.data(), sizeof(ViewOpt) * R, hipMemcpyHostToDevice, s) != hipSuccess) return LS_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return LS_ERR_HIP;
@@ -291,7 +291,8 @@ ls_status RegEngine::step(hipStream_t s) {
       (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
     return st;
   const ls_reg_params& pm = pairs[0].prm;
-  launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, R, pm.beta1, pm.beta2, pm.adam_eps, s);
+  launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, loss, R, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
+                   pm.exit_patience, s);
   return hip_ok();
 }
 
@@ -354,7 +355,8 @@ ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
   if (p->vP > 0 && (!p->rgbP || !p->depthP || !p->c2wP || p->Q.n < 0)) return LS_ERR_INVALID;
   if (p->vQ > 0 && (!p->rgbQ || !p->depthQ || !p->c2wQ || p->P.n < 0)) return LS_ERR_INVALID;
   if (prm->iters < 1 || !(prm->lr_rot >= 0) || !(prm->lr_trans >= 0) || !(prm->beta1 >= 0 && prm->beta1 < 1) ||
-      !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0))
+      !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0) || !(prm->exit_rel_tol >= 0) ||
+      prm->exit_patience < 0)
     return LS_ERR_INVALID;
   for (int i = 0; i < 12 * p->vP; ++i)
     if (!std::isfinite(p->c2wP[i])) return LS_ERR_NONFINITE;
@@ -399,11 +401,28 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg
       out->status = st;
       return st;
     }
-    for (int it = 0; it < prm->iters; ++it)
-      if ((st = e.step(s))) {
-        out->status = st;
-        return st;
+    int done = 0;
+    constexpr int kCheckEvery = 16;  // early exit: poll the views' active flags this often
+    while (done < prm->iters) {
+      const int k = prm->exit_patience > 0 ? std::min(kCheckEvery, prm->iters - done) : prm->iters - done;
+      for (int it = 0; it < k; ++it)
+        if ((st = e.step(s))) {
+          out->status = st;
+          return st;
+        }
+      done += k;
+      if (prm->exit_patience > 0 && done < prm->iters) {
+        std::vector<ViewOpt> ho(e.R);
+        if (hipMemcpyAsync(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess) {
+          out->status = LS_ERR_HIP;
+          return LS_ERR_HIP;
+        }
+        bool any = false;
+        for (const ViewOpt& o : ho) any |= o.active != 0;
+        if (!any) break;
       }
+    }
     std::vector<float> ph, lh;
     int32_t ovf = 0;
     if ((st = e.final_forward(s)) || (st = e.readback(ph, lh, &ovf, s))) {
@@ -416,7 +435,11 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg
     }
     st = e.fuse_pair(0, ph, lh, out);
     out->status = st;
-    out->iters_done = prm->iters;
+    std::vector<ViewOpt> ho(e.R);
+    hipMemcpy(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost);
+    int steps = 0;
+    for (const ViewOpt& o : ho) steps = std::max(steps, o.step);
+    out->iters_done = steps;
     return st;
   }
   out->status = LS_ERR_CAPACITY;

@@ -136,8 +136,11 @@ class Server {
         beta1_ = prm->beta1;
         beta2_ = prm->beta2;
         eps_ = prm->adam_eps;
+        exit_tol_ = prm->exit_rel_tol;
+        exit_patience_ = prm->exit_patience;
         have_betas_ = true;
-      } else if (prm->beta1 != beta1_ || prm->beta2 != beta2_ || prm->adam_eps != eps_) {
+      } else if (prm->beta1 != beta1_ || prm->beta2 != beta2_ || prm->adam_eps != eps_ ||
+                 prm->exit_rel_tol != exit_tol_ || prm->exit_patience != exit_patience_) {
         return LS_ERR_INVALID;
       }
     }
@@ -292,7 +295,7 @@ class Server {
           trgb.push_back((dir == 0 ? pr.rgbP : pr.rgbQ) + 3 * hw * i);
           tdep.push_back((dir == 0 ? pr.depthP : pr.depthQ) + hw * i);
           map.push_back(prev >= 0 ? prev + k : -1);
-          init.push_back(ViewOpt{s->rp.prm.lr_rot, s->rp.prm.lr_trans, 0, 1});
+          init.push_back(ViewOpt{s->rp.prm.lr_rot, s->rp.prm.lr_trans, 0, 1, 0.f, 0, 0.f, 0});
         }
       }
     }
@@ -318,7 +321,7 @@ class Server {
     hipMemcpyAsync(dmap, map.data(), 4 * (size_t)R_, hipMemcpyHostToDevice, stream_);
     hipMemcpyAsync(dinit, init.data(), sizeof(ViewOpt) * R_, hipMemcpyHostToDevice, stream_);
     StatePtrs a = state_ptrs(stateA_, std::max(Rold, 1)), b = state_ptrs(stateB_, R_);
-    launch_state_remap(a.pose, a.m, a.v, a.opt, b.pose, b.m, b.v, b.opt, dmap, dinit, R_, stream_);
+    launch_state_remap(a.pose, a.m, a.v, a.opt, b.pose, b.m, b.v, b.grad, b.opt, dmap, dinit, R_, stream_);
     if (hipStreamSynchronize(stream_) != hipSuccess) return LS_ERR_HIP;  // host map/init must outlive the copies
     std::swap(stateA_, stateB_);
 
@@ -412,7 +415,8 @@ class Server {
         (st = ls_render_bwd_tiles(batch_, s.pose, &proj_, &bins_c_, nullptr, &img_, &up, LS_BWD_POSE_ONLY, stream_)) ||
         (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
       return st;
-    launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, R_, beta1_, beta2_, eps_, stream_);
+    launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
+                     stream_);
     return LS_OK;
   }
 
@@ -478,9 +482,23 @@ class Server {
       stats_.overflow_retries += retries;
     }
     bool any_done = false;
+    std::vector<ViewOpt> ho;
+    if (exit_patience_ > 0) {  // pairs whose views have all stopped are finished early
+      ho.resize(R_);
+      hipMemcpyAsync(ho.data(), state_ptrs(stateA_, R_).opt, sizeof(ViewOpt) * R_, hipMemcpyDeviceToHost, stream_);
+      if (hipStreamSynchronize(stream_) != hipSuccess) {
+        fail_active(LS_ERR_HIP);
+        return;
+      }
+    }
     for (Slot* s : active_) {
       s->remaining -= k;
       s->iters_done += k;
+      if (!ho.empty()) {
+        bool any_active = false;
+        for (int v = 0; v < s->views; ++v) any_active |= ho[s->first_render + v].active != 0;
+        if (!any_active) s->remaining = 0;
+      }
       any_done |= s->remaining == 0;
     }
     if (any_done) retire();
@@ -583,7 +601,8 @@ class Server {
   std::mutex check_mu_;
   DevBuf check_buf_;
   bool have_betas_ = false;
-  float beta1_ = 0.9f, beta2_ = 0.999f, eps_ = 1e-8f;
+  float beta1_ = 0.9f, beta2_ = 0.999f, eps_ = 1e-8f, exit_tol_ = 0.f;
+  int32_t exit_patience_ = 0;
   std::thread worker_;
   std::mutex mu_;
   std::condition_variable cv_;

@@ -1,0 +1,89 @@
+"""Registration throughput and latency: the plain per-pair path
+(ls_register_pair, one pair at a time) against the serving loop (all pairs
+admitted together or as they arrive, continuously batched)."""
+
+from __future__ import annotations
+
+import math
+import time
+
+import numpy as np
+import torch
+
+from . import register as REG
+from . import synth
+from .render import GaussianSet
+
+
+def build_pair(spec: dict, width=640, height=480, f=500.0):
+    d = synth.registration_pair(spec["seed"], spec["n_p"], spec["n_q"], views_p=spec["views_p"],
+                                views_q=spec["views_q"], width=spec.get("width", width),
+                                height=spec.get("height", height), f=spec.get("f", f))
+    P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
+    rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
+    rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
+    return dict(T_gt=d["T_gt"], args=(P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ),
+                pixels=(spec["views_p"] + spec["views_q"]) * d["cam"]["width"] * d["cam"]["height"])
+
+
+def _errors(results, pairs):
+    rot = [REG.rotation_error_deg(r["T"], p["T_gt"]) for r, p in zip(results, pairs)]
+    tr = [REG.translation_error_cm(r["T"], p["T_gt"]) for r, p in zip(results, pairs)]
+    ok = [a < 0.5 and b < 1.0 for a, b in zip(rot, tr)]
+    return dict(success=float(np.mean(ok)), rot_deg_median=float(np.median(rot)), trans_cm_median=float(np.median(tr)),
+                rot_deg_max=float(np.max(rot)), trans_cm_max=float(np.max(tr)))
+
+
+def _pct(x, q):
+    return float(np.percentile(np.asarray(x, np.float64), q))
+
+
+def run_plain(pairs, iters=200):
+    """One pair at a time through ls_register_pair; latency of pair k counts
+    from the start of the run (all requests present at t = 0)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results, done = [], []
+    for p in pairs:
+        results.append(REG.register_pair(*p["args"], params=REG.default_params(iters)))
+        done.append(time.perf_counter() - t0)
+    total = time.perf_counter() - t0
+    return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(done, 50), p99_s=_pct(done, 99),
+                **_errors(results, pairs)), results
+
+
+def run_batched(pairs, iters=200, chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30):
+    """Every pair submitted at t = 0 to one server."""
+    from .serve import Server
+
+    with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters, use_graphs=use_graphs) as sv:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [sv.submit(*p["args"], params=REG.default_params(iters)) for p in pairs]
+        results = [sv.wait(t) for t in tickets]
+        total = time.perf_counter() - t0
+        st = sv.stats()
+    lat = [r["times"]["total"] for r in results]
+    return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(lat, 50), p99_s=_pct(lat, 99),
+                epochs=st["epochs"], graph_replays=st["graph_replays"], **_errors(results, pairs)), results
+
+
+def run_stream(stream, built, iters=200, chunk_iters=16, budget=200 << 30, max_slots=64):
+    """Requests submitted at their arrival times (a host thread paces them)."""
+    from .serve import Server
+
+    with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters) as sv:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = []
+        for spec, p in zip(stream, built):
+            delay = spec["arrival"] - (time.perf_counter() - t0)
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append(sv.submit(*p["args"], params=REG.default_params(iters)))
+        results = [sv.wait(t) for t in tickets]
+        total = time.perf_counter() - t0
+        st = sv.stats()
+    lat = [r["times"]["total"] for r in results]
+    return dict(seconds=total, pairs_per_s=len(built) / total, p50_s=_pct(lat, 50), p99_s=_pct(lat, 99),
+                max_active_bytes=st["peak_bytes"], **_errors(results, built)), results

@@ -39,8 +39,10 @@ def keyframe_targets(g: GaussianSet, cam: dict, c2ws: np.ndarray):
     return rgb, depth
 
 
-def default_params(iters=200, lr_rot=0.015, lr_trans=0.005) -> L.ls_reg_params:
-    return L.ls_reg_params(iters, lr_rot, lr_trans, 0.9, 0.999, 1e-8)
+def default_params(iters=200, lr_rot=0.015, lr_trans=0.005, exit_rel_tol=0.0, exit_patience=0) -> L.ls_reg_params:
+    """Registration settings: real-data learning rates of the paper's
+    loop-closure table by default; early exit off unless exit_patience > 0."""
+    return L.ls_reg_params(iters, lr_rot, lr_trans, 0.9, 0.999, 1e-8, exit_rel_tol, exit_patience)
 
 
 def make_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ):

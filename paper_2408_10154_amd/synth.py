@@ -260,3 +260,37 @@ def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, v
     kf_q = [t_gt @ c for c in keyframes(views_q)]
     return dict(P=P, Q=Q, kf_p=np.stack(kf_p).astype(np.float64), kf_q=np.stack(kf_q).astype(np.float64),
                 T_gt=t_gt, cam=camera(f, f, width / 2, height / 2, width, height), shared=s)
+
+
+def pair_set(seed: int, n_pairs: int, n_min: int = 20_000, n_max: int = 300_000, views_min: int = 4,
+             views_max: int = 12) -> list:
+    """Specs of a batch of registration pairs: per submap a Gaussian count
+    log-uniform in [n_min, n_max] and a keyframe count uniform in
+    {views_min..views_max}; each pair gets its own seed (hence its own room,
+    split and ground-truth transform)."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for k in range(n_pairs):
+        n_p, n_q = (int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max))))) for _ in range(2))
+        v_p, v_q = (int(rng.integers(views_min, views_max + 1)) for _ in range(2))
+        out.append(dict(seed=int(seed * 1000 + k), n_p=n_p, n_q=n_q, views_p=v_p, views_q=v_q))
+    return out
+
+
+def request_stream(seed: int, n_requests: int, rate_per_s: float, median_n: int = 100_000, sigma: float = 0.8,
+                   n_cap: int = 500_000, n_floor: int = 5_000, views_min: int = 4, views_max: int = 12,
+                   resolutions=((640, 480, 500.0), (1200, 680, 600.0))) -> list:
+    """A serving stream: Poisson arrivals at `rate_per_s` (exponential gaps),
+    submap sizes lognormal(median, sigma) clipped to [n_floor, n_cap], views
+    uniform in {views_min..views_max}, resolution drawn from `resolutions`."""
+    rng = np.random.default_rng(seed)
+    t = 0.0
+    out = []
+    for k in range(n_requests):
+        t += float(rng.exponential(1.0 / rate_per_s))
+        n_p, n_q = (int(np.clip(round(median_n * math.exp(sigma * rng.normal())), n_floor, n_cap)) for _ in range(2))
+        v_p, v_q = (int(rng.integers(views_min, views_max + 1)) for _ in range(2))
+        w, h, f = resolutions[int(rng.integers(len(resolutions)))]
+        out.append(dict(arrival=t, seed=int(seed * 100000 + k), n_p=n_p, n_q=n_q, views_p=v_p, views_q=v_q,
+                        width=int(w), height=int(h), f=float(f)))
+    return out

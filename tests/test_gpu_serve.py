@@ -138,3 +138,19 @@ def test_non_finite_pair_is_rejected_others_continue(pairs):
         assert e.value.status == L.LS_ERR_NONFINITE
         r = sv.wait(good)
     assert r["status"] == 0
+
+
+def test_reused_server_state_matches_plain(pairs):
+    """One slot: the three pairs run in three successive active sets on reused
+    buffers; each result still equals the plain path's bits (the per-view
+    gradient accumulator is cleared when a view is admitted)."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.serve import Server
+
+    with Server(max_slots=1, chunk_iters=9) as sv:
+        ts = [sv.submit(*p["args"], params=REG.default_params(ITERS)) for p in reversed(pairs)]
+        rs = [sv.wait(t) for t in ts]
+        st = sv.stats()
+    assert st["epochs"] >= 3
+    for r, p in zip(rs, reversed(pairs)):
+        assert r["status"] == 0 and _same(r, _plain(p))
