@@ -31,6 +31,17 @@ rendering steps, so each step below is a stated reading, numbered R1-R17
   R15 loss = mean over pixels with target depth > 0 of sum_c|C-C*| + |D-D*|
   R16 d|x|/dx = sign(x) with sign(0) = 0 (torch.abs)
   R17 no gradient through the alpha clamp when it is active
+  R24 tracking loss (Eq. 2 with the supplement's masks), per render:
+        L = (1/|Omega|) sum_{p in Omega} M_in M_a (lc sum_c|C-C*| + (1-lc)|D-D*|)
+      Omega = pixels with target depth > 0 (pixels without a valid depth
+      measurement are excluded); M_a = alpha^k (k = 3, a per-pixel weight,
+      no gradient flows through it); M_in = [e <= K_IN * median(e)], e =
+      |D - D*| over Omega, K_IN = 50, the median being the lower one (the
+      element of rank floor((n-1)/2) in ascending order).  The normalisation
+      by |Omega| instead of a plain sum leaves Adam's steps unchanged and
+      keeps residuals of views with different coverage comparable.  e, the
+      median and the inlier test are evaluated in FP32 on FP32 inputs, the
+      precision of the GPU path, since they decide a mask.
 
 Decisions that turn floating point into integers or control flow (radius,
 tile rect, cull, list order) are taken in FP32 on FP32-rounded inputs, the
@@ -380,6 +391,42 @@ def loss_l1(rgb, depth, tgt_rgb, tgt_depth):
         return (rgb.sum() + depth.sum()) * 0.0
     per_px = (torch.abs(rgb - tgt_rgb)).sum(0) + torch.abs(depth - tgt_depth)
     return (per_px * valid).sum() / cnt
+
+
+def lower_median_f32(x: np.ndarray) -> np.float32:
+    """Element of rank floor((n-1)/2) of the ascending order of x (float32);
+    0 for an empty array."""
+    x = np.sort(np.asarray(x, np.float32).ravel())
+    return x[(x.size - 1) // 2] if x.size else np.float32(0.0)
+
+
+def tracking_masks(alpha, depth, tgt_depth, alpha_power: int = 3, inlier_k: float = 50.0):
+    """Per-pixel weight M_in * M_a * [p in Omega] of R24 (float64, constant),
+    the FP32 median depth error and |Omega|.  alpha_power = 0 drops M_a;
+    inlier_k <= 0 drops M_in."""
+    d32 = np.asarray(torch.as_tensor(depth).detach().cpu().numpy(), np.float32)
+    t32 = np.asarray(torch.as_tensor(tgt_depth).detach().cpu().numpy(), np.float32)
+    valid = t32 > 0
+    err = np.abs(d32 - t32)
+    med = lower_median_f32(err[valid])
+    mask = valid.copy()
+    if inlier_k > 0:
+        mask &= err <= np.float32(inlier_k) * med
+    w = torch.as_tensor(mask.astype(np.float64))
+    if alpha_power > 0:
+        w = w * torch.as_tensor(alpha).detach().to(F64) ** alpha_power
+    return w, float(med), int(valid.sum())
+
+
+def loss_tracking(rgb, depth, alpha, tgt_rgb, tgt_depth, lambda_c: float = 0.6, alpha_power: int = 3,
+                  inlier_k: float = 50.0):
+    """Tracking / keyframe-localisation loss of R24 (Eq. 2 with its masks);
+    rgb [3,H,W], depth and alpha [H,W].  Returns (loss, median depth error)."""
+    w, med, n = tracking_masks(alpha, depth, tgt_depth, alpha_power, inlier_k)
+    if n == 0:
+        return (rgb.sum() + depth.sum()) * 0.0, med
+    per_px = lambda_c * torch.abs(rgb - tgt_rgb).sum(0) + (1.0 - lambda_c) * torch.abs(depth - tgt_depth)
+    return (w * per_px).sum() / n, med
 
 
 def to_f64(gauss_np: dict, requires_grad=False) -> dict:

@@ -8,7 +8,8 @@ Readings (the paper leaves these open):
       get their own learning rates (supplement, loop-closure hyper-parameter
       table: 0.003 / 0.001 synthetic-like, 0.015 / 0.005 real-like)
   R19 iteration count: a parameter (200 in the single-pair workload)
-  R20 residual eps_i: the L1 loss at the final pose, from one extra forward
+  R20 residual eps_i: the view's loss (plain L1 of R15, or the tracking loss
+      of R24 when `loss` says so) at the final pose, from one extra forward
   R21 weight 1 / max(eps_i, 1e-12)
   R22 translation: weighted mean of the P->Q translations, the Q->P
       estimates inverted first
@@ -65,12 +66,21 @@ def inv_rigid(t: np.ndarray) -> np.ndarray:
     return out
 
 
+def view_loss(out: dict, tgt_rgb, tgt_depth, loss):
+    """The localisation loss of one render: loss None -> plain L1 (R15);
+    else a dict of loss_tracking's keyword arguments -> R24."""
+    if loss is None:
+        return raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth)
+    return raster.loss_tracking(out["rgb"], out["depth"], out["alpha"], tgt_rgb, tgt_depth, **loss)[0]
+
+
 def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt_depth, iters: int,
-                  lr_rot: float, lr_trans: float, beta1=0.9, beta2=0.999, eps=1e-8):
+                  lr_rot: float, lr_trans: float, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
     """Optimise the camera-frame correction Delta of one keyframe (R18-R20).
 
     gauss: the *other* submap (float64 tensors, held fixed); c2w: the
-    keyframe's camera-to-world pose in its own submap; targets [3,H,W], [H,W].
+    keyframe's camera-to-world pose in its own submap; targets [3,H,W], [H,W];
+    loss: None (plain L1) or loss_tracking's keyword arguments (R24).
     Returns (Delta as a pose 7-vector, residual eps, loss history).
     """
     w2c = torch.as_tensor(inv_rigid(np.asarray(c2w, np.float64))[:3, :])
@@ -84,16 +94,16 @@ def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt
     hist = []
     for it in range(1, iters + 1):
         out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
-        loss = raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth)
-        gq, gt = torch.autograd.grad(loss, [q, t], allow_unused=True)
+        val = view_loss(out, tgt_rgb, tgt_depth, loss)
+        gq, gt = torch.autograd.grad(val, [q, t], allow_unused=True)
         gq = torch.zeros(4, dtype=F64) if gq is None else gq
         gt = torch.zeros(3, dtype=F64) if gt is None else gt
         adam_step(q, gq, mq, vq, it, lr_rot, beta1, beta2, eps)
         adam_step(t, gt, mt, vt, it, lr_trans, beta1, beta2, eps)
-        hist.append(float(loss.detach()))
+        hist.append(float(val.detach()))
     with torch.no_grad():
         out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
-        resid = float(raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth))
+        resid = float(view_loss(out, tgt_rgb, tgt_depth, loss))
     return torch.cat([q, t]).detach().numpy(), resid, hist
 
 
@@ -128,7 +138,7 @@ def fuse(estimates, residuals, reverse) -> np.ndarray:
 
 
 def register_pair(P: dict, Q: dict, views_p, views_q, cam: raster.Camera, iters: int, lr_rot: float,
-                  lr_trans: float):
+                  lr_trans: float, loss=None):
     """Full pair registration: every keyframe of P localised in Q and every
     keyframe of Q in P, then fused (Sec. 3.2).
 
@@ -137,12 +147,12 @@ def register_pair(P: dict, Q: dict, views_p, views_q, cam: raster.Camera, iters:
     """
     ests, res, rev = [], [], []
     for c2w, rgb, dep in views_p:
-        d, r, _ = localise_view(Q, cam, c2w, rgb, dep, iters, lr_rot, lr_trans)
+        d, r, _ = localise_view(Q, cam, c2w, rgb, dep, iters, lr_rot, lr_trans, loss=loss)
         ests.append(view_estimate(c2w, d))
         res.append(r)
         rev.append(False)
     for c2w, rgb, dep in views_q:
-        d, r, _ = localise_view(P, cam, c2w, rgb, dep, iters, lr_rot, lr_trans)
+        d, r, _ = localise_view(P, cam, c2w, rgb, dep, iters, lr_rot, lr_trans, loss=loss)
         ests.append(view_estimate(c2w, d))
         res.append(r)
         rev.append(True)

@@ -291,6 +291,103 @@ def test_loss_matches_library_l1_and_is_zero_at_identity():
     np.testing.assert_allclose(R.loss_l1(pr, pd, tr, td).item(), ref.item(), rtol=1e-14)
 
 
+def _track_case():
+    """1x4 image, hand-checked: target depth (1, 2, 0, 4) -> Omega = {0, 1, 3};
+    depth errors (0.5, 0.25, -, 6.0) (exact in binary); alpha (1, 0.5, 1, 1);
+    colour residual sums (0.6, 3, -, 0.5)."""
+    rgb = torch.zeros(3, 1, 4, dtype=F64)
+    tgt_rgb = torch.tensor([[[0.1, 1.0, 0.7, 0.0]], [[0.2, 1.0, 0.7, 0.0]], [[0.3, 1.0, 0.7, 0.5]]], dtype=F64)
+    depth = torch.tensor([[1.5, 2.25, 7.0, 10.0]], dtype=F64)
+    tgt_depth = torch.tensor([[1.0, 2.0, 0.0, 4.0]], dtype=F64)
+    alpha = torch.tensor([[1.0, 0.5, 1.0, 1.0]], dtype=F64)
+    return rgb, depth, alpha, tgt_rgb, tgt_depth
+
+
+def test_tracking_loss_hand_values():
+    """Eq. 2 with the supplement's masks on a hand-computed case (lambda_c = 0.6):
+    per-pixel terms 0.6 * 0.6 + 0.4 * 0.5 = 0.56, 0.6 * 3 + 0.4 * 0.25 = 1.9
+    (alpha^3 = 1/8 -> 0.2375), 0.6 * 0.5 + 0.4 * 6 = 2.7; median error 0.5."""
+    rgb, depth, alpha, tr, td = _track_case()
+    loss, med = R.loss_tracking(rgb, depth, alpha, tr, td, lambda_c=0.6, alpha_power=3, inlier_k=50.0)
+    assert med == 0.5
+    np.testing.assert_allclose(loss.item(), (0.56 + 0.2375 + 2.7) / 3, rtol=1e-13)
+    # K = 10: threshold 5 drops the pixel with error 6 (|Omega| stays 3)
+    loss, _ = R.loss_tracking(rgb, depth, alpha, tr, td, lambda_c=0.6, alpha_power=3, inlier_k=10.0)
+    np.testing.assert_allclose(loss.item(), (0.56 + 0.2375) / 3, rtol=1e-13)
+    # masks off
+    loss, _ = R.loss_tracking(rgb, depth, alpha, tr, td, lambda_c=0.6, alpha_power=0, inlier_k=0.0)
+    np.testing.assert_allclose(loss.item(), (0.56 + 1.9 + 2.7) / 3, rtol=1e-13)
+    # lambda_c = 1: colour only; 0: depth only
+    loss, _ = R.loss_tracking(rgb, depth, alpha, tr, td, lambda_c=1.0, alpha_power=0, inlier_k=0.0)
+    np.testing.assert_allclose(loss.item(), (0.6 + 3.0 + 0.5) / 3, rtol=1e-13)
+    loss, _ = R.loss_tracking(rgb, depth, alpha, tr, td, lambda_c=0.0, alpha_power=0, inlier_k=0.0)
+    np.testing.assert_allclose(loss.item(), (0.5 + 0.25 + 6.0) / 3, rtol=1e-13)
+    # no valid pixel -> 0
+    loss, _ = R.loss_tracking(rgb, depth, alpha, tr, td * 0.0)
+    assert loss.item() == 0.0
+
+
+def test_lower_median_hand_values():
+    assert R.lower_median_f32(np.array([0.4, 0.1, 0.3, 0.2])) == np.float32(0.2)
+    assert R.lower_median_f32(np.array([5.0, 1.0, 3.0])) == np.float32(3.0)
+    assert R.lower_median_f32(np.array([2.0])) == np.float32(2.0)
+    assert R.lower_median_f32(np.array([])) == np.float32(0.0)
+    assert R.lower_median_f32(np.array([0.0, 0.0, 7.0, 7.0])) == np.float32(0.0)
+
+
+def test_tracking_loss_reduces_to_l1_and_ignores_gross_outliers():
+    """Without masks and with lambda_c = 1/2 the tracking loss is half the
+    plain L1 (itself pinned to torch's l1_loss above); a pixel whose depth
+    error exceeds 50x the median leaves the numerator unchanged."""
+    rng = np.random.default_rng(3)
+    pr = torch.as_tensor(rng.random((3, 24, 32)))
+    pd = torch.as_tensor(rng.random((24, 32)) * 3 + 0.5)
+    tr = torch.as_tensor(rng.random((3, 24, 32)))
+    td = torch.as_tensor(np.where(rng.random((24, 32)) < 0.3, 0.0, pd.numpy() + rng.normal(0, 0.01, (24, 32))))
+    one = torch.ones(24, 32, dtype=F64)
+    lt, _ = R.loss_tracking(pr, pd, one, tr, td, lambda_c=0.5, alpha_power=0, inlier_k=0.0)
+    np.testing.assert_allclose(lt.item(), 0.5 * R.loss_l1(pr, pd, tr, td).item(), rtol=1e-13)
+    base, med = R.loss_tracking(pr, pd, one, tr, td, lambda_c=0.6)
+    n = int((td > 0).sum())
+    j = int(np.argmax(td.numpy().ravel() > 0))
+    pd2 = pd.clone().view(-1)
+    pd2[j] = td.view(-1)[j] + 100.0 * med + 1.0        # a gross depth outlier
+    pd2 = pd2.view(24, 32)
+    out, med2 = R.loss_tracking(pr, pd2, one, tr, td, lambda_c=0.6)
+    y, x = divmod(j, 32)
+    term_j = 0.6 * torch.abs(pr[:, y, x] - tr[:, y, x]).sum() + 0.4 * torch.abs(pd[y, x] - td[y, x])
+    np.testing.assert_allclose(out.item() * n, base.item() * n - term_j.item(), rtol=1e-10)
+
+
+def test_tracking_loss_gradient_matches_central_differences():
+    """Away from the mask thresholds the masks are constant, and the gradient
+    w.r.t. the rendered colour and depth matches central differences."""
+    rng = np.random.default_rng(5)
+    pr = torch.as_tensor(rng.random((3, 6, 8)), dtype=F64).requires_grad_(True)
+    pd = torch.as_tensor(rng.random((6, 8)) + 1.0, dtype=F64).requires_grad_(True)
+    al = torch.as_tensor(rng.random((6, 8)), dtype=F64)
+    tr = torch.as_tensor(rng.random((3, 6, 8)), dtype=F64)
+    td = torch.as_tensor(np.where(rng.random((6, 8)) < 0.2, 0.0, rng.random((6, 8)) + 1.0), dtype=F64)
+    al.requires_grad_(True)
+    loss, _ = R.loss_tracking(pr, pd, al, tr, td, lambda_c=0.6)
+    g_rgb, g_d, g_a = torch.autograd.grad(loss, [pr, pd, al], allow_unused=True)
+    assert g_a is None or torch.all(g_a == 0)     # M_a is a weight: no gradient through alpha
+    al = al.detach()
+    h = 1e-7
+    for (c, y, x) in ((0, 1, 2), (2, 4, 7), (1, 0, 0)):
+        a, b = pr.detach().clone(), pr.detach().clone()
+        a[c, y, x] += h
+        b[c, y, x] -= h
+        fd = (R.loss_tracking(a, pd.detach(), al, tr, td)[0] - R.loss_tracking(b, pd.detach(), al, tr, td)[0]) / (2 * h)
+        np.testing.assert_allclose(g_rgb[c, y, x].item(), fd.item(), rtol=1e-5, atol=1e-9)
+    for (y, x) in ((1, 2), (5, 5), (3, 0)):
+        a, b = pd.detach().clone(), pd.detach().clone()
+        a[y, x] += h
+        b[y, x] -= h
+        fd = (R.loss_tracking(pr.detach(), a, al, tr, td)[0] - R.loss_tracking(pr.detach(), b, al, tr, td)[0]) / (2 * h)
+        np.testing.assert_allclose(g_d[y, x].item(), fd.item(), rtol=1e-5, atol=1e-9)
+
+
 def _fd_scene():
     sc = synth.scene_tiny(21, 8, 32, 32, 50.0, half_extent=0.5, log_scale_mu=math.log(0.08))
     cam = R.Camera(**sc["cam"])

@@ -111,14 +111,17 @@ def test_exact_correction_gives_zero_loss():
     np.testing.assert_allclose(out["depth"].detach().numpy(), dep, atol=2e-5)
 
 
-def test_recovers_known_transform_tiny_scene():
+@pytest.mark.parametrize("loss", [None, dict(lambda_c=0.6, alpha_power=3, inlier_k=50.0)],
+                         ids=["plain_l1", "tracking_eq2"])
+def test_recovers_known_transform_tiny_scene(loss):
     """Both directions localised, 100 Adam steps each, fused: the transform
-    is recovered to < 0.5 deg and < 1 cm."""
+    is recovered to < 0.5 deg and < 1 cm, with the plain L1 and with the
+    masked tracking loss."""
     d = _tiny_pair(4, 2.0, 0.03)
     cam = R.Camera(**d["cam"])
     P, Q = R.to_f64(d["P"]), R.to_f64(d["Q"])
     t_bar, ests, res = G.register_pair(P, Q, _targets(P, cam, d["kf_p"]), _targets(Q, cam, d["kf_q"]), cam, 100,
-                                       0.003, 0.001)
+                                       0.003, 0.001, loss=loss)
     assert G.rotation_error_deg(t_bar, d["T_gt"]) < 0.5
     assert G.translation_error_cm(t_bar[:3, 3], d["T_gt"][:3, 3]) < 1.0
     assert all(r >= 0 for r in res)
