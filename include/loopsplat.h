@@ -272,6 +272,36 @@ ls_status ls_render_stats(const ls_batch* b, const ls_projected* p, const ls_bin
 ls_status ls_loss_l1(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
                      float* loss, float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s);
 
+/* Weights and masks of the tracking loss (Sec. 3.1 Eq. 2 and the
+ * supplement's tracking-loss details). */
+typedef struct {
+  float lambda_c;       /* colour weight in [0, 1]; depth gets 1 - lambda_c */
+  float inlier_k;       /* inlier mask: keep pixels whose depth error is <= inlier_k x the
+                           median depth error of the render (50); <= 0: no inlier mask */
+  int32_t alpha_power;  /* soft alpha mask M_a = alpha^alpha_power (3); 0: no alpha mask */
+  int32_t pad;
+} ls_loss_params;
+
+/* Tracking loss with masks (Sec. 3.1 Eq. 2; supplement, tracking loss): per
+ * render
+ *   L_r = (1/|Omega|) sum_{p in Omega} M_in M_a (lc sum_c |C_c - C*_c| + (1 - lc)|D - D*|)
+ * with Omega = pixels whose target depth is > 0 (pixels without a depth
+ * measurement are excluded), M_a = alpha^k a per-pixel weight through which
+ * no gradient flows, and M_in = [e <= inlier_k * med], e = |D - D*| in FP32,
+ * med = the lower median of e over Omega (rank floor((|Omega|-1)/2)),
+ * selected exactly.  Normalising by |Omega| rather than summing scales every
+ * view's loss by a constant, which leaves Adam's steps unchanged.
+ *   pred      rendered images; pred->alpha is required when alpha_power > 0
+ *   loss      device [R] (written), or NULL
+ *   median    device [R] (written) or NULL (kept inside the batch)
+ *   grad_rgb, grad_depth: device, image layout; receive M_in M_a lc sign(C - C*)
+ *             and M_in M_a (1 - lc) sign(D - D*) (0 outside Omega)
+ *   grad_scale device [R]: receives 1/|Omega| (0 when Omega is empty).
+ * Calls on one batch share its selection workspace: do not overlap them. */
+ls_status ls_loss_tracking(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
+                           const ls_loss_params* prm, float* loss, float* median, float* grad_rgb, float* grad_depth,
+                           float* grad_scale, hipStream_t s);
+
 /* One parameter group of a fused Adam step. */
 typedef struct {
   float* param;
@@ -299,7 +329,9 @@ ls_status ls_fill_i32(int32_t* ptr, int64_t count, int32_t value, hipStream_t s)
  * aligned; T_{P->Q} maps P's frame into Q's.  Every keyframe i of P (pose T_i
  * in P's frame, measurements (I, D)_i) is localised in Q: Q is rendered with
  * world-to-camera Delta_i o T_i^-1 and Delta_i is optimised (Q fixed) for the
- * L1 colour + depth loss, giving E_i = T_i Delta_i^-1 T_i^-1 ~ T_{P->Q}.
+ * colour + depth loss (plain L1, or the tracking loss of Eq. 2 with its masks,
+ * which discount content one submap never observed), giving
+ * E_i = T_i Delta_i^-1 T_i^-1 ~ T_{P->Q}.
  * Keyframes of Q are localised in P the same way (estimates of T_{Q->P}).
  * The 2V estimates are fused by weighted rotation averaging with weights
  * 1/eps_i (Eq. 7) and a weighted mean of the translations.
@@ -323,12 +355,14 @@ typedef struct {
   float beta1, beta2, adam_eps;
   float exit_rel_tol;       /* early exit: a view stops once its loss has not improved on its best */
   int32_t exit_patience;    /* by more than exit_rel_tol (relative) for exit_patience iterations; 0 = off */
+  int32_t loss_kind;        /* 0: plain L1 (ls_loss_l1); 1: tracking loss with masks (ls_loss_tracking) */
+  ls_loss_params track;     /* weights and masks when loss_kind == 1 */
 } ls_reg_params;
 
 typedef struct {
   float T_PQ[12];     /* fused T_{P->Q}, row-major 3x4 */
   float* per_view_T;  /* host [vP + vQ][12] or NULL: E_i (P views: ~T_{P->Q}; Q views: ~T_{Q->P}) */
-  float* residual;    /* host [vP + vQ] or NULL: eps_i, the final L1 loss of each view */
+  float* residual;    /* host [vP + vQ] or NULL: eps_i, the final loss of each view */
   int32_t status;     /* LS_OK, or the error of this pair */
   int32_t iters_done; /* Adam steps of the longest-running view */
 } ls_reg_result;

@@ -134,6 +134,23 @@ ls_status batch_loss_l1(const ls_batch* b, const ls_image* pred, float* loss, fl
                  grad_depth, b->loss_part_d, loss, grad_scale, s);
   return hip_check("loss over per-render targets");
 }
+
+ls_status check_loss_params(const ls_loss_params* prm, const ls_image* pred) {
+  if (!prm) return fail(LS_ERR_INVALID, "NULL ls_loss_params");
+  if (!(prm->lambda_c >= 0.f && prm->lambda_c <= 1.f)) return fail(LS_ERR_INVALID, "lambda_c must lie in [0, 1]");
+  if (!std::isfinite(prm->inlier_k)) return fail(LS_ERR_INVALID, "inlier_k must be finite");
+  if (prm->alpha_power < 0 || prm->alpha_power > 8) return fail(LS_ERR_INVALID, "alpha_power must lie in 0..8");
+  if (prm->alpha_power > 0 && !pred->alpha) return fail(LS_ERR_INVALID, "the alpha mask needs ls_image.alpha");
+  return LS_OK;
+}
+
+ls_status batch_loss_tracking(const ls_batch* b, const ls_image* pred, const ls_loss_params* prm, float* loss,
+                              float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s) {
+  launch_loss_track(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, pred->alpha, nullptr, nullptr,
+                    prm->lambda_c, prm->inlier_k, prm->alpha_power, b->sel_d, b->median_d, grad_rgb, grad_depth,
+                    b->loss_part_d, loss, grad_scale, s);
+  return hip_check("tracking loss over per-render targets");
+}
 }  // namespace ls
 
 extern "C" {
@@ -153,7 +170,7 @@ int64_t ls_struct_size(const char* name) {
       {"ls_gaussian_grads", sizeof(ls_gaussian_grads)}, {"ls_adam_group", sizeof(ls_adam_group)},
       {"ls_pair", sizeof(ls_pair)},                 {"ls_reg_params", sizeof(ls_reg_params)},
       {"ls_reg_result", sizeof(ls_reg_result)},     {"ls_server_params", sizeof(ls_server_params)},
-      {"ls_server_stats", sizeof(ls_server_stats)},
+      {"ls_server_stats", sizeof(ls_server_stats)}, {"ls_loss_params", sizeof(ls_loss_params)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -243,7 +260,11 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
     return st;
   }
   if (hipMalloc(reinterpret_cast<void**>(&b->loss_part_d), 8 * std::max(b->nblk_pix, 1)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&b->grads_d), sizeof(GradDev) * R) != hipSuccess) {
+      hipMalloc(reinterpret_cast<void**>(&b->grads_d), sizeof(GradDev) * R) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&b->sel_d), 4 * ls::sel_words(R)) != hipSuccess ||
+      hipMemset(b->sel_d, 0, 4 * ls::sel_words(R)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&b->median_d), 4 * (size_t)R) != hipSuccess ||
+      hipMemset(b->median_d, 0, 4 * (size_t)R) != hipSuccess) {
     ls_batch_destroy(b);
     return fail(LS_ERR_HIP, "hipMalloc of batch scratch failed");
   }
@@ -259,6 +280,8 @@ ls_status ls_batch_destroy(ls_batch* b) {
   hipFree(b->blk_off_d);
   hipFree(b->pblk_off_d);
   hipFree(b->loss_part_d);
+  hipFree(b->sel_d);
+  hipFree(b->median_d);
   hipFree(b->grads_d);
   delete b;
   return LS_OK;
@@ -422,6 +445,20 @@ ls_status ls_loss_l1(const ls_batch* b, const ls_image* pred, const float* tgt_r
   launch_loss_l1(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, tgt_rgb, tgt_depth, grad_rgb,
                  grad_depth, b->loss_part_d, loss, grad_scale, s);
   return hip_check("ls_loss_l1");
+}
+
+ls_status ls_loss_tracking(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
+                           const ls_loss_params* prm, float* loss, float* median, float* grad_rgb, float* grad_depth,
+                           float* grad_scale, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  if (!pred || !pred->rgb || !pred->depth || !tgt_rgb || !tgt_depth)
+    return fail(LS_ERR_INVALID, "NULL image arguments");
+  ls_status st;
+  if ((st = ls::check_loss_params(prm, pred)) || (st = ensure_device(b))) return st;
+  launch_loss_track(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, pred->alpha, tgt_rgb,
+                    tgt_depth, prm->lambda_c, prm->inlier_k, prm->alpha_power, b->sel_d,
+                    median ? median : b->median_d, grad_rgb, grad_depth, b->loss_part_d, loss, grad_scale, s);
+  return hip_check("ls_loss_tracking");
 }
 
 ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2, float eps,

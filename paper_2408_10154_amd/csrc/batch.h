@@ -26,6 +26,8 @@ struct ls_batch {
   int32_t* blk_off_d = nullptr;
   int32_t* pblk_off_d = nullptr;
   float* loss_part_d = nullptr;
+  uint32_t* sel_d = nullptr;     // median selection workspace (ls::sel_words(R)), kept zeroed
+  float* median_d = nullptr;     // [R] median depth error of the last tracking loss
   GradDev* grads_d = nullptr;
   std::vector<GradDev> grads_cached;
 };
@@ -38,4 +40,6 @@ ls_status batch_set_targets(ls_batch* b, const std::vector<const float*>& rgb, c
 // Loss over per-render targets (see batch_set_targets).
 ls_status batch_loss_l1(const ls_batch* b, const ls_image* pred, float* loss, float* grad_rgb, float* grad_depth,
                         float* grad_scale, hipStream_t s);
+ls_status batch_loss_tracking(const ls_batch* b, const ls_image* pred, const ls_loss_params* prm, float* loss,
+                              float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s);
 }  // namespace ls

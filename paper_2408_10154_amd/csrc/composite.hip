@@ -174,7 +174,7 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
-constexpr int kBwdChunk = 32;   // list entries staged per round
+constexpr int kBwdChunk = 32;   // list entries staged per round (full mode)
 constexpr int kPartRow = kGrad2D;          // floats per row partial
 constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row partials, padded against bank conflicts
 
@@ -183,20 +183,90 @@ constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row part
 // "behind" value acc = sum_{j>i} alpha_j prod_{i<k<j}(1 - alpha_k) v_j +
 // prod_{k>i}(1 - alpha_k)(bg . gC - gA), where v_j = c_j . gC + z_j gD:
 //   dL/dalpha_i = T_i (v_i - acc_i).
-// The ten image-space gradients of each Gaussian are summed over each 16-lane
-// row (DPP) and the 16 row sums of the block over LDS in a fixed order.  Full
-// mode adds the result to the item's accumulator (one atomic per value and
-// tile).  Pose-only mode (registration) instead applies the Gaussian's pose
-// Jacobian right here and writes one 12-value partial per tile: no atomics,
-// so the pose gradient is deterministic and independent of the other renders.
-// kPoseOnly: only the gradients a pose correction depends on (u, v, conic,
-// depth) are reduced; opacity and colour gradients are left out.
-template <bool kPoseOnly>
+// One such step at a pixel: returns false if the entry was not composited
+// there; else undoes its transmittance, updates acc and gives its weight
+// alpha T, ex = exp(-sigma), G = o ex and dG = dL/dG (zero when the 0.99
+// clamp is active).
+__device__ __forceinline__ bool bwd_step(float4 a, float4 b, float4 col, float dx, float dy, float gR, float gG,
+                                         float gB, float gD, float& T, float& acc, float& wgt, float& ex, float& G,
+                                         float& dG) {
+  const float sig = falloff(a.z, a.w, b.x, dx, dy);
+  if (!(sig >= 0.f)) return false;
+  ex = __expf(-sig);
+  G = b.y * ex;
+  const float al = fminf(LS_ALPHA_MAX, G);
+  if (!(al >= LS_ALPHA_MIN)) return false;
+  const float om = 1.f - al;
+  T = T * __builtin_amdgcn_rcpf(om);
+  wgt = al * T;
+  const float v = col.x * gR + col.y * gG + col.z * gB + b.z * gD;
+  const float dal = T * (v - acc);
+  acc = al * v + om * acc;
+  dG = (G < LS_ALPHA_MAX) ? dal : 0.f;
+  return true;
+}
+
+// Per-pixel state shared by both backward kernels: upstream gradients (scaled),
+// final transmittance, entries visited, and the initial "behind" value.
+struct BwdPixel {
+  float T, gR, gG, gB, gD, acc;
+  int nl;
+};
+
+__device__ __forceinline__ BwdPixel bwd_pixel(const TileCtx& c, const JobDev& J, float bg0, float bg1, float bg2,
+                                              const float* fwd_T, const int32_t* fwd_n, const float* up_rgb,
+                                              const float* up_depth, const float* up_alpha, const float* up_scale) {
+  BwdPixel p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
+  if (c.inside) {
+    const int64_t hw = (int64_t)J.W * J.H;
+    const int64_t ci = 3 * J.pix_off + (int64_t)c.y * J.W + c.x;
+    const float sc = up_scale ? up_scale[c.r] : 1.f;
+    if (up_rgb) { p.gR = sc * up_rgb[ci]; p.gG = sc * up_rgb[ci + hw]; p.gB = sc * up_rgb[ci + 2 * hw]; }
+    if (up_depth) p.gD = sc * up_depth[c.pix];
+    const float gA = up_alpha ? sc * up_alpha[c.pix] : 0.f;
+    p.T = fwd_T[c.pix];
+    p.nl = fwd_n[c.pix];
+    p.acc = bg0 * p.gR + bg1 * p.gG + bg2 * p.gB - gA;
+  }
+  return p;
+}
+
+// Wave 0 stages a chunk of the tile's list (records and item ids) and builds,
+// for each of the four wave bands, the list-ordered positions of the entries
+// that can reach it.
+template <int kChunk>
+__device__ __forceinline__ void stage_chunk(int lane, int cnt, int chunk, const int32_t* items, const float4* rec,
+                                            int tx0, int ty0, float4* s0, float4* s1, float4* s2, int32_t* sit,
+                                            uint32_t* smask, uint8_t (*slist)[kChunk], uint32_t* swc) {
+  uint32_t m = 0;
+  const bool valid = lane < cnt;
+  if (valid) {
+    const int64_t it = items[chunk + lane];
+    const float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+    sit[lane] = (int32_t)it;
+    s0[lane] = a;
+    s1[lane] = b;
+    s2[lane] = rec[it * 3 + 2];
+    m = wave_mask(a, b, tx0, ty0);
+    smask[lane] = m;
+  }
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int b2 = 0; b2 < 4; ++b2) {
+    const bool in = valid && ((m >> b2) & 1u);
+    const uint64_t bal = __ballot(in);
+    if (in) slist[b2][__popcll(bal & lt)] = (uint8_t)lane;
+    if (lane == 0) swc[b2] = (uint32_t)__popcll(bal);
+  }
+}
+
+// Full mode: the ten image-space gradients of each Gaussian are summed over
+// each 16-lane row (DPP), the 16 row sums of the block over LDS in a fixed
+// order, and the result is added to the item's accumulator (one atomic per
+// value and tile).
 __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
-                                                          const float4* __restrict__ aux,
-                                                          const float* __restrict__ pose,
                                                           const int32_t* __restrict__ items,
                                                           const int32_t* __restrict__ range, float bg0, float bg1,
                                                           float bg2, const float* __restrict__ fwd_T,
@@ -205,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
                                                           const float* __restrict__ up_depth,
                                                           const float* __restrict__ up_alpha,
                                                           const float* __restrict__ up_scale,
-                                                          float* __restrict__ g2d, float* __restrict__ tile_part) {
+                                                          float* __restrict__ g2d) {
   __shared__ float4 s0[kBwdChunk], s1[kBwdChunk], s2[kBwdChunk];
   __shared__ int32_t sit[kBwdChunk];
   __shared__ uint32_t smask[kBwdChunk];
@@ -223,66 +293,17 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int row = w * 4 + (lane >> 4);  // 0..15, one 16-pixel row of the tile
   const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
-
-  float T = 1.f, gR = 0.f, gG = 0.f, gB = 0.f, gD = 0.f, acc = 0.f;
-  int nl = 0;
-  if (c.inside) {
-    const int64_t hw = (int64_t)J.W * J.H;
-    const int64_t ci = 3 * J.pix_off + (int64_t)c.y * J.W + c.x;
-    const float sc = up_scale ? up_scale[c.r] : 1.f;
-    if (up_rgb) { gR = sc * up_rgb[ci]; gG = sc * up_rgb[ci + hw]; gB = sc * up_rgb[ci + 2 * hw]; }
-    if (up_depth) gD = sc * up_depth[c.pix];
-    const float gA = up_alpha ? sc * up_alpha[c.pix] : 0.f;
-    T = fwd_T[c.pix];
-    nl = fwd_n[c.pix];
-    acc = bg0 * gR + bg1 * gG + bg2 * gB - gA;
-  }
+  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
   if (threadIdx.x == 0) smax = 0;
   __syncthreads();
-  if (nl > 0) atomicMax(&smax, nl);
+  if (px.nl > 0) atomicMax(&smax, px.nl);
   __syncthreads();
   const int last = min(start + smax, end);  // exclusive end of the entries any pixel visited
-  // pose-only: per-tile accumulation of dL/d(R_d, t_d) by the entry-summing threads
-  float pacc[kPoseAcc];
-  float Rd[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, td[3] = {0.f, 0.f, 0.f};
-  if (kPoseOnly) {
-#pragma unroll
-    for (int k = 0; k < kPoseAcc; ++k) pacc[k] = 0.f;
-    if (pose) {
-      const float* pr = pose + 7 * c.r;
-      quat_to_rot(pr[0], pr[1], pr[2], pr[3], Rd);
-      td[0] = pr[4];
-      td[1] = pr[5];
-      td[2] = pr[6];
-    }
-  }
 
   for (int chunk_end = last; chunk_end > start; chunk_end -= kBwdChunk) {
     const int chunk = max(start, chunk_end - kBwdChunk);
     const int cnt = chunk_end - chunk;
-    if (w == 0) {
-      // wave 0 stages the chunk and builds each band's list in list order
-      uint32_t m = 0;
-      const bool valid = lane < cnt;
-      if (valid) {
-        const int64_t it = items[chunk + lane];
-        const float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
-        sit[lane] = (int32_t)it;
-        s0[lane] = a;
-        s1[lane] = b;
-        s2[lane] = rec[it * 3 + 2];
-        m = wave_mask(a, b, tx0, ty0);
-        smask[lane] = m;
-      }
-      const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-#pragma unroll
-      for (int b2 = 0; b2 < 4; ++b2) {
-        const bool in = valid && ((m >> b2) & 1u);
-        const uint64_t bal = __ballot(in);
-        if (in) slist[b2][__popcll(bal & lt)] = (uint8_t)lane;
-        if (lane == 0) swc[b2] = (uint32_t)__popcll(bal);
-      }
-    }
+    if (w == 0) stage_chunk<kBwdChunk>(lane, cnt, chunk, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
     __syncthreads();
     const int cw = (int)swc[w];
     for (int jj = cw - 1; jj >= 0; --jj) {
@@ -294,43 +315,29 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
 #pragma unroll
       for (int q = 0; q < kGrad2D; ++q) g[q] = 0.f;
       bool act = false;
-      if (k < nl) {
+      if (k < px.nl) {
         const float4 a = s0[j];
         const float4 b = s1[j];
         const float dx = fx - a.x, dy = fy - a.y;
-        const float sig = falloff(a.z, a.w, b.x, dx, dy);
-        if (sig >= 0.f) {
-          const float ex = __expf(-sig);
-          const float G = b.y * ex;
-          const float al = fminf(LS_ALPHA_MAX, G);
-          if (al >= LS_ALPHA_MIN) {
-            act = true;
-            const float om = 1.f - al;
-            T = T * __builtin_amdgcn_rcpf(om);
-            const float4 col = s2[j];
-            const float wgt = al * T;
-            const float v = col.x * gR + col.y * gG + col.z * gB + b.z * gD;
-            const float dal = T * (v - acc);
-            acc = al * v + om * acc;
-            g[7] = wgt * gR;
-            g[8] = wgt * gG;
-            g[9] = wgt * gB;
-            g[6] = wgt * gD;
-            const float dG = (G < LS_ALPHA_MAX) ? dal : 0.f;
-            g[5] = dG * ex;                      // dL/d opacity
-            const float ds = -dG * G;            // dL/d sigma
-            g[0] = -ds * (a.z * dx + a.w * dy);  // dL/du
-            g[1] = -ds * (a.w * dx + b.x * dy);  // dL/dv
-            g[2] = 0.5f * ds * dx * dx;          // dL/dA
-            g[3] = ds * dx * dy;                 // dL/dB
-            g[4] = 0.5f * ds * dy * dy;          // dL/dC
-          }
+        float wgt, ex, G, dG;
+        if (bwd_step(a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ex, G, dG)) {
+          act = true;
+          g[7] = wgt * px.gR;
+          g[8] = wgt * px.gG;
+          g[9] = wgt * px.gB;
+          g[6] = wgt * px.gD;
+          g[5] = dG * ex;                      // dL/d opacity
+          const float ds = -dG * G;            // dL/d sigma
+          g[0] = -ds * (a.z * dx + a.w * dy);  // dL/du
+          g[1] = -ds * (a.w * dx + b.x * dy);  // dL/dv
+          g[2] = 0.5f * ds * dx * dx;          // dL/dA
+          g[3] = ds * dx * dy;                 // dL/dB
+          g[4] = 0.5f * ds * dy * dy;          // dL/dC
         }
       }
       if (__ballot(act) != 0ull) {
 #pragma unroll
-        for (int q = 0; q < kGrad2D; ++q)
-          if (!kPoseOnly || q <= 4 || q == 6) g[q] = row_sum16(g[q]);
+        for (int q = 0; q < kGrad2D; ++q) g[q] = row_sum16(g[q]);
         if (lead) {
 #pragma unroll
           for (int q = 0; q < kGrad2D; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(g[q], g[q + 1]);
@@ -342,63 +349,183 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
     }
     __syncthreads();
     {
-      // 4 threads per entry; thread (j, t) sums values t, t + 4, t + 8 over the 16 rows in order
+      // 8 threads per entry; thread (j, t) sums values t, t + 8 over the 16 rows in order;
       // rows of bands that did not visit the entry hold stale values: skip them
-      if (!kPoseOnly) {
-        constexpr int kPer = kBlock / kBwdChunk;  // threads per entry
-        const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
-        const uint32_t mj = j < cnt ? smask[j] : 0u;
-        if (mj != 0u) {
-          float* dst = g2d + (int64_t)sit[j] * kGrad2D;
-          const float* pj = part + j * kPartStride;
-          for (int q = t; q < kGrad2D; q += kPer) {
-            float s = 0.f;
+      constexpr int kPer = kBlock / kBwdChunk;
+      const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
+      const uint32_t mj = j < cnt ? smask[j] : 0u;
+      if (mj != 0u) {
+        float* dst = g2d + (int64_t)sit[j] * kGrad2D;
+        const float* pj = part + j * kPartStride;
+        for (int q = t; q < kGrad2D; q += kPer) {
+          float s = 0.f;
 #pragma unroll
-            for (int r2 = 0; r2 < 16; ++r2)
-              if ((mj >> (r2 >> 2)) & 1u) s += pj[r2 * kPartRow + q];
-            if (s != 0.f) atomic_add_f32(dst + q, s);
-          }
-        }
-      } else if ((int)threadIdx.x < cnt) {
-        // one thread per entry: its image-space sums over the tile, then the
-        // Gaussian's pose Jacobian, accumulated per tile in a fixed order
-        const int j = threadIdx.x;
-        const uint32_t mj = smask[j];
-        if (mj != 0u) {
-          const float* pj = part + j * kPartStride;
-          float g6[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-          for (int r2 = 0; r2 < 16; ++r2) {
-            if (!((mj >> (r2 >> 2)) & 1u)) continue;
-            const float* pr2 = pj + r2 * kPartRow;
-            g6[0] += pr2[0];
-            g6[1] += pr2[1];
-            g6[2] += pr2[2];
-            g6[3] += pr2[3];
-            g6[4] += pr2[4];
-            g6[5] += pr2[6];
-          }
-          const int64_t it = sit[j];
-          const float4 a0 = aux[it * 3 + 0], a1 = aux[it * 3 + 1], a2 = aux[it * 3 + 2];
-          const float p[3] = {a0.x, a0.y, a0.z};
-          const float s6[6] = {a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
-          float Sc[9], dp[3], G[9];
-          sym3(s6, Sc);
-          camera_space_grads(p, Sc, J.fx, J.fy, g6, dp, G);
-          pose_contrib(p, Sc, Rd, td, dp, G, pacc);
+          for (int r2 = 0; r2 < 16; ++r2)
+            if ((mj >> (r2 >> 2)) & 1u) s += pj[r2 * kPartRow + q];
+          if (s != 0.f) atomic_add_f32(dst + q, s);
         }
       }
     }
     __syncthreads();
   }
-  if (kPoseOnly && w == 0) {
-    // entry threads are all in wave 0: its fixed-order sum is the tile's partial
+}
+
+// Pose-only mode (registration): only the gradients a pose correction acts
+// through (u, v, conic, depth) are formed.  Each entry's sums over the tile
+// are parked in an LDS queue; whenever it is full (and at the end) every
+// thread of the block applies the pose Jacobian of one queued Gaussian, so
+// the Jacobian work is spread over all four waves.  Each
+// round's results are reduced over the block in a fixed order and added to the
+// tile's running sum, written once as the tile's 12-value partial: no atomics,
+// so the pose gradient is deterministic and independent of the other renders.
+constexpr int kPoseChunk = 64;                    // entries staged per round
+constexpr int kPoseRow = 6;                       // du, dv, dA, dB, dC, d(depth weight)
+constexpr int kPoseStride = 16 * kPoseRow + 4;    // floats per entry, padded against bank conflicts
+constexpr int kPoseQueue = kBlock;                // queued entries per Jacobian round
+
+__global__ __launch_bounds__(kBlock) void k_composite_bwd_pose(const JobDev* __restrict__ jobs,
+                                                               const int32_t* __restrict__ tile_off, int R,
+                                                               int T_total, const float4* __restrict__ rec,
+                                                               const float4* __restrict__ aux,
+                                                               const float* __restrict__ pose,
+                                                               const int32_t* __restrict__ items,
+                                                               const int32_t* __restrict__ range, float bg0,
+                                                               float bg1, float bg2, const float* __restrict__ fwd_T,
+                                                               const int32_t* __restrict__ fwd_n,
+                                                               const float* __restrict__ up_rgb,
+                                                               const float* __restrict__ up_depth,
+                                                               const float* __restrict__ up_alpha,
+                                                               const float* __restrict__ up_scale,
+                                                               float* __restrict__ tile_part) {
+  __shared__ float4 s0[kPoseChunk], s1[kPoseChunk], s2[kPoseChunk];
+  __shared__ int32_t sit[kPoseChunk];
+  __shared__ uint32_t smask[kPoseChunk];
+  __shared__ uint8_t slist[4][kPoseChunk];
+  __shared__ uint32_t swc[4];
+  __shared__ __attribute__((aligned(16))) float part[kPoseChunk * kPoseStride];
+  __shared__ float qsum[kPoseRow * kPoseQueue];  // [value][slot]
+  __shared__ int32_t qit[kPoseQueue];
+  __shared__ float wred[4][kPoseAcc];
+  __shared__ int smax;
+  static_assert(kPoseChunk <= 64 && kPoseQueue % kPoseChunk == 0, "chunk must fit one staging wave");
+  const int tile = xcd_remap(blockIdx.x, T_total);
+  if (tile >= T_total) return;
+  const TileCtx c = tile_ctx(jobs, tile_off, R, tile);
+  const JobDev& J = jobs[c.r];
+  const int start = range[2 * tile], end = range[2 * tile + 1];
+  const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int row = w * 4 + (lane >> 4);
+  const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
+  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
+  if (threadIdx.x == 0) smax = 0;
+  __syncthreads();
+  if (px.nl > 0) atomicMax(&smax, px.nl);
+  __syncthreads();
+  const int last = min(start + smax, end);
+
+  float total = 0.f;  // threads 0..11: the tile's running pose-gradient sum
+  int nq = 0;  // queued entries (uniform)
+  for (int chunk_end = last; chunk_end > start; chunk_end -= kPoseChunk) {
+    const int chunk = max(start, chunk_end - kPoseChunk);
+    const int cnt = chunk_end - chunk;
+    if (w == 0) stage_chunk<kPoseChunk>(lane, cnt, chunk, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
+    __syncthreads();
+    const int cw = (int)swc[w];
+    for (int jj = cw - 1; jj >= 0; --jj) {
+      const int j = slist[w][jj];
+      float* pj = part + j * kPoseStride + row * kPoseRow;
+      const bool lead = (lane & 15) == 0;
+      const int k = chunk + j - start;
+      float g[kPoseRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      bool act = false;
+      if (k < px.nl) {
+        const float4 a = s0[j];
+        const float4 b = s1[j];
+        const float dx = fx - a.x, dy = fy - a.y;
+        float wgt, ex, G, dG;
+        if (bwd_step(a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ex, G, dG)) {
+          act = true;
+          const float ds = -dG * G;
+          g[0] = -ds * (a.z * dx + a.w * dy);
+          g[1] = -ds * (a.w * dx + b.x * dy);
+          g[2] = 0.5f * ds * dx * dx;
+          g[3] = ds * dx * dy;
+          g[4] = 0.5f * ds * dy * dy;
+          g[5] = wgt * px.gD;
+        }
+      }
+      if (__ballot(act) != 0ull) {
 #pragma unroll
-    for (int k = 0; k < kPoseAcc; ++k) {
-      const float v = wave_sum(pacc[k]);
-      if (lane == 0) tile_part[(int64_t)tile * kPoseAcc + k] = v;
+        for (int q = 0; q < kPoseRow; ++q) g[q] = row_sum16(g[q]);
+      }
+      if (lead) {
+#pragma unroll
+        for (int q = 0; q < kPoseRow; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(g[q], g[q + 1]);
+      }
     }
+    __syncthreads();
+    if ((int)threadIdx.x < cnt) {
+      // entry j: its sums over the rows of the bands it reaches, into queue slot nq + j
+      const int j = threadIdx.x;
+      const uint32_t mj = smask[j];
+      const float* pj = part + j * kPoseStride;
+      float g6[kPoseRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (mj != 0u) {
+#pragma unroll
+        for (int r2 = 0; r2 < 16; ++r2) {
+          if (!((mj >> (r2 >> 2)) & 1u)) continue;
+          const float* pr2 = pj + r2 * kPoseRow;
+#pragma unroll
+          for (int q = 0; q < kPoseRow; ++q) g6[q] += pr2[q];
+        }
+      }
+      const int slot = nq + j;
+      qit[slot] = mj != 0u ? sit[j] : -1;
+#pragma unroll
+      for (int q = 0; q < kPoseRow; ++q) qsum[q * kPoseQueue + slot] = g6[q];
+    }
+    nq += cnt;
+    if (nq + kPoseChunk > kPoseQueue || chunk == start) {
+      __syncthreads();
+      const int t = threadIdx.x;
+      float pc[kPoseAcc];
+#pragma unroll
+      for (int k = 0; k < kPoseAcc; ++k) pc[k] = 0.f;
+      if (t < nq && qit[t] >= 0) {
+        const int64_t it = qit[t];
+        float g6[kPoseRow];
+#pragma unroll
+        for (int q = 0; q < kPoseRow; ++q) g6[q] = qsum[q * kPoseQueue + t];
+        float Rd[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f}, td[3] = {0.f, 0.f, 0.f};
+        if (pose) {
+          const float* pr = pose + 7 * c.r;
+          quat_to_rot(pr[0], pr[1], pr[2], pr[3], Rd);
+          td[0] = pr[4];
+          td[1] = pr[5];
+          td[2] = pr[6];
+        }
+        const float4 a0 = aux[it * 3 + 0], a1 = aux[it * 3 + 1], a2 = aux[it * 3 + 2];
+        const float p[3] = {a0.x, a0.y, a0.z};
+        const float s6[6] = {a0.w, a1.x, a1.y, a1.z, a1.w, a2.x};
+        float Sc[9], dp[3], Gm[9];
+        sym3(s6, Sc);
+        camera_space_grads(p, Sc, J.fx, J.fy, g6, dp, Gm);
+        pose_contrib(p, Sc, Rd, td, dp, Gm, pc);
+      }
+      // fixed-order reduction of this round over the block
+#pragma unroll
+      for (int k = 0; k < kPoseAcc; ++k) {
+        const float v = wave_sum(pc[k]);
+        if (lane == 0) wred[w][k] = v;
+      }
+      __syncthreads();
+      if (t < kPoseAcc) total += (wred[0][t] + wred[1][t]) + (wred[2][t] + wred[3][t]);
+      nq = 0;
+    }
+    __syncthreads();
   }
+  if ((int)threadIdx.x < kPoseAcc) tile_part[(int64_t)tile * kPoseAcc + threadIdx.x] = total;
 }
 
 // Work statistics of a forward pass: entries evaluated and composited.
@@ -482,12 +609,11 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const float4* aux4 = reinterpret_cast<const float4*>(aux);
   if (pose_only)
-    hipLaunchKernelGGL(k_composite_bwd<true>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, aux4,
-                       pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d,
+    hipLaunchKernelGGL(k_composite_bwd_pose, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, aux4,
+                       pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
                        tile_part);
   else
-    hipLaunchKernelGGL(k_composite_bwd<false>, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4,
-                       aux4, pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
-                       g2d, tile_part);
+    hipLaunchKernelGGL(k_composite_bwd, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, items,
+                       range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d);
 }
 }  // namespace ls

@@ -56,6 +56,13 @@ void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int
 void launch_loss_l1(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
                     const float* pred_depth, const float* tgt_rgb, const float* tgt_depth, float* g_rgb,
                     float* g_depth, float* part, float* loss, float* scale, hipStream_t s);
+// Tracking loss with masks; sel = per-render selection workspace
+// (kSelWords(R) uint32, zero on first use, left zeroed after each call).
+void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
+                       const float* pred_depth, const float* pred_alpha, const float* tgt_rgb, const float* tgt_depth,
+                       float lambda_c, float inlier_k, int alpha_power, uint32_t* sel, float* median, float* g_rgb,
+                       float* g_depth, float* part, float* loss, float* scale, hipStream_t s);
+inline int64_t sel_words(int R) { return (int64_t)R * (4 + 2048); }
 
 void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,
                  int zero_grad, hipStream_t s);

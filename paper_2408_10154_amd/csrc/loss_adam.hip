@@ -69,6 +69,177 @@ __global__ void k_loss_reduce(const int32_t* __restrict__ pblk_off, int R, const
   }
 }
 
+// ---------------------------------------------------------------------------
+// Tracking loss with masks (Eq. 2 and the supplement's tracking-loss
+// details).  The inlier mask needs, per render, the median of the depth
+// error e = |D - D*| over pixels with D* > 0.  It is found exactly by radix
+// selection on the bit patterns of the non-negative FP32 errors (their
+// unsigned order is their numeric order): three passes over 11, 11 and 10
+// bits, each a histogram of the errors that match the digits fixed so far,
+// followed by a one-block-per-render pass that picks the digit holding the
+// element of rank floor((n-1)/2) and re-zeroes the histogram for the next
+// pass (no memset, so the sequence can be captured in a graph).
+
+constexpr int kSelBins = 2048;
+
+struct SelState {
+  uint32_t prefix, mask, k, n;
+};
+
+__device__ __forceinline__ int sel_shift(int pass) { return pass == 0 ? 21 : (pass == 1 ? 10 : 0); }
+__device__ __forceinline__ int sel_bins(int pass) { return pass == 2 ? 1024 : 2048; }
+
+__device__ __forceinline__ float depth_error(float d, float t) { return fabsf(d - t); }
+
+__global__ __launch_bounds__(256) void k_err_hist(const JobDev* __restrict__ jobs, const int32_t* __restrict__ pblk_off,
+                                                  int R, const float* __restrict__ pred_depth,
+                                                  const float* __restrict__ tgt_depth,
+                                                  const SelState* __restrict__ state, uint32_t* __restrict__ hist,
+                                                  int pass) {
+  __shared__ uint32_t h[kSelBins];
+  const int r = find_segment<int32_t>(pblk_off, R, (int32_t)blockIdx.x);
+  const JobDev& J = jobs[r];
+  const int64_t hw = (int64_t)J.W * J.H;
+  const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * kLossBlockPix;
+  const int shift = sel_shift(pass), nb = sel_bins(pass);
+  const uint32_t prefix = pass ? state[r].prefix : 0u, mask = pass ? state[r].mask : 0u;
+  for (int i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
+  __syncthreads();
+  for (int k = 0; k < kLossPix; ++k) {
+    const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
+    if (p >= hw) break;
+    const float td = tgt_depth ? tgt_depth[J.pix_off + p] : J.tgt_depth[p];
+    if (!(td > 0.f)) continue;
+    const uint32_t bits = __float_as_uint(depth_error(pred_depth[J.pix_off + p], td));
+    if ((bits & mask) == prefix) atomicAdd(&h[(bits >> shift) & (uint32_t)(nb - 1)], 1u);
+  }
+  __syncthreads();
+  uint32_t* __restrict__ g = hist + (int64_t)r * kSelBins;
+  for (int i = threadIdx.x; i < nb; i += 256)
+    if (h[i]) atomicAdd(&g[i], h[i]);
+}
+
+// One block per render: locate the digit of the rank-k element, fold it
+// into the prefix, clear the histogram; after the last pass write the median.
+__global__ __launch_bounds__(256) void k_err_select(int R, SelState* __restrict__ state, uint32_t* __restrict__ hist,
+                                                    float* __restrict__ median, int pass) {
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  const int shift = sel_shift(pass), nb = sel_bins(pass);
+  const int per = nb / 256;  // 8 or 4 bins per thread
+  uint32_t* __restrict__ g = hist + (int64_t)r * kSelBins;
+  uint32_t c[8];
+  uint32_t mine = 0;
+  for (int j = 0; j < per; ++j) {
+    c[j] = g[threadIdx.x * per + j];
+    mine += c[j];
+  }
+  // block-wide exclusive scan of the per-thread sums
+  __shared__ uint32_t wsum[4];
+  __shared__ uint32_t total_s;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  uint32_t incl = mine;
+  for (int o = 1; o < 64; o <<= 1) {
+    const uint32_t y = __shfl_up(incl, o, 64);
+    if (lane >= o) incl += y;
+  }
+  if (lane == 63) wsum[wv] = incl;
+  __syncthreads();
+  uint32_t before = incl - mine;
+  for (int w = 0; w < wv; ++w) before += wsum[w];
+  if (threadIdx.x == 0) total_s = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  __syncthreads();
+  SelState st = state[r];
+  if (pass == 0) {
+    st.prefix = 0u;
+    st.mask = 0u;
+    st.n = total_s;
+    st.k = total_s ? (total_s - 1u) / 2u : 0u;
+  }
+  __syncthreads();
+  if (st.n && st.k >= before && st.k < before + mine) {
+    uint32_t cum = before;
+    for (int j = 0; j < per; ++j) {
+      if (st.k < cum + c[j]) {
+        const uint32_t digit = (uint32_t)(threadIdx.x * per + j);
+        SelState o = st;
+        o.prefix |= digit << shift;
+        o.mask |= (uint32_t)(nb - 1) << shift;
+        o.k -= cum;
+        state[r] = o;
+        if (pass == 2) median[r] = __uint_as_float(o.prefix);
+        break;
+      }
+      cum += c[j];
+    }
+  }
+  if (!st.n && threadIdx.x == 0) {
+    state[r] = st;
+    if (pass == 2) median[r] = 0.f;
+  }
+  for (int j = 0; j < per; ++j) g[threadIdx.x * per + j] = 0u;
+}
+
+// Per block of 1024 pixels: the masked, weighted L1 of Eq. 2 with its
+// gradient w.r.t. the rendered colour and depth (the alpha weight is a
+// constant), and the block's (sum, valid count) partials.
+__global__ __launch_bounds__(256) void k_loss_track(const JobDev* __restrict__ jobs,
+                                                    const int32_t* __restrict__ pblk_off, int R,
+                                                    const float* __restrict__ pred_rgb,
+                                                    const float* __restrict__ pred_depth,
+                                                    const float* __restrict__ pred_alpha,
+                                                    const float* __restrict__ tgt_rgb,
+                                                    const float* __restrict__ tgt_depth,
+                                                    const float* __restrict__ median, float lambda_c, float inlier_k,
+                                                    int alpha_power, float* __restrict__ g_rgb,
+                                                    float* __restrict__ g_depth, float* __restrict__ part) {
+  const int r = find_segment<int32_t>(pblk_off, R, (int32_t)blockIdx.x);
+  const JobDev& J = jobs[r];
+  const int64_t hw = (int64_t)J.W * J.H;
+  const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * kLossBlockPix;
+  const float thr = inlier_k > 0.f ? inlier_k * median[r] : 0.f;
+  float s = 0.f, cnt = 0.f;
+  for (int k = 0; k < kLossPix; ++k) {
+    const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
+    if (p >= hw) break;
+    const int64_t pi = J.pix_off + p;
+    const int64_t ci = 3 * J.pix_off + p;
+    const float* trgb = tgt_rgb ? tgt_rgb + ci : J.tgt_rgb + p;
+    const float td = tgt_depth ? tgt_depth[pi] : J.tgt_depth[p];
+    const bool valid = td > 0.f;
+    const float dd = pred_depth[pi] - td;
+    float w = 0.f;
+    if (valid && (inlier_k <= 0.f || depth_error(pred_depth[pi], td) <= thr)) {
+      w = 1.f;
+      if (alpha_power > 0) {
+        const float a = pred_alpha[pi];
+        for (int e = 0; e < alpha_power; ++e) w *= a;
+      }
+    }
+    const float wc = w * lambda_c, wd = w * (1.f - lambda_c);
+    float lc = 0.f;
+    for (int ch = 0; ch < 3; ++ch) {
+      const float dc = pred_rgb[ci + ch * hw] - trgb[ch * hw];
+      lc += fabsf(dc);
+      if (g_rgb) g_rgb[ci + ch * hw] = dc > 0.f ? wc : (dc < 0.f ? -wc : 0.f);
+    }
+    if (g_depth) g_depth[pi] = dd > 0.f ? wd : (dd < 0.f ? -wd : 0.f);
+    if (valid) {
+      s += wc * lc + wd * fabsf(dd);
+      cnt += 1.f;
+    }
+  }
+  s = wave_sum(s);
+  cnt = wave_sum(cnt);
+  __shared__ float ws[4][2];
+  if ((threadIdx.x & 63) == 0) { ws[threadIdx.x >> 6][0] = s; ws[threadIdx.x >> 6][1] = cnt; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int q = threadIdx.x;
+    part[2 * (int64_t)blockIdx.x + q] = (ws[0][q] + ws[1][q]) + (ws[2][q] + ws[3][q]);
+  }
+}
+
 struct AdamArgs {
   float* param[16];
   float* grad[16];
@@ -107,6 +278,27 @@ void launch_loss_l1(const JobDev* jobs, const int32_t* pblk_off_d, int R, int np
   if (npblk > 0)
     hipLaunchKernelGGL(k_loss_l1, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, pred_rgb, pred_depth, tgt_rgb,
                        tgt_depth, g_rgb, g_depth, part);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale);
+}
+
+void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
+                       const float* pred_depth, const float* pred_alpha, const float* tgt_rgb, const float* tgt_depth,
+                       float lambda_c, float inlier_k, int alpha_power, uint32_t* sel, float* median, float* g_rgb,
+                       float* g_depth, float* part, float* loss, float* scale, hipStream_t s) {
+  SelState* st = reinterpret_cast<SelState*>(sel);
+  uint32_t* hist = sel + 4 * (int64_t)R;
+  if (inlier_k > 0.f) {
+    for (int pass = 0; pass < 3; ++pass) {
+      if (npblk > 0)
+        hipLaunchKernelGGL(k_err_hist, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, pred_depth, tgt_depth,
+                           (const SelState*)st, hist, pass);
+      hipLaunchKernelGGL(k_err_select, dim3(R), dim3(256), 0, s, R, st, hist, median, pass);
+    }
+  }
+  if (npblk > 0)
+    hipLaunchKernelGGL(k_loss_track, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, pred_rgb, pred_depth,
+                       pred_alpha, tgt_rgb, tgt_depth, (const float*)median, lambda_c, inlier_k, alpha_power, g_rgb,
+                       g_depth, part);
   hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale);
 }
 

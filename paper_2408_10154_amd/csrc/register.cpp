@@ -285,8 +285,7 @@ ls_status RegEngine::step(hipStream_t s) {
   const ls_image_grad up{g_rgb, g_depth, nullptr, scale};
   if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
-  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
-      (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)) ||
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) || (st = view_loss(s)) ||
       (st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
       (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
     return st;
@@ -300,10 +299,15 @@ ls_status RegEngine::final_forward(hipStream_t s) {
   ls_status st;
   if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
-  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
-      (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)))
-    return st;
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) || (st = view_loss(s))) return st;
   return hip_ok();
+}
+
+ls_status RegEngine::view_loss(hipStream_t s) {
+  const ls_reg_params& pm = pairs[0].prm;
+  if (pm.loss_kind == 1)
+    return ls_loss_tracking(batch, &img, tgt_rgb, tgt_depth, &pm.track, loss, nullptr, g_rgb, g_depth, scale, s);
+  return ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s);
 }
 
 ls_status RegEngine::readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow,
@@ -356,7 +360,11 @@ ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
   if (p->vQ > 0 && (!p->rgbQ || !p->depthQ || !p->c2wQ || p->P.n < 0)) return LS_ERR_INVALID;
   if (prm->iters < 1 || !(prm->lr_rot >= 0) || !(prm->lr_trans >= 0) || !(prm->beta1 >= 0 && prm->beta1 < 1) ||
       !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0) || !(prm->exit_rel_tol >= 0) ||
-      prm->exit_patience < 0)
+      prm->exit_patience < 0 || prm->loss_kind < 0 || prm->loss_kind > 1)
+    return LS_ERR_INVALID;
+  if (prm->loss_kind == 1 && (!(prm->track.lambda_c >= 0.f && prm->track.lambda_c <= 1.f) ||
+                              !std::isfinite(prm->track.inlier_k) || prm->track.alpha_power < 0 ||
+                              prm->track.alpha_power > 8))
     return LS_ERR_INVALID;
   for (int i = 0; i < 12 * p->vP; ++i)
     if (!std::isfinite(p->c2wP[i])) return LS_ERR_NONFINITE;

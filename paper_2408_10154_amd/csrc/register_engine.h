@@ -30,6 +30,7 @@ class RegEngine {
   ls_status alloc_bins(int64_t cap);
   ls_status step(hipStream_t s);
   ls_status final_forward(hipStream_t s);
+  ls_status view_loss(hipStream_t s);  // the loss the pair's parameters select
   ls_status readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow, hipStream_t s);
   ls_status fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h, ls_reg_result* out);
   void release();

@@ -138,9 +138,15 @@ class Server {
         eps_ = prm->adam_eps;
         exit_tol_ = prm->exit_rel_tol;
         exit_patience_ = prm->exit_patience;
+        loss_kind_ = prm->loss_kind;
+        track_ = prm->track;
         have_betas_ = true;
       } else if (prm->beta1 != beta1_ || prm->beta2 != beta2_ || prm->adam_eps != eps_ ||
-                 prm->exit_rel_tol != exit_tol_ || prm->exit_patience != exit_patience_) {
+                 prm->exit_rel_tol != exit_tol_ || prm->exit_patience != exit_patience_ ||
+                 prm->loss_kind != loss_kind_ ||
+                 (loss_kind_ == 1 && (prm->track.lambda_c != track_.lambda_c ||
+                                      prm->track.inlier_k != track_.inlier_k ||
+                                      prm->track.alpha_power != track_.alpha_power))) {
         return LS_ERR_INVALID;
       }
     }
@@ -402,6 +408,13 @@ class Server {
     return LS_OK;
   }
 
+  // The loss fixed for this server (plain L1 or the masked tracking loss).
+  ls_status view_loss(const StatePtrs& s) {
+    if (loss_kind_ == 1)
+      return batch_loss_tracking(batch_, &img_, &track_, s.loss, g_rgb_, g_depth_, s.scale, stream_);
+    return batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_);
+  }
+
   // One batched iteration (also the body of the captured graph).
   ls_status iteration() {
     const StatePtrs s = state_ptrs(stateA_, R_);
@@ -411,7 +424,7 @@ class Server {
       return st;
     launch_or_flag(count_, sticky_, stream_);
     if ((st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_)) ||
-        (st = batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_)) ||
+        (st = view_loss(s)) ||
         (st = ls_render_bwd_tiles(batch_, s.pose, &proj_, &bins_c_, nullptr, &img_, &up, LS_BWD_POSE_ONLY, stream_)) ||
         (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
       return st;
@@ -510,7 +523,7 @@ class Server {
     ls_status st;
     if ((st = ls_project(batch_, s.pose, &proj_, stream_)) || (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)) ||
         (st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_)) ||
-        (st = batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_))) {
+        (st = view_loss(s))) {
       fail_active(st);
       return;
     }
@@ -603,6 +616,8 @@ class Server {
   bool have_betas_ = false;
   float beta1_ = 0.9f, beta2_ = 0.999f, eps_ = 1e-8f, exit_tol_ = 0.f;
   int32_t exit_patience_ = 0;
+  int32_t loss_kind_ = 0;
+  ls_loss_params track_{};
   std::thread worker_;
   std::mutex mu_;
   std::condition_variable cv_;

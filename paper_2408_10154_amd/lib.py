@@ -80,10 +80,14 @@ class ls_pair(C.Structure):
                 ("rgbQ", C.c_void_p), ("depthQ", C.c_void_p), ("c2wQ", C.c_void_p), ("K", ls_intrinsics)]
 
 
+class ls_loss_params(C.Structure):
+    _fields_ = [("lambda_c", C.c_float), ("inlier_k", C.c_float), ("alpha_power", C.c_int32), ("pad", C.c_int32)]
+
+
 class ls_reg_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lr_rot", C.c_float), ("lr_trans", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("exit_rel_tol", C.c_float),
-                ("exit_patience", C.c_int32)]
+                ("exit_patience", C.c_int32), ("loss_kind", C.c_int32), ("track", ls_loss_params)]
 
 
 class ls_reg_result(C.Structure):
@@ -127,6 +131,8 @@ _PROTOS = {
                                           _P]),
     "ls_render_stats": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), C.POINTER(ls_image), _P, _P]),
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
+    "ls_loss_tracking": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, C.POINTER(ls_loss_params), _P, _P, _P, _P, _P,
+                                     _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
@@ -226,6 +232,11 @@ def ls_render_stats(h, proj, bins, fwd, stats, stream):
 
 def ls_loss_l1(h, pred, tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_scale, stream):
     return _call("ls_loss_l1", h, C.byref(pred), tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_scale, stream)
+
+
+def ls_loss_tracking(h, pred, tgt_rgb, tgt_depth, prm, loss, median, grad_rgb, grad_depth, grad_scale, stream):
+    return _call("ls_loss_tracking", h, C.byref(pred), tgt_rgb, tgt_depth, C.byref(prm), loss, median, grad_rgb,
+                 grad_depth, grad_scale, stream)
 
 
 def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):

@@ -16,6 +16,8 @@ from .render import GaussianSet
 
 
 def build_pair(spec: dict, width=640, height=480, f=500.0):
+    """Device-resident pair (Gaussians and keyframe targets) for a spec of
+    synth.pair_set / synth.request_stream, built by synth.registration_pair."""
     d = synth.registration_pair(spec["seed"], spec["n_p"], spec["n_q"], views_p=spec["views_p"],
                                 views_q=spec["views_q"], width=spec.get("width", width),
                                 height=spec.get("height", height), f=spec.get("f", f))
@@ -23,7 +25,8 @@ def build_pair(spec: dict, width=640, height=480, f=500.0):
     rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
     rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
     return dict(T_gt=d["T_gt"], args=(P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ),
-                pixels=(spec["views_p"] + spec["views_q"]) * d["cam"]["width"] * d["cam"]["height"])
+                pixels=(spec["views_p"] + spec["views_q"]) * d["cam"]["width"] * d["cam"]["height"],
+                n_p=d["P"]["mean"].shape[1], n_q=d["Q"]["mean"].shape[1], shared=d["shared"])
 
 
 def _errors(results, pairs):
@@ -38,28 +41,28 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, np.float64), q))
 
 
-def run_plain(pairs, iters=200):
+def run_plain(pairs, iters=200, loss="tracking"):
     """One pair at a time through ls_register_pair; latency of pair k counts
     from the start of the run (all requests present at t = 0)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results, done = [], []
     for p in pairs:
-        results.append(REG.register_pair(*p["args"], params=REG.default_params(iters)))
+        results.append(REG.register_pair(*p["args"], params=REG.default_params(iters, loss=loss)))
         done.append(time.perf_counter() - t0)
     total = time.perf_counter() - t0
     return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(done, 50), p99_s=_pct(done, 99),
                 **_errors(results, pairs)), results
 
 
-def run_batched(pairs, iters=200, chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30):
+def run_batched(pairs, iters=200, loss="tracking", chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30):
     """Every pair submitted at t = 0 to one server."""
     from .serve import Server
 
     with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters, use_graphs=use_graphs) as sv:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tickets = [sv.submit(*p["args"], params=REG.default_params(iters)) for p in pairs]
+        tickets = [sv.submit(*p["args"], params=REG.default_params(iters, loss=loss)) for p in pairs]
         results = [sv.wait(t) for t in tickets]
         total = time.perf_counter() - t0
         st = sv.stats()
@@ -68,7 +71,7 @@ def run_batched(pairs, iters=200, chunk_iters=16, use_graphs=True, max_slots=64,
                 epochs=st["epochs"], graph_replays=st["graph_replays"], **_errors(results, pairs)), results
 
 
-def run_stream(stream, built, iters=200, chunk_iters=16, budget=200 << 30, max_slots=64):
+def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget=200 << 30, max_slots=64):
     """Requests submitted at their arrival times (a host thread paces them)."""
     from .serve import Server
 
@@ -80,10 +83,46 @@ def run_stream(stream, built, iters=200, chunk_iters=16, budget=200 << 30, max_s
             delay = spec["arrival"] - (time.perf_counter() - t0)
             if delay > 0:
                 time.sleep(delay)
-            tickets.append(sv.submit(*p["args"], params=REG.default_params(iters)))
+            tickets.append(sv.submit(*p["args"], params=REG.default_params(iters, loss=loss)))
         results = [sv.wait(t) for t in tickets]
         total = time.perf_counter() - t0
         st = sv.stats()
     lat = [r["times"]["total"] for r in results]
     return dict(seconds=total, pairs_per_s=len(built) / total, p50_s=_pct(lat, 50), p99_s=_pct(lat, 99),
                 max_active_bytes=st["peak_bytes"], **_errors(results, built)), results
+
+
+def single_pair_spec(seed=2):
+    """The single-pair workload: 150k + 120k Gaussians (60 % shared), 8 + 8
+    keyframes at 640x480, f = 500."""
+    return dict(seed=seed, n_p=150_000, n_q=120_000, views_p=8, views_q=8)
+
+
+def main(argv=None):
+    """Command-line runs of the registration workloads (one JSON line each),
+    e.g. under a kernel-trace profiler:
+      python -m paper_2408_10154_amd.regbench --workload single --iters 50
+      python -m paper_2408_10154_amd.regbench --workload set --pairs 8 --mode both"""
+    import argparse
+    import json
+
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", choices=["single", "set"], default="single")
+    ap.add_argument("--pairs", type=int, default=8, help="pairs of the pair set (seed 3)")
+    ap.add_argument("--iters", type=int, default=200)
+    ap.add_argument("--mode", choices=["plain", "batched", "both"], default="plain")
+    ap.add_argument("--loss", choices=["tracking", "l1"], default="tracking")
+    a = ap.parse_args(argv)
+    torch.cuda.set_device(0)
+    specs = [single_pair_spec()] if a.workload == "single" else synth.pair_set(3, a.pairs)
+    pairs = [build_pair(sp) for sp in specs]
+    print(json.dumps(dict(event="built", pairs=len(pairs))), flush=True)
+    for mode in (["plain", "batched"] if a.mode == "both" else [a.mode]):
+        run = run_plain if mode == "plain" else run_batched
+        res, _ = run(pairs, iters=a.iters, loss=a.loss)
+        print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters,
+                              **{k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()})), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -233,6 +233,31 @@ class RenderBatch:
                      _ptr(grad_scale), _stream())
         return loss, grad_rgb, grad_depth, grad_scale
 
+    def loss_tracking(self, tgt_rgb, tgt_depth, lambda_c=0.6, inlier_k=50.0, alpha_power=3, pred=None, loss=None,
+                      median=None, grad_rgb=None, grad_depth=None, grad_scale=None):
+        """Tracking loss with masks on the batch's images, or on `pred` =
+        (rgb, depth, alpha) device tensors laid out like them."""
+        dev = self.device
+        img = self.image
+        if pred is not None:
+            for t, n in zip(pred, (3 * self.P, self.P, self.P)):
+                self._check_dev(t, n)
+            img = L.ls_image(pred[0].data_ptr(), pred[1].data_ptr(), pred[2].data_ptr(), None, None)
+        loss = torch.zeros(self.R, dtype=torch.float32, device=dev) if loss is None else loss
+        median = torch.zeros(self.R, dtype=torch.float32, device=dev) if median is None else median
+        grad_rgb = torch.empty_like(self.rgb) if grad_rgb is None else grad_rgb
+        grad_depth = torch.empty_like(self.depth) if grad_depth is None else grad_depth
+        grad_scale = torch.zeros(self.R, dtype=torch.float32, device=dev) if grad_scale is None else grad_scale
+        self._check_dev(tgt_rgb, 3 * self.P, name="tgt_rgb")
+        self._check_dev(tgt_depth, self.P, name="tgt_depth")
+        for t, n in ((loss, self.R), (median, self.R), (grad_rgb, 3 * self.P), (grad_depth, self.P),
+                     (grad_scale, self.R)):
+            self._check_dev(t, n)
+        prm = L.ls_loss_params(float(lambda_c), float(inlier_k), int(alpha_power), 0)
+        L.ls_loss_tracking(self.h, img, _ptr(tgt_rgb), _ptr(tgt_depth), prm, _ptr(loss), _ptr(median),
+                           _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_scale), _stream())
+        return loss, median, grad_rgb, grad_depth, grad_scale
+
     # ------------------------------------------------------------ views
     def image_views(self, r: int):
         cam = self.cams[r]

@@ -184,6 +184,37 @@ def room_points(rng: np.random.Generator, n: int, half=(3.0, 1.5, 2.0), boxes=4,
     return pts
 
 
+def pose_matrix4(pose: np.ndarray) -> np.ndarray:
+    """4x4 rigid matrix of a (w, x, y, z, tx, ty, tz) pose vector."""
+    w, x, y, z = pose[:4].astype(np.float64) / np.linalg.norm(pose[:4])
+    t = np.eye(4)
+    t[:3, :3] = [
+        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+    ]
+    t[:3, 3] = pose[4:7]
+    return t
+
+
+def in_frame(pose: np.ndarray, g: dict) -> dict:
+    """Gaussians moved rigidly by a (w, x, y, z, tx, ty, tz) pose: means mapped,
+    quaternions left-multiplied by the pose's (scales, opacities, colours
+    unchanged)."""
+    t = pose_matrix4(pose)
+    w, x, y, z = pose[:4].astype(np.float64) / np.linalg.norm(pose[:4])
+    out = dict(g)
+    out["mean"] = (t[:3, :3] @ g["mean"].astype(np.float64) + t[:3, 3:4]).astype(np.float32)
+    qq = g["quat"].astype(np.float64)
+    out["quat"] = np.stack([
+        w * qq[0] - x * qq[1] - y * qq[2] - z * qq[3],
+        w * qq[1] + x * qq[0] + y * qq[3] - z * qq[2],
+        w * qq[2] - x * qq[3] + y * qq[0] + z * qq[1],
+        w * qq[3] + x * qq[2] - y * qq[1] + z * qq[0],
+    ]).astype(np.float32)
+    return out
+
+
 def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, views_p: int = 8,
                       views_q: int = 8, width: int = 640, height: int = 480, f: float = 500.0,
                       rot_deg_max: float = 10.0, trans_max: float = 0.3, half=(3.0, 1.5, 2.0),
@@ -218,31 +249,9 @@ def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, v
         gt = axis_angle_pose(random_axis(rng), ang, rng.uniform(0.0, trans_max) * random_axis(rng))
     else:
         gt = np.asarray(fixed_gt, np.float32)
-    qn = gt[:4].astype(np.float64) / np.linalg.norm(gt[:4])
-    w, x, y, z = qn
-    rot = np.array([
-        [1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
-        [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
-        [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
-    ])
-    t_gt = np.eye(4)
-    t_gt[:3, :3] = rot
-    t_gt[:3, 3] = gt[4:7]
-
-    def subset(idx):
-        return {k: v[..., idx].copy() for k, v in g.items()}
-
-    P = subset(idx_p)
-    Q = subset(idx_q)
-    # Q in its own frame: means moved by T_gt, quaternions left-multiplied by q_gt
-    Q["mean"] = (rot @ Q["mean"].astype(np.float64) + t_gt[:3, 3:4]).astype(np.float32)
-    qq = Q["quat"].astype(np.float64)
-    Q["quat"] = np.stack([
-        w * qq[0] - x * qq[1] - y * qq[2] - z * qq[3],
-        w * qq[1] + x * qq[0] + y * qq[3] - z * qq[2],
-        w * qq[2] - x * qq[3] + y * qq[0] + z * qq[1],
-        w * qq[3] + x * qq[2] - y * qq[1] + z * qq[0],
-    ]).astype(np.float32)
+    t_gt = pose_matrix4(gt)
+    P = {k: v[..., idx_p].copy() for k, v in g.items()}
+    Q = in_frame(gt, {k: v[..., idx_q].copy() for k, v in g.items()})
     band = pts[:, n_w - n_q:n_p] if n_p > n_w - n_q else pts
     half = np.asarray(half)
 
@@ -294,3 +303,4 @@ def request_stream(seed: int, n_requests: int, rate_per_s: float, median_n: int 
         out.append(dict(arrival=t, seed=int(seed * 100000 + k), n_p=n_p, n_q=n_q, views_p=v_p, views_q=v_q,
                         width=int(w), height=int(h), f=float(f)))
     return out
+

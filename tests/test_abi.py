@@ -40,7 +40,7 @@ def test_binding_covers_the_header():
     assert set(L.declared_functions()) == declared()
 
 
-@pytest.mark.parametrize("name", ["ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
+@pytest.mark.parametrize("name", ["ls_loss_params", "ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
                                   "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group"])
 def test_struct_layouts_match(name):
     lib = L.load()
@@ -87,3 +87,23 @@ def test_server_rejects_bad_parameters_without_a_device():
     assert lib.ls_server_create(C.byref(prm), C.byref(h)) == L.LS_ERR_INVALID
     assert lib.ls_register_poll(None, 1, None, None) == L.LS_ERR_INVALID
     assert lib.ls_server_destroy(None) == L.LS_OK
+
+
+def test_register_pair_rejects_bad_loss_parameters_before_touching_a_device():
+    """A structurally valid pair whose loss settings are out of range is
+    refused before any device call."""
+    import numpy as np
+
+    lib = L.load()
+    c2w = np.eye(4, dtype=np.float32)[:3].reshape(-1).copy()
+    dummy = np.zeros(16, np.float32)
+    pair = L.ls_pair()
+    pair.vP, pair.vQ = 1, 0
+    pair.rgbP = pair.depthP = dummy.ctypes.data
+    pair.c2wP = c2w.ctypes.data
+    pair.K = L.ls_intrinsics(10.0, 10.0, 2.0, 2.0, 4, 4)
+    res = L.ls_reg_result()
+    for kind, track in ((2, L.ls_loss_params(0.6, 50.0, 3, 0)), (1, L.ls_loss_params(1.5, 50.0, 3, 0)),
+                        (1, L.ls_loss_params(0.6, float("nan"), 3, 0)), (1, L.ls_loss_params(0.6, 50.0, -1, 0))):
+        prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, 0, kind, track)
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID

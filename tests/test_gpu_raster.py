@@ -341,3 +341,63 @@ def test_pose_only_backward_matches_full_and_is_bitwise_repeatable(gpu):
     np.testing.assert_array_equal(runs[0], runs[1])
     for r in range(len(jobs)):
         assert U.rel_err(runs[0][r], full[r].cpu().numpy()) < 1e-4
+
+
+@pytest.mark.parametrize("lambda_c,inlier_k,alpha_power", [(0.6, 50.0, 3), (0.3, 0.0, 0), (1.0, 2.0, 1)])
+def test_loss_tracking_matches_oracle(gpu, lambda_c, inlier_k, alpha_power):
+    """Masked tracking loss on identical FP32 inputs: the median depth error of
+    every render bit-exact (exact selection, ties included), the loss within
+    1e-5 and the image gradients within 1e-5 of the FP64 oracle.  Renders:
+    640x480 (many blocks), 100x70, 33x17 (ragged), 5x3 with one valid pixel
+    and 33x17 with none."""
+    sizes = [(640, 480), (100, 70), (33, 17), (5, 3), (33, 17)]
+    jobs = []
+    for k, (w, h) in enumerate(sizes):
+        sc = synth.scene_tiny(40 + k, 50, w, h, 0.8 * w)
+        jobs.append((sc["gauss"], sc["cam"], sc["w2c"]))
+    b = _batch(jobs)
+    rng = np.random.default_rng(11)
+    pr = rng.random(3 * b.P).astype(np.float32)
+    tr = rng.random(3 * b.P).astype(np.float32)
+    td = np.where(rng.random(b.P) < 0.2, 0.0, rng.random(b.P) * 3 + 0.5).astype(np.float32)
+    # depth errors on a coarse grid (many exact ties), a few gross outliers
+    off = (np.round(rng.normal(0.0, 4.0, b.P)) * 0.01).astype(np.float32)
+    off[rng.random(b.P) < 0.02] = 5.0
+    pdp = (td + off).astype(np.float32)
+    al = rng.random(b.P).astype(np.float32)
+    o3, o4, o5 = (int(b.pix_off[i]) for i in (3, 4, 5))
+    td[o3:o4] = 0.0
+    td[o3 + 7] = 1.25                                     # one valid pixel
+    td[o4:o5] = 0.0                                       # none
+    pr[:5] = tr[:5]                                       # sign(0) = 0
+    dev = lambda a: torch.as_tensor(a, device="cuda")     # noqa: E731
+    loss, med, g_rgb, g_depth, scale = b.loss_tracking(dev(tr), dev(td), lambda_c, inlier_k, alpha_power,
+                                                       pred=(dev(pr), dev(pdp), dev(al)))
+    torch.cuda.synchronize()
+    for r, (_, cam, _) in enumerate(jobs):
+        H, W = cam["height"], cam["width"]
+        p0 = int(b.pix_off[r])
+        sl, sl3 = slice(p0, p0 + H * W), slice(3 * p0, 3 * p0 + 3 * H * W)
+        prr = torch.as_tensor(pr[sl3].reshape(3, H, W), dtype=F64).requires_grad_(True)
+        pdd = torch.as_tensor(pdp[sl].reshape(H, W), dtype=F64).requires_grad_(True)
+        ref, ref_med = R.loss_tracking(prr, pdd, torch.as_tensor(al[sl].reshape(H, W), dtype=F64),
+                                       torch.as_tensor(tr[sl3].reshape(3, H, W), dtype=F64),
+                                       torch.as_tensor(td[sl].reshape(H, W), dtype=F64),
+                                       lambda_c=lambda_c, alpha_power=alpha_power, inlier_k=inlier_k)
+        if inlier_k > 0:
+            assert np.float32(med[r].item()) == np.float32(ref_med), (r, med[r].item(), ref_med)
+        np.testing.assert_allclose(loss[r].item(), ref.item(), rtol=1e-5, atol=1e-12)
+        n = int((td[sl] > 0).sum())
+        if n == 0:
+            assert scale[r].item() == 0.0 and loss[r].item() == 0.0
+            continue
+        np.testing.assert_allclose(scale[r].item(), 1.0 / n, rtol=1e-6)
+        ref.backward()
+        sc = scale[r].item()
+        np.testing.assert_allclose(g_rgb[sl3].cpu().numpy() * sc, prr.grad.numpy().reshape(-1), rtol=1e-5, atol=1e-12)
+        np.testing.assert_allclose(g_depth[sl].cpu().numpy() * sc, pdd.grad.numpy().reshape(-1), rtol=1e-5,
+                                   atol=1e-12)
+    # a second call on the same batch (workspace left zeroed) gives the same result
+    loss2, med2, *_ = b.loss_tracking(dev(tr), dev(td), lambda_c, inlier_k, alpha_power,
+                                      pred=(dev(pr), dev(pdp), dev(al)))
+    assert torch.equal(loss, loss2) and (inlier_k <= 0 or torch.equal(med, med2))

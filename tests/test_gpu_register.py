@@ -13,7 +13,10 @@ from paper_2408_10154_amd import synth
 pytestmark = pytest.mark.gpu
 
 
-def _gpu_register(d, iters, lr_rot, lr_trans):
+TRACK = dict(lambda_c=0.6, alpha_power=3, inlier_k=50.0)
+
+
+def _gpu_register(d, iters, lr_rot, lr_trans, loss="tracking"):
     from paper_2408_10154_amd import register as REG
     from paper_2408_10154_amd.render import GaussianSet
 
@@ -21,7 +24,7 @@ def _gpu_register(d, iters, lr_rot, lr_trans):
     rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
     rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
     return REG.register_pair(P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ,
-                             REG.default_params(iters, lr_rot, lr_trans))
+                             REG.default_params(iters, lr_rot, lr_trans, loss=loss))
 
 
 def _errs(T, gt):
@@ -30,12 +33,15 @@ def _errs(T, gt):
     return REG.rotation_error_deg(T, gt), REG.translation_error_cm(T, gt)
 
 
-def test_tiny_pair_matches_oracle_registration(gpu):
+@pytest.mark.parametrize("loss", ["l1", "tracking"])
+def test_tiny_pair_matches_oracle_registration(gpu, loss):
     """Same tiny room as the oracle's recovery pin: both recover the known
-    transform and agree with each other."""
+    transform and agree with each other, with the plain L1 and with the
+    masked tracking loss."""
+    oracle_loss = None if loss == "l1" else TRACK
     d = synth.registration_pair(4, 1500, 1500, shared_frac=1.0, views_p=1, views_q=1, width=64, height=48, f=45,
                                 half=(1.0, 0.6, 0.8), log_scale_mu=math.log(0.05), rot_deg_max=2.0, trans_max=0.03)
-    res = _gpu_register(d, 100, 0.003, 0.001)
+    res = _gpu_register(d, 100, 0.003, 0.001, loss)
     assert res["status"] == 0 and res["iters"] == 100
     rot, tr = _errs(res["T"], d["T_gt"])
     assert rot < 0.5 and tr < 1.0, (rot, tr)
@@ -50,10 +56,10 @@ def test_tiny_pair_matches_oracle_registration(gpu):
         return out
 
     tp, tq = targets(Pg, d["kf_p"]), targets(Qg, d["kf_q"])
-    t_ref, _, res_ref = G.register_pair(Pg, Qg, tp, tq, cam, 100, 0.003, 0.001)
+    t_ref, _, res_ref = G.register_pair(Pg, Qg, tp, tq, cam, 100, 0.003, 0.001, loss=oracle_loss)
     assert G.rotation_error_deg(res["T"], t_ref) < 0.2
     assert G.translation_error_cm(res["T"][:3, 3], t_ref[:3, 3]) < 0.5
-    # each GPU residual is the L1 loss at the GPU's own final correction:
+    # each GPU residual is the view's loss at the GPU's own final correction:
     # recover Delta = C^-1 E^-1 C from the per-view estimate and evaluate the oracle there
     from scipy.spatial.transform import Rotation
 
@@ -63,7 +69,7 @@ def test_tiny_pair_matches_oracle_registration(gpu):
         q = Rotation.from_matrix(delta[:3, :3]).as_quat()
         d7 = torch.as_tensor(np.concatenate([[q[3]], q[:3], delta[:3, 3]]))
         o = R.render(g_other, cam, torch.as_tensor(G.inv_rigid(c2w)[:3]), d7, with_margins=False)
-        ref = float(R.loss_l1(o["rgb"], o["depth"], torch.as_tensor(rgb), torch.as_tensor(dep)))
+        ref = float(G.view_loss(o, torch.as_tensor(rgb), torch.as_tensor(dep), oracle_loss))
         assert abs(res["residual"][k] - ref) <= 2e-3 * max(ref, 1e-2), (k, res["residual"][k], ref)
 
 
@@ -84,7 +90,8 @@ def test_identical_submaps_zero_loss_at_identity(gpu):
 def test_pair_workload_recovers_transform(gpu, seed):
     """The single-pair registration workload: submaps of 150k and 120k
     Gaussians sharing 60 %, 8 + 8 keyframes at 640x480 (f = 500), ground truth
-    up to 10 deg / 0.3 m, 200 Adam iterations (real-data learning rates)."""
+    up to 10 deg / 0.3 m, 200 Adam iterations (real-data learning rates),
+    masked tracking loss."""
     d = synth.registration_pair(seed, 150000, 120000, views_p=8, views_q=8, width=640, height=480, f=500)
     res = _gpu_register(d, 200, 0.015, 0.005)
     assert res["status"] == 0
