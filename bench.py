@@ -8,10 +8,18 @@ project -> tile binning -> composite forward -> L1 loss -> composite backward
 -> projection backward -> Adam on every Gaussian parameter and on the camera
 pose.  Inputs are resident in HBM before timing; no host sync inside a step.
 
+Then the registration workloads (keyframe localisation with the masked
+tracking loss, 200 Adam iterations per view):
+  - one pair of 150k + 120k Gaussians with 8 + 8 keyframes at 640x480;
+  - a set of 32 pairs (Gaussians per submap log-uniform in [20k, 300k],
+    4..12 keyframes each at 640x480, each with its own ground truth), run
+    one pair at a time through ls_register_pair ("plain") and all submitted
+    at once to the continuous-batching server ("batched").
+
 Prints one JSON line (metric, value in Mpixels/s of fwd+bwd iterations,
 roofline of the dominant kernel measured with HIP events on the launch
-stream, and the FP64 CPU oracle timed on a bounded sample of the same
-workload).
+stream, the registration figures, and the FP64 CPU oracle timed on a bounded
+sample of the render workload).
 """
 
 from __future__ import annotations
@@ -63,6 +71,9 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-tiles", type=int, default=400, help="tiles in the oracle's timed sample")
     ap.add_argument("--gaussians", type=int, default=200_000)
+    ap.add_argument("--pairs", type=int, default=32, help="pairs in the batched-vs-plain registration set")
+    ap.add_argument("--reg-iters", type=int, default=200)
+    ap.add_argument("--no-registration", action="store_true")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device once (a known-size kernel that "
                          "calibrates HBM byte counters in a profiler run)")
@@ -106,6 +117,44 @@ def cpu_baseline(scene, sample_tiles: int):
                 sample=(f"FP64 oracle, one fwd+bwd: project+bin of all {len(pr['radius'])} Gaussians "
                         f"({t1 - t0:.1f} s), then fwd+L1+bwd on {len(subset)} of {ntiles} tiles ({px_sample} px, "
                         f"{t2 - t1:.1f} s); per-image time extrapolated by tile count"))
+
+
+def registration(n_pairs: int, iters: int):
+    """Single-pair time and accuracy, then the pair set plain vs batched.
+    Results of the two paths are compared bit for bit."""
+    import numpy as np
+    import torch
+
+    from paper_2408_10154_amd import regbench as RB
+    from paper_2408_10154_amd import synth
+
+    def rnd(d):
+        return {k: (round(v, 4) if isinstance(v, float) else v) for k, v in d.items()}
+
+    one = [RB.build_pair(RB.single_pair_spec())]
+    RB.run_plain(one, iters=10)                                  # warm-up
+    res, rs = RB.run_plain(one, iters=iters)
+    single = dict(workload="150k + 120k Gaussians (60 % shared), 8 + 8 keyframes at 640x480, f = 500",
+                  iters=iters, seconds=round(res["seconds"], 4),
+                  mpix_per_s=round(one[0]["pixels"] * iters / res["seconds"] / 1e6, 2),
+                  rot_deg=round(res["rot_deg_median"], 4), trans_cm=round(res["trans_cm_median"], 4))
+    del one, rs
+    specs = synth.pair_set(3, n_pairs)
+    pairs = [RB.build_pair(sp) for sp in specs]
+    RB.run_batched(pairs[:2], iters=10)                          # warm-up (server thread, graph path)
+    plain, rp = RB.run_plain(pairs, iters=iters)
+    batched, rb = RB.run_batched(pairs, iters=iters)
+    same = [bool(np.array_equal(a["T"], b["T"])) for a, b in zip(rp, rb)]
+    out = dict(single_pair=single,
+               pair_set=dict(workload=(f"{n_pairs} pairs, Gaussians per submap log-uniform [20k, 300k], 4..12 "
+                                       "keyframes each at 640x480, own ground truth (<= 10 deg, <= 0.3 m)"),
+                             iters=iters, pixels=int(sum(p["pixels"] for p in pairs)),
+                             plain=rnd(plain), batched=rnd(batched),
+                             speedup=round(batched["pairs_per_s"] / plain["pairs_per_s"], 3),
+                             identical_results=float(np.mean(same))))
+    del pairs, rp, rb
+    torch.cuda.empty_cache()
+    return out
 
 
 def main():
@@ -210,6 +259,12 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    reg = None
+    if not args.no_registration:
+        del b, gs, grads, groups
+        torch.cuda.empty_cache()
+        reg = registration(args.pairs, args.reg_iters)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(scene, args.cpu_tiles)
@@ -237,6 +292,7 @@ def main():
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "fragments": {"evaluated": evaluated, "composited": composited},
         "loss": {"first_timed": round(loss0, 5), "last": round(loss1, 5)},
+        "registration": reg,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

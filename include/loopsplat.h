@@ -362,7 +362,8 @@ typedef struct {
 typedef struct {
   float T_PQ[12];     /* fused T_{P->Q}, row-major 3x4 */
   float* per_view_T;  /* host [vP + vQ][12] or NULL: E_i (P views: ~T_{P->Q}; Q views: ~T_{Q->P}) */
-  float* residual;    /* host [vP + vQ] or NULL: eps_i, the final loss of each view */
+  float* residual;    /* host [vP + vQ] or NULL: eps_i, the unmasked colour + depth L1 (ls_loss_l1)
+                         of each view at its final pose, whichever loss drove it */
   int32_t status;     /* LS_OK, or the error of this pair */
   int32_t iters_done; /* Adam steps of the longest-running view */
 } ls_reg_result;

@@ -8,8 +8,11 @@ Readings (the paper leaves these open):
       get their own learning rates (supplement, loop-closure hyper-parameter
       table: 0.003 / 0.001 synthetic-like, 0.015 / 0.005 real-like)
   R19 iteration count: a parameter (200 in the single-pair workload)
-  R20 residual eps_i: the view's loss (plain L1 of R15, or the tracking loss
-      of R24 when `loss` says so) at the final pose, from one extra forward
+  R20 residual eps_i: the unmasked colour + depth L1 of R15 at the final
+      pose, from one extra forward, whichever loss drove the optimisation:
+      the residual rates how well the moved viewpoint explains its whole
+      observation (Sec. 3.2).  A masked residual would rate a view that
+      drifted off the other submap (alpha ~ 0, masked loss ~ 0) best.
   R21 weight 1 / max(eps_i, 1e-12)
   R22 translation: weighted mean of the P->Q translations, the Q->P
       estimates inverted first
@@ -95,7 +98,8 @@ def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt
     for it in range(1, iters + 1):
         out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
         val = view_loss(out, tgt_rgb, tgt_depth, loss)
-        gq, gt = torch.autograd.grad(val, [q, t], allow_unused=True)
+        # an empty render (nothing in front of the camera) does not depend on the pose
+        gq, gt = torch.autograd.grad(val, [q, t], allow_unused=True) if val.requires_grad else (None, None)
         gq = torch.zeros(4, dtype=F64) if gq is None else gq
         gt = torch.zeros(3, dtype=F64) if gt is None else gt
         adam_step(q, gq, mq, vq, it, lr_rot, beta1, beta2, eps)
@@ -103,7 +107,7 @@ def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt
         hist.append(float(val.detach()))
     with torch.no_grad():
         out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
-        resid = float(view_loss(out, tgt_rgb, tgt_depth, loss))
+        resid = float(raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth))
     return torch.cat([q, t]).detach().numpy(), resid, hist
 
 

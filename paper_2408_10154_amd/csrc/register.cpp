@@ -295,11 +295,17 @@ ls_status RegEngine::step(hipStream_t s) {
   return hip_ok();
 }
 
+// Residual of each view at its final pose: the unmasked colour + depth L1,
+// whichever loss drove the optimisation (it rates how well the moved view
+// explains its whole observation; a masked loss would rate a view that
+// drifted off the other submap best).
 ls_status RegEngine::final_forward(hipStream_t s) {
   ls_status st;
   if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
-  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) || (st = view_loss(s))) return st;
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
+      (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)))
+    return st;
   return hip_ok();
 }
 

@@ -518,12 +518,13 @@ class Server {
   }
 
   // Final forward at the current poses, readback, fusion of finished pairs.
+  // The residual of a view is the unmasked L1 there, as in ls_register_pair.
   void retire() {
     const StatePtrs s = state_ptrs(stateA_, R_);
     ls_status st;
     if ((st = ls_project(batch_, s.pose, &proj_, stream_)) || (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)) ||
         (st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_)) ||
-        (st = view_loss(s))) {
+        (st = batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_))) {
       fail_active(st);
       return;
     }

@@ -125,3 +125,28 @@ def test_recovers_known_transform_tiny_scene(loss):
     assert G.rotation_error_deg(t_bar, d["T_gt"]) < 0.5
     assert G.translation_error_cm(t_bar[:3, 3], d["T_gt"][:3, 3]) < 1.0
     assert all(r >= 0 for r in res)
+
+
+def test_residual_is_the_unmasked_l1_whatever_the_loss():
+    """With the pose frozen (zero learning rates) the residual of a view is the
+    plain L1 of its render at identity, also when the masked tracking loss
+    drives the optimisation; a view that sees nothing of the other submap
+    (alpha = 0 everywhere) gets the mean absolute measurement as residual,
+    not the zero of its masked loss."""
+    d = _tiny_pair(4, 2.0, 0.03)
+    cam = R.Camera(**d["cam"])
+    P, Q = R.to_f64(d["P"]), R.to_f64(d["Q"])
+    (c2w, rgb, dep), = _targets(P, cam, d["kf_p"])
+    track = dict(lambda_c=0.6, alpha_power=3, inlier_k=50.0)
+    _, resid, hist = G.localise_view(Q, cam, c2w, rgb, dep, 1, 0.0, 0.0, loss=track)
+    out = R.render(Q, cam, torch.as_tensor(G.inv_rigid(c2w)[:3]), R.identity_pose(), with_margins=False)
+    l1 = float(R.loss_l1(out["rgb"], out["depth"], torch.as_tensor(rgb), torch.as_tensor(dep)))
+    assert resid == pytest.approx(l1, rel=1e-12)
+    assert hist[0] != pytest.approx(l1, rel=1e-3)          # the masked loss is a different number
+    # the camera moved 1 km along its viewing axis: every Gaussian is behind it
+    away = np.array(c2w, np.float64)
+    away[:3, 3] += 1000.0 * away[:3, 2]
+    _, resid, hist = G.localise_view(Q, cam, away, rgb, dep, 1, 0.0, 0.0, loss=track)
+    valid = dep > 0
+    expect = (np.abs(rgb).sum(0)[valid].sum() + np.abs(dep)[valid].sum()) / valid.sum()
+    assert hist[0] == 0.0 and resid == pytest.approx(expect, rel=1e-12)
