@@ -409,6 +409,12 @@ typedef struct {
                                (>= 0.25; below 1 deliberately undersizes it, which exercises the
                                overflow-recovery path: the chunk is re-run with more room) */
   int32_t use_graphs;       /* 1: capture + replay iterations; 0: launch eagerly */
+  int64_t max_active_pixels;/* admission cap on the pixels rendered per iteration by the active set
+                               (0: none).  The head of the queue is admitted only into an empty
+                               active set or while the sum stays within the cap.  Once one pair
+                               fills the GPU, admitting more shares it between them and delays
+                               every result; a cap near the size that fills the device keeps large
+                               pairs first-come first-served and still batches small ones. */
 } ls_server_params;
 
 typedef struct {
@@ -419,6 +425,8 @@ typedef struct {
   int64_t overflow_retries;  /* chunks re-run after the instance capacity overflowed */
   int64_t peak_bytes;        /* peak estimated bytes of the active set */
   int32_t active, waiting;
+  int32_t peak_active;       /* most pairs active at once */
+  int32_t pad;
 } ls_server_stats;
 
 /* Creates a server on the current device with its own worker thread and

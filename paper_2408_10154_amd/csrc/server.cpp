@@ -248,13 +248,16 @@ class Server {
     while (!waiting_.empty() && (int)active_.size() < prm_.max_slots) {
       Slot* s = waiting_.front();
       if (active_bytes_ + s->bytes > prm_.hbm_budget_bytes) break;
+      if (prm_.max_active_pixels > 0 && !active_.empty() && active_pixels_ + s->pixels > prm_.max_active_pixels) break;
       waiting_.pop_front();
       s->state = SlotState::kActive;
       s->t_admit = Clock::now();
       s->first_render = -1;
       active_.push_back(s);
       active_bytes_ += s->bytes;
+      active_pixels_ += s->pixels;
       stats_.peak_bytes = std::max<int64_t>(stats_.peak_bytes, (int64_t)active_bytes_);
+      stats_.peak_active = std::max<int32_t>(stats_.peak_active, (int32_t)active_.size());
       changed = true;
     }
     return changed;
@@ -559,6 +562,7 @@ class Server {
       }
       finish_slot(sl, pose_h, loss_h);
       active_bytes_ -= sl->bytes;
+      active_pixels_ -= sl->pixels;
     }
     active_.swap(keep);
     rebuild_pending_ = true;
@@ -602,6 +606,7 @@ class Server {
       sl->t_done = Clock::now();
       ++stats_.failed;
       active_bytes_ -= sl->bytes;
+      active_pixels_ -= sl->pixels;
     }
     active_.clear();
     R_ = 0;
@@ -628,6 +633,7 @@ class Server {
   std::deque<Slot*> waiting_;
   std::vector<Slot*> active_;
   size_t active_bytes_ = 0;
+  int64_t active_pixels_ = 0;
   ls_server_stats stats_{};
   bool rebuild_pending_ = false;
 
@@ -656,7 +662,8 @@ extern "C" {
 ls_status ls_server_create(const ls_server_params* prm, ls_server** out) {
   if (!prm || !out) return LS_ERR_INVALID;
   *out = nullptr;
-  if (prm->max_slots < 1 || prm->chunk_iters < 1 || !(prm->instance_headroom >= 0.25f) || prm->hbm_budget_bytes == 0)
+  if (prm->max_slots < 1 || prm->chunk_iters < 1 || !(prm->instance_headroom >= 0.25f) || prm->hbm_budget_bytes == 0 ||
+      prm->max_active_pixels < 0)
     return LS_ERR_INVALID;
   auto* s = new ls_server();
   s->impl = std::make_unique<ls::Server>(*prm);

@@ -97,13 +97,14 @@ class ls_reg_result(C.Structure):
 
 class ls_server_params(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_size_t), ("max_slots", C.c_int32), ("chunk_iters", C.c_int32),
-                ("instance_headroom", C.c_float), ("use_graphs", C.c_int32)]
+                ("instance_headroom", C.c_float), ("use_graphs", C.c_int32), ("max_active_pixels", C.c_int64)]
 
 
 class ls_server_stats(C.Structure):
     _fields_ = [("submitted", C.c_int64), ("completed", C.c_int64), ("failed", C.c_int64), ("epochs", C.c_int64),
                 ("iterations", C.c_int64), ("graph_replays", C.c_int64), ("overflow_retries", C.c_int64),
-                ("peak_bytes", C.c_int64), ("active", C.c_int32), ("waiting", C.c_int32)]
+                ("peak_bytes", C.c_int64), ("active", C.c_int32), ("waiting", C.c_int32),
+                ("peak_active", C.c_int32), ("pad", C.c_int32)]
 
 
 class ls_adam_group(C.Structure):

@@ -71,11 +71,13 @@ def run_batched(pairs, iters=200, loss="tracking", chunk_iters=16, use_graphs=Tr
                 epochs=st["epochs"], graph_replays=st["graph_replays"], **_errors(results, pairs)), results
 
 
-def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget=200 << 30, max_slots=64):
+def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget=200 << 30, max_slots=64,
+               max_active_pixels=0):
     """Requests submitted at their arrival times (a host thread paces them)."""
     from .serve import Server
 
-    with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters) as sv:
+    with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters,
+                max_active_pixels=max_active_pixels) as sv:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tickets = []
@@ -89,7 +91,25 @@ def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget
         st = sv.stats()
     lat = [r["times"]["total"] for r in results]
     return dict(seconds=total, pairs_per_s=len(built) / total, p50_s=_pct(lat, 50), p99_s=_pct(lat, 99),
-                max_active_bytes=st["peak_bytes"], **_errors(results, built)), results
+                max_active_bytes=st["peak_bytes"], peak_active=st["peak_active"], epochs=st["epochs"],
+                **_errors(results, built)), results
+
+
+def run_stream_plain(stream, built, iters=200, loss="tracking"):
+    """The plain path under the same arrivals: a FIFO queue served one pair at
+    a time by ls_register_pair; latency counts from each request's arrival."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results, lat = [], []
+    for spec, p in zip(stream, built):
+        delay = spec["arrival"] - (time.perf_counter() - t0)
+        if delay > 0:
+            time.sleep(delay)
+        results.append(REG.register_pair(*p["args"], params=REG.default_params(iters, loss=loss)))
+        lat.append(time.perf_counter() - t0 - spec["arrival"])
+    total = time.perf_counter() - t0
+    return dict(seconds=total, pairs_per_s=len(built) / total, p50_s=_pct(lat, 50), p99_s=_pct(lat, 99),
+                **_errors(results, built)), results
 
 
 def single_pair_spec(seed=2):
@@ -102,26 +122,48 @@ def main(argv=None):
     """Command-line runs of the registration workloads (one JSON line each),
     e.g. under a kernel-trace profiler:
       python -m paper_2408_10154_amd.regbench --workload single --iters 50
-      python -m paper_2408_10154_amd.regbench --workload set --pairs 8 --mode both"""
+      python -m paper_2408_10154_amd.regbench --workload set --pairs 8 --mode both
+      python -m paper_2408_10154_amd.regbench --workload stream --requests 40 --rate 2 --mode both"""
     import argparse
     import json
 
     ap = argparse.ArgumentParser()
-    ap.add_argument("--workload", choices=["single", "set"], default="single")
+    ap.add_argument("--workload", choices=["single", "set", "stream"], default="single")
+    ap.add_argument("--requests", type=int, default=40, help="requests of the stream (seed 100)")
+    ap.add_argument("--rate", type=float, default=2.0, help="stream arrivals per second")
+    ap.add_argument("--max-active-pixels", type=int, nargs="+", default=[0],
+                    help="server admission caps to try (0: none)")
     ap.add_argument("--pairs", type=int, default=8, help="pairs of the pair set (seed 3)")
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--mode", choices=["plain", "batched", "both"], default="plain")
     ap.add_argument("--loss", choices=["tracking", "l1"], default="tracking")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
-    specs = [single_pair_spec()] if a.workload == "single" else synth.pair_set(3, a.pairs)
+    if a.workload == "single":
+        specs = [single_pair_spec()]
+    elif a.workload == "set":
+        specs = synth.pair_set(3, a.pairs)
+    else:
+        specs = synth.request_stream(100, a.requests, a.rate)
     pairs = [build_pair(sp) for sp in specs]
     print(json.dumps(dict(event="built", pairs=len(pairs))), flush=True)
     for mode in (["plain", "batched"] if a.mode == "both" else [a.mode]):
-        run = run_plain if mode == "plain" else run_batched
-        res, _ = run(pairs, iters=a.iters, loss=a.loss)
-        print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters,
-                              **{k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()})), flush=True)
+        caps = a.max_active_pixels if (mode == "batched" and a.workload == "stream") else [0]
+        for cap in caps:
+            if a.workload == "stream":
+                if mode == "plain":
+                    res, _ = run_stream_plain(specs, pairs, iters=a.iters, loss=a.loss)
+                else:
+                    res, _ = run_stream(specs, pairs, iters=a.iters, loss=a.loss, max_active_pixels=cap)
+            else:
+                run = run_plain if mode == "plain" else run_batched
+                res, _ = run(pairs, iters=a.iters, loss=a.loss)
+            extra = dict(rate=a.rate, requests=a.requests) if a.workload == "stream" else {}
+            if mode == "batched" and a.workload == "stream":
+                extra["max_active_pixels"] = cap
+            print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters, **extra,
+                                  **{k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()})),
+                  flush=True)
 
 
 if __name__ == "__main__":

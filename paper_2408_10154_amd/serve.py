@@ -19,10 +19,10 @@ from .register import default_params, make_pair
 
 class Server:
     def __init__(self, budget_bytes: int = 200 << 30, max_slots: int = 64, chunk_iters: int = 16,
-                 instance_headroom: float = 1.5, use_graphs: bool = True):
+                 instance_headroom: float = 1.5, use_graphs: bool = True, max_active_pixels: int = 0):
         L.load()
         prm = L.ls_server_params(int(budget_bytes), int(max_slots), int(chunk_iters), float(instance_headroom),
-                                 1 if use_graphs else 0)
+                                 1 if use_graphs else 0, int(max_active_pixels))
         h = C.c_void_p()
         L.check(L.load().ls_server_create(C.byref(prm), C.byref(h)))
         self.h = h
@@ -70,7 +70,7 @@ class Server:
     def stats(self) -> dict:
         st = L.ls_server_stats()
         L.check(L.load().ls_server_get_stats(self.h, C.byref(st)))
-        return {k: getattr(st, k) for k, _ in L.ls_server_stats._fields_}
+        return {k: getattr(st, k) for k, _ in L.ls_server_stats._fields_ if k != "pad"}
 
     def close(self):
         if getattr(self, "h", None) is not None:

@@ -85,6 +85,8 @@ def test_server_rejects_bad_parameters_without_a_device():
     assert lib.ls_server_create(C.byref(prm), C.byref(h)) == L.LS_ERR_INVALID
     prm = L.ls_server_params(1 << 30, 4, 16, 0.1, 1)  # headroom < 0.25
     assert lib.ls_server_create(C.byref(prm), C.byref(h)) == L.LS_ERR_INVALID
+    prm = L.ls_server_params(1 << 30, 4, 16, 1.5, 1, -1)  # negative pixel cap
+    assert lib.ls_server_create(C.byref(prm), C.byref(h)) == L.LS_ERR_INVALID
     assert lib.ls_register_poll(None, 1, None, None) == L.LS_ERR_INVALID
     assert lib.ls_server_destroy(None) == L.LS_OK
 

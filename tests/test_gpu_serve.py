@@ -105,6 +105,23 @@ def test_budget_admits_one_at_a_time_and_rejects_oversized(pairs):
     assert rs[1]["times"]["queue"] > 0.0
 
 
+@pytest.mark.parametrize("cap,peak", [(300_000, 1), (500_000, 2)])
+def test_active_pixel_cap_limits_concurrency(pairs, cap, peak):
+    """Pairs render 196,608 / 294,912 / 196,608 pixels per iteration.  A cap of
+    300k admits one pair at a time (the head always enters an empty active
+    set); 500k lets the first two share.  Results stay bit-identical."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.serve import Server
+
+    with Server(chunk_iters=8, max_active_pixels=cap) as sv:
+        ts = [sv.submit(*p["args"], params=REG.default_params(ITERS)) for p in pairs]
+        rs = [sv.wait(t) for t in ts]
+        st = sv.stats()
+    assert st["peak_active"] == peak, st
+    for r, p in zip(rs, pairs):
+        assert r["status"] == 0 and _same(r, _plain(p))
+
+
 def test_capacity_overflow_is_recovered(pairs):
     """headroom 0.5 sizes the instance buffers to half the count measured at
     each rebuild: the first chunk overflows, is rolled back and re-run with
