@@ -106,13 +106,16 @@ __device__ __forceinline__ float falloff(float A, float B, float C, float dx, fl
   return __builtin_fmaf(0.5f * A * dx, dx, __builtin_fmaf(B * dx, dy, 0.5f * C * dy * dy));
 }
 
+// The DPP reductions below use moves without an "old" operand (bound_ctrl
+// set): every lane's source is in range for these patterns, and the
+// compiler can fold each move into its add (v_add_f32 with a DPP operand).
 // Full-wave (64-lane) sum; the total is returned in every lane.
 __device__ __forceinline__ float wave_sum(float v) {
   // within rows of 16 lanes: swap pairs, quads, half-rows, rows
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));  // quad_perm 1,0,3,2
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));  // quad_perm 2,3,0,1
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false)); // row_half_mirror
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false)); // row_mirror
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));  // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));  // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true)); // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true)); // row_mirror
   // every lane of a row now holds the row sum; combine the four rows
   float r0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 0));
   float r1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 16));

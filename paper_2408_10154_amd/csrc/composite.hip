@@ -125,31 +125,33 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restri
       m = wave_mask(a, b, tx0, ty0);
     }
     build_wave_lists(m, e < end, slist, scnt, swc);
-    const int cw = (int)swc[w];
+    // the band's list is wave-uniform: scalar loop control, branch-free body
+    const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     for (int jj = 0; jj < cw; ++jj) {
       if (__ballot(!done) == 0ull) break;  // whole wave finished
-      if (done) continue;
-      const int j = slist[w][jj];
+      const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
       const float sig = falloff(a.z, a.w, b.x, dx, dy);
-      if (sig < 0.f) continue;
       const float al = fminf(LS_ALPHA_MAX, b.y * __expf(-sig));
-      if (al < LS_ALPHA_MIN) continue;
+      const bool hit = !done && sig >= 0.f && al >= LS_ALPHA_MIN;
       const float Tn = T * (1.f - al);
-      if (Tn < LS_T_STOP) {
+      const bool stop = hit && Tn < LS_T_STOP;
+      if (stop) {
         done = true;
         nlast = chunk + j - start;
-        continue;
       }
-      const float4 col = s2[j];
-      const float wgt = al * T;
-      cr += wgt * col.x;
-      cg += wgt * col.y;
-      cb += wgt * col.z;
-      dd += wgt * b.z;
-      T = Tn;
+      const bool use = hit && !stop;
+      if (__ballot(use) != 0ull) {
+        const float4 col = s2[j];
+        const float wgt = use ? al * T : 0.f;  // 0 adds an exact zero below
+        cr += wgt * col.x;
+        cg += wgt * col.y;
+        cb += wgt * col.z;
+        dd += wgt * b.z;
+        T = use ? Tn : T;
+      }
     }
   }
   if (!c.inside) return;
@@ -167,10 +169,10 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restri
 
 // Sum over each 16-lane row of the wave; every lane of a row gets its row sum.
 __device__ __forceinline__ float row_sum16(float v) {
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0xB1, 0xF, 0xF, false));   // quad_perm 1,0,3,2
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x4E, 0xF, 0xF, false));   // quad_perm 2,3,0,1
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x141, 0xF, 0xF, false));  // row_half_mirror
-  v += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x140, 0xF, 0xF, false));  // row_mirror
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
+  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
   return v;
 }
 
@@ -183,27 +185,30 @@ constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row part
 // "behind" value acc = sum_{j>i} alpha_j prod_{i<k<j}(1 - alpha_k) v_j +
 // prod_{k>i}(1 - alpha_k)(bg . gC - gA), where v_j = c_j . gC + z_j gD:
 //   dL/dalpha_i = T_i (v_i - acc_i).
-// One such step at a pixel: returns false if the entry was not composited
-// there; else undoes its transmittance, updates acc and gives its weight
-// alpha T, ex = exp(-sigma), G = o ex and dG = dL/dG (zero when the 0.99
-// clamp is active).
-__device__ __forceinline__ bool bwd_step(float4 a, float4 b, float4 col, float dx, float dy, float gR, float gG,
-                                         float gB, float gD, float& T, float& acc, float& wgt, float& ex, float& G,
-                                         float& dG) {
+// One such step at a pixel, branch-free: act says whether the entry was
+// composited there (visited, sigma >= 0, alpha >= 1/255); if so T is
+// recovered, acc updated, and wgt = alpha T, ds = dL/dsigma and dop =
+// dL/d(opacity) are set (both zero while the 0.99 clamp is active);
+// otherwise T and acc are unchanged and wgt = ds = dop = 0 (selected, never
+// formed from products with exp(-sigma)).
+__device__ __forceinline__ bool bwd_step(bool visited, float4 a, float4 b, float4 col, float dx, float dy, float gR,
+                                         float gG, float gB, float gD, float& T, float& acc, float& wgt, float& ds,
+                                         float& dop) {
   const float sig = falloff(a.z, a.w, b.x, dx, dy);
-  if (!(sig >= 0.f)) return false;
-  ex = __expf(-sig);
-  G = b.y * ex;
+  const float ex = __expf(-sig);
+  const float G = b.y * ex;
   const float al = fminf(LS_ALPHA_MAX, G);
-  if (!(al >= LS_ALPHA_MIN)) return false;
+  const bool act = visited && sig >= 0.f && al >= LS_ALPHA_MIN;
   const float om = 1.f - al;
-  T = T * __builtin_amdgcn_rcpf(om);
-  wgt = al * T;
+  T = act ? T * __builtin_amdgcn_rcpf(om) : T;
+  wgt = act ? al * T : 0.f;
   const float v = col.x * gR + col.y * gG + col.z * gB + b.z * gD;
   const float dal = T * (v - acc);
-  acc = al * v + om * acc;
-  dG = (G < LS_ALPHA_MAX) ? dal : 0.f;
-  return true;
+  acc = act ? al * v + om * acc : acc;
+  const bool grad = act && G < LS_ALPHA_MAX;  // dL/dG = dal; no gradient through an active clamp
+  ds = grad ? -dal * G : 0.f;
+  dop = grad ? dal * ex : 0.f;
+  return act;
 }
 
 // Per-pixel state shared by both backward kernels: upstream gradients (scaled),
@@ -305,37 +310,30 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
     const int cnt = chunk_end - chunk;
     if (w == 0) stage_chunk<kBwdChunk>(lane, cnt, chunk, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
     __syncthreads();
-    const int cw = (int)swc[w];
+    const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     for (int jj = cw - 1; jj >= 0; --jj) {
-      const int j = slist[w][jj];
+      const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
       float* pj = part + j * kPartStride + row * kPartRow;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;  // list position
-      float g[kGrad2D];
-#pragma unroll
-      for (int q = 0; q < kGrad2D; ++q) g[q] = 0.f;
-      bool act = false;
-      if (k < px.nl) {
-        const float4 a = s0[j];
-        const float4 b = s1[j];
-        const float dx = fx - a.x, dy = fy - a.y;
-        float wgt, ex, G, dG;
-        if (bwd_step(a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ex, G, dG)) {
-          act = true;
-          g[7] = wgt * px.gR;
-          g[8] = wgt * px.gG;
-          g[9] = wgt * px.gB;
-          g[6] = wgt * px.gD;
-          g[5] = dG * ex;                      // dL/d opacity
-          const float ds = -dG * G;            // dL/d sigma
-          g[0] = -ds * (a.z * dx + a.w * dy);  // dL/du
-          g[1] = -ds * (a.w * dx + b.x * dy);  // dL/dv
-          g[2] = 0.5f * ds * dx * dx;          // dL/dA
-          g[3] = ds * dx * dy;                 // dL/dB
-          g[4] = 0.5f * ds * dy * dy;          // dL/dC
-        }
-      }
+      const float4 a = s0[j];
+      const float4 b = s1[j];
+      const float dx = fx - a.x, dy = fy - a.y;
+      float wgt, ds, dop;
+      const bool act = bwd_step(k < px.nl, a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds,
+                                dop);
       if (__ballot(act) != 0ull) {
+        float g[kGrad2D];
+        g[0] = -ds * (a.z * dx + a.w * dy);  // dL/du
+        g[1] = -ds * (a.w * dx + b.x * dy);  // dL/dv
+        g[2] = 0.5f * ds * dx * dx;          // dL/dA
+        g[3] = ds * dx * dy;                 // dL/dB
+        g[4] = 0.5f * ds * dy * dy;          // dL/dC
+        g[5] = dop;                          // dL/d opacity
+        g[6] = wgt * px.gD;
+        g[7] = wgt * px.gR;
+        g[8] = wgt * px.gG;
+        g[9] = wgt * px.gB;
 #pragma unroll
         for (int q = 0; q < kGrad2D; ++q) g[q] = row_sum16(g[q]);
         if (lead) {
@@ -431,33 +429,26 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose(const JobDev* __r
     const int cnt = chunk_end - chunk;
     if (w == 0) stage_chunk<kPoseChunk>(lane, cnt, chunk, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
     __syncthreads();
-    const int cw = (int)swc[w];
+    const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     for (int jj = cw - 1; jj >= 0; --jj) {
-      const int j = slist[w][jj];
+      const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
       float* pj = part + j * kPoseStride + row * kPoseRow;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;
+      const float4 a = s0[j];
+      const float4 b = s1[j];
+      const float dx = fx - a.x, dy = fy - a.y;
+      float wgt, ds, dop;
+      const bool act = bwd_step(k < px.nl, a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds,
+                                dop);
       float g[kPoseRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      bool act = false;
-      if (k < px.nl) {
-        const float4 a = s0[j];
-        const float4 b = s1[j];
-        const float dx = fx - a.x, dy = fy - a.y;
-        float wgt, ex, G, dG;
-        if (bwd_step(a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ex, G, dG)) {
-          act = true;
-          const float ds = -dG * G;
-          g[0] = -ds * (a.z * dx + a.w * dy);
-          g[1] = -ds * (a.w * dx + b.x * dy);
-          g[2] = 0.5f * ds * dx * dx;
-          g[3] = ds * dx * dy;
-          g[4] = 0.5f * ds * dy * dy;
-          g[5] = wgt * px.gD;
-        }
-      }
       if (__ballot(act) != 0ull) {
-#pragma unroll
-        for (int q = 0; q < kPoseRow; ++q) g[q] = row_sum16(g[q]);
+        g[0] = row_sum16(-ds * (a.z * dx + a.w * dy));
+        g[1] = row_sum16(-ds * (a.w * dx + b.x * dy));
+        g[2] = row_sum16(0.5f * ds * dx * dx);
+        g[3] = row_sum16(ds * dx * dy);
+        g[4] = row_sum16(0.5f * ds * dy * dy);
+        g[5] = row_sum16(wgt * px.gD);
       }
       if (lead) {
 #pragma unroll
