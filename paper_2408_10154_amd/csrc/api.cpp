@@ -57,14 +57,14 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
     return o;
   };
   const int64_t M = b->M;
-  const int64_t nbd = (M + kSortTile - 1) / kSortTile;
-  const int64_t nbt = (cap + kSortTile - 1) / kSortTile;
+  const int64_t nbd = sort_blocks(M);
+  const int64_t nbt = sort_blocks(cap);
   L.dk0 = take(4 * M);
   L.dv0 = take(4 * M);
   L.dk1 = take(4 * M);
   L.dv1 = take(4 * M);
   L.hist = take(4 * 256 * std::max<int64_t>(std::max(nbd, nbt), 1));
-  L.bsum = take(4 * (nbd + 8 + 264));  // block sums, their total, then 257 digit bases
+  L.bsum = take(4 * (nbd + 8 + 264));  // block sums, then 256 digit totals
   L.tk = take(4 * cap);
   L.tv = take(4 * cap);
   L.g2d = take(4 * (size_t)kGrad2D * M);

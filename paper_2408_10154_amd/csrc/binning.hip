@@ -37,16 +37,16 @@ __device__ __forceinline__ int sort_count(const int32_t* n_dev, int64_t n_static
 // Per-block digit histogram, stored digit-major: hist[d * nblocks + block].
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys, const int32_t* n_dev,
                                                             int64_t n_static, int64_t cap, int shift,
-                                                            uint32_t* __restrict__ hist, int nblocks) {
+                                                            uint32_t* __restrict__ hist, int nblocks, int rounds) {
   __shared__ uint32_t h[256];
   const int n = sort_count(n_dev, n_static, cap);
   h[threadIdx.x] = 0;
   __syncthreads();
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (base < n) {
     const int lane = threadIdx.x & 63;
 #pragma unroll 4
-    for (int i = 0; i < kSortItems; ++i) {
+    for (int i = 0; i < rounds; ++i) {
       const int64_t idx = base + i * kSortThreads + threadIdx.x;
       const bool valid = idx < n;
       const uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
@@ -101,18 +101,9 @@ __global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, 
   if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-// Exclusive scan of n <= 256 words in place (one block); the sum goes to
-// data[n].
-__global__ __launch_bounds__(256) void k_scan_small(uint32_t* __restrict__ data, int n) {
-  __shared__ uint32_t wsum[4];
-  const uint32_t v = (int)threadIdx.x < n ? data[threadIdx.x] : 0u;
-  uint32_t tot;
-  const uint32_t x = block_excl_scan(v, wsum, &tot);
-  if ((int)threadIdx.x < n) data[threadIdx.x] = x;
-  if (threadIdx.x == 0) data[n] = tot;
-}
-
-// Stable scatter of one 8-bit digit pass.  Items of a block are taken in
+// Stable scatter of one 8-bit digit pass.  Each block first turns the digit
+// totals into digit bases (one block-wide scan of 256 words, cheaper than a
+// launch of its own), adds its scanned row entries, then takes its items in
 // rounds of 256 in index order; within a round, ranks come from wave-level
 // digit matching and per-wave counts combined in wave order.
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* __restrict__ kin,
@@ -120,16 +111,19 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
                                                                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                const int32_t* n_dev, int64_t n_static, int64_t cap,
                                                                int shift, const uint32_t* __restrict__ hist, int nblocks,
-                                                               const uint32_t* __restrict__ digit_base) {
+                                                               const uint32_t* __restrict__ digit_total, int rounds) {
   __shared__ uint32_t base[256];
   __shared__ uint32_t wcnt[4][256];
+  __shared__ uint32_t wsum[4];
   const int n = sort_count(n_dev, n_static, cap);
-  const int64_t bbase = (int64_t)blockIdx.x * kSortTile;
+  const int64_t bbase = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (bbase >= n) return;  // uniform for the block
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  base[tid] = digit_base[tid] + hist[(int64_t)tid * nblocks + blockIdx.x];
+  uint32_t all;
+  const uint32_t dbase = block_excl_scan(digit_total[tid], wsum, &all);
+  base[tid] = dbase + hist[(int64_t)tid * nblocks + blockIdx.x];
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int round = 0; round < kSortItems; ++round) {
+  for (int round = 0; round < rounds; ++round) {
     const int64_t rbase = bbase + (int64_t)round * kSortThreads;
     if (rbase >= n) break;  // uniform
     const int64_t idx = rbase + tid;
@@ -171,12 +165,12 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
 
 // Per-block (4096 items) sums of the tile counts of depth-sorted items.
 __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __restrict__ order,
-                                                            const int32_t* __restrict__ tiles, int64_t M,
+                                                            const int32_t* __restrict__ tiles, int64_t M, int rounds,
                                                             uint32_t* __restrict__ bsum) {
   __shared__ uint32_t ws[4];
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
+  const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
   uint32_t s = 0;
-  for (int i = 0; i < kSortItems; ++i) {
+  for (int i = 0; i < rounds; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
     if (k < M) s += (uint32_t)tiles[order[k]];
   }
@@ -186,18 +180,39 @@ __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __re
   if (threadIdx.x == 0) bsum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
 }
 
-// Exclusive offsets of every depth-sorted item: block offset (scanned bsum)
-// plus the in-block prefix, 16 rounds of 256 items in order.  Also writes
-// count[0] = min(I, cap) and the overflow flag count[1].
+// Exclusive offsets of every depth-sorted item: block offset (the sum of the
+// preceding block sums, formed here rather than by a scan launch) plus the
+// in-block prefix, 16 rounds of 256 items in order.  Block 0 also writes
+// count = {min(I, cap), I > cap, min(I, INT32_MAX), 0}.
 __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __restrict__ order,
                                                           const int32_t* __restrict__ tiles, int64_t M,
-                                                          const uint32_t* __restrict__ bsum_scanned, int nbd,
+                                                          const uint32_t* __restrict__ bsum, int nbd,
                                                           uint32_t* __restrict__ offs, int32_t* __restrict__ count,
-                                                          int64_t cap) {
+                                                          int64_t cap, int rounds) {
   __shared__ uint32_t wsum[4];
-  const int64_t base = (int64_t)blockIdx.x * kSortTile;
-  uint32_t run = bsum_scanned[blockIdx.x];
-  for (int i = 0; i < kSortItems; ++i) {
+  __shared__ uint64_t wtot[4];
+  const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
+  // the offset of this block (and, for block 0, the total over all blocks)
+  const int upto = blockIdx.x == 0 ? nbd : (int)blockIdx.x;
+  uint64_t before = 0, total = 0;
+  for (int b = threadIdx.x; b < upto; b += kSortThreads) {
+    const uint64_t v = bsum[b];
+    total += v;
+    if (b < (int)blockIdx.x) before += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    before += __shfl_xor(before, off, 64);
+    total += __shfl_xor(total, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wsum[threadIdx.x >> 6] = (uint32_t)before;
+    wtot[threadIdx.x >> 6] = total;
+  }
+  __syncthreads();
+  uint32_t run = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  const uint64_t I64 = wtot[0] + wtot[1] + wtot[2] + wtot[3];
+  __syncthreads();
+  for (int i = 0; i < rounds; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
     const uint32_t c = k < M ? (uint32_t)tiles[order[k]] : 0u;
     uint32_t tot;
@@ -206,7 +221,7 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
     run += tot;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
-    const int64_t I = bsum_scanned[nbd];
+    const int64_t I = (int64_t)I64;
     count[0] = (int32_t)min(I, cap);
     count[1] = I > cap ? 1 : 0;
     count[2] = (int32_t)min(I, (int64_t)INT32_MAX);
@@ -282,16 +297,16 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
-// One LSD pass: histogram, per-digit row scan, digit-total scan, scatter.
+// One LSD pass: histogram, per-digit row scan (row totals to digit_total),
+// scatter (which scans the 256 digit totals itself).
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const int32_t* n_dev,
-                       int64_t n_static, int64_t cap, int shift, uint32_t* hist, uint32_t* digit_base, int nblocks,
-                       hipStream_t s) {
+                       int64_t n_static, int64_t cap, int shift, uint32_t* hist, uint32_t* digit_total, int nblocks,
+                       int rounds, hipStream_t s) {
   hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift, hist,
-                     nblocks);
-  hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, s, hist, (int64_t)nblocks, digit_base);
-  hipLaunchKernelGGL(k_scan_small, dim3(1), dim3(256), 0, s, digit_base, 256);
+                     nblocks, rounds);
+  hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, s, hist, (int64_t)nblocks, digit_total);
   hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_dev, n_static,
-                     cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_base);
+                     cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_total, rounds);
 }
 
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
@@ -299,21 +314,20 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s) {
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
-  const int nbd = (int)((M + kSortTile - 1) / kSortTile);
-  uint32_t* digit_base = bsum + nbd + 8;  // 257 words after the block sums
+  const int rd = sort_rounds(M), nbd = (int)sort_blocks(M);
+  uint32_t* digit_base = bsum + nbd + 8;  // 256 digit totals after the block sums
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec4, tiles, M, dk0, dv0);
   uint32_t *ka = dk0, *va = dv0, *kb = dk1, *vb = dv1;
   for (int shift = 0; shift < 32; shift += 8) {
-    radix_pass(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, s);
+    radix_pass(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, rd, s);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
   const uint32_t* order = va;
   uint32_t* offs = ka;  // the free key buffer holds the per-item offsets
-  hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, bsum);
-  hipLaunchKernelGGL(k_scan_rows, dim3(1), dim3(256), 0, s, bsum, (int64_t)nbd, bsum + nbd);
+  hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, rd, bsum);
   hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const uint32_t*)bsum, nbd,
-                     offs, count, cap);
+                     offs, count, cap, rd);
   // emission lands in the buffer that, after tile_passes ping-pongs, is the output
   uint32_t* ek = (tile_passes & 1) ? tk : tile_of;
   uint32_t* ev = (tile_passes & 1) ? tv : reinterpret_cast<uint32_t*>(item);
@@ -324,9 +338,9 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((emit_threads + 255) / 256)), dim3(256), 0, s, jobs, item_off_d, R, order,
                        rec4, radius, tiles, M, (const uint32_t*)offs, (const int32_t*)count, ek,
                        reinterpret_cast<int32_t*>(ev));
-  const int nbt = (int)((cap + kSortTile - 1) / kSortTile);
+  const int rt = sort_rounds(cap), nbt = (int)sort_blocks(cap);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {
-    radix_pass(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, digit_base, nbt, s);
+    radix_pass(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, digit_base, nbt, rt, s);
     std::swap(ek, ok);
     std::swap(ev, ov);
   }
