@@ -35,26 +35,48 @@ __device__ __forceinline__ TileCtx tile_ctx(const JobDev* jobs, const int32_t* t
 }
 
 // Which of the block's four 16x4-pixel wave bands the Gaussian can reach
-// with alpha >= 1/255: the support {o exp(-sigma) >= 1/255} is the ellipse
-// sigma <= ln(255 o), whose bounding box has half-extents
-// sqrt(2 ln(255 o) Sigma_xx) and sqrt(2 ln(255 o) Sigma_yy), Sigma = conic^-1.
-// Widened by 0.1% + 0.02 px so that FP32 rounding never drops a contributor.
+// with alpha >= 1/255.  The support {o exp(-sigma) >= 1/255} is the ellipse
+// sigma <= s = ln(255 o).  Its x half-extent is sqrt(2 s Sigma_xx) (Sigma =
+// conic^-1); within the tile's column strip x0 <= x <= x1 its y-extent runs
+// from the lowest to the highest point of the ellipse when those lie inside
+// the strip, else to the ends of the chord on the nearer strip edge (the
+// ellipse's y-range over a vertical line x = xb is the root interval of a
+// quadratic in y).  A band is kept when that y-extent meets it.  s is widened
+// by 0.1% + 1e-4 and every extent by 0.1% + 0.02 px, so FP32 rounding never
+// drops a contributor.
 __device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int tile_x0, int tile_y0) {
   const float o = b.y;
   if (!(o >= LS_ALPHA_MIN)) return 0u;
   const float A = a.z, B = a.w, C = b.x;
   const float dq = A * C - B * B;
   if (!(dq > 0.f)) return 0xFu;
-  const float st = 2.f * __logf(o * (1.0f / LS_ALPHA_MIN));
-  const float hx = sqrtf(fmaxf(st * C / dq, 0.f)) * 1.001f + 0.02f;
-  const float hy = sqrtf(fmaxf(st * A / dq, 0.f)) * 1.001f + 0.02f;
+  const float smax = __logf(o * (1.0f / LS_ALPHA_MIN)) * 1.001f + 1e-4f;
+  const float hx = sqrtf(fmaxf(2.f * smax * C / dq, 0.f)) * 1.001f + 0.02f;
+  const float hy = sqrtf(fmaxf(2.f * smax * A / dq, 0.f)) * 1.001f + 0.02f;
   const float x0 = (float)tile_x0 + 0.5f, x1 = (float)tile_x0 + 15.5f;
   if (a.x + hx < x0 || a.x - hx > x1) return 0u;
+  const float sx = B / A * hy;  // the highest point sits at x = u - sx, the lowest at u + sx
+  const float top_x = a.x - sx, bot_x = a.x + sx;
+  float yhi = a.y + hy, ylo = a.y - hy;
+  if (top_x < x0 || top_x > x1) {
+    const float dx = (top_x < x0 ? x0 : x1) - a.x;
+    const float D = 2.f * C * smax - dq * dx * dx;
+    if (!(D >= 0.f)) return 0u;  // the ellipse does not reach the strip
+    yhi = a.y + (-B * dx + sqrtf(D)) / C;
+  }
+  if (bot_x < x0 || bot_x > x1) {
+    const float dx = (bot_x < x0 ? x0 : x1) - a.x;
+    const float D = 2.f * C * smax - dq * dx * dx;
+    if (!(D >= 0.f)) return 0u;
+    ylo = a.y + (-B * dx - sqrtf(D)) / C;
+  }
+  yhi += fabsf(yhi - a.y) * 1e-3f + 0.02f;
+  ylo -= fabsf(a.y - ylo) * 1e-3f + 0.02f;
   uint32_t m = 0;
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const float y0 = (float)(tile_y0 + 4 * w) + 0.5f, y1 = y0 + 3.f;
-    if (!(a.y + hy < y0 || a.y - hy > y1)) m |= 1u << w;
+    if (!(yhi < y0 || ylo > y1)) m |= 1u << w;
   }
   return m;
 }
