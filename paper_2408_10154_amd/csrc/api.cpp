@@ -45,7 +45,7 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 namespace {
 
 struct Layout {
-  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, total;
+  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, queues, total;
 };
 
 Layout layout_of(const ls_batch* b, int64_t cap) {
@@ -70,6 +70,7 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.g2d = take(4 * (size_t)kGrad2D * M);
   L.tile_part = take(4 * (size_t)kPoseAcc * std::max(b->T, 1));
   L.pose_part = take(4 * (size_t)kPoseAcc * std::max(b->nblk_items, 1));
+  L.queues = take(kTileQueueBytes);
   L.total = off;
   return L;
 }
@@ -345,9 +346,10 @@ ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins*
   if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
   if (!out || !out->rgb || !out->depth || !out->alpha || !out->T_final || !out->n_last)
     return fail(LS_ERR_INVALID, "ls_image has NULL members");
+  const Layout L = layout_of(b, bins->capacity);
   const float zero[3] = {0.f, 0.f, 0.f};
   launch_composite_fwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
-                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, s);
+                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, at<char>(bins->work, L.queues), s);
   return hip_check("ls_render_fwd");
 }
 
@@ -364,7 +366,7 @@ ls_status ls_render_bwd_tiles(const ls_batch* b, const float* pose, const ls_pro
   launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range,
                        bg ? bg : zero, fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale,
                        at<float>(bins->work, L.g2d), at<float>(bins->work, L.tile_part),
-                       (flags & LS_BWD_POSE_ONLY) ? 1 : 0, s);
+                       (flags & LS_BWD_POSE_ONLY) ? 1 : 0, at<char>(bins->work, L.queues), s);
   return hip_check("ls_render_bwd_tiles");
 }
 

@@ -21,15 +21,18 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s);
 
+// Persistent compositing kernels; queues = kTileQueueBytes of zero-initialised
+// workspace (left zeroed by every launch; one launch at a time per workspace).
+constexpr size_t kTileQueueBytes = 3 * 9 * 128;
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
-                          float* alpha, float* Tf, int32_t* nl, hipStream_t s);
+                          float* alpha, float* Tf, int32_t* nl, void* queues, hipStream_t s);
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,
                           const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
                           const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
-                          float* tile_part, int pose_only, hipStream_t s);
+                          float* tile_part, int pose_only, void* queues, hipStream_t s);
 
 // Registration helpers (reg_kernels.hip).
 struct ViewOpt {

@@ -41,34 +41,38 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, np.float64), q))
 
 
-def run_plain(pairs, iters=200, loss="tracking"):
+def run_plain(pairs, iters=200, loss="tracking", exit_rel_tol=0.0, exit_patience=0):
     """One pair at a time through ls_register_pair; latency of pair k counts
     from the start of the run (all requests present at t = 0)."""
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results, done = [], []
     for p in pairs:
-        results.append(REG.register_pair(*p["args"], params=REG.default_params(iters, loss=loss)))
+        results.append(REG.register_pair(*p["args"], params=REG.default_params(
+            iters, loss=loss, exit_rel_tol=exit_rel_tol, exit_patience=exit_patience)))
         done.append(time.perf_counter() - t0)
     total = time.perf_counter() - t0
     return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(done, 50), p99_s=_pct(done, 99),
-                **_errors(results, pairs)), results
+                mean_iters=float(np.mean([r["iters"] for r in results])), **_errors(results, pairs)), results
 
 
-def run_batched(pairs, iters=200, loss="tracking", chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30):
+def run_batched(pairs, iters=200, loss="tracking", chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30,
+                exit_rel_tol=0.0, exit_patience=0):
     """Every pair submitted at t = 0 to one server."""
     from .serve import Server
 
     with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters, use_graphs=use_graphs) as sv:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tickets = [sv.submit(*p["args"], params=REG.default_params(iters, loss=loss)) for p in pairs]
+        tickets = [sv.submit(*p["args"], params=REG.default_params(iters, loss=loss, exit_rel_tol=exit_rel_tol,
+                                                                   exit_patience=exit_patience)) for p in pairs]
         results = [sv.wait(t) for t in tickets]
         total = time.perf_counter() - t0
         st = sv.stats()
     lat = [r["times"]["total"] for r in results]
     return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(lat, 50), p99_s=_pct(lat, 99),
-                epochs=st["epochs"], graph_replays=st["graph_replays"], **_errors(results, pairs)), results
+                epochs=st["epochs"], graph_replays=st["graph_replays"],
+                mean_iters=float(np.mean([r["iters"] for r in results])), **_errors(results, pairs)), results
 
 
 def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget=200 << 30, max_slots=64,
@@ -137,6 +141,8 @@ def main(argv=None):
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--mode", choices=["plain", "batched", "both"], default="plain")
     ap.add_argument("--loss", choices=["tracking", "l1"], default="tracking")
+    ap.add_argument("--exit", type=float, nargs=2, default=[0.0, 0], metavar=("REL_TOL", "PATIENCE"),
+                    help="per-view early exit (0 0: off)")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if a.workload == "single":
@@ -157,8 +163,8 @@ def main(argv=None):
                     res, _ = run_stream(specs, pairs, iters=a.iters, loss=a.loss, max_active_pixels=cap)
             else:
                 run = run_plain if mode == "plain" else run_batched
-                res, _ = run(pairs, iters=a.iters, loss=a.loss)
-            extra = dict(rate=a.rate, requests=a.requests) if a.workload == "stream" else {}
+                res, _ = run(pairs, iters=a.iters, loss=a.loss, exit_rel_tol=a.exit[0], exit_patience=int(a.exit[1]))
+            extra = dict(rate=a.rate, requests=a.requests) if a.workload == "stream" else dict(exit=a.exit)
             if mode == "batched" and a.workload == "stream":
                 extra["max_active_pixels"] = cap
             print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters, **extra,
