@@ -158,8 +158,8 @@ ls_status ls_project(const ls_batch* b, const float* pose, const ls_projected* o
  *           instances required I, 0}
  *   work    workspace of ls_batch_info.workspace_bytes (256-byte aligned),
  *           zero-filled by the caller before its first use; also used by
- *           ls_render_fwd and ls_render_bwd (the persistent compositing
- *           kernels keep their tile-queue counters here and leave them zero). */
+ *           ls_render_bwd (the persistent backward kernels keep their
+ *           tile-queue counters here and leave them zero). */
 typedef struct {
   int64_t capacity;
   uint32_t* tile_of;

@@ -346,10 +346,9 @@ ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins*
   if ((st = check_projected(p)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
   if (!out || !out->rgb || !out->depth || !out->alpha || !out->T_final || !out->n_last)
     return fail(LS_ERR_INVALID, "ls_image has NULL members");
-  const Layout L = layout_of(b, bins->capacity);
   const float zero[3] = {0.f, 0.f, 0.f};
   launch_composite_fwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
-                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, at<char>(bins->work, L.queues), s);
+                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, s);
   return hip_check("ls_render_fwd");
 }
 

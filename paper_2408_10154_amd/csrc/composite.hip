@@ -4,8 +4,8 @@
 // Splat records of a tile's list are staged through LDS in chunks of 256;
 // every lane reads the same record (LDS broadcast).  The forward stops a
 // block's chunk loop once every pixel of the tile has terminated.  The
-// compositing kernels are persistent: a grid that fills the GPU once pulls
-// tiles from device-side queues.
+// backward kernels also exist in a persistent form: a grid that fills the
+// GPU once pulls tiles from device-side queues.
 #include "common.h"
 #include "kernels.h"
 
@@ -314,24 +314,6 @@ __global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restri
   composite_fwd_tile(jobs, tile_off, R, T_total, rec, items, range, bg0, bg1, bg2, out_rgb, out_depth, out_alpha,
                      out_T, out_n, tile);
 }
-
-__global__ __launch_bounds__(kBlock) void k_composite_fwd_persistent(const JobDev* __restrict__ jobs,
-    const int32_t* __restrict__ tile_off, int R, int T_total, const float4* __restrict__ rec,
-    const int32_t* __restrict__ items, const int32_t* __restrict__ range, float bg0, float bg1, float bg2,
-    float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_alpha,
-    float* __restrict__ out_T, int32_t* __restrict__ out_n, TileQueue* __restrict__ queue, int nstatic) {
-  __shared__ int s_tile;
-  bool first = true;
-  uint32_t dead = 0;
-  for (;;) {
-    const int tile = claim_tile(queue, T_total, nstatic, first, dead, &s_tile);
-    if (tile < 0) break;
-    composite_fwd_tile(jobs, tile_off, R, T_total, rec, items, range, bg0, bg1, bg2, out_rgb, out_depth, out_alpha,
-                       out_T, out_n, tile);
-  }
-  release_queue(queue);
-}
-
 
 // Sum over each 16-lane row of the wave; every lane of a row gets its row sum.
 __device__ __forceinline__ float row_sum16(float v) {
@@ -840,16 +822,17 @@ void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int
                      reinterpret_cast<unsigned long long*>(stats));
 }
 
-// Grid of a compositing kernel.  With more than 4 tiles per resident block
-// (residency = occupancy x compute units, as the runtime reports it) the
-// persistent kernel runs: nstatic = the resident blocks get the statically
-// mapped first tiles and then claim from the counters, and one more block per
-// compute unit fills slots the runtime's estimate leaves empty (such blocks
-// only claim, so if they cannot be resident they start late, find the queues
-// drained and exit).  With fewer tiles the plain one-block-per-tile kernel
-// is faster (measured on the 1200x680 render loop: fwd 0.130 vs 0.146 ms),
-// and with many the queues are (one 16-view registration iteration: 8.5 %
-// faster).  The residency is queried once per (kernel, device) and cached.
+// Grid of a backward compositing kernel.  With more than 4 tiles per
+// resident block (residency = occupancy x compute units, as the runtime
+// reports it) the persistent kernel runs: nstatic = the resident blocks get
+// the statically mapped first tiles and then claim from the counters, and
+// one more block per compute unit fills slots the runtime's estimate leaves
+// empty (such blocks only claim, so if they cannot be resident they start
+// late, find the queues drained and exit).  With fewer tiles the plain
+// one-block-per-tile kernel is faster (the loop-and-claim wrapper cost 4-5 %
+// on the 1200x680 render loop), with many the queues are (one 16-view
+// registration iteration: 8.5 % faster).  The residency is queried once per
+// (kernel, device) and cached.
 static inline int xcd_grid(int total) { return 8 * ((total + 7) / 8); }
 
 struct PersistentGrid {
@@ -858,7 +841,7 @@ struct PersistentGrid {
 };
 static PersistentGrid persistent_grid(int which, const void* kernel, int T) {
   static std::mutex mu;
-  static int cache[3][64][2] = {};
+  static int cache[2][64][2] = {};
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) dev = 0;
   int resident, cus;
@@ -884,17 +867,14 @@ static PersistentGrid persistent_grid(int which, const void* kernel, int T) {
 
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
-                          float* alpha, float* Tf, int32_t* nl, void* queues, hipStream_t s) {
+                          float* alpha, float* Tf, int32_t* nl, hipStream_t s) {
   if (T <= 0) return;
-  const float4* rec4 = reinterpret_cast<const float4*>(rec);
-  const PersistentGrid g = persistent_grid(0, reinterpret_cast<const void*>(k_composite_fwd_persistent), T);
-  if (g.on)
-    hipLaunchKernelGGL(k_composite_fwd_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4,
-                       items, range, bg[0], bg[1], bg[2], rgb, depth, alpha, Tf, nl,
-                       reinterpret_cast<TileQueue*>(queues) + 0, g.nstatic);
-  else
-    hipLaunchKernelGGL(k_composite_fwd, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, items, range,
-                       bg[0], bg[1], bg[2], rgb, depth, alpha, Tf, nl);
+  // always one block per tile: a forward tile is short, and claiming tiles
+  // from the queues cost more than it balanced (registration iteration A/B:
+  // 1.3 % slower persistent)
+  hipLaunchKernelGGL(k_composite_fwd, dim3(xcd_grid(T)), dim3(kBlock), 0, s, jobs, tile_off, R, T,
+                     reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], rgb, depth, alpha, Tf,
+                     nl);
 }
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
@@ -906,21 +886,21 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const float4* aux4 = reinterpret_cast<const float4*>(aux);
   if (pose_only) {
-    const PersistentGrid g = persistent_grid(2, reinterpret_cast<const void*>(k_composite_bwd_pose_persistent), T);
+    const PersistentGrid g = persistent_grid(1, reinterpret_cast<const void*>(k_composite_bwd_pose_persistent), T);
     if (g.on)
       hipLaunchKernelGGL(k_composite_bwd_pose_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T,
                          rec4, aux4, pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha,
-                         up_scale, tile_part, reinterpret_cast<TileQueue*>(queues) + 2, g.nstatic);
+                         up_scale, tile_part, reinterpret_cast<TileQueue*>(queues) + 1, g.nstatic);
     else
       hipLaunchKernelGGL(k_composite_bwd_pose, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, aux4,
                          pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
                          tile_part);
   } else {
-    const PersistentGrid g = persistent_grid(1, reinterpret_cast<const void*>(k_composite_bwd_persistent), T);
+    const PersistentGrid g = persistent_grid(0, reinterpret_cast<const void*>(k_composite_bwd_persistent), T);
     if (g.on)
       hipLaunchKernelGGL(k_composite_bwd_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4,
                          items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d,
-                         reinterpret_cast<TileQueue*>(queues) + 1, g.nstatic);
+                         reinterpret_cast<TileQueue*>(queues) + 0, g.nstatic);
     else
       hipLaunchKernelGGL(k_composite_bwd, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, items, range,
                          bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d);

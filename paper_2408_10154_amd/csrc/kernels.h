@@ -21,12 +21,14 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s);
 
-// Persistent compositing kernels; queues = kTileQueueBytes of zero-initialised
-// workspace (left zeroed by every launch; one launch at a time per workspace).
-constexpr size_t kTileQueueBytes = 3 * 9 * 128;
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
-                          float* alpha, float* Tf, int32_t* nl, void* queues, hipStream_t s);
+                          float* alpha, float* Tf, int32_t* nl, hipStream_t s);
+
+// Backward compositing (persistent when a launch has many tiles per resident
+// block); queues = kTileQueueBytes of zero-initialised workspace (left zeroed
+// by every launch; one launch at a time per workspace).
+constexpr size_t kTileQueueBytes = 2 * 9 * 128;
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,
