@@ -321,6 +321,10 @@ __device__ __forceinline__ float row_sum16(float v) {
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
   v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
+  // Keep the last add in every lane: callers store the sum from one lane per
+  // row, and sinking the add into that branch splits each fused DPP add into
+  // a DPP move plus an add (an empty asm that reads and writes v, no code).
+  asm volatile("" : "+v"(v));
   return v;
 }
 
