@@ -500,6 +500,10 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
         g[7] = wgt * px.gR;
         g[8] = wgt * px.gG;
         g[9] = wgt * px.gB;
+        // materialise the ten terms first, so that the first DPP step of each
+        // folds into one add instead of being re-associated into its products
+#pragma unroll
+        for (int q = 0; q < kGrad2D; ++q) asm volatile("" : "+v"(g[q]));
 #pragma unroll
         for (int q = 0; q < kGrad2D; ++q) g[q] = row_sum16(g[q]);  // interleaving measured 2 % slower here
         if (lead) {
@@ -652,6 +656,8 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
         g[3] = ds * dx * dy;
         g[4] = 0.5f * ds * dy * dy;
         g[5] = wgt * px.gD;
+#pragma unroll
+        for (int q = 0; q < kPoseRow; ++q) asm volatile("" : "+v"(g[q]));  // see the full-mode kernel
         row_sum16_n<kPoseRow>(g);
       }
       if (lead) {
