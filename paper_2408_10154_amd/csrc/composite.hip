@@ -259,8 +259,8 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
     build_wave_lists(m, e < end, slist, scnt, swc);
     // the band's list is wave-uniform: scalar loop control, branch-free body
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
-    for (int jj = 0; jj < cw; ++jj) {
-      if (__ballot(!done) == 0ull) break;  // whole wave finished
+    uint64_t alive = __ballot(!done);  // lanes still compositing (wave-uniform)
+    for (int jj = 0; jj < cw && alive != 0ull; ++jj) {
       const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
       const float4 a = s0[j];
       const float4 b = s1[j];
@@ -274,6 +274,7 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
         done = true;
         nlast = chunk + j - start;
       }
+      alive &= ~__ballot(stop);
       const bool use = hit && !stop;
       if (__ballot(use) != 0ull) {
         const float4 col = s2[j];
