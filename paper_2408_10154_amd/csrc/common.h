@@ -13,14 +13,15 @@ constexpr int kBlock = 256;         // one 16x16 tile per block, 4 wave64
 constexpr int kSortThreads = 256;   // radix sort block
 constexpr int kSortItems = 16;      // most items per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
-constexpr int64_t kSortBlocksTarget = 512;  // blocks a sort pass aims for (fills the chip)
+constexpr int64_t kSortBlocksTarget = 1024;  // blocks a sort pass aims for (fills the chip)
 
 // Rounds of kSortThreads items per sort block for n keys: as few as keep
-// about kSortBlocksTarget blocks busy, between 1 and kSortItems.  Host and
+// about kSortBlocksTarget blocks busy, between 2 and kSortItems (one round
+// per block measured slower: the per-block set-up then dominates).  Host and
 // device use it for the launch grids and for the workspace layout.
 __host__ __device__ inline int sort_rounds(int64_t n) {
   const int64_t r = (n + kSortBlocksTarget * kSortThreads - 1) / (kSortBlocksTarget * kSortThreads);
-  return (int)(r < 1 ? 1 : (r > kSortItems ? kSortItems : r));
+  return (int)(r < 2 ? 2 : (r > kSortItems ? kSortItems : r));
 }
 __host__ __device__ inline int64_t sort_blocks(int64_t n) {
   const int64_t per = (int64_t)sort_rounds(n) * kSortThreads;
