@@ -63,8 +63,10 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.dv0 = take(4 * M);
   L.dk1 = take(4 * M);
   L.dv1 = take(4 * M);
-  L.hist = take(4 * 256 * std::max<int64_t>(std::max(nbd, nbt), 1));
-  L.bsum = take(4 * (nbd + 8 + 264));  // block sums, then 256 digit totals
+  L.hist = take(4 * std::max<int64_t>(std::max<int64_t>((int64_t)(1 << kDepthDigitBits) * nbd,
+                                                         (int64_t)(1 << kTileDigitBits) * nbt),
+                                       256));
+  L.bsum = take(4 * (nbd + 8 + kMaxSortBins + 8));  // block sums, then the digit totals
   L.tk = take(4 * cap);
   L.tv = take(4 * cap);
   L.g2d = take(4 * (size_t)kGrad2D * M);
@@ -248,7 +250,7 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
   b->nblk_pix = b->pblk_off[R];
   int bits = 0;
   while (bits < 32 && ((int64_t)1 << bits) < (int64_t)b->T) ++bits;
-  b->tile_passes = (bits + 7) / 8;
+  b->tile_passes = (bits + kTileDigitBits - 1) / kTileDigitBits;
   if (hipGetDevice(&b->device) != hipSuccess) {
     delete b;
     return fail(LS_ERR_HIP, "hipGetDevice failed");

@@ -1,4 +1,4 @@
-// Tile binning on gfx950: depth keys, LSD radix sort (8-bit digits, stable),
+// Tile binning on gfx950: depth keys, LSD radix sorts (stable; 8-bit digits),
 // count scan, instance emission in depth order, tile ranges.
 //
 // Order of the final list: (tile, FP32 depth bits, item).  It is produced as
@@ -34,13 +34,16 @@ __device__ __forceinline__ int sort_count(const int32_t* n_dev, int64_t n_static
   return (int)n;
 }
 
-// Per-block digit histogram, stored digit-major: hist[d * nblocks + block].
+// Per-block digit histogram of kBits-bit digits, stored digit-major:
+// hist[d * nblocks + block].
+template <int kBits>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys, const int32_t* n_dev,
                                                             int64_t n_static, int64_t cap, int shift,
                                                             uint32_t* __restrict__ hist, int nblocks, int rounds) {
-  __shared__ uint32_t h[256];
+  constexpr int kBins = 1 << kBits;
+  __shared__ uint32_t h[kBins];
   const int n = sort_count(n_dev, n_static, cap);
-  h[threadIdx.x] = 0;
+  for (int i = threadIdx.x; i < kBins; i += kSortThreads) h[i] = 0;
   __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (base < n) {
@@ -49,11 +52,11 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
     for (int i = 0; i < rounds; ++i) {
       const int64_t idx = base + i * kSortThreads + threadIdx.x;
       const bool valid = idx < n;
-      const uint32_t d = valid ? (keys[idx] >> shift) & 255u : 0u;
+      const uint32_t d = valid ? (keys[idx] >> shift) & (uint32_t)(kBins - 1) : 0u;
       // aggregate equal digits within the wave before touching LDS
       uint64_t peers = __ballot(valid);
 #pragma unroll
-      for (int b = 0; b < 8; ++b) {
+      for (int b = 0; b < kBits; ++b) {
         const bool bit = (d >> b) & 1u;
         const uint64_t m = __ballot(bit);
         peers &= bit ? m : ~m;
@@ -62,7 +65,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
     }
   }
   __syncthreads();
-  hist[(int64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
+  for (int i = threadIdx.x; i < kBins; i += kSortThreads) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns
@@ -101,27 +104,51 @@ __global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, 
   if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-// Stable scatter of one 8-bit digit pass.  Each block first turns the digit
-// totals into digit bases (one block-wide scan of 256 words, cheaper than a
-// launch of its own), adds its scanned row entries, then takes its items in
-// rounds of 256 in index order; within a round, ranks come from wave-level
-// digit matching and per-wave counts combined in wave order.
+// Stable scatter of one kBits-bit digit pass.  Each block first turns the
+// digit totals into digit bases (a block-wide scan, cheaper than a launch of
+// its own) and adds its scanned row entries; then it takes its items in rounds
+// of 256 in index order.  Within a round an item's position is its digit's
+// base + the count of equal digits in earlier waves of the round + its rank
+// among equal digits in its own wave (ballot matching).  Only the one leader
+// lane per (wave, digit) present writes a count, adds it to the base and
+// clears it again, so a round costs work in proportion to its items, not to
+// the number of digits, and three barriers.
+template <int kBits>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
                                                                uint32_t* __restrict__ kout, uint32_t* __restrict__ vout,
                                                                const int32_t* n_dev, int64_t n_static, int64_t cap,
                                                                int shift, const uint32_t* __restrict__ hist, int nblocks,
                                                                const uint32_t* __restrict__ digit_total, int rounds) {
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[4][256];
+  constexpr int kBins = 1 << kBits;
+  constexpr int kPer = kBins / kSortThreads;  // digits per thread in the set-up
+  static_assert(kBins % kSortThreads == 0, "digit count must be a multiple of the block size");
+  __shared__ uint32_t base[kBins];
+  __shared__ uint32_t wcnt[4][kBins];
   __shared__ uint32_t wsum[4];
   const int n = sort_count(n_dev, n_static, cap);
   const int64_t bbase = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (bbase >= n) return;  // uniform for the block
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t all;
-  const uint32_t dbase = block_excl_scan(digit_total[tid], wsum, &all);
-  base[tid] = dbase + hist[(int64_t)tid * nblocks + blockIdx.x];
+  {
+    uint32_t loc[kPer];
+    uint32_t sum = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      loc[k] = digit_total[tid * kPer + k];
+      sum += loc[k];
+    }
+    uint32_t all;
+    uint32_t run = block_excl_scan(sum, wsum, &all);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = tid * kPer + k;
+      base[d] = run + hist[(int64_t)d * nblocks + blockIdx.x];
+      run += loc[k];
+      wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0u;
+    }
+  }
+  __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   for (int round = 0; round < rounds; ++round) {
     const int64_t rbase = bbase + (int64_t)round * kSortThreads;
@@ -130,35 +157,30 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
     const bool valid = idx < n;
     const uint32_t key = valid ? kin[idx] : 0u;
     const uint32_t val = valid ? vin[idx] : 0u;
-    const uint32_t d = (key >> shift) & 255u;
+    const uint32_t d = (key >> shift) & (uint32_t)(kBins - 1);
     uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < 8; ++b) {
+    for (int b = 0; b < kBits; ++b) {
       const bool bit = (d >> b) & 1u;
       const uint64_t m = __ballot(bit);
       peers &= bit ? m : ~m;
     }
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    // clear this wave's row, then publish the per-digit count from the leader
-#pragma unroll
-    for (int k = 0; k < 4; ++k) wcnt[w][lane * 4 + k] = 0;
-    __builtin_amdgcn_wave_barrier();
-    if (valid && rank == 0) wcnt[w][d] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    const uint32_t c0 = wcnt[0][tid], c1 = wcnt[1][tid], c2 = wcnt[2][tid], c3 = wcnt[3][tid];
-    __syncthreads();
-    wcnt[0][tid] = 0;
-    wcnt[1][tid] = c0;
-    wcnt[2][tid] = c0 + c1;
-    wcnt[3][tid] = c0 + c1 + c2;
+    const bool leader = valid && rank == 0;
+    const uint32_t cnt = (uint32_t)__popcll(peers);
+    if (leader) wcnt[w][d] = cnt;
     __syncthreads();
     if (valid) {
-      const uint32_t pos = base[d] + wcnt[w][d] + rank;
+      uint32_t pos = base[d] + rank;
+      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
       kout[pos] = key;
       vout[pos] = val;
     }
     __syncthreads();
-    base[tid] += c0 + c1 + c2 + c3;
+    if (leader) {
+      atomicAdd(&base[d], cnt);
+      wcnt[w][d] = 0u;
+    }
     __syncthreads();
   }
 }
@@ -297,16 +319,17 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
   hipLaunchKernelGGL(k_fill_i32, dim3((unsigned)blocks), dim3(256), 0, s, p, n, v);
 }
 
-// One LSD pass: histogram, per-digit row scan (row totals to digit_total),
-// scatter (which scans the 256 digit totals itself).
+// One LSD pass of kBits-bit digits: histogram, per-digit row scan (row totals
+// to digit_total), scatter (which scans the digit totals itself).
+template <int kBits>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const int32_t* n_dev,
                        int64_t n_static, int64_t cap, int shift, uint32_t* hist, uint32_t* digit_total, int nblocks,
                        int rounds, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_hist, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift, hist,
-                     nblocks, rounds);
-  hipLaunchKernelGGL(k_scan_rows, dim3(256), dim3(256), 0, s, hist, (int64_t)nblocks, digit_total);
-  hipLaunchKernelGGL(k_sort_scatter, dim3(nblocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_dev, n_static,
-                     cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_total, rounds);
+  hipLaunchKernelGGL(k_sort_hist<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift,
+                     hist, nblocks, rounds);
+  hipLaunchKernelGGL(k_scan_rows, dim3(1 << kBits), dim3(256), 0, s, hist, (int64_t)nblocks, digit_total);
+  hipLaunchKernelGGL(k_sort_scatter<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_dev,
+                     n_static, cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_total, rounds);
 }
 
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
@@ -315,11 +338,11 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s) {
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const int rd = sort_rounds(M), nbd = (int)sort_blocks(M);
-  uint32_t* digit_base = bsum + nbd + 8;  // 256 digit totals after the block sums
+  uint32_t* digit_base = bsum + nbd + 8;  // digit totals (up to kMaxSortBins) after the block sums
   hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec4, tiles, M, dk0, dv0);
   uint32_t *ka = dk0, *va = dv0, *kb = dk1, *vb = dv1;
-  for (int shift = 0; shift < 32; shift += 8) {
-    radix_pass(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, rd, s);
+  for (int shift = 0; shift < 32; shift += kDepthDigitBits) {
+    radix_pass<kDepthDigitBits>(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, rd, s);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
@@ -340,7 +363,7 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                        reinterpret_cast<int32_t*>(ev));
   const int rt = sort_rounds(cap), nbt = (int)sort_blocks(cap);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {
-    radix_pass(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, digit_base, nbt, rt, s);
+    radix_pass<kTileDigitBits>(ek, ev, ok, ov, count, 0, cap, kTileDigitBits * p, hist, digit_base, nbt, rt, s);
     std::swap(ek, ok);
     std::swap(ev, ov);
   }
