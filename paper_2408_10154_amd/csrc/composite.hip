@@ -329,25 +329,49 @@ __device__ __forceinline__ float row_sum16(float v) {
   return v;
 }
 
-// row_sum16 of N values at once, one DPP step of every value before the next
-// step of any: each step's operands were written N instructions earlier, so
-// the VALU-write -> DPP-read wait states are filled with useful work instead
-// of s_nop.
+// Lane exchanges of gfx950 that trade halves of two registers:
+// permlane32_swap gives x the lower 32 lanes of y in place of its upper 32,
+// permlane16_swap gives x the even 16-lane rows of y in place of its odd rows
+// (and y what x gave up).  Adding the two results sums each value over lane
+// pairs 32 (or 16) apart while packing two values into one register.
+__device__ __forceinline__ float swap32_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+__device__ __forceinline__ float swap16_sum(float x, float y) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(x), __float_as_uint(y), false, false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+// Slot of the value held by 16-lane row r after wave_sums (see below).
+__device__ __forceinline__ int wave_sum_slot(int lane) {
+  const int r = lane >> 4;
+  return ((r & 1) << 1) | (r >> 1);
+}
+
+// Sums of N values (N even) over the 64 lanes of the wave, by a transposing
+// reduction: two 32-lane swaps and adds pack values 2k, 2k+1 into register k
+// (half a wave each), two 16-lane swaps and adds pack four values into one
+// register (a row each), and a row sum (DPP) finishes each register.  N values
+// cost N/2 + 2 ceil(N/4) swaps and 4 ceil(N/4) DPP adds instead of 4 N DPP adds
+// for row sums alone.  Every lane of row r of out[i] holds the sum of value
+// 4 i + wave_sum_slot(r); when N/2 is odd the last register is paired with
+// itself and its rows 1 and 3 repeat rows 0 and 2 (slots >= N, to be ignored).
+// The whole wave must be active.
 template <int N>
-__device__ __forceinline__ void row_sum16_n(float* v) {
+__device__ __forceinline__ void wave_sums(const float* g, float* out) {
+  static_assert(N % 2 == 0, "an even number of values");
+  constexpr int H = N / 2, O = (H + 1) / 2;
+  float h[H];
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v[q]), 0xB1, 0xF, 0xF, true));
+  for (int k = 0; k < H; ++k) h[k] = swap32_sum(g[2 * k], g[2 * k + 1]);
 #pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v[q]), 0x4E, 0xF, 0xF, true));
-#pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v[q]), 0x141, 0xF, 0xF, true));
-#pragma unroll
-  for (int q = 0; q < N; ++q) v[q] += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v[q]), 0x140, 0xF, 0xF, true));
+  for (int i = 0; i < O; ++i) out[i] = row_sum16(swap16_sum(h[2 * i], h[2 * i + 1 < H ? 2 * i + 1 : 2 * i]));
 }
 
 constexpr int kBwdChunk = 32;   // list entries staged per round (full mode)
-constexpr int kPartRow = kGrad2D;          // floats per row partial
-constexpr int kPartStride = 16 * kPartRow + 4;  // floats per entry: 16 row partials, padded against bank conflicts
+constexpr int kWaveSlots = 4 * ((kGrad2D / 2 + 1) / 2);  // floats per wave partial (wave_sums slots)
+constexpr int kPartStride = 4 * kWaveSlots + 1;         // floats per entry: 4 wave partials, odd against bank conflicts
 
 // Backward.  Per pixel, walking the list from n_last - 1 down to 0 with the
 // transmittance recovered as T_i = T_{i+1} / (1 - alpha_i) and the running
@@ -463,7 +487,7 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row = w * 4 + (lane >> 4);  // 0..15, one 16-pixel row of the tile
+  const int wslot = w * kWaveSlots + wave_sum_slot(lane);  // where this lane's row stores its wave sums
   const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
   if (threadIdx.x == 0) smax = 0;
@@ -480,7 +504,7 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     for (int jj = cw - 1; jj >= 0; --jj) {
       const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
-      float* pj = part + j * kPartStride + row * kPartRow;
+      float* pj = part + j * kPartStride + wslot;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;  // list position
       const float4 a = s0[j];
@@ -490,48 +514,65 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
       const bool act = bwd_step(k < px.nl, a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds,
                                 dop);
       if (__ballot(act) != 0ull) {
+        // per-pixel terms whose sums give the ten gradients; the conic factors
+        // of dL/du, dL/dv and the halves of dL/dA, dL/dC are applied once per
+        // entry after the sums
         float g[kGrad2D];
-        g[0] = -ds * (a.z * dx + a.w * dy);  // dL/du
-        g[1] = -ds * (a.w * dx + b.x * dy);  // dL/dv
-        g[2] = 0.5f * ds * dx * dx;          // dL/dA
-        g[3] = ds * dx * dy;                 // dL/dB
-        g[4] = 0.5f * ds * dy * dy;          // dL/dC
-        g[5] = dop;                          // dL/d opacity
+        g[0] = ds * dx;
+        g[1] = ds * dy;
+        g[2] = g[0] * dx;
+        g[3] = g[0] * dy;
+        g[4] = g[1] * dy;
+        g[5] = dop;
         g[6] = wgt * px.gD;
         g[7] = wgt * px.gR;
         g[8] = wgt * px.gG;
         g[9] = wgt * px.gB;
-        // materialise the ten terms first, so that the first DPP step of each
-        // folds into one add instead of being re-associated into its products
-#pragma unroll
-        for (int q = 0; q < kGrad2D; ++q) asm volatile("" : "+v"(g[q]));
-#pragma unroll
-        for (int q = 0; q < kGrad2D; ++q) g[q] = row_sum16(g[q]);  // interleaving measured 2 % slower here
+        float out[kWaveSlots / 4];
+        wave_sums<kGrad2D>(g, out);
         if (lead) {
 #pragma unroll
-          for (int q = 0; q < kGrad2D; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(g[q], g[q + 1]);
+          for (int i = 0; i < kWaveSlots / 4; ++i) pj[4 * i] = out[i];
         }
       } else if (lead) {
 #pragma unroll
-        for (int q = 0; q < kGrad2D; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(0.f, 0.f);
+        for (int i = 0; i < kWaveSlots / 4; ++i) pj[4 * i] = 0.f;
       }
     }
     __syncthreads();
     {
-      // 8 threads per entry; thread (j, t) sums values t, t + 8 over the 16 rows in order;
-      // rows of bands that did not visit the entry hold stale values: skip them
+      // 8 threads per entry, each summing its values over the waves (bands)
+      // that reached the entry, in wave order; the partials of other waves
+      // are stale and skipped.  Thread 0 forms dL/du, dL/dv from the sums of
+      // ds dx and ds dy with the conic (A, B, C); threads 1..7 take values
+      // 2..9 (the last thread two of them).
       constexpr int kPer = kBlock / kBwdChunk;
+      static_assert(kPer == 8 && kGrad2D == 10, "value split assumes 8 threads per entry and 10 values");
       const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
       const uint32_t mj = j < cnt ? smask[j] : 0u;
       if (mj != 0u) {
         float* dst = g2d + (int64_t)sit[j] * kGrad2D;
         const float* pj = part + j * kPartStride;
-        for (int q = t; q < kGrad2D; q += kPer) {
-          float s = 0.f;
+        auto band_sum = [&](int q) {
+          float v = 0.f;
 #pragma unroll
-          for (int r2 = 0; r2 < 16; ++r2)
-            if ((mj >> (r2 >> 2)) & 1u) s += pj[r2 * kPartRow + q];
-          if (s != 0.f) atomic_add_f32(dst + q, s);
+          for (int b2 = 0; b2 < 4; ++b2)
+            if ((mj >> b2) & 1u) v += pj[b2 * kWaveSlots + q];
+          return v;
+        };
+        auto put = [&](int q, float v) {
+          if (v != 0.f) atomic_add_f32(dst + q, v);
+        };
+        if (t == 0) {
+          const float sx = band_sum(0), sy = band_sum(1);
+          const float cA = s0[j].z, cB = s0[j].w, cC = s1[j].x;
+          put(0, -(cA * sx + cB * sy));
+          put(1, -(cB * sx + cC * sy));
+        } else {
+          const int q = t + 1;
+          const float v = band_sum(q);
+          put(q, (q == 2 || q == 4) ? 0.5f * v : v);
+          if (t == kPer - 1) put(kGrad2D - 1, band_sum(kGrad2D - 1));
         }
       }
     }
@@ -588,7 +629,8 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDe
 // so the pose gradient is deterministic and independent of the other renders.
 constexpr int kPoseChunk = 64;                    // entries staged per round
 constexpr int kPoseRow = 6;                       // du, dv, dA, dB, dC, d(depth weight)
-constexpr int kPoseStride = 16 * kPoseRow + 4;    // floats per entry, padded against bank conflicts
+constexpr int kPoseSlots = 4 * ((kPoseRow / 2 + 1) / 2);  // floats per wave partial (wave_sums slots)
+constexpr int kPoseStride = 4 * kPoseSlots + 1;   // floats per entry: 4 wave partials, odd against bank conflicts
 constexpr int kPoseQueue = kBlock;                // queued entries per Jacobian round
 
 __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict__ jobs,
@@ -621,7 +663,7 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int row = w * 4 + (lane >> 4);
+  const int wslot = w * kPoseSlots + wave_sum_slot(lane);
   const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
   if (threadIdx.x == 0) smax = 0;
@@ -640,7 +682,7 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     for (int jj = cw - 1; jj >= 0; --jj) {
       const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
-      float* pj = part + j * kPoseStride + row * kPoseRow;
+      float* pj = part + j * kPoseStride + wslot;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;
       const float4 a = s0[j];
@@ -649,38 +691,48 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
       float wgt, ds, dop;
       const bool act = bwd_step(k < px.nl, a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds,
                                 dop);
-      float g[kPoseRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      if (__ballot(act) != 0ull) {
-        g[0] = -ds * (a.z * dx + a.w * dy);
-        g[1] = -ds * (a.w * dx + b.x * dy);
-        g[2] = 0.5f * ds * dx * dx;
-        g[3] = ds * dx * dy;
-        g[4] = 0.5f * ds * dy * dy;
-        g[5] = wgt * px.gD;
+      float out[kPoseSlots / 4];
 #pragma unroll
-        for (int q = 0; q < kPoseRow; ++q) asm volatile("" : "+v"(g[q]));  // see the full-mode kernel
-        row_sum16_n<kPoseRow>(g);
+      for (int i = 0; i < kPoseSlots / 4; ++i) out[i] = 0.f;
+      if (__ballot(act) != 0ull) {
+        // as in the full-mode kernel: conic factors and halves after the sums
+        float g[kPoseRow];
+        g[0] = ds * dx;
+        g[1] = ds * dy;
+        g[2] = g[0] * dx;
+        g[3] = g[0] * dy;
+        g[4] = g[1] * dy;
+        g[5] = wgt * px.gD;
+        wave_sums<kPoseRow>(g, out);
       }
       if (lead) {
 #pragma unroll
-        for (int q = 0; q < kPoseRow; q += 2) reinterpret_cast<float2*>(pj)[q >> 1] = make_float2(g[q], g[q + 1]);
+        for (int i = 0; i < kPoseSlots / 4; ++i) pj[4 * i] = out[i];
       }
     }
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
-      // entry j: its sums over the rows of the bands it reaches, into queue slot nq + j
+      // entry j: its sums over the waves (bands) it reaches, in wave order,
+      // turned into the six image-space gradients, into queue slot nq + j
       const int j = threadIdx.x;
       const uint32_t mj = smask[j];
       const float* pj = part + j * kPoseStride;
       float g6[kPoseRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       if (mj != 0u) {
+        float sum[kPoseRow] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-        for (int r2 = 0; r2 < 16; ++r2) {
-          if (!((mj >> (r2 >> 2)) & 1u)) continue;
-          const float* pr2 = pj + r2 * kPoseRow;
+        for (int b2 = 0; b2 < 4; ++b2) {
+          if (!((mj >> b2) & 1u)) continue;
 #pragma unroll
-          for (int q = 0; q < kPoseRow; ++q) g6[q] += pr2[q];
+          for (int q = 0; q < kPoseRow; ++q) sum[q] += pj[b2 * kPoseSlots + q];
         }
+        const float cA = s0[j].z, cB = s0[j].w, cC = s1[j].x;
+        g6[0] = -(cA * sum[0] + cB * sum[1]);
+        g6[1] = -(cB * sum[0] + cC * sum[1]);
+        g6[2] = 0.5f * sum[2];
+        g6[3] = sum[3];
+        g6[4] = 0.5f * sum[4];
+        g6[5] = sum[5];
       }
       const int slot = nq + j;
       qit[slot] = mj != 0u ? sit[j] : -1;
@@ -716,10 +768,14 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
         pose_contrib(p, Sc, Rd, td, dp, Gm, pc);
       }
       // fixed-order reduction of this round over the block
+      {
+        static_assert(kPoseAcc % 4 == 0, "pose sums fill whole slot groups");
+        float out[kPoseAcc / 4];
+        wave_sums<kPoseAcc>(pc, out);
+        if ((lane & 15) == 0) {
 #pragma unroll
-      for (int k = 0; k < kPoseAcc; ++k) {
-        const float v = wave_sum(pc[k]);
-        if (lane == 0) wred[w][k] = v;
+          for (int i = 0; i < kPoseAcc / 4; ++i) wred[w][4 * i + wave_sum_slot(lane)] = out[i];
+        }
       }
       __syncthreads();
       if (t < kPoseAcc) total += (wred[0][t] + wred[1][t]) + (wred[2][t] + wred[3][t]);
