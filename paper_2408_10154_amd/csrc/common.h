@@ -121,10 +121,25 @@ __device__ __forceinline__ Rect tile_rect(float u, float v, int r, int TX, int T
   return o;
 }
 
-// Gaussian falloff exponent at pixel offset (dx, dy) with explicit FMAs so
-// that forward and backward take identical decisions.
-__device__ __forceinline__ float falloff(float A, float B, float C, float dx, float dy) {
-  return __builtin_fmaf(0.5f * A * dx, dx, __builtin_fmaf(B * dx, dy, 0.5f * C * dy * dy));
+// The compositing kernels stage each splat's conic (A, B, C) pre-scaled to
+// (A / 2, B, C / 2) log2(e), so that the falloff sigma = (A dx^2 + 2 B dx dy +
+// C dy^2) / 2 comes out as sigma log2(e) and exp(-sigma) = 2^(-that): no
+// per-pixel multiply before the exponential.  Factors back to (A, B, C).
+constexpr float kHalfLog2e = 0.72134752044448170368f;  // log2(e) / 2
+constexpr float kLog2e = 1.44269504088896340736f;
+constexpr float kLn2 = 0.69314718055994530942f;
+constexpr float kTwoLn2 = 1.38629436111989061883f;
+
+__device__ __forceinline__ void stage_conic(float4& a, float4& b) {
+  a.z *= kHalfLog2e;
+  a.w *= kLog2e;
+  b.x *= kHalfLog2e;
+}
+
+// sigma log2(e) at pixel offset (dx, dy) from a staged conic, with explicit
+// FMAs so that forward and backward take identical decisions.
+__device__ __forceinline__ float falloff_log2(float hA, float B, float hC, float dx, float dy) {
+  return __builtin_fmaf(hA * dx, dx, __builtin_fmaf(B * dx, dy, hC * dy * dy));
 }
 
 // The DPP reductions below use moves without an "old" operand (bound_ctrl

@@ -242,48 +242,51 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
   const int tx0 = c.x - (threadIdx.x & 15), ty0 = c.y - (threadIdx.x >> 4);
 
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
-  bool done = !c.inside;
   int nlast = end - start;
+  // lanes still compositing, a wave-uniform mask; the per-entry decisions are
+  // ballots of plain compares combined in scalar registers, and a lane's own
+  // bit is read back with an inverse ballot
+  uint64_t alive = __ballot(c.inside);
   for (int chunk = start; chunk < end; chunk += kBlock) {
-    if (__syncthreads_count(done) == kBlock) break;
+    if (!__syncthreads_or(alive != 0ull)) break;
     const int e = chunk + threadIdx.x;
     uint32_t m = 0;
     if (e < end) {
       const int64_t it = items[e];
-      const float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+      float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+      m = wave_mask(a, b, tx0, ty0);
+      stage_conic(a, b);
       s0[threadIdx.x] = a;
       s1[threadIdx.x] = b;
       s2[threadIdx.x] = rec[it * 3 + 2];
-      m = wave_mask(a, b, tx0, ty0);
     }
     build_wave_lists(m, e < end, slist, scnt, swc);
     // the band's list is wave-uniform: scalar loop control, branch-free body
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
-    uint64_t alive = __ballot(!done);  // lanes still compositing (wave-uniform)
     for (int jj = 0; jj < cw && alive != 0ull; ++jj) {
       const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
-      const float sig = falloff(a.z, a.w, b.x, dx, dy);
-      const float al = fminf(LS_ALPHA_MAX, b.y * __expf(-sig));
-      const bool hit = !done && sig >= 0.f && al >= LS_ALPHA_MIN;
+      const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
+      const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
       const float Tn = T * (1.f - al);
-      const bool stop = hit && Tn < LS_T_STOP;
-      if (stop) {
-        done = true;
-        nlast = chunk + j - start;
+      const uint64_t hit = alive & __ballot(sl >= 0.f) & __ballot(al >= LS_ALPHA_MIN);
+      const uint64_t stop = hit & __ballot(Tn < LS_T_STOP);
+      const uint64_t use = hit & ~stop;
+      if (stop != 0ull) {
+        if (__builtin_amdgcn_inverse_ballot_w64(stop)) nlast = chunk + j - start;
+        alive &= ~stop;
       }
-      alive &= ~__ballot(stop);
-      const bool use = hit && !stop;
-      if (__ballot(use) != 0ull) {
+      if (use != 0ull) {
+        const bool u = __builtin_amdgcn_inverse_ballot_w64(use);
         const float4 col = s2[j];
-        const float wgt = use ? al * T : 0.f;  // 0 adds an exact zero below
+        const float wgt = u ? al * T : 0.f;  // 0 adds an exact zero below
         cr += wgt * col.x;
         cg += wgt * col.y;
         cb += wgt * col.z;
         dd += wgt * b.z;
-        T = use ? Tn : T;
+        T = u ? Tn : T;
       }
     }
   }
@@ -378,30 +381,39 @@ constexpr int kPartStride = 4 * kWaveSlots + 1;         // floats per entry: 4 w
 // "behind" value acc = sum_{j>i} alpha_j prod_{i<k<j}(1 - alpha_k) v_j +
 // prod_{k>i}(1 - alpha_k)(bg . gC - gA), where v_j = c_j . gC + z_j gD:
 //   dL/dalpha_i = T_i (v_i - acc_i).
-// One such step at a pixel, branch-free: act says whether the entry was
-// composited there (visited, sigma >= 0, alpha >= 1/255); if so T is
-// recovered, acc updated, and wgt = alpha T, ds = dL/dsigma and dop =
-// dL/d(opacity) are set (both zero while the 0.99 clamp is active);
-// otherwise T and acc are unchanged and wgt = ds = dop = 0 (selected, never
-// formed from products with exp(-sigma)).
-__device__ __forceinline__ bool bwd_step(bool visited, float4 a, float4 b, float4 col, float dx, float dy, float gR,
-                                         float gG, float gB, float gD, float& T, float& acc, float& wgt, float& ds,
-                                         float& dop) {
-  const float sig = falloff(a.z, a.w, b.x, dx, dy);
-  const float ex = __expf(-sig);
-  const float G = b.y * ex;
-  const float al = fminf(LS_ALPHA_MAX, G);
-  const bool act = visited && sig >= 0.f && al >= LS_ALPHA_MIN;
-  const float om = 1.f - al;
-  T = act ? T * __builtin_amdgcn_rcpf(om) : T;
-  wgt = act ? al * T : 0.f;
-  const float v = col.x * gR + col.y * gG + col.z * gB + b.z * gD;
+// One such step at a pixel, in two parts.  bwd_eval (every entry of the
+// band's list) says whether the entry was composited there: act = visited,
+// sigma >= 0 and alpha >= 1/255.  bwd_apply (entries some lane of the wave
+// composited), branch-free: where act, T is recovered, acc updated, and
+// wgt = alpha T, ds = dL/dsigma and dop = dL/d(opacity) are set (both zero
+// while the 0.99 clamp is active); elsewhere T and acc are unchanged and
+// wgt = ds = dop = 0 (selected, never formed from products with exp(-sigma)).
+struct BwdEval {
+  float ex, G, al;  // exp(-sigma), o exp(-sigma), alpha
+  bool act;
+};
+
+__device__ __forceinline__ BwdEval bwd_eval(bool visited, float4 a, float4 b, float dx, float dy) {
+  BwdEval e;
+  const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
+  e.ex = __builtin_amdgcn_exp2f(-sl);
+  e.G = b.y * e.ex;
+  e.al = fminf(LS_ALPHA_MAX, e.G);
+  e.act = visited && sl >= 0.f && e.al >= LS_ALPHA_MIN;
+  return e;
+}
+
+__device__ __forceinline__ void bwd_apply(const BwdEval& e, float4 col, float z, float gR, float gG, float gB,
+                                          float gD, float& T, float& acc, float& wgt, float& ds, float& dop) {
+  const float om = 1.f - e.al;
+  T = e.act ? T * __builtin_amdgcn_rcpf(om) : T;
+  wgt = e.act ? e.al * T : 0.f;
+  const float v = col.x * gR + col.y * gG + col.z * gB + z * gD;
   const float dal = T * (v - acc);
-  acc = act ? al * v + om * acc : acc;
-  const bool grad = act && G < LS_ALPHA_MAX;  // dL/dG = dal; no gradient through an active clamp
-  ds = grad ? -dal * G : 0.f;
-  dop = grad ? dal * ex : 0.f;
-  return act;
+  acc = e.act ? e.al * v + om * acc : acc;
+  const bool grad = e.act && e.G < LS_ALPHA_MAX;  // dL/dG = dal; no gradient through an active clamp
+  ds = grad ? -dal * e.G : 0.f;
+  dop = grad ? dal * e.ex : 0.f;
 }
 
 // Per-pixel state shared by both backward kernels: upstream gradients (scaled),
@@ -440,12 +452,13 @@ __device__ __forceinline__ void stage_chunk(int lane, int cnt, int chunk, const 
   const bool valid = lane < cnt;
   if (valid) {
     const int64_t it = items[chunk + lane];
-    const float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+    float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+    m = wave_mask(a, b, tx0, ty0);
+    stage_conic(a, b);
     sit[lane] = (int32_t)it;
     s0[lane] = a;
     s1[lane] = b;
     s2[lane] = rec[it * 3 + 2];
-    m = wave_mask(a, b, tx0, ty0);
     smask[lane] = m;
   }
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -510,10 +523,10 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
-      float wgt, ds, dop;
-      const bool act = bwd_step(k < px.nl, a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds,
-                                dop);
-      if (__ballot(act) != 0ull) {
+      const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
+      if (__ballot(e.act) != 0ull) {
+        float wgt, ds, dop;
+        bwd_apply(e, s2[j], b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
         // per-pixel terms whose sums give the ten gradients; the conic factors
         // of dL/du, dL/dv and the halves of dL/dA, dL/dC are applied once per
         // entry after the sums
@@ -565,7 +578,7 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
         };
         if (t == 0) {
           const float sx = band_sum(0), sy = band_sum(1);
-          const float cA = s0[j].z, cB = s0[j].w, cC = s1[j].x;
+          const float cA = kTwoLn2 * s0[j].z, cB = kLn2 * s0[j].w, cC = kTwoLn2 * s1[j].x;  // staged -> (A, B, C)
           put(0, -(cA * sx + cB * sy));
           put(1, -(cB * sx + cC * sy));
         } else {
@@ -688,13 +701,13 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
-      float wgt, ds, dop;
-      const bool act = bwd_step(k < px.nl, a, b, s2[j], dx, dy, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds,
-                                dop);
+      const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
       float out[kPoseSlots / 4];
 #pragma unroll
       for (int i = 0; i < kPoseSlots / 4; ++i) out[i] = 0.f;
-      if (__ballot(act) != 0ull) {
+      if (__ballot(e.act) != 0ull) {
+        float wgt, ds, dop;
+        bwd_apply(e, s2[j], b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
         // as in the full-mode kernel: conic factors and halves after the sums
         float g[kPoseRow];
         g[0] = ds * dx;
@@ -726,7 +739,7 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
 #pragma unroll
           for (int q = 0; q < kPoseRow; ++q) sum[q] += pj[b2 * kPoseSlots + q];
         }
-        const float cA = s0[j].z, cB = s0[j].w, cC = s1[j].x;
+        const float cA = kTwoLn2 * s0[j].z, cB = kLn2 * s0[j].w, cC = kTwoLn2 * s1[j].x;  // staged -> (A, B, C)
         g6[0] = -(cA * sum[0] + cB * sum[1]);
         g6[1] = -(cB * sum[0] + cC * sum[1]);
         g6[2] = 0.5f * sum[2];
@@ -849,8 +862,10 @@ __global__ __launch_bounds__(kBlock) void k_render_stats(const JobDev* __restric
     const int e = chunk + threadIdx.x;
     if (e < end) {
       const int64_t it = items[e];
-      s0[threadIdx.x] = rec[it * 3 + 0];
-      s1[threadIdx.x] = rec[it * 3 + 1];
+      float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
+      stage_conic(a, b);
+      s0[threadIdx.x] = a;
+      s1[threadIdx.x] = b;
     }
     __syncthreads();
     const int cnt = min(kBlock, end - chunk);
@@ -859,9 +874,9 @@ __global__ __launch_bounds__(kBlock) void k_render_stats(const JobDev* __restric
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
-      const float sig = falloff(a.z, a.w, b.x, dx, dy);
-      if (sig < 0.f) continue;
-      const float al = fminf(LS_ALPHA_MAX, b.y * __expf(-sig));
+      const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
+      if (sl < 0.f) continue;
+      const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
       if (al >= LS_ALPHA_MIN) ++comp;
     }
     __syncthreads();
