@@ -232,7 +232,7 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
                                                           float* __restrict__ out_T, int32_t* __restrict__ out_n,
                                                           int tile) {
   __shared__ float4 s0[kBlock], s1[kBlock], s2[kBlock];
-  __shared__ uint8_t slist[4][kBlock];
+  __shared__ __attribute__((aligned(4))) uint8_t slist[4][kBlock];
   __shared__ uint32_t scnt[4][4];
   __shared__ uint32_t swc[4];
   const TileCtx c = tile_ctx(jobs, tile_off, R, tile);
@@ -263,8 +263,11 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
     build_wave_lists(m, e < end, slist, scnt, swc);
     // the band's list is wave-uniform: scalar loop control, branch-free body
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
+    // the band's list in registers, four entries per lane: an entry's index
+    // is a lane read and a shift, not an LDS round trip per entry
+    const uint32_t idx4 = reinterpret_cast<const uint32_t*>(slist[w])[threadIdx.x & 63];
     for (int jj = 0; jj < cw && alive != 0ull; ++jj) {
-      const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
+      const int j = (int)((__builtin_amdgcn_readlane(idx4, jj >> 2) >> ((jj & 3) * 8)) & 0xFFu);
       const float4 a = s0[j];
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
@@ -515,8 +518,9 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     if (w == 0) stage_chunk<kBwdChunk>(lane, cnt, chunk, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
+    const uint32_t myj = lane < kBwdChunk ? slist[w][lane] : 0u;  // the band's list in a register
     for (int jj = cw - 1; jj >= 0; --jj) {
-      const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
+      const int j = (int)__builtin_amdgcn_readlane(myj, jj);
       float* pj = part + j * kPartStride + wslot;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;  // list position
@@ -693,8 +697,9 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
     if (w == 0) stage_chunk<kPoseChunk>(lane, cnt, chunk, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
+    const uint32_t myj = lane < kPoseChunk ? slist[w][lane] : 0u;  // the band's list in a register
     for (int jj = cw - 1; jj >= 0; --jj) {
-      const int j = __builtin_amdgcn_readfirstlane((int)slist[w][jj]);
+      const int j = (int)__builtin_amdgcn_readlane(myj, jj);
       float* pj = part + j * kPoseStride + wslot;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;
