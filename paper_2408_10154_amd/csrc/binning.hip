@@ -35,7 +35,8 @@ __device__ __forceinline__ int sort_count(const int32_t* n_dev, int64_t n_static
 }
 
 // Per-block digit histogram of kBits-bit digits, stored digit-major:
-// hist[d * nblocks + block].
+// hist[d * nblocks + block].  Every key of the block is loaded before any is
+// counted, so the block waits for memory once, not once per round.
 template <int kBits>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys, const int32_t* n_dev,
                                                             int64_t n_static, int64_t cap, int shift,
@@ -44,15 +45,21 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
   __shared__ uint32_t h[kBins];
   const int n = sort_count(n_dev, n_static, cap);
   for (int i = threadIdx.x; i < kBins; i += kSortThreads) h[i] = 0;
-  __syncthreads();
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
-  if (base < n) {
-    const int lane = threadIdx.x & 63;
-#pragma unroll 4
-    for (int i = 0; i < rounds; ++i) {
-      const int64_t idx = base + i * kSortThreads + threadIdx.x;
-      const bool valid = idx < n;
-      const uint32_t d = valid ? (keys[idx] >> shift) & (uint32_t)(kBins - 1) : 0u;
+  const int nb = base < n ? (int)min((int64_t)rounds * kSortThreads, (int64_t)n - base) : 0;
+  uint32_t key[kSortItems];
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    const int i = r * kSortThreads + threadIdx.x;
+    key[r] = (r < rounds && i < nb) ? keys[base + i] : 0u;
+  }
+  __syncthreads();
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r < rounds && r * kSortThreads < nb) {  // uniform; a guard, not a break, so the loop unrolls
+      const bool valid = r * kSortThreads + (int)threadIdx.x < nb;
+      const uint32_t d = (key[r] >> shift) & (uint32_t)(kBins - 1);
       // aggregate equal digits within the wave before touching LDS
       uint64_t peers = __ballot(valid);
 #pragma unroll
@@ -104,15 +111,21 @@ __global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, 
   if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-// Stable scatter of one kBits-bit digit pass.  Each block first turns the
-// digit totals into digit bases (a block-wide scan, cheaper than a launch of
-// its own) and adds its scanned row entries; then it takes its items in rounds
-// of 256 in index order.  Within a round an item's position is its digit's
-// base + the count of equal digits in earlier waves of the round + its rank
-// among equal digits in its own wave (ballot matching).  Only the one leader
-// lane per (wave, digit) present writes a count, adds it to the base and
-// clears it again, so a round costs work in proportion to its items, not to
-// the number of digits, and three barriers.
+// Stable scatter of one kBits-bit digit pass.  Each block loads all its
+// items at once, then
+//  - turns the digit totals into global digit bases (a block-wide scan,
+//    cheaper than a launch of its own) plus its scanned row entries, and its
+//    own digit counts (differences of neighbouring row entries) into local
+//    digit bases;
+//  - takes its items in rounds of 256 in index order and places each in LDS
+//    at its digit's running local base + the count of equal digits in earlier
+//    waves of the round + its rank among equal digits in its own wave (ballot
+//    matching).  Only the one leader lane per (wave, digit) present writes a
+//    count, adds it to the base and clears it again, so a round costs work in
+//    proportion to its items, not to the number of digits;
+//  - writes the block's items out in LDS order: item i of digit d goes to
+//    global base(d) - local base(d) + i, so neighbouring threads write
+//    neighbouring addresses along each digit's run.
 template <int kBits>
 __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* __restrict__ kin,
                                                                const uint32_t* __restrict__ vin,
@@ -123,65 +136,91 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
   constexpr int kBins = 1 << kBits;
   constexpr int kPer = kBins / kSortThreads;  // digits per thread in the set-up
   static_assert(kBins % kSortThreads == 0, "digit count must be a multiple of the block size");
-  __shared__ uint32_t base[kBins];
+  __shared__ uint32_t base[kBins];   // running local position of each digit
+  __shared__ uint32_t delta[kBins];  // global minus local start of each digit's run (mod 2^32)
   __shared__ uint32_t wcnt[4][kBins];
   __shared__ uint32_t wsum[4];
+  __shared__ uint32_t sk[kSortTile], sv[kSortTile];
   const int n = sort_count(n_dev, n_static, cap);
   const int64_t bbase = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (bbase >= n) return;  // uniform for the block
+  const int nb = (int)min((int64_t)rounds * kSortThreads, (int64_t)n - bbase);
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  {
-    uint32_t loc[kPer];
-    uint32_t sum = 0;
+  uint32_t key[kSortItems], val[kSortItems];
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      loc[k] = digit_total[tid * kPer + k];
-      sum += loc[k];
-    }
-    uint32_t all;
-    uint32_t run = block_excl_scan(sum, wsum, &all);
+  for (int r = 0; r < kSortItems; ++r) {
+    const int i = r * kSortThreads + tid;
+    const bool ok = r < rounds && i < nb;
+    key[r] = ok ? kin[bbase + i] : 0u;
+    val[r] = ok ? vin[bbase + i] : 0u;
+  }
+  {
+    uint32_t tot[kPer], cnt[kPer];
+    uint32_t gsum = 0, lsum = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int d = tid * kPer + k;
-      base[d] = run + hist[(int64_t)d * nblocks + blockIdx.x];
-      run += loc[k];
+      const uint32_t here = hist[(int64_t)d * nblocks + blockIdx.x];
+      tot[k] = digit_total[d];
+      const uint32_t next = (int)blockIdx.x + 1 < nblocks ? hist[(int64_t)d * nblocks + blockIdx.x + 1] : tot[k];
+      cnt[k] = next - here;
+      gsum += tot[k];
+      lsum += cnt[k];
+      delta[d] = here;
+    }
+    uint32_t all;
+    uint32_t grun = block_excl_scan(gsum, wsum, &all);
+    uint32_t lrun = block_excl_scan(lsum, wsum, &all);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const int d = tid * kPer + k;
+      base[d] = lrun;
+      delta[d] = grun + delta[d] - lrun;
+      grun += tot[k];
+      lrun += cnt[k];
       wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0u;
     }
   }
   __syncthreads();
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int round = 0; round < rounds; ++round) {
-    const int64_t rbase = bbase + (int64_t)round * kSortThreads;
-    if (rbase >= n) break;  // uniform
-    const int64_t idx = rbase + tid;
-    const bool valid = idx < n;
-    const uint32_t key = valid ? kin[idx] : 0u;
-    const uint32_t val = valid ? vin[idx] : 0u;
-    const uint32_t d = (key >> shift) & (uint32_t)(kBins - 1);
-    uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int b = 0; b < kBits; ++b) {
-      const bool bit = (d >> b) & 1u;
-      const uint64_t m = __ballot(bit);
-      peers &= bit ? m : ~m;
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r < rounds && r * kSortThreads < nb) {  // uniform; a guard, not a break, so the loop unrolls
+      const bool valid = r * kSortThreads + tid < nb;
+      const uint32_t d = (key[r] >> shift) & (uint32_t)(kBins - 1);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      const bool leader = valid && rank == 0;
+      const uint32_t c = (uint32_t)__popcll(peers);
+      if (leader) wcnt[w][d] = c;
+      __syncthreads();
+      if (valid) {
+        uint32_t pos = base[d] + rank;
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          if (k < w) pos += wcnt[k][d];
+        sk[pos] = key[r];
+        sv[pos] = val[r];
+      }
+      __syncthreads();
+      if (leader) {
+        atomicAdd(&base[d], c);
+        wcnt[w][d] = 0u;
+      }
+      __syncthreads();
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    const bool leader = valid && rank == 0;
-    const uint32_t cnt = (uint32_t)__popcll(peers);
-    if (leader) wcnt[w][d] = cnt;
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = base[d] + rank;
-      for (int k = 0; k < w; ++k) pos += wcnt[k][d];
-      kout[pos] = key;
-      vout[pos] = val;
-    }
-    __syncthreads();
-    if (leader) {
-      atomicAdd(&base[d], cnt);
-      wcnt[w][d] = 0u;
-    }
-    __syncthreads();
+  }
+  for (int i = tid; i < nb; i += kSortThreads) {
+    const uint32_t k = sk[i];
+    const uint32_t pos = delta[(k >> shift) & (uint32_t)(kBins - 1)] + (uint32_t)i;
+    kout[pos] = k;
+    vout[pos] = sv[i];
   }
 }
 
