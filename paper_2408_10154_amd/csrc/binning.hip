@@ -243,13 +243,15 @@ __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __re
 
 // Exclusive offsets of every depth-sorted item: block offset (the sum of the
 // preceding block sums, formed here rather than by a scan launch) plus the
-// in-block prefix, 16 rounds of 256 items in order.  Block 0 also writes
-// count = {min(I, cap), I > cap, min(I, INT32_MAX), 0}.
+// in-block prefix, 16 rounds of 256 items in order.  The item whose instance
+// range holds instance m * kEmitSpan (m < nspan) is recorded in first[m].
+// Block 0 also writes count = {min(I, cap), I > cap, min(I, INT32_MAX), 0}.
 __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __restrict__ order,
                                                           const int32_t* __restrict__ tiles, int64_t M,
                                                           const uint32_t* __restrict__ bsum, int nbd,
                                                           uint32_t* __restrict__ offs, int32_t* __restrict__ count,
-                                                          int64_t cap, int rounds) {
+                                                          int64_t cap, int rounds, uint32_t* __restrict__ first,
+                                                          int64_t nspan) {
   __shared__ uint32_t wsum[4];
   __shared__ uint64_t wtot[4];
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
@@ -278,7 +280,12 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
     const uint32_t c = k < M ? (uint32_t)tiles[order[k]] : 0u;
     uint32_t tot;
     const uint32_t x = block_excl_scan(c, wsum, &tot);
-    if (k < M) offs[k] = run + x;
+    if (k < M) {
+      const int64_t o = (int64_t)run + x;
+      offs[k] = (uint32_t)o;
+      for (int64_t m = (o + kEmitSpan - 1) / kEmitSpan; m < nspan && m * kEmitSpan < o + c; ++m)
+        first[m] = (uint32_t)k;
+    }
     run += tot;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -290,51 +297,93 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
   }
 }
 
-constexpr int kEmitPer = 8;  // instances per emission thread
+// Inclusive prefix maximum over the 64 lanes (DPP: shifts within 16-lane
+// rows, then the row ends broadcast to the later rows); -1 is the identity.
+__device__ __forceinline__ int wave_incl_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x111, 0xF, 0xF, false));  // row_shr:1
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x112, 0xF, 0xF, false));  // row_shr:2
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x114, 0xF, 0xF, false));  // row_shr:4
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x118, 0xF, 0xF, false));  // row_shr:8
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x142, 0xA, 0xF, false));  // row_bcast:15 -> rows 1, 3
+  v = max(v, __builtin_amdgcn_update_dpp(-1, v, 0x143, 0xC, 0xF, false));  // row_bcast:31 -> rows 2, 3
+  return v;
+}
 
-// Emission, balanced over instances: thread t owns instances
-// [8 t, 8 t + 8) of the output, finds the depth-sorted item that owns the
-// first one by binary search over the item offsets, and walks forward through
-// the items' tile rectangles (row by row).  Output runs are contiguous per
-// thread, so neighbouring threads write neighbouring addresses.
+// Emission of the tile instances in depth order, one wave per span of
+// kEmitSpan consecutive instances (so every wave has the same work, however
+// many tiles its items cover).  The wave takes the items from the span's first
+// one on, 64 at a time, lane l item kb + l: its instance offset, its tile
+// rectangle and the key of the rectangle's first tile.  It fills the span 64
+// instances at a time, lane l writing instance W0 + l, so every store is one
+// contiguous run; windows stop at the end of the loaded items, and the next
+// 64 items start there.  The owner of an instance is the last item that starts
+// at or before it: items starting inside the window mark their start position
+// (LDS), a prefix maximum over the lanes carries each mark forward, and
+// positions before the first start keep the previous owner (at first, lane 0:
+// the item that holds the span's first instance).  Within its owner's
+// rectangle, instance q lies in row q / width (row by row, as the tiles are
+// counted).  Instances at or beyond the capacity are not written.
 __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
                                               int R, const uint32_t* __restrict__ order,
                                               const float4* __restrict__ rec, const int32_t* __restrict__ radius,
                                               const int32_t* __restrict__ tiles, int64_t M,
                                               const uint32_t* __restrict__ offs, const int32_t* __restrict__ count,
+                                              const uint32_t* __restrict__ first, int64_t nspan,
                                               uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
+  __shared__ int marks[4][64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t span = (int64_t)blockIdx.x * 4 + w;
   const int64_t I = count[0];  // already clamped to the capacity
-  const int64_t i0 = ((int64_t)blockIdx.x * 256 + threadIdx.x) * kEmitPer;
-  if (i0 >= I) return;
-  const int64_t iend = min(i0 + kEmitPer, I);
-  int64_t lo = 0, hi = M - 1;  // largest k with offs[k] <= i0 (that item has tiles > 0)
-  while (lo < hi) {
-    const int64_t mid = (lo + hi + 1) >> 1;
-    if ((int64_t)offs[mid] <= i0) lo = mid; else hi = mid - 1;
-  }
-  int64_t k = lo;
-  int64_t i = i0;
-  while (i < iend && k < M) {
-    const uint32_t it = order[k];
-    const int nt = tiles[it];
-    if (nt > 0) {
-      const int r = find_segment<int64_t>(item_off, R, (int64_t)it);
-      const JobDev& J = jobs[r];
-      const float4 a = rec[(int64_t)it * 3];
-      const Rect rc = tile_rect(a.x, a.y, radius[it], J.TX, J.TY);
-      const int wdt = rc.x1 - rc.x0;
-      int q = (int)(i - (int64_t)offs[k]);
-      int dy = q / wdt, dx = q - dy * wdt;
-      int key = J.tile_off + (rc.y0 + dy) * J.TX + rc.x0 + dx;
-      for (; q < nt && i < iend; ++q, ++i) {
-        kout[i] = (uint32_t)key;
-        vout[i] = (int32_t)it;
-        ++dx;
-        ++key;
-        if (dx == wdt) { dx = 0; key += J.TX - wdt; }
+  if (span >= nspan || span * kEmitSpan >= I) return;  // uniform for the wave
+  const int64_t iend = min((span + 1) * kEmitSpan, I);
+  int64_t kb = (int64_t)first[span];
+  int64_t W0 = span * kEmitSpan;
+  while (W0 < iend && kb < M) {
+    const int64_t k = kb + lane;
+    const int last = (int)min((int64_t)63, M - 1 - kb);  // last lane with an item
+    uint32_t off = 0xFFFFFFFFu, it = 0;
+    int nt = 0, base_key = 0, stride = 0, wdt = 1;
+    if (k < M) {
+      off = offs[k];
+      it = order[k];
+      nt = tiles[it];
+      if (nt > 0) {
+        const int r = find_segment<int64_t>(item_off, R, (int64_t)it);
+        const JobDev& J = jobs[r];
+        const float4 a = rec[(int64_t)it * 3];
+        const Rect rc = tile_rect(a.x, a.y, radius[it], J.TX, J.TY);
+        wdt = rc.x1 - rc.x0;
+        base_key = J.tile_off + rc.y0 * J.TX + rc.x0;
+        stride = J.TX - wdt;
       }
     }
-    ++k;
+    const float inv = 1.0f / (float)wdt;
+    const int64_t cend = min((int64_t)(uint32_t)__builtin_amdgcn_readlane((int)(off + (uint32_t)nt), last), iend);
+    int carry = 0;
+    while (W0 < cend) {
+      marks[w][lane] = -1;
+      const int64_t rel = (int64_t)off - W0;
+      if (nt > 0 && rel >= 0 && rel < 64) marks[w][(int)rel] = lane;
+      __builtin_amdgcn_wave_barrier();
+      int o = wave_incl_max(marks[w][lane]);
+      o = o < 0 ? carry : o;
+      carry = __builtin_amdgcn_readlane(o, 63);
+      const int64_t i = W0 + lane;
+      const int o_key = __shfl(base_key, o, 64), o_stride = __shfl(stride, o, 64), o_wdt = __shfl(wdt, o, 64);
+      const float o_inv = __shfl(inv, o, 64);
+      const uint32_t o_off = (uint32_t)__shfl((int)off, o, 64), o_it = (uint32_t)__shfl((int)it, o, 64);
+      if (i < cend) {
+        const int q = (int)(i - (int64_t)o_off);
+        int dy = (int)((float)q * o_inv);
+        if ((dy + 1) * o_wdt <= q) ++dy;
+        else if (dy * o_wdt > q) --dy;
+        kout[i] = (uint32_t)(o_key + dy * o_stride + q);
+        vout[i] = (int32_t)o_it;
+      }
+      __builtin_amdgcn_wave_barrier();
+      W0 = min(W0 + 64, cend);
+    }
+    kb += 64;
   }
 }
 
@@ -388,18 +437,19 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   const uint32_t* order = va;
   uint32_t* offs = ka;  // the free key buffer holds the per-item offsets
   hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, rd, bsum);
+  const int64_t nspan = emit_spans(cap);
+  uint32_t* first = hist;  // free between the depth sort and the tile sort
   hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const uint32_t*)bsum, nbd,
-                     offs, count, cap, rd);
+                     offs, count, cap, rd, first, nspan);
   // emission lands in the buffer that, after tile_passes ping-pongs, is the output
   uint32_t* ek = (tile_passes & 1) ? tk : tile_of;
   uint32_t* ev = (tile_passes & 1) ? tv : reinterpret_cast<uint32_t*>(item);
   uint32_t* ok = (tile_passes & 1) ? tile_of : tk;
   uint32_t* ov = (tile_passes & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
-  const int64_t emit_threads = (cap + kEmitPer - 1) / kEmitPer;
-  if (emit_threads > 0)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((emit_threads + 255) / 256)), dim3(256), 0, s, jobs, item_off_d, R, order,
-                       rec4, radius, tiles, M, (const uint32_t*)offs, (const int32_t*)count, ek,
-                       reinterpret_cast<int32_t*>(ev));
+  if (nspan > 0 && M > 0)
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)((nspan + 3) / 4)), dim3(256), 0, s, jobs, item_off_d, R, order, rec4,
+                       radius, tiles, M, (const uint32_t*)offs, (const int32_t*)count, (const uint32_t*)first, nspan,
+                       ek, reinterpret_cast<int32_t*>(ev));
   const int rt = sort_rounds(cap), nbt = (int)sort_blocks(cap);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {
     radix_pass<kTileDigitBits>(ek, ev, ok, ov, count, 0, cap, kTileDigitBits * p, hist, digit_base, nbt, rt, s);

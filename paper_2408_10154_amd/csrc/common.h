@@ -34,6 +34,10 @@ __host__ __device__ inline int64_t sort_blocks(int64_t n) {
   const int64_t per = (int64_t)sort_rounds(n) * kSortThreads;
   return (n + per - 1) / per;
 }
+// Tile instances emitted per wave; the first item of every span is recorded
+// while the item offsets are formed (in the sort histogram buffer, free then).
+constexpr int kEmitSpan = 512;
+__host__ __device__ inline int64_t emit_spans(int64_t cap) { return (cap + kEmitSpan - 1) / kEmitSpan; }
 constexpr int kGrad2D = 10;         // du dv dA dB dC dop dz dr dg db
 constexpr int kPoseAcc = 12;        // dL/dR (9, row-major) and dL/dt (3)
 constexpr int kAuxFloats = 12;      // per item: camera-space mean (3), covariance (6), 0 x3
