@@ -266,10 +266,9 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
     // the band's list in registers, four entries per lane: an entry's index
     // is a lane read and a shift, not an LDS round trip per entry
     const uint32_t idx4 = reinterpret_cast<const uint32_t*>(slist[w])[threadIdx.x & 63];
-    for (int jj = 0; jj < cw && alive != 0ull; ++jj) {
-      const int j = (int)((__builtin_amdgcn_readlane(idx4, jj >> 2) >> ((jj & 3) * 8)) & 0xFFu);
-      const float4 a = s0[j];
-      const float4 b = s1[j];
+    auto entry = [&](int jj) { return (int)((__builtin_amdgcn_readlane(idx4, jj >> 2) >> ((jj & 3) * 8)) & 0xFFu); };
+    // one compositing step at entry jj of the band's list, record (a, b, col)
+    auto step = [&](int jj, int j, const float4& a, const float4& b, const float4& col) {
       const float dx = fx - a.x, dy = fy - a.y;
       const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
       const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
@@ -283,7 +282,6 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
       }
       if (use != 0ull) {
         const bool u = __builtin_amdgcn_inverse_ballot_w64(use);
-        const float4 col = s2[j];
         const float wgt = u ? al * T : 0.f;  // 0 adds an exact zero below
         cr += wgt * col.x;
         cg += wgt * col.y;
@@ -291,6 +289,25 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
         dd += wgt * b.z;
         T = u ? Tn : T;
       }
+    };
+    // Records are read one entry ahead into two alternating register sets, so
+    // the LDS latency of the next entry overlaps the arithmetic of this one
+    // (with no entries, entry 0 is read and never used).
+    int jA = entry(0), jB = 0;
+    float4 aA = s0[jA], bA = s1[jA], cA = s2[jA], aB, bB, cB;
+    for (int jj = 0; jj < cw && alive != 0ull;) {
+      jB = entry(jj + 1 < cw ? jj + 1 : jj);
+      aB = s0[jB];
+      bB = s1[jB];
+      cB = s2[jB];
+      step(jj, jA, aA, bA, cA);
+      if (++jj >= cw || alive == 0ull) break;
+      jA = entry(jj + 1 < cw ? jj + 1 : jj);
+      aA = s0[jA];
+      bA = s1[jA];
+      cA = s2[jA];
+      step(jj, jB, aB, bB, cB);
+      ++jj;
     }
   }
   if (!c.inside) return;
@@ -519,18 +536,15 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     const uint32_t myj = lane < kBwdChunk ? slist[w][lane] : 0u;  // the band's list in a register
-    for (int jj = cw - 1; jj >= 0; --jj) {
-      const int j = (int)__builtin_amdgcn_readlane(myj, jj);
+    auto bstep = [&](int j, const float4& a, const float4& b, const float4& col) {
       float* pj = part + j * kPartStride + wslot;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;  // list position
-      const float4 a = s0[j];
-      const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
       const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
       if (__ballot(e.act) != 0ull) {
         float wgt, ds, dop;
-        bwd_apply(e, s2[j], b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
+        bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
         // per-pixel terms whose sums give the ten gradients; the conic factors
         // of dL/du, dL/dv and the halves of dL/dA, dL/dC are applied once per
         // entry after the sums
@@ -555,6 +569,23 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
 #pragma unroll
         for (int i = 0; i < kWaveSlots / 4; ++i) pj[4 * i] = 0.f;
       }
+    };
+    // records read one entry ahead into alternating register sets (as in the forward)
+    int jA = (int)__builtin_amdgcn_readlane(myj, cw > 0 ? cw - 1 : 0), jB = 0;
+    float4 aA = s0[jA], bA = s1[jA], cA = s2[jA], aB, bB, cB;
+    for (int jj = cw - 1; jj >= 0;) {
+      jB = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      aB = s0[jB];
+      bB = s1[jB];
+      cB = s2[jB];
+      bstep(jA, aA, bA, cA);
+      if (--jj < 0) break;
+      jA = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      aA = s0[jA];
+      bA = s1[jA];
+      cA = s2[jA];
+      bstep(jB, aB, bB, cB);
+      --jj;
     }
     __syncthreads();
     {
@@ -698,13 +729,10 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     const uint32_t myj = lane < kPoseChunk ? slist[w][lane] : 0u;  // the band's list in a register
-    for (int jj = cw - 1; jj >= 0; --jj) {
-      const int j = (int)__builtin_amdgcn_readlane(myj, jj);
+    auto pstep = [&](int j, const float4& a, const float4& b, const float4& col) {
       float* pj = part + j * kPoseStride + wslot;
       const bool lead = (lane & 15) == 0;
       const int k = chunk + j - start;
-      const float4 a = s0[j];
-      const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
       const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
       float out[kPoseSlots / 4];
@@ -712,7 +740,7 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
       for (int i = 0; i < kPoseSlots / 4; ++i) out[i] = 0.f;
       if (__ballot(e.act) != 0ull) {
         float wgt, ds, dop;
-        bwd_apply(e, s2[j], b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
+        bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
         // as in the full-mode kernel: conic factors and halves after the sums
         float g[kPoseRow];
         g[0] = ds * dx;
@@ -727,6 +755,23 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
 #pragma unroll
         for (int i = 0; i < kPoseSlots / 4; ++i) pj[4 * i] = out[i];
       }
+    };
+    // records read one entry ahead into alternating register sets (as in the forward)
+    int jA = (int)__builtin_amdgcn_readlane(myj, cw > 0 ? cw - 1 : 0), jB = 0;
+    float4 aA = s0[jA], bA = s1[jA], cA = s2[jA], aB, bB, cB;
+    for (int jj = cw - 1; jj >= 0;) {
+      jB = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      aB = s0[jB];
+      bB = s1[jB];
+      cB = s2[jB];
+      pstep(jA, aA, bA, cA);
+      if (--jj < 0) break;
+      jA = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      aA = s0[jA];
+      bA = s1[jA];
+      cA = s2[jA];
+      pstep(jB, aB, bB, cB);
+      --jj;
     }
     __syncthreads();
     if ((int)threadIdx.x < cnt) {
