@@ -392,7 +392,7 @@ __device__ __forceinline__ void wave_sums(const float* g, float* out) {
   for (int i = 0; i < O; ++i) out[i] = row_sum16(swap16_sum(h[2 * i], h[2 * i + 1 < H ? 2 * i + 1 : 2 * i]));
 }
 
-constexpr int kBwdChunk = 32;   // list entries staged per round (full mode)
+constexpr int kBwdChunk = 64;   // list entries staged per round (full mode)
 constexpr int kWaveSlots = 4 * ((kGrad2D / 2 + 1) / 2);  // floats per wave partial (wave_sums slots)
 constexpr int kPartStride = 4 * kWaveSlots + 1;         // floats per entry: 4 wave partials, odd against bank conflicts
 
@@ -589,13 +589,13 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     }
     __syncthreads();
     {
-      // 8 threads per entry, each summing its values over the waves (bands)
-      // that reached the entry, in wave order; the partials of other waves
-      // are stale and skipped.  Thread 0 forms dL/du, dL/dv from the sums of
-      // ds dx and ds dy with the conic (A, B, C); threads 1..7 take values
-      // 2..9 (the last thread two of them).
+      // kBlock / kBwdChunk threads per entry, each summing its values over
+      // the waves (bands) that reached the entry, in wave order; the partials
+      // of other waves are stale and skipped.  Thread 0 forms dL/du, dL/dv
+      // from the sums of ds dx and ds dy with the conic (A, B, C); the other
+      // threads split values 2..9 between them.
       constexpr int kPer = kBlock / kBwdChunk;
-      static_assert(kPer == 8 && kGrad2D == 10, "value split assumes 8 threads per entry and 10 values");
+      static_assert(kPer >= 2 && kGrad2D == 10, "value split assumes at least two threads per entry and 10 values");
       const int j = threadIdx.x / kPer, t = threadIdx.x % kPer;
       const uint32_t mj = j < cnt ? smask[j] : 0u;
       if (mj != 0u) {
@@ -617,10 +617,11 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
           put(0, -(cA * sx + cB * sy));
           put(1, -(cB * sx + cC * sy));
         } else {
-          const int q = t + 1;
-          const float v = band_sum(q);
-          put(q, (q == 2 || q == 4) ? 0.5f * v : v);
-          if (t == kPer - 1) put(kGrad2D - 1, band_sum(kGrad2D - 1));
+          const int lo = 2 + ((t - 1) * (kGrad2D - 2)) / (kPer - 1), hi = 2 + (t * (kGrad2D - 2)) / (kPer - 1);
+          for (int q = lo; q < hi; ++q) {
+            const float v = band_sum(q);
+            put(q, (q == 2 || q == 4) ? 0.5f * v : v);
+          }
         }
       }
     }
