@@ -115,6 +115,42 @@ def test_bin_sort_bit_exact_with_ties(gpu):
             assert (s, e) == (0, 0)
 
 
+@pytest.mark.parametrize("n_items,seed", [(1500, 11), (9000, 12)])
+def test_bin_sort_bit_exact_long_tile_lists(gpu, n_items, seed):
+    """Tile lists from a few hundred to ~9,000 entries (items covering up to
+    the whole 5 x 3 tile grid), with equal-depth runs, culled items and a
+    ragged grid; the order must equal the oracle's (tile, depth bits, item)."""
+    rng = np.random.default_rng(seed)
+    s = synth.scene_tiny(seed, n_items, 70, 45, 60.0)  # 5 x 3 tiles, the last column and row partial
+    jobs = [(s["gauss"], s["cam"], s["w2c"])]
+    b = _batch(jobs, capacity=4 * n_items * 15)
+    camo = U.oracle_camera(s["cam"])
+    u = rng.uniform(-10.0, 80.0, n_items).astype(np.float32)
+    v = rng.uniform(-10.0, 55.0, n_items).astype(np.float32)
+    rad = rng.integers(1, 40, n_items).astype(np.int64)
+    rad[rng.random(n_items) < 0.05] = 0  # culled
+    z = rng.uniform(0.5, 9.0, n_items).astype(np.float32)
+    z[100:700] = np.float32(2.0)          # a long run of equal depths
+    z[1000::37] = z[1000]                 # scattered ties
+    x0, x1, y0, y1 = R.tile_rect_f32(u, v, rad, camo)
+    tl = np.where(rad > 0, np.maximum(x1 - x0, 0) * np.maximum(y1 - y0, 0), 0)
+    rad = np.where(tl > 0, rad, 0)
+    rc = np.zeros((n_items, 12), np.float32)
+    rc[:, 0], rc[:, 1], rc[:, 6] = u, v, z
+    rc[:, 2], rc[:, 4], rc[:, 5] = 0.01, 0.01, 0.5
+    _load_records(b, [(rc, rad.astype(np.int32), tl.astype(np.int32))])
+    exp_t, exp_i, ranges = R.bin_sort(u, v, z, rad, camo)
+    lens = np.diff(np.asarray(ranges), axis=1).ravel()
+    b.bin_sort()
+    n = b.instances()
+    assert n == len(exp_t) and int(b.count[1].item()) == 0
+    if n_items > 5000:
+        assert lens.max() > 4096  # lists longer than a radix-sort block takes
+    np.testing.assert_array_equal(b.tile_of[:n].cpu().numpy().astype(np.int64), exp_t)
+    np.testing.assert_array_equal(b.item[:n].cpu().numpy().astype(np.int64), exp_i)
+    np.testing.assert_array_equal(b.range.cpu().numpy().reshape(-1, 2), np.asarray(ranges).reshape(-1, 2))
+
+
 def test_render_fwd_same_inputs(gpu):
     jobs, poses = _three_scenes()
     b = _batch(jobs)
