@@ -325,7 +325,7 @@ __device__ __forceinline__ void composite_fwd_tile(const JobDev* __restrict__ jo
 
 // One block per tile (XCD-aware mapping), for launches with few tiles per
 // resident block.
-__global__ __launch_bounds__(kBlock) void k_composite_fwd(const JobDev* __restrict__ jobs,
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(8))) void k_composite_fwd(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
                                                           const int32_t* __restrict__ items,
