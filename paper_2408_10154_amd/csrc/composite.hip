@@ -491,10 +491,10 @@ __device__ __forceinline__ void stage_chunk(int lane, int cnt, int chunk, const 
   }
 }
 
-// Full mode: the ten image-space gradients of each Gaussian are summed over
-// each 16-lane row (DPP), the 16 row sums of the block over LDS in a fixed
-// order, and the result is added to the item's accumulator (one atomic per
-// value and tile).
+// Full mode: the ten per-pixel terms of each entry are summed over each
+// wave's 64 lanes (wave_sums), the four wave sums of the block over LDS in a
+// fixed order, and the ten gradients formed from them are added to the item's
+// accumulator (one atomic per nonzero value and tile).
 __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jobs,
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
@@ -677,7 +677,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDe
 // tile's running sum, written once as the tile's 12-value partial: no atomics,
 // so the pose gradient is deterministic and independent of the other renders.
 constexpr int kPoseChunk = 64;                    // entries staged per round
-constexpr int kPoseRow = 6;                       // du, dv, dA, dB, dC, d(depth weight)
+constexpr int kPoseRow = 6;                       // sums giving du, dv, dA, dB, dC, d(depth weight)
 constexpr int kPoseSlots = 4 * ((kPoseRow / 2 + 1) / 2);  // floats per wave partial (wave_sums slots)
 constexpr int kPoseStride = 4 * kPoseSlots + 1;   // floats per entry: 4 wave partials, odd against bank conflicts
 constexpr int kPoseQueue = kBlock;                // queued entries per Jacobian round
