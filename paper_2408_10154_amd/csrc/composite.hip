@@ -211,10 +211,12 @@ __device__ __forceinline__ int claim_tile(TileQueue* q, int T, int nstatic, bool
 }
 
 // After a block's last claim: the last block to exit re-zeroes the queue, so
-// the next launch (or graph replay) on the stream starts from zero.
+// the next launch (or graph replay) on the stream starts from zero.  No fence:
+// every claim of a block returned (its value decided the block's exit) before
+// the block counts itself done, and the atomics are ordered at the device
+// scope; a release fence here would write back the L2 once per block.
 __device__ __forceinline__ void release_queue(TileQueue* q) {
   if (threadIdx.x == 0) {
-    __threadfence();
     if (atomicAdd(&q->done.v, 1u) == gridDim.x - 1) {
       for (int x = 0; x < 8; ++x) atomicExch(&q->next[x].v, 0u);
       atomicExch(&q->done.v, 0u);
