@@ -9,6 +9,7 @@
 #include "common.h"
 #include "kernels.h"
 
+#include <cstdlib>
 #include <mutex>
 
 namespace ls {
@@ -967,8 +968,16 @@ void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int
 // one-block-per-tile kernel is faster (the loop-and-claim wrapper cost 4-5 %
 // on the 1200x680 render loop), with many the queues are (one 16-view
 // registration iteration: 8.5 % faster).  The residency is queried once per
-// (kernel, device) and cached.
+// (kernel, device) and cached.  The environment variable LS_PERSISTENT=0 / 1
+// forces the plain / persistent form (read at every launch; for tests and
+// measurements).
 static inline int xcd_grid(int total) { return 8 * ((total + 7) / 8); }
+
+static int forced_persistent() {
+  const char* e = std::getenv("LS_PERSISTENT");
+  if (!e || (e[0] != '0' && e[0] != '1') || e[1] != '\0') return -1;
+  return e[0] - '0';
+}
 
 struct PersistentGrid {
   bool on;
@@ -994,7 +1003,8 @@ static PersistentGrid persistent_grid(int which, const void* kernel, int T) {
     }
   }
   PersistentGrid g;
-  g.on = T > 4 * resident;
+  const int forced = forced_persistent();
+  g.on = forced >= 0 ? forced == 1 : T > 4 * resident;
   g.blocks = g.on ? resident + cus : xcd_grid(T);
   g.nstatic = g.on ? resident : 0;
   return g;

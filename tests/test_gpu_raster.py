@@ -379,6 +379,46 @@ def test_pose_only_backward_matches_full_and_is_bitwise_repeatable(gpu):
         assert U.rel_err(runs[0][r], full[r].cpu().numpy()) < 1e-4
 
 
+@pytest.mark.parametrize("pose_only", [False, True])
+def test_persistent_backward_matches_plain(gpu, monkeypatch, pose_only):
+    """The persistent backward kernels (tiles claimed from device queues; the
+    library picks them for launches with many tiles per resident block) give
+    what the one-block-per-tile kernels give: the pose-only gradient bit for
+    bit (per-tile partials, fixed-order reduction), the full-mode Gaussian
+    gradients to float-atomic ordering.  Each form runs twice, so the second
+    persistent launch also checks that the queues were left at zero."""
+    jobs, poses = _three_scenes()
+    b = _batch(jobs)
+    rng = np.random.default_rng(9)
+    up = synth.random_image_grads(rng, b.P)
+    dev = lambda x: torch.as_tensor(x, device="cuda")  # noqa: E731
+    pose = torch.as_tensor(np.stack(poses), device="cuda")
+    b.project(pose)
+    b.bin_sort()
+    b.render_fwd()
+    kw = dict(up_rgb=dev(up["rgb"].reshape(-1)), up_depth=dev(up["depth"]), up_alpha=dev(up["alpha"]), pose=pose)
+    out = {}
+    for mode in ("0", "1", "1", "0"):
+        monkeypatch.setenv("LS_PERSISTENT", mode)
+        pg = torch.zeros_like(pose)
+        grads = None if pose_only else [gs.zeros_like() for gs in b.gsets]
+        b.render_bwd(grads=grads, pose_grad=pg, **kw)
+        torch.cuda.synchronize()
+        res = [pg.cpu().numpy()] + ([] if pose_only else [t.cpu().numpy() for g in grads for t in g.tensors()])
+        out.setdefault(mode, []).append(res)
+    plain, pers = out["0"][0], out["1"][0]
+    if pose_only:
+        for mode in ("0", "1"):  # each form repeats itself bit for bit
+            np.testing.assert_array_equal(out[mode][0][0], out[mode][1][0])
+        np.testing.assert_array_equal(plain[0], pers[0])
+    else:
+        for mode in ("0", "1"):
+            for x, y in zip(out[mode][0], out[mode][1]):
+                assert U.rel_err(x, y) < 1e-5
+        for x, y in zip(pers, plain):
+            assert U.rel_err(x, y) < 1e-5
+
+
 @pytest.mark.parametrize("lambda_c,inlier_k,alpha_power", [(0.6, 50.0, 3), (0.3, 0.0, 0), (1.0, 2.0, 1)])
 def test_loss_tracking_matches_oracle(gpu, lambda_c, inlier_k, alpha_power):
     """Masked tracking loss on identical FP32 inputs: the median depth error of
