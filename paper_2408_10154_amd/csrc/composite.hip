@@ -218,9 +218,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
   const int lane = threadIdx.x;
   const int r = find_segment<int32_t>(tile_off, R, tile);
   const JobDev& J = jobs[r];
-  const int lt_ = tile - J.tile_off;
-  const int tyi = lt_ / J.TX, txi = lt_ - tyi * J.TX;
-  const int tx0 = txi * kTile, ty0 = tyi * kTile;
+  const int local = tile - J.tile_off;  // tile index within its render
+  const int tile_y = local / J.TX, tile_x = local - tile_y * J.TX;
+  const int tx0 = tile_x * kTile, ty0 = tile_y * kTile;
   const int x = tx0 + (lane & 15), y = ty0 + 4 * band + (lane >> 4);
   const bool inside = x < J.W && y < J.H;
   const int start = range[2 * tile], end = range[2 * tile + 1];
@@ -233,23 +233,23 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
   for (int chunk = start; chunk < end && alive != 0ull; chunk += 64) {
     const int e = chunk + lane;
     bool in = false;
-    float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a, cc = a;
+    float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;  // this lane's record
     if (e < end) {
       const int64_t it = items[e];
-      a = rec[it * 3 + 0];
-      b = rec[it * 3 + 1];
-      in = (wave_mask(a, b, tx0, ty0) >> band) & 1u;
+      r0 = rec[it * 3 + 0];
+      r1 = rec[it * 3 + 1];
+      in = (wave_mask(r0, r1, tx0, ty0) >> band) & 1u;
       if (in) {
-        stage_conic(a, b);
-        cc = rec[it * 3 + 2];
+        stage_conic(r0, r1);
+        r2 = rec[it * 3 + 2];
       }
     }
     const uint64_t bal = __ballot(in);
     if (in) {
       const int pos = __popcll(bal & lt);
-      s0[pos] = a;
-      s1[pos] = b;
-      s2[pos] = cc;
+      s0[pos] = r0;
+      s1[pos] = r1;
+      s2[pos] = r2;
       spos[pos] = e - start;
     }
     __builtin_amdgcn_wave_barrier();
@@ -276,7 +276,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
         T = u ? Tn : T;
       }
     };
-    // records read one entry ahead into alternating register sets (as in the block form)
+    // Records are read one entry ahead into two alternating register sets
+    // (the loop unrolled by hand, so no copies), so the LDS latency of the
+    // next entry overlaps the arithmetic of this one.  With no entries, entry
+    // 0 is read and never used.
     float4 aA = s0[0], bA = s1[0], cA = s2[0], aB, bB, cB;
     for (int jj = 0; jj < cw && alive != 0ull;) {
       const int jn = jj + 1 < cw ? jj + 1 : jj;
