@@ -353,6 +353,48 @@ def test_autograd_function_matches_direct_calls(gpu):
     assert math.isfinite(float(rgb.sum()))
 
 
+def test_small_workload_full_step_matches_oracle(gpu):
+    """The plain single-view workload exactly as configured (4,096 Gaussians,
+    160x120, f = 150): render at the identity pose, L1 loss against the render
+    at the 2 deg / 3 cm perturbed pose (the same FP32 target on both sides),
+    backward through the loss to every Gaussian parameter and the pose; all
+    80 tiles against the FP64 oracle."""
+    sc = synth.scene_small(0)
+    cam, w2c = sc["cam"], sc["w2c"]
+    b = _batch([(sc["gauss"], cam, w2c)])
+    b.project(torch.as_tensor(sc["target_pose"][None], device="cuda"))
+    b.bin_sort()
+    b.render_fwd()
+    tgt_rgb, tgt_depth = b.rgb.clone(), b.depth.clone()
+    pose_np = synth.identity_pose()
+    pose = torch.as_tensor(pose_np[None], device="cuda").contiguous()
+    b.project(pose)
+    b.bin_sort()
+    b.render_fwd()
+    loss, g_rgb, g_depth, g_scale = b.loss_l1(tgt_rgb, tgt_depth)
+    grads = [b.gsets[0].zeros_like()]
+    pose_grad = torch.zeros_like(pose)
+    b.render_bwd(up_rgb=g_rgb, up_depth=g_depth, scale=g_scale, grads=grads, pose=pose, pose_grad=pose_grad)
+    torch.cuda.synchronize()
+    g, pt, o = U.oracle_render(sc["gauss"], cam, w2c, pose_np, requires_grad=True)
+    H, W = cam["height"], cam["width"]
+    ok = o["margin"] >= 2e-4
+    assert ok.mean() > 0.99
+    v = b.image_views(0)
+    for key in ("rgb", "depth", "alpha"):
+        mask = ok[None] if key == "rgb" else ok
+        assert U.image_close(v[key].cpu().numpy(), o[key].detach().numpy(), mask) == 0, key
+    ref = R.loss_l1(o["rgb"], o["depth"], torch.as_tensor(tgt_rgb.cpu().numpy().reshape(3, H, W), dtype=F64),
+                    torch.as_tensor(tgt_depth.cpu().numpy().reshape(H, W), dtype=F64))
+    np.testing.assert_allclose(loss[0].item(), ref.item(), rtol=1e-4)
+    ref.backward()
+    for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
+        got = getattr(grads[0], name).cpu().numpy()
+        got = got.T if got.ndim == 2 else got
+        assert U.rel_err(got, g[name].grad.numpy()) < 1e-3, name
+    assert U.rel_err(pose_grad[0].cpu().numpy(), pt.grad.numpy()) < 1e-3
+
+
 def test_render_loop_workload_sampled_tiles_match_oracle(gpu):
     """The render-loop workload at its full size (200k Gaussians, 1200x680,
     1.6 M tile instances), run through the same calls and kernels the bench
