@@ -11,9 +11,11 @@ Modules
   raster    projection (EWA), tile binning, front-to-back compositing, L1 loss
   register  Adam, per-view keyframe localisation, weighted rotation averaging
             (paper Sec. 3.2, Eq. 7), transform errors
+  mapping   submap-update loss: L1 + SSIM colour term, depth term and the
+            isotropic scale regulariser (paper Sec. 3.1, Eq. 3-5)
 
 Every function with no independent pin is marked "parity unpinned" in its
 docstring; the pins live in tests/test_oracle_*.py.
 """
 
-from . import raster, register  # noqa: F401
+from . import mapping, raster, register  # noqa: F401
