@@ -41,6 +41,12 @@ if ROOT not in sys.path:
 # that is composited.
 FWD_EVAL, FWD_COMP = 14, 11
 BWD_EVAL, BWD_COMP = 14, 53
+# mapping-loss kernel, algorithmic work per pixel: HBM bytes (rendered and
+# target colour 24, rendered and target depth 8, colour and depth gradients
+# 16) and FP32 operations (separable 11-tap filtering of five moments and of
+# three derivative maps, the index and its derivatives: ~390 per channel).
+MAP_BYTES_PX = 48
+MAP_FLOPS_PX = 3 * 390
 PEAK_FP32_TFLOPS = 157.3   # MI355X published FP32 vector peak
 PEAK_HBM_GBS = 8000.0
 
@@ -74,6 +80,8 @@ def parse():
     ap.add_argument("--pairs", type=int, default=32, help="pairs in the batched-vs-plain registration set")
     ap.add_argument("--reg-iters", type=int, default=200)
     ap.add_argument("--no-registration", action="store_true")
+    ap.add_argument("--mapping-steps", type=int, default=20,
+                    help="timed iterations of the same loop with the full mapping loss (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
                     help="after the run, copy this many MiB device-to-device once (a known-size kernel that "
                          "calibrates HBM byte counters in a profiler run)")
@@ -250,6 +258,54 @@ def main():
     achieved = flops[dom] / (kms[dom] * 1e-3) / 1e12
     instances = b.instances()
 
+    mapping = None
+    if args.mapping_steps > 0:
+        # the same loop with the submap-update loss: L1 + SSIM colour term,
+        # depth term, isotropic scale regulariser (all weights 1, SSIM 0.2)
+        from paper_2408_10154_amd.render import loss_isotropic
+
+        reg_loss = torch.zeros(1, device="cuda")
+        work = torch.empty(L.LS_ISOTROPIC_WORK_FLOATS, device="cuda")
+        mev = []
+
+        def map_step(timed: bool):
+            b.project(pose)
+            L.ls_bin_sort(b.h, b.proj, b.bins, L.C.c_void_p(stream.cuda_stream))
+            b.render_fwd()
+            if timed:
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+            b.loss_mapping(tgt_rgb, tgt_depth, 0.2, 1.0, 1.0, loss, g_rgb, g_depth, g_scale)
+            if timed:
+                e1.record(stream)
+                mev.append((e0, e1))
+            b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=g_scale)
+            b.render_bwd_project(grads=[grads], pose=pose, pose_grad=pose_grad)
+            loss_isotropic(gs.log_scale, 1.0, loss=reg_loss, grad=grads.log_scale, work=work)
+            step_no[0] += 1
+            adam(groups, step_no[0])
+
+        for _ in range(3):
+            map_step(False)
+        torch.cuda.synchronize()
+        m0 = time.perf_counter()
+        for _ in range(args.mapping_steps):
+            map_step(True)
+        torch.cuda.synchronize()
+        mdt = (time.perf_counter() - m0) / args.mapping_steps
+        if int(b.count[1].item()) != 0:
+            raise RuntimeError("tile-instance capacity overflowed during the mapping steps")
+        lms = sum(a.elapsed_time(c) for a, c in mev) / len(mev)
+        px = cam["width"] * cam["height"]
+        mapping = {
+            "loss": "lambda_color (0.8 L1 + 0.2 (1 - SSIM)) + lambda_depth L1 + lambda_reg isotropic, weights 1",
+            "ms_per_step": round(mdt * 1e3, 4), "mpix_s": round(px / mdt / 1e6, 3),
+            "loss_ms": round(lms, 4),
+            "loss_roofline": {"hbm_frac": round(MAP_BYTES_PX * px / (lms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
+                              "alu_frac": round(MAP_FLOPS_PX * px / (lms * 1e-3) / 1e12 / PEAK_FP32_TFLOPS, 4)},
+            "last_loss": round(float(loss.item()) + float(reg_loss.item()), 5),
+        }
+
     if args.calib_copy_mb > 0:
         n = args.calib_copy_mb * (1 << 20) // 4
         src = torch.ones(n, dtype=torch.float32, device="cuda")
@@ -292,6 +348,7 @@ def main():
         "kernels_ms": {k: round(v, 4) for k, v in kms.items()},
         "fragments": {"evaluated": evaluated, "composited": composited},
         "loss": {"first_timed": round(loss0, 5), "last": round(loss1, 5)},
+        "mapping": mapping,
         "registration": reg,
         "cpu_baseline": cpu,
     }

@@ -304,6 +304,49 @@ ls_status ls_loss_tracking(const ls_batch* b, const ls_image* pred, const float*
                            const ls_loss_params* prm, float* loss, float* median, float* grad_rgb, float* grad_depth,
                            float* grad_scale, hipStream_t s);
 
+/* Weights of the submap-update (mapping) loss, Sec. 3.1 Eq. 3 and Eq. 4;
+ * the supplement sets lambda_color = lambda_depth = 1 (and lambda_reg = 1,
+ * see ls_loss_isotropic); the paper gives no lambda_ssim (0.2 is the usual
+ * value). */
+typedef struct {
+  float lambda_ssim;   /* weight of (1 - SSIM) inside the colour term, in [0, 1] */
+  float lambda_color;  /* weight of the colour term */
+  float lambda_depth;  /* weight of the depth term */
+  int32_t pad;
+} ls_mapping_params;
+
+/* Image part of the mapping loss (Sec. 3.1 Eq. 3 and Eq. 4): per render
+ *   L_r = lc ((1 - ls) L1_rgb + ls (1 - SSIM)) + ld L1_depth,
+ *   L1_rgb   = (1/|Omega|) sum_{p in Omega} sum_c |C_c - C*_c|,
+ *   L1_depth = (1/|Omega|) sum_{p in Omega} |D - D*|   (0 when Omega is empty),
+ * Omega = pixels with target depth > 0.  SSIM is the mean over the three
+ * colour channels and all pixels of the windowed index of Wang et al. with an
+ * 11 x 11 Gaussian window (sigma 1.5, weights summing to 1), zero padding
+ * outside the image, C1 = 0.01^2, C2 = 0.03^2, moments E[xy] - mu_x mu_y.
+ *   loss       device [R] (written), or NULL
+ *   grad_rgb, grad_depth: device, image layout, or NULL; receive dL_r/dC and
+ *              dL_r/dD with every weight and normalisation applied
+ *   grad_scale device [R] (written with 1), or NULL: pass it as
+ *              ls_image_grad.scale like the other losses' scales.
+ * Uses the batch's loss scratch: do not overlap with another loss call on
+ * the same batch.  Errors: LS_ERR_INVALID (NULL images or targets, weights
+ * not finite or lambda_ssim outside [0, 1]). */
+ls_status ls_loss_mapping(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
+                          const ls_mapping_params* prm, float* loss, float* grad_rgb, float* grad_depth,
+                          float* grad_scale, hipStream_t s);
+
+/* Isotropic regulariser of one submap (Sec. 3.1 Eq. 5):
+ *   L = lambda_reg (1/K) sum_k sum_j |s_kj - mean_j(s_kj)|,  s = exp(log_scale),
+ * the mean over the three axes being differentiated through.
+ *   log_scale       device [3][n] (the ls_gaussians layout), n >= 0
+ *   loss            device [1] (written; 0 when n = 0)
+ *   grad_log_scale  device [3][n], accumulated (+=), or NULL
+ *   work            device scratch of LS_ISOTROPIC_WORK_FLOATS floats
+ * The sum is taken in a fixed order (bit-reproducible).  Errors: LS_ERR_INVALID. */
+#define LS_ISOTROPIC_WORK_FLOATS 256
+ls_status ls_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, float* loss, float* grad_log_scale,
+                            float* work, hipStream_t s);
+
 /* One parameter group of a fused Adam step. */
 typedef struct {
   float* param;

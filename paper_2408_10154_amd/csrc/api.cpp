@@ -173,6 +173,7 @@ int64_t ls_struct_size(const char* name) {
       {"ls_pair", sizeof(ls_pair)},                 {"ls_reg_params", sizeof(ls_reg_params)},
       {"ls_reg_result", sizeof(ls_reg_result)},     {"ls_server_params", sizeof(ls_server_params)},
       {"ls_server_stats", sizeof(ls_server_stats)}, {"ls_loss_params", sizeof(ls_loss_params)},
+      {"ls_mapping_params", sizeof(ls_mapping_params)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -190,6 +191,7 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
   b->tile_off.assign(R + 1, 0);
   b->blk_off.assign(R + 1, 0);
   b->pblk_off.assign(R + 1, 0);
+  b->sblk_off.assign(R + 1, 0);
   b->jobs_h.resize(R);
   for (int r = 0; r < R; ++r) {
     const ls_render_job& j = jobs[r];
@@ -237,6 +239,7 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
     b->tile_off[r + 1] = b->tile_off[r] + TX * TY;
     b->blk_off[r + 1] = b->blk_off[r] + (j.g.n + 255) / 256;
     b->pblk_off[r + 1] = b->pblk_off[r] + (int32_t)((hw + 1023) / 1024);
+    b->sblk_off[r + 1] = b->sblk_off[r] + ls::ssim_blocks(K.width, K.height);
     if (b->item_off[r + 1] > INT32_MAX || b->tile_off[r + 1] < 0) {
       delete b;
       return fail(LS_ERR_INVALID, "batch too large (items or tiles exceed int32)");
@@ -247,6 +250,7 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
   b->T = b->tile_off[R];
   b->nblk_items = b->blk_off[R];
   b->nblk_pix = b->pblk_off[R];
+  b->nblk_ssim = b->sblk_off[R];
   int bits = 0;
   while (bits < 32 && ((int64_t)1 << bits) < (int64_t)b->T) ++bits;
   b->tile_passes = (bits + kTileDigitBits - 1) / kTileDigitBits;
@@ -257,11 +261,12 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
   ls_status st;
   if ((st = upload(&b->jobs_d, b->jobs_h)) || (st = upload(&b->item_off_d, b->item_off)) ||
       (st = upload(&b->tile_off_d, b->tile_off)) || (st = upload(&b->blk_off_d, b->blk_off)) ||
-      (st = upload(&b->pblk_off_d, b->pblk_off))) {
+      (st = upload(&b->pblk_off_d, b->pblk_off)) || (st = upload(&b->sblk_off_d, b->sblk_off))) {
     ls_batch_destroy(b);
     return st;
   }
   if (hipMalloc(reinterpret_cast<void**>(&b->loss_part_d), 8 * std::max(b->nblk_pix, 1)) != hipSuccess ||
+      hipMalloc(reinterpret_cast<void**>(&b->map_part_d), 4 * (3 * (size_t)b->nblk_ssim + R)) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&b->grads_d), sizeof(GradDev) * R) != hipSuccess ||
       hipMalloc(reinterpret_cast<void**>(&b->sel_d), 4 * ls::sel_words(R)) != hipSuccess ||
       hipMemset(b->sel_d, 0, 4 * ls::sel_words(R)) != hipSuccess ||
@@ -281,6 +286,8 @@ ls_status ls_batch_destroy(ls_batch* b) {
   hipFree(b->tile_off_d);
   hipFree(b->blk_off_d);
   hipFree(b->pblk_off_d);
+  hipFree(b->sblk_off_d);
+  hipFree(b->map_part_d);
   hipFree(b->loss_part_d);
   hipFree(b->sel_d);
   hipFree(b->median_d);
@@ -461,6 +468,33 @@ ls_status ls_loss_tracking(const ls_batch* b, const ls_image* pred, const float*
                     tgt_depth, prm->lambda_c, prm->inlier_k, prm->alpha_power, b->sel_d,
                     median ? median : b->median_d, grad_rgb, grad_depth, b->loss_part_d, loss, grad_scale, s);
   return hip_check("ls_loss_tracking");
+}
+
+ls_status ls_loss_mapping(const ls_batch* b, const ls_image* pred, const float* tgt_rgb, const float* tgt_depth,
+                          const ls_mapping_params* prm, float* loss, float* grad_rgb, float* grad_depth,
+                          float* grad_scale, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  if (!pred || !pred->rgb || !pred->depth || !tgt_rgb || !tgt_depth)
+    return fail(LS_ERR_INVALID, "NULL image arguments");
+  if (!prm) return fail(LS_ERR_INVALID, "NULL mapping-loss parameters");
+  if (!std::isfinite(prm->lambda_color) || !std::isfinite(prm->lambda_depth) || !(prm->lambda_ssim >= 0.f) ||
+      !(prm->lambda_ssim <= 1.f))
+    return fail(LS_ERR_INVALID, "mapping-loss weights must be finite, lambda_ssim in [0, 1]");
+  ls_status st;
+  if ((st = ensure_device(b))) return st;
+  launch_loss_mapping(b->jobs_d, b->pblk_off_d, b->nblk_pix, b->sblk_off_d, b->nblk_ssim, b->R, pred->rgb,
+                      pred->depth, tgt_rgb, tgt_depth, prm->lambda_ssim, prm->lambda_color, prm->lambda_depth,
+                      grad_rgb, grad_depth, b->loss_part_d, b->map_part_d, loss, grad_scale, s);
+  return hip_check("ls_loss_mapping");
+}
+
+ls_status ls_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, float* loss, float* grad_log_scale,
+                            float* work, hipStream_t s) {
+  if (n < 0 || n > INT32_MAX) return fail(LS_ERR_INVALID, "n out of range");
+  if (!loss || !work || (n > 0 && !log_scale)) return fail(LS_ERR_INVALID, "NULL arguments");
+  if (!std::isfinite(lambda_reg)) return fail(LS_ERR_INVALID, "lambda_reg must be finite");
+  launch_loss_isotropic(log_scale, n, lambda_reg, loss, grad_log_scale, work, s);
+  return hip_check("ls_loss_isotropic");
 }
 
 ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2, float eps,

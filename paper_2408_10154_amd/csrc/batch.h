@@ -15,17 +15,20 @@ struct ls_batch {
   int64_t P = 0;
   int nblk_items = 0;
   int nblk_pix = 0;
+  int nblk_ssim = 0;  // mapping-loss SSIM blocks (3 channels x 32x32 tiles per render)
   int tile_passes = 0;
   int device = 0;
   std::vector<JobDev> jobs_h;
   std::vector<int64_t> item_off, pix_off;
-  std::vector<int32_t> tile_off, blk_off, pblk_off;
+  std::vector<int32_t> tile_off, blk_off, pblk_off, sblk_off;
   JobDev* jobs_d = nullptr;
   int64_t* item_off_d = nullptr;
   int32_t* tile_off_d = nullptr;
   int32_t* blk_off_d = nullptr;
   int32_t* pblk_off_d = nullptr;
+  int32_t* sblk_off_d = nullptr;
   float* loss_part_d = nullptr;
+  float* map_part_d = nullptr;   // mapping loss: 3 floats per SSIM block, then 1/|Omega| per render
   uint32_t* sel_d = nullptr;     // median selection workspace (ls::sel_words(R)), kept zeroed
   float* median_d = nullptr;     // [R] median depth error of the last tracking loss
   GradDev* grads_d = nullptr;

@@ -69,6 +69,20 @@ void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int
                        float* g_depth, float* part, float* loss, float* scale, hipStream_t s);
 inline int64_t sel_words(int R) { return (int64_t)R * (4 + 2048); }
 
+// Mapping loss (mapping_loss.hip).  SSIM blocks of a W x H render (3 colour
+// channels x 32 x 32 tiles); cnt_part: one float per 1024-pixel block;
+// map_part: 3 floats per SSIM block + R.
+int ssim_blocks(int W, int H);
+void launch_loss_mapping(const JobDev* jobs, const int32_t* pblk_off_d, int npblk, const int32_t* sblk_off_d,
+                         int nsblk, int R, const float* pred_rgb, const float* pred_depth, const float* tgt_rgb,
+                         const float* tgt_depth, float lambda_ssim, float lambda_color, float lambda_depth,
+                         float* g_rgb, float* g_depth, float* cnt_part, float* map_part, float* loss, float* scale,
+                         hipStream_t s);
+// Isotropic regulariser; part = kIsotropicBlocks floats.
+constexpr int kIsotropicBlocks = LS_ISOTROPIC_WORK_FLOATS;
+void launch_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, float* loss, float* grad, float* part,
+                           hipStream_t s);
+
 void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,
                  int zero_grad, hipStream_t s);
 

@@ -84,6 +84,11 @@ class ls_loss_params(C.Structure):
     _fields_ = [("lambda_c", C.c_float), ("inlier_k", C.c_float), ("alpha_power", C.c_int32), ("pad", C.c_int32)]
 
 
+class ls_mapping_params(C.Structure):
+    _fields_ = [("lambda_ssim", C.c_float), ("lambda_color", C.c_float), ("lambda_depth", C.c_float),
+                ("pad", C.c_int32)]
+
+
 class ls_reg_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lr_rot", C.c_float), ("lr_trans", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("exit_rel_tol", C.c_float),
@@ -112,6 +117,8 @@ class ls_adam_group(C.Structure):
                 ("n", C.c_int64), ("lr", C.c_float)]
 
 
+LS_ISOTROPIC_WORK_FLOATS = 256  # scratch floats of ls_loss_isotropic
+
 _P = C.c_void_p
 _PROTOS = {
     "ls_last_error": (C.c_char_p, []),
@@ -134,6 +141,9 @@ _PROTOS = {
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
     "ls_loss_tracking": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, C.POINTER(ls_loss_params), _P, _P, _P, _P, _P,
                                      _P]),
+    "ls_loss_mapping": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, C.POINTER(ls_mapping_params), _P, _P, _P,
+                                    _P, _P]),
+    "ls_loss_isotropic": (C.c_int32, [_P, C.c_int64, C.c_float, _P, _P, _P, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
@@ -238,6 +248,15 @@ def ls_loss_l1(h, pred, tgt_rgb, tgt_depth, loss, grad_rgb, grad_depth, grad_sca
 def ls_loss_tracking(h, pred, tgt_rgb, tgt_depth, prm, loss, median, grad_rgb, grad_depth, grad_scale, stream):
     return _call("ls_loss_tracking", h, C.byref(pred), tgt_rgb, tgt_depth, C.byref(prm), loss, median, grad_rgb,
                  grad_depth, grad_scale, stream)
+
+
+def ls_loss_mapping(h, pred, tgt_rgb, tgt_depth, prm, loss, grad_rgb, grad_depth, grad_scale, stream):
+    return _call("ls_loss_mapping", h, C.byref(pred), tgt_rgb, tgt_depth, C.byref(prm), loss, grad_rgb, grad_depth,
+                 grad_scale, stream)
+
+
+def ls_loss_isotropic(log_scale, n, lambda_reg, loss, grad_log_scale, work, stream):
+    return _call("ls_loss_isotropic", log_scale, n, lambda_reg, loss, grad_log_scale, work, stream)
 
 
 def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):

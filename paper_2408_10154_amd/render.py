@@ -258,6 +258,25 @@ class RenderBatch:
                            _ptr(grad_rgb), _ptr(grad_depth), _ptr(grad_scale), _stream())
         return loss, median, grad_rgb, grad_depth, grad_scale
 
+    def loss_mapping(self, tgt_rgb, tgt_depth, lambda_ssim=0.2, lambda_color=1.0, lambda_depth=1.0, loss=None,
+                     grad_rgb=None, grad_depth=None, grad_scale=None):
+        """Image part of the submap-update loss (L1 + SSIM colour term and L1
+        depth term) on the batch's images; the gradients come fully weighted
+        and grad_scale is 1."""
+        dev = self.device
+        loss = torch.zeros(self.R, dtype=torch.float32, device=dev) if loss is None else loss
+        grad_rgb = torch.empty_like(self.rgb) if grad_rgb is None else grad_rgb
+        grad_depth = torch.empty_like(self.depth) if grad_depth is None else grad_depth
+        grad_scale = torch.zeros(self.R, dtype=torch.float32, device=dev) if grad_scale is None else grad_scale
+        self._check_dev(tgt_rgb, 3 * self.P, name="tgt_rgb")
+        self._check_dev(tgt_depth, self.P, name="tgt_depth")
+        for t, n in ((loss, self.R), (grad_rgb, 3 * self.P), (grad_depth, self.P), (grad_scale, self.R)):
+            self._check_dev(t, n)
+        prm = L.ls_mapping_params(float(lambda_ssim), float(lambda_color), float(lambda_depth), 0)
+        L.ls_loss_mapping(self.h, self.image, _ptr(tgt_rgb), _ptr(tgt_depth), prm, _ptr(loss), _ptr(grad_rgb),
+                          _ptr(grad_depth), _ptr(grad_scale), _stream())
+        return loss, grad_rgb, grad_depth, grad_scale
+
     # ------------------------------------------------------------ views
     def image_views(self, r: int):
         cam = self.cams[r]
@@ -270,6 +289,21 @@ class RenderBatch:
             T_final=self.T_final[p0: p0 + H * W].view(H, W),
             n_last=self.n_last[p0: p0 + H * W].view(H, W),
         )
+
+
+def loss_isotropic(log_scale: torch.Tensor, lambda_reg: float = 1.0, loss=None, grad=None, work=None):
+    """Isotropic scale regulariser of one Gaussian set: log_scale [3, n]
+    device tensor; grad (same shape) is accumulated when given."""
+    if log_scale.dim() != 2 or log_scale.shape[0] != 3 or not log_scale.is_contiguous() or not log_scale.is_cuda:
+        raise ValueError("log_scale must be a contiguous [3, n] device tensor")
+    n = log_scale.shape[1]
+    dev = log_scale.device
+    loss = torch.zeros(1, dtype=torch.float32, device=dev) if loss is None else loss
+    work = torch.empty(L.LS_ISOTROPIC_WORK_FLOATS, dtype=torch.float32, device=dev) if work is None else work
+    if grad is not None and (grad.shape != log_scale.shape or not grad.is_contiguous()):
+        raise ValueError("grad must match log_scale")
+    L.ls_loss_isotropic(_ptr(log_scale), n, float(lambda_reg), _ptr(loss), _ptr(grad), _ptr(work), _stream())
+    return loss
 
 
 def adam(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=True):
