@@ -22,14 +22,25 @@ constexpr int kSsimT = 32;                   // output tile side
 constexpr int kSsimM = kSsimT + 2 * kSsimR;  // 42: side of the region whose SSIM terms reach the tile
 constexpr int kSsimI = kSsimT + 4 * kSsimR;  // 52: side of the input region those terms read
 constexpr int kSsimIn = kSsimI * kSsimI;     // 2704
+constexpr int kSsimLoadPer = (kSsimIn + kBlock - 1) / kBlock;  // 11 input values per thread
 constexpr int kSsimRowMom = kSsimI * kSsimM; // 2184: row-filtered moments per map
 constexpr int kSsimMom = kSsimM * kSsimM;    // 1764: SSIM terms per map
-constexpr int kSsimMomPer = (kSsimMom + kBlock - 1) / kBlock;  // 7 per thread
 constexpr int kSsimRowD = kSsimM * kSsimT;   // 1344: row-filtered derivatives per map
-constexpr int kSsimOutPer = kSsimT * kSsimT / kBlock;         // 4 output pixels per thread
+// Each filter pass gives a work item a strip of consecutive outputs along the
+// filter direction, so an input is read from LDS once per strip rather than
+// once per tap.
+constexpr int kRowStrip = 6;                         // moment row pass: 52 rows x 7 strips
+constexpr int kRowStrips = kSsimM / kRowStrip;
+constexpr int kColStrip = 7;                         // moment column pass: 42 columns x 6 strips
+constexpr int kColStrips = kSsimM / kColStrip;
+constexpr int kDRowStrip = 8;                        // derivative row pass: 42 rows x 4 strips
+constexpr int kDRowStrips = kSsimT / kDRowStrip;
+constexpr int kOutStrip = kSsimT * kSsimT / kBlock;  // derivative column pass: 32 columns x 8 strips of 4
+static_assert(kSsimM % kRowStrip == 0 && kSsimM % kColStrip == 0 && kSsimT % kDRowStrip == 0, "whole strips");
+static_assert(kSsimM * kColStrips <= kBlock, "one column strip per thread");
+static_assert(kSsimT * (kSsimT / kOutStrip) == kBlock, "one output strip per thread");
 constexpr float kSsimC1 = 0.01f * 0.01f;
 constexpr float kSsimC2 = 0.03f * 0.03f;
-static_assert(kSsimT * kSsimT % kBlock == 0, "whole output pixels per thread");
 static_assert(3 * kSsimRowD <= 2 * kSsimIn, "row-filtered derivatives fit the input buffer");
 static_assert(3 * kSsimMom <= 5 * kSsimRowMom, "derivative maps fit the moment buffer");
 
@@ -62,14 +73,23 @@ __global__ __launch_bounds__(256) void k_valid_count(const JobDev* __restrict__ 
   if (threadIdx.x == 0) part[blockIdx.x] = (ws[0] + ws[1]) + (ws[2] + ws[3]);
 }
 
-// One wave per render: 1 / |Omega| (0 when no pixel has a target depth).
-__global__ void k_valid_inv(const int32_t* __restrict__ pblk_off, int R, const float* __restrict__ part,
-                            float* __restrict__ inv) {
+// Block-wide sum of one value per thread (256 threads), fixed order; the
+// total is returned to thread 0.
+__device__ __forceinline__ float block_sum(float v, float* ws) {
+  v = wave_sum(v);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = v;
+  __syncthreads();
+  return (ws[0] + ws[1]) + (ws[2] + ws[3]);
+}
+
+// One block per render: 1 / |Omega| (0 when no pixel has a target depth).
+__global__ __launch_bounds__(256) void k_valid_inv(const int32_t* __restrict__ pblk_off, int R,
+                                                   const float* __restrict__ part, float* __restrict__ inv) {
+  __shared__ float ws[4];
   const int r = blockIdx.x;
-  if (r >= R) return;
   float c = 0.f;
-  for (int b = pblk_off[r] + threadIdx.x; b < pblk_off[r + 1]; b += 64) c += part[b];
-  c = wave_sum(c);
+  for (int b = pblk_off[r] + threadIdx.x; b < pblk_off[r + 1]; b += kBlock) c += part[b];
+  c = block_sum(c, ws);
   if (threadIdx.x == 0) inv[r] = c > 0.f ? 1.f / c : 0.f;
 }
 
@@ -109,154 +129,227 @@ __global__ __launch_bounds__(256) void k_loss_ssim(const JobDev* __restrict__ jo
 
   float* sx = sA;
   float* sy = sA + kSsimIn;
-  for (int i = threadIdx.x; i < kSsimIn; i += kBlock) {
-    const int rr = i / kSsimI, cc = i - rr * kSsimI;
-    const int gy = y0 - 2 * kSsimR + rr, gx = x0 - 2 * kSsimR + cc;
-    float xv = 0.f, yv = 0.f;
-    if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+  {
+    // every load of the input region is issued before the first is used
+    float xv[kSsimLoadPer], yv[kSsimLoadPer];
+#pragma unroll
+    for (int j = 0; j < kSsimLoadPer; ++j) {
+      const int i = threadIdx.x + kBlock * j;
+      const int rr = i / kSsimI, cc = i - rr * kSsimI;
+      const int gy = y0 - 2 * kSsimR + rr, gx = x0 - 2 * kSsimR + cc;
+      xv[j] = 0.f;
+      yv[j] = 0.f;
+      if (i < kSsimIn && gx >= 0 && gx < W && gy >= 0 && gy < H) {
+        const int64_t p = (int64_t)gy * W + gx;
+        xv[j] = X[p];
+        yv[j] = Y[p];
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < kSsimLoadPer; ++j) {
+      const int i = threadIdx.x + kBlock * j;
+      if (i < kSsimIn) {
+        sx[i] = xv[j];
+        sy[i] = yv[j];
+      }
+    }
+  }
+  __syncthreads();
+
+  // this thread's output strip (column ocol, rows o0 .. o0 + kOutStrip - 1):
+  // centre values from LDS, depths issued now and used at the end
+  const int ocol = threadIdx.x % kSsimT, o0 = (threadIdx.x / kSsimT) * kOutStrip;
+  float xq[kOutStrip], yq[kOutStrip], tq[kOutStrip], dq[kOutStrip];
+#pragma unroll
+  for (int q = 0; q < kOutStrip; ++q) {
+    const int li = (o0 + q + 2 * kSsimR) * kSsimI + ocol + 2 * kSsimR;
+    xq[q] = sx[li];
+    yq[q] = sy[li];
+    const int gy = y0 + o0 + q, gx = x0 + ocol;
+    tq[q] = dq[q] = 0.f;
+    if (gx < W && gy < H) {
       const int64_t p = (int64_t)gy * W + gx;
-      xv = X[p];
-      yv = Y[p];
+      tq[q] = tgt_depth ? tgt_depth[J.pix_off + p] : J.tgt_depth[p];
+      if (ch == 0) dq[q] = pred_depth[J.pix_off + p];
     }
-    sx[i] = xv;
-    sy[i] = yv;
-  }
-  __syncthreads();
-
-  // centre values of this thread's output pixels (rows tid/32 + 8k)
-  float cx[kSsimOutPer], cy[kSsimOutPer];
-#pragma unroll
-  for (int k = 0; k < kSsimOutPer; ++k) {
-    const int o = threadIdx.x + kBlock * k;
-    const int li = ((o / kSsimT) + 2 * kSsimR) * kSsimI + (o % kSsimT) + 2 * kSsimR;
-    cx[k] = sx[li];
-    cy[k] = sy[li];
   }
 
-  // row pass: the five moments over each input row, for the 42 moment columns
-  for (int i = threadIdx.x; i < kSsimRowMom; i += kBlock) {
-    const int rr = i / kSsimM, mc = i - rr * kSsimM;
-    const float* xr = sx + rr * kSsimI + mc;
-    const float* yr = sy + rr * kSsimI + mc;
-    float a = 0.f, b = 0.f, c = 0.f, d = 0.f, e = 0.f;
+  // row pass: the five moments of each input row at the 42 moment columns,
+  // kRowStrip consecutive columns per work item (each input read once)
+  for (int it = threadIdx.x; it < kSsimI * kRowStrips; it += kBlock) {
+    const int rr = it / kRowStrips, c0 = (it - rr * kRowStrips) * kRowStrip;
+    const float* xr = sx + rr * kSsimI + c0;
+    const float* yr = sy + rr * kSsimI + c0;
+    float a[kRowStrip], b[kRowStrip], c[kRowStrip], d[kRowStrip], e[kRowStrip];
 #pragma unroll
-    for (int k = 0; k < kSsimTaps; ++k) {
+    for (int o = 0; o < kRowStrip; ++o) a[o] = b[o] = c[o] = d[o] = e[o] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kRowStrip + 2 * kSsimR; ++k) {
       const float xv = xr[k], yv = yr[k];
-      const float wx = win.w[k] * xv, wy = win.w[k] * yv;
-      a += wx;
-      b += wy;
-      c += wx * xv;
-      d += wy * yv;
-      e += wx * yv;
+      const float xx = xv * xv, yy = yv * yv, xy = xv * yv;
+#pragma unroll
+      for (int o = 0; o < kRowStrip; ++o) {
+        const int tap = k - o;
+        if (tap >= 0 && tap < kSsimTaps) {
+          const float w = win.w[tap];
+          a[o] += w * xv;
+          b[o] += w * yv;
+          c[o] += w * xx;
+          d[o] += w * yy;
+          e[o] += w * xy;
+        }
+      }
     }
-    sB[i] = a;
-    sB[kSsimRowMom + i] = b;
-    sB[2 * kSsimRowMom + i] = c;
-    sB[3 * kSsimRowMom + i] = d;
-    sB[4 * kSsimRowMom + i] = e;
+    float* out = sB + rr * kSsimM + c0;
+#pragma unroll
+    for (int o = 0; o < kRowStrip; ++o) {
+      out[o] = a[o];
+      out[kSsimRowMom + o] = b[o];
+      out[2 * kSsimRowMom + o] = c[o];
+      out[3 * kSsimRowMom + o] = d[o];
+      out[4 * kSsimRowMom + o] = e[o];
+    }
   }
   __syncthreads();
 
-  // column pass, SSIM index and its derivative maps on the 42 x 42 region
-  float dA[kSsimMomPer], dB[kSsimMomPer], dC[kSsimMomPer];
+  // column pass, SSIM index and its derivative maps on the 42 x 42 region:
+  // one strip of kColStrip rows of one moment column per thread
+  float dA[kColStrip], dB[kColStrip], dC[kColStrip];
   float ssum = 0.f;
+  const int mc = threadIdx.x % kSsimM, r0 = (threadIdx.x / kSsimM) * kColStrip;
+  const bool col_item = threadIdx.x < kSsimM * kColStrips;
 #pragma unroll
-  for (int j = 0; j < kSsimMomPer; ++j) {
-    const int i = threadIdx.x + kBlock * j;
-    dA[j] = 0.f;
-    dB[j] = 0.f;
-    dC[j] = 0.f;
-    if (i < kSsimMom) {
-      const int mr = i / kSsimM, mc = i - mr * kSsimM;
-      const int gy = y0 - kSsimR + mr, gx = x0 - kSsimR + mc;
-      if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
-        float mx = 0.f, my = 0.f, exx = 0.f, eyy = 0.f, exy = 0.f;
+  for (int q = 0; q < kColStrip; ++q) dA[q] = dB[q] = dC[q] = 0.f;
+  if (col_item) {
+    float mx[kColStrip], my[kColStrip], exx[kColStrip], eyy[kColStrip], exy[kColStrip];
 #pragma unroll
-        for (int k = 0; k < kSsimTaps; ++k) {
-          const int o = (mr + k) * kSsimM + mc;
-          const float w = win.w[k];
-          mx += w * sB[o];
-          my += w * sB[kSsimRowMom + o];
-          exx += w * sB[2 * kSsimRowMom + o];
-          eyy += w * sB[3 * kSsimRowMom + o];
-          exy += w * sB[4 * kSsimRowMom + o];
+    for (int q = 0; q < kColStrip; ++q) mx[q] = my[q] = exx[q] = eyy[q] = exy[q] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kColStrip + 2 * kSsimR; ++k) {
+      const int o = (r0 + k) * kSsimM + mc;
+      const float v0 = sB[o], v1 = sB[kSsimRowMom + o], v2 = sB[2 * kSsimRowMom + o];
+      const float v3 = sB[3 * kSsimRowMom + o], v4 = sB[4 * kSsimRowMom + o];
+#pragma unroll
+      for (int q = 0; q < kColStrip; ++q) {
+        const int tap = k - q;
+        if (tap >= 0 && tap < kSsimTaps) {
+          const float w = win.w[tap];
+          mx[q] += w * v0;
+          my[q] += w * v1;
+          exx[q] += w * v2;
+          eyy[q] += w * v3;
+          exy[q] += w * v4;
         }
-        const float vx = exx - mx * mx, vy = eyy - my * my, cxy = exy - mx * my;
-        const float n1 = 2.f * mx * my + kSsimC1, n2 = 2.f * cxy + kSsimC2;
-        const float i1 = 1.f / (mx * mx + my * my + kSsimC1), i2 = 1.f / (vx + vy + kSsimC2);
-        const float s = n1 * n2 * i1 * i2;
-        dA[j] = 2.f * my * (n2 - n1) * i1 * i2 - 2.f * mx * s * (i1 - i2);
-        dB[j] = -s * i2;
-        dC[j] = 2.f * n1 * i1 * i2;
-        if (mr >= kSsimR && mr < kSsimR + kSsimT && mc >= kSsimR && mc < kSsimR + kSsimT) ssum += s;
+      }
+    }
+    const int gx = x0 - kSsimR + mc;
+#pragma unroll
+    for (int q = 0; q < kColStrip; ++q) {
+      const int mr = r0 + q;
+      const int gy = y0 - kSsimR + mr;
+      if (gx >= 0 && gx < W && gy >= 0 && gy < H) {
+        const float vx = exx[q] - mx[q] * mx[q], vy = eyy[q] - my[q] * my[q], cxy = exy[q] - mx[q] * my[q];
+        const float n1 = 2.f * mx[q] * my[q] + kSsimC1, n2 = 2.f * cxy + kSsimC2;
+        const float i1 = 1.f / (mx[q] * mx[q] + my[q] * my[q] + kSsimC1), i2 = 1.f / (vx + vy + kSsimC2);
+        const float sv = n1 * n2 * i1 * i2;
+        dA[q] = 2.f * my[q] * (n2 - n1) * i1 * i2 - 2.f * mx[q] * sv * (i1 - i2);
+        dB[q] = -sv * i2;
+        dC[q] = 2.f * n1 * i1 * i2;
+        if (mr >= kSsimR && mr < kSsimR + kSsimT && mc >= kSsimR && mc < kSsimR + kSsimT) ssum += sv;
       }
     }
   }
   __syncthreads();  // every thread is done with the moments
+  if (col_item) {
 #pragma unroll
-  for (int j = 0; j < kSsimMomPer; ++j) {
-    const int i = threadIdx.x + kBlock * j;
-    if (i < kSsimMom) {
-      sB[i] = dA[j];
-      sB[kSsimMom + i] = dB[j];
-      sB[2 * kSsimMom + i] = dC[j];
+    for (int q = 0; q < kColStrip; ++q) {
+      const int i = (r0 + q) * kSsimM + mc;
+      sB[i] = dA[q];
+      sB[kSsimMom + i] = dB[q];
+      sB[2 * kSsimMom + i] = dC[q];
     }
   }
   __syncthreads();
 
-  // row pass over the derivative maps: 42 rows x 32 output columns
-  for (int i = threadIdx.x; i < kSsimRowD; i += kBlock) {
-    const int mr = i / kSsimT, oc = i - mr * kSsimT;
-    const int o = mr * kSsimM + oc;
-    float a = 0.f, b = 0.f, c = 0.f;
+  // row pass over the derivative maps: 42 rows x 32 output columns,
+  // kDRowStrip columns per work item
+  for (int it = threadIdx.x; it < kSsimM * kDRowStrips; it += kBlock) {
+    const int mr = it / kDRowStrips, c0 = (it - mr * kDRowStrips) * kDRowStrip;
+    const float* in = sB + mr * kSsimM + c0;
+    float a[kDRowStrip], b[kDRowStrip], c[kDRowStrip];
 #pragma unroll
-    for (int k = 0; k < kSsimTaps; ++k) {
-      const float w = win.w[k];
-      a += w * sB[o + k];
-      b += w * sB[kSsimMom + o + k];
-      c += w * sB[2 * kSsimMom + o + k];
+    for (int o = 0; o < kDRowStrip; ++o) a[o] = b[o] = c[o] = 0.f;
+#pragma unroll
+    for (int k = 0; k < kDRowStrip + 2 * kSsimR; ++k) {
+      const float va = in[k], vb = in[kSsimMom + k], vc = in[2 * kSsimMom + k];
+#pragma unroll
+      for (int o = 0; o < kDRowStrip; ++o) {
+        const int tap = k - o;
+        if (tap >= 0 && tap < kSsimTaps) {
+          const float w = win.w[tap];
+          a[o] += w * va;
+          b[o] += w * vb;
+          c[o] += w * vc;
+        }
+      }
     }
-    sA[i] = a;
-    sA[kSsimRowD + i] = b;
-    sA[2 * kSsimRowD + i] = c;
+    float* out = sA + mr * kSsimT + c0;
+#pragma unroll
+    for (int o = 0; o < kDRowStrip; ++o) {
+      out[o] = a[o];
+      out[kSsimRowD + o] = b[o];
+      out[2 * kSsimRowD + o] = c[o];
+    }
   }
   __syncthreads();
 
-  // column pass onto the tile and the weighted gradients
+  // column pass onto the tile (a strip of kOutStrip rows of one column per
+  // thread) and the weighted gradients
   const float inv = inv_valid[r];
   const float k_l1 = lambda_color * (1.f - lambda_ssim) * inv;
   const float k_ss = -lambda_color * lambda_ssim / (3.f * (float)hw);
   const float k_d = lambda_depth * inv;
   float l1 = 0.f, l1d = 0.f;
+  {
+    float fa[kOutStrip], fb[kOutStrip], fc[kOutStrip];
 #pragma unroll
-  for (int k = 0; k < kSsimOutPer; ++k) {
-    const int o = threadIdx.x + kBlock * k;
-    const int orow = o / kSsimT, ocol = o % kSsimT;
-    const int gy = y0 + orow, gx = x0 + ocol;
-    if (gx < W && gy < H) {
-      float fa = 0.f, fb = 0.f, fc = 0.f;
+    for (int q = 0; q < kOutStrip; ++q) fa[q] = fb[q] = fc[q] = 0.f;
 #pragma unroll
-      for (int q = 0; q < kSsimTaps; ++q) {
-        const int li = (orow + q) * kSsimT + ocol;
-        const float w = win.w[q];
-        fa += w * sA[li];
-        fb += w * sA[kSsimRowD + li];
-        fc += w * sA[2 * kSsimRowD + li];
+    for (int k = 0; k < kOutStrip + 2 * kSsimR; ++k) {
+      const int li = (o0 + k) * kSsimT + ocol;
+      const float va = sA[li], vb = sA[kSsimRowD + li], vc = sA[2 * kSsimRowD + li];
+#pragma unroll
+      for (int q = 0; q < kOutStrip; ++q) {
+        const int tap = k - q;
+        if (tap >= 0 && tap < kSsimTaps) {
+          const float w = win.w[tap];
+          fa[q] += w * va;
+          fb[q] += w * vb;
+          fc[q] += w * vc;
+        }
       }
-      const int64_t p = (int64_t)gy * W + gx;
-      const float td = tgt_depth ? tgt_depth[J.pix_off + p] : J.tgt_depth[p];
-      const bool valid = td > 0.f;
-      const float dc = cx[k] - cy[k];
-      float g = k_ss * (fa + 2.f * cx[k] * fb + cy[k] * fc);
-      if (valid) {
-        l1 += fabsf(dc);
-        g += dc > 0.f ? k_l1 : (dc < 0.f ? -k_l1 : 0.f);
-      }
-      if (g_rgb) g_rgb[3 * J.pix_off + ch * hw + p] = g;
-      if (ch == 0) {
-        const float dd = pred_depth[J.pix_off + p] - td;
-        if (valid) l1d += fabsf(dd);
-        if (g_depth) g_depth[J.pix_off + p] = valid ? (dd > 0.f ? k_d : (dd < 0.f ? -k_d : 0.f)) : 0.f;
+    }
+    const int gx = x0 + ocol;
+#pragma unroll
+    for (int q = 0; q < kOutStrip; ++q) {
+      const int gy = y0 + o0 + q;
+      if (gx < W && gy < H) {
+        const int64_t p = (int64_t)gy * W + gx;
+        const float xv = xq[q], yv = yq[q];
+        const float td = tq[q];
+        const bool valid = td > 0.f;
+        const float dc = xv - yv;
+        float g = k_ss * (fa[q] + 2.f * xv * fb[q] + yv * fc[q]);
+        if (valid) {
+          l1 += fabsf(dc);
+          g += dc > 0.f ? k_l1 : (dc < 0.f ? -k_l1 : 0.f);
+        }
+        if (g_rgb) g_rgb[3 * J.pix_off + ch * hw + p] = g;
+        if (ch == 0) {
+          const float dd = dq[q] - td;
+          if (valid) l1d += fabsf(dd);
+          if (g_depth) g_depth[J.pix_off + p] = valid ? (dd > 0.f ? k_d : (dd < 0.f ? -k_d : 0.f)) : 0.f;
+        }
       }
     }
   }
@@ -276,23 +369,25 @@ __global__ __launch_bounds__(256) void k_loss_ssim(const JobDev* __restrict__ jo
   }
 }
 
-// One wave per render: ordered sums of the block partials and the loss
+// One block per render: ordered sums of the block partials and the loss
 //   lc ((1 - ls) L1_rgb + ls (1 - mean SSIM)) + ld L1_depth.
-__global__ void k_map_reduce(const JobDev* __restrict__ jobs, const int32_t* __restrict__ sblk_off, int R,
-                             const float* __restrict__ part, const float* __restrict__ inv_valid, float lambda_ssim,
-                             float lambda_color, float lambda_depth, float* __restrict__ loss,
-                             float* __restrict__ scale) {
+__global__ __launch_bounds__(256) void k_map_reduce(const JobDev* __restrict__ jobs,
+                                                    const int32_t* __restrict__ sblk_off, int R,
+                                                    const float* __restrict__ part,
+                                                    const float* __restrict__ inv_valid, float lambda_ssim,
+                                                    float lambda_color, float lambda_depth, float* __restrict__ loss,
+                                                    float* __restrict__ scale) {
+  __shared__ float ws[3][4];
   const int r = blockIdx.x;
-  if (r >= R) return;
   float s = 0.f, c = 0.f, d = 0.f;
-  for (int b = sblk_off[r] + threadIdx.x; b < sblk_off[r + 1]; b += 64) {
+  for (int b = sblk_off[r] + threadIdx.x; b < sblk_off[r + 1]; b += kBlock) {
     s += part[3 * (int64_t)b];
     c += part[3 * (int64_t)b + 1];
     d += part[3 * (int64_t)b + 2];
   }
-  s = wave_sum(s);
-  c = wave_sum(c);
-  d = wave_sum(d);
+  s = block_sum(s, ws[0]);
+  c = block_sum(c, ws[1]);
+  d = block_sum(d, ws[2]);
   if (threadIdx.x == 0) {
     const float inv = inv_valid[r];
     const float n = 3.f * (float)jobs[r].W * (float)jobs[r].H;
@@ -363,14 +458,14 @@ void launch_loss_mapping(const JobDev* jobs, const int32_t* pblk_off_d, int npbl
   float* inv = map_part + 3 * (int64_t)nsblk;
   if (npblk > 0)
     hipLaunchKernelGGL(k_valid_count, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, tgt_depth, cnt_part);
-  hipLaunchKernelGGL(k_valid_inv, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)cnt_part, inv);
+  hipLaunchKernelGGL(k_valid_inv, dim3(R), dim3(kBlock), 0, s, pblk_off_d, R, (const float*)cnt_part, inv);
   if (nsblk > 0) {
     const int grid = 8 * ((nsblk + 7) / 8);
     hipLaunchKernelGGL(k_loss_ssim, dim3(grid), dim3(kBlock), 0, s, jobs, sblk_off_d, R, nsblk, pred_rgb, pred_depth,
                        tgt_rgb, tgt_depth, (const float*)inv, ssim_window(), lambda_ssim, lambda_color, lambda_depth,
                        g_rgb, g_depth, map_part);
   }
-  hipLaunchKernelGGL(k_map_reduce, dim3(R), dim3(64), 0, s, jobs, sblk_off_d, R, (const float*)map_part,
+  hipLaunchKernelGGL(k_map_reduce, dim3(R), dim3(kBlock), 0, s, jobs, sblk_off_d, R, (const float*)map_part,
                      (const float*)inv, lambda_ssim, lambda_color, lambda_depth, loss, scale);
 }
 
