@@ -13,9 +13,11 @@ Modules
             (paper Sec. 3.2, Eq. 7), transform errors
   mapping   submap-update loss: L1 + SSIM colour term, depth term and the
             isotropic scale regulariser (paper Sec. 3.1, Eq. 3-5)
+  adjust    rigid map adjustment of submaps and keyframe poses after pose-graph
+            optimisation (paper Sec. 3.3, Eq. 8)
 
 Every function with no independent pin is marked "parity unpinned" in its
 docstring; the pins live in tests/test_oracle_*.py.
 """
 
-from . import mapping, raster, register  # noqa: F401
+from . import adjust, mapping, raster, register  # noqa: F401

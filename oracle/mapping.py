@@ -9,16 +9,16 @@ regulariser pulls each Gaussian's three scales towards their mean (Eq. 5).
 The supplement sets the three weights of Eq. 3 to 1.  What the paper leaves
 open is fixed by these readings:
 
-  R25 SSIM is the windowed index of Wang et al. (2004) with an 11 x 11
+  R26 SSIM is the windowed index of Wang et al. (2004) with an 11 x 11
       Gaussian window of standard deviation 1.5 (weights normalised to sum
       to 1), zero padding outside the image, C1 = 0.01^2 and C2 = 0.03^2
       (dynamic range 1), moments taken as E[xy] - mu_x mu_y, evaluated per
       colour channel; SSIM(I^, I) is the mean of the index over the three
       channels and every pixel.
-  R26 lambda_SSIM = 0.2 (the paper gives none; this is the usual 3DGS value).
-  R27 the L1 parts of the colour and depth terms follow R15: the mean over
+  R27 lambda_SSIM = 0.2 (the paper gives none; this is the usual 3DGS value).
+  R28 the L1 parts of the colour and depth terms follow R15: the mean over
       the pixels with target depth > 0 of sum_c |C^ - C| and of |D^ - D|.
-  R28 the regulariser's |.|_1 is summed over the three axes and averaged over
+  R29 the regulariser's |.|_1 is summed over the three axes and averaged over
       the K Gaussians, on the scales s = exp(log_scale); the mean s-bar is the
       arithmetic mean of the three scales and is differentiated through.
 """
@@ -41,7 +41,7 @@ LAMBDA_SSIM = 0.2
 
 
 def ssim_window() -> torch.Tensor:
-    """The 11 normalised 1D Gaussian weights (R25); the 2D window is their
+    """The 11 normalised 1D Gaussian weights (R26); the 2D window is their
     outer product."""
     k = torch.arange(-SSIM_RADIUS, SSIM_RADIUS + 1, dtype=F64)
     g = torch.exp(-(k * k) / (2.0 * SSIM_SIGMA ** 2))
@@ -49,7 +49,7 @@ def ssim_window() -> torch.Tensor:
 
 
 def ssim_map(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
-    """Per-pixel SSIM index of two [C, H, W] images (R25), float64, by 2D
+    """Per-pixel SSIM index of two [C, H, W] images (R26), float64, by 2D
     convolution with the zero-padded window; differentiable."""
     g = ssim_window()
     w2 = torch.outer(g, g)[None, None]
@@ -71,7 +71,7 @@ def ssim_map(x: torch.Tensor, y: torch.Tensor) -> torch.Tensor:
 def loss_mapping(rgb, depth, tgt_rgb, tgt_depth, lambda_ssim: float = LAMBDA_SSIM, lambda_color: float = 1.0,
                  lambda_depth: float = 1.0):
     """Image part of the mapping loss (Eq. 3 without the regulariser, Eq. 4,
-    R25-R27) for one render: rgb [3,H,W], depth [H,W].
+    R26-R28) for one render: rgb [3,H,W], depth [H,W].
 
     L = lc ((1 - ls) L1_rgb + ls (1 - SSIM)) + ld L1_depth.  The L1 means are
     0 when no pixel has a target depth; the SSIM term is not masked."""
@@ -89,7 +89,7 @@ def loss_mapping(rgb, depth, tgt_rgb, tgt_depth, lambda_ssim: float = LAMBDA_SSI
 
 
 def loss_isotropic(log_scale: torch.Tensor, lambda_reg: float = 1.0) -> torch.Tensor:
-    """Isotropic regulariser (Eq. 5, R28) of one submap: log_scale [K, 3]."""
+    """Isotropic regulariser (Eq. 5, R29) of one submap: log_scale [K, 3]."""
     s = torch.exp(log_scale.to(F64))
     if s.shape[0] == 0:
         return s.sum() * 0.0

@@ -1,4 +1,4 @@
-"""Pins of the FP64 mapping-loss oracle (Eq. 3-5, readings R25-R28) against
+"""Pins of the FP64 mapping-loss oracle (Eq. 3-5, readings R26-R29) against
 closed forms, brute-force window sums, special cases and finite differences.
 CPU only."""
 
