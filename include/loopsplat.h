@@ -347,6 +347,26 @@ ls_status ls_loss_mapping(const ls_batch* b, const ls_image* pred, const float* 
 ls_status ls_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, float* loss, float* grad_log_scale,
                             float* work, hipStream_t s);
 
+/* One submap of a globally consistent map adjustment (Sec. 3.3, Eq. 8). */
+typedef struct {
+  int32_t n;        /* Gaussians (>= 0) */
+  int32_t n_poses;  /* keyframe poses (>= 0; ignored when c2w is NULL) */
+  float* mean;      /* device [3][n], updated in place */
+  float* quat;      /* device [4][n] (w, x, y, z, any norm), updated in place */
+  float* c2w;       /* device [n_poses][12] row-major 3x4 camera-to-world, updated in place, or NULL */
+  float T[12];      /* host: the submap's correction [R_c | t_c], row-major 3x4; R_c a rotation */
+} ls_submap_adjust;
+
+/* Applies each submap's pose-graph correction in place (Sec. 3.3, Eq. 8):
+ *   mu <- R_c mu + t_c;  Sigma <- R_c Sigma R_c^T, realised as q <- q_c q
+ *   (Hamilton product with the unit quaternion of R_c, so |q| is kept and
+ *   scales, opacities and colours are untouched);  T_j <- T_c T_j.
+ * Up to 32 submaps share a launch; any count is accepted.  Arrays of
+ * different submaps must not overlap.  Errors: LS_ERR_INVALID (count < 0,
+ * NULL arrays with n > 0, a non-finite T or an R_c that is not a rotation to
+ * 1e-3: |R^T R - I| or det R <= 0). */
+ls_status ls_adjust_submaps(const ls_submap_adjust* subs, int32_t count, hipStream_t s);
+
 /* One parameter group of a fused Adam step. */
 typedef struct {
   float* param;

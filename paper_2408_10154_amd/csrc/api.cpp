@@ -174,6 +174,7 @@ int64_t ls_struct_size(const char* name) {
       {"ls_reg_result", sizeof(ls_reg_result)},     {"ls_server_params", sizeof(ls_server_params)},
       {"ls_server_stats", sizeof(ls_server_stats)}, {"ls_loss_params", sizeof(ls_loss_params)},
       {"ls_mapping_params", sizeof(ls_mapping_params)},
+      {"ls_submap_adjust", sizeof(ls_submap_adjust)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -495,6 +496,31 @@ ls_status ls_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg,
   if (!std::isfinite(lambda_reg)) return fail(LS_ERR_INVALID, "lambda_reg must be finite");
   launch_loss_isotropic(log_scale, n, lambda_reg, loss, grad_log_scale, work, s);
   return hip_check("ls_loss_isotropic");
+}
+
+ls_status ls_adjust_submaps(const ls_submap_adjust* subs, int32_t count, hipStream_t s) {
+  if (count < 0 || (count > 0 && !subs)) return fail(LS_ERR_INVALID, "bad submap list");
+  for (int k = 0; k < count; ++k) {
+    const ls_submap_adjust& u = subs[k];
+    if (u.n < 0 || u.n_poses < 0) return fail(LS_ERR_INVALID, "submap %d: negative size", k);
+    if (u.n > 0 && (!u.mean || !u.quat)) return fail(LS_ERR_INVALID, "submap %d: NULL Gaussian arrays", k);
+    for (int i = 0; i < 12; ++i)
+      if (!std::isfinite(u.T[i])) return fail(LS_ERR_INVALID, "submap %d: non-finite correction", k);
+    double dev = 0.0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double d = 0.0;
+        for (int r = 0; r < 3; ++r) d += (double)u.T[r * 4 + a] * u.T[r * 4 + b];
+        dev = std::max(dev, std::fabs(d - (a == b ? 1.0 : 0.0)));
+      }
+    const float* R = u.T;
+    const double det = (double)R[0] * (R[5] * R[10] - R[6] * R[9]) - (double)R[1] * (R[4] * R[10] - R[6] * R[8]) +
+                       (double)R[2] * (R[4] * R[9] - R[5] * R[8]);
+    if (dev > 1e-3 || det <= 0.0) return fail(LS_ERR_INVALID, "submap %d: correction is not a rigid motion", k);
+  }
+  if (count == 0) return LS_OK;
+  launch_adjust_submaps(subs, count, s);
+  return hip_check("ls_adjust_submaps");
 }
 
 ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2, float eps,

@@ -83,6 +83,9 @@ constexpr int kIsotropicBlocks = LS_ISOTROPIC_WORK_FLOATS;
 void launch_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, float* loss, float* grad, float* part,
                            hipStream_t s);
 
+// Map adjustment (adjust.hip): validated descriptors, any count.
+int launch_adjust_submaps(const ls_submap_adjust* subs, int count, hipStream_t s);
+
 void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,
                  int zero_grad, hipStream_t s);
 

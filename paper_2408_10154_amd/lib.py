@@ -89,6 +89,11 @@ class ls_mapping_params(C.Structure):
                 ("pad", C.c_int32)]
 
 
+class ls_submap_adjust(C.Structure):
+    _fields_ = [("n", C.c_int32), ("n_poses", C.c_int32), ("mean", C.c_void_p), ("quat", C.c_void_p),
+                ("c2w", C.c_void_p), ("T", C.c_float * 12)]
+
+
 class ls_reg_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lr_rot", C.c_float), ("lr_trans", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("exit_rel_tol", C.c_float),
@@ -144,6 +149,7 @@ _PROTOS = {
     "ls_loss_mapping": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, C.POINTER(ls_mapping_params), _P, _P, _P,
                                     _P, _P]),
     "ls_loss_isotropic": (C.c_int32, [_P, C.c_int64, C.c_float, _P, _P, _P, _P]),
+    "ls_adjust_submaps": (C.c_int32, [C.POINTER(ls_submap_adjust), C.c_int32, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
@@ -257,6 +263,10 @@ def ls_loss_mapping(h, pred, tgt_rgb, tgt_depth, prm, loss, grad_rgb, grad_depth
 
 def ls_loss_isotropic(log_scale, n, lambda_reg, loss, grad_log_scale, work, stream):
     return _call("ls_loss_isotropic", log_scale, n, lambda_reg, loss, grad_log_scale, work, stream)
+
+
+def ls_adjust_submaps(subs, count, stream):
+    return _call("ls_adjust_submaps", subs, count, stream)
 
 
 def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):

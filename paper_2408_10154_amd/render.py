@@ -306,6 +306,22 @@ def loss_isotropic(log_scale: torch.Tensor, lambda_reg: float = 1.0, loss=None, 
     return loss
 
 
+def adjust_submaps(subs):
+    """Applies pose-graph corrections in place (map adjustment): subs is a
+    list of (GaussianSet, c2w, T) with c2w a contiguous device tensor
+    [k, 12] (row-major 3x4 camera-to-world keyframe poses) or None, and T
+    the submap's correction as a 3x4 or 4x4 array."""
+    arr = (L.ls_submap_adjust * max(len(subs), 1))()
+    for k, (g, c2w, T) in enumerate(subs):
+        T = np.asarray(T, np.float64)[:3, :4]
+        if c2w is not None and (not c2w.is_cuda or not c2w.is_contiguous() or c2w.dim() != 2 or c2w.shape[1] != 12):
+            raise ValueError("c2w must be a contiguous [k, 12] device tensor")
+        arr[k] = L.ls_submap_adjust(g.n, 0 if c2w is None else c2w.shape[0], g.mean.data_ptr(), g.quat.data_ptr(),
+                                    None if c2w is None else c2w.data_ptr(),
+                                    (C.c_float * 12)(*[float(v) for v in T.reshape(-1)]))
+    L.ls_adjust_submaps(arr, len(subs), _stream())
+
+
 def adam(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=True):
     """Fused Adam over (param, grad, m, v, lr) tuples of float32 device tensors."""
     for i in range(0, len(groups), 16):

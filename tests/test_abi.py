@@ -40,7 +40,7 @@ def test_binding_covers_the_header():
     assert set(L.declared_functions()) == declared()
 
 
-@pytest.mark.parametrize("name", ["ls_loss_params", "ls_mapping_params", "ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
+@pytest.mark.parametrize("name", ["ls_loss_params", "ls_mapping_params", "ls_submap_adjust", "ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
                                   "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group"])
 def test_struct_layouts_match(name):
     lib = L.load()
@@ -64,6 +64,12 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert lib.ls_fill_i32(None, 4, 0, None) == L.LS_ERR_INVALID
     assert lib.ls_loss_isotropic(None, -1, 1.0, None, None, None, None) == L.LS_ERR_INVALID
     assert lib.ls_loss_isotropic(None, 4, 1.0, None, None, None, None) == L.LS_ERR_INVALID  # NULL arrays
+    sub = L.ls_submap_adjust(0, 0, None, None, None, (C.c_float * 12)(2, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0))
+    assert lib.ls_adjust_submaps(C.byref(sub), 1, None) == L.LS_ERR_INVALID  # not a rotation
+    assert b"rigid" in lib.ls_last_error()
+    sub = L.ls_submap_adjust(5, 0, None, None, None, (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0))
+    assert lib.ls_adjust_submaps(C.byref(sub), 1, None) == L.LS_ERR_INVALID  # NULL arrays
+    assert lib.ls_adjust_submaps(None, -1, None) == L.LS_ERR_INVALID
     prm = L.ls_mapping_params(1.5, 1.0, 1.0, 0)  # lambda_ssim outside [0, 1]
     assert lib.ls_loss_mapping(None, None, None, None, C.byref(prm), None, None, None, None, None) == L.LS_ERR_INVALID
     assert lib.ls_struct_size(b"no_such_struct") == -1
