@@ -15,9 +15,11 @@ Modules
             isotropic scale regulariser (paper Sec. 3.1, Eq. 3-5)
   adjust    rigid map adjustment of submaps and keyframe poses after pose-graph
             optimisation (paper Sec. 3.3, Eq. 8)
+  overlap   geometric overlap ratio of two submaps by reciprocal nearest
+            neighbours (supplement, loop detection, Eq. 9)
 
 Every function with no independent pin is marked "parity unpinned" in its
 docstring; the pins live in tests/test_oracle_*.py.
 """
 
-from . import adjust, mapping, raster, register  # noqa: F401
+from . import adjust, mapping, overlap, raster, register  # noqa: F401
