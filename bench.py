@@ -10,7 +10,9 @@ pose.  Inputs are resident in HBM before timing; no host sync inside a step.
 
 The same loop is then timed with the full mapping loss (L1 + SSIM colour
 term, depth term, isotropic scale regulariser), and the map adjustment after
-pose-graph optimisation is timed on 64 resident submaps of 200k Gaussians.
+pose-graph optimisation is timed on 64 resident submaps of 200k Gaussians,
+and the geometric overlap ratio (reciprocal nearest neighbours) of the
+registration pair's submaps.
 
 Then the registration workloads (keyframe localisation with the masked
 tracking loss, 200 Adam iterations per view):
@@ -86,6 +88,7 @@ def parse():
     ap.add_argument("--no-registration", action="store_true")
     ap.add_argument("--mapping-steps", type=int, default=20,
                     help="timed iterations of the same loop with the full mapping loss (0: skip)")
+    ap.add_argument("--no-overlap", action="store_true", help="skip the overlap-ratio timing")
     ap.add_argument("--adjust-submaps", type=int, default=64,
                     help="submaps of 200k Gaussians in the timed map adjustment (0: skip)")
     ap.add_argument("--calib-copy-mb", type=int, default=0,
@@ -187,6 +190,40 @@ def map_adjust(n_sub: int, n: int = 200_000, poses: int = 100, reps: int = 20):
             "achieved_gbs": round(algo / (ms * 1e-3) / 1e9, 1), "bound": "hbm",
             "frac": round(algo / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4),
             "same_bytes_copy_gbs": round(algo / (cms * 1e-3) / 1e9, 1)}
+
+
+def overlap(reps: int = 10):
+    """Geometric overlap ratio (reciprocal nearest neighbours, tau = 0.2 m)
+    of the single-pair registration workload's submaps (150k + 120k
+    Gaussians) under the ground truth and under the identity, timed with HIP
+    events on the launch stream (inputs resident)."""
+    import numpy as np
+    import torch
+
+    from paper_2408_10154_amd import lib as L
+    from paper_2408_10154_amd import synth
+    from paper_2408_10154_amd.render import overlap_ratio
+
+    d = synth.registration_pair(2, 150_000, 120_000, views_p=1, views_q=1)
+    p = torch.as_tensor(np.asarray(d["P"]["mean"], np.float32), device="cuda").contiguous()
+    q = torch.as_tensor(np.asarray(d["Q"]["mean"], np.float32), device="cuda").contiguous()
+    work = torch.empty(L.ls_overlap_workspace_size(p.shape[1], q.shape[1]), dtype=torch.uint8, device="cuda")
+    stream = torch.cuda.current_stream()
+    out = {}
+    for name, T in (("ground_truth", d["T_gt"]), ("identity", np.eye(4))):
+        r, pairs, inl, _, _ = overlap_ratio(p, q, T, 0.2, work=work)
+        evs = []
+        for _ in range(reps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            overlap_ratio(p, q, T, 0.2, work=work)
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        ms = sorted(a.elapsed_time(b) for a, b in evs)[reps // 2]
+        out[name] = {"ratio": round(r, 4), "pairs": pairs, "within_tau": inl, "ms": round(ms, 4)}
+    out["points"] = [int(p.shape[1]), int(q.shape[1])]
+    return out
 
 
 def registration(n_pairs: int, iters: int):
@@ -384,6 +421,7 @@ def main():
     if args.adjust_submaps > 0:
         adjust = map_adjust(args.adjust_submaps)
         torch.cuda.empty_cache()
+    ovl = None if args.no_overlap else overlap()
     if not args.no_registration:
         torch.cuda.empty_cache()
         reg = registration(args.pairs, args.reg_iters)
@@ -417,6 +455,7 @@ def main():
         "loss": {"first_timed": round(loss0, 5), "last": round(loss1, 5)},
         "mapping": mapping,
         "map_adjust": adjust,
+        "overlap": ovl,
         "registration": reg,
         "cpu_baseline": cpu,
     }

@@ -367,6 +367,27 @@ typedef struct {
  * 1e-3: |R^T R - I| or det R <= 0). */
 ls_status ls_adjust_submaps(const ls_submap_adjust* subs, int32_t count, hipStream_t s);
 
+/* Geometric overlap ratio of two submaps (supplement, loop detection, Eq. 9):
+ *   OR = (1/|K|) sum_{(p,q) in K} [ |T(p) - q| < tau ],
+ * K = reciprocal nearest neighbours between the Gaussian means of P moved by
+ * T (an estimate of T_{P->Q}) and those of Q.  Nearest neighbours are exact
+ * under FP32 decisions with a fixed rounding sequence (no fused multiply-add):
+ * T(p)_r = ((R_r0 x + R_r1 y) + R_r2 z) + t_r, d^2 = (dx^2 + dy^2) + dz^2,
+ * ties to the lower index; the test is d^2 < fl32(tau^2).
+ *   p_mean, q_mean  device [3][np], [3][nq] (the ls_gaussians layout)
+ *   T_pq            host, row-major 3x4
+ *   nn_pq, nn_qp    device [np], [nq] (written): index of the nearest point of
+ *                   the other set (-1 when that set is empty)
+ *   counts          device int32 [2] (written): {|K|, pairs closer than tau};
+ *                   OR = counts[1] / counts[0] (0 when |K| = 0)
+ *   work            device scratch of ls_overlap_workspace_size(np, nq) bytes
+ * Errors: LS_ERR_INVALID (sizes, NULL arrays, non-finite T, tau not > 0),
+ * LS_ERR_CAPACITY (work_bytes too small). */
+size_t ls_overlap_workspace_size(int32_t np, int32_t nq);
+ls_status ls_overlap_ratio(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
+                           float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, size_t work_bytes,
+                           hipStream_t s);
+
 /* One parameter group of a fused Adam step. */
 typedef struct {
   float* param;

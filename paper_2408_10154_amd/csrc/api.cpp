@@ -523,6 +523,27 @@ ls_status ls_adjust_submaps(const ls_submap_adjust* subs, int32_t count, hipStre
   return hip_check("ls_adjust_submaps");
 }
 
+size_t ls_overlap_workspace_size(int32_t np, int32_t nq) {
+  if (np < 0 || nq < 0) return 0;
+  return overlap_workspace_bytes(np, nq);
+}
+
+ls_status ls_overlap_ratio(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
+                           float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, size_t work_bytes,
+                           hipStream_t s) {
+  if (np < 0 || nq < 0) return fail(LS_ERR_INVALID, "negative point count");
+  if (!T_pq || !counts || (np > 0 && (!p_mean || !nn_pq)) || (nq > 0 && (!q_mean || !nn_qp)))
+    return fail(LS_ERR_INVALID, "NULL arguments");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(T_pq[k])) return fail(LS_ERR_INVALID, "non-finite transform");
+  if (!(tau > 0.f) || !std::isfinite(tau)) return fail(LS_ERR_INVALID, "tau must be finite and > 0");
+  const size_t need = overlap_workspace_bytes(np, nq);
+  if (work_bytes < need || (need > 0 && !work))
+    return fail(LS_ERR_CAPACITY, "overlap workspace needs %zu bytes", need);
+  launch_overlap(p_mean, np, q_mean, nq, T_pq, tau, nn_pq, nn_qp, counts, work, s);
+  return hip_check("ls_overlap_ratio");
+}
+
 ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2, float eps,
                   int32_t zero_grad, hipStream_t s) {
   if (!groups || ngroups < 1 || ngroups > 16) return fail(LS_ERR_INVALID, "need 1..16 Adam groups");

@@ -420,6 +420,20 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
                      n_static, cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_total, rounds);
 }
 
+int launch_radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
+                            uint32_t* hist, uint32_t* digit_total, hipStream_t s) {
+  if (n <= 0) return 0;
+  const int rd = sort_rounds(n), nb = (int)sort_blocks(n);
+  uint32_t *ka = k0, *va = v0, *kb = k1, *vb = v1;
+  int passes = 0;
+  for (int shift = 0; shift < bits; shift += 8, ++passes) {
+    radix_pass<8>(ka, va, kb, vb, nullptr, n, n, shift, hist, digit_total, nb, rd, s);
+    std::swap(ka, kb);
+    std::swap(va, vb);
+  }
+  return passes & 1;
+}
+
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
                      const float* rec, const int32_t* radius, const int32_t* tiles, int64_t cap, uint32_t* tile_of,
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,

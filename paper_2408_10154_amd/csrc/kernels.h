@@ -21,6 +21,13 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s);
 
+// Stable LSD radix sort of n (key, value) pairs on the low `bits` key bits,
+// 8 bits per pass (binning.hip); hist holds 256 * sort_blocks(n) words and
+// digit_total 256.  The result is in (k0, v0) when the return value is 0,
+// else in (k1, v1).
+int launch_radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
+                            uint32_t* hist, uint32_t* digit_total, hipStream_t s);
+
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
                           float* alpha, float* Tf, int32_t* nl, hipStream_t s);
@@ -85,6 +92,11 @@ void launch_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, 
 
 // Map adjustment (adjust.hip): validated descriptors, any count.
 int launch_adjust_submaps(const ls_submap_adjust* subs, int count, hipStream_t s);
+
+// Overlap ratio (overlap.hip).
+size_t overlap_workspace_bytes(int np, int nq);
+void launch_overlap(const float* p_mean, int np, const float* q_mean, int nq, const float* T, float tau,
+                    int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, hipStream_t s);
 
 void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,
                  int zero_grad, hipStream_t s);

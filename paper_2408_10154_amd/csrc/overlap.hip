@@ -1,0 +1,370 @@
+// Geometric overlap ratio of two submaps (supplement, loop detection,
+// Eq. 9): the fraction of reciprocal nearest-neighbour pairs between the
+// Gaussian means of P, moved by an estimate of T_{P->Q}, and those of Q whose
+// distance is below tau_1.
+//
+// Every nearest neighbour is exact: both point sets are sorted along a
+// 30-bit Morton curve and cut into leaf blocks of 64 points (one wave) and
+// superblocks of 32 leaves, each with its bounding box.  A wave of 64 query
+// points visits the candidate superblocks and leaves outward from the
+// query's place on the curve and skips any box farther from the query box
+// than the farthest current best of its lanes (with a margin over FP32
+// rounding), so no skipped point can win or tie.  Distances and the
+// transform follow one fixed FP32 rounding sequence (no fused multiply-add)
+// so that matches and ties are reproducible: d^2 = (dx^2 + dy^2) + dz^2,
+// ties to the lower index.
+#include <algorithm>
+#include <cmath>
+
+#include "kernels.h"
+
+namespace ls {
+
+constexpr int kOvLeaf = 64;       // points per leaf block (one wave)
+constexpr int kOvSuper = 32;      // leaves per superblock
+constexpr int kOvBoxBlocks = 256; // blocks of the bounding-box reduction
+constexpr float kOvPrune = 1.f - 1e-5f;  // a box is skipped only if lb^2 * kOvPrune > bound
+
+__device__ __forceinline__ float sq_dist_rn(float ax, float ay, float az, float bx, float by, float bz) {
+#pragma clang fp contract(off)
+  const float dx = ax - bx, dy = ay - by, dz = az - bz;
+  return (dx * dx + dy * dy) + dz * dz;
+}
+
+__device__ __forceinline__ float wave_max_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fmaxf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+__device__ __forceinline__ float wave_min_f(float v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// Squared distance between two boxes (min xyz, max xyz); 0 when they meet.
+__device__ __forceinline__ float box_dist2(const float* a, const float* b) {
+  const float g0 = fmaxf(fmaxf(a[0] - b[3], b[0] - a[3]), 0.f);
+  const float g1 = fmaxf(fmaxf(a[1] - b[4], b[1] - a[4]), 0.f);
+  const float g2 = fmaxf(fmaxf(a[2] - b[5], b[2] - a[5]), 0.f);
+  return g0 * g0 + g1 * g1 + g2 * g2;
+}
+
+// P moved by T (row-major 3x4): ((R_r0 x + R_r1 y) + R_r2 z) + t_r, each
+// operation rounded to FP32 (contraction into fused multiply-adds is off in
+// this and the distance function).
+struct Rigid {
+  float m[12];
+};
+__global__ __launch_bounds__(256) void k_ov_transform(const float* __restrict__ p, int n, Rigid T,
+                                                      float* __restrict__ out) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float x = p[i], y = p[(int64_t)n + i], z = p[2 * (int64_t)n + i];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma clang fp contract(off)
+    const float* M = T.m + 4 * r;
+    out[(int64_t)r * n + i] = ((M[0] * x + M[1] * y) + M[2] * z) + M[3];
+  }
+}
+
+// Bounding box of both sets: per-block partials, then one block.
+__global__ __launch_bounds__(256) void k_ov_box_part(const float* __restrict__ a, int na, const float* __restrict__ b,
+                                                     int nb, float* __restrict__ part) {
+  float lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < (int64_t)na + nb; i += (int64_t)gridDim.x * kBlock) {
+    const float* s = i < na ? a : b;
+    const int64_t n = i < na ? na : nb, k = i < na ? i : i - na;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const float v = s[d * n + k];
+      lo[d] = fminf(lo[d], v);
+      hi[d] = fmaxf(hi[d], v);
+    }
+  }
+  __shared__ float ws[4][6];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = wave_min_f(lo[d]);
+    hi[d] = wave_max_f(hi[d]);
+  }
+  if ((threadIdx.x & 63) == 0)
+    for (int d = 0; d < 3; ++d) {
+      ws[threadIdx.x >> 6][d] = lo[d];
+      ws[threadIdx.x >> 6][3 + d] = hi[d];
+    }
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int d = threadIdx.x;
+    float v = ws[0][d];
+    for (int w = 1; w < 4; ++w) v = d < 3 ? fminf(v, ws[w][d]) : fmaxf(v, ws[w][d]);
+    part[6 * blockIdx.x + d] = v;
+  }
+}
+
+__global__ void k_ov_box_final(const float* __restrict__ part, int nblk, float* __restrict__ box) {
+  if (threadIdx.x >= 6) return;
+  const int d = threadIdx.x;
+  float v = part[d];
+  for (int k = 1; k < nblk; ++k) v = d < 3 ? fminf(v, part[6 * k + d]) : fmaxf(v, part[6 * k + d]);
+  box[d] = v;
+}
+
+__device__ __forceinline__ uint32_t spread10(uint32_t v) {
+  v &= 0x3FFu;
+  v = (v | (v << 16)) & 0x030000FFu;
+  v = (v | (v << 8)) & 0x0300F00Fu;
+  v = (v | (v << 4)) & 0x030C30C3u;
+  v = (v | (v << 2)) & 0x09249249u;
+  return v;
+}
+
+// 30-bit Morton code of every point on a cubic grid of 1024 cells per axis
+// over the common box; value = the point's index.
+__global__ __launch_bounds__(256) void k_ov_codes(const float* __restrict__ p, int n, const float* __restrict__ box,
+                                                  uint32_t* __restrict__ code, uint32_t* __restrict__ idx) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float ext = fmaxf(fmaxf(box[3] - box[0], box[4] - box[1]), box[5] - box[2]);
+  const float inv = ext > 0.f ? 1023.f / ext : 0.f;
+  uint32_t c = 0;
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    const float q = (p[(int64_t)d * n + i] - box[d]) * inv;
+    const uint32_t u = (uint32_t)fminf(fmaxf(q, 0.f), 1023.f);
+    c |= spread10(u) << d;
+  }
+  code[i] = c;
+  idx[i] = (uint32_t)i;
+}
+
+// Points in curve order (SoA x, y, z, original index, code) and one box per leaf
+// (one wave per leaf).
+__global__ __launch_bounds__(256) void k_ov_gather(const float* __restrict__ p, int n,
+                                                   const uint32_t* __restrict__ order,
+                                                   const uint32_t* __restrict__ code, float* __restrict__ sp,
+                                                   int32_t* __restrict__ sidx, uint32_t* __restrict__ scode,
+                                                   float* __restrict__ leaf_box) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  const bool v = i < n;
+  float c[3] = {0.f, 0.f, 0.f};
+  if (v) {
+    const uint32_t k = order[i];
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      c[d] = p[(int64_t)d * n + k];
+      sp[(int64_t)d * n + i] = c[d];
+    }
+    sidx[i] = (int32_t)k;
+    scode[i] = code[i];
+  }
+  float lo[3], hi[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    lo[d] = wave_min_f(v ? c[d] : INFINITY);
+    hi[d] = wave_max_f(v ? c[d] : -INFINITY);
+  }
+  const int leaf = i / kOvLeaf;
+  if ((threadIdx.x & 63) == 0 && leaf * kOvLeaf < n)
+    for (int d = 0; d < 3; ++d) {
+      leaf_box[6 * leaf + d] = lo[d];
+      leaf_box[6 * leaf + 3 + d] = hi[d];
+    }
+}
+
+__global__ __launch_bounds__(256) void k_ov_super(const float* __restrict__ leaf_box, int nleaf,
+                                                  float* __restrict__ super_box, int nsuper) {
+  const int s = blockIdx.x * kBlock + threadIdx.x;
+  if (s >= nsuper) return;
+  float b[6] = {INFINITY, INFINITY, INFINITY, -INFINITY, -INFINITY, -INFINITY};
+  const int l1 = (s + 1) * kOvSuper < nleaf ? (s + 1) * kOvSuper : nleaf;
+  for (int l = s * kOvSuper; l < l1; ++l)
+    for (int d = 0; d < 3; ++d) {
+      b[d] = fminf(b[d], leaf_box[6 * l + d]);
+      b[3 + d] = fmaxf(b[3 + d], leaf_box[6 * l + 3 + d]);
+    }
+  for (int d = 0; d < 6; ++d) super_box[6 * s + d] = b[d];
+}
+
+struct OvSet {
+  const float* p;        // [3][n] in curve order
+  const int32_t* idx;    // original indices
+  const uint32_t* code;  // sorted Morton codes
+  const float* leaf;     // [nleaf][6]
+  const float* super;    // [nsuper][6]
+  int n, nleaf, nsuper;
+};
+
+// One wave per query leaf: the exact nearest candidate of each of its points.
+__global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __restrict__ nn_out) {
+  const int leaf = (int)((blockIdx.x * (int64_t)kBlock + threadIdx.x) / kOvLeaf);
+  const int lane = threadIdx.x & 63;
+  if (leaf >= q.nleaf) return;  // whole waves
+  const int qi = leaf * kOvLeaf + lane;
+  const bool qv = qi < q.n;
+  const float px = qv ? q.p[qi] : 0.f, py = qv ? q.p[(int64_t)q.n + qi] : 0.f;
+  const float pz = qv ? q.p[2 * (int64_t)q.n + qi] : 0.f;
+  float qb[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) qb[d] = q.leaf[6 * leaf + d];
+  // start at the candidate superblock holding the query leaf's first code
+  const uint32_t code0 = q.code[leaf * kOvLeaf];
+  int lo = 0, hi = c.n;
+  while (lo < hi) {
+    const int mid = (lo + hi) >> 1;
+    if (c.code[mid] < code0) lo = mid + 1; else hi = mid;
+  }
+  const int s0 = lo / (kOvLeaf * kOvSuper) < c.nsuper - 1 ? lo / (kOvLeaf * kOvSuper) : c.nsuper - 1;
+  float best = INFINITY;
+  int bi = 0x7fffffff;
+  float bound = INFINITY;
+  for (int k = 0; k < 2 * c.nsuper; ++k) {
+    const int s = (k & 1) ? s0 + (k + 1) / 2 : s0 - k / 2;
+    if (s < 0 || s >= c.nsuper) continue;
+    if (box_dist2(qb, c.super + 6 * s) * kOvPrune > bound) continue;
+    const int l1 = (s + 1) * kOvSuper < c.nleaf ? (s + 1) * kOvSuper : c.nleaf;
+    for (int l = s * kOvSuper; l < l1; ++l) {
+      if (box_dist2(qb, c.leaf + 6 * l) * kOvPrune > bound) continue;
+      const int ci = l * kOvLeaf + lane;
+      const bool cv = ci < c.n;
+      const float ax = cv ? c.p[ci] : 0.f, ay = cv ? c.p[(int64_t)c.n + ci] : 0.f;
+      const float az = cv ? c.p[2 * (int64_t)c.n + ci] : 0.f;
+      const int aid = cv ? c.idx[ci] : 0;
+      const int cnt = c.n - l * kOvLeaf < kOvLeaf ? c.n - l * kOvLeaf : kOvLeaf;
+      for (int j = 0; j < cnt; ++j) {
+        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), j));
+        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), j));
+        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), j));
+        const int bid = __builtin_amdgcn_readlane(aid, j);
+        const float d = sq_dist_rn(px, py, pz, bx, by, bz);
+        if (d < best || (d == best && bid < bi)) {
+          best = d;
+          bi = bid;
+        }
+      }
+      bound = wave_max_f(qv ? best : -INFINITY);
+    }
+  }
+  if (qv) nn_out[q.idx[qi]] = bi;
+}
+
+// Reciprocity and the threshold test per point of P; integer atomics.
+__global__ __launch_bounds__(256) void k_ov_count(const float* __restrict__ pt, int np, const float* __restrict__ q,
+                                                  int nq, const int32_t* __restrict__ nn_pq,
+                                                  const int32_t* __restrict__ nn_qp, float tau2,
+                                                  int32_t* __restrict__ counts) {
+  const int i = blockIdx.x * kBlock + threadIdx.x;
+  bool pair = false, in = false;
+  if (i < np) {
+    const int j = nn_pq[i];
+    if (j >= 0 && j < nq && nn_qp[j] == i) {
+      pair = true;
+      const float d = sq_dist_rn(pt[i], pt[(int64_t)np + i], pt[2 * (int64_t)np + i], q[j], q[(int64_t)nq + j],
+                                 q[2 * (int64_t)nq + j]);
+      in = d < tau2;
+    }
+  }
+  const uint64_t bp = __ballot(pair), bn = __ballot(in);
+  if ((threadIdx.x & 63) == 0) {
+    if (bp) atomicAdd(&counts[0], (int32_t)__popcll(bp));
+    if (bn) atomicAdd(&counts[1], (int32_t)__popcll(bn));
+  }
+}
+
+// Workspace layout (all pieces 256-byte aligned).
+struct OvLayout {
+  size_t pt, box_part, box, code_a, idx_a, code_b, idx_b, hist, digits, set_p[5], set_q[5], total;
+};
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+static OvLayout ov_layout(int np, int nq) {
+  OvLayout L{};
+  size_t o = 0;
+  auto take = [&](size_t bytes) {
+    const size_t at = o;
+    o += align256(bytes);
+    return at;
+  };
+  const int64_t nmax = std::max(np, nq);
+  L.pt = take(12 * (size_t)np);
+  L.box_part = take(4 * 6 * kOvBoxBlocks);
+  L.box = take(4 * 6);
+  L.code_a = take(4 * (size_t)nmax);
+  L.idx_a = take(4 * (size_t)nmax);
+  L.code_b = take(4 * (size_t)nmax);
+  L.idx_b = take(4 * (size_t)nmax);
+  L.hist = take(4 * 256 * (size_t)std::max<int64_t>(sort_blocks(nmax), 1));
+  L.digits = take(4 * 256);
+  for (int s = 0; s < 2; ++s) {
+    const int n = s ? nq : np;
+    const int nleaf = (n + kOvLeaf - 1) / kOvLeaf, nsuper = (nleaf + kOvSuper - 1) / kOvSuper;
+    size_t* S = s ? L.set_q : L.set_p;
+    S[0] = take(12 * (size_t)n);         // points in curve order
+    S[1] = take(4 * (size_t)n);          // original indices
+    S[2] = take(4 * (size_t)n);          // sorted codes
+    S[3] = take(24 * (size_t)nleaf);     // leaf boxes
+    S[4] = take(24 * (size_t)nsuper);    // superblock boxes
+  }
+  L.total = o;
+  return L;
+}
+
+size_t overlap_workspace_bytes(int np, int nq) { return ov_layout(np, nq).total; }
+
+void launch_overlap(const float* p_mean, int np, const float* q_mean, int nq, const float* T, float tau,
+                    int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, hipStream_t s) {
+  const OvLayout L = ov_layout(np, nq);
+  char* w = static_cast<char*>(work);
+  launch_fill_i32(counts, 2, 0, s);
+  if (np == 0 || nq == 0) {
+    launch_fill_i32(nn_pq, np, -1, s);
+    launch_fill_i32(nn_qp, nq, -1, s);
+    return;
+  }
+  float* pt = reinterpret_cast<float*>(w + L.pt);
+  Rigid R;
+  for (int k = 0; k < 12; ++k) R.m[k] = T[k];
+  hipLaunchKernelGGL(k_ov_transform, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, p_mean, np, R, pt);
+  float* box_part = reinterpret_cast<float*>(w + L.box_part);
+  float* box = reinterpret_cast<float*>(w + L.box);
+  hipLaunchKernelGGL(k_ov_box_part, dim3(kOvBoxBlocks), dim3(kBlock), 0, s, (const float*)pt, np, q_mean, nq,
+                     box_part);
+  hipLaunchKernelGGL(k_ov_box_final, dim3(1), dim3(64), 0, s, (const float*)box_part, kOvBoxBlocks, box);
+  OvSet set[2];
+  for (int k = 0; k < 2; ++k) {
+    const int n = k ? nq : np;
+    const float* src = k ? q_mean : pt;
+    const size_t* S = k ? L.set_q : L.set_p;
+    uint32_t* ca = reinterpret_cast<uint32_t*>(w + L.code_a);
+    uint32_t* ia = reinterpret_cast<uint32_t*>(w + L.idx_a);
+    uint32_t* cb = reinterpret_cast<uint32_t*>(w + L.code_b);
+    uint32_t* ib = reinterpret_cast<uint32_t*>(w + L.idx_b);
+    hipLaunchKernelGGL(k_ov_codes, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, n, (const float*)box, ca,
+                       ia);
+    const int which = launch_radix_sort_pairs(ca, ia, cb, ib, n, 30, reinterpret_cast<uint32_t*>(w + L.hist),
+                                              reinterpret_cast<uint32_t*>(w + L.digits), s);
+    const uint32_t* code = which ? cb : ca;
+    const uint32_t* order = which ? ib : ia;
+    const int nleaf = (n + kOvLeaf - 1) / kOvLeaf, nsuper = (nleaf + kOvSuper - 1) / kOvSuper;
+    float* sp = reinterpret_cast<float*>(w + S[0]);
+    int32_t* sidx = reinterpret_cast<int32_t*>(w + S[1]);
+    uint32_t* scode = reinterpret_cast<uint32_t*>(w + S[2]);
+    float* leaf = reinterpret_cast<float*>(w + S[3]);
+    float* sup = reinterpret_cast<float*>(w + S[4]);
+    hipLaunchKernelGGL(k_ov_gather, dim3((n + kBlock - 1) / kBlock), dim3(kBlock), 0, s, src, n, order, code, sp,
+                       sidx, scode, leaf);
+    hipLaunchKernelGGL(k_ov_super, dim3((nsuper + kBlock - 1) / kBlock), dim3(kBlock), 0, s, (const float*)leaf,
+                       nleaf, sup, nsuper);
+    set[k] = OvSet{sp, sidx, scode, leaf, sup, n, nleaf, nsuper};
+  }
+  const int waves_per_block = kBlock / kOvLeaf;
+  hipLaunchKernelGGL(k_ov_nn, dim3((set[0].nleaf + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, s,
+                     set[0], set[1], nn_pq);
+  hipLaunchKernelGGL(k_ov_nn, dim3((set[1].nleaf + waves_per_block - 1) / waves_per_block), dim3(kBlock), 0, s,
+                     set[1], set[0], nn_qp);
+  const float tau2 = tau * tau;
+  hipLaunchKernelGGL(k_ov_count, dim3((np + kBlock - 1) / kBlock), dim3(kBlock), 0, s, (const float*)pt, np, q_mean,
+                     nq, (const int32_t*)nn_pq, (const int32_t*)nn_qp, tau2, counts);
+}
+
+}  // namespace ls

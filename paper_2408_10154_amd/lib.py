@@ -150,6 +150,9 @@ _PROTOS = {
                                     _P, _P]),
     "ls_loss_isotropic": (C.c_int32, [_P, C.c_int64, C.c_float, _P, _P, _P, _P]),
     "ls_adjust_submaps": (C.c_int32, [C.POINTER(ls_submap_adjust), C.c_int32, _P]),
+    "ls_overlap_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32]),
+    "ls_overlap_ratio": (C.c_int32, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_float), C.c_float, _P, _P, _P, _P,
+                                     C.c_size_t, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
@@ -267,6 +270,14 @@ def ls_loss_isotropic(log_scale, n, lambda_reg, loss, grad_log_scale, work, stre
 
 def ls_adjust_submaps(subs, count, stream):
     return _call("ls_adjust_submaps", subs, count, stream)
+
+
+def ls_overlap_workspace_size(np_, nq):
+    return load().ls_overlap_workspace_size(np_, nq)
+
+
+def ls_overlap_ratio(p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, work, work_bytes, stream):
+    return _call("ls_overlap_ratio", p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, work, work_bytes, stream)
 
 
 def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):

@@ -322,6 +322,29 @@ def adjust_submaps(subs):
     L.ls_adjust_submaps(arr, len(subs), _stream())
 
 
+def overlap_ratio(p_mean: torch.Tensor, q_mean: torch.Tensor, T, tau: float, work=None):
+    """Geometric overlap ratio of two Gaussian sets (means [3, n] device
+    tensors) under the estimate T (3x4 or 4x4) of T_{P->Q}: returns
+    (ratio, reciprocal pairs, pairs closer than tau, nn_pq, nn_qp); the two
+    counts are read back to the host."""
+    for t in (p_mean, q_mean):
+        if t.dim() != 2 or t.shape[0] != 3 or not t.is_contiguous() or not t.is_cuda:
+            raise ValueError("means must be contiguous [3, n] device tensors")
+    n_p, n_q = p_mean.shape[1], q_mean.shape[1]
+    dev = p_mean.device
+    need = L.ls_overlap_workspace_size(n_p, n_q)
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    nn_pq = torch.empty(n_p, dtype=torch.int32, device=dev)
+    nn_qp = torch.empty(n_q, dtype=torch.int32, device=dev)
+    counts = torch.empty(2, dtype=torch.int32, device=dev)
+    Tc = (C.c_float * 12)(*[float(v) for v in np.asarray(T, np.float64)[:3, :4].reshape(-1)])
+    L.ls_overlap_ratio(_ptr(p_mean), n_p, _ptr(q_mean), n_q, Tc, float(tau), _ptr(nn_pq), _ptr(nn_qp), _ptr(counts),
+                       _ptr(work), work.numel(), _stream())
+    pairs, inliers = (int(v) for v in counts.cpu())
+    return (inliers / pairs if pairs else 0.0), pairs, inliers, nn_pq, nn_qp
+
+
 def adam(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=True):
     """Fused Adam over (param, grad, m, v, lr) tuples of float32 device tensors."""
     for i in range(0, len(groups), 16):

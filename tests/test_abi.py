@@ -70,6 +70,11 @@ def test_invalid_arguments_are_rejected_without_a_device():
     sub = L.ls_submap_adjust(5, 0, None, None, None, (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0))
     assert lib.ls_adjust_submaps(C.byref(sub), 1, None) == L.LS_ERR_INVALID  # NULL arrays
     assert lib.ls_adjust_submaps(None, -1, None) == L.LS_ERR_INVALID
+    T = (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    fake = C.c_void_p(256)  # never dereferenced: the calls fail validation first
+    assert lib.ls_overlap_ratio(fake, 4, fake, 4, T, 0.0, fake, fake, fake, fake, 1 << 30, None) == L.LS_ERR_INVALID
+    assert lib.ls_overlap_ratio(fake, 4, fake, 4, T, 0.1, fake, fake, fake, fake, 0, None) == L.LS_ERR_CAPACITY
+    assert lib.ls_overlap_workspace_size(1000, 2000) > 0 and lib.ls_overlap_workspace_size(-1, 5) == 0
     prm = L.ls_mapping_params(1.5, 1.0, 1.0, 0)  # lambda_ssim outside [0, 1]
     assert lib.ls_loss_mapping(None, None, None, None, C.byref(prm), None, None, None, None, None) == L.LS_ERR_INVALID
     assert lib.ls_struct_size(b"no_such_struct") == -1
