@@ -7,8 +7,8 @@
 // 30-bit Morton curve and cut into leaf blocks of 64 points (one wave) and
 // superblocks of 32 leaves, each with its bounding box.  A wave of 64 query
 // points visits the candidate superblocks and leaves outward from the
-// query's place on the curve and skips any box farther from the query box
-// than the farthest current best of its lanes (with a margin over FP32
+// query's place on the curve and skips any box that is farther from every
+// one of its points than that point's current best (with a margin over FP32
 // rounding), so no skipped point can win or tie.  Distances and the
 // transform follow one fixed FP32 rounding sequence (no fused multiply-add)
 // so that matches and ties are reproducible: d^2 = (dx^2 + dy^2) + dz^2,
@@ -40,14 +40,6 @@ __device__ __forceinline__ float wave_min_f(float v) {
 #pragma unroll
   for (int o = 32; o > 0; o >>= 1) v = fminf(v, __shfl_xor(v, o, 64));
   return v;
-}
-
-// Squared distance between two boxes (min xyz, max xyz); 0 when they meet.
-__device__ __forceinline__ float box_dist2(const float* a, const float* b) {
-  const float g0 = fmaxf(fmaxf(a[0] - b[3], b[0] - a[3]), 0.f);
-  const float g1 = fmaxf(fmaxf(a[1] - b[4], b[1] - a[4]), 0.f);
-  const float g2 = fmaxf(fmaxf(a[2] - b[5], b[2] - a[5]), 0.f);
-  return g0 * g0 + g1 * g1 + g2 * g2;
 }
 
 // P moved by T (row-major 3x4): ((R_r0 x + R_r1 y) + R_r2 z) + t_r, each
@@ -196,7 +188,40 @@ struct OvSet {
   int n, nleaf, nsuper;
 };
 
+// Squared distance from a point to a box (min xyz, max xyz); 0 inside.
+__device__ __forceinline__ float point_box_dist2(float x, float y, float z, const float* b) {
+  const float g0 = fmaxf(fmaxf(b[0] - x, x - b[3]), 0.f);
+  const float g1 = fmaxf(fmaxf(b[1] - y, y - b[4]), 0.f);
+  const float g2 = fmaxf(fmaxf(b[2] - z, z - b[5]), 0.f);
+  return g0 * g0 + g1 * g1 + g2 * g2;
+}
+
 // One wave per query leaf: the exact nearest candidate of each of its points.
+// The wave first scans the candidate leaf at the query leaf's place on the
+// curve (a close first bound), then every superblock outward from there; a
+// superblock or leaf is skipped when, for every lane, its box is farther than
+// that lane's current best (scaled by kOvPrune against FP32 rounding), so a
+// skipped point can neither win nor tie.
+__device__ __forceinline__ void ov_scan_leaf(const OvSet& c, int l, int lane, float px, float py, float pz,
+                                             float& best, int& bi) {
+  const int ci = l * kOvLeaf + lane;
+  const bool cv = ci < c.n;
+  const float ax = cv ? c.p[ci] : 0.f, ay = cv ? c.p[(int64_t)c.n + ci] : 0.f;
+  const float az = cv ? c.p[2 * (int64_t)c.n + ci] : 0.f;
+  const int aid = cv ? c.idx[ci] : 0;
+  const int cnt = c.n - l * kOvLeaf < kOvLeaf ? c.n - l * kOvLeaf : kOvLeaf;
+  for (int j = 0; j < cnt; ++j) {
+    const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), j));
+    const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), j));
+    const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), j));
+    const int bid = __builtin_amdgcn_readlane(aid, j);
+    const float d = sq_dist_rn(px, py, pz, bx, by, bz);
+    const bool take = d < best || (d == best && bid < bi);
+    best = take ? d : best;
+    bi = take ? bid : bi;
+  }
+}
+
 __global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __restrict__ nn_out) {
   const int leaf = (int)((blockIdx.x * (int64_t)kBlock + threadIdx.x) / kOvLeaf);
   const int lane = threadIdx.x & 63;
@@ -205,45 +230,27 @@ __global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __rest
   const bool qv = qi < q.n;
   const float px = qv ? q.p[qi] : 0.f, py = qv ? q.p[(int64_t)q.n + qi] : 0.f;
   const float pz = qv ? q.p[2 * (int64_t)q.n + qi] : 0.f;
-  float qb[6];
-#pragma unroll
-  for (int d = 0; d < 6; ++d) qb[d] = q.leaf[6 * leaf + d];
-  // start at the candidate superblock holding the query leaf's first code
+  // the candidate leaf holding the query leaf's first code on the curve
   const uint32_t code0 = q.code[leaf * kOvLeaf];
   int lo = 0, hi = c.n;
   while (lo < hi) {
     const int mid = (lo + hi) >> 1;
     if (c.code[mid] < code0) lo = mid + 1; else hi = mid;
   }
-  const int s0 = lo / (kOvLeaf * kOvSuper) < c.nsuper - 1 ? lo / (kOvLeaf * kOvSuper) : c.nsuper - 1;
+  const int l0 = lo / kOvLeaf < c.nleaf - 1 ? lo / kOvLeaf : c.nleaf - 1;
+  const int s0 = l0 / kOvSuper;
   float best = INFINITY;
   int bi = 0x7fffffff;
-  float bound = INFINITY;
+  ov_scan_leaf(c, l0, lane, px, py, pz, best, bi);
   for (int k = 0; k < 2 * c.nsuper; ++k) {
     const int s = (k & 1) ? s0 + (k + 1) / 2 : s0 - k / 2;
     if (s < 0 || s >= c.nsuper) continue;
-    if (box_dist2(qb, c.super + 6 * s) * kOvPrune > bound) continue;
+    if (!__ballot(qv && point_box_dist2(px, py, pz, c.super + 6 * s) * kOvPrune <= best)) continue;
     const int l1 = (s + 1) * kOvSuper < c.nleaf ? (s + 1) * kOvSuper : c.nleaf;
     for (int l = s * kOvSuper; l < l1; ++l) {
-      if (box_dist2(qb, c.leaf + 6 * l) * kOvPrune > bound) continue;
-      const int ci = l * kOvLeaf + lane;
-      const bool cv = ci < c.n;
-      const float ax = cv ? c.p[ci] : 0.f, ay = cv ? c.p[(int64_t)c.n + ci] : 0.f;
-      const float az = cv ? c.p[2 * (int64_t)c.n + ci] : 0.f;
-      const int aid = cv ? c.idx[ci] : 0;
-      const int cnt = c.n - l * kOvLeaf < kOvLeaf ? c.n - l * kOvLeaf : kOvLeaf;
-      for (int j = 0; j < cnt; ++j) {
-        const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), j));
-        const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), j));
-        const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), j));
-        const int bid = __builtin_amdgcn_readlane(aid, j);
-        const float d = sq_dist_rn(px, py, pz, bx, by, bz);
-        if (d < best || (d == best && bid < bi)) {
-          best = d;
-          bi = bid;
-        }
-      }
-      bound = wave_max_f(qv ? best : -INFINITY);
+      if (l == l0) continue;
+      if (!__ballot(qv && point_box_dist2(px, py, pz, c.leaf + 6 * l) * kOvPrune <= best)) continue;
+      ov_scan_leaf(c, l, lane, px, py, pz, best, bi);
     }
   }
   if (qv) nn_out[q.idx[qi]] = bi;
