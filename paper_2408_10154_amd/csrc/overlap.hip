@@ -95,12 +95,26 @@ __global__ __launch_bounds__(256) void k_ov_box_part(const float* __restrict__ a
   }
 }
 
-__global__ void k_ov_box_final(const float* __restrict__ part, int nblk, float* __restrict__ box) {
-  if (threadIdx.x >= 6) return;
-  const int d = threadIdx.x;
-  float v = part[d];
-  for (int k = 1; k < nblk; ++k) v = d < 3 ? fminf(v, part[6 * k + d]) : fmaxf(v, part[6 * k + d]);
-  box[d] = v;
+__global__ __launch_bounds__(256) void k_ov_box_final(const float* __restrict__ part, int nblk,
+                                                      float* __restrict__ box) {
+  __shared__ float ws[4][6];
+  float v[6];
+#pragma unroll
+  for (int d = 0; d < 6; ++d) v[d] = d < 3 ? INFINITY : -INFINITY;
+  for (int k = threadIdx.x; k < nblk; k += kBlock)
+#pragma unroll
+    for (int d = 0; d < 6; ++d) v[d] = d < 3 ? fminf(v[d], part[6 * k + d]) : fmaxf(v[d], part[6 * k + d]);
+#pragma unroll
+  for (int d = 0; d < 6; ++d) v[d] = d < 3 ? wave_min_f(v[d]) : wave_max_f(v[d]);
+  if ((threadIdx.x & 63) == 0)
+    for (int d = 0; d < 6; ++d) ws[threadIdx.x >> 6][d] = v[d];
+  __syncthreads();
+  if (threadIdx.x < 6) {
+    const int d = threadIdx.x;
+    float r = ws[0][d];
+    for (int w = 1; w < 4; ++w) r = d < 3 ? fminf(r, ws[w][d]) : fmaxf(r, ws[w][d]);
+    box[d] = r;
+  }
 }
 
 __device__ __forceinline__ uint32_t spread10(uint32_t v) {
@@ -256,7 +270,8 @@ __global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __rest
   if (qv) nn_out[q.idx[qi]] = bi;
 }
 
-// Reciprocity and the threshold test per point of P; integer atomics.
+// Reciprocity and the threshold test per point of P; one integer atomic per
+// block and count.
 __global__ __launch_bounds__(256) void k_ov_count(const float* __restrict__ pt, int np, const float* __restrict__ q,
                                                   int nq, const int32_t* __restrict__ nn_pq,
                                                   const int32_t* __restrict__ nn_qp, float tau2,
@@ -272,10 +287,16 @@ __global__ __launch_bounds__(256) void k_ov_count(const float* __restrict__ pt, 
       in = d < tau2;
     }
   }
+  __shared__ int32_t ws[4][2];
   const uint64_t bp = __ballot(pair), bn = __ballot(in);
   if ((threadIdx.x & 63) == 0) {
-    if (bp) atomicAdd(&counts[0], (int32_t)__popcll(bp));
-    if (bn) atomicAdd(&counts[1], (int32_t)__popcll(bn));
+    ws[threadIdx.x >> 6][0] = (int32_t)__popcll(bp);
+    ws[threadIdx.x >> 6][1] = (int32_t)__popcll(bn);
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int32_t v = (ws[0][threadIdx.x] + ws[1][threadIdx.x]) + (ws[2][threadIdx.x] + ws[3][threadIdx.x]);
+    if (v) atomicAdd(&counts[threadIdx.x], v);
   }
 }
 
@@ -336,7 +357,7 @@ void launch_overlap(const float* p_mean, int np, const float* q_mean, int nq, co
   float* box = reinterpret_cast<float*>(w + L.box);
   hipLaunchKernelGGL(k_ov_box_part, dim3(kOvBoxBlocks), dim3(kBlock), 0, s, (const float*)pt, np, q_mean, nq,
                      box_part);
-  hipLaunchKernelGGL(k_ov_box_final, dim3(1), dim3(64), 0, s, (const float*)box_part, kOvBoxBlocks, box);
+  hipLaunchKernelGGL(k_ov_box_final, dim3(1), dim3(kBlock), 0, s, (const float*)box_part, kOvBoxBlocks, box);
   OvSet set[2];
   for (int k = 0; k < 2; ++k) {
     const int n = k ? nq : np;
