@@ -16,6 +16,13 @@ Readings (the paper leaves these open):
   R21 weight 1 / max(eps_i, 1e-12)
   R22 translation: weighted mean of the P->Q translations, the Q->P
       estimates inverted first
+  R23 exposure coefficients (supplement, 3DGS registration; optional): per
+      view an affine brightness map of the rendered colour,
+      C' = exp(a) C + b with scalars a, b shared by the three channels,
+      starting at a = b = 0 and optimised with the pose by Adam (learning
+      rate 0.1, the supplement's table; same step count and moments rule).
+      The loss and the residual of R20 see C'.  The paper names exposure
+      coefficients but not their form; this gain/offset form is the reading.
 
 Per-view problem (Sec. 3.2, keyframe localisation).  For keyframe i of P with
 camera-to-world pose T_i (in P's frame) and measurements (I, D)_i, the
@@ -78,13 +85,16 @@ def view_loss(out: dict, tgt_rgb, tgt_depth, loss):
 
 
 def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt_depth, iters: int,
-                  lr_rot: float, lr_trans: float, beta1=0.9, beta2=0.999, eps=1e-8, loss=None):
-    """Optimise the camera-frame correction Delta of one keyframe (R18-R20).
+                  lr_rot: float, lr_trans: float, beta1=0.9, beta2=0.999, eps=1e-8, loss=None,
+                  lr_exposure: float | None = None, return_exposure: bool = False):
+    """Optimise the camera-frame correction Delta of one keyframe (R18-R20),
+    and with lr_exposure set its exposure coefficients (a, b) too (R23).
 
     gauss: the *other* submap (float64 tensors, held fixed); c2w: the
     keyframe's camera-to-world pose in its own submap; targets [3,H,W], [H,W];
     loss: None (plain L1) or loss_tracking's keyword arguments (R24).
-    Returns (Delta as a pose 7-vector, residual eps, loss history).
+    Returns (Delta as a pose 7-vector, residual eps, loss history), plus (a, b)
+    when return_exposure.
     """
     w2c = torch.as_tensor(inv_rigid(np.asarray(c2w, np.float64))[:3, :])
     fixed = {k: v.detach() for k, v in gauss.items()}
@@ -94,20 +104,34 @@ def localise_view(gauss: dict, cam: raster.Camera, c2w: np.ndarray, tgt_rgb, tgt
     mt, vt = torch.zeros(3, dtype=F64), torch.zeros(3, dtype=F64)
     tgt_rgb = torch.as_tensor(np.asarray(tgt_rgb, np.float64))
     tgt_depth = torch.as_tensor(np.asarray(tgt_depth, np.float64))
+    ab = torch.zeros(2, dtype=F64, requires_grad=lr_exposure is not None)
+    mab, vab = torch.zeros(2, dtype=F64), torch.zeros(2, dtype=F64)
+
+    def exposed(out):
+        if lr_exposure is None:
+            return out
+        return dict(out, rgb=torch.exp(ab[0]) * out["rgb"] + ab[1])
+
+    params = [q, t] + ([ab] if lr_exposure is not None else [])
     hist = []
     for it in range(1, iters + 1):
-        out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
+        out = exposed(raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False))
         val = view_loss(out, tgt_rgb, tgt_depth, loss)
         # an empty render (nothing in front of the camera) does not depend on the pose
-        gq, gt = torch.autograd.grad(val, [q, t], allow_unused=True) if val.requires_grad else (None, None)
-        gq = torch.zeros(4, dtype=F64) if gq is None else gq
-        gt = torch.zeros(3, dtype=F64) if gt is None else gt
+        grads = torch.autograd.grad(val, params, allow_unused=True) if val.requires_grad else [None] * len(params)
+        gq = torch.zeros(4, dtype=F64) if grads[0] is None else grads[0]
+        gt = torch.zeros(3, dtype=F64) if grads[1] is None else grads[1]
         adam_step(q, gq, mq, vq, it, lr_rot, beta1, beta2, eps)
         adam_step(t, gt, mt, vt, it, lr_trans, beta1, beta2, eps)
+        if lr_exposure is not None:
+            gab = torch.zeros(2, dtype=F64) if grads[2] is None else grads[2]
+            adam_step(ab, gab, mab, vab, it, lr_exposure, beta1, beta2, eps)
         hist.append(float(val.detach()))
     with torch.no_grad():
-        out = raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False)
+        out = exposed(raster.render(fixed, cam, w2c, torch.cat([q, t]), with_margins=False))
         resid = float(raster.loss_l1(out["rgb"], out["depth"], tgt_rgb, tgt_depth))
+    if return_exposure:
+        return torch.cat([q, t]).detach().numpy(), resid, hist, ab.detach().numpy().copy()
     return torch.cat([q, t]).detach().numpy(), resid, hist
 
 
@@ -142,24 +166,22 @@ def fuse(estimates, residuals, reverse) -> np.ndarray:
 
 
 def register_pair(P: dict, Q: dict, views_p, views_q, cam: raster.Camera, iters: int, lr_rot: float,
-                  lr_trans: float, loss=None):
+                  lr_trans: float, loss=None, lr_exposure: float | None = None):
     """Full pair registration: every keyframe of P localised in Q and every
-    keyframe of Q in P, then fused (Sec. 3.2).
+    keyframe of Q in P, then fused (Sec. 3.2); with lr_exposure set, each
+    view also fits its exposure coefficients (R23).
 
     P, Q: float64 Gaussian dicts; views_*: lists of (c2w 4x4, rgb [3,H,W],
     depth [H,W]).  Returns (T_bar 4x4, per-view estimates, residuals).
     """
     ests, res, rev = [], [], []
-    for c2w, rgb, dep in views_p:
-        d, r, _ = localise_view(Q, cam, c2w, rgb, dep, iters, lr_rot, lr_trans, loss=loss)
-        ests.append(view_estimate(c2w, d))
-        res.append(r)
-        rev.append(False)
-    for c2w, rgb, dep in views_q:
-        d, r, _ = localise_view(P, cam, c2w, rgb, dep, iters, lr_rot, lr_trans, loss=loss)
-        ests.append(view_estimate(c2w, d))
-        res.append(r)
-        rev.append(True)
+    for views, other, reverse in ((views_p, Q, False), (views_q, P, True)):
+        for c2w, rgb, dep in views:
+            d, r, _ = localise_view(other, cam, c2w, rgb, dep, iters, lr_rot, lr_trans, loss=loss,
+                                    lr_exposure=lr_exposure)
+            ests.append(view_estimate(c2w, d))
+            res.append(r)
+            rev.append(reverse)
     return fuse(ests, res, rev), ests, res
 
 

@@ -150,3 +150,57 @@ def test_residual_is_the_unmasked_l1_whatever_the_loss():
     valid = dep > 0
     expect = (np.abs(rgb).sum(0)[valid].sum() + np.abs(dep)[valid].sum()) / valid.sum()
     assert hist[0] == 0.0 and resid == pytest.approx(expect, rel=1e-12)
+
+
+def _exposed_target(seed, a_true, b_true):
+    d = _tiny_pair(seed, 2.0, 0.03)
+    cam = R.Camera(**d["cam"])
+    P = R.to_f64(d["P"])
+    (c2w, rgb, dep), = _targets(P, cam, d["kf_p"])
+    return d, cam, P, c2w, math.exp(a_true) * rgb + b_true, dep
+
+
+def test_exposure_recovers_a_known_gain_and_offset():
+    """R23: the keyframe's own submap rendered at its exact pose, but with the
+    colours under a known exposure (gain 1.2, offset 0.03).  With exposure
+    coefficients the view recovers them (a to 0.02, b to 0.01) and stays at
+    the identity pose (< 0.3 cm); without them the pose drifts to absorb the
+    brightness change and the residual is 20x larger."""
+    a0, b0 = math.log(1.2), 0.03
+    d, cam, P, c2w, rgb, dep = _exposed_target(4, a0, b0)
+    pose_e, res_e, _, ab = G.localise_view(P, cam, c2w, rgb, dep, 100, 0.003, 0.001, lr_exposure=0.1,
+                                           return_exposure=True)
+    pose_n, res_n, _ = G.localise_view(P, cam, c2w, rgb, dep, 100, 0.003, 0.001)
+    assert abs(ab[0] - a0) < 0.02 and abs(ab[1] - b0) < 0.01, ab
+    assert np.linalg.norm(pose_e[4:]) < 0.003
+    assert res_n > 20 * res_e
+
+
+def test_exposure_with_zero_learning_rate_is_the_plain_path():
+    """a = b = 0 held fixed: exp(0) C + 0 = C, so every step equals the
+    localisation without exposure coefficients, bit for bit."""
+    d, cam, P, c2w, rgb, dep = _exposed_target(5, 0.1, 0.02)
+    a = G.localise_view(P, cam, c2w, rgb, dep, 15, 0.003, 0.001, lr_exposure=0.0, return_exposure=True)
+    b = G.localise_view(P, cam, c2w, rgb, dep, 15, 0.003, 0.001)
+    np.testing.assert_array_equal(a[0], b[0])
+    assert a[1] == b[1] and a[2] == b[2] and np.all(a[3] == 0.0)
+
+
+def test_exposure_gradient_matches_finite_differences():
+    """d loss / d(a, b) of the exposed render (autograd) against central
+    differences, away from the L1 kinks of the unmasked loss."""
+    d, cam, P, c2w, rgb, dep = _exposed_target(6, 0.15, 0.05)
+    out = R.render(P, cam, torch.as_tensor(G.inv_rigid(c2w)[:3]), with_margins=False)
+    C = out["rgb"].detach()
+    tr, td = torch.as_tensor(rgb), torch.as_tensor(dep)
+
+    def f(ab):
+        return R.loss_l1(torch.exp(ab[0]) * C + ab[1], out["depth"].detach(), tr, td)
+
+    ab = torch.tensor([0.05, 0.01], dtype=torch.float64, requires_grad=True)
+    (g,) = torch.autograd.grad(f(ab), [ab])
+    for k in range(2):
+        e = torch.zeros(2, dtype=torch.float64)
+        e[k] = 1e-7
+        fd = (float(f(ab.detach() + e)) - float(f(ab.detach() - e))) / 2e-7
+        np.testing.assert_allclose(float(g[k]), fd, rtol=1e-5)
