@@ -443,6 +443,11 @@ typedef struct {
   int32_t exit_patience;    /* by more than exit_rel_tol (relative) for exit_patience iterations; 0 = off */
   int32_t loss_kind;        /* 0: plain L1 (ls_loss_l1); 1: tracking loss with masks (ls_loss_tracking) */
   ls_loss_params track;     /* weights and masks when loss_kind == 1 */
+  int32_t exposure;         /* 1: per-view exposure coefficients (supplement, 3DGS registration): the
+                               rendered colour enters the loss and the residual as exp(a) C + b, with
+                               scalars a, b per view starting at 0 and taking the pose's Adam step
+                               (ls_register_pair only; the server rejects it); 0: off */
+  float lr_exposure;        /* their learning rate (0.1 in the supplement) */
 } ls_reg_params;
 
 typedef struct {
@@ -452,6 +457,7 @@ typedef struct {
                          of each view at its final pose, whichever loss drove it */
   int32_t status;     /* LS_OK, or the error of this pair */
   int32_t iters_done; /* Adam steps of the longest-running view */
+  float* exposure;    /* host [vP + vQ][2] or NULL: each view's final (a, b) when exposure is on */
 } ls_reg_result;
 
 /* Registers one pair with all 2V views in one launch set per iteration.

@@ -146,6 +146,20 @@ ls_status check_loss_params(const ls_loss_params* prm, const ls_image* pred) {
   return LS_OK;
 }
 
+ls_status batch_loss_exposure(const ls_batch* b, int kind, const ls_loss_params* prm, const ls_image* pred,
+                              const float* tgt_rgb, const float* tgt_depth, const float* expo, float* epart,
+                              float* egrad, float* loss, float* grad_rgb, float* grad_depth, float* grad_scale,
+                              hipStream_t s) {
+  if (kind == 1)
+    launch_loss_track(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, pred->alpha, tgt_rgb,
+                      tgt_depth, prm->lambda_c, prm->inlier_k, prm->alpha_power, b->sel_d, b->median_d, grad_rgb,
+                      grad_depth, b->loss_part_d, loss, grad_scale, s, expo, epart, egrad);
+  else
+    launch_loss_l1(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, tgt_rgb, tgt_depth, grad_rgb,
+                   grad_depth, b->loss_part_d, loss, grad_scale, s, expo, epart, egrad);
+  return hipGetLastError() == hipSuccess ? LS_OK : LS_ERR_HIP;
+}
+
 ls_status batch_loss_tracking(const ls_batch* b, const ls_image* pred, const ls_loss_params* prm, float* loss,
                               float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s) {
   launch_loss_track(b->jobs_d, b->pblk_off_d, b->R, b->nblk_pix, pred->rgb, pred->depth, pred->alpha, nullptr, nullptr,

@@ -45,4 +45,12 @@ ls_status batch_loss_l1(const ls_batch* b, const ls_image* pred, float* loss, fl
                         float* grad_scale, hipStream_t s);
 ls_status batch_loss_tracking(const ls_batch* b, const ls_image* pred, const ls_loss_params* prm, float* loss,
                               float* grad_rgb, float* grad_depth, float* grad_scale, hipStream_t s);
+// The registration losses with per-render exposure coefficients expo [R][2]
+// (colour residual on exp(a) C + b): kind 0 plain L1, 1 tracking loss.  egrad
+// [R][2] (or NULL) receives dL/d(a, b); epart holds 2 floats per 1024-pixel
+// block.  Targets laid out like the batch's images.
+ls_status batch_loss_exposure(const ls_batch* b, int kind, const ls_loss_params* prm, const ls_image* pred,
+                              const float* tgt_rgb, const float* tgt_depth, const float* expo, float* epart,
+                              float* egrad, float* loss, float* grad_rgb, float* grad_depth, float* grad_scale,
+                              hipStream_t s);
 }  // namespace ls

@@ -54,8 +54,12 @@ struct ViewOpt {
   int32_t pad;
 };
 void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s);
+// With expo non-null, each view's exposure coefficients (a, b) take the same
+// Adam step (learning rate lr_expo) from egrad, which is consumed.
 void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
-                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s);
+                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s,
+                      float* expo = nullptr, float* egrad = nullptr, float* em = nullptr, float* ev = nullptr,
+                      float lr_expo = 0.f);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
 void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
                         float* nm, float* nv, float* ngrad, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt,
@@ -65,15 +69,20 @@ void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s);
 void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                          const int32_t* items, const int32_t* range, const int32_t* nl, int64_t* stats, hipStream_t s);
 
+// The loss launchers take optional exposure coefficients (expo [R][2], the
+// colour residual then taken on exp(a) C + b) with their block partials
+// (epart, 2 floats per 1024-pixel block) and gradients (egrad [R][2]).
 void launch_loss_l1(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
                     const float* pred_depth, const float* tgt_rgb, const float* tgt_depth, float* g_rgb,
-                    float* g_depth, float* part, float* loss, float* scale, hipStream_t s);
+                    float* g_depth, float* part, float* loss, float* scale, hipStream_t s,
+                    const float* expo = nullptr, float* epart = nullptr, float* egrad = nullptr);
 // Tracking loss with masks; sel = per-render selection workspace
 // (kSelWords(R) uint32, zero on first use, left zeroed after each call).
 void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
                        const float* pred_depth, const float* pred_alpha, const float* tgt_rgb, const float* tgt_depth,
                        float lambda_c, float inlier_k, int alpha_power, uint32_t* sel, float* median, float* g_rgb,
-                       float* g_depth, float* part, float* loss, float* scale, hipStream_t s);
+                       float* g_depth, float* part, float* loss, float* scale, hipStream_t s,
+                       const float* expo = nullptr, float* epart = nullptr, float* egrad = nullptr);
 inline int64_t sel_words(int R) { return (int64_t)R * (4 + 2048); }
 
 // Mapping loss (mapping_loss.hip).  SSIM blocks of a W x H render (3 colour

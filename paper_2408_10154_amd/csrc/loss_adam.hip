@@ -8,19 +8,53 @@ namespace ls {
 constexpr int kLossPix = 4;  // pixels per thread
 constexpr int kLossBlockPix = 256 * kLossPix;
 
+// Per-render exposure coefficients (a, b) of the rendered colour, C' =
+// exp(a) C + b (registration with exposure compensation); identity without.
+struct Exposure {
+  float gain, offset;
+  bool on;
+};
+__device__ __forceinline__ Exposure exposure_of(const float* expo, int r) {
+  Exposure e{1.f, 0.f, expo != nullptr};
+  if (e.on) {
+    e.gain = expf(expo[2 * r]);
+    e.offset = expo[2 * r + 1];
+  }
+  return e;
+}
+
+// Block sums of the exposure-gradient terms (sum g' e^a C and sum g' over
+// the block's pixels and channels, g' = dL/dC' before the 1/|Omega| scale).
+__device__ __forceinline__ void exposure_partials(float sa, float sb, float* epart) {
+  sa = wave_sum(sa);
+  sb = wave_sum(sb);
+  __shared__ float we[4][2];
+  if ((threadIdx.x & 63) == 0) { we[threadIdx.x >> 6][0] = sa; we[threadIdx.x >> 6][1] = sb; }
+  __syncthreads();
+  if (threadIdx.x < 2) {
+    const int q = threadIdx.x;
+    epart[2 * (int64_t)blockIdx.x + q] = (we[0][q] + we[1][q]) + (we[2][q] + we[3][q]);
+  }
+}
+
 // Per block of 1024 pixels (blocks never straddle renders): writes sign
-// gradients on valid pixels and the block's (sum |residual|, valid count).
+// gradients on valid pixels and the block's (sum |residual|, valid count);
+// with exposure coefficients the colour residual is taken on exp(a) C + b,
+// the colour gradient carries the factor exp(a) and epart receives the
+// block's exposure-gradient terms.
 __global__ __launch_bounds__(256) void k_loss_l1(const JobDev* __restrict__ jobs, const int32_t* __restrict__ pblk_off,
                                                  int R, const float* __restrict__ pred_rgb,
                                                  const float* __restrict__ pred_depth,
                                                  const float* __restrict__ tgt_rgb,
                                                  const float* __restrict__ tgt_depth, float* __restrict__ g_rgb,
-                                                 float* __restrict__ g_depth, float* __restrict__ part) {
+                                                 float* __restrict__ g_depth, float* __restrict__ part,
+                                                 const float* __restrict__ expo, float* __restrict__ epart) {
   const int r = find_segment<int32_t>(pblk_off, R, (int32_t)blockIdx.x);
   const JobDev& J = jobs[r];
   const int64_t hw = (int64_t)J.W * J.H;
   const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * kLossBlockPix;
-  float s = 0.f, cnt = 0.f;
+  const Exposure ex = exposure_of(expo, r);
+  float s = 0.f, cnt = 0.f, sa = 0.f, sb = 0.f;
   for (int k = 0; k < kLossPix; ++k) {
     const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
     if (p >= hw) break;
@@ -34,12 +68,19 @@ __global__ __launch_bounds__(256) void k_loss_l1(const JobDev* __restrict__ jobs
     l += fabsf(dd);
     if (g_depth) g_depth[pi] = valid ? (dd > 0.f ? 1.f : (dd < 0.f ? -1.f : 0.f)) : 0.f;
     for (int ch = 0; ch < 3; ++ch) {
-      const float dc = pred_rgb[ci + ch * hw] - trgb[ch * hw];
+      const float pc = pred_rgb[ci + ch * hw];
+      const float dc = (ex.on ? ex.gain * pc + ex.offset : pc) - trgb[ch * hw];
       l += fabsf(dc);
-      if (g_rgb) g_rgb[ci + ch * hw] = valid ? (dc > 0.f ? 1.f : (dc < 0.f ? -1.f : 0.f)) : 0.f;
+      const float sg = dc > 0.f ? 1.f : (dc < 0.f ? -1.f : 0.f);
+      if (g_rgb) g_rgb[ci + ch * hw] = valid ? (ex.on ? ex.gain * sg : sg) : 0.f;
+      if (valid && ex.on) {
+        sa += sg * ex.gain * pc;
+        sb += sg;
+      }
     }
     if (valid) { s += l; cnt += 1.f; }
   }
+  if (epart) exposure_partials(sa, sb, epart);
   s = wave_sum(s);
   cnt = wave_sum(cnt);
   __shared__ float ws[4][2];
@@ -51,21 +92,36 @@ __global__ __launch_bounds__(256) void k_loss_l1(const JobDev* __restrict__ jobs
   }
 }
 
-// One wave per render: ordered sum of the block partials.
+// One wave per render: ordered sum of the block partials; with exposure
+// partials, also dL/d(a, b) = (1/|Omega|) (sum g' e^a C, sum g').
 __global__ void k_loss_reduce(const int32_t* __restrict__ pblk_off, int R, const float* __restrict__ part,
-                              float* __restrict__ loss, float* __restrict__ scale) {
+                              float* __restrict__ loss, float* __restrict__ scale, const float* __restrict__ epart,
+                              float* __restrict__ egrad) {
   const int r = blockIdx.x;
   if (r >= R) return;
-  float s = 0.f, c = 0.f;
+  float s = 0.f, c = 0.f, sa = 0.f, sb = 0.f;
   for (int b = pblk_off[r] + threadIdx.x; b < pblk_off[r + 1]; b += 64) {
     s += part[2 * (int64_t)b];
     c += part[2 * (int64_t)b + 1];
+    if (epart) {
+      sa += epart[2 * (int64_t)b];
+      sb += epart[2 * (int64_t)b + 1];
+    }
   }
   s = wave_sum(s);
   c = wave_sum(c);
+  if (epart) {
+    sa = wave_sum(sa);
+    sb = wave_sum(sb);
+  }
   if (threadIdx.x == 0) {
+    const float inv = c > 0.f ? 1.f / c : 0.f;
     if (loss) loss[r] = c > 0.f ? s / c : 0.f;
-    if (scale) scale[r] = c > 0.f ? 1.f / c : 0.f;
+    if (scale) scale[r] = inv;
+    if (egrad) {
+      egrad[2 * r] = sa * inv;
+      egrad[2 * r + 1] = sb * inv;
+    }
   }
 }
 
@@ -192,13 +248,15 @@ __global__ __launch_bounds__(256) void k_loss_track(const JobDev* __restrict__ j
                                                     const float* __restrict__ tgt_depth,
                                                     const float* __restrict__ median, float lambda_c, float inlier_k,
                                                     int alpha_power, float* __restrict__ g_rgb,
-                                                    float* __restrict__ g_depth, float* __restrict__ part) {
+                                                    float* __restrict__ g_depth, float* __restrict__ part,
+                                                    const float* __restrict__ expo, float* __restrict__ epart) {
   const int r = find_segment<int32_t>(pblk_off, R, (int32_t)blockIdx.x);
   const JobDev& J = jobs[r];
   const int64_t hw = (int64_t)J.W * J.H;
   const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * kLossBlockPix;
   const float thr = inlier_k > 0.f ? inlier_k * median[r] : 0.f;
-  float s = 0.f, cnt = 0.f;
+  const Exposure ex = exposure_of(expo, r);
+  float s = 0.f, cnt = 0.f, sa = 0.f, sb = 0.f;
   for (int k = 0; k < kLossPix; ++k) {
     const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
     if (p >= hw) break;
@@ -219,9 +277,15 @@ __global__ __launch_bounds__(256) void k_loss_track(const JobDev* __restrict__ j
     const float wc = w * lambda_c, wd = w * (1.f - lambda_c);
     float lc = 0.f;
     for (int ch = 0; ch < 3; ++ch) {
-      const float dc = pred_rgb[ci + ch * hw] - trgb[ch * hw];
+      const float pc = pred_rgb[ci + ch * hw];
+      const float dc = (ex.on ? ex.gain * pc + ex.offset : pc) - trgb[ch * hw];
       lc += fabsf(dc);
-      if (g_rgb) g_rgb[ci + ch * hw] = dc > 0.f ? wc : (dc < 0.f ? -wc : 0.f);
+      const float gc = dc > 0.f ? wc : (dc < 0.f ? -wc : 0.f);
+      if (g_rgb) g_rgb[ci + ch * hw] = ex.on ? ex.gain * gc : gc;
+      if (ex.on) {
+        sa += gc * ex.gain * pc;
+        sb += gc;
+      }
     }
     if (g_depth) g_depth[pi] = dd > 0.f ? wd : (dd < 0.f ? -wd : 0.f);
     if (valid) {
@@ -229,6 +293,7 @@ __global__ __launch_bounds__(256) void k_loss_track(const JobDev* __restrict__ j
       cnt += 1.f;
     }
   }
+  if (epart) exposure_partials(sa, sb, epart);
   s = wave_sum(s);
   cnt = wave_sum(cnt);
   __shared__ float ws[4][2];
@@ -274,17 +339,20 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a, float beta1, float bet
 namespace ls {
 void launch_loss_l1(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
                     const float* pred_depth, const float* tgt_rgb, const float* tgt_depth, float* g_rgb,
-                    float* g_depth, float* part, float* loss, float* scale, hipStream_t s) {
+                    float* g_depth, float* part, float* loss, float* scale, hipStream_t s, const float* expo,
+                    float* epart, float* egrad) {
   if (npblk > 0)
     hipLaunchKernelGGL(k_loss_l1, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, pred_rgb, pred_depth, tgt_rgb,
-                       tgt_depth, g_rgb, g_depth, part);
-  hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale);
+                       tgt_depth, g_rgb, g_depth, part, expo, epart);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale,
+                     (const float*)epart, egrad);
 }
 
 void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int npblk, const float* pred_rgb,
                        const float* pred_depth, const float* pred_alpha, const float* tgt_rgb, const float* tgt_depth,
                        float lambda_c, float inlier_k, int alpha_power, uint32_t* sel, float* median, float* g_rgb,
-                       float* g_depth, float* part, float* loss, float* scale, hipStream_t s) {
+                       float* g_depth, float* part, float* loss, float* scale, hipStream_t s, const float* expo,
+                       float* epart, float* egrad) {
   SelState* st = reinterpret_cast<SelState*>(sel);
   uint32_t* hist = sel + 4 * (int64_t)R;
   if (inlier_k > 0.f) {
@@ -298,8 +366,9 @@ void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int
   if (npblk > 0)
     hipLaunchKernelGGL(k_loss_track, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, pred_rgb, pred_depth,
                        pred_alpha, tgt_rgb, tgt_depth, (const float*)median, lambda_c, inlier_k, alpha_power, g_rgb,
-                       g_depth, part);
-  hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale);
+                       g_depth, part, expo, epart);
+  hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale,
+                     (const float*)epart, egrad);
 }
 
 void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,

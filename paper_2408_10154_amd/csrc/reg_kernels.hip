@@ -24,14 +24,17 @@ __global__ void k_pose_init(float* __restrict__ pose, float* __restrict__ m, flo
 }
 
 // One thread per render: Adam on its 7 pose values (lr_rot for q, lr_trans
-// for t), bias correction from the render's own step count; the gradient is
-// consumed (zeroed).  Early exit (exit_patience > 0): a view whose loss has
+// for t), and on its 2 exposure coefficients when given (lr_expo), bias
+// correction from the render's own step count; the gradients are consumed
+// (zeroed).  Early exit (exit_patience > 0): a view whose loss has
 // not improved on its best by more than the relative tolerance for
 // exit_patience iterations freezes at its current pose (whose loss is the
 // one just computed) instead of stepping.  Frozen views keep their pose.
 __global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ grad, float* __restrict__ m,
                             float* __restrict__ v, ViewOpt* __restrict__ opt, const float* __restrict__ loss, int R,
-                            float beta1, float beta2, float eps, float exit_tol, int exit_patience) {
+                            float beta1, float beta2, float eps, float exit_tol, int exit_patience,
+                            float* __restrict__ expo, float* __restrict__ egrad, float* __restrict__ em,
+                            float* __restrict__ ev, float lr_expo) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   ViewOpt o = opt[r];
@@ -67,12 +70,28 @@ __global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ grad, 
         const float lr = k < 4 ? o.lr_rot : o.lr_trans;
         pose[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
       }
+      if (expo) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int i = 2 * r + k;
+          const float g = egrad[i];
+          const float mi = beta1 * em[i] + (1.f - beta1) * g;
+          const float vi = beta2 * ev[i] + (1.f - beta2) * g * g;
+          em[i] = mi;
+          ev[i] = vi;
+          expo[i] -= lr_expo * (mi * bc1) / (sqrtf(vi * bc2) + eps);
+        }
+      }
       o.step = step;
     }
     opt[r] = o;
   }
 #pragma unroll
   for (int k = 0; k < 7; ++k) grad[7 * r + k] = 0.f;
+  if (expo) {
+    egrad[2 * r] = 0.f;
+    egrad[2 * r + 1] = 0.f;
+  }
 }
 
 __global__ void k_or_flag(const int32_t* __restrict__ count, int32_t* __restrict__ sticky) {
@@ -85,9 +104,10 @@ void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipS
 }
 
 void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
-                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s) {
+                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s,
+                      float* expo, float* egrad, float* em, float* ev, float lr_expo) {
   hipLaunchKernelGGL(k_pose_adam, dim3((R + 255) / 256), dim3(256), 0, s, pose, grad, m, v, opt, loss, R, beta1, beta2,
-                     eps, exit_tol, exit_patience);
+                     eps, exit_tol, exit_patience, expo, egrad, em, ev, lr_expo);
 }
 
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s) {

@@ -9,6 +9,7 @@
 #include <cstring>
 #include <vector>
 
+#include "batch.h"
 #include "kernels.h"
 #include "register_engine.h"
 
@@ -193,6 +194,9 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   const size_t o_scale = take(4 * R), o_loss = take(4 * R), o_pose = take(28 * R), o_pg = take(28 * R);
   const size_t o_m = take(28 * R), o_v = take(28 * R), o_opt = take(sizeof(ViewOpt) * R), o_range = take(8 * (size_t)T);
   const size_t o_count = take(16), o_sticky = take(4);
+  const bool with_expo = pairs[0].prm.exposure != 0;
+  const int32_t nblk_pix = batch->nblk_pix;
+  const size_t o_expo = with_expo ? take(4 * (8 * (size_t)R + 2 * (size_t)nblk_pix)) : 0;
   if (hipMalloc(&arena, off) != hipSuccess) return LS_ERR_HIP;
   char* a = static_cast<char*>(arena);
   proj.rec = reinterpret_cast<float*>(a + o_rec);
@@ -218,7 +222,14 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   range = reinterpret_cast<int32_t*>(a + o_range);
   count = reinterpret_cast<int32_t*>(a + o_count);
   sticky = reinterpret_cast<int32_t*>(a + o_sticky);
-  if (hipMemsetAsync(arena, 0, off, s) != hipSuccess) return LS_ERR_HIP;
+  if (with_expo) {
+    expo = reinterpret_cast<float*>(a + o_expo);
+    expo_grad = expo + 2 * R;
+    expo_m = expo + 4 * R;
+    expo_v = expo + 6 * R;
+    expo_part = expo + 8 * R;
+  }
+  if (hipMemsetAsync(arena, 0, off, s) != hipSuccess) return LS_ERR_HIP;  // also a = b = 0 and their moments
 
   // targets: each view's measurements, laid out like the batch's images
   for (int r = 0; r < R; ++r) {
@@ -291,7 +302,7 @@ ls_status RegEngine::step(hipStream_t s) {
     return st;
   const ls_reg_params& pm = pairs[0].prm;
   launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, loss, R, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
-                   pm.exit_patience, s);
+                   pm.exit_patience, s, expo, expo_grad, expo_m, expo_v, pm.lr_exposure);
   return hip_ok();
 }
 
@@ -303,14 +314,21 @@ ls_status RegEngine::final_forward(hipStream_t s) {
   ls_status st;
   if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
-  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) ||
-      (st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s)))
-    return st;
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s))) return st;
+  if (expo)  // the residual sees the view's fitted exposure
+    st = batch_loss_exposure(batch, 0, nullptr, &img, tgt_rgb, tgt_depth, expo, nullptr, nullptr, loss, g_rgb,
+                             g_depth, scale, s);
+  else
+    st = ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s);
+  if (st) return st;
   return hip_ok();
 }
 
 ls_status RegEngine::view_loss(hipStream_t s) {
   const ls_reg_params& pm = pairs[0].prm;
+  if (expo)
+    return batch_loss_exposure(batch, pm.loss_kind, &pm.track, &img, tgt_rgb, tgt_depth, expo, expo_part, expo_grad,
+                               loss, g_rgb, g_depth, scale, s);
   if (pm.loss_kind == 1)
     return ls_loss_tracking(batch, &img, tgt_rgb, tgt_depth, &pm.track, loss, nullptr, g_rgb, g_depth, scale, s);
   return ls_loss_l1(batch, &img, tgt_rgb, tgt_depth, loss, g_rgb, g_depth, scale, s);
@@ -358,6 +376,15 @@ ls_status RegEngine::fuse_pair(int p, const std::vector<float>& pose_h, const st
   return LS_OK;
 }
 
+ls_status RegEngine::read_exposure(int p, ls_reg_result* out, hipStream_t s) {
+  if (!out->exposure || !expo) return LS_OK;
+  const int v0 = first_view[p], n = first_view[p + 1] - v0;
+  if (hipMemcpyAsync(out->exposure, expo + 2 * v0, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LS_ERR_HIP;
+  return LS_OK;
+}
+
 ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
   if (!p || !prm) return LS_ERR_INVALID;
   if (p->vP < 0 || p->vQ < 0 || p->vP + p->vQ < 1) return LS_ERR_INVALID;
@@ -366,7 +393,8 @@ ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
   if (p->vQ > 0 && (!p->rgbQ || !p->depthQ || !p->c2wQ || p->P.n < 0)) return LS_ERR_INVALID;
   if (prm->iters < 1 || !(prm->lr_rot >= 0) || !(prm->lr_trans >= 0) || !(prm->beta1 >= 0 && prm->beta1 < 1) ||
       !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0) || !(prm->exit_rel_tol >= 0) ||
-      prm->exit_patience < 0 || prm->loss_kind < 0 || prm->loss_kind > 1)
+      prm->exit_patience < 0 || prm->loss_kind < 0 || prm->loss_kind > 1 || prm->exposure < 0 ||
+      prm->exposure > 1 || (prm->exposure && !(prm->lr_exposure >= 0.f && std::isfinite(prm->lr_exposure))))
     return LS_ERR_INVALID;
   if (prm->loss_kind == 1 && (!(prm->track.lambda_c >= 0.f && prm->track.lambda_c <= 1.f) ||
                               !std::isfinite(prm->track.inlier_k) || prm->track.alpha_power < 0 ||
@@ -448,6 +476,7 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg
       continue;
     }
     st = e.fuse_pair(0, ph, lh, out);
+    if (!st) st = e.read_exposure(0, out, s);
     out->status = st;
     std::vector<ViewOpt> ho(e.R);
     hipMemcpy(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost);

@@ -33,6 +33,7 @@ class RegEngine {
   ls_status view_loss(hipStream_t s);  // the loss the pair's parameters select
   ls_status readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow, hipStream_t s);
   ls_status fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h, ls_reg_result* out);
+  ls_status read_exposure(int p, ls_reg_result* out, hipStream_t s);
   void release();
 
   std::vector<RegPair> pairs;
@@ -51,6 +52,9 @@ class RegEngine {
   float *scale = nullptr, *loss = nullptr, *pose = nullptr, *pose_grad = nullptr, *adam_m = nullptr,
         *adam_v = nullptr;
   ViewOpt* opt = nullptr;
+  // exposure coefficients (a, b) per view, their gradient, Adam moments and
+  // block partials; null unless the pair asks for exposure compensation
+  float *expo = nullptr, *expo_grad = nullptr, *expo_m = nullptr, *expo_v = nullptr, *expo_part = nullptr;
   int32_t *range = nullptr, *count = nullptr, *sticky = nullptr;
 
  private:

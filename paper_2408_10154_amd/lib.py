@@ -97,12 +97,13 @@ class ls_submap_adjust(C.Structure):
 class ls_reg_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lr_rot", C.c_float), ("lr_trans", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("exit_rel_tol", C.c_float),
-                ("exit_patience", C.c_int32), ("loss_kind", C.c_int32), ("track", ls_loss_params)]
+                ("exit_patience", C.c_int32), ("loss_kind", C.c_int32), ("track", ls_loss_params),
+                ("exposure", C.c_int32), ("lr_exposure", C.c_float)]
 
 
 class ls_reg_result(C.Structure):
     _fields_ = [("T_PQ", C.c_float * 12), ("per_view_T", C.c_void_p), ("residual", C.c_void_p),
-                ("status", C.c_int32), ("iters_done", C.c_int32)]
+                ("status", C.c_int32), ("iters_done", C.c_int32), ("exposure", C.c_void_p)]
 
 
 class ls_server_params(C.Structure):

@@ -3,7 +3,8 @@
 `keyframe_targets` renders a submap at its own keyframes with the rasterizer
 (the synthetic stand-in for the keyframes' RGB-D measurements);
 `register_pair` hands one pair to ls_register_pair and returns the fused
-T_{P->Q}, the per-view estimates and residuals.
+T_{P->Q}, the per-view estimates and residuals (and exposure coefficients
+when they are optimised).
 """
 
 from __future__ import annotations
@@ -40,16 +41,20 @@ def keyframe_targets(g: GaussianSet, cam: dict, c2ws: np.ndarray):
 
 
 def default_params(iters=200, lr_rot=0.015, lr_trans=0.005, exit_rel_tol=0.0, exit_patience=0, loss="tracking",
-                   lambda_c=0.6, inlier_k=50.0, alpha_power=3) -> L.ls_reg_params:
+                   lambda_c=0.6, inlier_k=50.0, alpha_power=3, exposure=False,
+                   lr_exposure=0.1) -> L.ls_reg_params:
     """Registration settings: real-data learning rates of the paper's
     loop-closure table by default; early exit off unless exit_patience > 0.
     loss "tracking" is Eq. 2 with the supplement's alpha and inlier masks
     (lambda_c of the real-data column of the per-dataset table), "l1" the
-    plain unmasked colour + depth L1."""
+    plain unmasked colour + depth L1.  exposure: per-view exposure
+    coefficients (gain and offset of the rendered colour) optimised with the
+    pose at lr_exposure (the supplement's 0.1); ls_register_pair only."""
     if loss not in ("tracking", "l1"):
         raise ValueError(f"loss must be 'tracking' or 'l1', not {loss!r}")
     return L.ls_reg_params(iters, lr_rot, lr_trans, 0.9, 0.999, 1e-8, exit_rel_tol, exit_patience,
-                           1 if loss == "tracking" else 0, L.ls_loss_params(lambda_c, inlier_k, alpha_power, 0))
+                           1 if loss == "tracking" else 0, L.ls_loss_params(lambda_c, inlier_k, alpha_power, 0),
+                           1 if exposure else 0, lr_exposure)
 
 
 def make_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ):
@@ -77,16 +82,19 @@ def register_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP,
     nv = pair.vP + pair.vQ
     per_view = np.zeros((nv, 12), np.float32)
     resid = np.zeros(nv, np.float32)
+    expo = np.zeros((nv, 2), np.float32)
     res = L.ls_reg_result()
     res.per_view_T = per_view.ctypes.data_as(C.c_void_p)
     res.residual = resid.ctypes.data_as(C.c_void_p)
+    res.exposure = expo.ctypes.data_as(C.c_void_p)
     L.ls_register_pair(pair, params, res, _stream())
     T = np.eye(4)
     T[:3, :] = np.asarray(res.T_PQ, np.float64).reshape(3, 4)
     pv = np.tile(np.eye(4), (nv, 1, 1))
     pv[:, :3, :] = per_view.reshape(nv, 3, 4)
     del keep
-    return dict(T=T, per_view=pv, residual=resid.astype(np.float64), status=res.status, iters=res.iters_done)
+    return dict(T=T, per_view=pv, residual=resid.astype(np.float64), status=res.status, iters=res.iters_done,
+                exposure=expo.astype(np.float64) if params.exposure else None)
 
 
 def fuse_estimates(estimates, residuals, reverse) -> np.ndarray:

@@ -124,3 +124,8 @@ def test_register_pair_rejects_bad_loss_parameters_before_touching_a_device():
                         (1, L.ls_loss_params(0.6, float("nan"), 3, 0)), (1, L.ls_loss_params(0.6, 50.0, -1, 0))):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, 0, kind, track)
         assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+    # exposure coefficients: flag out of range, or a bad learning rate
+    good = L.ls_loss_params(0.6, 50.0, 3, 0)
+    for expo, lr in ((2, 0.1), (-1, 0.1), (1, -0.1), (1, float("inf"))):
+        prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, 0, 1, good, expo, lr)
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
