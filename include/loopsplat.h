@@ -445,8 +445,8 @@ typedef struct {
   ls_loss_params track;     /* weights and masks when loss_kind == 1 */
   int32_t exposure;         /* 1: per-view exposure coefficients (supplement, 3DGS registration): the
                                rendered colour enters the loss and the residual as exp(a) C + b, with
-                               scalars a, b per view starting at 0 and taking the pose's Adam step
-                               (ls_register_pair only; the server rejects it); 0: off */
+                               scalars a, b per view starting at 0 and taking the pose's Adam step;
+                               0: off.  A server fixes it (and lr_exposure) with its first request */
   float lr_exposure;        /* their learning rate (0.1 in the supplement) */
 } ls_reg_params;
 

@@ -61,9 +61,14 @@ void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt
                       float* expo = nullptr, float* egrad = nullptr, float* em = nullptr, float* ev = nullptr,
                       float lr_expo = 0.f);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
+// Per-view exposure coefficients (a, b) [R][2] with their Adam moments and
+// gradient, or all null.
+struct ExpoState {
+  float *expo, *m, *v, *grad;
+};
 void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
                         float* nm, float* nv, float* ngrad, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt,
-                        int R, hipStream_t s);
+                        int R, hipStream_t s, ExpoState oe = {}, ExpoState ne = {});
 void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s);
 
 void launch_render_stats(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,

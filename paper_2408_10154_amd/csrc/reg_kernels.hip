@@ -125,7 +125,7 @@ __global__ void k_state_remap(const float* __restrict__ opose, const float* __re
                               const float* __restrict__ ov, const ViewOpt* __restrict__ oopt,
                               float* __restrict__ npose, float* __restrict__ nm, float* __restrict__ nv,
                               float* __restrict__ ngrad, ViewOpt* __restrict__ nopt, const int32_t* __restrict__ map,
-                              const ViewOpt* __restrict__ init_opt, int R) {
+                              const ViewOpt* __restrict__ init_opt, int R, ExpoState oe, ExpoState ne) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= R) return;
   const int o = map[r];
@@ -134,6 +134,14 @@ __global__ void k_state_remap(const float* __restrict__ opose, const float* __re
     nm[7 * r + k] = o >= 0 ? om[7 * o + k] : 0.f;
     nv[7 * r + k] = o >= 0 ? ov[7 * o + k] : 0.f;
     ngrad[7 * r + k] = 0.f;  // the backward accumulates into it; Adam consumes it
+  }
+  if (ne.expo) {  // exposure coefficients (a, b) and their moments; new views start at 0
+    for (int k = 0; k < 2; ++k) {
+      ne.expo[2 * r + k] = o >= 0 ? oe.expo[2 * o + k] : 0.f;
+      ne.m[2 * r + k] = o >= 0 ? oe.m[2 * o + k] : 0.f;
+      ne.v[2 * r + k] = o >= 0 ? oe.v[2 * o + k] : 0.f;
+      ne.grad[2 * r + k] = 0.f;
+    }
   }
   nopt[r] = o >= 0 ? oopt[o] : init_opt[r];
 }
@@ -145,10 +153,10 @@ __global__ void k_all_finite(const float* __restrict__ a, int64_t n, int32_t* __
 
 void launch_state_remap(const float* opose, const float* om, const float* ov, const ViewOpt* oopt, float* npose,
                         float* nm, float* nv, float* ngrad, ViewOpt* nopt, const int32_t* map, const ViewOpt* init_opt,
-                        int R, hipStream_t s) {
+                        int R, hipStream_t s, ExpoState oe, ExpoState ne) {
   if (R > 0)
     hipLaunchKernelGGL(k_state_remap, dim3((R + 127) / 128), dim3(128), 0, s, opose, om, ov, oopt, npose, nm, nv,
-                       ngrad, nopt, map, init_opt, R);
+                       ngrad, nopt, map, init_opt, R, oe, ne);
 }
 
 void launch_all_finite(const float* a, int64_t n, int32_t* bad, hipStream_t s) {

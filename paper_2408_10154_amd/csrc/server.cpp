@@ -68,7 +68,7 @@ struct Slot {
   int iters_done = 0;
   int first_render = -1;  // position of its first view in the current epoch
   float T[12] = {0};
-  std::vector<float> per_view, resid;
+  std::vector<float> per_view, resid, expo;  // expo: (a, b) per view when exposure is on
   Clock::time_point t_submit, t_admit, t_done;
 };
 
@@ -130,7 +130,6 @@ class Server {
   ls_status submit(const ls_pair* pair, const ls_reg_params* prm, uint64_t* ticket) {
     ls_status st = validate_pair(pair, prm);
     if (st) return st;
-    if (prm->exposure) return LS_ERR_INVALID;  // exposure coefficients: ls_register_pair only
     {
       std::lock_guard<std::mutex> g(mu_);
       if (!have_betas_) {
@@ -141,10 +140,13 @@ class Server {
         exit_patience_ = prm->exit_patience;
         loss_kind_ = prm->loss_kind;
         track_ = prm->track;
+        exposure_ = prm->exposure;
+        lr_exposure_ = prm->exposure ? prm->lr_exposure : 0.f;
         have_betas_ = true;
       } else if (prm->beta1 != beta1_ || prm->beta2 != beta2_ || prm->adam_eps != eps_ ||
                  prm->exit_rel_tol != exit_tol_ || prm->exit_patience != exit_patience_ ||
-                 prm->loss_kind != loss_kind_ ||
+                 prm->loss_kind != loss_kind_ || prm->exposure != exposure_ ||
+                 (exposure_ && prm->lr_exposure != lr_exposure_) ||
                  (loss_kind_ == 1 && (prm->track.lambda_c != track_.lambda_c ||
                                       prm->track.inlier_k != track_.inlier_k ||
                                       prm->track.alpha_power != track_.alpha_power))) {
@@ -181,6 +183,7 @@ class Server {
       std::memcpy(out->T_PQ, s->T, sizeof(s->T));
       if (out->per_view_T && !s->per_view.empty()) std::memcpy(out->per_view_T, s->per_view.data(), 4 * s->per_view.size());
       if (out->residual && !s->resid.empty()) std::memcpy(out->residual, s->resid.data(), 4 * s->resid.size());
+      if (out->exposure && !s->expo.empty()) std::memcpy(out->exposure, s->expo.data(), 4 * s->expo.size());
       out->status = s->status;
       out->iters_done = s->iters_done;
     }
@@ -213,7 +216,7 @@ class Server {
     if (batch_) ls_batch_destroy(batch_);
     batch_ = nullptr;
     for (DevBuf* b : {&items_, &pixels_, &tiles_, &bins_, &work_, &stateA_, &stateB_, &snap_, &small_, &stage_,
-                      &check_buf_})
+                      &check_buf_, &epart_})
       b->release();
     if (stream_) hipStreamDestroy(stream_);
     if (check_stream_) hipStreamDestroy(check_stream_);
@@ -331,7 +334,9 @@ class Server {
     hipMemcpyAsync(dmap, map.data(), 4 * (size_t)R_, hipMemcpyHostToDevice, stream_);
     hipMemcpyAsync(dinit, init.data(), sizeof(ViewOpt) * R_, hipMemcpyHostToDevice, stream_);
     StatePtrs a = state_ptrs(stateA_, std::max(Rold, 1)), b = state_ptrs(stateB_, R_);
-    launch_state_remap(a.pose, a.m, a.v, a.opt, b.pose, b.m, b.v, b.grad, b.opt, dmap, dinit, R_, stream_);
+    launch_state_remap(a.pose, a.m, a.v, a.opt, b.pose, b.m, b.v, b.grad, b.opt, dmap, dinit, R_, stream_,
+                       ExpoState{a.expo, a.em, a.ev, a.eg}, ExpoState{b.expo, b.em, b.ev, b.eg});
+    if ((st = epart_.ensure(8 * (size_t)std::max(batch_->nblk_pix, 1)))) return st;
     if (hipStreamSynchronize(stream_) != hipSuccess) return LS_ERR_HIP;  // host map/init must outlive the copies
     std::swap(stateA_, stateB_);
 
@@ -379,9 +384,12 @@ class Server {
   struct StatePtrs {
     float *pose, *m, *v, *grad, *loss, *scale;
     ViewOpt* opt;
+    float *expo, *em, *ev, *eg;  // exposure coefficients (a, b) per view, their moments and gradient
   };
   static size_t align(size_t x) { return (x + 255) & ~size_t(255); }
-  static size_t state_bytes(int R) { return 4 * align(28 * (size_t)R) + 2 * align(4 * (size_t)R) + align(sizeof(ViewOpt) * R); }
+  static size_t state_bytes(int R) {
+    return 4 * align(28 * (size_t)R) + 2 * align(4 * (size_t)R) + align(sizeof(ViewOpt) * R) + 4 * align(8 * (size_t)R);
+  }
   static StatePtrs state_ptrs(const DevBuf& b, int R) {
     StatePtrs s;
     size_t o = 0;
@@ -391,7 +399,11 @@ class Server {
     s.grad = b.as<float>(o); o += align(28 * (size_t)R);
     s.loss = b.as<float>(o); o += align(4 * (size_t)R);
     s.scale = b.as<float>(o); o += align(4 * (size_t)R);
-    s.opt = b.as<ViewOpt>(o);
+    s.opt = b.as<ViewOpt>(o); o += align(sizeof(ViewOpt) * R);
+    s.expo = b.as<float>(o); o += align(8 * (size_t)R);
+    s.em = b.as<float>(o); o += align(8 * (size_t)R);
+    s.ev = b.as<float>(o); o += align(8 * (size_t)R);
+    s.eg = b.as<float>(o);
     return s;
   }
 
@@ -414,6 +426,9 @@ class Server {
 
   // The loss fixed for this server (plain L1 or the masked tracking loss).
   ls_status view_loss(const StatePtrs& s) {
+    if (exposure_)
+      return batch_loss_exposure(batch_, loss_kind_, &track_, &img_, nullptr, nullptr, s.expo, epart_.as<float>(), s.eg,
+                                 s.loss, g_rgb_, g_depth_, s.scale, stream_);
     if (loss_kind_ == 1)
       return batch_loss_tracking(batch_, &img_, &track_, s.loss, g_rgb_, g_depth_, s.scale, stream_);
     return batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_);
@@ -432,8 +447,12 @@ class Server {
         (st = ls_render_bwd_tiles(batch_, s.pose, &proj_, &bins_c_, nullptr, &img_, &up, LS_BWD_POSE_ONLY, stream_)) ||
         (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
       return st;
-    launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
-                     stream_);
+    if (exposure_)
+      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
+                       stream_, s.expo, s.eg, s.em, s.ev, lr_exposure_);
+    else
+      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
+                       stream_);
     return LS_OK;
   }
 
@@ -528,12 +547,15 @@ class Server {
     ls_status st;
     if ((st = ls_project(batch_, s.pose, &proj_, stream_)) || (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)) ||
         (st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_)) ||
-        (st = batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_))) {
+        (st = exposure_ ? batch_loss_exposure(batch_, 0, nullptr, &img_, nullptr, nullptr, s.expo, nullptr, nullptr,
+                                              s.loss, g_rgb_, g_depth_, s.scale, stream_)
+                        : batch_loss_l1(batch_, &img_, s.loss, g_rgb_, g_depth_, s.scale, stream_))) {
       fail_active(st);
       return;
     }
-    std::vector<float> pose_h(7 * (size_t)R_), loss_h(R_);
+    std::vector<float> pose_h(7 * (size_t)R_), loss_h(R_), expo_h(exposure_ ? 2 * (size_t)R_ : 0);
     int32_t hc[4] = {0, 0, 0, 0};
+    if (exposure_) hipMemcpyAsync(expo_h.data(), s.expo, 8 * (size_t)R_, hipMemcpyDeviceToHost, stream_);
     hipMemcpyAsync(pose_h.data(), s.pose, 28 * (size_t)R_, hipMemcpyDeviceToHost, stream_);
     hipMemcpyAsync(loss_h.data(), s.loss, 4 * (size_t)R_, hipMemcpyDeviceToHost, stream_);
     hipMemcpyAsync(hc, count_, 16, hipMemcpyDeviceToHost, stream_);
@@ -561,7 +583,7 @@ class Server {
         keep.push_back(sl);
         continue;
       }
-      finish_slot(sl, pose_h, loss_h);
+      finish_slot(sl, pose_h, loss_h, expo_h);
       active_bytes_ -= sl->bytes;
       active_pixels_ -= sl->pixels;
     }
@@ -570,8 +592,10 @@ class Server {
     cv_.notify_all();
   }
 
-  void finish_slot(Slot* sl, const std::vector<float>& pose_h, const std::vector<float>& loss_h) {
+  void finish_slot(Slot* sl, const std::vector<float>& pose_h, const std::vector<float>& loss_h,
+                   const std::vector<float>& expo_h) {
     const int n = sl->views, r0 = sl->first_render;
+    if (!expo_h.empty()) sl->expo.assign(expo_h.begin() + 2 * (size_t)r0, expo_h.begin() + 2 * (size_t)(r0 + n));
     std::vector<double> est(12 * (size_t)n), res(n);
     std::vector<int32_t> rev(n);
     sl->per_view.assign(12 * (size_t)n, 0.f);
@@ -625,6 +649,9 @@ class Server {
   int32_t exit_patience_ = 0;
   int32_t loss_kind_ = 0;
   ls_loss_params track_{};
+  int32_t exposure_ = 0;  // exposure coefficients on (fixed by the first request, like the loss)
+  float lr_exposure_ = 0.f;
+  DevBuf epart_;           // exposure-gradient block partials of the active set
   std::thread worker_;
   std::mutex mu_;
   std::condition_variable cv_;

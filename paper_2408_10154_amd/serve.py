@@ -33,18 +33,21 @@ class Server:
         pair, keep = make_pair(P, Q, cam, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ)
         t = C.c_uint64()
         L.check(L.load().ls_register_submit(self.h, C.byref(pair), C.byref(params), C.byref(t)))
-        self._keep[t.value] = (keep, P, Q, pair.vP + pair.vQ)
+        self._keep[t.value] = (keep, P, Q, pair.vP + pair.vQ, bool(params.exposure))
         return t.value
 
     def poll(self, ticket: int):
-        """None while running; else dict(T, per_view, residual, status, iters, times)."""
+        """None while running; else dict(T, per_view, residual, status, iters,
+        times, exposure) (exposure: per-view (a, b) when requested, else None)."""
         keep = self._keep.get(ticket)
         nv = keep[3] if keep else 1
         per_view = np.zeros((nv, 12), np.float32)
         resid = np.zeros(nv, np.float32)
+        expo = np.zeros((nv, 2), np.float32)
         res = L.ls_reg_result()
         res.per_view_T = per_view.ctypes.data_as(C.c_void_p)
         res.residual = resid.ctypes.data_as(C.c_void_p)
+        res.exposure = expo.ctypes.data_as(C.c_void_p)
         times = np.zeros(3, np.float64)
         st = L.load().ls_register_poll(self.h, ticket, C.byref(res), times.ctypes.data_as(C.c_void_p))
         if st == L.LS_NOT_READY:
@@ -55,7 +58,8 @@ class Server:
         pv = np.tile(np.eye(4), (nv, 1, 1))
         pv[:, :3, :] = per_view.reshape(nv, 3, 4)
         return dict(T=T, per_view=pv, residual=resid.astype(np.float64), status=int(st), iters=res.iters_done,
-                    times=dict(queue=times[0], run=times[1], total=times[2]))
+                    times=dict(queue=times[0], run=times[1], total=times[2]),
+                    exposure=expo.astype(np.float64) if keep and keep[4] else None)
 
     def wait(self, ticket: int, timeout: float = 600.0, interval: float = 0.002):
         t0 = time.time()

@@ -190,18 +190,36 @@ def test_exposure_compensation_on_the_pair_workload(gpu):
     print("exposure on", (rot, tr), "off", _errs(off["T"], d["T_gt"]))
 
 
-def test_server_refuses_exposure_coefficients(gpu):
-    """Exposure coefficients are an ls_register_pair option: the serving
-    loop refuses such a request instead of ignoring the setting."""
+def test_server_with_exposure_matches_the_plain_path_bitwise(gpu):
+    """Two pairs with exposure coefficients through the serving loop (with
+    graphs, both in one batch) give the same transforms, estimates,
+    residuals and exposure coefficients as ls_register_pair, bit for bit;
+    a request whose exposure setting differs from the server's is refused."""
     from paper_2408_10154_amd import lib as L
     from paper_2408_10154_amd import register as REG
     from paper_2408_10154_amd.render import GaussianSet
     from paper_2408_10154_amd.serve import Server
 
-    d = synth.registration_pair(9, 2000, 2000, views_p=1, views_q=1, width=64, height=48, f=45)
-    P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
-    rgbP, depP, rgbQ, depQ = _exposed_targets(d, 1.0, 0.0)
-    with Server(budget_bytes=1 << 30, max_slots=4) as sv:
+    prm = REG.default_params(48, exposure=True)
+    cases = []
+    for seed in (9, 10):
+        d = synth.registration_pair(seed, 3000, 2500, views_p=2, views_q=3, width=96, height=72, f=70)
+        cases.append((d, _exposed_targets(d, 1.2, 0.03)))
+    plain = [_gpu_register_targets(d, *t, prm) for d, t in cases]
+    with Server(budget_bytes=1 << 32, max_slots=8, chunk_iters=16, use_graphs=True) as sv:
+        tickets = []
+        for d, t in cases:
+            P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
+            tickets.append(sv.submit(P, Q, d["cam"], d["kf_p"], d["kf_q"], *t, params=prm))
+        d, t = cases[0]
+        P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
         with pytest.raises(L.LsError):
-            sv.submit(P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ,
-                      params=REG.default_params(10, exposure=True))
+            sv.submit(P, Q, d["cam"], d["kf_p"], d["kf_q"], *t, params=REG.default_params(48))
+        served = [sv.wait(tk) for tk in tickets]
+    for a, b in zip(served, plain):
+        assert a["status"] == 0 and b["status"] == 0
+        np.testing.assert_array_equal(a["T"], b["T"])
+        np.testing.assert_array_equal(a["per_view"], b["per_view"])
+        np.testing.assert_array_equal(a["residual"], b["residual"])
+        np.testing.assert_array_equal(a["exposure"], b["exposure"])
+        assert np.abs(b["exposure"]).max() > 0.01  # the coefficients moved
