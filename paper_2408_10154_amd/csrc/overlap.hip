@@ -217,29 +217,35 @@ __device__ __forceinline__ float point_box_dist2(float x, float y, float z, cons
 // that lane's current best (scaled by kOvPrune against FP32 rounding), so a
 // skipped point can neither win nor tie.
 __device__ __forceinline__ void ov_scan_leaf(const OvSet& c, int l, int lane, float px, float py, float pz,
-                                             float& best, int& bi) {
+                                             float& best, int& bi, float4* stage) {
+  // the leaf's candidates go through the wave's LDS slot and are read back
+  // with one uniform (broadcast) load each
   const int ci = l * kOvLeaf + lane;
   const bool cv = ci < c.n;
   const float ax = cv ? c.p[ci] : 0.f, ay = cv ? c.p[(int64_t)c.n + ci] : 0.f;
   const float az = cv ? c.p[2 * (int64_t)c.n + ci] : 0.f;
   const int aid = cv ? c.idx[ci] : 0;
+  stage[lane] = make_float4(ax, ay, az, __int_as_float(aid));
+  __builtin_amdgcn_wave_barrier();
   const int cnt = c.n - l * kOvLeaf < kOvLeaf ? c.n - l * kOvLeaf : kOvLeaf;
+#pragma unroll 4
   for (int j = 0; j < cnt; ++j) {
-    const float bx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), j));
-    const float by = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), j));
-    const float bz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), j));
-    const int bid = __builtin_amdgcn_readlane(aid, j);
-    const float d = sq_dist_rn(px, py, pz, bx, by, bz);
+    const float4 b = stage[j];
+    const float d = sq_dist_rn(px, py, pz, b.x, b.y, b.z);
+    const int bid = __float_as_int(b.w);
     const bool take = d < best || (d == best && bid < bi);
     best = take ? d : best;
     bi = take ? bid : bi;
   }
+  __builtin_amdgcn_wave_barrier();  // every lane has read the slot before it is refilled
 }
 
 __global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __restrict__ nn_out) {
+  __shared__ float4 stage_all[kBlock];
   const int leaf = (int)((blockIdx.x * (int64_t)kBlock + threadIdx.x) / kOvLeaf);
   const int lane = threadIdx.x & 63;
-  if (leaf >= q.nleaf) return;  // whole waves
+  float4* stage = stage_all + (threadIdx.x & ~63);  // this wave's slot
+  if (leaf >= q.nleaf) return;  // whole waves; no block-wide barrier follows
   const int qi = leaf * kOvLeaf + lane;
   const bool qv = qi < q.n;
   const float px = qv ? q.p[qi] : 0.f, py = qv ? q.p[(int64_t)q.n + qi] : 0.f;
@@ -255,7 +261,7 @@ __global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __rest
   const int s0 = l0 / kOvSuper;
   float best = INFINITY;
   int bi = 0x7fffffff;
-  ov_scan_leaf(c, l0, lane, px, py, pz, best, bi);
+  ov_scan_leaf(c, l0, lane, px, py, pz, best, bi, stage);
   for (int k = 0; k < 2 * c.nsuper; ++k) {
     const int s = (k & 1) ? s0 + (k + 1) / 2 : s0 - k / 2;
     if (s < 0 || s >= c.nsuper) continue;
@@ -264,7 +270,7 @@ __global__ __launch_bounds__(256) void k_ov_nn(OvSet q, OvSet c, int32_t* __rest
     for (int l = s * kOvSuper; l < l1; ++l) {
       if (l == l0) continue;
       if (!__ballot(qv && point_box_dist2(px, py, pz, c.leaf + 6 * l) * kOvPrune <= best)) continue;
-      ov_scan_leaf(c, l, lane, px, py, pz, best, bi);
+      ov_scan_leaf(c, l, lane, px, py, pz, best, bi, stage);
     }
   }
   if (qv) nn_out[q.idx[qi]] = bi;
