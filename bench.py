@@ -245,7 +245,22 @@ def registration(n_pairs: int, iters: int):
                   iters=iters, seconds=round(res["seconds"], 4),
                   mpix_per_s=round(one[0]["pixels"] * iters / res["seconds"] / 1e6, 2),
                   rot_deg=round(res["rot_deg_median"], 4), trans_cm=round(res["trans_cm_median"], 4))
-    del one, rs
+    # the same pair with Q's keyframes under another exposure (gain 1.15,
+    # offset 0.03), registered with per-view exposure coefficients
+    from paper_2408_10154_amd import register as REG
+
+    p0 = one[0]
+    args = list(p0["args"])
+    args[7] = (1.15 * args[7] + 0.03).contiguous()  # rgbQ
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rx = REG.register_pair(*args, params=REG.default_params(iters, exposure=True))
+    tx = time.perf_counter() - t0
+    single["exposure_changed_q"] = dict(seconds=round(tx, 4), rot_deg=round(REG.rotation_error_deg(rx["T"], p0["T_gt"]), 4),
+                                        trans_cm=round(REG.translation_error_cm(rx["T"], p0["T_gt"]), 4),
+                                        q_exposure_median=[round(float(v), 4) for v in
+                                                           np.median(rx["exposure"][8:], axis=0)])
+    del one, rs, args
     specs = synth.pair_set(3, n_pairs)
     pairs = [RB.build_pair(sp) for sp in specs]
     RB.run_batched(pairs[:2], iters=10)                          # warm-up (server thread, graph path)
