@@ -571,3 +571,56 @@ def test_loss_tracking_matches_oracle(gpu, lambda_c, inlier_k, alpha_power):
     loss2, med2, *_ = b.loss_tracking(dev(tr), dev(td), lambda_c, inlier_k, alpha_power,
                                       pred=(dev(pr), dev(pdp), dev(al)))
     assert torch.equal(loss, loss2) and (inlier_k <= 0 or torch.equal(med, med2))
+
+
+def test_gpu_gradients_match_gpu_finite_differences(gpu):
+    """FP32 sanity check of the backward against the forward alone (no
+    oracle): for L = sum w . image with smooth weights, the derivative of the
+    GPU's own forward along the GPU's pose gradient, and along its gradient
+    with respect to all Gaussian means, by central differences, equals the
+    gradient's norm within 10 %.  Directional checks along the gradient keep
+    the bar meaningful although the alpha-skip contours move inside the step
+    (the backward, like the method, has no gradient through that threshold;
+    per-component differences pick up those jumps at the few-percent level of
+    the largest component)."""
+    sc = synth.scene_small(0, n=800)
+    cam, w2c = sc["cam"], sc["w2c"]
+    b = _batch([(sc["gauss"], cam, w2c)])
+    H, W = cam["height"], cam["width"]
+    yy, xx = np.mgrid[0:H, 0:W]
+    field = 1.0 + 0.5 * np.sin(xx / 23.0) * np.cos(yy / 17.0)
+    w_rgb = torch.as_tensor(np.stack([field, 0.8 * field, 1.2 * field]).astype(np.float32).reshape(-1), device="cuda")
+    w_dep = torch.as_tensor((0.3 * field).astype(np.float32).reshape(-1), device="cuda")
+
+    def loss_at(pose):
+        b.project(pose)
+        b.bin_sort()
+        b.render_fwd()
+        return float((b.rgb.double() * w_rgb.double()).sum() + (b.depth.double() * w_dep.double()).sum())
+
+    pose = torch.as_tensor(sc["target_pose"][None], device="cuda").contiguous()
+    b.project(pose)
+    b.bin_sort()
+    b.render_fwd()
+    grads = [b.gsets[0].zeros_like()]
+    pose_grad = torch.zeros_like(pose)
+    b.render_bwd(up_rgb=w_rgb, up_depth=w_dep, grads=grads, pose=pose, pose_grad=pose_grad)
+    torch.cuda.synchronize()
+    g = pose_grad.double()
+    gn = float(g.norm())
+    d = (g / gn).float()
+    h = 1e-4
+    fd = (loss_at(pose + h * d) - loss_at(pose - h * d)) / (2 * h)
+    assert abs(fd - gn) <= 0.1 * gn, (fd, gn)
+    gm = grads[0].mean.double()
+    gmn = float(gm.norm())
+    dm = (gm / gmn).float()
+    base = b.gsets[0].mean.clone()
+    h = 1e-4
+    b.gsets[0].mean.copy_(base + h * dm)
+    lp = loss_at(pose)
+    b.gsets[0].mean.copy_(base - h * dm)
+    lm = loss_at(pose)
+    b.gsets[0].mean.copy_(base)
+    fd = (lp - lm) / (2 * h)
+    assert abs(fd - gmn) <= 0.1 * gmn, (fd, gmn)
