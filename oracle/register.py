@@ -16,6 +16,13 @@ Readings (the paper leaves these open):
   R21 weight 1 / max(eps_i, 1e-12)
   R22 translation: weighted mean of the P->Q translations, the Q->P
       estimates inverted first
+  R33 joint registration (optional comparison, not the paper's estimator):
+      one T = T_{P->Q} (unnormalised quaternion and translation, starting
+      at identity) shared by all views.  View i's camera-frame correction is
+      Delta_i = C_i^-1 T^-1 C_i for a keyframe of P and C_i^-1 T C_i for one
+      of Q (C_i its camera-to-world pose), the objective is the sum of the
+      views' losses and T takes the Adam steps (lr_rot for q, lr_trans for
+      t); the estimate is T itself, with no Eq. 7 fusion.
   R23 exposure coefficients (supplement, 3DGS registration; optional): per
       view an affine brightness map of the rendered colour,
       C' = exp(a) C + b with scalars a, b shared by the three channels,
@@ -183,6 +190,76 @@ def register_pair(P: dict, Q: dict, views_p, views_q, cam: raster.Camera, iters:
             res.append(r)
             rev.append(reverse)
     return fuse(ests, res, rev), ests, res
+
+
+def _quat_mul(a, b):
+    """Hamilton product of (w, x, y, z) quaternions (torch, differentiable)."""
+    w1, x1, y1, z1 = a
+    w2, x2, y2, z2 = b
+    return torch.stack([w1 * w2 - x1 * x2 - y1 * y2 - z1 * z2, w1 * x2 + x1 * w2 + y1 * z2 - z1 * y2,
+                        w1 * y2 - x1 * z2 + y1 * w2 + z1 * x2, w1 * z2 + x1 * y2 - y1 * x2 + z1 * w2])
+
+
+def _quat_of(rot: np.ndarray) -> torch.Tensor:
+    from scipy.spatial.transform import Rotation
+
+    q = Rotation.from_matrix(np.asarray(rot, np.float64)).as_quat()  # x, y, z, w
+    return torch.as_tensor([q[3], q[0], q[1], q[2]], dtype=F64)
+
+
+def joint_delta(T7: torch.Tensor, c2w: np.ndarray, reverse: bool) -> torch.Tensor:
+    """Delta_i of R33 as a pose 7-vector, differentiable in T7."""
+    T7 = T7.to(F64)
+    q = T7[:4] / torch.linalg.norm(T7[:4])
+    t = T7[4:7]
+    conj = torch.tensor([1.0, -1.0, -1.0, -1.0], dtype=F64)
+    qc = _quat_of(np.asarray(c2w)[:3, :3])
+    Rc = torch.as_tensor(np.asarray(c2w, np.float64)[:3, :3])
+    tc = torch.as_tensor(np.asarray(c2w, np.float64)[:3, 3])
+    Rt = raster.quat_to_rotmat(q)
+    if reverse:  # keyframe of Q: Delta = C^-1 T C
+        qd = _quat_mul(_quat_mul(qc * conj, q), qc)
+        td = Rc.T @ (Rt @ tc + t - tc)
+    else:  # keyframe of P: Delta = C^-1 T^-1 C
+        qd = _quat_mul(_quat_mul(qc * conj, q * conj), qc)
+        td = Rc.T @ (Rt.T @ (tc - t) - tc)
+    return torch.cat([qd, td])
+
+
+def register_pair_joint(P: dict, Q: dict, views_p, views_q, cam: raster.Camera, iters: int, lr_rot: float,
+                        lr_trans: float, loss=None, beta1=0.9, beta2=0.999, eps=1e-8):
+    """R33: one shared T_{P->Q} optimised over every view's loss.  Returns
+    (T 4x4, residuals of the views at the final T)."""
+    T7 = torch.tensor([1.0, 0, 0, 0, 0, 0, 0], dtype=F64, requires_grad=True)
+    m, v = torch.zeros(7, dtype=F64), torch.zeros(7, dtype=F64)
+    views = [(c2w, rgb, dep, other, rev) for vs, other, rev in ((views_p, Q, False), (views_q, P, True))
+             for c2w, rgb, dep in vs]
+    prepared = []
+    for c2w, rgb, dep, other, rev in views:
+        w2c = torch.as_tensor(inv_rigid(np.asarray(c2w, np.float64))[:3, :])
+        prepared.append((c2w, w2c, torch.as_tensor(np.asarray(rgb, np.float64)),
+                         torch.as_tensor(np.asarray(dep, np.float64)), {k: x.detach() for k, x in other.items()}, rev))
+    for it in range(1, iters + 1):
+        total = None
+        for c2w, w2c, rgb, dep, other, rev in prepared:
+            out = raster.render(other, cam, w2c, joint_delta(T7, c2w, rev), with_margins=False)
+            val = view_loss(out, rgb, dep, loss)
+            total = val if total is None else total + val
+        (g,) = torch.autograd.grad(total, [T7], allow_unused=True) if total.requires_grad else (None,)
+        g = torch.zeros(7, dtype=F64) if g is None else g
+        with torch.no_grad():
+            m[:4] = beta1 * m[:4] + (1 - beta1) * g[:4]
+            m[4:] = beta1 * m[4:] + (1 - beta1) * g[4:]
+            v.mul_(beta2).add_((1 - beta2) * g * g)
+            mh, vh = m / (1 - beta1 ** it), v / (1 - beta2 ** it)
+            lr = torch.tensor([lr_rot] * 4 + [lr_trans] * 3, dtype=F64)
+            T7.sub_(lr * mh / (torch.sqrt(vh) + eps))
+    res = []
+    with torch.no_grad():
+        for c2w, w2c, rgb, dep, other, rev in prepared:
+            out = raster.render(other, cam, w2c, joint_delta(T7, c2w, rev), with_margins=False)
+            res.append(float(raster.loss_l1(out["rgb"], out["depth"], rgb, dep)))
+    return pose_matrix(T7.detach().numpy()), res
 
 
 def rotation_error_deg(r: np.ndarray, r_gt: np.ndarray) -> float:
