@@ -260,6 +260,14 @@ def registration(n_pairs: int, iters: int):
                                         trans_cm=round(REG.translation_error_cm(rx["T"], p0["T_gt"]), 4),
                                         q_exposure_median=[round(float(v), 4) for v in
                                                            np.median(rx["exposure"][8:], axis=0)])
+    # the same pair with one transform shared by all views (a comparison to
+    # the per-view estimates and their fusion)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    rj = REG.register_pair(*p0["args"], params=REG.default_params(iters, joint=True))
+    tj = time.perf_counter() - t0
+    single["joint_transform"] = dict(seconds=round(tj, 4), rot_deg=round(REG.rotation_error_deg(rj["T"], p0["T_gt"]), 4),
+                                     trans_cm=round(REG.translation_error_cm(rj["T"], p0["T_gt"]), 4))
     del one, rs, args
     specs = synth.pair_set(3, n_pairs)
     pairs = [RB.build_pair(sp) for sp in specs]

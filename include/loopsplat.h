@@ -448,6 +448,10 @@ typedef struct {
                                scalars a, b per view starting at 0 and taking the pose's Adam step;
                                0: off.  A server fixes it (and lr_exposure) with its first request */
   float lr_exposure;        /* their learning rate (0.1 in the supplement) */
+  int32_t joint;            /* 1: one T_{P->Q} shared by all views, each view's correction derived from
+                               it, Adam on T (lr_rot, lr_trans) over the sum of the views' losses; T is
+                               the estimate (no Eq. 7 fusion).  A comparison to the paper's per-view
+                               estimates; ls_register_pair only, without exposure or early exit */
 } ls_reg_params;
 
 typedef struct {

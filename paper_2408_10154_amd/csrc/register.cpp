@@ -44,6 +44,60 @@ void rigid_mul(const double* A, const double* B, double* out) {
   std::memcpy(out, o, sizeof(o));
 }
 
+static void quat_mul(const double* a, const double* b, double* o) {
+  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// Unit quaternion of a rotation (row-major), largest-diagonal branch.
+static void quat_of_rot(const double* R, double* q) {
+  const double tr = R[0] + R[4] + R[8];
+  if (tr > 0.0) {
+    const double S = std::sqrt(tr + 1.0) * 2.0;
+    q[0] = 0.25 * S; q[1] = (R[7] - R[5]) / S; q[2] = (R[2] - R[6]) / S; q[3] = (R[3] - R[1]) / S;
+  } else if (R[0] > R[4] && R[0] > R[8]) {
+    const double S = std::sqrt(1.0 + R[0] - R[4] - R[8]) * 2.0;
+    q[0] = (R[7] - R[5]) / S; q[1] = 0.25 * S; q[2] = (R[1] + R[3]) / S; q[3] = (R[2] + R[6]) / S;
+  } else if (R[4] > R[8]) {
+    const double S = std::sqrt(1.0 + R[4] - R[0] - R[8]) * 2.0;
+    q[0] = (R[2] - R[6]) / S; q[1] = (R[1] + R[3]) / S; q[2] = 0.25 * S; q[3] = (R[5] + R[7]) / S;
+  } else {
+    const double S = std::sqrt(1.0 + R[8] - R[0] - R[4]) * 2.0;
+    q[0] = (R[3] - R[1]) / S; q[1] = (R[2] + R[6]) / S; q[2] = (R[5] + R[7]) / S; q[3] = 0.25 * S;
+  }
+  const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
+  for (int k = 0; k < 4; ++k) q[k] /= n;
+}
+
+// Joint registration: the camera-frame correction of a view implied by one
+// shared T = T_{P->Q} (7 values, unnormalised quaternion and translation):
+// Delta = C^-1 T^-1 C for a keyframe of P, C^-1 T C for one of Q.
+void joint_delta(const double* T7, const double* c2w, bool reverse, double* d7) {
+  const double n = std::sqrt(T7[0] * T7[0] + T7[1] * T7[1] + T7[2] * T7[2] + T7[3] * T7[3]);
+  const double q[4] = {T7[0] / n, T7[1] / n, T7[2] / n, T7[3] / n};
+  const double qi[4] = {q[0], -q[1], -q[2], -q[3]};
+  double Rc[9], qc[4], Rt[9];
+  for (int i = 0; i < 3; ++i)
+    for (int j = 0; j < 3; ++j) Rc[i * 3 + j] = c2w[i * 4 + j];
+  quat_of_rot(Rc, qc);
+  const double qci[4] = {qc[0], -qc[1], -qc[2], -qc[3]};
+  rot_of_quat(q, Rt);
+  const double tc[3] = {c2w[3], c2w[7], c2w[11]};
+  double tmp[4], v[3];
+  quat_mul(qci, reverse ? q : qi, tmp);
+  quat_mul(tmp, qc, d7);
+  for (int i = 0; i < 3; ++i) {
+    if (reverse)  // Rt tc + t - tc
+      v[i] = Rt[i * 3 + 0] * tc[0] + Rt[i * 3 + 1] * tc[1] + Rt[i * 3 + 2] * tc[2] + T7[4 + i] - tc[i];
+    else  // Rt^T (tc - t) - tc
+      v[i] = Rt[0 * 3 + i] * (tc[0] - T7[4]) + Rt[1 * 3 + i] * (tc[1] - T7[5]) + Rt[2 * 3 + i] * (tc[2] - T7[6]) -
+             tc[i];
+  }
+  for (int i = 0; i < 3; ++i) d7[4 + i] = Rc[0 * 3 + i] * v[0] + Rc[1 * 3 + i] * v[1] + Rc[2 * 3 + i] * v[2];
+}
+
 // E = C Delta^-1 C^-1 for a keyframe c2w C and its optimised correction Delta.
 void view_estimate(const double* c2w, const float* pose7, double* E) {
   const double q[4] = {pose7[0], pose7[1], pose7[2], pose7[3]};
@@ -250,6 +304,11 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   if (hipMemcpyAsync(opt, ho.data(), sizeof(ViewOpt) * R, hipMemcpyHostToDevice, s) != hipSuccess) return LS_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return LS_ERR_HIP;
   launch_pose_init(pose, adam_m, adam_v, opt, R, s);
+  joint_T.assign(7 * pairs.size(), 0.0);
+  for (size_t p = 0; p < pairs.size(); ++p) joint_T[7 * p] = 1.0;
+  joint_m.assign(7 * pairs.size(), 0.0);
+  joint_v.assign(7 * pairs.size(), 0.0);
+  joint_step = 0;
   return hip_ok();
 }
 
@@ -303,6 +362,70 @@ ls_status RegEngine::step(hipStream_t s) {
   const ls_reg_params& pm = pairs[0].prm;
   launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, loss, R, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
                    pm.exit_patience, s, expo, expo_grad, expo_m, expo_v, pm.lr_exposure);
+  return hip_ok();
+}
+
+// Joint registration: uploads every view's correction implied by its pair's
+// shared T.
+ls_status RegEngine::upload_joint_poses(hipStream_t s) {
+  joint_pose_h.assign(7 * (size_t)R, 0.f);
+  for (int r = 0; r < R; ++r) {
+    double d[7];
+    joint_delta(&joint_T[7 * (size_t)views[r].pair], views[r].c2w, views[r].reverse, d);
+    for (int k = 0; k < 7; ++k) joint_pose_h[7 * (size_t)r + k] = (float)d[k];
+  }
+  return hipMemcpyAsync(pose, joint_pose_h.data(), 28 * (size_t)R, hipMemcpyHostToDevice, s) == hipSuccess
+             ? LS_OK
+             : LS_ERR_HIP;
+}
+
+// One joint iteration: the views' pose gradients from the pose-only
+// backward, chained to each pair's T through the Jacobian of the map
+// T -> Delta (central differences of that smooth map in double precision),
+// summed over the pair's views, then an Adam step on T on the host.
+ls_status RegEngine::step_joint(hipStream_t s) {
+  ls_status st;
+  if ((st = upload_joint_poses(s))) return st;
+  const ls_image_grad up{g_rgb, g_depth, nullptr, scale};
+  if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
+  launch_or_flag(count, sticky, s);
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) || (st = view_loss(s)) ||
+      (st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
+      (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
+    return st;
+  std::vector<float> gh(7 * (size_t)R);
+  if (hipMemcpyAsync(gh.data(), pose_grad, 28 * (size_t)R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemsetAsync(pose_grad, 0, 28 * (size_t)R, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return LS_ERR_HIP;
+  ++joint_step;
+  const ls_reg_params& pm = pairs[0].prm;
+  const double bc1 = 1.0 / (1.0 - std::pow((double)pm.beta1, joint_step));
+  const double bc2 = 1.0 / (1.0 - std::pow((double)pm.beta2, joint_step));
+  for (size_t p = 0; p < pairs.size(); ++p) {
+    double* T = &joint_T[7 * p];
+    double g[7] = {0, 0, 0, 0, 0, 0, 0};
+    for (int r = first_view[p]; r < first_view[p + 1]; ++r) {
+      for (int k = 0; k < 7; ++k) {
+        constexpr double h = 1e-7;
+        double Tp[7], Tm[7], dp[7], dm[7];
+        std::memcpy(Tp, T, sizeof(Tp));
+        std::memcpy(Tm, T, sizeof(Tm));
+        Tp[k] += h;
+        Tm[k] -= h;
+        joint_delta(Tp, views[r].c2w, views[r].reverse, dp);
+        joint_delta(Tm, views[r].c2w, views[r].reverse, dm);
+        for (int i = 0; i < 7; ++i) g[k] += (dp[i] - dm[i]) / (2 * h) * gh[7 * (size_t)r + i];
+      }
+    }
+    for (int k = 0; k < 7; ++k) {
+      double& m = joint_m[7 * p + k];
+      double& v = joint_v[7 * p + k];
+      m = pm.beta1 * m + (1.0 - pm.beta1) * g[k];
+      v = pm.beta2 * v + (1.0 - pm.beta2) * g[k] * g[k];
+      const double lr = k < 4 ? pm.lr_rot : pm.lr_trans;
+      T[k] -= lr * (m * bc1) / (std::sqrt(v * bc2) + pm.adam_eps);
+    }
+  }
   return hip_ok();
 }
 
@@ -394,7 +517,8 @@ ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
   if (prm->iters < 1 || !(prm->lr_rot >= 0) || !(prm->lr_trans >= 0) || !(prm->beta1 >= 0 && prm->beta1 < 1) ||
       !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0) || !(prm->exit_rel_tol >= 0) ||
       prm->exit_patience < 0 || prm->loss_kind < 0 || prm->loss_kind > 1 || prm->exposure < 0 ||
-      prm->exposure > 1 || (prm->exposure && !(prm->lr_exposure >= 0.f && std::isfinite(prm->lr_exposure))))
+      prm->exposure > 1 || (prm->exposure && !(prm->lr_exposure >= 0.f && std::isfinite(prm->lr_exposure))) ||
+      prm->joint < 0 || prm->joint > 1 || (prm->joint && (prm->exposure || prm->exit_patience > 0)))
     return LS_ERR_INVALID;
   if (prm->loss_kind == 1 && (!(prm->track.lambda_c >= 0.f && prm->track.lambda_c <= 1.f) ||
                               !std::isfinite(prm->track.inlier_k) || prm->track.alpha_power < 0 ||
@@ -445,6 +569,17 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg
     }
     int done = 0;
     constexpr int kCheckEvery = 16;  // early exit: poll the views' active flags this often
+    if (prm->joint) {
+      for (; done < prm->iters; ++done)
+        if ((st = e.step_joint(s))) {
+          out->status = st;
+          return st;
+        }
+      if ((st = e.upload_joint_poses(s))) {  // the final forward sees the final T
+        out->status = st;
+        return st;
+      }
+    }
     while (done < prm->iters) {
       const int k = prm->exit_patience > 0 ? std::min(kCheckEvery, prm->iters - done) : prm->iters - done;
       for (int it = 0; it < k; ++it)
@@ -477,7 +612,20 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg
     }
     st = e.fuse_pair(0, ph, lh, out);
     if (!st) st = e.read_exposure(0, out, s);
+    if (!st && prm->joint) {  // the shared T is the estimate (no fusion)
+      double T[12], Rm[9];
+      rot_of_quat(&e.joint_T[0], Rm);
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) T[i * 4 + j] = Rm[i * 3 + j];
+        T[i * 4 + 3] = e.joint_T[4 + i];
+      }
+      for (int q = 0; q < 12; ++q) out->T_PQ[q] = (float)T[q];
+    }
     out->status = st;
+    if (prm->joint) {
+      out->iters_done = e.joint_step;
+      return st;
+    }
     std::vector<ViewOpt> ho(e.R);
     hipMemcpy(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost);
     int steps = 0;

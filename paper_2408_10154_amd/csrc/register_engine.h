@@ -34,6 +34,12 @@ class RegEngine {
   ls_status readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow, hipStream_t s);
   ls_status fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h, ls_reg_result* out);
   ls_status read_exposure(int p, ls_reg_result* out, hipStream_t s);
+  // joint registration (one T per pair, optimised on the host)
+  ls_status step_joint(hipStream_t s);
+  ls_status upload_joint_poses(hipStream_t s);
+  std::vector<double> joint_T, joint_m, joint_v;  // [pairs][7]
+  std::vector<float> joint_pose_h;               // staging of the uploaded corrections
+  int joint_step = 0;
   void release();
 
   std::vector<RegPair> pairs;
@@ -65,6 +71,7 @@ void rot_of_quat(const double* q, double* R);
 void rigid_inv(const double* A, double* out);
 void rigid_mul(const double* A, const double* B, double* out);
 void view_estimate(const double* c2w, const float* pose7, double* E);
+void joint_delta(const double* T7, const double* c2w, bool reverse, double* d7);
 int fuse_estimates(const double* est, const double* resid, const int32_t* rev, int n, double* out);
 ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm);
 RegPair make_reg_pair(const ls_pair* p, const ls_reg_params* prm);

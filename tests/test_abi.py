@@ -129,3 +129,7 @@ def test_register_pair_rejects_bad_loss_parameters_before_touching_a_device():
     for expo, lr in ((2, 0.1), (-1, 0.1), (1, -0.1), (1, float("inf"))):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, 0, 1, good, expo, lr)
         assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+    # joint registration: flag out of range, or combined with exposure or early exit
+    for expo, joint, patience in ((0, 2, 0), (1, 1, 0), (0, 1, 5)):
+        prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, patience, 1, good, expo, 0.1, joint)
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
