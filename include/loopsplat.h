@@ -14,7 +14,12 @@
  *     the frame of the previous camera (supplement, frame-to-model tracking);
  *   - registration localises every keyframe of one submap in the other and
  *     fuses the per-view estimates by weighted rotation averaging (Sec. 3.2,
- *     Eq. 7).
+ *     Eq. 7), optionally with per-view exposure coefficients (supplement);
+ *   - the submap-update loss mixes L1 and SSIM for colour, L1 for depth and an
+ *     isotropic scale regulariser (Sec. 3.1, Eq. 3-5);
+ *   - after pose-graph optimisation submaps and keyframes are moved by their
+ *     corrections (Sec. 3.3, Eq. 8); loop candidates are filtered by the
+ *     geometric overlap ratio of two submaps (supplement, Eq. 9).
  *
  * Conventions shared by every call
  *   - Every call returns an ls_status.  Negative values are errors; the detail
@@ -381,8 +386,10 @@ ls_status ls_adjust_submaps(const ls_submap_adjust* subs, int32_t count, hipStre
  *   counts          device int32 [2] (written): {|K|, pairs closer than tau};
  *                   OR = counts[1] / counts[0] (0 when |K| = 0)
  *   work            device scratch of ls_overlap_workspace_size(np, nq) bytes
- * Errors: LS_ERR_INVALID (sizes, NULL arrays, non-finite T, tau not > 0),
- * LS_ERR_CAPACITY (work_bytes too small). */
+ * The means must be finite (they are not checked; a non-finite coordinate
+ * gives unspecified matches).  ls_overlap_workspace_size returns 0 for
+ * negative counts.  Errors: LS_ERR_INVALID (sizes, NULL arrays, non-finite T,
+ * tau not > 0), LS_ERR_CAPACITY (work_bytes too small). */
 size_t ls_overlap_workspace_size(int32_t np, int32_t nq);
 ls_status ls_overlap_ratio(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
                            float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, size_t work_bytes,
