@@ -302,6 +302,50 @@ def test_adam_matches_oracle(gpu):
         np.testing.assert_allclose(d[0].cpu().numpy(), rf[0].numpy(), rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("frac", [0.0, 0.37, 1.0])
+def test_bin_sort_overflow_stays_within_capacity(gpu, frac):
+    """Capacity below the instance count I (and 0, and exactly I): count is
+    {min(I, capacity), I > capacity, I, 0}, nothing is written past the
+    capacity in the instance arrays or past the workspace, and a re-run at
+    capacity count[2] gives the lists of an ample capacity bit for bit."""
+    from paper_2408_10154_amd import lib as L
+
+    jobs, poses = _three_scenes()
+    pose = torch.as_tensor(np.stack(poses), device="cuda")
+    ref = _batch(jobs)
+    ref.project(pose)
+    ref.bin_sort()
+    n = ref.instances()
+    assert n > 1000 and int(ref.count[1].item()) == 0
+    b = _batch(jobs, capacity=max(n, 1))
+    b.auto_grow = False
+    b.project(pose)
+    cap, guard = int(n * frac), 4096
+    tile_of = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+    item = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+    wbytes = int(L.ls_batch_query(b.h, cap).workspace_bytes)
+    work = torch.zeros(wbytes + 256 + guard, dtype=torch.uint8, device="cuda")
+    wp = (work.data_ptr() + 255) // 256 * 256
+    tail = wp - work.data_ptr() + wbytes
+    work[tail:] = 0xA5
+    bins = L.ls_bins(cap, tile_of.data_ptr(), item.data_ptr(), b.range.data_ptr(), b.count.data_ptr(), wp)
+    L.ls_bin_sort(b.h, b.proj, bins, L.C.c_void_p(torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert b.count.cpu().tolist() == [min(n, cap), int(n > cap), n, 0]
+    assert bool((tile_of[cap:] == -7).all()) and bool((item[cap:] == -7).all())
+    assert bool((work[tail:] == 0xA5).all())
+    if cap == n:
+        np.testing.assert_array_equal(tile_of[:n].cpu().numpy(), ref.tile_of[:n].cpu().numpy())
+        np.testing.assert_array_equal(item[:n].cpu().numpy(), ref.item[:n].cpu().numpy())
+        return
+    b._alloc_bins(int(b.count[2].item()))
+    b.bin_sort()
+    assert int(b.count[1].item()) == 0 and b.instances() == n
+    np.testing.assert_array_equal(b.tile_of[:n].cpu().numpy(), ref.tile_of[:n].cpu().numpy())
+    np.testing.assert_array_equal(b.item[:n].cpu().numpy(), ref.item[:n].cpu().numpy())
+    np.testing.assert_array_equal(b.range.cpu().numpy(), ref.range.cpu().numpy())
+
+
 def test_empty_and_fully_culled_renders(gpu):
     s = synth.scene_small(0, n=500)
     behind = {k: v.copy() for k, v in s["gauss"].items()}
