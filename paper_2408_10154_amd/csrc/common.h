@@ -20,9 +20,7 @@ constexpr int kTileDigitBits = 8;   // tile keys: ceil(bits / 8) passes
 constexpr int kMaxSortBins = 1 << (kDepthDigitBits > kTileDigitBits ? kDepthDigitBits : kTileDigitBits);
 constexpr int kSortItems = 16;      // most items per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
-// Blocks a sort pass aims for (fills the chip); 256, 512 and 2048 measured
-// 1-2 % slower on the render loop.
-constexpr int64_t kSortBlocksTarget = 1024;
+constexpr int64_t kSortBlocksTarget = 1024;  // blocks a sort pass aims for (fills the chip)
 
 // Rounds of kSortThreads items per sort block for n keys: as few as keep
 // about kSortBlocksTarget blocks busy, between 2 and kSortItems (one round
