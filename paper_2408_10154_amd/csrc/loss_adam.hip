@@ -159,14 +159,22 @@ __global__ __launch_bounds__(256) void k_err_hist(const JobDev* __restrict__ job
   const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * kLossBlockPix;
   const int shift = sel_shift(pass), nb = sel_bins(pass);
   const uint32_t prefix = pass ? state[r].prefix : 0u, mask = pass ? state[r].mask : 0u;
-  for (int i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
-  __syncthreads();
+  // every pixel of the thread is loaded before any is counted (one wait for
+  // memory, overlapping the histogram clear)
+  float td[kLossPix], pd[kLossPix];
+#pragma unroll
   for (int k = 0; k < kLossPix; ++k) {
     const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
-    if (p >= hw) break;
-    const float td = tgt_depth ? tgt_depth[J.pix_off + p] : J.tgt_depth[p];
-    if (!(td > 0.f)) continue;
-    const uint32_t bits = __float_as_uint(depth_error(pred_depth[J.pix_off + p], td));
+    const bool in = p < hw;
+    td[k] = in ? (tgt_depth ? tgt_depth[J.pix_off + p] : J.tgt_depth[p]) : 0.f;
+    pd[k] = in ? pred_depth[J.pix_off + p] : 0.f;
+  }
+  for (int i = threadIdx.x; i < nb; i += 256) h[i] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kLossPix; ++k) {
+    if (!(td[k] > 0.f)) continue;  // out-of-image pixels carry td = 0
+    const uint32_t bits = __float_as_uint(depth_error(pd[k], td[k]));
     if ((bits & mask) == prefix) atomicAdd(&h[(bits >> shift) & (uint32_t)(nb - 1)], 1u);
   }
   __syncthreads();
