@@ -37,6 +37,40 @@ __device__ __forceinline__ void exposure_partials(float sa, float sb, float* epa
   }
 }
 
+// One pixel's inputs to the loss kernels.
+struct PixIn {
+  float td, pd, al, pc[3], tc[3];
+};
+
+// Loads every pixel of the thread (kLossPix, 256 apart) before any is used,
+// so the thread waits for memory once; pixels past the image read as zero.
+// Targets come batch-laid-out (tgt_* non-null) or per render from the job.
+__device__ __forceinline__ void load_pixels(const JobDev& J, int64_t hw, int64_t b0, const float* __restrict__ pred_rgb,
+                                            const float* __restrict__ pred_depth,
+                                            const float* __restrict__ pred_alpha,
+                                            const float* __restrict__ tgt_rgb,
+                                            const float* __restrict__ tgt_depth, PixIn (&in)[kLossPix]) {
+#pragma unroll
+  for (int k = 0; k < kLossPix; ++k) {
+    const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
+    PixIn v{0.f, 0.f, 0.f, {0.f, 0.f, 0.f}, {0.f, 0.f, 0.f}};
+    if (p < hw) {
+      const int64_t pi = J.pix_off + p;
+      const int64_t ci = 3 * J.pix_off + p;
+      const float* trgb = tgt_rgb ? tgt_rgb + ci : J.tgt_rgb + p;
+      v.td = tgt_depth ? tgt_depth[pi] : J.tgt_depth[p];
+      v.pd = pred_depth[pi];
+      if (pred_alpha) v.al = pred_alpha[pi];
+#pragma unroll
+      for (int ch = 0; ch < 3; ++ch) {
+        v.pc[ch] = pred_rgb[ci + ch * hw];
+        v.tc[ch] = trgb[ch * hw];
+      }
+    }
+    in[k] = v;
+  }
+}
+
 // Per block of 1024 pixels (blocks never straddle renders): writes sign
 // gradients on valid pixels and the block's (sum |residual|, valid count);
 // with exposure coefficients the colour residual is taken on exp(a) C + b,
@@ -55,21 +89,24 @@ __global__ __launch_bounds__(256) void k_loss_l1(const JobDev* __restrict__ jobs
   const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * kLossBlockPix;
   const Exposure ex = exposure_of(expo, r);
   float s = 0.f, cnt = 0.f, sa = 0.f, sb = 0.f;
+  PixIn in[kLossPix];
+  load_pixels(J, hw, b0, pred_rgb, pred_depth, nullptr, tgt_rgb, tgt_depth, in);
+#pragma unroll
   for (int k = 0; k < kLossPix; ++k) {
     const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
-    if (p >= hw) break;
+    if (p >= hw) continue;
     const int64_t pi = J.pix_off + p;
     const int64_t ci = 3 * J.pix_off + p;
-    const float* trgb = tgt_rgb ? tgt_rgb + ci : J.tgt_rgb + p;  // per-render targets when not batch-laid-out
-    const float td = tgt_depth ? tgt_depth[pi] : J.tgt_depth[p];
+    const float td = in[k].td;
     const bool valid = td > 0.f;
     float l = 0.f;
-    const float dd = pred_depth[pi] - td;
+    const float dd = in[k].pd - td;
     l += fabsf(dd);
     if (g_depth) g_depth[pi] = valid ? (dd > 0.f ? 1.f : (dd < 0.f ? -1.f : 0.f)) : 0.f;
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      const float pc = pred_rgb[ci + ch * hw];
-      const float dc = (ex.on ? ex.gain * pc + ex.offset : pc) - trgb[ch * hw];
+      const float pc = in[k].pc[ch];
+      const float dc = (ex.on ? ex.gain * pc + ex.offset : pc) - in[k].tc[ch];
       l += fabsf(dc);
       const float sg = dc > 0.f ? 1.f : (dc < 0.f ? -1.f : 0.f);
       if (g_rgb) g_rgb[ci + ch * hw] = valid ? (ex.on ? ex.gain * sg : sg) : 0.f;
@@ -265,28 +302,31 @@ __global__ __launch_bounds__(256) void k_loss_track(const JobDev* __restrict__ j
   const float thr = inlier_k > 0.f ? inlier_k * median[r] : 0.f;
   const Exposure ex = exposure_of(expo, r);
   float s = 0.f, cnt = 0.f, sa = 0.f, sb = 0.f;
+  PixIn in[kLossPix];
+  load_pixels(J, hw, b0, pred_rgb, pred_depth, alpha_power > 0 ? pred_alpha : nullptr, tgt_rgb, tgt_depth, in);
+#pragma unroll
   for (int k = 0; k < kLossPix; ++k) {
     const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
-    if (p >= hw) break;
+    if (p >= hw) continue;
     const int64_t pi = J.pix_off + p;
     const int64_t ci = 3 * J.pix_off + p;
-    const float* trgb = tgt_rgb ? tgt_rgb + ci : J.tgt_rgb + p;
-    const float td = tgt_depth ? tgt_depth[pi] : J.tgt_depth[p];
+    const float td = in[k].td;
     const bool valid = td > 0.f;
-    const float dd = pred_depth[pi] - td;
+    const float dd = in[k].pd - td;
     float w = 0.f;
-    if (valid && (inlier_k <= 0.f || depth_error(pred_depth[pi], td) <= thr)) {
+    if (valid && (inlier_k <= 0.f || depth_error(in[k].pd, td) <= thr)) {
       w = 1.f;
       if (alpha_power > 0) {
-        const float a = pred_alpha[pi];
+        const float a = in[k].al;
         for (int e = 0; e < alpha_power; ++e) w *= a;
       }
     }
     const float wc = w * lambda_c, wd = w * (1.f - lambda_c);
     float lc = 0.f;
+#pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-      const float pc = pred_rgb[ci + ch * hw];
-      const float dc = (ex.on ? ex.gain * pc + ex.offset : pc) - trgb[ch * hw];
+      const float pc = in[k].pc[ch];
+      const float dc = (ex.on ? ex.gain * pc + ex.offset : pc) - in[k].tc[ch];
       lc += fabsf(dc);
       const float gc = dc > 0.f ? wc : (dc < 0.f ? -wc : 0.f);
       if (g_rgb) g_rgb[ci + ch * hw] = ex.on ? ex.gain * gc : gc;
