@@ -256,7 +256,7 @@ def bin_sort(u32, v32, z32, radius, cam: Camera):
 
 
 def composite(u, v, conic, opacity, rgb, depth, gid, ranges, cam: Camera, bg=None, with_margins=True,
-              tiles_subset=None):
+              tiles_subset=None, with_decisions=False):
     """Front-to-back alpha compositing over each tile's ordered list (R7, R12-R14).
 
     u, v, depth [N], conic [N,3], opacity [N], rgb [N,3]: float64 tensors
@@ -272,6 +272,11 @@ def composite(u, v, conic, opacity, rgb, depth, gid, ranges, cam: Camera, bg=Non
 
     `tiles_subset` restricts the work to the listed tile indices (other pixels
     are left at their background values); used for sampled checks at size.
+
+    `with_decisions` adds "decisions": every discrete choice of the loop (per
+    tile, per pixel and list entry: skipped, clamped at ALPHA_MAX, composited)
+    packed into one byte string, so that two renders can be checked for the
+    same decisions (finite differences must not straddle a threshold).
     """
     if bg is None:
         bg = torch.zeros(3, dtype=F64)
@@ -284,6 +289,7 @@ def composite(u, v, conic, opacity, rgb, depth, gid, ranges, cam: Camera, bg=Non
     img_d = torch.zeros(H, W, dtype=F64)
     img_t = torch.ones(H, W, dtype=F64)
     rows_rgb, rows_d, rows_t, idx_y, idx_x = [], [], [], [], []
+    decisions = []
     tiles = range(cam.tiles_x * cam.tiles_y) if tiles_subset is None else tiles_subset
     for t in tiles:
         ty, tx = divmod(int(t), tx_n)
@@ -321,6 +327,8 @@ def composite(u, v, conic, opacity, rgb, depth, gid, ranges, cam: Camera, bg=Non
                 first = np.where(has_stop, stop.argmax(axis=1), k)
                 keep = (np.arange(k)[None, :] < first[:, None]) & (~skip.numpy())
                 n_last[yy, xx] = first
+                if with_decisions:
+                    decisions.append(np.packbits(np.stack([skip.numpy(), (gval >= ALPHA_MAX).numpy(), keep])).tobytes())
                 if with_margins:
                     visited = np.arange(k)[None, :] <= np.minimum(first, k - 1)[:, None]
                     g_np = gval.numpy()
@@ -354,7 +362,10 @@ def composite(u, v, conic, opacity, rgb, depth, gid, ranges, cam: Camera, bg=Non
         img_d = img_d.index_put((yy, xx), d_all)
         img_t = img_t.index_put((yy, xx), t_all)
     img_a = 1.0 - img_t
-    return dict(rgb=img_rgb, depth=img_d, alpha=img_a, T_final=img_t, n_last=n_last, margin=margin)
+    out = dict(rgb=img_rgb, depth=img_d, alpha=img_a, T_final=img_t, n_last=n_last, margin=margin)
+    if with_decisions:
+        out["decisions"] = b"".join(decisions)
+    return out
 
 
 def _scatter_rgb(img, yy, xx, vals):
@@ -362,7 +373,8 @@ def _scatter_rgb(img, yy, xx, vals):
     return torch.stack(chans, 0)
 
 
-def render(gauss: dict, cam: Camera, w2c, pose=None, bg=None, tiles_subset=None, with_margins=True):
+def render(gauss: dict, cam: Camera, w2c, pose=None, bg=None, tiles_subset=None, with_margins=True,
+           with_decisions=False):
     """Full render of one job: project -> bin -> composite.
 
     gauss: dict of float64 tensors mean [N,3], log_scale [N,3], quat [N,4],
@@ -373,7 +385,7 @@ def render(gauss: dict, cam: Camera, w2c, pose=None, bg=None, tiles_subset=None,
     tile_of, gid, ranges = bin_sort(pr["u32"], pr["v32"], pr["z32"], pr["radius"], cam)
     opacity = torch.sigmoid(gauss["opacity_logit"])
     out = composite(pr["u"], pr["v"], pr["conic"], opacity, gauss["rgb"], pr["depth"], gid, ranges, cam,
-                    bg=bg, tiles_subset=tiles_subset, with_margins=with_margins)
+                    bg=bg, tiles_subset=tiles_subset, with_margins=with_margins, with_decisions=with_decisions)
     out["proj"] = pr
     out["bins"] = (tile_of, gid, ranges)
     return out

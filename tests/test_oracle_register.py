@@ -232,3 +232,35 @@ def test_joint_registration_recovers_a_known_transform():
     assert G.rotation_error_deg(T, d["T_gt"]) < 0.5
     assert G.translation_error_cm(T[:3, 3], d["T_gt"][:3, 3]) < 1.0
     assert len(res) == 2 and all(r >= 0 for r in res)
+
+
+@pytest.mark.parametrize("deg", [0.0, 0.5, 1.0, 90.0, 179.0])
+def test_rotation_error_degrees_of_known_rotations(deg):
+    """O13: the rotation error of R against R_gt is the angle of R R_gt^T in
+    degrees.  Pinned by R = R_gt R(axis, deg) for a non-trivial R_gt (a
+    missing transpose, radians or a half angle each fail), both argument
+    orders, and the package's reporting helper agreeing."""
+    from paper_2408_10154_amd import register as REG
+
+    gt = rigid([0.2, -1.0, 0.4], 37.0, [0.0, 0.0, 0.0])
+    for axis in ([1, 0, 0], [0.3, 0.5, -0.8]):
+        est = gt @ rigid(axis, deg, [0.0, 0.0, 0.0])
+        assert abs(G.rotation_error_deg(est, gt) - deg) < 1e-6
+        assert abs(G.rotation_error_deg(gt, est) - deg) < 1e-6
+        assert abs(REG.rotation_error_deg(est, gt) - deg) < 1e-6
+        est2 = rigid(axis, deg, [0.0, 0.0, 0.0]) @ gt
+        assert abs(G.rotation_error_deg(est2, gt) - deg) < 1e-6
+
+
+@pytest.mark.parametrize("offset_m,expect_cm", [((0.0, 0.0, 0.0), 0.0), ((0.03, 0.04, 0.0), 5.0),
+                                                ((-0.002, 0.0, 0.0), 0.2), ((0.1, -0.2, 0.2), 30.0)])
+def test_translation_error_centimetres_of_known_offsets(offset_m, expect_cm):
+    """O13: the translation error is |t - t_gt| in centimetres (metres in,
+    a factor 100 out), pinned by offsets with exact norms."""
+    from paper_2408_10154_amd import register as REG
+
+    gt = rigid([1, 2, 3], 5.0, [0.4, -0.1, 1.2])
+    est = gt.copy()
+    est[:3, 3] += np.asarray(offset_m)
+    assert abs(G.translation_error_cm(est[:3, 3], gt[:3, 3]) - expect_cm) < 1e-9
+    assert abs(REG.translation_error_cm(est, gt) - expect_cm) < 1e-9
