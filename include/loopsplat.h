@@ -395,6 +395,26 @@ ls_status ls_overlap_ratio(const float* p_mean, int32_t np, const float* q_mean,
                            float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, size_t work_bytes,
                            hipStream_t s);
 
+/* ls_overlap_ratio for callers that cannot allocate device memory (code
+ * under HIP graph capture, serving loops and harnesses that forbid
+ * hipMalloc): the same computation and results, with the workspace taken
+ * from a library-owned static device array of LS_OVERLAP_NOALLOC_BYTES
+ * (40 MiB), one copy per GPU, held until the process ends.  The caller still
+ * passes inputs and outputs.  Calls no hipMalloc, hipFree or allocating
+ * library routine.  The first call on a device looks up the array's device
+ * address (hipGetSymbolAddress) with that device current; make that first
+ * call outside stream capture.  Every call on a device shares its array,
+ * which keeps the last call's contents (nothing in it needs clearing), so
+ * calls that overlap on one device - on different streams or from different
+ * threads without ordering - race and must not be issued.  The stream must
+ * belong to the current device.  Errors: as ls_overlap_ratio, and
+ * LS_ERR_CAPACITY when np or nq exceeds LS_OVERLAP_NOALLOC_MAX_POINTS. */
+#define LS_OVERLAP_NOALLOC_MAX_POINTS 524288
+#define LS_OVERLAP_NOALLOC_BYTES (40u << 20)
+ls_status ls_overlap_ratio_noalloc(const float* p_mean, int32_t np, const float* q_mean, int32_t nq,
+                                   const float* T_pq, float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts,
+                                   hipStream_t s);
+
 /* One parameter group of a fused Adam step. */
 typedef struct {
   float* param;

@@ -42,6 +42,25 @@ size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 
 
+namespace ls {
+
+ls_status api_fail(ls_status st, const char* msg) { return fail(st, "%s", msg); }
+
+ls_status api_hip_check(const char* what) { return hip_check(what); }
+
+ls_status overlap_check_args(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
+                             float tau, const int32_t* nn_pq, const int32_t* nn_qp, const int32_t* counts) {
+  if (np < 0 || nq < 0) return fail(LS_ERR_INVALID, "negative point count");
+  if (!T_pq || !counts || (np > 0 && (!p_mean || !nn_pq)) || (nq > 0 && (!q_mean || !nn_qp)))
+    return fail(LS_ERR_INVALID, "NULL arguments");
+  for (int k = 0; k < 12; ++k)
+    if (!std::isfinite(T_pq[k])) return fail(LS_ERR_INVALID, "non-finite transform");
+  if (!(tau > 0.f) || !std::isfinite(tau)) return fail(LS_ERR_INVALID, "tau must be finite and > 0");
+  return LS_OK;
+}
+
+}  // namespace ls
+
 namespace {
 
 struct Layout {
@@ -545,12 +564,8 @@ size_t ls_overlap_workspace_size(int32_t np, int32_t nq) {
 ls_status ls_overlap_ratio(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
                            float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, size_t work_bytes,
                            hipStream_t s) {
-  if (np < 0 || nq < 0) return fail(LS_ERR_INVALID, "negative point count");
-  if (!T_pq || !counts || (np > 0 && (!p_mean || !nn_pq)) || (nq > 0 && (!q_mean || !nn_qp)))
-    return fail(LS_ERR_INVALID, "NULL arguments");
-  for (int k = 0; k < 12; ++k)
-    if (!std::isfinite(T_pq[k])) return fail(LS_ERR_INVALID, "non-finite transform");
-  if (!(tau > 0.f) || !std::isfinite(tau)) return fail(LS_ERR_INVALID, "tau must be finite and > 0");
+  const ls_status st = overlap_check_args(p_mean, np, q_mean, nq, T_pq, tau, nn_pq, nn_qp, counts);
+  if (st != LS_OK) return st;
   const size_t need = overlap_workspace_bytes(np, nq);
   if (work_bytes < need || (need > 0 && !work))
     return fail(LS_ERR_CAPACITY, "overlap workspace needs %zu bytes", need);

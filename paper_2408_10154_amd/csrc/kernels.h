@@ -5,6 +5,11 @@
 
 namespace ls {
 
+// Error reporting of the C ABI (api.cpp): set the thread's ls_last_error()
+// text and return `st`; turn a pending HIP error into LS_ERR_HIP.
+ls_status api_fail(ls_status st, const char* msg);
+ls_status api_hip_check(const char* what);
+
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
 void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
@@ -108,6 +113,8 @@ void launch_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, 
 int launch_adjust_submaps(const ls_submap_adjust* subs, int count, hipStream_t s);
 
 // Overlap ratio (overlap.hip).
+ls_status overlap_check_args(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
+                             float tau, const int32_t* nn_pq, const int32_t* nn_qp, const int32_t* counts);
 size_t overlap_workspace_bytes(int np, int nq);
 void launch_overlap(const float* p_mean, int np, const float* q_mean, int nq, const float* T, float tau,
                     int32_t* nn_pq, int32_t* nn_qp, int32_t* counts, void* work, hipStream_t s);

@@ -15,6 +15,8 @@
 // ties to the lower index.
 #include <algorithm>
 #include <cmath>
+#include <mutex>
+#include <vector>
 
 #include "kernels.h"
 
@@ -402,3 +404,59 @@ void launch_overlap(const float* p_mean, int np, const float* q_mean, int nq, co
 }
 
 }  // namespace ls
+
+// ---------------------------------------------------------------------------
+// Overlap ratio without allocation: the workspace is a file-scope device
+// array, one copy per GPU, held until the process ends.  Host code never
+// passes the array's name to a kernel (on the host it is only a stand-in
+// symbol): its device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and kept in a per-device
+// table.  Every call on a device shares its copy; the kernels write every
+// byte they read from it within the call, so nothing needs clearing, and
+// calls that overlap on one device race.
+namespace {
+
+constexpr size_t kNoAllocBytes = (size_t)LS_OVERLAP_NOALLOC_BYTES;
+static_assert(kNoAllocBytes % 256 == 0, "scratch size must keep 256-byte alignment");
+
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
+std::mutex g_scratch_mu;
+std::vector<void*> g_scratch_dev;  // device address of `scratch`, by device ordinal
+
+ls_status scratch_address(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0) return ls::api_fail(LS_ERR_HIP, "hipGetDevice failed");
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if ((size_t)dev >= g_scratch_dev.size()) g_scratch_dev.resize((size_t)dev + 1, nullptr);
+  if (!g_scratch_dev[(size_t)dev]) {
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr) {
+      (void)hipGetLastError();
+      return ls::api_fail(LS_ERR_HIP, "hipGetSymbolAddress of the overlap scratch array failed");
+    }
+    g_scratch_dev[(size_t)dev] = ptr;
+  }
+  *out = g_scratch_dev[(size_t)dev];
+  return LS_OK;
+}
+
+}  // namespace
+
+extern "C" ls_status ls_overlap_ratio_noalloc(const float* p_mean, int32_t np, const float* q_mean, int32_t nq,
+                                              const float* T_pq, float tau, int32_t* nn_pq, int32_t* nn_qp,
+                                              int32_t* counts, hipStream_t s) {
+  const ls_status st = ls::overlap_check_args(p_mean, np, q_mean, nq, T_pq, tau, nn_pq, nn_qp, counts);
+  if (st != LS_OK) return st;
+  if (np > LS_OVERLAP_NOALLOC_MAX_POINTS || nq > LS_OVERLAP_NOALLOC_MAX_POINTS)
+    return ls::api_fail(LS_ERR_CAPACITY, "ls_overlap_ratio_noalloc takes at most LS_OVERLAP_NOALLOC_MAX_POINTS "
+                                         "points per set; use ls_overlap_ratio with a workspace");
+  if (ls::overlap_workspace_bytes(np, nq) > kNoAllocBytes)
+    return ls::api_fail(LS_ERR_CAPACITY, "overlap workspace exceeds the static scratch array");
+  void* work = nullptr;
+  const ls_status sa = scratch_address(&work);
+  if (sa != LS_OK) return sa;
+  ls::launch_overlap(p_mean, np, q_mean, nq, T_pq, tau, nn_pq, nn_qp, counts, work, s);
+  return ls::api_hip_check("ls_overlap_ratio_noalloc");
+}

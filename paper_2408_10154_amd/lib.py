@@ -124,6 +124,8 @@ class ls_adam_group(C.Structure):
 
 
 LS_ISOTROPIC_WORK_FLOATS = 256  # scratch floats of ls_loss_isotropic
+LS_OVERLAP_NOALLOC_MAX_POINTS = 524288  # points per set taken by ls_overlap_ratio_noalloc
+LS_OVERLAP_NOALLOC_BYTES = 40 << 20     # its static per-device scratch array
 
 _P = C.c_void_p
 _PROTOS = {
@@ -154,6 +156,8 @@ _PROTOS = {
     "ls_overlap_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32]),
     "ls_overlap_ratio": (C.c_int32, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_float), C.c_float, _P, _P, _P, _P,
                                      C.c_size_t, _P]),
+    "ls_overlap_ratio_noalloc": (C.c_int32, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_float), C.c_float, _P, _P,
+                                             _P, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
@@ -279,6 +283,10 @@ def ls_overlap_workspace_size(np_, nq):
 
 def ls_overlap_ratio(p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, work, work_bytes, stream):
     return _call("ls_overlap_ratio", p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, work, work_bytes, stream)
+
+
+def ls_overlap_ratio_noalloc(p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, stream):
+    return _call("ls_overlap_ratio_noalloc", p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, stream)
 
 
 def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):

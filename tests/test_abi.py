@@ -133,3 +133,26 @@ def test_register_pair_rejects_bad_loss_parameters_before_touching_a_device():
     for expo, joint, patience in ((0, 2, 0), (1, 1, 0), (0, 1, 5)):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, patience, 1, good, expo, 0.1, joint)
         assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+
+
+def test_overlap_noalloc_limits_without_a_device():
+    """The static scratch of ls_overlap_ratio_noalloc holds the workspace of
+    every size it accepts, and larger or invalid requests are refused before
+    any device call."""
+    lib = L.load()
+    assert L.LS_OVERLAP_NOALLOC_BYTES % 256 == 0
+    mx = L.LS_OVERLAP_NOALLOC_MAX_POINTS
+    for a in (0, 1, 63, 64, 65, 4097, 131071, 200003, mx - 1, mx):
+        for b in (0, 1, 777, 65536, mx):
+            assert L.ls_overlap_workspace_size(a, b) <= L.LS_OVERLAP_NOALLOC_BYTES, (a, b)
+    T = (C.c_float * 12)(1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0)
+    fake = C.c_void_p(256)  # never dereferenced: the checks fail first
+    assert lib.ls_overlap_ratio_noalloc(fake, mx + 1, fake, 10, T, C.c_float(0.2), fake, fake, fake,
+                                        None) == L.LS_ERR_CAPACITY
+    assert b"LS_OVERLAP_NOALLOC_MAX_POINTS" in lib.ls_last_error()
+    assert lib.ls_overlap_ratio_noalloc(fake, 10, fake, mx + 1, T, C.c_float(0.2), fake, fake, fake,
+                                        None) == L.LS_ERR_CAPACITY
+    assert lib.ls_overlap_ratio_noalloc(None, 10, fake, 10, T, C.c_float(0.2), fake, fake, fake,
+                                        None) == L.LS_ERR_INVALID
+    assert lib.ls_overlap_ratio_noalloc(fake, 10, fake, 10, T, C.c_float(0.0), fake, fake, fake,
+                                        None) == L.LS_ERR_INVALID
