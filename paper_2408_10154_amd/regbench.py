@@ -20,7 +20,8 @@ def build_pair(spec: dict, width=640, height=480, f=500.0):
     synth.pair_set / synth.request_stream, built by synth.registration_pair."""
     d = synth.registration_pair(spec["seed"], spec["n_p"], spec["n_q"], views_p=spec["views_p"],
                                 views_q=spec["views_q"], width=spec.get("width", width),
-                                height=spec.get("height", height), f=spec.get("f", f))
+                                height=spec.get("height", height), f=spec.get("f", f),
+                                layout=spec.get("layout", "views"))
     P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
     rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
     rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
@@ -41,7 +42,7 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, np.float64), q))
 
 
-def run_plain(pairs, iters=200, loss="tracking", exit_rel_tol=0.0, exit_patience=0):
+def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0):
     """One pair at a time through ls_register_pair; latency of pair k counts
     from the start of the run (all requests present at t = 0)."""
     torch.cuda.synchronize()
@@ -56,7 +57,7 @@ def run_plain(pairs, iters=200, loss="tracking", exit_rel_tol=0.0, exit_patience
                 mean_iters=float(np.mean([r["iters"] for r in results])), **_errors(results, pairs)), results
 
 
-def run_batched(pairs, iters=200, loss="tracking", chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30,
+def run_batched(pairs, iters=200, loss="l1", chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30,
                 exit_rel_tol=0.0, exit_patience=0):
     """Every pair submitted at t = 0 to one server."""
     from .serve import Server
@@ -75,7 +76,7 @@ def run_batched(pairs, iters=200, loss="tracking", chunk_iters=16, use_graphs=Tr
                 mean_iters=float(np.mean([r["iters"] for r in results])), **_errors(results, pairs)), results
 
 
-def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget=200 << 30, max_slots=64,
+def run_stream(stream, built, iters=200, loss="l1", chunk_iters=16, budget=200 << 30, max_slots=64,
                max_active_pixels=0):
     """Requests submitted at their arrival times (a host thread paces them)."""
     from .serve import Server
@@ -99,7 +100,7 @@ def run_stream(stream, built, iters=200, loss="tracking", chunk_iters=16, budget
                 **_errors(results, built)), results
 
 
-def run_stream_plain(stream, built, iters=200, loss="tracking"):
+def run_stream_plain(stream, built, iters=200, loss="l1"):
     """The plain path under the same arrivals: a FIFO queue served one pair at
     a time by ls_register_pair; latency counts from each request's arrival."""
     torch.cuda.synchronize()
@@ -119,7 +120,7 @@ def run_stream_plain(stream, built, iters=200, loss="tracking"):
 def single_pair_spec(seed=2):
     """The single-pair workload: 150k + 120k Gaussians (60 % shared), 8 + 8
     keyframes at 640x480, f = 500."""
-    return dict(seed=seed, n_p=150_000, n_q=120_000, views_p=8, views_q=8)
+    return dict(seed=seed, n_p=150_000, n_q=120_000, views_p=8, views_q=8, layout="views")
 
 
 def main(argv=None):
@@ -140,7 +141,9 @@ def main(argv=None):
     ap.add_argument("--pairs", type=int, default=8, help="pairs of the pair set (seed 3)")
     ap.add_argument("--iters", type=int, default=200)
     ap.add_argument("--mode", choices=["plain", "batched", "both"], default="plain")
-    ap.add_argument("--loss", choices=["tracking", "l1"], default="tracking")
+    ap.add_argument("--loss", choices=["tracking", "l1"], default="l1")
+    ap.add_argument("--layout", choices=["views", "x_split"], default="views",
+                    help="submap split of the synthetic pairs (see synth.registration_pair)")
     ap.add_argument("--exit", type=float, nargs=2, default=[0.0, 0], metavar=("REL_TOL", "PATIENCE"),
                     help="per-view early exit (0 0: off)")
     a = ap.parse_args(argv)
@@ -151,6 +154,8 @@ def main(argv=None):
         specs = synth.pair_set(3, a.pairs)
     else:
         specs = synth.request_stream(100, a.requests, a.rate)
+    for sp in specs:
+        sp["layout"] = a.layout
     pairs = [build_pair(sp) for sp in specs]
     print(json.dumps(dict(event="built", pairs=len(pairs))), flush=True)
     for mode in (["plain", "batched"] if a.mode == "both" else [a.mode]):

@@ -40,14 +40,15 @@ def keyframe_targets(g: GaussianSet, cam: dict, c2ws: np.ndarray):
     return rgb, depth
 
 
-def default_params(iters=200, lr_rot=0.015, lr_trans=0.005, exit_rel_tol=0.0, exit_patience=0, loss="tracking",
+def default_params(iters=200, lr_rot=0.015, lr_trans=0.005, exit_rel_tol=0.0, exit_patience=0, loss="l1",
                    lambda_c=0.6, inlier_k=50.0, alpha_power=3, exposure=False,
                    lr_exposure=0.1, joint=False) -> L.ls_reg_params:
     """Registration settings: real-data learning rates of the paper's
     loop-closure table by default; early exit off unless exit_patience > 0.
-    loss "tracking" is Eq. 2 with the supplement's alpha and inlier masks
-    (lambda_c of the real-data column of the per-dataset table), "l1" the
-    plain unmasked colour + depth L1.  exposure: per-view exposure
+    loss "l1" (the default) is the registration loss of Sec. 3.2, the plain
+    unmasked colour + depth L1; "tracking" is Eq. 2 with the supplement's
+    alpha and inlier masks (lambda_c of the real-data column of the
+    per-dataset table), a variant.  exposure: per-view exposure
     coefficients (gain and offset of the rendered colour) optimised with the
     pose at lr_exposure (the supplement's 0.1).  joint: one transform shared
     by all views instead of per-view estimates and their fusion (a

@@ -139,11 +139,11 @@ def _smooth_colour(rng: np.random.Generator, pts: np.ndarray, n_waves=8, wl=(0.3
     return out
 
 
-def room_points(rng: np.random.Generator, n: int, half=(3.0, 1.5, 2.0), boxes=4, jitter=0.01) -> np.ndarray:
-    """Points on the inner shell of a box room (6 x 3 x 4 m by default) plus
-    the surfaces of `boxes` random boxes inside it, jittered along the normal."""
+def room_faces(rng: np.random.Generator, half=(3.0, 1.5, 2.0), boxes=4) -> list:
+    """Faces (centre, u-axis half, v-axis half, normal) of the inner shell of a
+    box room (6 x 3 x 4 m by default) and of `boxes` random boxes inside it."""
     half = np.asarray(half, np.float64)
-    faces = []  # (centre, u-axis half, v-axis half, normal)
+    faces = []
     for ax in range(3):
         for sgn in (-1.0, 1.0):
             c = np.zeros(3)
@@ -172,6 +172,11 @@ def room_points(rng: np.random.Generator, n: int, half=(3.0, 1.5, 2.0), boxes=4,
                 nrm = np.zeros(3)
                 nrm[ax] = 1.0
                 faces.append((c, eu, ev, nrm))
+    return faces
+
+
+def face_points(rng: np.random.Generator, faces: list, n: int, jitter=0.01) -> np.ndarray:
+    """n points uniform by area over `faces`, jittered along the normal; [3,n]."""
     areas = np.array([4 * np.linalg.norm(f[1]) * np.linalg.norm(f[2]) for f in faces])
     which = rng.choice(len(faces), size=n, p=areas / areas.sum())
     pts = np.zeros((3, n))
@@ -182,6 +187,31 @@ def room_points(rng: np.random.Generator, n: int, half=(3.0, 1.5, 2.0), boxes=4,
         b = rng.uniform(-1, 1, k)
         pts[:, m] = (c[:, None] + eu[:, None] * a + ev[:, None] * b + nrm[:, None] * rng.normal(0, jitter, k))
     return pts
+
+
+def room_points(rng: np.random.Generator, n: int, half=(3.0, 1.5, 2.0), boxes=4, jitter=0.01) -> np.ndarray:
+    """Points on the inner shell of a box room (6 x 3 x 4 m by default) plus
+    the surfaces of `boxes` random boxes inside it, jittered along the normal."""
+    return face_points(rng, room_faces(rng, half, boxes), n, jitter)
+
+
+def in_view(pts: np.ndarray, c2ws, cam: dict, margin_px: float, z_near: float = 0.2) -> np.ndarray:
+    """Mask of the points [3,N] that project into any of the cameras' images
+    grown by `margin_px` on every side, in front of z_near (a pinhole
+    frustum test; occlusion is ignored, so it over-approximates what a camera
+    sees)."""
+    out = np.zeros(pts.shape[1], bool)
+    for c in c2ws:
+        c = np.asarray(c, np.float64)
+        p = c[:3, :3].T @ (pts - c[:3, 3:4])
+        z = p[2]
+        ok = z > z_near
+        zs = np.where(ok, z, 1.0)
+        u = cam["fx"] * p[0] / zs + cam["cx"]
+        v = cam["fy"] * p[1] / zs + cam["cy"]
+        out |= ok & (u >= -margin_px) & (u <= cam["width"] + margin_px) & (v >= -margin_px) & \
+            (v <= cam["height"] + margin_px)
+    return out
 
 
 def pose_matrix4(pose: np.ndarray) -> np.ndarray:
@@ -218,21 +248,44 @@ def in_frame(pose: np.ndarray, g: dict) -> dict:
 def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, views_p: int = 8,
                       views_q: int = 8, width: int = 640, height: int = 480, f: float = 500.0,
                       rot_deg_max: float = 10.0, trans_max: float = 0.3, half=(3.0, 1.5, 2.0),
-                      log_scale_mu=math.log(0.02), fixed_gt=None) -> dict:
+                      log_scale_mu=math.log(0.02), fixed_gt=None, layout: str = "x_split",
+                      view_margin_px: float = 64.0) -> dict:
     """Two overlapping submaps of one synthetic room and their keyframes.
 
-    The room's Gaussians are ordered along x; the lowest (n_p - S) belong
-    to P only, the highest (n_q - S) to Q only and the S = shared_frac *
-    (n_p + n_q) / 2 in between to both.  P is kept in the world frame; Q is
-    expressed in its own frame through the ground-truth T_gt (rotation about a
-    random axis by U[0, rot_deg_max] deg, translation of length
-    U[0, trans_max] m), so x_Q = T_gt x_P.  Keyframes: `views_*` cameras per
-    submap in a small region near the room centre, each looking at a point of
-    the shared band; their camera-to-world poses are given in the submap's
-    own frame.  Targets (the submaps rendered at their own keyframes) are made
-    by the caller with the renderer.
+    P is kept in the world frame; Q is expressed in its own frame through the
+    ground-truth T_gt (rotation about a random axis by U[0, rot_deg_max] deg,
+    translation of length U[0, trans_max] m), so x_Q = T_gt x_P.  Keyframe
+    poses are camera-to-world in the submap's own frame.  Targets (the
+    submaps rendered at their own keyframes) are made by the caller with the
+    renderer.  Two layouts:
+
+    "x_split": the room's points are ordered along x; the lowest (n_p - S)
+    belong to P only, the highest (n_q - S) to Q only and the
+    S = shared_frac * (n_p + n_q) / 2 in between (at most min(n_p, n_q)) to
+    both.  Keyframes: cameras near the room centre, each looking at a point
+    of the shared band.  When one submap is much smaller than the other, the
+    shared band is a thin x-slab and the keyframes also see content that
+    only one submap holds.
+
+    "views": keyframes first, then the split.  Every keyframe of either
+    submap stands near the room centre and looks at a point of one wall (a
+    random x or z wall) between knee and head height, so views hold that
+    wall, the floor near it and any box in front of it.  The shared
+    Gaussians are S = min(shared_frac * (n_p + n_q) / 2, 0.8 min(n_p, n_q))
+    points drawn over the part of the room inside some keyframe's frustum
+    (image grown by `view_margin_px`); the unshared ones are drawn over the
+    rest of the room, ordered along the wall and split into P's side and
+    Q's side.  So every keyframe of either submap sees only Gaussians that
+    both submaps hold: each view's target is reproduced by the other submap
+    at the true transform.
     """
+    if layout not in ("x_split", "views"):
+        raise ValueError(f"layout must be 'x_split' or 'views', not {layout!r}")
     rng = np.random.default_rng(seed)
+    cam = camera(f, f, width / 2, height / 2, width, height)
+    if layout == "views":
+        return _pair_views(rng, n_p, n_q, shared_frac, views_p, views_q, cam, rot_deg_max, trans_max,
+                           np.asarray(half, np.float64), log_scale_mu, fixed_gt, view_margin_px)
     s = int(round(shared_frac * (n_p + n_q) / 2))
     s = min(s, n_p, n_q)
     n_w = n_p + n_q - s
@@ -244,11 +297,7 @@ def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, v
     g["rgb"] = _smooth_colour(rng, pts).astype(np.float32)
     idx_p = np.arange(0, n_p)
     idx_q = np.arange(n_w - n_q, n_w)
-    if fixed_gt is None:
-        ang = math.radians(rng.uniform(0.0, rot_deg_max))
-        gt = axis_angle_pose(random_axis(rng), ang, rng.uniform(0.0, trans_max) * random_axis(rng))
-    else:
-        gt = np.asarray(fixed_gt, np.float32)
+    gt = _ground_truth(rng, rot_deg_max, trans_max, fixed_gt)
     t_gt = pose_matrix4(gt)
     P = {k: v[..., idx_p].copy() for k, v in g.items()}
     Q = in_frame(gt, {k: v[..., idx_q].copy() for k, v in g.items()})
@@ -268,21 +317,78 @@ def registration_pair(seed: int, n_p: int, n_q: int, shared_frac: float = 0.6, v
     kf_p = keyframes(views_p)
     kf_q = [t_gt @ c for c in keyframes(views_q)]
     return dict(P=P, Q=Q, kf_p=np.stack(kf_p).astype(np.float64), kf_q=np.stack(kf_q).astype(np.float64),
-                T_gt=t_gt, cam=camera(f, f, width / 2, height / 2, width, height), shared=s)
+                T_gt=t_gt, cam=cam, shared=s)
+
+
+def _ground_truth(rng, rot_deg_max, trans_max, fixed_gt):
+    if fixed_gt is not None:
+        return np.asarray(fixed_gt, np.float32)
+    ang = math.radians(rng.uniform(0.0, rot_deg_max))
+    return axis_angle_pose(random_axis(rng), ang, rng.uniform(0.0, trans_max) * random_axis(rng))
+
+
+def _pair_views(rng, n_p, n_q, shared_frac, views_p, views_q, cam, rot_deg_max, trans_max, half, log_scale_mu,
+                fixed_gt, margin_px) -> dict:
+    """The "views" layout of registration_pair."""
+    s = int(round(min(shared_frac * (n_p + n_q) / 2, 0.8 * min(n_p, n_q))))
+    n_w = n_p + n_q - s
+    faces = room_faces(rng, half)
+    ax = (0, 2)[int(rng.integers(2))]           # the wall the keyframes look at: an x or a z wall
+    sgn = (-1.0, 1.0)[int(rng.integers(2))]
+    along = 2 if ax == 0 else 0                 # horizontal axis within that wall
+
+    def keyframes(k):
+        out = []
+        for _ in range(k):
+            pos = rng.uniform(-0.35, 0.35, 3) * half
+            pos[ax] -= sgn * 0.2 * half[ax]     # a step back from the wall
+            tgt = np.zeros(3)
+            tgt[ax] = sgn * half[ax]
+            tgt[along] = rng.uniform(-0.5, 0.5) * half[along]
+            tgt[1] = rng.uniform(-0.9, 0.2) * half[1]
+            out.append(look_at_c2w(pos, tgt))
+        return out
+
+    kf_p = keyframes(views_p)
+    kf_q_world = keyframes(views_q)
+    seen, unseen = [], []
+    n_seen = n_unseen = 0
+    while n_seen < s or n_unseen < n_w - s:
+        pool = face_points(rng, faces, max(4 * n_w, 4096))
+        m = in_view(pool, kf_p + kf_q_world, cam, margin_px)
+        seen.append(pool[:, m])
+        unseen.append(pool[:, ~m])
+        n_seen += int(m.sum())
+        n_unseen += int((~m).sum())
+    shared = np.concatenate(seen, 1)[:, :s]
+    rest = np.concatenate(unseen, 1)[:, :n_w - s]
+    rest = rest[:, np.argsort(rest[along], kind="stable")]
+    pts = np.concatenate([rest[:, :n_p - s], shared, rest[:, n_p - s:]], 1)
+    g = gaussians_in_box(rng, n_w, (0, 0, 0), (1, 1, 1), log_scale_mu=log_scale_mu)
+    g["mean"] = pts.astype(np.float32)
+    g["rgb"] = _smooth_colour(rng, pts).astype(np.float32)
+    gt = _ground_truth(rng, rot_deg_max, trans_max, fixed_gt)
+    t_gt = pose_matrix4(gt)
+    P = {k: v[..., :n_p].copy() for k, v in g.items()}
+    Q = in_frame(gt, {k: v[..., n_w - n_q:].copy() for k, v in g.items()})
+    kf_q = [t_gt @ c for c in kf_q_world]
+    return dict(P=P, Q=Q, kf_p=np.stack(kf_p).astype(np.float64), kf_q=np.stack(kf_q).astype(np.float64),
+                T_gt=t_gt, cam=cam, shared=s)
 
 
 def pair_set(seed: int, n_pairs: int, n_min: int = 20_000, n_max: int = 300_000, views_min: int = 4,
-             views_max: int = 12) -> list:
+             views_max: int = 12, layout: str = "views") -> list:
     """Specs of a batch of registration pairs: per submap a Gaussian count
     log-uniform in [n_min, n_max] and a keyframe count uniform in
     {views_min..views_max}; each pair gets its own seed (hence its own room,
-    split and ground-truth transform)."""
+    split and ground-truth transform) and the submap layout `layout` of
+    registration_pair."""
     rng = np.random.default_rng(seed)
     out = []
     for k in range(n_pairs):
         n_p, n_q = (int(round(math.exp(rng.uniform(math.log(n_min), math.log(n_max))))) for _ in range(2))
         v_p, v_q = (int(rng.integers(views_min, views_max + 1)) for _ in range(2))
-        out.append(dict(seed=int(seed * 1000 + k), n_p=n_p, n_q=n_q, views_p=v_p, views_q=v_q))
+        out.append(dict(seed=int(seed * 1000 + k), n_p=n_p, n_q=n_q, views_p=v_p, views_q=v_q, layout=layout))
     return out
 
 
@@ -301,6 +407,6 @@ def request_stream(seed: int, n_requests: int, rate_per_s: float, median_n: int 
         v_p, v_q = (int(rng.integers(views_min, views_max + 1)) for _ in range(2))
         w, h, f = resolutions[int(rng.integers(len(resolutions)))]
         out.append(dict(arrival=t, seed=int(seed * 100000 + k), n_p=n_p, n_q=n_q, views_p=v_p, views_q=v_q,
-                        width=int(w), height=int(h), f=float(f)))
+                        width=int(w), height=int(h), f=float(f), layout="views"))
     return out
 
