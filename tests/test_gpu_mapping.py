@@ -3,7 +3,8 @@ Sec. 3.1 Eq. 3-5) against the FP64 oracle.  Bars: loss values within 1e-5
 relative (1e-6 absolute); image gradients within 1e-3 of the reference, both
 as the L2 relative error and as the largest deviation over the largest
 reference entry; the depth gradient (a weighted sign) exactly; Gaussian
-gradients through the rasterizer within 1e-3 (L2 relative)."""
+gradients through the rasterizer within 1e-3 (L2 relative per parameter
+group, and element-wise away from flipped decisions)."""
 
 import numpy as np
 import pytest
@@ -176,10 +177,23 @@ def test_small_workload_mapping_step_matches_oracle(gpu):
     np.testing.assert_allclose(loss[0].item(), ref.item(), rtol=1e-4)
     np.testing.assert_allclose(reg.item(), ref_reg.item(), rtol=1e-5)
     (ref + ref_reg).backward()
+    # excluded from the element clause: Gaussians at flipped compositing
+    # decisions, at pixels whose L1 residual is within FP32 reach of zero
+    # (sign decided by rounding), and Gaussians whose scale sits within 1e-6
+    # of its mean (the regulariser's sign decided by rounding)
+    t_rgb = tgt_rgb.cpu().numpy().reshape(3, H, W).astype(np.float64)
+    t_dep = tgt_depth.cpu().numpy().reshape(H, W).astype(np.float64)
+    close = [(o["rgb"].detach().numpy() - t_rgb, 1e-5 * np.maximum(np.abs(t_rgb), 1.0)),
+             (o["depth"].detach().numpy() - t_dep, 1e-5 * np.maximum(np.abs(t_dep), 1.0))]
+    n = len(sc["gauss"]["opacity_logit"])
+    excl = U.render_flips(b, 0, o, n, close_pairs=close)
+    sc_ = np.exp(np.asarray(sc["gauss"]["log_scale"], np.float64).T)
+    excl |= (np.abs(sc_ - sc_.mean(1, keepdims=True)).min(1) / sc_.mean(1)) < 1e-6
+    pairs = []
     for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
         got = getattr(grads[0], name).cpu().numpy()
-        got = got.T if got.ndim == 2 else got
-        assert U.rel_err(got, g[name].grad.numpy()) < 1e-3, name
+        pairs.append((name, got.T if got.ndim == 2 else got, g[name].grad.numpy()))
+    print(U.check_gradients(pairs, excl, f"mapping step (excluded {int(excl.sum())} of {n})"))
 
 
 @pytest.mark.parametrize("n", [0, 1, 5003, 200_003])

@@ -226,10 +226,14 @@ def _backward_case(jobs, poses, want_pose=True, seed=0):
 
 
 def test_backward_matches_oracle(gpu):
+    """Gradients of a random linear function of the three renders' images
+    (colour, depth, alpha) to every Gaussian parameter and the pose, against
+    the oracle: the norm clause over all Gaussians and the element clause
+    over those not touched by a flipped decision."""
     jobs, poses = _three_scenes()
     b, up, grads, pose_grad = _backward_case(jobs, poses)
     for r, (g, cam, w2c) in enumerate(jobs):
-        gt, pt, o = U.oracle_render(g, cam, w2c, poses[r], requires_grad=True, with_margins=False)
+        gt, pt, o = U.oracle_render(g, cam, w2c, poses[r], requires_grad=True)
         H, W = cam["height"], cam["width"]
         p0 = int(b.pix_off[r])
         ur = torch.as_tensor(up["rgb"].reshape(-1)[3 * p0:3 * p0 + 3 * H * W].reshape(3, H, W), dtype=F64)
@@ -237,14 +241,15 @@ def test_backward_matches_oracle(gpu):
         ua = torch.as_tensor(up["alpha"][p0:p0 + H * W].reshape(H, W), dtype=F64)
         ((o["rgb"] * ur).sum() + (o["depth"] * ud).sum() + (o["alpha"] * ua).sum()).backward()
         gg = grads[r]
+        n = len(g["opacity_logit"])
+        excl = U.render_flips(b, r, o, n)
+        pairs = []
         for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
-            ref = gt[name].grad.numpy()
             got = getattr(gg, name).cpu().numpy()
-            got = got.T if got.ndim == 2 else got
-            err = U.rel_err(got, ref)
-            assert err < 1e-3, (r, name, err)
-        err = U.rel_err(pose_grad[r].cpu().numpy(), pt.grad.numpy())
-        assert err < 1e-3, (r, "pose", err)
+            pairs.append((name, got.T if got.ndim == 2 else got, gt[name].grad.numpy()))
+        print(U.check_gradients(pairs, excl, f"render {r} (excluded {int(excl.sum())} of {n})"))
+        print(U.check_gradients([("pose", pose_grad[r].cpu().numpy()[None], pt.grad.numpy()[None])], None,
+                                f"render {r}"))
 
 
 def test_loss_l1_matches_oracle(gpu):
@@ -428,15 +433,21 @@ def test_small_workload_full_step_matches_oracle(gpu):
     for key in ("rgb", "depth", "alpha"):
         mask = ok[None] if key == "rgb" else ok
         assert U.image_close(v[key].cpu().numpy(), o[key].detach().numpy(), mask) == 0, key
-    ref = R.loss_l1(o["rgb"], o["depth"], torch.as_tensor(tgt_rgb.cpu().numpy().reshape(3, H, W), dtype=F64),
-                    torch.as_tensor(tgt_depth.cpu().numpy().reshape(H, W), dtype=F64))
+    t_rgb = torch.as_tensor(tgt_rgb.cpu().numpy().reshape(3, H, W), dtype=F64)
+    t_dep = torch.as_tensor(tgt_depth.cpu().numpy().reshape(H, W), dtype=F64)
+    ref = R.loss_l1(o["rgb"], o["depth"], t_rgb, t_dep)
     np.testing.assert_allclose(loss[0].item(), ref.item(), rtol=1e-4)
     ref.backward()
+    valid = (t_dep.numpy() > 0).astype(np.float64)
+    signs = [(g_rgb.cpu().numpy().reshape(3, H, W), (o["rgb"].detach().numpy() - t_rgb.numpy()) * valid[None]),
+             (g_depth.cpu().numpy().reshape(H, W), (o["depth"].detach().numpy() - t_dep.numpy()) * valid)]
+    excl = U.render_flips(b, 0, o, len(sc["gauss"]["opacity_logit"]), sign_pairs=signs)
+    pairs = []
     for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
         got = getattr(grads[0], name).cpu().numpy()
-        got = got.T if got.ndim == 2 else got
-        assert U.rel_err(got, g[name].grad.numpy()) < 1e-3, name
-    assert U.rel_err(pose_grad[0].cpu().numpy(), pt.grad.numpy()) < 1e-3
+        pairs.append((name, got.T if got.ndim == 2 else got, g[name].grad.numpy()))
+    print(U.check_gradients(pairs, excl, f"4096-Gaussian step (excluded {int(excl.sum())})"))
+    print(U.check_gradients([("pose", pose_grad[0].cpu().numpy()[None], pt.grad.numpy()[None])], None, "step"))
 
 
 def test_render_loop_workload_sampled_tiles_match_oracle(gpu):
@@ -483,12 +494,21 @@ def test_render_loop_workload_sampled_tiles_match_oracle(gpu):
     np.testing.assert_array_equal(v["n_last"].cpu().numpy()[ok], o["n_last"][ok])
     f64 = lambda a: torch.as_tensor(a, dtype=F64)  # noqa: E731
     ((o["rgb"] * f64(up_rgb)).sum() + (o["depth"] * f64(up_d)).sum() + (o["alpha"] * f64(up_a)).sum()).backward()
+    # decision flips only count inside the sampled tiles (the oracle left the rest at background)
+    vv = {k: t.cpu().numpy() for k, t in v.items()}
+    for k in ("rgb", "depth", "alpha", "n_last"):
+        ora = o[k] if k == "n_last" else o[k].detach().numpy()
+        vv[k] = np.where(sel[None] if k == "rgb" else sel, vv[k], ora)
+    excl, flip = U.decision_flips(o, vv, 200000, b.radius.cpu().numpy())
+    flip &= sel
+    assert flip.sum() <= 1e-3 * sel.sum() and np.all(np.asarray(o["margin"])[flip] < 1e-3)
+    pairs = []
     for name in ("mean", "log_scale", "quat", "opacity_logit", "rgb"):
-        ref = g[name].grad.numpy()
         got = getattr(grads[0], name).cpu().numpy()
-        got = got.T if got.ndim == 2 else got
-        assert U.rel_err(got, ref) < 1e-3, name
-    assert U.rel_err(pose_grad[0].cpu().numpy(), pt.grad.numpy()) < 1e-3
+        pairs.append((name, got.T if got.ndim == 2 else got, g[name].grad.numpy()))
+    print(U.check_gradients(pairs, excl, f"render loop, 96 tiles (flipped px {int(flip.sum())}, "
+                                         f"excluded {int(excl.sum())})"))
+    print(U.check_gradients([("pose", pose_grad[0].cpu().numpy()[None], pt.grad.numpy()[None])], None, "loop"))
 
 
 def test_pose_only_backward_matches_full_and_is_bitwise_repeatable(gpu):
@@ -618,53 +638,93 @@ def test_loss_tracking_matches_oracle(gpu, lambda_c, inlier_k, alpha_power):
 
 
 def test_gpu_gradients_match_gpu_finite_differences(gpu):
-    """FP32 sanity check of the backward against the forward alone (no
-    oracle): for L = sum w . image with smooth weights, the derivative of the
-    GPU's own forward along the GPU's pose gradient, and along its gradient
-    with respect to all Gaussian means, by central differences, equals the
-    gradient's norm within 10 %.  Directional checks along the gradient keep
-    the bar meaningful although the alpha-skip contours move inside the step
-    (the backward, like the method, has no gradient through that threshold;
-    per-component differences pick up those jumps at the few-percent level of
-    the largest component)."""
-    sc = synth.scene_small(0, n=800)
-    cam, w2c = sc["cam"], sc["w2c"]
-    b = _batch([(sc["gauss"], cam, w2c)])
-    H, W = cam["height"], cam["width"]
-    yy, xx = np.mgrid[0:H, 0:W]
-    field = 1.0 + 0.5 * np.sin(xx / 23.0) * np.cos(yy / 17.0)
-    w_rgb = torch.as_tensor(np.stack([field, 0.8 * field, 1.2 * field]).astype(np.float32).reshape(-1), device="cuda")
-    w_dep = torch.as_tensor((0.3 * field).astype(np.float32).reshape(-1), device="cuda")
+    """FP32 check of the backward against the forward alone (no oracle): for
+    L = sum w . image with smooth weights, single components of every
+    parameter group (Gaussian mean, log-scale, quaternion, opacity logit,
+    colour; the pose) are moved by +-h and the central difference of the
+    GPU's own FP32 forward (L summed in FP64, the step taken as the FP32
+    difference of the two parameter values) must equal the GPU gradient
+    within 1e-2.  Samples are components whose gradient is at least 0.1 of
+    the group's largest, and a sample is rejected when any discrete decision
+    differs between the base point and either side of the step: radius or
+    tile count of any Gaussian, the stop position of any pixel, or the number
+    of composited entries (an alpha-skip decision), or when the differences
+    at h and h/2 disagree by more than 0.5 % (a flip that leaves the counts
+    unchanged).  A pose step moves every Gaussian and flips some decision of
+    a dense scene at any step that FP32 can resolve, so the pose (and the
+    means and scales of that scene) is checked on three broad Gaussians that
+    take no decision anywhere in the image, at h = 1e-3."""
+    for n, groups in ((800, dict(mean=[1e-4], log_scale=[1e-4], quat=[1e-4], opacity_logit=[1e-4], rgb=[1e-3])),
+                      (3, dict(pose=[1e-3], mean=[1e-3], log_scale=[1e-3]))):
+        sc = synth.scene_small(0, n=n)
+        if n == 3:
+            # three broad Gaussians (sigma ~ 0.8 m at 2-3 m, opacity 0.5) whose alpha stays between 1/255
+            # and 0.99 over the whole image and whose transmittance never reaches 1e-4: no decision exists
+            # for a step to flip, so the pose is checked at the survey's h = 1e-3
+            g = sc["gauss"]
+            g["mean"] = np.array([[0.05, -0.1, 0.08], [0.02, 0.06, -0.05], [2.0, 2.5, 3.0]], np.float32)
+            g["log_scale"] = np.log(np.array([[0.8, 0.9, 1.0], [0.7, 0.85, 0.95], [0.75, 0.8, 1.1]], np.float32))
+            g["opacity_logit"] = np.zeros(3, np.float32)
+        cam, w2c = sc["cam"], sc["w2c"]
+        b = _batch([(sc["gauss"], cam, w2c)])
+        H, W = cam["height"], cam["width"]
+        yy, xx = np.mgrid[0:H, 0:W]
+        field = 1.0 + 0.5 * np.sin(xx / 23.0) * np.cos(yy / 17.0)
+        w_rgb = torch.as_tensor(np.stack([field, 0.8 * field, 1.2 * field]).reshape(-1), device="cuda")
+        w_dep = torch.as_tensor((0.3 * field).reshape(-1), device="cuda")
+        gs = b.gsets[0]
+        pose = torch.as_tensor(sc["target_pose"][None], device="cuda").contiguous()
 
-    def loss_at(pose):
-        b.project(pose)
-        b.bin_sort()
-        b.render_fwd()
-        return float((b.rgb.double() * w_rgb.double()).sum() + (b.depth.double() * w_dep.double()).sum())
+        def forward():
+            b.project(pose)
+            b.bin_sort()
+            b.render_fwd()
+            val = float((b.rgb.double() * w_rgb).sum() + (b.depth.double() * w_dep).sum())
+            dec = (b.radius.cpu().numpy().tobytes(), b.tiles.cpu().numpy().tobytes(),
+                   b.n_last.cpu().numpy().tobytes(), b.render_stats())
+            return val, dec
 
-    pose = torch.as_tensor(sc["target_pose"][None], device="cuda").contiguous()
-    b.project(pose)
-    b.bin_sort()
-    b.render_fwd()
-    grads = [b.gsets[0].zeros_like()]
-    pose_grad = torch.zeros_like(pose)
-    b.render_bwd(up_rgb=w_rgb, up_depth=w_dep, grads=grads, pose=pose, pose_grad=pose_grad)
-    torch.cuda.synchronize()
-    g = pose_grad.double()
-    gn = float(g.norm())
-    d = (g / gn).float()
-    h = 1e-4
-    fd = (loss_at(pose + h * d) - loss_at(pose - h * d)) / (2 * h)
-    assert abs(fd - gn) <= 0.1 * gn, (fd, gn)
-    gm = grads[0].mean.double()
-    gmn = float(gm.norm())
-    dm = (gm / gmn).float()
-    base = b.gsets[0].mean.clone()
-    h = 1e-4
-    b.gsets[0].mean.copy_(base + h * dm)
-    lp = loss_at(pose)
-    b.gsets[0].mean.copy_(base - h * dm)
-    lm = loss_at(pose)
-    b.gsets[0].mean.copy_(base)
-    fd = (lp - lm) / (2 * h)
-    assert abs(fd - gmn) <= 0.1 * gmn, (fd, gmn)
+        _, dec0 = forward()
+        grads = [gs.zeros_like()]
+        pose_grad = torch.zeros_like(pose)
+        b.render_bwd(up_rgb=w_rgb.float(), up_depth=w_dep.float(), grads=grads, pose=pose, pose_grad=pose_grad)
+        torch.cuda.synchronize()
+        rng = np.random.default_rng(5)
+        accepted = {}
+        for name, hs in groups.items():
+            param = pose[0] if name == "pose" else getattr(gs, name)
+            grad = (pose_grad[0] if name == "pose" else getattr(grads[0], name)).cpu().numpy().astype(np.float64)
+            flat = grad.reshape(-1)
+            cand = np.nonzero(np.abs(flat) >= 0.1 * np.abs(flat).max())[0]
+            accepted[name] = 0
+            for idx in rng.choice(cand, size=min(len(cand), 8), replace=False):
+                pv = param.view(-1)
+                x0 = pv[idx].item()
+
+                def central(h):
+                    vals, xs, ok = [], [], True
+                    for sgn in (1, -1):
+                        pv[idx] = float(np.float32(x0 + sgn * h))
+                        xs.append(pv[idx].item())
+                        v, dec = forward()
+                        vals.append(v)
+                        ok &= dec == dec0
+                    pv[idx] = x0
+                    return (vals[0] - vals[1]) / (xs[0] - xs[1]), ok
+
+                fd = None
+                for h in hs:
+                    f1, ok1 = central(h)
+                    f2, ok2 = central(0.5 * h)
+                    # two step sizes must agree: a decision that flips inside the step without changing
+                    # the counted decisions (two contours crossing in opposite directions) gives a jump
+                    # whose slope scales with 1/h
+                    if ok1 and ok2 and abs(f1 - f2) <= 5e-3 * max(abs(f1), abs(f2)):
+                        fd = f1
+                        break
+                if fd is None:
+                    continue
+                assert abs(fd - flat[idx]) <= 1e-2 * abs(flat[idx]), (name, int(idx), h, fd, flat[idx])
+                accepted[name] += 1
+        print(f"{n} Gaussians: accepted finite-difference samples per group:", accepted)
+        assert all(v >= 3 for v in accepted.values()), accepted
