@@ -489,13 +489,34 @@ typedef struct {
   int32_t status;     /* LS_OK, or the error of this pair */
   int32_t iters_done; /* Adam steps of the longest-running view */
   float* exposure;    /* host [vP + vQ][2] or NULL: each view's final (a, b) when exposure is on */
+  int64_t instances_required; /* ls_register_pair, LS_ERR_CAPACITY: tile instances needed (0 if the
+                                 workspace, not the capacity, was short) */
+  int64_t workspace_required; /* ls_register_pair: bytes of workspace the call needed */
 } ls_reg_result;
 
-/* Registers one pair with all 2V views in one launch set per iteration.
- * Blocks until the result is on the host.  Allocates its device buffers for
- * the duration of the call.  Errors: LS_ERR_INVALID (bad sizes, NULL
- * pointers), LS_ERR_NONFINITE (non-finite poses or loss), LS_ERR_HIP. */
-ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg_result* out, hipStream_t s);
+/* Device bytes of the workspace ls_register_pair needs for `pair` with room
+ * for `capacity` tile instances (all views' 16x16-tile lists together).
+ * Host-only: no device work.  Errors: LS_ERR_INVALID (as ls_register_pair,
+ * or capacity outside [0, INT32_MAX]). */
+ls_status ls_register_workspace_size(const ls_pair* pair, const ls_reg_params* prm, int64_t capacity,
+                                     size_t* bytes);
+
+/* Registers one pair (Sec. 3.2: every keyframe of P localised in Q and every
+ * keyframe of Q in P, then the Eq. 7 fusion) with all 2V views in one launch
+ * set per iteration.  Blocks until the result is on the host.  All device
+ * memory of the call is the caller's workspace `work` (work_bytes >=
+ * ls_register_workspace_size(pair, prm, capacity), 256-byte aligned; no
+ * allocation inside the call; contents need no initialisation and are
+ * scratch afterwards); `capacity` bounds the tile instances of all views at
+ * any iteration.  When the lists outgrow it (at the starting poses or during
+ * the optimisation) the call returns LS_ERR_CAPACITY with
+ * out->instances_required set: the caller re-runs with a larger capacity
+ * (with headroom: the count changes as the poses move).  A short workspace
+ * returns LS_ERR_CAPACITY with out->workspace_required set.  Errors:
+ * LS_ERR_INVALID (bad sizes, NULL pointers), LS_ERR_NONFINITE (non-finite
+ * poses or loss), LS_ERR_CAPACITY, LS_ERR_HIP. */
+ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, void* work, size_t work_bytes,
+                           int64_t capacity, ls_reg_result* out, hipStream_t s);
 
 /* Host-only fusion of per-view estimates (Eq. 7 + weighted translation mean):
  * est [n][12] row-major 3x4, resid [n], reverse [n] (1 for a Q->P estimate,
@@ -555,12 +576,17 @@ typedef struct {
 /* Creates a server on the current device with its own worker thread and
  * stream.  Errors: LS_ERR_INVALID (bad parameters), LS_ERR_HIP. */
 ls_status ls_server_create(const ls_server_params* prm, ls_server** out);
-/* Queues a pair (copied; device pointers referenced).  Errors:
+/* Queues a pair (copied; device pointers referenced).  The server reads the
+ * pair's device buffers on its own streams: every read is ordered after the
+ * work queued on `producer` at the time of the call (an event is recorded
+ * there), so buffers still being written on that stream are read complete;
+ * with producer NULL the buffers must already be complete.  Errors:
  * LS_ERR_INVALID (including Adam beta1/beta2/eps different from the first
  * request the server saw), LS_ERR_NONFINITE (non-finite keyframe poses or
- * Gaussian parameters; checked on the device before queueing),
- * LS_ERR_BUDGET (the pair alone exceeds the budget). */
-ls_status ls_register_submit(ls_server* sv, const ls_pair* pair, const ls_reg_params* prm, uint64_t* ticket);
+ * Gaussian parameters; checked on the device before queueing, after the
+ * producer's work), LS_ERR_BUDGET (the pair alone exceeds the budget). */
+ls_status ls_register_submit(ls_server* sv, const ls_pair* pair, const ls_reg_params* prm, hipStream_t producer,
+                             uint64_t* ticket);
 /* LS_NOT_READY while the ticket runs; otherwise fills `out` (per_view_T and
  * residual when non-NULL) and `times` (double [3] or NULL: seconds from
  * submit to admission, admission to completion, submit to completion),

@@ -107,15 +107,6 @@ ls_status ensure_device(const ls_batch* b) {
   return LS_OK;
 }
 
-template <typename T>
-ls_status upload(T** dst, const std::vector<T>& src) {
-  if (hipMalloc(reinterpret_cast<void**>(dst), std::max<size_t>(src.size() * sizeof(T), 16)) != hipSuccess)
-    return fail(LS_ERR_HIP, "hipMalloc of a batch table failed");
-  if (!src.empty() && hipMemcpy(*dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice) != hipSuccess)
-    return fail(LS_ERR_HIP, "upload of a batch table failed");
-  return LS_OK;
-}
-
 ls_status check_projected(const ls_projected* p, bool need_aux = false) {
   if (!p || !p->rec || !p->radius || !p->tiles) return fail(LS_ERR_INVALID, "ls_projected has NULL members");
   if (reinterpret_cast<uintptr_t>(p->rec) % 16) return fail(LS_ERR_INVALID, "ls_projected.rec must be 16-byte aligned");
@@ -186,36 +177,38 @@ ls_status batch_loss_tracking(const ls_batch* b, const ls_image* pred, const ls_
                     b->loss_part_d, loss, grad_scale, s);
   return hip_check("tracking loss over per-render targets");
 }
-}  // namespace ls
 
-extern "C" {
+// Device tables of a batch, in the order they are carved from one region.
+struct BatchTables {
+  size_t jobs, item_off, tile_off, blk_off, pblk_off, sblk_off, loss_part, map_part, grads, sel, median, total;
+};
 
-const char* ls_last_error(void) { return g_err.c_str(); }
-
-int32_t ls_version(void) { return 100; }
-
-int64_t ls_struct_size(const char* name) {
-  if (!name) return -1;
-  struct Entry { const char* n; size_t s; };
-  static const Entry table[] = {
-      {"ls_gaussians", sizeof(ls_gaussians)},       {"ls_intrinsics", sizeof(ls_intrinsics)},
-      {"ls_render_job", sizeof(ls_render_job)},     {"ls_batch_info", sizeof(ls_batch_info)},
-      {"ls_projected", sizeof(ls_projected)},       {"ls_bins", sizeof(ls_bins)},
-      {"ls_image", sizeof(ls_image)},               {"ls_image_grad", sizeof(ls_image_grad)},
-      {"ls_gaussian_grads", sizeof(ls_gaussian_grads)}, {"ls_adam_group", sizeof(ls_adam_group)},
-      {"ls_pair", sizeof(ls_pair)},                 {"ls_reg_params", sizeof(ls_reg_params)},
-      {"ls_reg_result", sizeof(ls_reg_result)},     {"ls_server_params", sizeof(ls_server_params)},
-      {"ls_server_stats", sizeof(ls_server_stats)}, {"ls_loss_params", sizeof(ls_loss_params)},
-      {"ls_mapping_params", sizeof(ls_mapping_params)},
-      {"ls_submap_adjust", sizeof(ls_submap_adjust)},
+static BatchTables batch_tables(const ls_batch* b) {
+  BatchTables t{};
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off = align256(off + std::max<size_t>(bytes, 16));
+    return o;
   };
-  for (const Entry& e : table)
-    if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
-  return -1;
+  const size_t R1 = (size_t)b->R + 1;
+  t.jobs = take(sizeof(JobDev) * b->R);
+  t.item_off = take(8 * R1);
+  t.tile_off = take(4 * R1);
+  t.blk_off = take(4 * R1);
+  t.pblk_off = take(4 * R1);
+  t.sblk_off = take(4 * R1);
+  t.loss_part = take(8 * (size_t)std::max(b->nblk_pix, 1));
+  t.map_part = take(4 * (3 * (size_t)b->nblk_ssim + b->R));
+  t.grads = take(sizeof(GradDev) * b->R);
+  t.sel = take(4 * (size_t)ls::sel_words(b->R));
+  t.median = take(4 * (size_t)b->R);
+  t.total = off;
+  return t;
 }
 
-ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) {
-  if (!out) return fail(LS_ERR_INVALID, "out is NULL");
+// Host tables of a batch (offsets, job records); no device work.
+static ls_status batch_host(const ls_render_job* jobs, int32_t R, ls_batch** out) {
   *out = nullptr;
   if (!jobs || R < 1) return fail(LS_ERR_INVALID, "need R >= 1 jobs (R = %d)", R);
   auto* b = new ls_batch();
@@ -288,44 +281,106 @@ ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) 
   int bits = 0;
   while (bits < 32 && ((int64_t)1 << bits) < (int64_t)b->T) ++bits;
   b->tile_passes = (bits + kTileDigitBits - 1) / kTileDigitBits;
-  if (hipGetDevice(&b->device) != hipSuccess) {
-    delete b;
-    return fail(LS_ERR_HIP, "hipGetDevice failed");
-  }
-  ls_status st;
-  if ((st = upload(&b->jobs_d, b->jobs_h)) || (st = upload(&b->item_off_d, b->item_off)) ||
-      (st = upload(&b->tile_off_d, b->tile_off)) || (st = upload(&b->blk_off_d, b->blk_off)) ||
-      (st = upload(&b->pblk_off_d, b->pblk_off)) || (st = upload(&b->sblk_off_d, b->sblk_off))) {
-    ls_batch_destroy(b);
-    return st;
-  }
-  if (hipMalloc(reinterpret_cast<void**>(&b->loss_part_d), 8 * std::max(b->nblk_pix, 1)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&b->map_part_d), 4 * (3 * (size_t)b->nblk_ssim + R)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&b->grads_d), sizeof(GradDev) * R) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&b->sel_d), 4 * ls::sel_words(R)) != hipSuccess ||
-      hipMemset(b->sel_d, 0, 4 * ls::sel_words(R)) != hipSuccess ||
-      hipMalloc(reinterpret_cast<void**>(&b->median_d), 4 * (size_t)R) != hipSuccess ||
-      hipMemset(b->median_d, 0, 4 * (size_t)R) != hipSuccess) {
-    ls_batch_destroy(b);
-    return fail(LS_ERR_HIP, "hipMalloc of batch scratch failed");
-  }
   *out = b;
   return LS_OK;
 }
 
+ls_status batch_create_host(const ls_render_job* jobs, int32_t R, ls_batch** out) {
+  if (!out) return fail(LS_ERR_INVALID, "out is NULL");
+  return batch_host(jobs, R, out);
+}
+
+size_t batch_tables_bytes(const ls_batch* b) { return batch_tables(b).total; }
+
+ls_status batch_bind(ls_batch* b, void* mem, size_t mem_bytes, hipStream_t s) {
+  if (hipGetDevice(&b->device) != hipSuccess) return fail(LS_ERR_HIP, "hipGetDevice failed");
+  const BatchTables t = batch_tables(b);
+  char* base = nullptr;
+  if (mem) {
+    if (mem_bytes < t.total || reinterpret_cast<uintptr_t>(mem) % 256)
+      return fail(LS_ERR_CAPACITY, "batch tables need %zu bytes at 256-byte alignment", t.total);
+    base = static_cast<char*>(mem);
+    b->external = true;
+  } else {
+    void* p = nullptr;
+    if (hipMalloc(&p, t.total) != hipSuccess) return fail(LS_ERR_HIP, "hipMalloc of the batch tables failed");
+    base = static_cast<char*>(p);
+  }
+  const int R = b->R;
+  b->dev_base = base;
+  b->jobs_d = reinterpret_cast<JobDev*>(base + t.jobs);
+  b->item_off_d = reinterpret_cast<int64_t*>(base + t.item_off);
+  b->tile_off_d = reinterpret_cast<int32_t*>(base + t.tile_off);
+  b->blk_off_d = reinterpret_cast<int32_t*>(base + t.blk_off);
+  b->pblk_off_d = reinterpret_cast<int32_t*>(base + t.pblk_off);
+  b->sblk_off_d = reinterpret_cast<int32_t*>(base + t.sblk_off);
+  b->loss_part_d = reinterpret_cast<float*>(base + t.loss_part);
+  b->map_part_d = reinterpret_cast<float*>(base + t.map_part);
+  b->grads_d = reinterpret_cast<GradDev*>(base + t.grads);
+  b->sel_d = reinterpret_cast<uint32_t*>(base + t.sel);
+  b->median_d = reinterpret_cast<float*>(base + t.median);
+  // the host vectors live as long as the batch, so the copies may stay queued on s
+  const bool ok =
+      hipMemcpyAsync(b->jobs_d, b->jobs_h.data(), sizeof(JobDev) * R, hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(b->item_off_d, b->item_off.data(), 8 * (R + 1), hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(b->tile_off_d, b->tile_off.data(), 4 * (R + 1), hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(b->blk_off_d, b->blk_off.data(), 4 * (R + 1), hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(b->pblk_off_d, b->pblk_off.data(), 4 * (R + 1), hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemcpyAsync(b->sblk_off_d, b->sblk_off.data(), 4 * (R + 1), hipMemcpyHostToDevice, s) == hipSuccess &&
+      hipMemsetAsync(b->sel_d, 0, 4 * (size_t)ls::sel_words(R), s) == hipSuccess &&
+      hipMemsetAsync(b->median_d, 0, 4 * (size_t)R, s) == hipSuccess;
+  if (!ok || (!mem && hipStreamSynchronize(s) != hipSuccess))
+    return fail(LS_ERR_HIP, "upload of the batch tables failed");
+  return LS_OK;
+}
+
+ls_status batch_create(const ls_render_job* jobs, int32_t R, void* mem, size_t mem_bytes, hipStream_t s,
+                       ls_batch** out) {
+  ls_batch* b = nullptr;
+  ls_status st = batch_create_host(jobs, R, &b);
+  if (st) return st;
+  if ((st = batch_bind(b, mem, mem_bytes, s))) {
+    ls_batch_destroy(b);
+    return st;
+  }
+  *out = b;
+  return LS_OK;
+}
+}  // namespace ls
+
+extern "C" {
+
+const char* ls_last_error(void) { return g_err.c_str(); }
+
+int32_t ls_version(void) { return 100; }
+
+int64_t ls_struct_size(const char* name) {
+  if (!name) return -1;
+  struct Entry { const char* n; size_t s; };
+  static const Entry table[] = {
+      {"ls_gaussians", sizeof(ls_gaussians)},       {"ls_intrinsics", sizeof(ls_intrinsics)},
+      {"ls_render_job", sizeof(ls_render_job)},     {"ls_batch_info", sizeof(ls_batch_info)},
+      {"ls_projected", sizeof(ls_projected)},       {"ls_bins", sizeof(ls_bins)},
+      {"ls_image", sizeof(ls_image)},               {"ls_image_grad", sizeof(ls_image_grad)},
+      {"ls_gaussian_grads", sizeof(ls_gaussian_grads)}, {"ls_adam_group", sizeof(ls_adam_group)},
+      {"ls_pair", sizeof(ls_pair)},                 {"ls_reg_params", sizeof(ls_reg_params)},
+      {"ls_reg_result", sizeof(ls_reg_result)},     {"ls_server_params", sizeof(ls_server_params)},
+      {"ls_server_stats", sizeof(ls_server_stats)}, {"ls_loss_params", sizeof(ls_loss_params)},
+      {"ls_mapping_params", sizeof(ls_mapping_params)},
+      {"ls_submap_adjust", sizeof(ls_submap_adjust)},
+  };
+  for (const Entry& e : table)
+    if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
+  return -1;
+}
+
+ls_status ls_batch_create(const ls_render_job* jobs, int32_t R, ls_batch** out) {
+  return ls::batch_create(jobs, R, nullptr, 0, nullptr, out);
+}
+
 ls_status ls_batch_destroy(ls_batch* b) {
   if (!b) return LS_OK;
-  hipFree(b->jobs_d);
-  hipFree(b->item_off_d);
-  hipFree(b->tile_off_d);
-  hipFree(b->blk_off_d);
-  hipFree(b->pblk_off_d);
-  hipFree(b->sblk_off_d);
-  hipFree(b->map_part_d);
-  hipFree(b->loss_part_d);
-  hipFree(b->sel_d);
-  hipFree(b->median_d);
-  hipFree(b->grads_d);
+  if (!b->external && b->dev_base) hipFree(b->dev_base);
   delete b;
   return LS_OK;
 }

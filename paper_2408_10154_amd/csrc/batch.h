@@ -33,9 +33,22 @@ struct ls_batch {
   float* median_d = nullptr;     // [R] median depth error of the last tracking loss
   GradDev* grads_d = nullptr;
   std::vector<GradDev> grads_cached;
+  char* dev_base = nullptr;  // one region holding every device table above
+  bool external = false;     // the region belongs to the caller (not freed with the batch)
 };
 
 namespace ls {
+// A batch whose device tables are carved from `mem` (mem_bytes >= its
+// batch_tables_bytes, 256-byte aligned; the caller keeps it until
+// ls_batch_destroy) with the uploads queued on s, or allocated by the batch
+// when mem is NULL (then s may be NULL and the call synchronises).
+ls_status batch_create(const ls_render_job* jobs, int32_t R, void* mem, size_t mem_bytes, hipStream_t s,
+                       ls_batch** out);
+// The same in two steps: the host tables (no device work; sizes and
+// ls_batch_query are available), then the device tables.
+ls_status batch_create_host(const ls_render_job* jobs, int32_t R, ls_batch** out);
+size_t batch_tables_bytes(const ls_batch* b);
+ls_status batch_bind(ls_batch* b, void* mem, size_t mem_bytes, hipStream_t s);
 // Points every render's loss at its own measurements (device [3][H][W] and
 // [H][W]); re-uploads the job table.  Used by engines that do not lay the
 // targets out contiguously.

@@ -94,8 +94,13 @@ __global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ grad, 
   }
 }
 
+// sticky[0] |= overflow; sticky[1] keeps the instance count required at the
+// first overflow (the pose before any step taken on truncated lists).
 __global__ void k_or_flag(const int32_t* __restrict__ count, int32_t* __restrict__ sticky) {
-  if (threadIdx.x == 0 && count[1] != 0) *sticky = 1;
+  if (threadIdx.x == 0 && count[1] != 0) {
+    if (sticky[0] == 0) sticky[1] = count[2];
+    sticky[0] = 1;
+  }
 }
 
 void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s) {

@@ -192,13 +192,11 @@ RegEngine::~RegEngine() { release(); }
 void RegEngine::release() {
   if (batch) ls_batch_destroy(batch);
   batch = nullptr;
-  if (arena) hipFree(arena);
-  arena = nullptr;
-  if (bins_mem) hipFree(bins_mem);
-  bins_mem = nullptr;
 }
 
-ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) {
+// Host side of an engine: one render job per view (a keyframe of one submap
+// rendering the other), the host batch tables and the workspace layout.
+ls_status RegEngine::prepare(const std::vector<RegPair>& pairs_in) {
   release();
   pairs = pairs_in;
   std::vector<ls_render_job> jobs;
@@ -228,7 +226,7 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   }
   first_view[pairs.size()] = (int)jobs.size();
   R = (int)jobs.size();
-  ls_status st = ls_batch_create(jobs.data(), R, &batch);
+  ls_status st = batch_create_host(jobs.data(), R, &batch);
   if (st) return st;
   ls_batch_info info{};
   ls_batch_query(batch, 0, &info);
@@ -237,53 +235,102 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   T = info.tiles;
   pix_off.assign(R + 1, 0);
   ls_batch_offsets(batch, nullptr, pix_off.data(), nullptr);
+  return LS_OK;
+}
 
-  // one arena for everything that does not depend on the instance capacity
+// Workspace layout for an instance capacity: the batch's device tables, the
+// per-item / per-pixel / per-view arena, the two instance arrays and the bins
+// workspace, each piece 256-byte aligned.
+RegEngine::Layout RegEngine::layout(int64_t cap) const {
+  Layout L{};
   size_t off = 0;
   auto take = [&](size_t bytes) { const size_t o = off; off = (off + std::max<size_t>(bytes, 4) + 255) & ~size_t(255); return o; };
-  const size_t o_rec = take(48 * (size_t)std::max<int64_t>(M, 1)), o_rad = take(4 * M), o_til = take(4 * M);
-  const size_t o_aux = take(48 * (size_t)std::max<int64_t>(M, 1));
-  const size_t o_rgb = take(12 * P), o_dep = take(4 * P), o_alp = take(4 * P), o_T = take(4 * P), o_nl = take(4 * P);
-  const size_t o_trgb = take(12 * P), o_tdep = take(4 * P), o_grgb = take(12 * P), o_gdep = take(4 * P);
-  const size_t o_scale = take(4 * R), o_loss = take(4 * R), o_pose = take(28 * R), o_pg = take(28 * R);
-  const size_t o_m = take(28 * R), o_v = take(28 * R), o_opt = take(sizeof(ViewOpt) * R), o_range = take(8 * (size_t)T);
-  const size_t o_count = take(16), o_sticky = take(4);
-  const bool with_expo = pairs[0].prm.exposure != 0;
-  const int32_t nblk_pix = batch->nblk_pix;
-  const size_t o_expo = with_expo ? take(4 * (8 * (size_t)R + 2 * (size_t)nblk_pix)) : 0;
-  if (hipMalloc(&arena, off) != hipSuccess) return LS_ERR_HIP;
-  char* a = static_cast<char*>(arena);
-  proj.rec = reinterpret_cast<float*>(a + o_rec);
-  proj.radius = reinterpret_cast<int32_t*>(a + o_rad);
-  proj.tiles = reinterpret_cast<int32_t*>(a + o_til);
-  proj.aux = reinterpret_cast<float*>(a + o_aux);
-  img.rgb = reinterpret_cast<float*>(a + o_rgb);
-  img.depth = reinterpret_cast<float*>(a + o_dep);
-  img.alpha = reinterpret_cast<float*>(a + o_alp);
-  img.T_final = reinterpret_cast<float*>(a + o_T);
-  img.n_last = reinterpret_cast<int32_t*>(a + o_nl);
-  tgt_rgb = reinterpret_cast<float*>(a + o_trgb);
-  tgt_depth = reinterpret_cast<float*>(a + o_tdep);
-  g_rgb = reinterpret_cast<float*>(a + o_grgb);
-  g_depth = reinterpret_cast<float*>(a + o_gdep);
-  scale = reinterpret_cast<float*>(a + o_scale);
-  loss = reinterpret_cast<float*>(a + o_loss);
-  pose = reinterpret_cast<float*>(a + o_pose);
-  pose_grad = reinterpret_cast<float*>(a + o_pg);
-  adam_m = reinterpret_cast<float*>(a + o_m);
-  adam_v = reinterpret_cast<float*>(a + o_v);
-  opt = reinterpret_cast<ViewOpt*>(a + o_opt);
-  range = reinterpret_cast<int32_t*>(a + o_range);
-  count = reinterpret_cast<int32_t*>(a + o_count);
-  sticky = reinterpret_cast<int32_t*>(a + o_sticky);
-  if (with_expo) {
-    expo = reinterpret_cast<float*>(a + o_expo);
+  L.tables = take(batch_tables_bytes(batch));
+  L.rec = take(48 * (size_t)std::max<int64_t>(M, 1));
+  L.rad = take(4 * M);
+  L.til = take(4 * M);
+  L.aux = take(48 * (size_t)std::max<int64_t>(M, 1));
+  L.rgb = take(12 * P);
+  L.dep = take(4 * P);
+  L.alp = take(4 * P);
+  L.Tf = take(4 * P);
+  L.nl = take(4 * P);
+  L.trgb = take(12 * P);
+  L.tdep = take(4 * P);
+  L.grgb = take(12 * P);
+  L.gdep = take(4 * P);
+  L.scale = take(4 * R);
+  L.loss = take(4 * R);
+  L.pose = take(28 * R);
+  L.pg = take(28 * R);
+  L.m = take(28 * R);
+  L.v = take(28 * R);
+  L.opt = take(sizeof(ViewOpt) * R);
+  L.range = take(8 * (size_t)T);
+  L.count = take(16);
+  L.sticky = take(8);
+  L.expo = pairs[0].prm.exposure ? take(4 * (8 * (size_t)R + 2 * (size_t)batch->nblk_pix)) : 0;
+  L.zero_end = off;  // everything above starts at zero
+  L.tile_of = take(4 * (size_t)cap);
+  L.item = take(4 * (size_t)cap);
+  ls_batch_info info{};
+  ls_batch_query(batch, cap, &info);
+  L.work = take(info.workspace_bytes);
+  L.total = off;
+  return L;
+}
+
+size_t RegEngine::workspace_bytes(int64_t cap) const { return layout(cap).total; }
+
+// Device side: carves the caller's workspace, uploads the tables, copies the
+// keyframe targets, clears the state and starts every view at identity.
+ls_status RegEngine::bind(void* work, size_t work_bytes, int64_t cap, hipStream_t s) {
+  const Layout L = layout(cap);
+  if (!work || work_bytes < L.total || reinterpret_cast<uintptr_t>(work) % 256) return LS_ERR_CAPACITY;
+  char* a = static_cast<char*>(work);
+  ls_status st = batch_bind(batch, a + L.tables, L.rec - L.tables, s);
+  if (st) return st;
+  proj.rec = reinterpret_cast<float*>(a + L.rec);
+  proj.radius = reinterpret_cast<int32_t*>(a + L.rad);
+  proj.tiles = reinterpret_cast<int32_t*>(a + L.til);
+  proj.aux = reinterpret_cast<float*>(a + L.aux);
+  img.rgb = reinterpret_cast<float*>(a + L.rgb);
+  img.depth = reinterpret_cast<float*>(a + L.dep);
+  img.alpha = reinterpret_cast<float*>(a + L.alp);
+  img.T_final = reinterpret_cast<float*>(a + L.Tf);
+  img.n_last = reinterpret_cast<int32_t*>(a + L.nl);
+  tgt_rgb = reinterpret_cast<float*>(a + L.trgb);
+  tgt_depth = reinterpret_cast<float*>(a + L.tdep);
+  g_rgb = reinterpret_cast<float*>(a + L.grgb);
+  g_depth = reinterpret_cast<float*>(a + L.gdep);
+  scale = reinterpret_cast<float*>(a + L.scale);
+  loss = reinterpret_cast<float*>(a + L.loss);
+  pose = reinterpret_cast<float*>(a + L.pose);
+  pose_grad = reinterpret_cast<float*>(a + L.pg);
+  adam_m = reinterpret_cast<float*>(a + L.m);
+  adam_v = reinterpret_cast<float*>(a + L.v);
+  opt = reinterpret_cast<ViewOpt*>(a + L.opt);
+  range = reinterpret_cast<int32_t*>(a + L.range);
+  count = reinterpret_cast<int32_t*>(a + L.count);
+  sticky = reinterpret_cast<int32_t*>(a + L.sticky);
+  if (pairs[0].prm.exposure) {
+    expo = reinterpret_cast<float*>(a + L.expo);
     expo_grad = expo + 2 * R;
     expo_m = expo + 4 * R;
     expo_v = expo + 6 * R;
     expo_part = expo + 8 * R;
   }
-  if (hipMemsetAsync(arena, 0, off, s) != hipSuccess) return LS_ERR_HIP;  // also a = b = 0 and their moments
+  bins.capacity = cap;
+  bins.tile_of = reinterpret_cast<uint32_t*>(a + L.tile_of);
+  bins.item = reinterpret_cast<int32_t*>(a + L.item);
+  bins.range = range;
+  bins.count = count;
+  bins.work = a + L.work;
+  capacity = cap;
+  // the state (a = b = 0 and their moments included) and the bins workspace start at zero
+  if (hipMemsetAsync(a + L.rec, 0, L.zero_end - L.rec, s) != hipSuccess ||
+      hipMemsetAsync(a + L.work, 0, L.total - L.work, s) != hipSuccess)
+    return LS_ERR_HIP;
 
   // targets: each view's measurements, laid out like the batch's images
   for (int r = 0; r < R; ++r) {
@@ -312,42 +359,14 @@ ls_status RegEngine::build(const std::vector<RegPair>& pairs_in, hipStream_t s) 
   return hip_ok();
 }
 
-ls_status RegEngine::alloc_bins(int64_t cap) {
-  if (bins_mem) hipFree(bins_mem);
-  bins_mem = nullptr;
-  ls_batch_info info{};
-  ls_status st = ls_batch_query(batch, cap, &info);
-  if (st) return st;
-  const size_t o_tile = 0, o_item = (4 * cap + 255) & ~size_t(255);
-  const size_t o_work = (o_item + 4 * cap + 255) & ~size_t(255);
-  const size_t total = o_work + info.workspace_bytes;
-  if (hipMalloc(&bins_mem, total) != hipSuccess) return LS_ERR_HIP;
-  if (hipMemset(bins_mem, 0, total) != hipSuccess) return LS_ERR_HIP;
-  char* b = static_cast<char*>(bins_mem);
-  bins.capacity = cap;
-  bins.tile_of = reinterpret_cast<uint32_t*>(b + o_tile);
-  bins.item = reinterpret_cast<int32_t*>(b + o_item);
-  bins.range = range;
-  bins.count = count;
-  bins.work = b + o_work;
-  capacity = cap;
-  return LS_OK;
-}
-
-ls_status RegEngine::size_capacity(hipStream_t s, double headroom) {
+// Bins every view at its current pose and reads the instance count back:
+// {kept, overflow, required, 0}.
+ls_status RegEngine::measure(hipStream_t s, int32_t* hc) {
   ls_status st;
-  int64_t cap = std::max<int64_t>(4096, 6 * M);
-  for (int attempt = 0; attempt < 3; ++attempt) {
-    if ((st = alloc_bins(cap))) return st;
-    if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
-    int32_t hc[4];
-    if (hipMemcpyAsync(hc, count, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-      return LS_ERR_HIP;
-    const int64_t want = std::min<int64_t>((int64_t)INT32_MAX, std::max<int64_t>(4096, (int64_t)(hc[2] * headroom)));
-    if (hc[1] == 0) return want > cap ? alloc_bins(want) : LS_OK;
-    cap = want;  // overflow: re-bin with the required count plus headroom
-  }
-  return LS_ERR_CAPACITY;
+  if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
+  if (hipMemcpyAsync(hc, count, 16, hipMemcpyDeviceToHost, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+    return LS_ERR_HIP;
+  return LS_OK;
 }
 
 ls_status RegEngine::step(hipStream_t s) {
@@ -463,7 +482,7 @@ ls_status RegEngine::readback(std::vector<float>& pose_h, std::vector<float>& lo
   loss_h.resize(R);
   if (hipMemcpyAsync(pose_h.data(), pose, 28 * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipMemcpyAsync(loss_h.data(), loss, 4 * R, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemcpyAsync(overflow, sticky, 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipMemcpyAsync(overflow, sticky, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return LS_ERR_HIP;
   return LS_OK;
@@ -553,88 +572,97 @@ ls_status ls_fuse_estimates(const double* est, const double* resid, const int32_
   return fuse_estimates(est, resid, reverse, n, out);
 }
 
-ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, ls_reg_result* out, hipStream_t s) {
+ls_status ls_register_workspace_size(const ls_pair* pair, const ls_reg_params* prm, int64_t capacity,
+                                     size_t* bytes) {
+  if (!bytes || capacity < 0 || capacity > INT32_MAX) return LS_ERR_INVALID;
+  *bytes = 0;
+  ls_status st = validate_pair(pair, prm);
+  if (st) return st;
+  RegEngine e;
+  if ((st = e.prepare({make_reg_pair(pair, prm)}))) return st;
+  *bytes = e.workspace_bytes(capacity);
+  return LS_OK;
+}
+
+ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, void* work, size_t work_bytes,
+                           int64_t capacity, ls_reg_result* out, hipStream_t s) {
   if (!out) return LS_ERR_INVALID;
+  out->status = LS_ERR_INVALID;
+  out->iters_done = 0;
+  out->instances_required = 0;
+  out->workspace_required = 0;
+  if (capacity < 0 || capacity > INT32_MAX) return LS_ERR_INVALID;
   ls_status st = validate_pair(pair, prm);
   out->status = st;
-  out->iters_done = 0;
   if (st) return st;
-  std::vector<RegPair> v{make_reg_pair(pair, prm)};
-  double headroom = 1.5;
-  for (int attempt = 0; attempt < 2; ++attempt) {
-    RegEngine e;
-    if ((st = e.build(v, s)) || (st = e.size_capacity(s, headroom))) {
-      out->status = st;
-      return st;
-    }
-    int done = 0;
-    constexpr int kCheckEvery = 16;  // early exit: poll the views' active flags this often
-    if (prm->joint) {
-      for (; done < prm->iters; ++done)
-        if ((st = e.step_joint(s))) {
-          out->status = st;
-          return st;
-        }
-      if ((st = e.upload_joint_poses(s))) {  // the final forward sees the final T
-        out->status = st;
-        return st;
-      }
-    }
-    while (done < prm->iters) {
-      const int k = prm->exit_patience > 0 ? std::min(kCheckEvery, prm->iters - done) : prm->iters - done;
-      for (int it = 0; it < k; ++it)
-        if ((st = e.step(s))) {
-          out->status = st;
-          return st;
-        }
-      done += k;
-      if (prm->exit_patience > 0 && done < prm->iters) {
-        std::vector<ViewOpt> ho(e.R);
-        if (hipMemcpyAsync(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost, s) != hipSuccess ||
-            hipStreamSynchronize(s) != hipSuccess) {
-          out->status = LS_ERR_HIP;
-          return LS_ERR_HIP;
-        }
-        bool any = false;
-        for (const ViewOpt& o : ho) any |= o.active != 0;
-        if (!any) break;
-      }
-    }
-    std::vector<float> ph, lh;
-    int32_t ovf = 0;
-    if ((st = e.final_forward(s)) || (st = e.readback(ph, lh, &ovf, s))) {
-      out->status = st;
-      return st;
-    }
-    if (ovf) {  // the instance count outgrew the headroom during optimisation: redo with more
-      headroom *= 2.0;
-      continue;
-    }
-    st = e.fuse_pair(0, ph, lh, out);
-    if (!st) st = e.read_exposure(0, out, s);
-    if (!st && prm->joint) {  // the shared T is the estimate (no fusion)
-      double T[12], Rm[9];
-      rot_of_quat(&e.joint_T[0], Rm);
-      for (int i = 0; i < 3; ++i) {
-        for (int j = 0; j < 3; ++j) T[i * 4 + j] = Rm[i * 3 + j];
-        T[i * 4 + 3] = e.joint_T[4 + i];
-      }
-      for (int q = 0; q < 12; ++q) out->T_PQ[q] = (float)T[q];
-    }
-    out->status = st;
-    if (prm->joint) {
-      out->iters_done = e.joint_step;
-      return st;
-    }
-    std::vector<ViewOpt> ho(e.R);
-    hipMemcpy(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost);
-    int steps = 0;
-    for (const ViewOpt& o : ho) steps = std::max(steps, o.step);
-    out->iters_done = steps;
-    return st;
+  auto finish = [&](ls_status code) {
+    out->status = code;
+    return code;
+  };
+  RegEngine e;
+  if ((st = e.prepare({make_reg_pair(pair, prm)}))) return finish(st);
+  out->workspace_required = (int64_t)e.workspace_bytes(capacity);
+  if (!work || work_bytes < (size_t)out->workspace_required || reinterpret_cast<uintptr_t>(work) % 256)
+    return finish(LS_ERR_CAPACITY);
+  if ((st = e.bind(work, work_bytes, capacity, s))) return finish(st);
+  int32_t hc[4];
+  if ((st = e.measure(s, hc))) return finish(st);
+  if (hc[1]) {  // the lists at the starting poses do not fit
+    out->instances_required = hc[2];
+    return finish(LS_ERR_CAPACITY);
   }
-  out->status = LS_ERR_CAPACITY;
-  return LS_ERR_CAPACITY;
+  int done = 0;
+  constexpr int kCheckEvery = 16;  // early exit: poll the views' active flags this often
+  if (prm->joint) {
+    for (; done < prm->iters; ++done)
+      if ((st = e.step_joint(s))) return finish(st);
+    if ((st = e.upload_joint_poses(s))) return finish(st);  // the final forward sees the final T
+  }
+  while (done < prm->iters) {
+    const int k = prm->exit_patience > 0 ? std::min(kCheckEvery, prm->iters - done) : prm->iters - done;
+    for (int it = 0; it < k; ++it)
+      if ((st = e.step(s))) return finish(st);
+    done += k;
+    if (prm->exit_patience > 0 && done < prm->iters) {
+      std::vector<ViewOpt> ho(e.R);
+      if (hipMemcpyAsync(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return finish(LS_ERR_HIP);
+      bool any = false;
+      for (const ViewOpt& o : ho) any |= o.active != 0;
+      if (!any) break;
+    }
+  }
+  std::vector<float> ph, lh;
+  int32_t ovf[2] = {0, 0};
+  if ((st = e.final_forward(s)) || (st = e.readback(ph, lh, ovf, s))) return finish(st);
+  if (ovf[0]) {  // the instance count outgrew the capacity during the optimisation
+    out->instances_required = ovf[1];
+    return finish(LS_ERR_CAPACITY);
+  }
+  st = e.fuse_pair(0, ph, lh, out);
+  if (!st) st = e.read_exposure(0, out, s);
+  if (!st && prm->joint) {  // the shared T is the estimate (no fusion)
+    double T[12], Rm[9];
+    rot_of_quat(&e.joint_T[0], Rm);
+    for (int i = 0; i < 3; ++i) {
+      for (int j = 0; j < 3; ++j) T[i * 4 + j] = Rm[i * 3 + j];
+      T[i * 4 + 3] = e.joint_T[4 + i];
+    }
+    for (int q = 0; q < 12; ++q) out->T_PQ[q] = (float)T[q];
+  }
+  if (prm->joint) {
+    out->iters_done = e.joint_step;
+    return finish(st);
+  }
+  std::vector<ViewOpt> ho(e.R);
+  if (hipMemcpyAsync(ho.data(), e.opt, sizeof(ViewOpt) * e.R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return finish(LS_ERR_HIP);
+  int steps = 0;
+  for (const ViewOpt& o : ho) steps = std::max(steps, o.step);
+  out->iters_done = steps;
+  return finish(st);
 }
 
 }  // extern "C"

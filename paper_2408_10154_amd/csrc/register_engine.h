@@ -25,12 +25,16 @@ struct View {
 class RegEngine {
  public:
   ~RegEngine();
-  ls_status build(const std::vector<RegPair>& pairs, hipStream_t s);
-  ls_status size_capacity(hipStream_t s, double headroom);
-  ls_status alloc_bins(int64_t cap);
+  // Host tables of the pairs' views (no device work), then the device state
+  // in a caller workspace of workspace_bytes(capacity) bytes.
+  ls_status prepare(const std::vector<RegPair>& pairs);
+  size_t workspace_bytes(int64_t capacity) const;
+  ls_status bind(void* work, size_t work_bytes, int64_t capacity, hipStream_t s);
+  ls_status measure(hipStream_t s, int32_t* count4);
   ls_status step(hipStream_t s);
   ls_status final_forward(hipStream_t s);
   ls_status view_loss(hipStream_t s);  // the loss the pair's parameters select
+  // overflow[2]: {any overflow since bind, instances required at the first one}
   ls_status readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow, hipStream_t s);
   ls_status fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h, ls_reg_result* out);
   ls_status read_exposure(int p, ls_reg_result* out, hipStream_t s);
@@ -49,8 +53,6 @@ class RegEngine {
   int R = 0, T = 0;
   int64_t M = 0, P = 0, capacity = 0;
   ls_batch* batch = nullptr;
-  void* arena = nullptr;
-  void* bins_mem = nullptr;
   ls_projected proj{};
   ls_bins bins{};
   ls_image img{};
@@ -64,6 +66,11 @@ class RegEngine {
   int32_t *range = nullptr, *count = nullptr, *sticky = nullptr;
 
  private:
+  struct Layout {
+    size_t tables, rec, rad, til, aux, rgb, dep, alp, Tf, nl, trgb, tdep, grgb, gdep, scale, loss, pose, pg, m, v,
+        opt, range, count, sticky, expo, zero_end, tile_of, item, work, total;
+  };
+  Layout layout(int64_t capacity) const;
   static ls_status hip_ok();
 };
 

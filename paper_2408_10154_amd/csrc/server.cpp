@@ -70,6 +70,11 @@ struct Slot {
   float T[12] = {0};
   std::vector<float> per_view, resid, expo;  // expo: (a, b) per view when exposure is on
   Clock::time_point t_submit, t_admit, t_done;
+  hipEvent_t ready = nullptr;  // recorded on the producer stream at submit; the worker waits on it
+  bool waited = false;
+  ~Slot() {
+    if (ready) hipEventDestroy(ready);
+  }
 };
 
 // Device bytes the server allocates per item / pixel / expected instance.
@@ -103,11 +108,12 @@ class Server {
   }
 
   // Device-side check that every Gaussian parameter of the pair is finite.
-  ls_status check_finite(const ls_pair* p) {
+  ls_status check_finite(const ls_pair* p, hipEvent_t ready) {
     std::lock_guard<std::mutex> g(check_mu_);
     int cur = -1;
     hipGetDevice(&cur);
     if (cur != device_) hipSetDevice(device_);
+    if (ready && hipStreamWaitEvent(check_stream_, ready, 0) != hipSuccess) return LS_ERR_HIP;
     int32_t* flag = check_buf_.as<int32_t>();
     launch_fill_i32(flag, 1, 0, check_stream_);
     for (const ls_gaussians* gs : {&p->P, &p->Q}) {
@@ -127,7 +133,7 @@ class Server {
     return h == 0 ? LS_OK : LS_ERR_NONFINITE;
   }
 
-  ls_status submit(const ls_pair* pair, const ls_reg_params* prm, uint64_t* ticket) {
+  ls_status submit(const ls_pair* pair, const ls_reg_params* prm, hipStream_t producer, uint64_t* ticket) {
     ls_status st = validate_pair(pair, prm);
     if (st) return st;
     if (prm->joint) return LS_ERR_INVALID;  // joint registration: ls_register_pair only
@@ -154,8 +160,12 @@ class Server {
         return LS_ERR_INVALID;
       }
     }
-    if ((st = check_finite(pair))) return st;
     auto s = std::make_unique<Slot>();
+    if (producer) {  // order every read of the pair's buffers after the work queued on the producer
+      if (hipEventCreateWithFlags(&s->ready, hipEventDisableTiming) != hipSuccess) return LS_ERR_HIP;
+      if (hipEventRecord(s->ready, producer) != hipSuccess) return LS_ERR_HIP;
+    }
+    if ((st = check_finite(pair, s->ready))) return st;
     s->rp = make_reg_pair(pair, prm);
     s->views = pair->vP + pair->vQ;
     s->items = (int64_t)pair->vP * pair->Q.n + (int64_t)pair->vQ * pair->P.n;
@@ -187,6 +197,8 @@ class Server {
       if (out->exposure && !s->expo.empty()) std::memcpy(out->exposure, s->expo.data(), 4 * s->expo.size());
       out->status = s->status;
       out->iters_done = s->iters_done;
+      out->instances_required = 0;
+      out->workspace_required = 0;
     }
     if (times) {
       times[0] = seconds_since(s->t_submit, s->t_admit);
@@ -254,6 +266,9 @@ class Server {
       Slot* s = waiting_.front();
       if (active_bytes_ + s->bytes > prm_.hbm_budget_bytes) break;
       if (prm_.max_active_pixels > 0 && !active_.empty() && active_pixels_ + s->pixels > prm_.max_active_pixels) break;
+      // the tile lists of one launch set are indexed in int32: hold the head back while the
+      // active set's expected instance count would pass that (a pair alone is always admitted)
+      if (!active_.empty() && (double)(active_items_ + s->items) * kInstancesPerItem > (double)INT32_MAX) break;
       waiting_.pop_front();
       s->state = SlotState::kActive;
       s->t_admit = Clock::now();
@@ -261,6 +276,7 @@ class Server {
       active_.push_back(s);
       active_bytes_ += s->bytes;
       active_pixels_ += s->pixels;
+      active_items_ += s->items;
       stats_.peak_bytes = std::max<int64_t>(stats_.peak_bytes, (int64_t)active_bytes_);
       stats_.peak_active = std::max<int32_t>(stats_.peak_active, (int32_t)active_.size());
       changed = true;
@@ -278,6 +294,11 @@ class Server {
     if (exec_) hipGraphExecDestroy(exec_);
     exec_ = nullptr;
     if (active_.empty()) return LS_OK;
+    for (Slot* s : active_)  // a new pair's buffers are read only after its producer's work
+      if (s->ready && !s->waited) {
+        if (hipStreamWaitEvent(stream_, s->ready, 0) != hipSuccess) return LS_ERR_HIP;
+        s->waited = true;
+      }
     std::vector<ls_render_job> jobs;
     std::vector<const float*> trgb, tdep;
     std::vector<int32_t> map;
@@ -543,7 +564,10 @@ class Server {
 
   // Final forward at the current poses, readback, fusion of finished pairs.
   // The residual of a view is the unmasked L1 there, as in ls_register_pair.
-  void retire() {
+  // An overflow of the residual forward grows the capacity and retries, at
+  // most kRetireAttempts times.
+  static constexpr int kRetireAttempts = 3;
+  void retire(int attempt = 0) {
     const StatePtrs s = state_ptrs(stateA_, R_);
     ls_status st;
     if ((st = ls_project(batch_, s.pose, &proj_, stream_)) || (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)) ||
@@ -570,11 +594,12 @@ class Server {
         ++stats_.overflow_retries;
       }
       const int64_t want = std::min<int64_t>((int64_t)INT32_MAX, (int64_t)(hc[2] * 1.25) + 4096);
-      if (set_capacity(want) || (prm_.use_graphs && capture())) {
+      if (attempt + 1 >= kRetireAttempts || want <= capacity_ || set_capacity(want) ||
+          (prm_.use_graphs && capture())) {
         fail_active(LS_ERR_CAPACITY);
         return;
       }
-      retire();
+      retire(attempt + 1);
       return;
     }
     std::vector<Slot*> keep;
@@ -587,6 +612,7 @@ class Server {
       finish_slot(sl, pose_h, loss_h, expo_h);
       active_bytes_ -= sl->bytes;
       active_pixels_ -= sl->pixels;
+      active_items_ -= sl->items;
     }
     active_.swap(keep);
     rebuild_pending_ = true;
@@ -633,6 +659,7 @@ class Server {
       ++stats_.failed;
       active_bytes_ -= sl->bytes;
       active_pixels_ -= sl->pixels;
+      active_items_ -= sl->items;
     }
     active_.clear();
     R_ = 0;
@@ -663,6 +690,7 @@ class Server {
   std::vector<Slot*> active_;
   size_t active_bytes_ = 0;
   int64_t active_pixels_ = 0;
+  int64_t active_items_ = 0;  // rendered Gaussians per iteration of the active set
   ls_server_stats stats_{};
   bool rebuild_pending_ = false;
 
@@ -705,9 +733,10 @@ ls_status ls_server_create(const ls_server_params* prm, ls_server** out) {
   return LS_OK;
 }
 
-ls_status ls_register_submit(ls_server* sv, const ls_pair* pair, const ls_reg_params* prm, uint64_t* ticket) {
+ls_status ls_register_submit(ls_server* sv, const ls_pair* pair, const ls_reg_params* prm, hipStream_t producer,
+                             uint64_t* ticket) {
   if (!sv || !ticket) return LS_ERR_INVALID;
-  return sv->impl->submit(pair, prm, ticket);
+  return sv->impl->submit(pair, prm, producer, ticket);
 }
 
 ls_status ls_register_poll(ls_server* sv, uint64_t ticket, ls_reg_result* out, double* times) {

@@ -103,7 +103,8 @@ class ls_reg_params(C.Structure):
 
 class ls_reg_result(C.Structure):
     _fields_ = [("T_PQ", C.c_float * 12), ("per_view_T", C.c_void_p), ("residual", C.c_void_p),
-                ("status", C.c_int32), ("iters_done", C.c_int32), ("exposure", C.c_void_p)]
+                ("status", C.c_int32), ("iters_done", C.c_int32), ("exposure", C.c_void_p),
+                ("instances_required", C.c_int64), ("workspace_required", C.c_int64)]
 
 
 class ls_server_params(C.Structure):
@@ -161,10 +162,13 @@ _PROTOS = {
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
                             C.c_int32, _P]),
     "ls_fill_i32": (C.c_int32, [_P, C.c_int64, C.c_int32, _P]),
-    "ls_register_pair": (C.c_int32, [C.POINTER(ls_pair), C.POINTER(ls_reg_params), C.POINTER(ls_reg_result), _P]),
+    "ls_register_workspace_size": (C.c_int32, [C.POINTER(ls_pair), C.POINTER(ls_reg_params), C.c_int64,
+                                               C.POINTER(C.c_size_t)]),
+    "ls_register_pair": (C.c_int32, [C.POINTER(ls_pair), C.POINTER(ls_reg_params), _P, C.c_size_t, C.c_int64,
+                                     C.POINTER(ls_reg_result), _P]),
     "ls_fuse_estimates": (C.c_int32, [_P, _P, _P, C.c_int32, _P]),
     "ls_server_create": (C.c_int32, [C.POINTER(ls_server_params), C.POINTER(_P)]),
-    "ls_register_submit": (C.c_int32, [_P, C.POINTER(ls_pair), C.POINTER(ls_reg_params), C.POINTER(C.c_uint64)]),
+    "ls_register_submit": (C.c_int32, [_P, C.POINTER(ls_pair), C.POINTER(ls_reg_params), _P, C.POINTER(C.c_uint64)]),
     "ls_register_poll": (C.c_int32, [_P, C.c_uint64, C.POINTER(ls_reg_result), _P]),
     "ls_server_get_stats": (C.c_int32, [_P, C.POINTER(ls_server_stats)]),
     "ls_server_destroy": (C.c_int32, [_P]),
@@ -293,8 +297,16 @@ def ls_adam(groups, ngroups, step, beta1, beta2, eps, zero_grad, stream):
     return _call("ls_adam", groups, ngroups, step, beta1, beta2, eps, zero_grad, stream)
 
 
-def ls_register_pair(pair, prm, result, stream):
-    return _call("ls_register_pair", C.byref(pair), C.byref(prm), C.byref(result), stream)
+def ls_register_workspace_size(pair, prm, capacity):
+    out = C.c_size_t(0)
+    _call("ls_register_workspace_size", C.byref(pair), C.byref(prm), int(capacity), C.byref(out))
+    return int(out.value)
+
+
+def ls_register_pair(pair, prm, work, work_bytes, capacity, result, stream, raise_on_error=True):
+    st = getattr(load(), "ls_register_pair")(C.byref(pair), C.byref(prm), work, work_bytes, int(capacity),
+                                             C.byref(result), stream)
+    return check(st) if raise_on_error else st
 
 
 def ls_fuse_estimates(est, resid, reverse, n, out):

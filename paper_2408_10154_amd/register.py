@@ -76,28 +76,59 @@ def make_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, dep
     return pair, (hp, hq, rgbP, depthP, rgbQ, depthQ)
 
 
+_WORK = {}  # device -> grow-only workspace tensor of ls_register_pair
+
+
+def _workspace(device: int, nbytes: int) -> torch.Tensor:
+    w = _WORK.get(device)
+    if w is None or w.numel() < nbytes:
+        _WORK.pop(device, None)
+        w = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=f"cuda:{device}")
+        assert w.data_ptr() % 256 == 0
+        _WORK[device] = w
+    return w
+
+
 def register_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ,
-                  params: L.ls_reg_params | None = None):
-    """Runs ls_register_pair.  Returns dict(T [4,4] float64, per_view [V,4,4],
-    residual [V], status)."""
+                  params: L.ls_reg_params | None = None, capacity: int | None = None):
+    """Runs ls_register_pair in a workspace kept per device (grown, never
+    shrunk, so a stream of pairs allocates only when one needs more than any
+    before).  The tile-instance capacity starts at 6 instances per rendered
+    Gaussian (or `capacity`); when the call reports more are needed it is
+    re-run with 1.5x the reported count.  Returns dict(T [4,4] float64,
+    per_view [V,4,4], residual [V], status, iters, exposure, capacity)."""
     params = params or default_params()
     pair, keep = make_pair(P, Q, cam, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ)
     nv = pair.vP + pair.vQ
+    items = pair.vP * pair.Q.n + pair.vQ * pair.P.n
+    cap = int(capacity) if capacity is not None else max(4096, 6 * items)
     per_view = np.zeros((nv, 12), np.float32)
     resid = np.zeros(nv, np.float32)
     expo = np.zeros((nv, 2), np.float32)
-    res = L.ls_reg_result()
-    res.per_view_T = per_view.ctypes.data_as(C.c_void_p)
-    res.residual = resid.ctypes.data_as(C.c_void_p)
-    res.exposure = expo.ctypes.data_as(C.c_void_p)
-    L.ls_register_pair(pair, params, res, _stream())
+    dev = torch.cuda.current_device()
+    for _ in range(4):
+        res = L.ls_reg_result()
+        res.per_view_T = per_view.ctypes.data_as(C.c_void_p)
+        res.residual = resid.ctypes.data_as(C.c_void_p)
+        res.exposure = expo.ctypes.data_as(C.c_void_p)
+        need = L.ls_register_workspace_size(pair, params, cap)
+        work = _workspace(dev, need)
+        st = L.ls_register_pair(pair, params, work.data_ptr(), work.numel(), cap, res, _stream(),
+                                raise_on_error=False)
+        if st == L.LS_ERR_CAPACITY and res.instances_required > 0:
+            cap = min(int(res.instances_required * 1.5) + 4096, 2**31 - 1)
+            continue
+        L.check(st)
+        break
+    else:
+        raise L.LsError(L.LS_ERR_CAPACITY, "tile-instance capacity kept overflowing")
     T = np.eye(4)
     T[:3, :] = np.asarray(res.T_PQ, np.float64).reshape(3, 4)
     pv = np.tile(np.eye(4), (nv, 1, 1))
     pv[:, :3, :] = per_view.reshape(nv, 3, 4)
     del keep
     return dict(T=T, per_view=pv, residual=resid.astype(np.float64), status=res.status, iters=res.iters_done,
-                exposure=expo.astype(np.float64) if params.exposure else None)
+                exposure=expo.astype(np.float64) if params.exposure else None, capacity=cap)
 
 
 def fuse_estimates(estimates, residuals, reverse) -> np.ndarray:

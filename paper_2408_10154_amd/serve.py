@@ -12,6 +12,7 @@ import ctypes as C
 import time
 
 import numpy as np
+import torch
 
 from . import lib as L
 from .register import default_params, make_pair
@@ -32,7 +33,9 @@ class Server:
         params = params or default_params()
         pair, keep = make_pair(P, Q, cam, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ)
         t = C.c_uint64()
-        L.check(L.load().ls_register_submit(self.h, C.byref(pair), C.byref(params), C.byref(t)))
+        # the server reads the buffers after the work queued so far on the current stream
+        producer = C.c_void_p(torch.cuda.current_stream().cuda_stream)
+        L.check(L.load().ls_register_submit(self.h, C.byref(pair), C.byref(params), producer, C.byref(t)))
         self._keep[t.value] = (keep, P, Q, pair.vP + pair.vQ, bool(params.exposure))
         return t.value
 

@@ -87,10 +87,55 @@ def test_register_pair_rejects_bad_parameters_before_touching_a_device():
     pair = L.ls_pair()
     prm = L.ls_reg_params(0, 0.01, 0.01, 0.9, 0.999, 1e-8)  # iters = 0
     res = L.ls_reg_result()
-    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res), None) == L.LS_ERR_INVALID
     prm.iters = 10
-    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID  # no views
+    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res),
+                                None) == L.LS_ERR_INVALID  # no views
     assert lib.ls_fuse_estimates(None, None, None, 0, None) == L.LS_ERR_INVALID
+
+
+def _host_pair(vp=3, vq=2, n_p=1000, n_q=700, w=64, h=48):
+    """An ls_pair whose device pointers are placeholders: only host-side
+    calls may see it."""
+    fake = 256
+    pair = L.ls_pair()
+    pair.P = L.ls_gaussians(n_p, fake, fake, fake, fake, fake)
+    pair.Q = L.ls_gaussians(n_q, fake, fake, fake, fake, fake)
+    pair.vP, pair.vQ = vp, vq
+    pair.rgbP = pair.depthP = pair.rgbQ = pair.depthQ = fake
+    eye = [1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0]
+    keep = [(C.c_float * (12 * vp))(*(eye * vp)), (C.c_float * (12 * vq))(*(eye * vq))]
+    pair.c2wP = C.cast(keep[0], C.c_void_p)
+    pair.c2wQ = C.cast(keep[1], C.c_void_p)
+    pair.K = L.ls_intrinsics(50.0, 50.0, w / 2, h / 2, w, h)
+    return pair, keep
+
+
+def test_register_workspace_query_without_a_device():
+    """ls_register_workspace_size is host-only: it grows with the instance
+    capacity (8 bytes per instance plus the sort buffers), with the views and
+    with the Gaussians, rejects what ls_register_pair rejects, and the pair
+    call itself refuses a short workspace before any device work, reporting
+    the bytes it needs."""
+    pair, keep = _host_pair()
+    prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8)
+    b0 = L.ls_register_workspace_size(pair, prm, 0)
+    b1 = L.ls_register_workspace_size(pair, prm, 100_000)
+    b2 = L.ls_register_workspace_size(pair, prm, 200_000)
+    assert 0 < b0 < b1 < b2 and b2 - b1 >= 8 * 100_000
+    more_views, k2 = _host_pair(vp=6)
+    assert L.ls_register_workspace_size(more_views, prm, 100_000) > b1
+    more_g, k3 = _host_pair(n_q=5000)
+    assert L.ls_register_workspace_size(more_g, prm, 100_000) > b1
+    lib = L.load()
+    out = C.c_size_t(0)
+    assert lib.ls_register_workspace_size(C.byref(pair), C.byref(prm), -1, C.byref(out)) == L.LS_ERR_INVALID
+    bad = L.ls_reg_params(0, 0.01, 0.01, 0.9, 0.999, 1e-8)
+    assert lib.ls_register_workspace_size(C.byref(pair), C.byref(bad), 10, C.byref(out)) == L.LS_ERR_INVALID
+    res = L.ls_reg_result()
+    assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.c_void_p(256), 1024, 100_000, C.byref(res),
+                                None) == L.LS_ERR_CAPACITY
+    assert res.workspace_required == b1 and res.instances_required == 0
 
 
 def test_server_rejects_bad_parameters_without_a_device():
@@ -123,16 +168,16 @@ def test_register_pair_rejects_bad_loss_parameters_before_touching_a_device():
     for kind, track in ((2, L.ls_loss_params(0.6, 50.0, 3, 0)), (1, L.ls_loss_params(1.5, 50.0, 3, 0)),
                         (1, L.ls_loss_params(0.6, float("nan"), 3, 0)), (1, L.ls_loss_params(0.6, 50.0, -1, 0))):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, 0, kind, track)
-        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res), None) == L.LS_ERR_INVALID
     # exposure coefficients: flag out of range, or a bad learning rate
     good = L.ls_loss_params(0.6, 50.0, 3, 0)
     for expo, lr in ((2, 0.1), (-1, 0.1), (1, -0.1), (1, float("inf"))):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, 0, 1, good, expo, lr)
-        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res), None) == L.LS_ERR_INVALID
     # joint registration: flag out of range, or combined with exposure or early exit
     for expo, joint, patience in ((0, 2, 0), (1, 1, 0), (0, 1, 5)):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, patience, 1, good, expo, 0.1, joint)
-        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), C.byref(res), None) == L.LS_ERR_INVALID
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res), None) == L.LS_ERR_INVALID
 
 
 def test_overlap_noalloc_limits_without_a_device():

@@ -283,3 +283,55 @@ def test_joint_registration_on_the_pair_workload(gpu):
     with Server(budget_bytes=1 << 34, max_slots=4) as sv:
         with pytest.raises(L.LsError):
             sv.submit(P, Q, d["cam"], d["kf_p"], d["kf_q"], *t, params=REG.default_params(10, joint=True))
+
+
+def test_register_pair_workspace_and_capacity_reports(gpu):
+    """ls_register_pair runs in the caller's workspace: a short workspace is
+    refused with the bytes it needs; a capacity below the starting lists'
+    instance count is refused with that count; a capacity the lists outgrow
+    during the optimisation is refused with the count at the first overflow;
+    re-running at the reported sizes gives the transform, estimates and
+    residuals of an ample capacity bit for bit."""
+    import ctypes as C
+
+    from paper_2408_10154_amd import lib as L
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.render import GaussianSet, _stream
+
+    d = synth.registration_pair(9, 3000, 2500, views_p=2, views_q=2, width=96, height=72, f=70)
+    P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
+    rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
+    rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
+    args = (P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ)
+    prm = REG.default_params(30)
+    ample = REG.register_pair(*args, params=prm)
+    pair, keep = REG.make_pair(*args)
+
+    def call(work_bytes, cap):
+        res = L.ls_reg_result()
+        pv, rs = np.zeros((4, 12), np.float32), np.zeros(4, np.float32)
+        res.per_view_T, res.residual = pv.ctypes.data_as(C.c_void_p), rs.ctypes.data_as(C.c_void_p)
+        work = torch.empty(max(work_bytes, 256), dtype=torch.uint8, device="cuda")
+        st = L.ls_register_pair(pair, prm, work.data_ptr(), work_bytes, cap, res, _stream(), raise_on_error=False)
+        return st, res, pv, rs
+
+    need = L.ls_register_workspace_size(pair, prm, 64)
+    st, res, _, _ = call(need - 256, 64)
+    assert st == L.LS_ERR_CAPACITY and res.workspace_required == need and res.instances_required == 0
+    st, res, _, _ = call(need, 64)
+    assert st == L.LS_ERR_CAPACITY and res.instances_required > 64
+    start = res.instances_required
+    cap = start
+    for _ in range(3):
+        st, res, pv, rs = call(L.ls_register_workspace_size(pair, prm, cap), cap)
+        if st == L.LS_OK:
+            break
+        assert st == L.LS_ERR_CAPACITY and res.instances_required > cap
+        cap = res.instances_required + res.instances_required // 2
+    assert st == L.LS_OK and cap >= start
+    T = np.eye(4)
+    T[:3, :] = np.asarray(res.T_PQ, np.float64).reshape(3, 4)
+    np.testing.assert_array_equal(T, ample["T"])
+    np.testing.assert_array_equal(rs.astype(np.float64), ample["residual"])
+    np.testing.assert_array_equal(pv.reshape(4, 3, 4), ample["per_view"][:, :3, :].astype(np.float32))
+    del keep

@@ -171,3 +171,33 @@ def test_reused_server_state_matches_plain(pairs):
     assert st["epochs"] >= 3
     for r, p in zip(rs, reversed(pairs)):
         assert r["status"] == 0 and _same(r, _plain(p))
+
+
+def test_submit_orders_reads_after_the_producer_stream(pairs):
+    """A request whose Gaussians are written on a side stream just before
+    submitting (behind a chain of long kernels): the server's finiteness
+    check and its iterations read them only after the producer's work, so
+    the request is accepted (the buffers start as NaN) and its result equals
+    the plain path's bit for bit."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.render import GaussianSet
+    from paper_2408_10154_amd.serve import Server
+
+    args = list(pairs[0]["args"])
+    src_p, src_q = args[0], args[1]
+    Pn = GaussianSet(*[torch.full_like(t, float("nan")) for t in src_p.tensors()])
+    Qn = GaussianSet(*[torch.full_like(t, float("nan")) for t in src_q.tensors()])
+    big = torch.randn(4096, 4096, device="cuda")
+    torch.cuda.synchronize()
+    side = torch.cuda.Stream()
+    with Server() as sv:
+        with torch.cuda.stream(side):
+            for _ in range(16):
+                big = big @ big
+                big = big / big.norm()
+            for dst, src in zip(Pn.tensors() + Qn.tensors(), src_p.tensors() + src_q.tensors()):
+                dst.copy_(src)
+            ticket = sv.submit(Pn, Qn, *args[2:], params=REG.default_params(ITERS))
+        r = sv.wait(ticket)
+    assert r["status"] == 0
+    assert _same(r, _plain(pairs[0]))
