@@ -17,9 +17,11 @@ Modules
             optimisation (paper Sec. 3.3, Eq. 8)
   overlap   geometric overlap ratio of two submaps by reciprocal nearest
             neighbours (supplement, loop detection, Eq. 9)
+  prune     opacity pruning of a submap after mapping (supplement, submap
+            update)
 
 Every function with no independent pin is marked "parity unpinned" in its
 docstring; the pins live in tests/test_oracle_*.py.
 """
 
-from . import adjust, mapping, overlap, raster, register  # noqa: F401
+from . import adjust, mapping, overlap, prune, raster, register  # noqa: F401
