@@ -13,7 +13,8 @@ order, with all their parameters.
       sigmoid is increasing, so o < o_thre <=> logit < ln(o_thre / (1 -
       o_thre)).  The keep test is taken on the stored FP32 logit against the
       FP32 rounding of that threshold, logit >= fl32(ln(o / (1 - o))), so
-      that both sides decide in the same precision; a Gaussian whose opacity
+      that both sides decide in the same precision (o_thre is taken as an
+      FP32 value, the logarithm in FP64); a Gaussian whose opacity
       equals the threshold is kept ("lower than" prunes).  A NaN logit is
       pruned.  The oracle's decisions equal the FP64 definition sigmoid(w) <
       o_thre everywhere except within FP32 rounding of the threshold (pinned
@@ -28,10 +29,12 @@ import numpy as np
 
 
 def logit_threshold(o_thre: float) -> np.float32:
-    """The keep threshold on the FP32 logit: fl32(ln(o / (1 - o))) (R34)."""
-    if not 0.0 < o_thre < 1.0:
+    """The keep threshold on the FP32 logit: fl32(ln(o / (1 - o))) with o the
+    FP32 value of o_thre, the logarithm taken in FP64 (R34)."""
+    o = float(np.float32(o_thre))
+    if not 0.0 < o < 1.0:
         raise ValueError("o_thre must lie in (0, 1)")
-    return np.float32(math.log(o_thre / (1.0 - o_thre)))
+    return np.float32(math.log(o / (1.0 - o)))
 
 
 def keep_mask(opacity_logit, o_thre: float) -> np.ndarray:
