@@ -415,6 +415,40 @@ ls_status ls_overlap_ratio_noalloc(const float* p_mean, int32_t np, const float*
                                    const float* T_pq, float tau, int32_t* nn_pq, int32_t* nn_qp, int32_t* counts,
                                    hipStream_t s);
 
+/* One structure-of-arrays array compacted by ls_prune_gaussians:
+ * src [components][n] -> dst [components][count] (rows count floats apart,
+ * the ls_gaussians layout for the new count; dst must hold components * n
+ * floats, as count is only known on the device).  src and dst must not
+ * overlap. */
+typedef struct {
+  const float* src;
+  float* dst;
+  int32_t components;
+  int32_t pad;
+} ls_prune_array;
+#define LS_PRUNE_MAX_ARRAYS 16
+
+/* Opacity pruning of a submap after its mapping optimisation (supplement,
+ * Implementation Details, submap update): the Gaussians whose opacity
+ * sigmoid(opacity_logit) is below o_thre are removed, the others kept in
+ * their order.  The test is taken on the FP32 logit against the FP32
+ * rounding of ln(o_thre / (1 - o_thre)): kept <=> logit >= that value (a
+ * Gaussian at the threshold is kept; a NaN logit is pruned).
+ *   opacity_logit device [n]
+ *   arrays        host [narrays] (0..LS_PRUNE_MAX_ARRAYS) arrays to compact
+ *                 with the same selection (Gaussian parameters, optimiser
+ *                 moments, ...); the opacity logits themselves only if listed
+ *   kept_index    device int32 [n] (written): the kept Gaussians' indices,
+ *                 ascending, in its first count entries
+ *   count         device int32 [1] (written): number kept
+ *   work          device scratch of ls_prune_workspace_size(n) bytes
+ * Errors: LS_ERR_INVALID (n < 0, o_thre outside (0, 1), NULL pointers,
+ * too many arrays, components < 0), LS_ERR_CAPACITY (work too small). */
+size_t ls_prune_workspace_size(int32_t n);
+ls_status ls_prune_gaussians(const float* opacity_logit, int32_t n, float o_thre, const ls_prune_array* arrays,
+                             int32_t narrays, int32_t* kept_index, int32_t* count, void* work, size_t work_bytes,
+                             hipStream_t s);
+
 /* One parameter group of a fused Adam step. */
 typedef struct {
   float* param;

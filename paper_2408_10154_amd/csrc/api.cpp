@@ -368,6 +368,7 @@ int64_t ls_struct_size(const char* name) {
       {"ls_server_stats", sizeof(ls_server_stats)}, {"ls_loss_params", sizeof(ls_loss_params)},
       {"ls_mapping_params", sizeof(ls_mapping_params)},
       {"ls_submap_adjust", sizeof(ls_submap_adjust)},
+      {"ls_prune_array", sizeof(ls_prune_array)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -626,6 +627,34 @@ ls_status ls_overlap_ratio(const float* p_mean, int32_t np, const float* q_mean,
     return fail(LS_ERR_CAPACITY, "overlap workspace needs %zu bytes", need);
   launch_overlap(p_mean, np, q_mean, nq, T_pq, tau, nn_pq, nn_qp, counts, work, s);
   return hip_check("ls_overlap_ratio");
+}
+
+size_t ls_prune_workspace_size(int32_t n) { return n < 0 ? 0 : prune_workspace_bytes(n); }
+
+ls_status ls_prune_gaussians(const float* opacity_logit, int32_t n, float o_thre, const ls_prune_array* arrays,
+                             int32_t narrays, int32_t* kept_index, int32_t* count, void* work, size_t work_bytes,
+                             hipStream_t s) {
+  if (n < 0) return fail(LS_ERR_INVALID, "negative Gaussian count");
+  if (!(o_thre > 0.f && o_thre < 1.f)) return fail(LS_ERR_INVALID, "o_thre must lie in (0, 1)");
+  if (!count || !work || (n > 0 && (!opacity_logit || !kept_index)))
+    return fail(LS_ERR_INVALID, "NULL arguments");
+  if (narrays < 0 || narrays > LS_PRUNE_MAX_ARRAYS || (narrays > 0 && !arrays))
+    return fail(LS_ERR_INVALID, "0..%d arrays", LS_PRUNE_MAX_ARRAYS);
+  PruneArrays arr{};
+  arr.count = narrays;
+  for (int a = 0; a < narrays; ++a) {
+    if (arrays[a].components < 0) return fail(LS_ERR_INVALID, "array %d: negative component count", a);
+    if (n > 0 && arrays[a].components > 0 && (!arrays[a].src || !arrays[a].dst))
+      return fail(LS_ERR_INVALID, "array %d: NULL pointer", a);
+    arr.src[a] = arrays[a].src;
+    arr.dst[a] = arrays[a].dst;
+    arr.comp[a] = arrays[a].components;
+  }
+  const size_t need = prune_workspace_bytes(n);
+  if (work_bytes < need) return fail(LS_ERR_CAPACITY, "pruning workspace needs %zu bytes", need);
+  const float tau = (float)std::log((double)o_thre / (1.0 - (double)o_thre));
+  launch_prune(opacity_logit, n, tau, arr, kept_index, count, work, s);
+  return hip_check("ls_prune_gaussians");
 }
 
 ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2, float eps,

@@ -112,6 +112,19 @@ void launch_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, 
 // Map adjustment (adjust.hip): validated descriptors, any count.
 int launch_adjust_submaps(const ls_submap_adjust* subs, int count, hipStream_t s);
 
+// Opacity pruning (prune.hip): up to kPruneArrays SoA arrays [comp][n]
+// compacted to [comp][count] by the keep test logit >= tau.
+constexpr int kPruneArrays = 16;
+struct PruneArrays {
+  const float* src[kPruneArrays];
+  float* dst[kPruneArrays];
+  int comp[kPruneArrays];
+  int count;
+};
+size_t prune_workspace_bytes(int n);
+void launch_prune(const float* logit, int n, float tau, const PruneArrays& arr, int32_t* kept, int32_t* count,
+                  void* work, hipStream_t s);
+
 // Overlap ratio (overlap.hip).
 ls_status overlap_check_args(const float* p_mean, int32_t np, const float* q_mean, int32_t nq, const float* T_pq,
                              float tau, const int32_t* nn_pq, const int32_t* nn_qp, const int32_t* counts);

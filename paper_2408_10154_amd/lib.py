@@ -101,6 +101,10 @@ class ls_reg_params(C.Structure):
                 ("exposure", C.c_int32), ("lr_exposure", C.c_float), ("joint", C.c_int32)]
 
 
+class ls_prune_array(C.Structure):
+    _fields_ = [("src", C.c_void_p), ("dst", C.c_void_p), ("components", C.c_int32), ("pad", C.c_int32)]
+
+
 class ls_reg_result(C.Structure):
     _fields_ = [("T_PQ", C.c_float * 12), ("per_view_T", C.c_void_p), ("residual", C.c_void_p),
                 ("status", C.c_int32), ("iters_done", C.c_int32), ("exposure", C.c_void_p),
@@ -127,6 +131,7 @@ class ls_adam_group(C.Structure):
 LS_ISOTROPIC_WORK_FLOATS = 256  # scratch floats of ls_loss_isotropic
 LS_OVERLAP_NOALLOC_MAX_POINTS = 524288  # points per set taken by ls_overlap_ratio_noalloc
 LS_OVERLAP_NOALLOC_BYTES = 40 << 20     # its static per-device scratch array
+LS_PRUNE_MAX_ARRAYS = 16                # arrays one ls_prune_gaussians call compacts
 
 _P = C.c_void_p
 _PROTOS = {
@@ -157,6 +162,9 @@ _PROTOS = {
     "ls_overlap_workspace_size": (C.c_size_t, [C.c_int32, C.c_int32]),
     "ls_overlap_ratio": (C.c_int32, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_float), C.c_float, _P, _P, _P, _P,
                                      C.c_size_t, _P]),
+    "ls_prune_workspace_size": (C.c_size_t, [C.c_int32]),
+    "ls_prune_gaussians": (C.c_int32, [_P, C.c_int32, C.c_float, C.POINTER(ls_prune_array), C.c_int32, _P, _P, _P,
+                                       C.c_size_t, _P]),
     "ls_overlap_ratio_noalloc": (C.c_int32, [_P, C.c_int32, _P, C.c_int32, C.POINTER(C.c_float), C.c_float, _P, _P,
                                              _P, _P]),
     "ls_adam": (C.c_int32, [C.POINTER(ls_adam_group), C.c_int32, C.c_int32, C.c_float, C.c_float, C.c_float,
@@ -287,6 +295,14 @@ def ls_overlap_workspace_size(np_, nq):
 
 def ls_overlap_ratio(p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, work, work_bytes, stream):
     return _call("ls_overlap_ratio", p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, work, work_bytes, stream)
+
+
+def ls_prune_workspace_size(n):
+    return load().ls_prune_workspace_size(n)
+
+
+def ls_prune_gaussians(logit, n, o_thre, arrays, narrays, kept, count, work, work_bytes, stream):
+    return _call("ls_prune_gaussians", logit, n, o_thre, arrays, narrays, kept, count, work, work_bytes, stream)
 
 
 def ls_overlap_ratio_noalloc(p_mean, np_, q_mean, nq, T, tau, nn_pq, nn_qp, counts, stream):

@@ -345,6 +345,36 @@ def overlap_ratio(p_mean: torch.Tensor, q_mean: torch.Tensor, T, tau: float, wor
     return (inliers / pairs if pairs else 0.0), pairs, inliers, nn_pq, nn_qp
 
 
+def prune_gaussians(g: "GaussianSet", o_thre: float, extra=(), work=None):
+    """Opacity pruning of a Gaussian set (supplement, submap update): returns
+    (GaussianSet of the kept Gaussians, kept indices [k] int32 device tensor,
+    compacted extra arrays).  `extra` holds further [c, n] (or [n]) float32
+    device tensors compacted with the same selection (e.g. optimiser moments).
+    The kept count is read back to the host."""
+    n = g.n
+    dev = g.mean.device
+    srcs = [getattr(g, k) for k in GaussianSet.FIELDS] + list(extra)
+    if len(srcs) > L.LS_PRUNE_MAX_ARRAYS:
+        raise ValueError(f"at most {L.LS_PRUNE_MAX_ARRAYS} arrays per call")
+    dsts = [torch.empty_like(t) for t in srcs]
+    arr = (L.ls_prune_array * len(srcs))()
+    for i, (a, b) in enumerate(zip(srcs, dsts)):
+        if a.dtype != torch.float32 or not a.is_contiguous() or a.shape[-1] != n:
+            raise ValueError("arrays must be contiguous float32 [c, n] or [n]")
+        arr[i] = L.ls_prune_array(a.data_ptr(), b.data_ptr(), 1 if a.dim() == 1 else a.shape[0], 0)
+    kept = torch.empty(max(n, 1), dtype=torch.int32, device=dev)
+    count = torch.empty(1, dtype=torch.int32, device=dev)
+    need = L.ls_prune_workspace_size(n)
+    if work is None or work.numel() < need:
+        work = torch.empty(max(need, 256), dtype=torch.uint8, device=dev)
+    L.ls_prune_gaussians(_ptr(g.opacity_logit), n, float(o_thre), arr, len(srcs), _ptr(kept), _ptr(count),
+                         _ptr(work), work.numel(), _stream())
+    k = int(count.item())
+    views = [(d.view(-1)[: d.shape[0] * k].view(d.shape[0], k) if d.dim() == 2 else d[:k]) for d in dsts]
+    out = GaussianSet(*views[:5])
+    return out, kept[:k], views[5:]
+
+
 def adam(groups, step: int, beta1=0.9, beta2=0.999, eps=1e-8, zero_grad=True):
     """Fused Adam over (param, grad, m, v, lr) tuples of float32 device tensors."""
     for i in range(0, len(groups), 16):

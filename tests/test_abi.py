@@ -40,7 +40,7 @@ def test_binding_covers_the_header():
     assert set(L.declared_functions()) == declared()
 
 
-@pytest.mark.parametrize("name", ["ls_loss_params", "ls_mapping_params", "ls_submap_adjust", "ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
+@pytest.mark.parametrize("name", ["ls_prune_array", "ls_loss_params", "ls_mapping_params", "ls_submap_adjust", "ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
                                   "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group"])
 def test_struct_layouts_match(name):
     lib = L.load()
@@ -201,3 +201,18 @@ def test_overlap_noalloc_limits_without_a_device():
                                         None) == L.LS_ERR_INVALID
     assert lib.ls_overlap_ratio_noalloc(fake, 10, fake, 10, T, C.c_float(0.0), fake, fake, fake,
                                         None) == L.LS_ERR_INVALID
+
+
+def test_prune_rejects_bad_arguments_without_a_device():
+    lib = L.load()
+    fake = C.c_void_p(256)
+    arr = (L.ls_prune_array * 1)(L.ls_prune_array(256, 512, 3, 0))
+    assert L.ls_prune_workspace_size(-1) == 0 and L.ls_prune_workspace_size(0) > 0
+    assert L.ls_prune_workspace_size(10_000) >= L.ls_prune_workspace_size(100)
+    for n, o, narr, work_bytes, expect in ((-1, 0.5, 1, 1 << 20, L.LS_ERR_INVALID), (10, 0.0, 1, 1 << 20, L.LS_ERR_INVALID),
+                                           (10, 1.0, 1, 1 << 20, L.LS_ERR_INVALID), (10, 0.5, 17, 1 << 20, L.LS_ERR_INVALID),
+                                           (10_000_000, 0.5, 1, 16, L.LS_ERR_CAPACITY)):
+        assert lib.ls_prune_gaussians(fake, n, C.c_float(o), arr, narr, fake, fake, fake, work_bytes,
+                                      None) == expect, (n, o, narr)
+    bad = (L.ls_prune_array * 1)(L.ls_prune_array(256, 512, -1, 0))
+    assert lib.ls_prune_gaussians(fake, 10, C.c_float(0.5), bad, 1, fake, fake, fake, 1 << 20, None) == L.LS_ERR_INVALID
