@@ -513,6 +513,13 @@ typedef struct {
                                it, Adam on T (lr_rot, lr_trans) over the sum of the views' losses; T is
                                the estimate (no Eq. 7 fusion).  A comparison to the paper's per-view
                                estimates; ls_register_pair only, without exposure or early exit */
+  int32_t top_k;            /* views kept per direction (0: all).  The paper keeps the top-k (k = 2)
+                               overlapping viewpoints found by image retrieval (Sec. 3.2; supplement,
+                               3DGS registration); here a keyframe's overlap is its rendered
+                               co-visibility: the fraction of its pixels with a measured depth that
+                               the other submap, rendered at the keyframe pose (identity correction),
+                               covers with alpha >= 0.5; ties go to the lower keyframe index.  Views
+                               not kept report residual -1 and a zero estimate.  ls_register_pair only */
 } ls_reg_params;
 
 typedef struct {

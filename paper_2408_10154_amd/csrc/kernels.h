@@ -66,6 +66,10 @@ void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt
                       float* expo = nullptr, float* egrad = nullptr, float* em = nullptr, float* ev = nullptr,
                       float lr_expo = 0.f);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
+// Per render: fraction of the pixels with a target depth > 0 whose rendered
+// alpha is >= 0.5 (part: 2 floats per 1024-pixel block).
+void launch_view_coverage(const JobDev* jobs, const int32_t* pblk_off, int R, int npblk, const float* alpha,
+                          const float* tgt_depth, float* part, float* coverage, hipStream_t s);
 // Per-view exposure coefficients (a, b) [R][2] with their Adam moments and
 // gradient, or all null.
 struct ExpoState {

@@ -115,6 +115,58 @@ void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt
                      eps, exit_tol, exit_patience, expo, egrad, em, ev, lr_expo);
 }
 
+// View co-visibility for the top-k selection of registration views: per
+// 1024-pixel block, the pixels with a measured depth and, of those, the ones
+// the other submap covers (rendered alpha >= 0.5); then per render, in a
+// fixed order, covered / measured (0 when nothing is measured).
+__global__ __launch_bounds__(256) void k_view_cover(const JobDev* __restrict__ jobs, const int32_t* __restrict__ pblk_off,
+                                                    int R, const float* __restrict__ alpha,
+                                                    const float* __restrict__ tgt_depth, float* __restrict__ part) {
+  const int r = find_segment<int32_t>(pblk_off, R, (int32_t)blockIdx.x);
+  const JobDev& J = jobs[r];
+  const int64_t hw = (int64_t)J.W * J.H;
+  const int64_t b0 = (int64_t)(blockIdx.x - pblk_off[r]) * 1024;
+  float valid = 0.f, cover = 0.f;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t p = b0 + (int64_t)k * 256 + threadIdx.x;
+    if (p < hw && tgt_depth[J.pix_off + p] > 0.f) {
+      valid += 1.f;
+      cover += alpha[J.pix_off + p] >= 0.5f ? 1.f : 0.f;
+    }
+  }
+  valid = wave_sum(valid);
+  cover = wave_sum(cover);
+  __shared__ float ws[2][4];
+  if ((threadIdx.x & 63) == 0) {
+    ws[0][threadIdx.x >> 6] = valid;
+    ws[1][threadIdx.x >> 6] = cover;
+  }
+  __syncthreads();
+  if (threadIdx.x < 2) part[2 * blockIdx.x + threadIdx.x] = (ws[threadIdx.x][0] + ws[threadIdx.x][1]) +
+                                                             (ws[threadIdx.x][2] + ws[threadIdx.x][3]);
+}
+
+__global__ void k_view_cover_reduce(const int32_t* __restrict__ pblk_off, int R, const float* __restrict__ part,
+                                    float* __restrict__ coverage) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  float v = 0.f, c = 0.f;
+  for (int b = pblk_off[r]; b < pblk_off[r + 1]; ++b) {
+    v += part[2 * b];
+    c += part[2 * b + 1];
+  }
+  coverage[r] = v > 0.f ? c / v : 0.f;
+}
+
+void launch_view_coverage(const JobDev* jobs, const int32_t* pblk_off, int R, int npblk, const float* alpha,
+                          const float* tgt_depth, float* part, float* coverage, hipStream_t s) {
+  if (npblk > 0)
+    hipLaunchKernelGGL(k_view_cover, dim3(npblk), dim3(256), 0, s, jobs, pblk_off, R, alpha, tgt_depth, part);
+  hipLaunchKernelGGL(k_view_cover_reduce, dim3((R + 63) / 64), dim3(64), 0, s, pblk_off, R, (const float*)part,
+                     coverage);
+}
+
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s) {
   hipLaunchKernelGGL(k_or_flag, dim3(1), dim3(64), 0, s, count, sticky);
 }

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <vector>
 
 #include "batch.h"
@@ -207,7 +208,10 @@ ls_status RegEngine::prepare(const std::vector<RegPair>& pairs_in) {
     first_view[p] = (int)jobs.size();
     for (int dir = 0; dir < 2; ++dir) {
       const int nv = dir == 0 ? pr.vP : pr.vQ;
-      for (int i = 0; i < nv; ++i) {
+      const std::vector<int>& sel = pairs[p].sel[dir];
+      const int nsel = sel.empty() ? nv : (int)sel.size();
+      for (int k = 0; k < nsel; ++k) {
+        const int i = sel.empty() ? k : sel[k];
         View v;
         v.pair = (int)p;
         v.reverse = dir == 1;
@@ -359,6 +363,17 @@ ls_status RegEngine::bind(void* work, size_t work_bytes, int64_t cap, hipStream_
   return hip_ok();
 }
 
+ls_status RegEngine::coverage(hipStream_t s, std::vector<float>& cov) {
+  ls_status st;
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s))) return st;
+  launch_view_coverage(batch->jobs_d, batch->pblk_off_d, R, batch->nblk_pix, img.alpha, tgt_depth, g_rgb, loss, s);
+  cov.resize(R);
+  if (hipMemcpyAsync(cov.data(), loss, 4 * (size_t)R, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LS_ERR_HIP;
+  return hip_ok();
+}
+
 // Bins every view at its current pose and reads the instance count back:
 // {kept, overflow, required, 0}.
 ls_status RegEngine::measure(hipStream_t s, int32_t* hc) {
@@ -497,10 +512,14 @@ ls_status RegEngine::fuse_pair(int p, const std::vector<float>& pose_h, const st
                                ls_reg_result* out) {
   const int v0 = first_view[p], v1 = first_view[p + 1];
   const int n = v1 - v0;
+  const int vp = pairs[p].pair.vP, vall = vp + pairs[p].pair.vQ;
+  if (out->per_view_T) std::fill(out->per_view_T, out->per_view_T + 12 * (size_t)vall, 0.f);
+  if (out->residual) std::fill(out->residual, out->residual + vall, -1.f);  // views not kept
   std::vector<double> est(12 * n), res(n);
   std::vector<int32_t> rev(n);
   for (int k = 0; k < n; ++k) {
     const View& v = views[v0 + k];
+    const int slot = (v.reverse ? vp : 0) + v.index;  // the keyframe's position among all of the pair's
     for (int q = 0; q < 7; ++q)
       if (!std::isfinite(pose_h[7 * (v0 + k) + q])) return LS_ERR_NONFINITE;
     if (!std::isfinite(loss_h[v0 + k])) return LS_ERR_NONFINITE;
@@ -508,8 +527,8 @@ ls_status RegEngine::fuse_pair(int p, const std::vector<float>& pose_h, const st
     res[k] = loss_h[v0 + k];
     rev[k] = v.reverse ? 1 : 0;
     if (out->per_view_T)
-      for (int q = 0; q < 12; ++q) out->per_view_T[12 * k + q] = (float)est[12 * k + q];
-    if (out->residual) out->residual[k] = loss_h[v0 + k];
+      for (int q = 0; q < 12; ++q) out->per_view_T[12 * slot + q] = (float)est[12 * k + q];
+    if (out->residual) out->residual[slot] = loss_h[v0 + k];
   }
   double T[12];
   const int st = fuse_estimates(est.data(), res.data(), rev.data(), n, T);
@@ -521,9 +540,18 @@ ls_status RegEngine::fuse_pair(int p, const std::vector<float>& pose_h, const st
 ls_status RegEngine::read_exposure(int p, ls_reg_result* out, hipStream_t s) {
   if (!out->exposure || !expo) return LS_OK;
   const int v0 = first_view[p], n = first_view[p + 1] - v0;
-  if (hipMemcpyAsync(out->exposure, expo + 2 * v0, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
+  std::vector<float> h(2 * (size_t)n);
+  if (hipMemcpyAsync(h.data(), expo + 2 * v0, 8 * (size_t)n, hipMemcpyDeviceToHost, s) != hipSuccess ||
       hipStreamSynchronize(s) != hipSuccess)
     return LS_ERR_HIP;
+  const int vp = pairs[p].pair.vP;
+  std::fill(out->exposure, out->exposure + 2 * (size_t)(vp + pairs[p].pair.vQ), 0.f);
+  for (int k = 0; k < n; ++k) {
+    const View& v = views[v0 + k];
+    const int slot = (v.reverse ? vp : 0) + v.index;
+    out->exposure[2 * slot] = h[2 * k];
+    out->exposure[2 * slot + 1] = h[2 * k + 1];
+  }
   return LS_OK;
 }
 
@@ -537,7 +565,8 @@ ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
       !(prm->beta2 >= 0 && prm->beta2 < 1) || !(prm->adam_eps > 0) || !(prm->exit_rel_tol >= 0) ||
       prm->exit_patience < 0 || prm->loss_kind < 0 || prm->loss_kind > 1 || prm->exposure < 0 ||
       prm->exposure > 1 || (prm->exposure && !(prm->lr_exposure >= 0.f && std::isfinite(prm->lr_exposure))) ||
-      prm->joint < 0 || prm->joint > 1 || (prm->joint && (prm->exposure || prm->exit_patience > 0)))
+      prm->joint < 0 || prm->joint > 1 || (prm->joint && (prm->exposure || prm->exit_patience > 0)) ||
+      prm->top_k < 0)
     return LS_ERR_INVALID;
   if (prm->loss_kind == 1 && (!(prm->track.lambda_c >= 0.f && prm->track.lambda_c <= 1.f) ||
                               !std::isfinite(prm->track.inlier_k) || prm->track.alpha_power < 0 ||
@@ -599,18 +628,44 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, void* 
     out->status = code;
     return code;
   };
-  RegEngine e;
-  if ((st = e.prepare({make_reg_pair(pair, prm)}))) return finish(st);
-  out->workspace_required = (int64_t)e.workspace_bytes(capacity);
+  RegPair rp = make_reg_pair(pair, prm);
+  auto engine = std::make_unique<RegEngine>();
+  if ((st = engine->prepare({rp}))) return finish(st);
+  out->workspace_required = (int64_t)engine->workspace_bytes(capacity);
   if (!work || work_bytes < (size_t)out->workspace_required || reinterpret_cast<uintptr_t>(work) % 256)
     return finish(LS_ERR_CAPACITY);
-  if ((st = e.bind(work, work_bytes, capacity, s))) return finish(st);
+  if ((st = engine->bind(work, work_bytes, capacity, s))) return finish(st);
   int32_t hc[4];
-  if ((st = e.measure(s, hc))) return finish(st);
+  if ((st = engine->measure(s, hc))) return finish(st);
   if (hc[1]) {  // the lists at the starting poses do not fit
     out->instances_required = hc[2];
     return finish(LS_ERR_CAPACITY);
   }
+  const int k = prm->top_k;
+  if (k > 0 && (pair->vP > k || pair->vQ > k)) {
+    // top-k views per direction by co-visibility at the starting poses, then
+    // a fresh engine over those views only (its workspace fits in the same one)
+    std::vector<float> cov;
+    if ((st = engine->coverage(s, cov))) return finish(st);
+    for (int dir = 0; dir < 2; ++dir) {
+      const int nv = dir == 0 ? pair->vP : pair->vQ, r0 = dir == 0 ? 0 : pair->vP;
+      std::vector<int> order(nv);
+      for (int i = 0; i < nv; ++i) order[i] = i;
+      std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return cov[r0 + a] > cov[r0 + b]; });
+      order.resize(std::min(nv, k));
+      std::sort(order.begin(), order.end());
+      rp.sel[dir] = order;
+    }
+    engine = std::make_unique<RegEngine>();
+    if ((st = engine->prepare({rp})) || (st = engine->bind(work, work_bytes, capacity, s)) ||
+        (st = engine->measure(s, hc)))
+      return finish(st);
+    if (hc[1]) {
+      out->instances_required = hc[2];
+      return finish(LS_ERR_CAPACITY);
+    }
+  }
+  RegEngine& e = *engine;
   int done = 0;
   constexpr int kCheckEvery = 16;  // early exit: poll the views' active flags this often
   if (prm->joint) {

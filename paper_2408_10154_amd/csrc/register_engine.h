@@ -12,6 +12,7 @@ struct RegPair {
   ls_reg_params prm;
   std::vector<double> c2wP;   // [vP][12]
   std::vector<double> c2wQ;   // [vQ][12]
+  std::vector<int> sel[2];    // keyframes of P / of Q taking part (ascending; empty: all)
 };
 
 // One localisation problem: a keyframe of one submap rendering the other.
@@ -31,6 +32,9 @@ class RegEngine {
   size_t workspace_bytes(int64_t capacity) const;
   ls_status bind(void* work, size_t work_bytes, int64_t capacity, hipStream_t s);
   ls_status measure(hipStream_t s, int32_t* count4);
+  // After measure(): renders every view and returns its co-visibility
+  // (fraction of measured pixels the other submap covers, alpha >= 0.5).
+  ls_status coverage(hipStream_t s, std::vector<float>& cov);
   ls_status step(hipStream_t s);
   ls_status final_forward(hipStream_t s);
   ls_status view_loss(hipStream_t s);  // the loss the pair's parameters select

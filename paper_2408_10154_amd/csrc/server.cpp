@@ -136,7 +136,7 @@ class Server {
   ls_status submit(const ls_pair* pair, const ls_reg_params* prm, hipStream_t producer, uint64_t* ticket) {
     ls_status st = validate_pair(pair, prm);
     if (st) return st;
-    if (prm->joint) return LS_ERR_INVALID;  // joint registration: ls_register_pair only
+    if (prm->joint || prm->top_k > 0) return LS_ERR_INVALID;  // joint registration, view selection: ls_register_pair only
     {
       std::lock_guard<std::mutex> g(mu_);
       if (!have_betas_) {

@@ -335,3 +335,47 @@ def test_register_pair_workspace_and_capacity_reports(gpu):
     np.testing.assert_array_equal(rs.astype(np.float64), ample["residual"])
     np.testing.assert_array_equal(pv.reshape(4, 3, 4), ample["per_view"][:, :3, :].astype(np.float32))
     del keep
+
+
+def test_top_k_view_selection(gpu):
+    """k = 2 keyframes per direction (supplement, 3DGS registration): the
+    views kept are the two per direction with the highest rendered
+    co-visibility at the starting poses (fraction of measured pixels the
+    other submap covers with alpha >= 0.5, computed here from the
+    rasterizer's own renders), the others report residual -1; the result
+    equals, bit for bit, registering a pair that holds only those keyframes;
+    and top_k >= the view count is the all-views run."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.render import GaussianSet, RenderBatch
+
+    d = synth.registration_pair(3, 20000, 16000, views_p=5, views_q=4, width=160, height=120, f=130,
+                                layout="views")
+    P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
+    rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
+    rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
+    args = (P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ)
+    res = REG.register_pair(*args, params=REG.default_params(60, top_k=2))
+    assert res["status"] == 0
+    kept = res["residual"] >= 0
+    assert kept[:5].sum() == 2 and kept[5:].sum() == 2
+    # co-visibility from the rasterizer: P's keyframes render Q and Q's render P
+    cov = []
+    for g_other, kfs, dep in ((Q, d["kf_p"], depP), (P, d["kf_q"], depQ)):
+        b = RenderBatch([(g_other, d["cam"], REG.inv_rigid(c)[:3]) for c in kfs])
+        b.project()
+        b.bin_sort()
+        b.render_fwd()
+        a = b.alpha.view(len(kfs), -1)
+        m = dep.view(len(kfs), -1) > 0
+        cov += [float(((a[i] >= 0.5) & m[i]).sum()) / max(float(m[i].sum()), 1.0) for i in range(len(kfs))]
+    for lo, hi in ((0, 5), (5, 9)):
+        order = sorted(range(lo, hi), key=lambda i: (-cov[i], i))[:2]
+        assert set(np.nonzero(kept[lo:hi])[0] + lo) == set(order), (cov, kept)
+    sp, sq = np.nonzero(kept[:5])[0], np.nonzero(kept[5:])[0]
+    sub = REG.register_pair(P, Q, d["cam"], d["kf_p"][sp], d["kf_q"][sq], rgbP[sp].contiguous(), depP[sp].contiguous(),
+                            rgbQ[sq].contiguous(), depQ[sq].contiguous(), params=REG.default_params(60))
+    np.testing.assert_array_equal(sub["T"], res["T"])
+    np.testing.assert_array_equal(sub["residual"], res["residual"][kept])
+    full = REG.register_pair(*args, params=REG.default_params(60))
+    same = REG.register_pair(*args, params=REG.default_params(60, top_k=5))
+    np.testing.assert_array_equal(full["T"], same["T"])
