@@ -15,19 +15,41 @@ from . import synth
 from .render import GaussianSet
 
 
-def build_pair(spec: dict, width=640, height=480, f=500.0):
-    """Device-resident pair (Gaussians and keyframe targets) for a spec of
-    synth.pair_set / synth.request_stream, built by synth.registration_pair."""
-    d = synth.registration_pair(spec["seed"], spec["n_p"], spec["n_q"], views_p=spec["views_p"],
-                                views_q=spec["views_q"], width=spec.get("width", width),
-                                height=spec.get("height", height), f=spec.get("f", f),
-                                layout=spec.get("layout", "views"))
+def gen_pair(spec: dict, width=640, height=480, f=500.0) -> dict:
+    """Host arrays of a pair spec of synth.pair_set / synth.request_stream
+    (NumPy only, no device work), built by synth.registration_pair."""
+    return synth.registration_pair(spec["seed"], spec["n_p"], spec["n_q"], views_p=spec["views_p"],
+                                   views_q=spec["views_q"], width=spec.get("width", width),
+                                   height=spec.get("height", height), f=spec.get("f", f),
+                                   layout=spec.get("layout", "views"))
+
+
+def gen_pairs(specs, workers: int = 1) -> list:
+    """gen_pair over many specs, in `workers` forked processes when > 1 (call
+    it before the process touches the GPU)."""
+    if workers <= 1 or len(specs) <= 1:
+        return [gen_pair(sp) for sp in specs]
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(min(workers, len(specs))) as pool:
+        return pool.map(gen_pair, specs)
+
+
+def upload_pair(d: dict, spec: dict) -> dict:
+    """Device-resident pair (Gaussians and keyframe targets rendered by the
+    rasterizer) from gen_pair's host arrays."""
     P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
     rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
     rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
     return dict(T_gt=d["T_gt"], args=(P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ),
                 pixels=(spec["views_p"] + spec["views_q"]) * d["cam"]["width"] * d["cam"]["height"],
                 n_p=d["P"]["mean"].shape[1], n_q=d["Q"]["mean"].shape[1], shared=d["shared"])
+
+
+def build_pair(spec: dict, width=640, height=480, f=500.0):
+    """Device-resident pair (Gaussians and keyframe targets) for a spec of
+    synth.pair_set / synth.request_stream, built by synth.registration_pair."""
+    return upload_pair(gen_pair(spec, width, height, f), spec)
 
 
 def _errors(results, pairs):
@@ -42,7 +64,7 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, np.float64), q))
 
 
-def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0):
+def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0, top_k=0):
     """One pair at a time through ls_register_pair; latency of pair k counts
     from the start of the run (all requests present at t = 0)."""
     torch.cuda.synchronize()
@@ -50,7 +72,7 @@ def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0):
     results, done = [], []
     for p in pairs:
         results.append(REG.register_pair(*p["args"], params=REG.default_params(
-            iters, loss=loss, exit_rel_tol=exit_rel_tol, exit_patience=exit_patience)))
+            iters, loss=loss, exit_rel_tol=exit_rel_tol, exit_patience=exit_patience, top_k=top_k)))
         done.append(time.perf_counter() - t0)
     total = time.perf_counter() - t0
     return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(done, 50), p99_s=_pct(done, 99),
