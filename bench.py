@@ -302,9 +302,10 @@ def prune_timing(reps: int = 20):
     one 200k-Gaussian submap and of 12.8 M Gaussians in one call, with the
     five parameter arrays and two Adam moments per parameter compacted:
     median call time (HIP events around ls_prune_gaussians, no host read-back
-    inside) and HBM fraction of the algorithmic bytes (4 per Gaussian for the
-    keep test; per kept Gaussian its 14 floats x 3 arrays read and written
-    and the index written)."""
+    inside) and HBM fraction of the algorithmic bytes: every array read once
+    (the logit and 14 floats x 3 arrays per Gaussian: with half of the
+    Gaussians kept at random every cache line of the inputs is needed) and
+    the kept Gaussians' 42 floats and index written once."""
     import numpy as np
     import torch
 
@@ -338,7 +339,7 @@ def prune_timing(reps: int = 20):
         torch.cuda.synchronize()
         k = int(count.item())
         ms = sorted(a.elapsed_time(c) for a, c in evs)[reps // 2]
-        algo = 4 * n + k * (2 * 4 * 14 * 3 + 4)
+        algo = 4 * n + n * 4 * 14 * 3 + k * (4 * 14 * 3 + 4)
         out[str(n)] = {"kept": k, "ms": round(ms, 4), "achieved_gbs": round(algo / (ms * 1e-3) / 1e9, 1),
                        "frac": round(algo / (ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4)}
         del gs, srcs, dsts, kept, work

@@ -18,14 +18,17 @@
 namespace ls {
 
 constexpr int kPruneThreads = 256;
-constexpr int kPruneRounds = 4;                              // items per thread
-constexpr int kPruneTile = kPruneThreads * kPruneRounds;     // items per block
+// Items per thread: 4 for large sets; 1 below kPruneSmall items, so that a
+// submap-sized set still spreads over more blocks than the GPU has CUs.
+constexpr int kPruneSmall = 1 << 20;
+__host__ __device__ constexpr int prune_tile(int rounds) { return kPruneThreads * rounds; }
 
 __device__ __forceinline__ bool prune_keep(float w, float tau) { return w >= tau; }
 
+template <int kPruneRounds>
 __global__ __launch_bounds__(kPruneThreads) void k_prune_count(const float* __restrict__ logit, int n, float tau,
                                                                int32_t* __restrict__ tile_count) {
-  const int64_t base = (int64_t)blockIdx.x * kPruneTile;
+  const int64_t base = (int64_t)blockIdx.x * prune_tile(kPruneRounds);
   int c = 0;
 #pragma unroll
   for (int r = 0; r < kPruneRounds; ++r) {
@@ -64,12 +67,13 @@ __global__ __launch_bounds__(1024) void k_prune_scan(const int32_t* __restrict__
   if (threadIdx.x == 1023) *count = run;
 }
 
+template <int kPruneRounds>
 __global__ __launch_bounds__(kPruneThreads) void k_prune_scatter(const float* __restrict__ logit, int n, float tau,
                                                                  const int32_t* __restrict__ tile_off,
                                                                  const int32_t* __restrict__ count, PruneArrays arr,
                                                                  int32_t* __restrict__ kept) {
   __shared__ int32_t wcnt[kPruneRounds][kPruneThreads / 64];
-  const int64_t base = (int64_t)blockIdx.x * kPruneTile;
+  const int64_t base = (int64_t)blockIdx.x * prune_tile(kPruneRounds);
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const uint64_t below = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   bool keep[kPruneRounds];
@@ -84,37 +88,59 @@ __global__ __launch_bounds__(kPruneThreads) void k_prune_scatter(const float* __
   }
   __syncthreads();
   const int64_t stride = count[0];
+  int64_t pos[kPruneRounds];
   int run = tile_off[blockIdx.x];
 #pragma unroll
   for (int r = 0; r < kPruneRounds; ++r) {
     int before = run;
     for (int k = 0; k < w; ++k) before += wcnt[r][k];
-    if (keep[r]) {
-      const int64_t i = base + r * kPruneThreads + threadIdx.x;
-      const int64_t pos = before + rank[r];
-      kept[pos] = (int32_t)i;
-      for (int a = 0; a < arr.count; ++a)
-        for (int c = 0; c < arr.comp[a]; ++c) arr.dst[a][c * stride + pos] = arr.src[a][(int64_t)c * n + i];
-    }
+    pos[r] = before + rank[r];
+    if (keep[r]) kept[pos[r]] = (int32_t)(base + r * kPruneThreads + threadIdx.x);
     run += (wcnt[r][0] + wcnt[r][1]) + (wcnt[r][2] + wcnt[r][3]);
+  }
+  // one row at a time: the four rounds' loads are issued before their stores
+  for (int a = 0; a < kPruneArrays; ++a) {
+    if (a >= arr.count) break;  // uniform
+    const float* __restrict__ src = arr.src[a];
+    float* __restrict__ dst = arr.dst[a];
+    for (int c = 0; c < arr.comp[a]; ++c) {
+      float v[kPruneRounds];
+#pragma unroll
+      for (int r = 0; r < kPruneRounds; ++r)
+        v[r] = keep[r] ? src[(int64_t)c * n + base + r * kPruneThreads + threadIdx.x] : 0.f;
+#pragma unroll
+      for (int r = 0; r < kPruneRounds; ++r)
+        if (keep[r]) dst[c * stride + pos[r]] = v[r];
+    }
   }
 }
 
+static int prune_rounds(int n) { return n < kPruneSmall ? 1 : 4; }
+
 size_t prune_workspace_bytes(int n) {
-  const size_t tiles = (size_t)std::max((n + kPruneTile - 1) / kPruneTile, 1);
+  const size_t tiles = (size_t)std::max((n + prune_tile(prune_rounds(n)) - 1) / prune_tile(prune_rounds(n)), 1);
   return 2 * ((4 * tiles + 255) & ~(size_t)255);
+}
+
+template <int kRounds>
+static void launch_prune_rounds(const float* logit, int n, float tau, const PruneArrays& arr, int32_t* kept,
+                                int32_t* count, void* work, hipStream_t s) {
+  const int tiles = std::max((n + prune_tile(kRounds) - 1) / prune_tile(kRounds), 1);
+  int32_t* tile_count = static_cast<int32_t*>(work);
+  int32_t* tile_off = tile_count + (((4 * (size_t)tiles + 255) & ~(size_t)255) / 4);
+  hipLaunchKernelGGL(k_prune_count<kRounds>, dim3(tiles), dim3(kPruneThreads), 0, s, logit, n, tau, tile_count);
+  hipLaunchKernelGGL(k_prune_scan, dim3(1), dim3(1024), 0, s, (const int32_t*)tile_count, tiles, tile_off, count);
+  if (n > 0)
+    hipLaunchKernelGGL(k_prune_scatter<kRounds>, dim3(tiles), dim3(kPruneThreads), 0, s, logit, n, tau,
+                       (const int32_t*)tile_off, (const int32_t*)count, arr, kept);
 }
 
 void launch_prune(const float* logit, int n, float tau, const PruneArrays& arr, int32_t* kept, int32_t* count,
                   void* work, hipStream_t s) {
-  const int tiles = std::max((n + kPruneTile - 1) / kPruneTile, 1);
-  int32_t* tile_count = static_cast<int32_t*>(work);
-  int32_t* tile_off = tile_count + (((4 * (size_t)tiles + 255) & ~(size_t)255) / 4);
-  hipLaunchKernelGGL(k_prune_count, dim3(tiles), dim3(kPruneThreads), 0, s, logit, n, tau, tile_count);
-  hipLaunchKernelGGL(k_prune_scan, dim3(1), dim3(1024), 0, s, (const int32_t*)tile_count, tiles, tile_off, count);
-  if (n > 0)
-    hipLaunchKernelGGL(k_prune_scatter, dim3(tiles), dim3(kPruneThreads), 0, s, logit, n, tau,
-                       (const int32_t*)tile_off, (const int32_t*)count, arr, kept);
+  if (prune_rounds(n) == 1)
+    launch_prune_rounds<1>(logit, n, tau, arr, kept, count, work, s);
+  else
+    launch_prune_rounds<4>(logit, n, tau, arr, kept, count, work, s);
 }
 
 }  // namespace ls

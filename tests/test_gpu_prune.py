@@ -25,7 +25,7 @@ def _gauss(rng, n, tau=None):
     return g
 
 
-@pytest.mark.parametrize("n", [0, 1, 1023, 1024, 1025, 200_003])
+@pytest.mark.parametrize("n", [0, 1, 1023, 1024, 1025, 200_003, 1_100_003])
 @pytest.mark.parametrize("o_thre", [0.1, 0.5])
 def test_prune_matches_oracle_bit_exact(gpu, n, o_thre):
     from paper_2408_10154_amd.render import GaussianSet, prune_gaussians
