@@ -501,7 +501,8 @@ typedef struct {
   float lr_rot, lr_trans;   /* learning rates of the quaternion and the translation */
   float beta1, beta2, adam_eps;
   float exit_rel_tol;       /* early exit: a view stops once its loss has not improved on its best */
-  int32_t exit_patience;    /* by more than exit_rel_tol (relative) for exit_patience iterations; 0 = off */
+  int32_t exit_patience;    /* by more than exit_rel_tol (relative) for exit_patience iterations; 0 = off
+                               (see exit_mode for the step rule) */
   int32_t loss_kind;        /* 0: plain L1 (ls_loss_l1); 1: tracking loss with masks (ls_loss_tracking) */
   ls_loss_params track;     /* weights and masks when loss_kind == 1 */
   int32_t exposure;         /* 1: per-view exposure coefficients (supplement, 3DGS registration): the
@@ -513,6 +514,10 @@ typedef struct {
                                it, Adam on T (lr_rot, lr_trans) over the sum of the views' losses; T is
                                the estimate (no Eq. 7 fusion).  A comparison to the paper's per-view
                                estimates; ls_register_pair only, without exposure or early exit */
+  int32_t exit_mode;        /* early exit rule when exit_patience > 0: 0 the loss plateau above; 1 the
+                               pose step: a view stops once the largest |m_hat| / (sqrt(v_hat) + eps)
+                               of its Adam update (the step in units of the learning rate) has stayed
+                               below exit_rel_tol for exit_patience iterations */
   int32_t top_k;            /* views kept per direction (0: all).  The paper keeps the top-k (k = 2)
                                overlapping viewpoints found by image retrieval (Sec. 3.2; supplement,
                                3DGS registration); here a keyframe's overlap is its rendered

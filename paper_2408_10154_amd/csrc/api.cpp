@@ -346,6 +346,16 @@ ls_status batch_create(const ls_render_job* jobs, int32_t R, void* mem, size_t m
   *out = b;
   return LS_OK;
 }
+
+ls_status project_views(const ls_batch* b, const float* pose, const ls_projected* out, const ViewOpt* live,
+                        hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(out)) || (st = ensure_device(b))) return st;
+  launch_project(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, out->rec, out->radius, out->tiles, out->aux, live,
+                 s);
+  return hip_check("ls_project");
+}
 }  // namespace ls
 
 extern "C" {
@@ -412,11 +422,7 @@ ls_status ls_fill_i32(int32_t* ptr, int64_t count, int32_t value, hipStream_t s)
 }
 
 ls_status ls_project(const ls_batch* b, const float* pose, const ls_projected* out, hipStream_t s) {
-  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
-  ls_status st;
-  if ((st = check_projected(out)) || (st = ensure_device(b))) return st;
-  launch_project(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, out->rec, out->radius, out->tiles, out->aux, s);
-  return hip_check("ls_project");
+  return project_views(b, pose, out, nullptr, s);
 }
 
 ls_status ls_bin_sort(const ls_batch* b, const ls_projected* p, const ls_bins* bins, hipStream_t s) {

@@ -49,6 +49,11 @@ ls_status batch_create(const ls_render_job* jobs, int32_t R, void* mem, size_t m
 ls_status batch_create_host(const ls_render_job* jobs, int32_t R, ls_batch** out);
 size_t batch_tables_bytes(const ls_batch* b);
 ls_status batch_bind(ls_batch* b, void* mem, size_t mem_bytes, hipStream_t s);
+// ls_project with every render gated on live[r].active (live NULL: all): a
+// frozen registration view contributes no tile instances, so binning,
+// compositing and the backward skip it.
+ls_status project_views(const ls_batch* b, const float* pose, const ls_projected* out, const ViewOpt* live,
+                        hipStream_t s);
 // Points every render's loss at its own measurements (device [3][H][W] and
 // [H][W]); re-uploads the job table.  Used by engines that do not lay the
 // targets out contiguously.

@@ -12,8 +12,11 @@ ls_status api_hip_check(const char* what);
 
 void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s);
 
+struct ViewOpt;
+// live (or NULL: every render) gates each render on its active flag: the
+// items of a frozen render project to radius 0, so it has no tile instances.
 void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
-                    int32_t* radius, int32_t* tiles, float* aux, hipStream_t s);
+                    int32_t* radius, int32_t* tiles, float* aux, const ViewOpt* live, hipStream_t s);
 
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
                         const int32_t* radius, const float* aux, float* g2d, const GradDev* grads, int want_gauss,
@@ -62,7 +65,8 @@ void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipS
 // With expo non-null, each view's exposure coefficients (a, b) take the same
 // Adam step (learning rate lr_expo) from egrad, which is consumed.
 void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
-                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, hipStream_t s,
+                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, int exit_mode,
+                      hipStream_t s,
                       float* expo = nullptr, float* egrad = nullptr, float* em = nullptr, float* ev = nullptr,
                       float lr_expo = 0.f);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);

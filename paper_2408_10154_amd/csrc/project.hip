@@ -3,14 +3,14 @@
 // One thread per item; blocks never straddle two renders (each render owns
 // ceil(n / 256) blocks starting at blk_off), so the per-render pose-gradient
 // partials of the backward can be reduced in a fixed order.
-#include "common.h"
+#include "kernels.h"
 
 namespace ls {
 
 __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
                                                  int R, const float* __restrict__ pose, float4* __restrict__ rec,
                                                  int32_t* __restrict__ radius_out, int32_t* __restrict__ tiles_out,
-                                                 float4* __restrict__ aux) {
+                                                 float4* __restrict__ aux, const ViewOpt* __restrict__ live) {
   const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
   const JobDev& J = jobs[r];
   const int g = (blockIdx.x - J.blk_off) * 256 + threadIdx.x;
@@ -30,7 +30,7 @@ __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs
   int rad = 0, ntiles = 0;
   float4 o0 = make_float4(0.f, 0.f, 0.f, 0.f), o1 = o0, o2 = o0;
   float4 x0 = make_float4(px, py, pz, 0.f), x1 = make_float4(0.f, 0.f, 0.f, 0.f), x2 = x1;
-  if (pz > LS_NEAR_Z) {
+  if (pz > LS_NEAR_Z && (!live || live[r].active)) {
     // Sigma = M M^T, M = R(q) diag(s)
     float Rq[9];
     quat_to_rot(J.quat[g], J.quat[n + g], J.quat[2 * n + g], J.quat[3 * n + g], Rq);
@@ -251,10 +251,10 @@ __global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const floa
 
 namespace ls {
 void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
-                    int32_t* radius, int32_t* tiles, float* aux, hipStream_t s) {
+                    int32_t* radius, int32_t* tiles, float* aux, const ViewOpt* live, hipStream_t s) {
   if (nblk > 0)
     hipLaunchKernelGGL(k_project, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, reinterpret_cast<float4*>(rec),
-                       radius, tiles, reinterpret_cast<float4*>(aux));
+                       radius, tiles, reinterpret_cast<float4*>(aux), live);
 }
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
                         const int32_t* radius, const float* aux, float* g2d, const GradDev* grads, int want_gauss,

@@ -387,7 +387,9 @@ ls_status RegEngine::measure(hipStream_t s, int32_t* hc) {
 ls_status RegEngine::step(hipStream_t s) {
   ls_status st;
   const ls_image_grad up{g_rgb, g_depth, nullptr, scale};
-  if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
+  // views frozen by the early exit are not rendered (the final forward
+  // renders every view)
+  if ((st = project_views(batch, pose, &proj, opt, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
   if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) || (st = view_loss(s)) ||
       (st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
@@ -395,7 +397,7 @@ ls_status RegEngine::step(hipStream_t s) {
     return st;
   const ls_reg_params& pm = pairs[0].prm;
   launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, loss, R, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
-                   pm.exit_patience, s, expo, expo_grad, expo_m, expo_v, pm.lr_exposure);
+                   pm.exit_patience, pm.exit_mode, s, expo, expo_grad, expo_m, expo_v, pm.lr_exposure);
   return hip_ok();
 }
 
@@ -566,7 +568,7 @@ ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {
       prm->exit_patience < 0 || prm->loss_kind < 0 || prm->loss_kind > 1 || prm->exposure < 0 ||
       prm->exposure > 1 || (prm->exposure && !(prm->lr_exposure >= 0.f && std::isfinite(prm->lr_exposure))) ||
       prm->joint < 0 || prm->joint > 1 || (prm->joint && (prm->exposure || prm->exit_patience > 0)) ||
-      prm->top_k < 0)
+      prm->top_k < 0 || prm->exit_mode < 0 || prm->exit_mode > 1)
     return LS_ERR_INVALID;
   if (prm->loss_kind == 1 && (!(prm->track.lambda_c >= 0.f && prm->track.lambda_c <= 1.f) ||
                               !std::isfinite(prm->track.inlier_k) || prm->track.alpha_power < 0 ||

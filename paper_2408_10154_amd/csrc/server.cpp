@@ -145,6 +145,7 @@ class Server {
         eps_ = prm->adam_eps;
         exit_tol_ = prm->exit_rel_tol;
         exit_patience_ = prm->exit_patience;
+        exit_mode_ = prm->exit_mode;
         loss_kind_ = prm->loss_kind;
         track_ = prm->track;
         exposure_ = prm->exposure;
@@ -152,6 +153,7 @@ class Server {
         have_betas_ = true;
       } else if (prm->beta1 != beta1_ || prm->beta2 != beta2_ || prm->adam_eps != eps_ ||
                  prm->exit_rel_tol != exit_tol_ || prm->exit_patience != exit_patience_ ||
+                 prm->exit_mode != exit_mode_ ||
                  prm->loss_kind != loss_kind_ || prm->exposure != exposure_ ||
                  (exposure_ && prm->lr_exposure != lr_exposure_) ||
                  (loss_kind_ == 1 && (prm->track.lambda_c != track_.lambda_c ||
@@ -461,7 +463,8 @@ class Server {
     const StatePtrs s = state_ptrs(stateA_, R_);
     const ls_image_grad up{g_rgb_, g_depth_, nullptr, s.scale};
     ls_status st;
-    if ((st = ls_project(batch_, s.pose, &proj_, stream_)) || (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)))
+    if ((st = project_views(batch_, s.pose, &proj_, s.opt, stream_)) ||
+        (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)))
       return st;
     launch_or_flag(count_, sticky_, stream_);
     if ((st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_)) ||
@@ -470,10 +473,10 @@ class Server {
         (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
       return st;
     if (exposure_)
-      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
+      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_, exit_mode_,
                        stream_, s.expo, s.eg, s.em, s.ev, lr_exposure_);
     else
-      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
+      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_, exit_mode_,
                        stream_);
     return LS_OK;
   }
@@ -674,7 +677,7 @@ class Server {
   DevBuf check_buf_;
   bool have_betas_ = false;
   float beta1_ = 0.9f, beta2_ = 0.999f, eps_ = 1e-8f, exit_tol_ = 0.f;
-  int32_t exit_patience_ = 0;
+  int32_t exit_patience_ = 0, exit_mode_ = 0;
   int32_t loss_kind_ = 0;
   ls_loss_params track_{};
   int32_t exposure_ = 0;  // exposure coefficients on (fixed by the first request, like the loss)

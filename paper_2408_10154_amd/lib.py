@@ -98,7 +98,8 @@ class ls_reg_params(C.Structure):
     _fields_ = [("iters", C.c_int32), ("lr_rot", C.c_float), ("lr_trans", C.c_float), ("beta1", C.c_float),
                 ("beta2", C.c_float), ("adam_eps", C.c_float), ("exit_rel_tol", C.c_float),
                 ("exit_patience", C.c_int32), ("loss_kind", C.c_int32), ("track", ls_loss_params),
-                ("exposure", C.c_int32), ("lr_exposure", C.c_float), ("joint", C.c_int32), ("top_k", C.c_int32)]
+                ("exposure", C.c_int32), ("lr_exposure", C.c_float), ("joint", C.c_int32), ("exit_mode", C.c_int32),
+                ("top_k", C.c_int32)]
 
 
 class ls_prune_array(C.Structure):

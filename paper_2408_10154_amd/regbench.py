@@ -64,7 +64,7 @@ def _pct(x, q):
     return float(np.percentile(np.asarray(x, np.float64), q))
 
 
-def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0, top_k=0):
+def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0, top_k=0, exit_mode="loss"):
     """One pair at a time through ls_register_pair; latency of pair k counts
     from the start of the run (all requests present at t = 0)."""
     torch.cuda.synchronize()
@@ -72,7 +72,8 @@ def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0, to
     results, done = [], []
     for p in pairs:
         results.append(REG.register_pair(*p["args"], params=REG.default_params(
-            iters, loss=loss, exit_rel_tol=exit_rel_tol, exit_patience=exit_patience, top_k=top_k)))
+            iters, loss=loss, exit_rel_tol=exit_rel_tol, exit_patience=exit_patience, top_k=top_k,
+            exit_mode=exit_mode)))
         done.append(time.perf_counter() - t0)
     total = time.perf_counter() - t0
     return dict(seconds=total, pairs_per_s=len(pairs) / total, p50_s=_pct(done, 50), p99_s=_pct(done, 99),
@@ -80,15 +81,16 @@ def run_plain(pairs, iters=200, loss="l1", exit_rel_tol=0.0, exit_patience=0, to
 
 
 def run_batched(pairs, iters=200, loss="l1", chunk_iters=16, use_graphs=True, max_slots=64, budget=200 << 30,
-                exit_rel_tol=0.0, exit_patience=0):
+                exit_rel_tol=0.0, exit_patience=0, exit_mode="loss"):
     """Every pair submitted at t = 0 to one server."""
     from .serve import Server
 
     with Server(budget_bytes=budget, max_slots=max_slots, chunk_iters=chunk_iters, use_graphs=use_graphs) as sv:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        tickets = [sv.submit(*p["args"], params=REG.default_params(iters, loss=loss, exit_rel_tol=exit_rel_tol,
-                                                                   exit_patience=exit_patience)) for p in pairs]
+        prm = REG.default_params(iters, loss=loss, exit_rel_tol=exit_rel_tol, exit_patience=exit_patience,
+                                 exit_mode=exit_mode)
+        tickets = [sv.submit(*p["args"], params=prm) for p in pairs]
         results = [sv.wait(t) for t in tickets]
         total = time.perf_counter() - t0
         st = sv.stats()
@@ -145,6 +147,16 @@ def single_pair_spec(seed=2):
     return dict(seed=seed, n_p=150_000, n_q=120_000, views_p=8, views_q=8, layout="views")
 
 
+def _exit_rule(text):
+    """'off' -> ("loss", 0, 0); 'loss:TOL:PATIENCE' / 'step:RATIO:PATIENCE'."""
+    if text == "off":
+        return "loss", 0.0, 0
+    kind, tol, patience = text.split(":")
+    if kind not in ("loss", "step"):
+        raise ValueError(f"unknown early exit rule {text!r}")
+    return kind, float(tol), int(patience)
+
+
 def main(argv=None):
     """Command-line runs of the registration workloads (one JSON line each),
     e.g. under a kernel-trace profiler:
@@ -166,8 +178,9 @@ def main(argv=None):
     ap.add_argument("--loss", choices=["tracking", "l1"], default="l1")
     ap.add_argument("--layout", choices=["views", "x_split"], default="views",
                     help="submap split of the synthetic pairs (see synth.registration_pair)")
-    ap.add_argument("--exit", type=float, nargs=2, default=[0.0, 0], metavar=("REL_TOL", "PATIENCE"),
-                    help="per-view early exit (0 0: off)")
+    ap.add_argument("--exit", nargs="+", default=["off"],
+                    help="per-view early exit rules to run in turn: 'off', 'loss:REL_TOL:PATIENCE' or "
+                         "'step:RATIO:PATIENCE' (set and single workloads)")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     if a.workload == "single":
@@ -188,15 +201,21 @@ def main(argv=None):
                     res, _ = run_stream_plain(specs, pairs, iters=a.iters, loss=a.loss)
                 else:
                     res, _ = run_stream(specs, pairs, iters=a.iters, loss=a.loss, max_active_pixels=cap)
-            else:
-                run = run_plain if mode == "plain" else run_batched
-                res, _ = run(pairs, iters=a.iters, loss=a.loss, exit_rel_tol=a.exit[0], exit_patience=int(a.exit[1]))
-            extra = dict(rate=a.rate, requests=a.requests) if a.workload == "stream" else dict(exit=a.exit)
-            if mode == "batched" and a.workload == "stream":
-                extra["max_active_pixels"] = cap
-            print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters, **extra,
-                                  **{k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()})),
-                  flush=True)
+                extra = dict(rate=a.rate, requests=a.requests)
+                if mode == "batched":
+                    extra["max_active_pixels"] = cap
+                print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters, **extra,
+                                      **{k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()})),
+                      flush=True)
+                continue
+            run = run_plain if mode == "plain" else run_batched
+            for rule in a.exit:
+                kind, tol, patience = _exit_rule(rule)
+                res, _ = run(pairs, iters=a.iters, loss=a.loss, exit_rel_tol=tol, exit_patience=patience,
+                             exit_mode=kind)
+                print(json.dumps(dict(workload=a.workload, mode=mode, iters=a.iters, exit=rule,
+                                      **{k: round(v, 4) if isinstance(v, float) else v for k, v in res.items()})),
+                      flush=True)
 
 
 if __name__ == "__main__":

@@ -42,7 +42,7 @@ def keyframe_targets(g: GaussianSet, cam: dict, c2ws: np.ndarray):
 
 def default_params(iters=200, lr_rot=0.015, lr_trans=0.005, exit_rel_tol=0.0, exit_patience=0, loss="l1",
                    lambda_c=0.6, inlier_k=50.0, alpha_power=3, exposure=False,
-                   lr_exposure=0.1, joint=False, top_k=0) -> L.ls_reg_params:
+                   lr_exposure=0.1, joint=False, top_k=0, exit_mode="loss") -> L.ls_reg_params:
     """Registration settings: real-data learning rates of the paper's
     loop-closure table by default; early exit off unless exit_patience > 0.
     loss "l1" (the default) is the registration loss of Sec. 3.2, the plain
@@ -53,12 +53,17 @@ def default_params(iters=200, lr_rot=0.015, lr_trans=0.005, exit_rel_tol=0.0, ex
     pose at lr_exposure (the supplement's 0.1).  joint: one transform shared
     by all views instead of per-view estimates and their fusion (a
     comparison; ls_register_pair only).  top_k: keyframes kept per direction
-    (0: all), ranked by rendered co-visibility (ls_register_pair only)."""
+    (0: all), ranked by rendered co-visibility (ls_register_pair only).
+    exit_mode: "loss" (plateau of the loss, exit_rel_tol relative) or "step"
+    (Adam step below exit_rel_tol learning rates) when exit_patience > 0."""
     if loss not in ("tracking", "l1"):
         raise ValueError(f"loss must be 'tracking' or 'l1', not {loss!r}")
+    if exit_mode not in ("loss", "step"):
+        raise ValueError(f"exit_mode must be 'loss' or 'step', not {exit_mode!r}")
     return L.ls_reg_params(iters, lr_rot, lr_trans, 0.9, 0.999, 1e-8, exit_rel_tol, exit_patience,
                            1 if loss == "tracking" else 0, L.ls_loss_params(lambda_c, inlier_k, alpha_power, 0),
-                           1 if exposure else 0, lr_exposure, 1 if joint else 0, int(top_k))
+                           1 if exposure else 0, lr_exposure, 1 if joint else 0, 1 if exit_mode == "step" else 0,
+                           int(top_k))
 
 
 def make_pair(P: GaussianSet, Q: GaussianSet, cam: dict, c2w_p, c2w_q, rgbP, depthP, rgbQ, depthQ):

@@ -139,6 +139,63 @@ def test_exposure_with_zero_rate_is_bitwise_the_plain_path(gpu):
     assert np.all(a["exposure"] == 0.0)
 
 
+def test_early_exit_rules_reduce_to_fixed_iteration_counts(gpu):
+    """The two early-exit rules at their limits, bit for bit:
+    loss rule, rel_tol 1: no loss is below 0, so every view stalls from its
+      second call on and freezes after p Adam steps: the run equals p
+      iterations without early exit;
+    step rule, ratio 1e30: every step counts as small, so a view freezes on
+      its p-th call after p - 1 steps: the run equals p - 1 iterations;
+    step rule, ratio 0: no step is below 0, so nothing exits and the run
+      equals the full iteration count."""
+    from paper_2408_10154_amd import register as REG
+
+    d = synth.registration_pair(9, 3000, 2500, views_p=2, views_q=3, width=96, height=72, f=70)
+    P_ = 12
+
+    def run(**kw):
+        r = _gpu_register_targets(d, *_exposed_targets(d, 1.0, 0.0), REG.default_params(**kw))
+        assert r["status"] == 0
+        return r
+
+    def same(a, b):
+        np.testing.assert_array_equal(a["T"], b["T"])
+        np.testing.assert_array_equal(a["per_view"], b["per_view"])
+        np.testing.assert_array_equal(a["residual"], b["residual"])
+
+    loss_rule = run(iters=40, exit_rel_tol=1.0, exit_patience=P_, exit_mode="loss")
+    same(loss_rule, run(iters=P_))
+    assert loss_rule["iters"] == P_
+    step_rule = run(iters=40, exit_rel_tol=1e30, exit_patience=P_, exit_mode="step")
+    same(step_rule, run(iters=P_ - 1))
+    assert step_rule["iters"] == P_ - 1
+    never = run(iters=40, exit_rel_tol=0.0, exit_patience=P_, exit_mode="step")
+    same(never, run(iters=40))
+    assert never["iters"] == 40
+
+
+def test_step_exit_on_the_pair_workload(gpu):
+    """Step rule (Adam step below 0.1 learning rates for 10 iterations) on the
+    single-pair registration workload with the 200-iteration limit: the
+    transform is recovered as without early exit, and the run reports the
+    iterations of its longest-running view."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.render import GaussianSet
+
+    d = synth.registration_pair(2, 150000, 120000, views_p=8, views_q=8, width=640, height=480, f=500,
+                                layout="views")
+    P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
+    rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
+    rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
+    args = (P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ)
+    r = REG.register_pair(*args, params=REG.default_params(200, exit_rel_tol=0.1, exit_patience=10,
+                                                           exit_mode="step"))
+    assert r["status"] == 0 and 1 <= r["iters"] <= 200
+    rot, tr = _errs(r["T"], d["T_gt"])
+    print("step exit: iters", r["iters"], "errors", (rot, tr))
+    assert rot < 0.5 and tr < 1.0, (rot, tr)
+
+
 def test_exposure_tiny_pair_matches_oracle(gpu):
     """The tiny room with Q's keyframe under gain 1.2 and offset 0.03: the
     GPU and the oracle (both fitting exposure coefficients, plain L1) agree

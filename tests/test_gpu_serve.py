@@ -173,6 +173,28 @@ def test_reused_server_state_matches_plain(pairs):
         assert r["status"] == 0 and _same(r, _plain(p))
 
 
+def test_server_step_exit_matches_plain(pairs):
+    """Early exit by the step rule in the serving loop: the pairs' views
+    freeze at the same iterations as in ls_register_pair (the rule runs in
+    the same kernel on per-view state), so the results are the same bits;
+    a request with the loss rule is refused by a server that runs the step
+    rule."""
+    from paper_2408_10154_amd import lib as L
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.serve import Server
+
+    prm = REG.default_params(ITERS, exit_rel_tol=0.2, exit_patience=5, exit_mode="step")
+    plain = [REG.register_pair(*p["args"], params=prm) for p in pairs]
+    with Server(max_slots=8, chunk_iters=8) as sv:
+        ts = [sv.submit(*p["args"], params=prm) for p in pairs]
+        with pytest.raises(L.LsError):
+            sv.submit(*pairs[0]["args"], params=REG.default_params(ITERS, exit_rel_tol=0.2, exit_patience=5))
+        rs = [sv.wait(t) for t in ts]
+    for r, b in zip(rs, plain):
+        assert r["status"] == 0 and b["status"] == 0 and _same(r, b)
+    print("plain iterations", [b["iters"] for b in plain])
+
+
 def test_submit_orders_reads_after_the_producer_stream(pairs):
     """A request whose Gaussians are written on a side stream just before
     submitting (behind a chain of long kernels): the server's finiteness
