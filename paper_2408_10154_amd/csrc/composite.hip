@@ -331,19 +331,6 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
   out_n[pix] = nlast;
 }
 
-// Sum over each 16-lane row of the wave; every lane of a row gets its row sum.
-__device__ __forceinline__ float row_sum16(float v) {
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0xB1, 0xF, 0xF, true));   // quad_perm 1,0,3,2
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x4E, 0xF, 0xF, true));   // quad_perm 2,3,0,1
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x141, 0xF, 0xF, true));  // row_half_mirror
-  v += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), 0x140, 0xF, 0xF, true));  // row_mirror
-  // Keep the last add in every lane: callers store the sum from one lane per
-  // row, and sinking the add into that branch splits each fused DPP add into
-  // a DPP move plus an add (an empty asm that reads and writes v, no code).
-  asm volatile("" : "+v"(v));
-  return v;
-}
-
 // Lane exchanges of gfx950 that trade halves of two registers:
 // permlane32_swap gives x the lower 32 lanes of y in place of its upper 32,
 // permlane16_swap gives x the even 16-lane rows of y in place of its odd rows
@@ -358,34 +345,77 @@ __device__ __forceinline__ float swap16_sum(float x, float y) {
   return __uint_as_float(r[0]) + __uint_as_float(r[1]);
 }
 
-// Slot of the value held by 16-lane row r after wave_sums (see below).
-__device__ __forceinline__ int wave_sum_slot(int lane) {
-  const int r = lane >> 4;
-  return ((r & 1) << 1) | (r >> 1);
+// Swap-add of two registers between the two halves of each group of 2m
+// lanes (m = 8: row_ror:8 pairs lane i with i +- 8 of its row; m = 4:
+// row_half_mirror pairs lane i with 7 - i of its 8-lane half): lanes of the
+// lower m keep a's value summed with a's partner, lanes of the upper m keep
+// b's.  With a == b this is a plain add of the partner (one instruction).
+template <int kCtrl, int kM>
+__device__ __forceinline__ float pair_sum(float a, float b, int lane) {
+  const bool lo = (lane & kM) == 0;
+  const float s = lo ? a : b, t = lo ? b : a;
+  return s + __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(t), kCtrl, 0xF, 0xF, true));
 }
 
-// Sums of N values (N even) over the 64 lanes of the wave, by a transposing
-// reduction: two 32-lane swaps and adds pack values 2k, 2k+1 into register k
-// (half a wave each), two 16-lane swaps and adds pack four values into one
-// register (a row each), and a row sum (DPP) finishes each register.  N values
-// cost N/2 + 2 ceil(N/4) swaps and 4 ceil(N/4) DPP adds instead of 4 N DPP adds
-// for row sums alone.  Every lane of row r of out[i] holds the sum of value
-// 4 i + wave_sum_slot(r); when N/2 is odd the last register is paired with
-// itself and its rows 1 and 3 repeat rows 0 and 2 (slots >= N, to be ignored).
-// The whole wave must be active.
+// Sums of N values (N even, N <= 16) over the 64 lanes of the wave, by a
+// transposing reduction that halves the lanes holding each value at every
+// level while packing more values per register:
+//  - 32-lane swaps and adds: value 2k in the lower half of register h[k],
+//    2k + 1 in the upper half;
+//  - 16-lane swaps and adds: four values per register q[i], one per row
+//    (value 4 i + slot(r) in row r, slot = 0, 2, 1, 3);
+//  - within rows, swap-adds 8 lanes apart (q[0] with q[1], q[2] with q[3]),
+//    then 4 apart, leave one value per 4-lane group of one register, and two
+//    DPP adds sum each group.
+// The result: the lane that wave_value() names holds the total of that
+// value.  N = 10 costs 5 + 3 swaps and 17 VALU adds or selects; a plain row
+// sum after the 16-lane level would take 20 adds.  When N/2 is odd the last
+// 16-lane pair is the register with itself (its rows 1 and 3 repeat rows 0
+// and 2), and with fewer than three row registers the 8-apart level pairs a
+// register with itself: those duplicates are not named by wave_value().  The
+// whole wave must be active.
 template <int N>
-__device__ __forceinline__ void wave_sums(const float* g, float* out) {
-  static_assert(N % 2 == 0, "an even number of values");
+__device__ __forceinline__ float wave_sums(const float* g, int lane) {
+  static_assert(N % 2 == 0 && N <= 16, "an even number of values, at most 16");
   constexpr int H = N / 2, O = (H + 1) / 2;
-  float h[H];
+  float h[H], q[O];
 #pragma unroll
   for (int k = 0; k < H; ++k) h[k] = swap32_sum(g[2 * k], g[2 * k + 1]);
 #pragma unroll
-  for (int i = 0; i < O; ++i) out[i] = row_sum16(swap16_sum(h[2 * i], h[2 * i + 1 < H ? 2 * i + 1 : 2 * i]));
+  for (int i = 0; i < O; ++i) q[i] = swap16_sum(h[2 * i], h[2 * i + 1 < H ? 2 * i + 1 : 2 * i]);
+  constexpr int kRor8 = 0x128, kHalfMirror = 0x141, kQuad1032 = 0xB1, kQuad2301 = 0x4E;
+  const float z0 = pair_sum<kRor8, 8>(q[0], O > 1 ? q[O > 1 ? 1 : 0] : q[0], lane);
+  const float z1 = O > 2 ? pair_sum<kRor8, 8>(q[O > 2 ? 2 : 0], q[O > 3 ? 3 : (O > 2 ? 2 : 0)], lane) : z0;
+  float y = pair_sum<kHalfMirror, 4>(z0, z1, lane);
+  y += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), kQuad1032, 0xF, 0xF, true));
+  y += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), kQuad2301, 0xF, 0xF, true));
+  return y;
+}
+
+// The value whose total lane `lane` holds after wave_sums<N>, or -1 for the
+// lanes that hold none, a duplicate, or one of the same group (exactly one
+// lane per value is named).
+template <int N>
+__device__ __forceinline__ int wave_value(int lane) {
+  constexpr int O = (N / 2 + 1) / 2;
+  if (lane & 3) return -1;
+  const int r = lane >> 4, grp = (lane >> 2) & 3;
+  // 8 apart: lanes 0-7 of a row keep q[0] (q[2]), 8-15 q[1] (q[3]); 4 apart:
+  // groups 0 and 2 keep the first register's, 1 and 3 the second's
+  int qi;
+  if (O > 2)
+    qi = (grp & 1) ? ((grp >> 1) ? 3 : 2) : (grp >> 1);
+  else if (O == 2)
+    qi = (grp & 1) ? -1 : (grp >> 1);
+  else
+    qi = grp == 0 ? 0 : -1;
+  if (qi < 0 || qi >= O) return -1;
+  const int v = 4 * qi + (((r & 1) << 1) | (r >> 1));
+  return v < N ? v : -1;
 }
 
 constexpr int kBwdChunk = 64;   // list entries staged per round (full mode)
-constexpr int kWaveSlots = 4 * ((kGrad2D / 2 + 1) / 2);  // floats per wave partial (wave_sums slots)
+constexpr int kWaveSlots = 4 * ((kGrad2D / 2 + 1) / 2);  // floats per wave partial (a slot per value index)
 constexpr int kPartStride = 4 * kWaveSlots + 1;         // floats per entry: 4 wave partials, odd against bank conflicts
 
 // Backward.  Per pixel, walking the list from n_last - 1 down to 0 with the
@@ -519,7 +549,7 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wslot = w * kWaveSlots + wave_sum_slot(lane);  // where this lane's row stores its wave sums
+  const int wval = wave_value<kGrad2D>(lane);  // the value whose wave sum this lane stores, or -1
   const int tx0 = c.x0, ty0 = c.y0;
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
@@ -538,8 +568,7 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     const uint32_t myj = lane < kBwdChunk ? slist[w][lane] : 0u;  // the band's list in a register
     auto bstep = [&](int j, const float4& a, const float4& b, const float4& col) {
-      float* pj = part + j * kPartStride + wslot;
-      const bool lead = (lane & 15) == 0;
+      float* pj = part + j * kPartStride + w * kWaveSlots + max(wval, 0);  // written only where wval >= 0
       const int k = chunk + j - start;  // list position
       const float dx = fx - a.x, dy = fy - a.y;
       const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
@@ -560,15 +589,10 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
         g[7] = wgt * px.gR;
         g[8] = wgt * px.gG;
         g[9] = wgt * px.gB;
-        float out[kWaveSlots / 4];
-        wave_sums<kGrad2D>(g, out);
-        if (lead) {
-#pragma unroll
-          for (int i = 0; i < kWaveSlots / 4; ++i) pj[4 * i] = out[i];
-        }
-      } else if (lead) {
-#pragma unroll
-        for (int i = 0; i < kWaveSlots / 4; ++i) pj[4 * i] = 0.f;
+        const float out = wave_sums<kGrad2D>(g, lane);
+        if (wval >= 0) *pj = out;
+      } else if (wval >= 0) {
+        *pj = 0.f;
       }
     };
     // records read one entry ahead into alternating register sets (as in the forward)
@@ -679,7 +703,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDe
 // so the pose gradient is deterministic and independent of the other renders.
 constexpr int kPoseChunk = 64;                    // entries staged per round
 constexpr int kPoseRow = 6;                       // sums giving du, dv, dA, dB, dC, d(depth weight)
-constexpr int kPoseSlots = 4 * ((kPoseRow / 2 + 1) / 2);  // floats per wave partial (wave_sums slots)
+constexpr int kPoseSlots = 4 * ((kPoseRow / 2 + 1) / 2);  // floats per wave partial (a slot per value index)
 constexpr int kPoseStride = 4 * kPoseSlots + 1;   // floats per entry: 4 wave partials, odd against bank conflicts
 constexpr int kPoseQueue = kBlock;                // queued entries per Jacobian round
 
@@ -713,7 +737,7 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int wslot = w * kPoseSlots + wave_sum_slot(lane);
+  const int wval = wave_value<kPoseRow>(lane);
   const int tx0 = c.x0, ty0 = c.y0;
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
@@ -735,14 +759,11 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     const uint32_t myj = lane < kPoseChunk ? slist[w][lane] : 0u;  // the band's list in a register
     auto pstep = [&](int j, const float4& a, const float4& b, const float4& col) {
-      float* pj = part + j * kPoseStride + wslot;
-      const bool lead = (lane & 15) == 0;
+      float* pj = part + j * kPoseStride + w * kPoseSlots + max(wval, 0);  // written only where wval >= 0
       const int k = chunk + j - start;
       const float dx = fx - a.x, dy = fy - a.y;
       const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
-      float out[kPoseSlots / 4];
-#pragma unroll
-      for (int i = 0; i < kPoseSlots / 4; ++i) out[i] = 0.f;
+      float out = 0.f;
       if (__ballot(e.act) != 0ull) {
         float wgt, ds, dop;
         bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
@@ -754,12 +775,9 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
         g[3] = g[0] * dy;
         g[4] = g[1] * dy;
         g[5] = wgt * px.gD;
-        wave_sums<kPoseRow>(g, out);
+        out = wave_sums<kPoseRow>(g, lane);
       }
-      if (lead) {
-#pragma unroll
-        for (int i = 0; i < kPoseSlots / 4; ++i) pj[4 * i] = out[i];
-      }
+      if (wval >= 0) *pj = out;
     };
     // records read one entry ahead into alternating register sets (as in the forward)
     int jA = (int)__builtin_amdgcn_readlane(myj, cw > 0 ? cw - 1 : 0), jB = 0;
@@ -837,13 +855,9 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
       }
       // fixed-order reduction of this round over the block
       {
-        static_assert(kPoseAcc % 4 == 0, "pose sums fill whole slot groups");
-        float out[kPoseAcc / 4];
-        wave_sums<kPoseAcc>(pc, out);
-        if ((lane & 15) == 0) {
-#pragma unroll
-          for (int i = 0; i < kPoseAcc / 4; ++i) wred[w][4 * i + wave_sum_slot(lane)] = out[i];
-        }
+        const float out = wave_sums<kPoseAcc>(pc, lane);
+        const int v = wave_value<kPoseAcc>(lane);
+        if (v >= 0) wred[w][v] = out;
       }
       __syncthreads();
       if (t < kPoseAcc) total += (wred[0][t] + wred[1][t]) + (wred[2][t] + wred[3][t]);
