@@ -17,21 +17,39 @@ __global__ void k_fill_i32(int32_t* __restrict__ p, int64_t n, int32_t v) {
   for (int64_t k = i; k < n; k += stride) p[k] = v;
 }
 
-// Depth keys: FP32 depth bits (positive depths order like their bits);
-// culled items get 0xFFFFFFFF and sort last.
-__global__ void k_depth_keys(const float4* __restrict__ rec, const int32_t* __restrict__ tiles, int64_t M,
-                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= M) return;
-  const float z = rec[i * 3 + 1].z;
-  keys[i] = tiles[i] > 0 ? __float_as_uint(z) : 0xFFFFFFFFu;
-  vals[i] = (uint32_t)i;
-}
-
 __device__ __forceinline__ int sort_count(const int32_t* n_dev, int64_t n_static, int64_t cap) {
   int64_t n = n_static;
   if (n_dev) n = min((int64_t)n_dev[0], cap);
   return (int)n;
+}
+
+// Digit histogram of one sort block's keys (kSortItems registers per thread,
+// rounds of them valid, nb keys in all) into LDS h, then to
+// hist[d * nblocks + block] (digit-major).  Equal digits within a wave are
+// merged before the LDS atomic.
+template <int kBits>
+__device__ __forceinline__ void block_digit_hist(const uint32_t (&key)[kSortItems], int rounds, int nb, int shift,
+                                                 uint32_t* h, uint32_t* __restrict__ hist, int nblocks) {
+  constexpr int kBins = 1 << kBits;
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r < rounds && r * kSortThreads < nb) {  // uniform; a guard, not a break, so the loop unrolls
+      const bool valid = r * kSortThreads + (int)threadIdx.x < nb;
+      const uint32_t d = (key[r] >> shift) & (uint32_t)(kBins - 1);
+      // aggregate equal digits within the wave before touching LDS
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      if (valid && lane == (int)__builtin_ctzll(peers)) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kBins; i += kSortThreads) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
 }
 
 // Per-block digit histogram of kBits-bit digits, stored digit-major:
@@ -54,25 +72,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
     key[r] = (r < rounds && i < nb) ? keys[base + i] : 0u;
   }
   __syncthreads();
-  const int lane = threadIdx.x & 63;
+  block_digit_hist<kBits>(key, rounds, nb, shift, h, hist, nblocks);
+}
+
+// Depth keys of one sort block's items (FP32 depth bits: positive depths
+// order like their bits; culled items get 0xFFFFFFFF and sort last), item ids
+// as values, and the histogram of the first radix pass's digits, so that pass
+// needs no histogram launch of its own.
+template <int kBits>
+__global__ __launch_bounds__(kSortThreads) void k_depth_keys(const float4* __restrict__ rec,
+                                                             const int32_t* __restrict__ tiles, int64_t M,
+                                                             uint32_t* __restrict__ keys, uint32_t* __restrict__ vals,
+                                                             uint32_t* __restrict__ hist, int nblocks, int rounds) {
+  constexpr int kBins = 1 << kBits;
+  __shared__ uint32_t h[kBins];
+  for (int i = threadIdx.x; i < kBins; i += kSortThreads) h[i] = 0;
+  const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
+  const int nb = base < M ? (int)min((int64_t)rounds * kSortThreads, M - base) : 0;
+  uint32_t key[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    if (r < rounds && r * kSortThreads < nb) {  // uniform; a guard, not a break, so the loop unrolls
-      const bool valid = r * kSortThreads + (int)threadIdx.x < nb;
-      const uint32_t d = (key[r] >> shift) & (uint32_t)(kBins - 1);
-      // aggregate equal digits within the wave before touching LDS
-      uint64_t peers = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < kBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      if (valid && lane == (int)__builtin_ctzll(peers)) atomicAdd(&h[d], (uint32_t)__popcll(peers));
+    const int i = r * kSortThreads + threadIdx.x;
+    key[r] = 0u;
+    if (r < rounds && i < nb) {
+      const int64_t it = base + i;
+      key[r] = tiles[it] > 0 ? __float_as_uint(rec[it * 3 + 1].z) : 0xFFFFFFFFu;
+      keys[it] = key[r];
+      vals[it] = (uint32_t)it;
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < kBins; i += kSortThreads) hist[(int64_t)i * nblocks + blockIdx.x] = h[i];
+  block_digit_hist<kBits>(key, rounds, nb, 0, h, hist, nblocks);
 }
 
 // Block-wide exclusive scan of one value per thread (256 threads); returns
@@ -387,15 +417,40 @@ __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, c
   }
 }
 
-// [start, end) of each tile's run in the sorted instance keys.
+// [start, end) of each tile's run in the sorted instance keys, for every one
+// of the T tiles, empty tiles [0, 0): the thread at the start of a run also
+// clears the tiles between the previous run's tile and its own (the first
+// thread those before the first run, the last thread those after the last
+// run); with no instances, thread t clears tile t.  The grid covers
+// max(capacity, T) threads.
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const int32_t* __restrict__ count,
-                              int32_t* __restrict__ range) {
+                              int32_t* __restrict__ range, int T) {
   const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t n = count[0];
+  if (n == 0) {
+    if (k < T) {
+      range[2 * k] = 0;
+      range[2 * k + 1] = 0;
+    }
+    return;
+  }
   if (k >= n) return;
-  const uint32_t t = keys[k];
-  if (k == 0 || keys[k - 1] != t) range[2 * (int64_t)t] = (int32_t)k;
-  if (k == n - 1 || keys[k + 1] != t) range[2 * (int64_t)t + 1] = (int32_t)(k + 1);
+  const int64_t t = keys[k];
+  if (k == 0 || keys[k - 1] != (uint32_t)t) {
+    for (int64_t u = k == 0 ? 0 : (int64_t)keys[k - 1] + 1; u < t; ++u) {
+      range[2 * u] = 0;
+      range[2 * u + 1] = 0;
+    }
+    range[2 * t] = (int32_t)k;
+  }
+  if (k == n - 1 || keys[k + 1] != (uint32_t)t) {
+    range[2 * t + 1] = (int32_t)(k + 1);
+    if (k == n - 1)
+      for (int64_t u = t + 1; u < T; ++u) {
+        range[2 * u] = 0;
+        range[2 * u + 1] = 0;
+      }
+  }
 }
 
 }  // namespace ls
@@ -412,9 +467,10 @@ void launch_fill_i32(int32_t* p, int64_t n, int32_t v, hipStream_t s) {
 template <int kBits>
 static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout, uint32_t* vout, const int32_t* n_dev,
                        int64_t n_static, int64_t cap, int shift, uint32_t* hist, uint32_t* digit_total, int nblocks,
-                       int rounds, hipStream_t s) {
-  hipLaunchKernelGGL(k_sort_hist<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift,
-                     hist, nblocks, rounds);
+                       int rounds, hipStream_t s, bool hist_done = false) {
+  if (!hist_done)
+    hipLaunchKernelGGL(k_sort_hist<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift,
+                       hist, nblocks, rounds);
   hipLaunchKernelGGL(k_scan_rows, dim3(1 << kBits), dim3(256), 0, s, hist, (int64_t)nblocks, digit_total);
   hipLaunchKernelGGL(k_sort_scatter<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_dev,
                      n_static, cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_total, rounds);
@@ -441,10 +497,11 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const int rd = sort_rounds(M), nbd = (int)sort_blocks(M);
   uint32_t* digit_base = bsum + nbd + 8;  // digit totals (up to kMaxSortBins) after the block sums
-  hipLaunchKernelGGL(k_depth_keys, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, s, rec4, tiles, M, dk0, dv0);
+  hipLaunchKernelGGL(k_depth_keys<kDepthDigitBits>, dim3(nbd), dim3(kSortThreads), 0, s, rec4, tiles, M, dk0, dv0,
+                     hist, nbd, rd);
   uint32_t *ka = dk0, *va = dv0, *kb = dk1, *vb = dv1;
   for (int shift = 0; shift < 32; shift += kDepthDigitBits) {
-    radix_pass<kDepthDigitBits>(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, rd, s);
+    radix_pass<kDepthDigitBits>(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, rd, s, shift == 0);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
@@ -470,9 +527,9 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
     std::swap(ek, ok);
     std::swap(ev, ov);
   }
-  launch_fill_i32(range, 2 * (int64_t)T, 0, s);
-  if (cap > 0)
-    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((cap + 255) / 256)), dim3(256), 0, s, (const uint32_t*)tile_of,
-                       (const int32_t*)count, range);
+  const int64_t nr = std::max<int64_t>(cap, T);
+  if (nr > 0)
+    hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, (const uint32_t*)tile_of,
+                       (const int32_t*)count, range, T);
 }
 }  // namespace ls
