@@ -136,7 +136,9 @@ ls_status ls_batch_offsets(const ls_batch* b, int64_t* item_off, int64_t* pix_of
  *   tiles  [M]: number of tiles of the item's tile rectangle, 0 = culled
  *   aux    [M][12] or NULL: camera-space mean (x, y, z) and covariance
  *          (xx, xy, xz, yy, yz, zz), 0, 0, 0 - kept by the forward for the
- *          backward; required by ls_render_bwd*.  16-byte aligned. */
+ *          backward; required by ls_render_bwd*.  16-byte aligned.
+ * rec and aux of a culled item are left as they were (only its radius and
+ * tiles, 0, are written). */
 typedef struct {
   float* rec;
   int32_t* radius;

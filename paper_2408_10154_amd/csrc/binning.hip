@@ -8,6 +8,7 @@
 #include "common.h"
 
 #include <algorithm>
+#include <cstdlib>
 
 namespace ls {
 
@@ -254,16 +255,85 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
   }
 }
 
-// Per-block (4096 items) sums of the tile counts of depth-sorted items.
+// Compaction of the items that have tiles before the depth sort (most items
+// of a registration view lie outside it): kept items per sort block ...
+__global__ __launch_bounds__(kSortThreads) void k_keep_count(const int32_t* __restrict__ tiles, int64_t M, int rounds,
+                                                             uint32_t* __restrict__ bsum) {
+  __shared__ uint32_t ws[4];
+  const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
+  uint32_t c = 0;
+  for (int i = 0; i < rounds; ++i) {
+    const int64_t k = base + i * kSortThreads + threadIdx.x;
+    if (k < M && tiles[k] > 0) ++c;
+  }
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) bsum[blockIdx.x] = ws[0] + ws[1] + ws[2] + ws[3];
+}
+
+// ... then their depth keys and item ids, written in item order from the
+// block's offset (the sum of the preceding blocks' counts, formed here); block
+// 0 writes the kept total to *nkeep.  The stable sort then orders them exactly
+// as the uncompacted keys (where culled items sort last).
+__global__ __launch_bounds__(kSortThreads) void k_depth_keys_compact(const float4* __restrict__ rec,
+                                                                     const int32_t* __restrict__ tiles, int64_t M,
+                                                                     int rounds, const uint32_t* __restrict__ bsum,
+                                                                     int nbd, uint32_t* __restrict__ keys,
+                                                                     uint32_t* __restrict__ vals,
+                                                                     int32_t* __restrict__ nkeep) {
+  __shared__ uint32_t wsum[4], wtot[4];
+  const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
+  const int upto = blockIdx.x == 0 ? nbd : (int)blockIdx.x;
+  uint32_t before = 0, total = 0;
+  for (int b = threadIdx.x; b < upto; b += kSortThreads) {
+    const uint32_t v = bsum[b];
+    total += v;
+    if (b < (int)blockIdx.x) before += v;
+  }
+  for (int off = 32; off > 0; off >>= 1) {
+    before += __shfl_xor(before, off, 64);
+    total += __shfl_xor(total, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    wsum[threadIdx.x >> 6] = before;
+    wtot[threadIdx.x >> 6] = total;
+  }
+  __syncthreads();
+  uint32_t run = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+  if (blockIdx.x == 0 && threadIdx.x == 0) *nkeep = (int32_t)(wtot[0] + wtot[1] + wtot[2] + wtot[3]);
+  __syncthreads();
+  for (int i = 0; i < rounds; ++i) {
+    const int64_t k = base + i * kSortThreads + threadIdx.x;
+    const bool keep = k < M && tiles[k] > 0;
+    uint32_t tot;
+    const uint32_t x = block_excl_scan(keep ? 1u : 0u, wsum, &tot);
+    if (keep) {
+      keys[run + x] = __float_as_uint(rec[k * 3 + 1].z);
+      vals[run + x] = (uint32_t)k;
+    }
+    run += tot;
+  }
+}
+
+// Items in the depth order: M, or the kept count when the items were
+// compacted before the sort.
+__device__ __forceinline__ int64_t order_len(int64_t M, const int32_t* n_dev) {
+  return n_dev ? min((int64_t)n_dev[0], M) : M;
+}
+
+// Per-block (rounds x 256 items) sums of the tile counts of depth-sorted items.
 __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __restrict__ order,
-                                                            const int32_t* __restrict__ tiles, int64_t M, int rounds,
+                                                            const int32_t* __restrict__ tiles, int64_t M,
+                                                            const int32_t* n_dev, int rounds,
                                                             uint32_t* __restrict__ bsum) {
   __shared__ uint32_t ws[4];
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
+  const int64_t n = order_len(M, n_dev);
   uint32_t s = 0;
   for (int i = 0; i < rounds; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
-    if (k < M) s += (uint32_t)tiles[order[k]];
+    if (k < n) s += (uint32_t)tiles[order[k]];
   }
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off, 64);
   if ((threadIdx.x & 63) == 0) ws[threadIdx.x >> 6] = s;
@@ -278,13 +348,15 @@ __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __re
 // Block 0 also writes count = {min(I, cap), I > cap, min(I, INT32_MAX), 0}.
 __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __restrict__ order,
                                                           const int32_t* __restrict__ tiles, int64_t M,
-                                                          const uint32_t* __restrict__ bsum, int nbd,
+                                                          const int32_t* n_dev, const uint32_t* __restrict__ bsum,
+                                                          int nbd,
                                                           uint32_t* __restrict__ offs, int32_t* __restrict__ count,
                                                           int64_t cap, int rounds, uint32_t* __restrict__ first,
                                                           int64_t nspan) {
   __shared__ uint32_t wsum[4];
   __shared__ uint64_t wtot[4];
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
+  const int64_t n = order_len(M, n_dev);
   // the offset of this block (and, for block 0, the total over all blocks)
   const int upto = blockIdx.x == 0 ? nbd : (int)blockIdx.x;
   uint64_t before = 0, total = 0;
@@ -307,10 +379,10 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
   __syncthreads();
   for (int i = 0; i < rounds; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
-    const uint32_t c = k < M ? (uint32_t)tiles[order[k]] : 0u;
+    const uint32_t c = k < n ? (uint32_t)tiles[order[k]] : 0u;
     uint32_t tot;
     const uint32_t x = block_excl_scan(c, wsum, &tot);
-    if (k < M) {
+    if (k < n) {
       const int64_t o = (int64_t)run + x;
       offs[k] = (uint32_t)o;
       for (int64_t m = (o + kEmitSpan - 1) / kEmitSpan; m < nspan && m * kEmitSpan < o + c; ++m)
@@ -356,7 +428,7 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
                                               int R, const uint32_t* __restrict__ order,
                                               const float4* __restrict__ rec, const int32_t* __restrict__ radius,
-                                              const int32_t* __restrict__ tiles, int64_t M,
+                                              const int32_t* __restrict__ tiles, int64_t M_all, const int32_t* n_dev,
                                               const uint32_t* __restrict__ offs, const int32_t* __restrict__ count,
                                               const uint32_t* __restrict__ first, int64_t nspan,
                                               uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
@@ -364,6 +436,7 @@ __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, c
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int64_t span = (int64_t)blockIdx.x * 4 + w;
   const int64_t I = count[0];  // already clamped to the capacity
+  const int64_t M = order_len(M_all, n_dev);
   if (span >= nspan || span * kEmitSpan >= I) return;  // uniform for the wave
   const int64_t iend = min((span + 1) * kEmitSpan, I);
   int64_t kb = (int64_t)first[span];
@@ -490,6 +563,16 @@ int launch_radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* 
   return passes & 1;
 }
 
+// Compaction before the depth sort for batches of at least 1 M items (the
+// registration views, where most items are culled); the environment variable
+// LS_COMPACT=0 / 1 forces it off / on (read at every launch; for tests and
+// measurements).
+static bool compact_items(int64_t M) {
+  const char* e = std::getenv("LS_COMPACT");
+  if (e && (e[0] == '0' || e[0] == '1') && e[1] == '\0') return e[0] == '1';
+  return M >= (int64_t)1 << 20;
+}
+
 void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
                      const float* rec, const int32_t* radius, const int32_t* tiles, int64_t cap, uint32_t* tile_of,
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
@@ -497,20 +580,33 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const int rd = sort_rounds(M), nbd = (int)sort_blocks(M);
   uint32_t* digit_base = bsum + nbd + 8;  // digit totals (up to kMaxSortBins) after the block sums
-  hipLaunchKernelGGL(k_depth_keys<kDepthDigitBits>, dim3(nbd), dim3(kSortThreads), 0, s, rec4, tiles, M, dk0, dv0,
-                     hist, nbd, rd);
+  // large batches sort only the items with tiles; the kept count sits in a
+  // spare word after the block sums
+  const bool compact = compact_items(M);
+  int32_t* nkeep = compact ? reinterpret_cast<int32_t*>(bsum + nbd) : nullptr;
+  if (compact) {
+    hipLaunchKernelGGL(k_keep_count, dim3(nbd), dim3(kSortThreads), 0, s, tiles, M, rd, bsum);
+    hipLaunchKernelGGL(k_depth_keys_compact, dim3(nbd), dim3(kSortThreads), 0, s, rec4, tiles, M, rd,
+                       (const uint32_t*)bsum, nbd, dk0, dv0, nkeep);
+  } else {
+    hipLaunchKernelGGL(k_depth_keys<kDepthDigitBits>, dim3(nbd), dim3(kSortThreads), 0, s, rec4, tiles, M, dk0, dv0,
+                       hist, nbd, rd);
+  }
   uint32_t *ka = dk0, *va = dv0, *kb = dk1, *vb = dv1;
   for (int shift = 0; shift < 32; shift += kDepthDigitBits) {
-    radix_pass<kDepthDigitBits>(ka, va, kb, vb, nullptr, M, M, shift, hist, digit_base, nbd, rd, s, shift == 0);
+    radix_pass<kDepthDigitBits>(ka, va, kb, vb, nkeep, M, M, shift, hist, digit_base, nbd, rd, s,
+                                shift == 0 && !compact);
     std::swap(ka, kb);
     std::swap(va, vb);
   }
   const uint32_t* order = va;
   uint32_t* offs = ka;  // the free key buffer holds the per-item offsets
-  hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, rd, bsum);
+  hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const int32_t*)nkeep, rd,
+                     bsum);
   const int64_t nspan = emit_spans(cap);
   uint32_t* first = hist;  // free between the depth sort and the tile sort
-  hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const uint32_t*)bsum, nbd,
+  hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const int32_t*)nkeep,
+                     (const uint32_t*)bsum, nbd,
                      offs, count, cap, rd, first, nspan);
   // emission lands in the buffer that, after tile_passes ping-pongs, is the output
   uint32_t* ek = (tile_passes & 1) ? tk : tile_of;
@@ -519,7 +615,8 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   uint32_t* ov = (tile_passes & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
   if (nspan > 0 && M > 0)
     hipLaunchKernelGGL(k_emit, dim3((unsigned)((nspan + 3) / 4)), dim3(256), 0, s, jobs, item_off_d, R, order, rec4,
-                       radius, tiles, M, (const uint32_t*)offs, (const int32_t*)count, (const uint32_t*)first, nspan,
+                       radius, tiles, M, (const int32_t*)nkeep, (const uint32_t*)offs, (const int32_t*)count,
+                       (const uint32_t*)first, nspan,
                        ek, reinterpret_cast<int32_t*>(ev));
   const int rt = sort_rounds(cap), nbt = (int)sort_blocks(cap);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {

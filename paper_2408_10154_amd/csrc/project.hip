@@ -78,6 +78,9 @@ __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs
     }
   }
   if (rad == 0) ntiles = 0;
+  radius_out[item] = rad;
+  tiles_out[item] = ntiles;
+  if (rad == 0) return;  // nothing reads a culled item's record or aux (most items of a registration view)
   out[0] = o0;
   out[1] = o1;
   out[2] = o2;
@@ -86,8 +89,6 @@ __global__ __launch_bounds__(256) void k_project(const JobDev* __restrict__ jobs
     aux[item * 3 + 1] = x1;
     aux[item * 3 + 2] = x2;
   }
-  radius_out[item] = rad;
-  tiles_out[item] = ntiles;
 }
 
 // d R(q/|q|) / d(q) contracted with G (row-major dL/dR): returns dL/dq for the

@@ -80,7 +80,11 @@ def test_project_matches_oracle(gpu):
         np.testing.assert_array_equal(rec[o:e, 8:11][vis], ref[vis, 8:11])
 
 
-def test_bin_sort_bit_exact_with_ties(gpu):
+@pytest.mark.parametrize("compact", ["0", "1"])
+def test_bin_sort_bit_exact_with_ties(gpu, monkeypatch, compact):
+    """Equal-depth runs across many Gaussians, three renders, a small capacity;
+    with and without the compaction of kept items before the depth sort."""
+    monkeypatch.setenv("LS_COMPACT", compact)
     jobs, poses = _three_scenes()
     b = _batch(jobs, capacity=4096)  # deliberately small: exercises the regrow path
     per, expect_tiles, expect_items = [], [], []
@@ -115,11 +119,14 @@ def test_bin_sort_bit_exact_with_ties(gpu):
             assert (s, e) == (0, 0)
 
 
+@pytest.mark.parametrize("compact", ["0", "1"])
 @pytest.mark.parametrize("n_items,seed", [(1500, 11), (9000, 12)])
-def test_bin_sort_bit_exact_long_tile_lists(gpu, n_items, seed):
+def test_bin_sort_bit_exact_long_tile_lists(gpu, monkeypatch, n_items, seed, compact):
     """Tile lists from a few hundred to ~9,000 entries (items covering up to
     the whole 5 x 3 tile grid), with equal-depth runs, culled items and a
-    ragged grid; the order must equal the oracle's (tile, depth bits, item)."""
+    ragged grid; the order must equal the oracle's (tile, depth bits, item),
+    with and without the compaction of kept items before the depth sort."""
+    monkeypatch.setenv("LS_COMPACT", compact)
     rng = np.random.default_rng(seed)
     s = synth.scene_tiny(seed, n_items, 70, 45, 60.0)  # 5 x 3 tiles, the last column and row partial
     jobs = [(s["gauss"], s["cam"], s["w2c"])]
@@ -307,14 +314,16 @@ def test_adam_matches_oracle(gpu):
         np.testing.assert_allclose(d[0].cpu().numpy(), rf[0].numpy(), rtol=1e-5, atol=1e-5)
 
 
+@pytest.mark.parametrize("compact", ["0", "1"])
 @pytest.mark.parametrize("frac", [0.0, 0.37, 1.0])
-def test_bin_sort_overflow_stays_within_capacity(gpu, frac):
+def test_bin_sort_overflow_stays_within_capacity(gpu, monkeypatch, frac, compact):
     """Capacity below the instance count I (and 0, and exactly I): count is
     {min(I, capacity), I > capacity, I, 0}, nothing is written past the
     capacity in the instance arrays or past the workspace, and a re-run at
     capacity count[2] gives the lists of an ample capacity bit for bit."""
     from paper_2408_10154_amd import lib as L
 
+    monkeypatch.setenv("LS_COMPACT", compact)
     jobs, poses = _three_scenes()
     pose = torch.as_tensor(np.stack(poses), device="cuda")
     ref = _batch(jobs)
@@ -351,7 +360,9 @@ def test_bin_sort_overflow_stays_within_capacity(gpu, frac):
     np.testing.assert_array_equal(b.range.cpu().numpy(), ref.range.cpu().numpy())
 
 
-def test_empty_and_fully_culled_renders(gpu):
+@pytest.mark.parametrize("compact", ["0", "1"])
+def test_empty_and_fully_culled_renders(gpu, monkeypatch, compact):
+    monkeypatch.setenv("LS_COMPACT", compact)
     s = synth.scene_small(0, n=500)
     behind = {k: v.copy() for k, v in s["gauss"].items()}
     behind["mean"][2] = -np.abs(behind["mean"][2])  # every Gaussian behind the camera
