@@ -9,6 +9,7 @@ import re
 import pytest
 
 from paper_2408_10154_amd import lib as L
+from paper_2408_10154_amd import register as REG
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADERS = [os.path.join(ROOT, "include", f) for f in os.listdir(os.path.join(ROOT, "include")) if f.endswith(".h")]
@@ -178,6 +179,12 @@ def test_register_pair_rejects_bad_loss_parameters_before_touching_a_device():
     for expo, joint, patience in ((0, 2, 0), (1, 1, 0), (0, 1, 5)):
         prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.0, patience, 1, good, expo, 0.1, joint)
         assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res), None) == L.LS_ERR_INVALID
+    # early-exit rule out of range; negative top-k
+    for mode, top_k in ((2, 0), (-1, 0), (0, -1)):
+        prm = L.ls_reg_params(10, 0.01, 0.01, 0.9, 0.999, 1e-8, 0.1, 5, 1, good, 0, 0.1, 0, mode, top_k)
+        assert lib.ls_register_pair(C.byref(pair), C.byref(prm), None, 0, 0, C.byref(res), None) == L.LS_ERR_INVALID
+    with pytest.raises(ValueError):
+        REG.default_params(10, exit_rel_tol=0.1, exit_patience=5, exit_mode="plateau")
 
 
 def test_overlap_noalloc_limits_without_a_device():
