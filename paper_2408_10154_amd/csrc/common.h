@@ -140,10 +140,11 @@ __device__ __forceinline__ void stage_conic(float4& a, float4& b) {
   b.x *= kHalfLog2e;
 }
 
-// sigma log2(e) at pixel offset (dx, dy) from a staged conic, with explicit
+// sigma log2(e) at pixel offset (dx, dy) from a staged conic, as
+// dx (hA dx + B dy) + hC dy^2 (three multiplies and two FMAs), with explicit
 // FMAs so that forward and backward take identical decisions.
 __device__ __forceinline__ float falloff_log2(float hA, float B, float hC, float dx, float dy) {
-  return __builtin_fmaf(hA * dx, dx, __builtin_fmaf(B * dx, dy, hC * dy * dy));
+  return __builtin_fmaf(dx, __builtin_fmaf(hA, dx, B * dy), hC * dy * dy);
 }
 
 // The DPP reductions below use moves without an "old" operand (bound_ctrl

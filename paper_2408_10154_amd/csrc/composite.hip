@@ -389,6 +389,10 @@ __device__ __forceinline__ float wave_sums(const float* g, int lane) {
   float y = pair_sum<kHalfMirror, 4>(z0, z1, lane);
   y += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), kQuad1032, 0xF, 0xF, true));
   y += __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(y), kQuad2301, 0xF, 0xF, true));
+  // Keep the last add in every lane: callers store the sum from a few lanes,
+  // and sinking the add into that branch splits the fused DPP add into a DPP
+  // move plus an add (an empty asm that reads and writes y, no code).
+  asm volatile("" : "+v"(y));
   return y;
 }
 
@@ -566,7 +570,9 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
       stage_chunk<kBwdChunk>(lane, cnt, chunk, start, bmax, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
-    const uint32_t myj = lane < kBwdChunk ? slist[w][lane] : 0u;  // the band's list in a register
+    // the band's list in a register; lanes past its end hold 0, so the
+    // read-ahead index (jj - 1) & 63 below names a staged entry even at jj = 0
+    const uint32_t myj = lane < cw ? slist[w][lane] : 0u;
     auto bstep = [&](int j, const float4& a, const float4& b, const float4& col) {
       float* pj = part + j * kPartStride + w * kWaveSlots + max(wval, 0);  // written only where wval >= 0
       const int k = chunk + j - start;  // list position
@@ -599,13 +605,13 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     int jA = (int)__builtin_amdgcn_readlane(myj, cw > 0 ? cw - 1 : 0), jB = 0;
     float4 aA = s0[jA], bA = s1[jA], cA = s2[jA], aB, bB, cB;
     for (int jj = cw - 1; jj >= 0;) {
-      jB = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      jB = (int)__builtin_amdgcn_readlane(myj, (jj - 1) & 63);
       aB = s0[jB];
       bB = s1[jB];
       cB = s2[jB];
       bstep(jA, aA, bA, cA);
       if (--jj < 0) break;
-      jA = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      jA = (int)__builtin_amdgcn_readlane(myj, (jj - 1) & 63);
       aA = s0[jA];
       bA = s1[jA];
       cA = s2[jA];
@@ -757,7 +763,9 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
                               swc);
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
-    const uint32_t myj = lane < kPoseChunk ? slist[w][lane] : 0u;  // the band's list in a register
+    // the band's list in a register; lanes past its end hold 0, so the
+    // read-ahead index (jj - 1) & 63 below names a staged entry even at jj = 0
+    const uint32_t myj = lane < cw ? slist[w][lane] : 0u;
     auto pstep = [&](int j, const float4& a, const float4& b, const float4& col) {
       float* pj = part + j * kPoseStride + w * kPoseSlots + max(wval, 0);  // written only where wval >= 0
       const int k = chunk + j - start;
@@ -783,13 +791,13 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
     int jA = (int)__builtin_amdgcn_readlane(myj, cw > 0 ? cw - 1 : 0), jB = 0;
     float4 aA = s0[jA], bA = s1[jA], cA = s2[jA], aB, bB, cB;
     for (int jj = cw - 1; jj >= 0;) {
-      jB = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      jB = (int)__builtin_amdgcn_readlane(myj, (jj - 1) & 63);
       aB = s0[jB];
       bB = s1[jB];
       cB = s2[jB];
       pstep(jA, aA, bA, cA);
       if (--jj < 0) break;
-      jA = (int)__builtin_amdgcn_readlane(myj, jj > 0 ? jj - 1 : 0);
+      jA = (int)__builtin_amdgcn_readlane(myj, (jj - 1) & 63);
       aA = s0[jA];
       bA = s1[jA];
       cA = s2[jA];
