@@ -347,6 +347,31 @@ ls_status batch_create(const ls_render_job* jobs, int32_t R, void* mem, size_t m
   return LS_OK;
 }
 
+ls_status batch_valid_inv(const ls_batch* b, const float* tgt_depth, float* inv, hipStream_t s) {
+  if (!b || !inv) return fail(LS_ERR_INVALID, "NULL batch or output");
+  ls_status st;
+  if ((st = ensure_device(b))) return st;
+  launch_valid_inv(b->jobs_d, b->pblk_off_d, b->nblk_pix, b->R, tgt_depth, b->loss_part_d, inv, s);
+  return hip_check("1 / |Omega| per render");
+}
+
+ls_status render_bwd_pose_l1(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                             const ls_image* fwd, const float* tgt_rgb, const float* tgt_depth, const float* scale,
+                             hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p, true)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if (!fwd || !fwd->T_final || !fwd->n_last || !fwd->rgb || !fwd->depth || !scale)
+    return fail(LS_ERR_INVALID, "forward images or 1 / |Omega| missing");
+  const Layout L = layout_of(b, bins->capacity);
+  const float zero[3] = {0.f, 0.f, 0.f};
+  const L1Targets l1{fwd->rgb, fwd->depth, tgt_rgb, tgt_depth};
+  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range, zero,
+                       fwd->T_final, fwd->n_last, nullptr, nullptr, nullptr, scale, at<float>(bins->work, L.g2d),
+                       at<float>(bins->work, L.tile_part), 1, at<char>(bins->work, L.queues), s, &l1);
+  return hip_check("pose-only backward with the L1 gradient");
+}
+
 ls_status project_views(const ls_batch* b, const float* pose, const ls_projected* out, const ViewOpt* live,
                         hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");

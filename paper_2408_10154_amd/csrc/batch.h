@@ -54,6 +54,18 @@ ls_status batch_bind(ls_batch* b, void* mem, size_t mem_bytes, hipStream_t s);
 // compositing and the backward skip it.
 ls_status project_views(const ls_batch* b, const float* pose, const ls_projected* out, const ViewOpt* live,
                         hipStream_t s);
+// Per render 1 / |Omega| (pixels with a target depth) into inv [R]; targets in
+// the image layout, or NULL: each render's own.  Equals the grad_scale the L1
+// loss kernels write.
+ls_status batch_valid_inv(const ls_batch* b, const float* tgt_depth, float* inv, hipStream_t s);
+// Pose-only ls_render_bwd_tiles whose per-pixel upstream gradient is the
+// plain colour + depth L1 of the forward images against the targets (image
+// layout, or NULL: each render's own), scaled by scale [R] (batch_valid_inv):
+// the same gradient as the L1 loss kernel's, with no loss kernel and no
+// gradient images.
+ls_status render_bwd_pose_l1(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                             const ls_image* fwd, const float* tgt_rgb, const float* tgt_depth, const float* scale,
+                             hipStream_t s);
 // Points every render's loss at its own measurements (device [3][H][W] and
 // [H][W]); re-uploads the job table.  Used by engines that do not lay the
 // targets out contiguously.

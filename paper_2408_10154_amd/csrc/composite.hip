@@ -469,14 +469,28 @@ struct BwdPixel {
   int nl;
 };
 
+__device__ __forceinline__ float l1_sign(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
+
 __device__ __forceinline__ BwdPixel bwd_pixel(const TileCtx& c, const JobDev& J, float bg0, float bg1, float bg2,
                                               const float* fwd_T, const int32_t* fwd_n, const float* up_rgb,
-                                              const float* up_depth, const float* up_alpha, const float* up_scale) {
+                                              const float* up_depth, const float* up_alpha, const float* up_scale,
+                                              const L1Targets& l1) {
   BwdPixel p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
   if (c.inside) {
     const int64_t hw = (int64_t)J.W * J.H;
     const int64_t ci = 3 * J.pix_off + (int64_t)c.y * J.W + c.x;
     const float sc = up_scale ? up_scale[c.r] : 1.f;
+    if (l1.pred_rgb) {
+      // the loss gradient of this pixel, as the L1 loss kernel forms it
+      const int64_t q = (int64_t)c.y * J.W + c.x;
+      const float* trgb = l1.tgt_rgb ? l1.tgt_rgb + ci : J.tgt_rgb + q;
+      const float td = l1.tgt_depth ? l1.tgt_depth[c.pix] : J.tgt_depth[q];
+      const bool valid = td > 0.f;
+      p.gR = sc * (valid ? l1_sign(l1.pred_rgb[ci] - trgb[0]) : 0.f);
+      p.gG = sc * (valid ? l1_sign(l1.pred_rgb[ci + hw] - trgb[hw]) : 0.f);
+      p.gB = sc * (valid ? l1_sign(l1.pred_rgb[ci + 2 * hw] - trgb[2 * hw]) : 0.f);
+      p.gD = sc * (valid ? l1_sign(l1.pred_depth[c.pix] - td) : 0.f);
+    }
     if (up_rgb) { p.gR = sc * up_rgb[ci]; p.gG = sc * up_rgb[ci + hw]; p.gB = sc * up_rgb[ci + 2 * hw]; }
     if (up_depth) p.gD = sc * up_depth[c.pix];
     const float gA = up_alpha ? sc * up_alpha[c.pix] : 0.f;
@@ -555,7 +569,8 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wval = wave_value<kGrad2D>(lane);  // the value whose wave sum this lane stores, or -1
   const int tx0 = c.x0, ty0 = c.y0;
-  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
+  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale,
+                          L1Targets{nullptr, nullptr, nullptr, nullptr});
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
   __syncthreads();
   if (px.nl > 0) atomicMax(&bmax[w], px.nl);
@@ -726,7 +741,8 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
                                                                const float* __restrict__ up_depth,
                                                                const float* __restrict__ up_alpha,
                                                                const float* __restrict__ up_scale,
-                                                               float* __restrict__ tile_part, int tile) {
+                                                               float* __restrict__ tile_part, const L1Targets& l1,
+                                                               int tile) {
   __shared__ float4 s0[kPoseChunk], s1[kPoseChunk], s2[kPoseChunk];
   __shared__ int32_t sit[kPoseChunk];
   __shared__ uint32_t smask[kPoseChunk];
@@ -745,7 +761,7 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wval = wave_value<kPoseRow>(lane);
   const int tx0 = c.x0, ty0 = c.y0;
-  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale);
+  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, l1);
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
   __syncthreads();
   if (px.nl > 0) atomicMax(&bmax[w], px.nl);
@@ -891,11 +907,11 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose(const JobDev* __r
                                                                const float* __restrict__ up_depth,
                                                                const float* __restrict__ up_alpha,
                                                                const float* __restrict__ up_scale,
-                                                               float* __restrict__ tile_part) {
+                                                               float* __restrict__ tile_part, L1Targets l1) {
   const int tile = xcd_remap(blockIdx.x, T_total);
   if (tile >= T_total) return;
   composite_bwd_pose_tile(jobs, tile_off, R, T_total, rec, aux, pose, items, range, bg0, bg1, bg2, fwd_T, fwd_n,
-                          up_rgb, up_depth, up_alpha, up_scale, tile_part, tile);
+                          up_rgb, up_depth, up_alpha, up_scale, tile_part, l1, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose_persistent(const JobDev* __restrict__ jobs,
@@ -904,7 +920,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose_persistent(const 
     const int32_t* __restrict__ range, float bg0, float bg1, float bg2, const float* __restrict__ fwd_T,
     const int32_t* __restrict__ fwd_n, const float* __restrict__ up_rgb, const float* __restrict__ up_depth,
     const float* __restrict__ up_alpha, const float* __restrict__ up_scale, float* __restrict__ tile_part,
-    TileQueue* __restrict__ queue, int nstatic) {
+    TileQueue* __restrict__ queue, int nstatic, L1Targets l1) {
   __shared__ int s_tile;
   bool first = true;
   uint32_t dead = 0;
@@ -912,7 +928,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose_persistent(const 
     const int tile = claim_tile(queue, T_total, nstatic, first, dead, &s_tile);
     if (tile < 0) break;
     composite_bwd_pose_tile(jobs, tile_off, R, T_total, rec, aux, pose, items, range, bg0, bg1, bg2, fwd_T, fwd_n,
-                            up_rgb, up_depth, up_alpha, up_scale, tile_part, tile);
+                            up_rgb, up_depth, up_alpha, up_scale, tile_part, l1, tile);
   }
   release_queue(queue);
 }
@@ -1049,8 +1065,9 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,
                           const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
                           const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
-                          float* tile_part, int pose_only, void* queues, hipStream_t s) {
+                          float* tile_part, int pose_only, void* queues, hipStream_t s, const L1Targets* l1) {
   if (T <= 0) return;
+  const L1Targets l1v = l1 ? *l1 : L1Targets{nullptr, nullptr, nullptr, nullptr};
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const float4* aux4 = reinterpret_cast<const float4*>(aux);
   if (pose_only) {
@@ -1058,11 +1075,11 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
     if (g.on)
       hipLaunchKernelGGL(k_composite_bwd_pose_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T,
                          rec4, aux4, pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha,
-                         up_scale, tile_part, reinterpret_cast<TileQueue*>(queues) + 1, g.nstatic);
+                         up_scale, tile_part, reinterpret_cast<TileQueue*>(queues) + 1, g.nstatic, l1v);
     else
       hipLaunchKernelGGL(k_composite_bwd_pose, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, aux4,
                          pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
-                         tile_part);
+                         tile_part, l1v);
   } else {
     const PersistentGrid g = persistent_grid(0, reinterpret_cast<const void*>(k_composite_bwd_persistent), T);
     if (g.on)

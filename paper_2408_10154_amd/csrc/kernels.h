@@ -45,11 +45,25 @@ void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, in
 // by every launch; one launch at a time per workspace).
 constexpr size_t kTileQueueBytes = 2 * 9 * 128;
 
+// The plain colour + depth L1 of registration (Sec. 3.2), formed per pixel
+// by the pose-only backward itself from the forward's images and the targets
+// instead of read from a loss kernel's gradient images: on pixels with a
+// target depth, sign(rendered - target) per colour channel and for depth,
+// times the render's 1 / |Omega| (up_scale); 0 elsewhere.  Targets in the
+// batch's image layout, or NULL: each render's own (JobDev.tgt_*).
+struct L1Targets {
+  const float* pred_rgb;    // forward colour [3][P]; NULL: off
+  const float* pred_depth;  // forward depth [P]
+  const float* tgt_rgb;
+  const float* tgt_depth;
+};
+
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,
                           const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
                           const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
-                          float* tile_part, int pose_only, void* queues, hipStream_t s);
+                          float* tile_part, int pose_only, void* queues, hipStream_t s,
+                          const L1Targets* l1 = nullptr);
 
 // Registration helpers (reg_kernels.hip).
 struct ViewOpt {
@@ -112,6 +126,10 @@ void launch_loss_mapping(const JobDev* jobs, const int32_t* pblk_off_d, int npbl
                          const float* tgt_depth, float lambda_ssim, float lambda_color, float lambda_depth,
                          float* g_rgb, float* g_depth, float* cnt_part, float* map_part, float* loss, float* scale,
                          hipStream_t s);
+// Per render 1 / |Omega| (pixels with a target depth; 0 when none) into inv
+// [R]; cnt_part = npblk floats.  Targets as for L1Targets.
+void launch_valid_inv(const JobDev* jobs, const int32_t* pblk_off_d, int npblk, int R, const float* tgt_depth,
+                      float* cnt_part, float* inv, hipStream_t s);
 // Isotropic regulariser; part = kIsotropicBlocks floats.
 constexpr int kIsotropicBlocks = LS_ISOTROPIC_WORK_FLOATS;
 void launch_loss_isotropic(const float* log_scale, int64_t n, float lambda_reg, float* loss, float* grad, float* part,

@@ -448,6 +448,13 @@ static SsimWindow ssim_window() {
   return w;
 }
 
+void launch_valid_inv(const JobDev* jobs, const int32_t* pblk_off_d, int npblk, int R, const float* tgt_depth,
+                      float* cnt_part, float* inv, hipStream_t s) {
+  if (npblk > 0)
+    hipLaunchKernelGGL(k_valid_count, dim3(npblk), dim3(256), 0, s, jobs, pblk_off_d, R, tgt_depth, cnt_part);
+  if (R > 0) hipLaunchKernelGGL(k_valid_inv, dim3(R), dim3(kBlock), 0, s, pblk_off_d, R, (const float*)cnt_part, inv);
+}
+
 int ssim_blocks(int W, int H) { return 3 * ((W + kSsimT - 1) / kSsimT) * ((H + kSsimT - 1) / kSsimT); }
 
 void launch_loss_mapping(const JobDev* jobs, const int32_t* pblk_off_d, int npblk, const int32_t* sblk_off_d,

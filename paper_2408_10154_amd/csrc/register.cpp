@@ -6,6 +6,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstdlib>
 #include <cstring>
 #include <memory>
 #include <vector>
@@ -355,6 +356,8 @@ ls_status RegEngine::bind(void* work, size_t work_bytes, int64_t cap, hipStream_
   if (hipMemcpyAsync(opt, ho.data(), sizeof(ViewOpt) * R, hipMemcpyHostToDevice, s) != hipSuccess) return LS_ERR_HIP;
   if (hipStreamSynchronize(s) != hipSuccess) return LS_ERR_HIP;
   launch_pose_init(pose, adam_m, adam_v, opt, R, s);
+  fused_l1 = fused_l1_allowed(pairs[0].prm);
+  if (fused_l1 && (st = batch_valid_inv(batch, tgt_depth, scale, s))) return st;  // constant over the iterations
   joint_T.assign(7 * pairs.size(), 0.0);
   for (size_t p = 0; p < pairs.size(); ++p) joint_T[7 * p] = 1.0;
   joint_m.assign(7 * pairs.size(), 0.0);
@@ -391,9 +394,12 @@ ls_status RegEngine::step(hipStream_t s) {
   // renders every view)
   if ((st = project_views(batch, pose, &proj, opt, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
-  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s)) || (st = view_loss(s)) ||
-      (st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
-      (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
+  if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s))) return st;
+  if (fused_l1)  // the backward forms the L1 gradient itself; no per-iteration loss value
+    st = render_bwd_pose_l1(batch, pose, &proj, &bins, &img, tgt_rgb, tgt_depth, scale, s);
+  else if (!(st = view_loss(s)))
+    st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s);
+  if (st || (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
     return st;
   const ls_reg_params& pm = pairs[0].prm;
   launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, loss, R, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
@@ -555,6 +561,12 @@ ls_status RegEngine::read_exposure(int p, ls_reg_result* out, hipStream_t s) {
     out->exposure[2 * slot + 1] = h[2 * k + 1];
   }
   return LS_OK;
+}
+
+bool fused_l1_allowed(const ls_reg_params& pm) {
+  const char* e = std::getenv("LS_FUSED_L1");
+  if (e && e[0] == '0' && e[1] == '\0') return false;
+  return pm.loss_kind == 0 && !pm.exposure && !pm.joint && !(pm.exit_patience > 0 && pm.exit_mode == 0);
 }
 
 ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm) {

@@ -68,6 +68,11 @@ class RegEngine {
   // block partials; null unless the pair asks for exposure compensation
   float *expo = nullptr, *expo_grad = nullptr, *expo_m = nullptr, *expo_v = nullptr, *expo_part = nullptr;
   int32_t *range = nullptr, *count = nullptr, *sticky = nullptr;
+  // plain L1 without exposure, joint mode or the loss-plateau exit: the
+  // pose-only backward forms the loss gradient itself (render_bwd_pose_l1)
+  // with 1 / |Omega| computed once at bind, and no loss kernel runs per
+  // iteration (the final forward still computes the residuals)
+  bool fused_l1 = false;
 
  private:
   struct Layout {
@@ -85,6 +90,9 @@ void view_estimate(const double* c2w, const float* pose7, double* E);
 void joint_delta(const double* T7, const double* c2w, bool reverse, double* d7);
 int fuse_estimates(const double* est, const double* resid, const int32_t* rev, int n, double* out);
 ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm);
+// Whether the iterations may take the fused L1 backward (LS_FUSED_L1=0 in the
+// environment turns it off; for tests and measurements).
+bool fused_l1_allowed(const ls_reg_params& pm);
 RegPair make_reg_pair(const ls_pair* p, const ls_reg_params* prm);
 
 }  // namespace ls

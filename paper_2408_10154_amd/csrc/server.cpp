@@ -150,6 +150,7 @@ class Server {
         track_ = prm->track;
         exposure_ = prm->exposure;
         lr_exposure_ = prm->exposure ? prm->lr_exposure : 0.f;
+        fused_l1_ = fused_l1_allowed(*prm);
         have_betas_ = true;
       } else if (prm->beta1 != beta1_ || prm->beta2 != beta2_ || prm->adam_eps != eps_ ||
                  prm->exit_rel_tol != exit_tol_ || prm->exit_patience != exit_patience_ ||
@@ -363,6 +364,8 @@ class Server {
     if ((st = epart_.ensure(8 * (size_t)std::max(batch_->nblk_pix, 1)))) return st;
     if (hipStreamSynchronize(stream_) != hipSuccess) return LS_ERR_HIP;  // host map/init must outlive the copies
     std::swap(stateA_, stateB_);
+    // with the fused L1 backward, 1 / |Omega| of every view once per active set
+    if (fused_l1_ && (st = batch_valid_inv(batch_, nullptr, state_ptrs(stateA_, R_).scale, stream_))) return st;
 
     // scratch sized for this active set
     const size_t o_rad = align(48 * (size_t)std::max<int64_t>(M_, 1)), o_til = o_rad + align(4 * M_);
@@ -467,10 +470,12 @@ class Server {
         (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)))
       return st;
     launch_or_flag(count_, sticky_, stream_);
-    if ((st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_)) ||
-        (st = view_loss(s)) ||
-        (st = ls_render_bwd_tiles(batch_, s.pose, &proj_, &bins_c_, nullptr, &img_, &up, LS_BWD_POSE_ONLY, stream_)) ||
-        (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
+    if ((st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_))) return st;
+    if (fused_l1_)  // the backward forms the L1 gradient itself (no per-iteration loss value)
+      st = render_bwd_pose_l1(batch_, s.pose, &proj_, &bins_c_, &img_, nullptr, nullptr, s.scale, stream_);
+    else if (!(st = view_loss(s)))
+      st = ls_render_bwd_tiles(batch_, s.pose, &proj_, &bins_c_, nullptr, &img_, &up, LS_BWD_POSE_ONLY, stream_);
+    if (st || (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
       return st;
     if (exposure_)
       launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_, exit_mode_,
@@ -678,6 +683,7 @@ class Server {
   bool have_betas_ = false;
   float beta1_ = 0.9f, beta2_ = 0.999f, eps_ = 1e-8f, exit_tol_ = 0.f;
   int32_t exit_patience_ = 0, exit_mode_ = 0;
+  bool fused_l1_ = false;  // iterations take render_bwd_pose_l1 (set with the first request's settings)
   int32_t loss_kind_ = 0;
   ls_loss_params track_{};
   int32_t exposure_ = 0;  // exposure coefficients on (fixed by the first request, like the loss)

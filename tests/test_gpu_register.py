@@ -212,6 +212,33 @@ def test_compaction_before_the_depth_sort_is_bitwise_neutral(gpu, monkeypatch):
         np.testing.assert_array_equal(out["1"][k], out["0"][k])
 
 
+@pytest.mark.parametrize("exit_mode", ["off", "step"])
+def test_fused_l1_backward_is_bitwise_neutral(gpu, monkeypatch, exit_mode):
+    """Plain L1 registration forms the loss gradient inside the pose-only
+    backward (with 1 / |Omega| computed once) instead of running the loss
+    kernel every iteration: on the single-pair workload, 30 iterations, with
+    and without the step-rule early exit, the transform, the estimates and
+    the residuals equal those of the loss-kernel path bit for bit."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.render import GaussianSet
+
+    d = synth.registration_pair(3, 150000, 120000, views_p=8, views_q=8, width=640, height=480, f=500,
+                                layout="views")
+    P, Q = GaussianSet.from_numpy(d["P"]), GaussianSet.from_numpy(d["Q"])
+    rgbP, depP = REG.keyframe_targets(P, d["cam"], d["kf_p"])
+    rgbQ, depQ = REG.keyframe_targets(Q, d["cam"], d["kf_q"])
+    args = (P, Q, d["cam"], d["kf_p"], d["kf_q"], rgbP, depP, rgbQ, depQ)
+    kw = dict(exit_rel_tol=0.5, exit_patience=3, exit_mode="step") if exit_mode == "step" else {}
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("LS_FUSED_L1", mode)
+        out[mode] = REG.register_pair(*args, params=REG.default_params(30, **kw))
+        assert out[mode]["status"] == 0
+    for k in ("T", "per_view", "residual"):
+        np.testing.assert_array_equal(out["1"][k], out["0"][k])
+    assert out["1"]["iters"] == out["0"]["iters"]
+
+
 def test_exposure_tiny_pair_matches_oracle(gpu):
     """The tiny room with Q's keyframe under gain 1.2 and offset 0.03: the
     GPU and the oracle (both fitting exposure coefficients, plain L1) agree

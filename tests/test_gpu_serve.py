@@ -195,6 +195,23 @@ def test_server_step_exit_matches_plain(pairs):
     print("plain iterations", [b["iters"] for b in plain])
 
 
+def test_server_fused_l1_matches_the_loss_kernel_path(pairs, monkeypatch):
+    """A server whose iterations form the L1 gradient inside the backward
+    (the default for plain L1) and one that runs the loss kernel every
+    iteration give the same results bit for bit."""
+    from paper_2408_10154_amd import register as REG
+    from paper_2408_10154_amd.serve import Server
+
+    out = {}
+    for mode in ("1", "0"):
+        monkeypatch.setenv("LS_FUSED_L1", mode)
+        with Server(max_slots=8, chunk_iters=8) as sv:
+            ts = [sv.submit(*p["args"], params=REG.default_params(ITERS)) for p in pairs]
+            out[mode] = [sv.wait(t) for t in ts]
+    for a, b in zip(out["1"], out["0"]):
+        assert a["status"] == 0 and b["status"] == 0 and _same(a, b)
+
+
 def test_submit_orders_reads_after_the_producer_stream(pairs):
     """A request whose Gaussians are written on a side stream just before
     submitting (behind a chain of long kernels): the server's finiteness
