@@ -372,6 +372,16 @@ ls_status render_bwd_pose_l1(const ls_batch* b, const float* pose, const ls_proj
   return hip_check("pose-only backward with the L1 gradient");
 }
 
+ls_status pose_reduce_adam(const ls_batch* b, const ls_bins* bins, const PoseAdamArgs& a, const int32_t* count,
+                           int32_t* sticky, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  const Layout L = layout_of(b, bins->capacity);
+  launch_pose_reduce_adam(b->jobs_d, b->R, at<float>(bins->work, L.tile_part), a, count, sticky, s);
+  return hip_check("pose reduction and Adam step");
+}
+
 ls_status project_views(const ls_batch* b, const float* pose, const ls_projected* out, const ViewOpt* live,
                         hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");

@@ -54,6 +54,11 @@ ls_status batch_bind(ls_batch* b, void* mem, size_t mem_bytes, hipStream_t s);
 // compositing and the backward skip it.
 ls_status project_views(const ls_batch* b, const float* pose, const ls_projected* out, const ViewOpt* live,
                         hipStream_t s);
+// After a pose-only backward: each render's pose gradient from the tile
+// partials and its Adam step (a.grad is added to and consumed), and the
+// sticky overflow flag updated from count (launch_pose_reduce_adam).
+ls_status pose_reduce_adam(const ls_batch* b, const ls_bins* bins, const PoseAdamArgs& a, const int32_t* count,
+                           int32_t* sticky, hipStream_t s);
 // Per render 1 / |Omega| (pixels with a target depth) into inv [R]; targets in
 // the image layout, or NULL: each render's own.  Equals the grad_scale the L1
 // loss kernels write.

@@ -75,14 +75,116 @@ struct ViewOpt {
   float resid;     // loss at the pose the view froze at
   int32_t pad;
 };
+// Adam on one render's 7 pose values (lr_rot for q, lr_trans for t) from its
+// gradient g, and on its 2 exposure coefficients when given (lr_expo), bias
+// correction from the render's own step count; the gradients are consumed
+// (zeroed).  Early exit (exit_patience > 0) freezes a view at its current
+// pose (whose loss is the one just computed) instead of stepping once, for
+// exit_patience iterations in a row,
+//   exit_mode 0: its loss has not improved on its best by more than exit_tol
+//                (relative);
+//   exit_mode 1: its Adam step would have been small: the largest
+//                |m_hat| / (sqrt(v_hat) + eps) over its 7 pose values (the
+//                step in units of the learning rate) is below exit_tol.
+// Frozen views keep their pose.
+struct PoseAdamArgs {
+  float* pose;
+  float* grad;  // [R][7], zeroed here
+  float* m;
+  float* v;
+  ViewOpt* opt;
+  const float* loss;
+  float beta1, beta2, eps, exit_tol;
+  int exit_patience, exit_mode;
+  float* expo;  // exposure coefficients (a, b) per render, or NULL
+  float* egrad;
+  float* em;
+  float* ev;
+  float lr_expo;
+};
+
+__device__ inline void pose_adam_view(const PoseAdamArgs& a, int r, const float (&g)[7]) {
+  ViewOpt o = a.opt[r];
+  if (o.active) {
+    const int step = o.step + 1;
+    const float bc1 = 1.f / (1.f - __powf(a.beta1, (float)step));
+    const float bc2 = 1.f / (1.f - __powf(a.beta2, (float)step));
+    float mn[7], vn[7], ratio = 0.f;
+#pragma unroll
+    for (int k = 0; k < 7; ++k) {
+      const int i = 7 * r + k;
+      mn[k] = a.beta1 * a.m[i] + (1.f - a.beta1) * g[k];
+      vn[k] = a.beta2 * a.v[i] + (1.f - a.beta2) * g[k] * g[k];
+      ratio = fmaxf(ratio, fabsf(mn[k] * bc1) / (sqrtf(vn[k] * bc2) + a.eps));
+    }
+    bool step_now = true;
+    if (a.exit_patience > 0) {
+      const float l = a.loss[r];
+      if (a.exit_mode == 1) {
+        o.stall = ratio < a.exit_tol ? o.stall + 1 : 0;
+        o.best = o.step == 0 ? l : fminf(o.best, l);
+      } else if (o.step == 0 || l < o.best * (1.f - a.exit_tol)) {
+        o.best = o.step == 0 ? l : fminf(o.best, l);
+        o.stall = 0;
+      } else {
+        o.best = fminf(o.best, l);
+        ++o.stall;
+      }
+      if (o.stall >= a.exit_patience) {
+        o.active = 0;
+        o.resid = l;
+        step_now = false;
+      }
+    }
+    if (step_now) {
+#pragma unroll
+      for (int k = 0; k < 7; ++k) {
+        const int i = 7 * r + k;
+        a.m[i] = mn[k];
+        a.v[i] = vn[k];
+        const float lr = k < 4 ? o.lr_rot : o.lr_trans;
+        a.pose[i] -= lr * (mn[k] * bc1) / (sqrtf(vn[k] * bc2) + a.eps);
+      }
+      if (a.expo) {
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+          const int i = 2 * r + k;
+          const float eg = a.egrad[i];
+          const float mi = a.beta1 * a.em[i] + (1.f - a.beta1) * eg;
+          const float vi = a.beta2 * a.ev[i] + (1.f - a.beta2) * eg * eg;
+          a.em[i] = mi;
+          a.ev[i] = vi;
+          a.expo[i] -= a.lr_expo * (mi * bc1) / (sqrtf(vi * bc2) + a.eps);
+        }
+      }
+      o.step = step;
+    }
+    a.opt[r] = o;
+  }
+#pragma unroll
+  for (int k = 0; k < 7; ++k) a.grad[7 * r + k] = 0.f;
+  if (a.expo) {
+    a.egrad[2 * r] = 0.f;
+    a.egrad[2 * r + 1] = 0.f;
+  }
+}
+
+// sticky[0] |= overflow; sticky[1] keeps the instance count required at the
+// first overflow (the pose before any step taken on truncated lists).
+__device__ inline void or_flag(const int32_t* count, int32_t* sticky) {
+  if (count[1] != 0) {
+    if (sticky[0] == 0) sticky[1] = count[2];
+    sticky[0] = 1;
+  }
+}
+
+// One iteration's end in pose-only registration: per render, the tile
+// partials reduced to its pose gradient (as launch_pose_reduce_tiles) and
+// its Adam step (pose_adam_view) in one launch; render 0 also updates the
+// sticky overflow flag from count (as launch_or_flag).
+void launch_pose_reduce_adam(const JobDev* jobs, int R, const float* tile_part, const PoseAdamArgs& a,
+                             const int32_t* count, int32_t* sticky, hipStream_t s);
 void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s);
-// With expo non-null, each view's exposure coefficients (a, b) take the same
-// Adam step (learning rate lr_expo) from egrad, which is consumed.
-void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
-                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, int exit_mode,
-                      hipStream_t s,
-                      float* expo = nullptr, float* egrad = nullptr, float* em = nullptr, float* ev = nullptr,
-                      float lr_expo = 0.f);
 void launch_or_flag(const int32_t* count, int32_t* sticky, hipStream_t s);
 // Per render: fraction of the pixels with a target depth > 0 whose rendered
 // alpha is >= 0.5 (part: 2 floats per 1024-pixel block).

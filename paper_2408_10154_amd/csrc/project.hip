@@ -267,6 +267,37 @@ void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int n
     hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, (const float*)pose_part, pose_grad, 0);
 }
 
+// Pose reduction by tile partials (as k_pose_reduce with by_tile) followed
+// by the render's Adam step; block 0 also folds the overflow count into the
+// sticky flag.
+__global__ void k_pose_reduce_adam(const JobDev* __restrict__ jobs, int R, const float* __restrict__ tile_part,
+                                   PoseAdamArgs a, const int32_t* __restrict__ count, int32_t* __restrict__ sticky) {
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  const JobDev& J = jobs[r];
+  const int first = J.tile_off, nb = J.TX * J.TY;
+  const int lane = threadIdx.x;
+  float acc[kPoseAcc];
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
+  for (int b = lane; b < nb; b += 64)
+    for (int k = 0; k < kPoseAcc; ++k) acc[k] += tile_part[(int64_t)(first + b) * kPoseAcc + k];
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = wave_sum(acc[k]);
+  if (lane == 0) {
+    const float* pr = a.pose + 7 * r;
+    float dq[4], g[7];
+    rot_backward(pr[0], pr[1], pr[2], pr[3], acc, dq);
+    for (int k = 0; k < 4; ++k) g[k] = a.grad[7 * r + k] + dq[k];
+    for (int k = 0; k < 3; ++k) g[4 + k] = a.grad[7 * r + 4 + k] + acc[9 + k];
+    pose_adam_view(a, r, g);
+    if (r == 0 && count) or_flag(count, sticky);
+  }
+}
+
+void launch_pose_reduce_adam(const JobDev* jobs, int R, const float* tile_part, const PoseAdamArgs& a,
+                             const int32_t* count, int32_t* sticky, hipStream_t s) {
+  if (R > 0) hipLaunchKernelGGL(k_pose_reduce_adam, dim3(R), dim3(64), 0, s, jobs, R, tile_part, a, count, sticky);
+}
+
 void launch_pose_reduce_tiles(const JobDev* jobs, int R, const float* pose, const float* tile_part, float* pose_grad,
                               hipStream_t s) {
   hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, tile_part, pose_grad, 1);

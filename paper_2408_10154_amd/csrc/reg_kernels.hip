@@ -23,111 +23,15 @@ __global__ void k_pose_init(float* __restrict__ pose, float* __restrict__ m, flo
   }
 }
 
-// One thread per render: Adam on its 7 pose values (lr_rot for q, lr_trans
-// for t), and on its 2 exposure coefficients when given (lr_expo), bias
-// correction from the render's own step count; the gradients are consumed
-// (zeroed).  Early exit (exit_patience > 0) freezes a view at its current
-// pose (whose loss is the one just computed) instead of stepping once, for
-// exit_patience iterations in a row,
-//   exit_mode 0: its loss has not improved on its best by more than exit_tol
-//                (relative);
-//   exit_mode 1: its Adam step would have been small: the largest
-//                |m_hat| / (sqrt(v_hat) + eps) over its 7 pose values (the
-//                step in units of the learning rate) is below exit_tol.
-// Frozen views keep their pose.
-__global__ void k_pose_adam(float* __restrict__ pose, float* __restrict__ grad, float* __restrict__ m,
-                            float* __restrict__ v, ViewOpt* __restrict__ opt, const float* __restrict__ loss, int R,
-                            float beta1, float beta2, float eps, float exit_tol, int exit_patience, int exit_mode,
-                            float* __restrict__ expo, float* __restrict__ egrad, float* __restrict__ em,
-                            float* __restrict__ ev, float lr_expo) {
-  const int r = blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= R) return;
-  ViewOpt o = opt[r];
-  if (o.active) {
-    const int step = o.step + 1;
-    const float bc1 = 1.f / (1.f - __powf(beta1, (float)step));
-    const float bc2 = 1.f / (1.f - __powf(beta2, (float)step));
-    float mn[7], vn[7], ratio = 0.f;
-#pragma unroll
-    for (int k = 0; k < 7; ++k) {
-      const int i = 7 * r + k;
-      const float g = grad[i];
-      mn[k] = beta1 * m[i] + (1.f - beta1) * g;
-      vn[k] = beta2 * v[i] + (1.f - beta2) * g * g;
-      ratio = fmaxf(ratio, fabsf(mn[k] * bc1) / (sqrtf(vn[k] * bc2) + eps));
-    }
-    bool step_now = true;
-    if (exit_patience > 0) {
-      const float l = loss[r];
-      if (exit_mode == 1) {
-        o.stall = ratio < exit_tol ? o.stall + 1 : 0;
-        o.best = o.step == 0 ? l : fminf(o.best, l);
-      } else if (o.step == 0 || l < o.best * (1.f - exit_tol)) {
-        o.best = o.step == 0 ? l : fminf(o.best, l);
-        o.stall = 0;
-      } else {
-        o.best = fminf(o.best, l);
-        ++o.stall;
-      }
-      if (o.stall >= exit_patience) {
-        o.active = 0;
-        o.resid = l;
-        step_now = false;
-      }
-    }
-    if (step_now) {
-#pragma unroll
-      for (int k = 0; k < 7; ++k) {
-        const int i = 7 * r + k;
-        m[i] = mn[k];
-        v[i] = vn[k];
-        const float lr = k < 4 ? o.lr_rot : o.lr_trans;
-        pose[i] -= lr * (mn[k] * bc1) / (sqrtf(vn[k] * bc2) + eps);
-      }
-      if (expo) {
-#pragma unroll
-        for (int k = 0; k < 2; ++k) {
-          const int i = 2 * r + k;
-          const float g = egrad[i];
-          const float mi = beta1 * em[i] + (1.f - beta1) * g;
-          const float vi = beta2 * ev[i] + (1.f - beta2) * g * g;
-          em[i] = mi;
-          ev[i] = vi;
-          expo[i] -= lr_expo * (mi * bc1) / (sqrtf(vi * bc2) + eps);
-        }
-      }
-      o.step = step;
-    }
-    opt[r] = o;
-  }
-#pragma unroll
-  for (int k = 0; k < 7; ++k) grad[7 * r + k] = 0.f;
-  if (expo) {
-    egrad[2 * r] = 0.f;
-    egrad[2 * r + 1] = 0.f;
-  }
-}
-
 // sticky[0] |= overflow; sticky[1] keeps the instance count required at the
 // first overflow (the pose before any step taken on truncated lists).
 __global__ void k_or_flag(const int32_t* __restrict__ count, int32_t* __restrict__ sticky) {
-  if (threadIdx.x == 0 && count[1] != 0) {
-    if (sticky[0] == 0) sticky[1] = count[2];
-    sticky[0] = 1;
-  }
+  if (threadIdx.x == 0) or_flag(count, sticky);
 }
 
 void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s) {
   const int n = 7 * R;
   hipLaunchKernelGGL(k_pose_init, dim3((n + 255) / 256), dim3(256), 0, s, pose, m, v, opt, R);
-}
-
-void launch_pose_adam(float* pose, float* grad, float* m, float* v, ViewOpt* opt, const float* loss, int R,
-                      float beta1, float beta2, float eps, float exit_tol, int exit_patience, int exit_mode,
-                      hipStream_t s,
-                      float* expo, float* egrad, float* em, float* ev, float lr_expo) {
-  hipLaunchKernelGGL(k_pose_adam, dim3((R + 255) / 256), dim3(256), 0, s, pose, grad, m, v, opt, loss, R, beta1, beta2,
-                     eps, exit_tol, exit_patience, exit_mode, expo, egrad, em, ev, lr_expo);
 }
 
 // View co-visibility for the top-k selection of registration views: per

@@ -393,17 +393,17 @@ ls_status RegEngine::step(hipStream_t s) {
   // views frozen by the early exit are not rendered (the final forward
   // renders every view)
   if ((st = project_views(batch, pose, &proj, opt, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
-  launch_or_flag(count, sticky, s);
   if ((st = ls_render_fwd(batch, &proj, &bins, nullptr, &img, s))) return st;
   if (fused_l1)  // the backward forms the L1 gradient itself; no per-iteration loss value
     st = render_bwd_pose_l1(batch, pose, &proj, &bins, &img, tgt_rgb, tgt_depth, scale, s);
   else if (!(st = view_loss(s)))
     st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s);
-  if (st || (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
-    return st;
+  if (st) return st;
+  // pose gradients, Adam steps and the sticky overflow flag in one launch
   const ls_reg_params& pm = pairs[0].prm;
-  launch_pose_adam(pose, pose_grad, adam_m, adam_v, opt, loss, R, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
-                   pm.exit_patience, pm.exit_mode, s, expo, expo_grad, expo_m, expo_v, pm.lr_exposure);
+  const PoseAdamArgs a{pose, pose_grad, adam_m, adam_v, opt, loss, pm.beta1, pm.beta2, pm.adam_eps, pm.exit_rel_tol,
+                       pm.exit_patience, pm.exit_mode, expo, expo_grad, expo_m, expo_v, pm.lr_exposure};
+  if ((st = pose_reduce_adam(batch, &bins, a, count, sticky, s))) return st;
   return hip_ok();
 }
 

@@ -469,21 +469,16 @@ class Server {
     if ((st = project_views(batch_, s.pose, &proj_, s.opt, stream_)) ||
         (st = ls_bin_sort(batch_, &proj_, &bins_c_, stream_)))
       return st;
-    launch_or_flag(count_, sticky_, stream_);
     if ((st = ls_render_fwd(batch_, &proj_, &bins_c_, nullptr, &img_, stream_))) return st;
     if (fused_l1_)  // the backward forms the L1 gradient itself (no per-iteration loss value)
       st = render_bwd_pose_l1(batch_, s.pose, &proj_, &bins_c_, &img_, nullptr, nullptr, s.scale, stream_);
     else if (!(st = view_loss(s)))
       st = ls_render_bwd_tiles(batch_, s.pose, &proj_, &bins_c_, nullptr, &img_, &up, LS_BWD_POSE_ONLY, stream_);
-    if (st || (st = ls_render_bwd_project(batch_, s.pose, &proj_, &bins_c_, nullptr, s.grad, LS_BWD_POSE_ONLY, stream_)))
-      return st;
-    if (exposure_)
-      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_, exit_mode_,
-                       stream_, s.expo, s.eg, s.em, s.ev, lr_exposure_);
-    else
-      launch_pose_adam(s.pose, s.grad, s.m, s.v, s.opt, s.loss, R_, beta1_, beta2_, eps_, exit_tol_, exit_patience_, exit_mode_,
-                       stream_);
-    return LS_OK;
+    if (st) return st;
+    // pose gradients, Adam steps and the sticky overflow flag in one launch
+    const PoseAdamArgs a{s.pose, s.grad, s.m, s.v, s.opt, s.loss, beta1_, beta2_, eps_, exit_tol_, exit_patience_,
+                         exit_mode_, exposure_ ? s.expo : nullptr, s.eg, s.em, s.ev, lr_exposure_};
+    return pose_reduce_adam(batch_, &bins_c_, a, count_, sticky_, stream_);
   }
 
   ls_status capture() {
