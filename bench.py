@@ -77,8 +77,10 @@ def algorithmic_bytes(n: int, inst: int, px: int, tiles: int) -> dict:
         "fwd": 44 * inst + 28 * px,                       # record gather, image out
         "loss": 56 * px,                                  # images and targets in, gradients out
         "bwd": 44 * inst + 44 * px + 40 * n,              # record gather, image state in, 2D gradients out
-        "bwd_project": 152 * n,                           # 2D gradients 40, parameters 56, gradients 56
-        "adam": 28 * 14 * n,                              # p, g, m, v read; p, m, v written; 14 per Gaussian
+        # projection backward with the Adam step fused: 2D gradients 40, parameters 56 in and out,
+        # moments 112 in and out (the gradients never go to memory)
+        "bwd_project_adam": 376 * n,
+        "adam": 28 * 7,                                   # the pose: p, g, m, v read; p, m, v written
     }
 
 
@@ -529,19 +531,24 @@ def main():
     grads = gs.zeros_like()
     pose_grad = torch.zeros_like(pose)
     lr = dict(mean=1e-3, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, rgb=2.5e-3)
+    # render loop: the Gaussians' Adam step fused into the projection backward, the pose's by ls_adam
+    mom = {name: (torch.zeros_like(getattr(gs, name)), torch.zeros_like(getattr(gs, name)), lr[name])
+           for name in GaussianSet.FIELDS}
+    pm, pv = torch.zeros_like(pose), torch.zeros_like(pose)
+    pose_groups = [(pose[0, :4], pose_grad[0, :4], pm[0, :4], pv[0, :4], 2e-3),   # tracking rotation lr
+                   (pose[0, 4:], pose_grad[0, 4:], pm[0, 4:], pv[0, 4:], 1e-2)]   # tracking translation lr
+    # mapping loop (its regulariser adds to the log-scale gradient): gradient arrays and one ls_adam
     groups = []
     for name in GaussianSet.FIELDS:
         p = getattr(gs, name)
         groups.append((p, getattr(grads, name), torch.zeros_like(p), torch.zeros_like(p), lr[name]))
-    pm, pv = torch.zeros_like(pose), torch.zeros_like(pose)
-    groups.append((pose[0, :4], pose_grad[0, :4], pm[0, :4], pv[0, :4], 2e-3))   # tracking rotation lr
-    groups.append((pose[0, 4:], pose_grad[0, 4:], pm[0, 4:], pv[0, 4:], 1e-2))   # tracking translation lr
+    groups += pose_groups
     loss = torch.zeros(1, device="cuda")
     g_rgb = torch.zeros_like(b.rgb)
     g_depth = torch.zeros_like(b.depth)
     g_scale = torch.zeros(1, device="cuda")
     stream = torch.cuda.current_stream()
-    kinds = ("project", "bin_sort", "fwd", "loss", "bwd", "bwd_project", "adam")
+    kinds = ("project", "bin_sort", "fwd", "loss", "bwd", "bwd_project_adam", "adam")
     ev = {k: [] for k in kinds}
     step_no = [0]
     sp = L.C.c_void_p(stream.cuda_stream)
@@ -561,9 +568,9 @@ def main():
         run("fwd", lambda: b.render_fwd())
         run("loss", lambda: b.loss_l1(tgt_rgb, tgt_depth, loss, g_rgb, g_depth, g_scale))
         run("bwd", lambda: b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=g_scale))
-        run("bwd_project", lambda: b.render_bwd_project(grads=[grads], pose=pose, pose_grad=pose_grad))
         step_no[0] += 1
-        run("adam", lambda: adam(groups, step_no[0]))
+        run("bwd_project_adam", lambda: b.render_bwd_project_adam([mom], step_no[0], pose=pose, pose_grad=pose_grad))
+        run("adam", lambda: adam(pose_groups, step_no[0]))
 
     for _ in range(args.warmup):
         step("")
@@ -662,7 +669,7 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
-    del b, gs, grads, groups
+    del b, gs, grads, groups, mom
     torch.cuda.empty_cache()
     log("pruning, map adjustment, overlap ratio")
     prune = None if args.no_prune else prune_timing()

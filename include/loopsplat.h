@@ -222,6 +222,21 @@ typedef struct {
   float* rgb;
 } ls_gaussian_grads;
 
+/* Adam state of one parameter array of a Gaussian set (fused backward):
+ * first and second moments (device, the array's layout) and its rate. */
+typedef struct {
+  float* m;
+  float* v;
+  float lr;
+} ls_adam_array;
+
+/* Per render: the five arrays in ls_gaussians order. */
+typedef struct {
+  ls_adam_array mean, log_scale, quat, opacity_logit, rgb;
+} ls_gaussian_adam;
+
+#define LS_ADAM_FUSED_MAX_RENDERS 16
+
 /* Backward of ls_project + ls_render_fwd (= ls_render_bwd_tiles followed by
  * ls_render_bwd_project).  Recomputes the per-pixel transmittance back to
  * front from T_final / n_last (no per-pixel lists are stored), reduces the
@@ -466,6 +481,27 @@ typedef struct {
  * does not name the optimiser (supplement hyper-parameter tables). */
 ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, float beta1, float beta2,
                   float eps, int32_t zero_grad, hipStream_t s);
+
+/* ls_render_bwd_project (full mode) with one Adam step fused in, for the
+ * mapping and tracking iterations (Sec. 3.1): each Gaussian's gradient of
+ * this backward goes straight into an Adam update (beta1, beta2, eps, bias
+ * correction of `step` >= 1, as ls_adam) of the parameters its render job
+ * points to, updated in place, so the gradients never go to memory.  Culled
+ * Gaussians step with zero gradients, as ls_adam does for every element.
+ * Given the same gradients, the same arithmetic as ls_render_bwd_project
+ * into zeroed gradient arrays followed by ls_adam over those five arrays
+ * (the gradients themselves carry the float-atomic ordering of the tile
+ * backward).
+ *   adam:      host [R], one per render (R <= LS_ADAM_FUSED_MAX_RENDERS);
+ *              renders may not share a Gaussian array (a shared set's
+ *              gradient is only complete after all of its renders)
+ *   pose_grad: device [R][7], accumulated, or NULL; needs `pose` (the pose
+ *              takes its own step, e.g. with ls_adam)
+ * Errors: LS_ERR_INVALID (NULL state, too many renders, shared arrays, step
+ * < 1, bad constants). */
+ls_status ls_render_bwd_project_adam(const ls_batch* b, const float* pose, const ls_projected* p,
+                                     const ls_bins* bins, const ls_gaussian_adam* adam, int32_t step, float beta1,
+                                     float beta2, float eps, float* pose_grad, hipStream_t s);
 
 /* Fills `count` int32 words at `ptr` with `value` (a kernel, never a memset
  * node, so it is safe inside captured graphs). */

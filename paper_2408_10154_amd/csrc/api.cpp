@@ -414,6 +414,7 @@ int64_t ls_struct_size(const char* name) {
       {"ls_mapping_params", sizeof(ls_mapping_params)},
       {"ls_submap_adjust", sizeof(ls_submap_adjust)},
       {"ls_prune_array", sizeof(ls_prune_array)},
+      {"ls_adam_array", sizeof(ls_adam_array)},     {"ls_gaussian_adam", sizeof(ls_gaussian_adam)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -553,6 +554,51 @@ ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_p
                      at<float>(bins->work, L.g2d), b->grads_d, want_gauss, at<float>(bins->work, L.pose_part),
                      pose_grad != nullptr, pose_grad, s);
   return hip_check("ls_render_bwd_project");
+}
+
+ls_status ls_render_bwd_project_adam(const ls_batch* b, const float* pose, const ls_projected* p,
+                                     const ls_bins* bins, const ls_gaussian_adam* adam, int32_t step, float beta1,
+                                     float beta2, float eps, float* pose_grad, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p, true)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if (!adam) return fail(LS_ERR_INVALID, "NULL Adam state");
+  if (b->R > LS_ADAM_FUSED_MAX_RENDERS) return fail(LS_ERR_INVALID, "at most %d renders", LS_ADAM_FUSED_MAX_RENDERS);
+  if (step < 1) return fail(LS_ERR_INVALID, "Adam step counts from 1");
+  if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
+  if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
+    return fail(LS_ERR_INVALID, "bad Adam constants");
+  GaussAdamArgs a{};
+  for (int r = 0; r < b->R; ++r) {
+    const JobDev& J = b->jobs_h[r];
+    const float* par[5] = {J.mean, J.log_scale, J.quat, J.opac, J.rgb};
+    const ls_adam_array* arr[5] = {&adam[r].mean, &adam[r].log_scale, &adam[r].quat, &adam[r].opacity_logit,
+                                   &adam[r].rgb};
+    for (int q = 0; q < 5; ++q) {
+      if (J.n > 0 && (!arr[q]->m || !arr[q]->v || !std::isfinite(arr[q]->lr)))
+        return fail(LS_ERR_INVALID, "render %d: Adam array %d needs moments and a finite rate", r, q);
+      a.m[r][q] = arr[q]->m;
+      a.v[r][q] = arr[q]->v;
+      a.lr[r][q] = arr[q]->lr;
+      for (int o = 0; o < r; ++o) {
+        const JobDev& K = b->jobs_h[o];
+        const float* other[5] = {K.mean, K.log_scale, K.quat, K.opac, K.rgb};
+        for (int u = 0; u < 5; ++u)
+          if (J.n > 0 && K.n > 0 && par[q] == other[u])
+            return fail(LS_ERR_INVALID, "renders %d and %d share a Gaussian array: use ls_render_bwd_project", o, r);
+      }
+    }
+  }
+  a.beta1 = beta1;
+  a.beta2 = beta2;
+  a.eps = eps;
+  a.bc1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
+  a.bc2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  const Layout L = layout_of(b, bins->capacity);
+  launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, p->aux,
+                     at<float>(bins->work, L.g2d), nullptr, 1, at<float>(bins->work, L.pose_part),
+                     pose_grad != nullptr, pose_grad, s, &a);
+  return hip_check("ls_render_bwd_project_adam");
 }
 
 ls_status ls_render_bwd(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,

@@ -18,9 +18,34 @@ struct ViewOpt;
 void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose, float* rec,
                     int32_t* radius, int32_t* tiles, float* aux, const ViewOpt* live, hipStream_t s);
 
+// One Adam update of a parameter from its gradient, with explicit FMAs so
+// that every kernel applying it (k_adam, the fused backward) gives the same
+// bits.
+__device__ __forceinline__ void adam_update(float& p, float& m, float& v, float g, float lr, float beta1, float beta2,
+                                            float eps, float bc1, float bc2) {
+  m = __builtin_fmaf(beta1, m, (1.f - beta1) * g);
+  v = __builtin_fmaf(beta2, v, (1.f - beta2) * g * g);
+  p -= lr * (m * bc1) / (sqrtf(v * bc2) + eps);
+}
+
+// Adam state of the fused projection backward: per render (at most
+// kAdamRenders) and per parameter array (mean, log_scale, quat, opacity,
+// rgb) the moments and the learning rate; bias corrections of the step.
+constexpr int kAdamRenders = 16;
+struct GaussAdamArgs {
+  float* m[kAdamRenders][5];
+  float* v[kAdamRenders][5];
+  float lr[kAdamRenders][5];
+  float beta1, beta2, eps, bc1, bc2;
+};
+
+// adam (or NULL): instead of accumulating the Gaussian gradients into grads,
+// apply one Adam step to each Gaussian's parameters (the arrays its render
+// job points to) from its gradient; culled items step with zero gradients.
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
                         const int32_t* radius, const float* aux, float* g2d, const GradDev* grads, int want_gauss,
-                        float* pose_part, int want_pose, float* pose_grad, hipStream_t s);
+                        float* pose_part, int want_pose, float* pose_grad, hipStream_t s,
+                        const GaussAdamArgs* adam = nullptr);
 void launch_pose_reduce_tiles(const JobDev* jobs, int R, const float* pose, const float* tile_part, float* pose_grad,
                               hipStream_t s);
 

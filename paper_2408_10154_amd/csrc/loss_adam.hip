@@ -1,5 +1,6 @@
 // L1 registration/tracking loss with its image gradients, and fused Adam.
 #include "common.h"
+#include "kernels.h"
 
 #include <algorithm>
 
@@ -372,12 +373,11 @@ __global__ __launch_bounds__(256) void k_adam(AdamArgs a, float beta1, float bet
   float* __restrict__ v = a.v[gidx];
   const float lr = a.lr[gidx];
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
-    const float gi = g[i];
-    const float mi = beta1 * m[i] + (1.f - beta1) * gi;
-    const float vi = beta2 * v[i] + (1.f - beta2) * gi * gi;
+    float pi = p[i], mi = m[i], vi = v[i];
+    adam_update(pi, mi, vi, g[i], lr, beta1, beta2, eps, bc1, bc2);
+    p[i] = pi;
     m[i] = mi;
     v[i] = vi;
-    p[i] -= lr * (mi * bc1) / (sqrtf(vi * bc2) + eps);
     if (zero_grad) g[i] = 0.f;
   }
 }

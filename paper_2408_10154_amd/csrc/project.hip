@@ -119,11 +119,13 @@ __device__ __forceinline__ void store_grad(float* p, float v, bool shared) {
 // Chains image-space gradients (du dv dA dB dC dop dz dr dg db, accumulated
 // per item over its tiles) to the Gaussian parameters and to the per-render
 // pose correction, and clears the accumulator for the next backward.
+template <bool kAdam>
 __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ jobs, const int32_t* __restrict__ blk_off,
                                                      int R, const float* __restrict__ pose,
                                                      const int32_t* __restrict__ radius, const float4* __restrict__ aux,
                                                      float* __restrict__ g2d, const GradDev* __restrict__ grads,
-                                                     int want_gauss, float* __restrict__ pose_part, int want_pose) {
+                                                     int want_gauss, float* __restrict__ pose_part, int want_pose,
+                                                     GaussAdamArgs adam) {
   const int r = find_segment<int32_t>(blk_off, R, (int32_t)blockIdx.x);
   const JobDev& J = jobs[r];
   const int g = (blockIdx.x - J.blk_off) * 256 + threadIdx.x;
@@ -131,6 +133,17 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
   float acc[kPoseAcc];
 #pragma unroll
   for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
+
+  // fused Adam: the 14 gradient values of this Gaussian (mean 0-2,
+  // log_scale 3-5, quat 6-9, opacity 10, rgb 11-13; zero for a culled one,
+  // whose moments still decay and which still moves) are gathered first and
+  // stepped together after the chain, every load before any store
+  float* const params[5] = {const_cast<float*>(J.mean), const_cast<float*>(J.log_scale), const_cast<float*>(J.quat),
+                            const_cast<float*>(J.opac), const_cast<float*>(J.rgb)};
+  constexpr int kSlot0[5] = {0, 3, 6, 10, 11};
+  float gv[14];
+#pragma unroll
+  for (int j = 0; j < 14; ++j) gv[j] = 0.f;
 
   const int64_t item = J.item_off + g;
   if (g < n && radius[item] > 0) {
@@ -154,11 +167,16 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
     if (want_gauss) {
       float W[9], t[3];
       camera_of(J, pr, W, t);
-      const GradDev& GD = grads[r];
+      const GradDev GD = kAdam ? GradDev{params[0], params[1], params[2], params[3], params[4], 0, 0} : grads[r];
       const bool sh = GD.shared != 0;
+      // gradient of component k of array q: accumulated, or kept for the Adam step
+      auto emit = [&](int q, int k, float* base, float val) {
+        if (kAdam) gv[kSlot0[q] + k] = val;
+        else store_grad(base + (int64_t)k * n + g, val, sh);
+      };
       if (GD.mean) {
         for (int k = 0; k < 3; ++k)
-          store_grad(GD.mean + k * n + g, W[0 * 3 + k] * dp[0] + W[1 * 3 + k] * dp[1] + W[2 * 3 + k] * dp[2], sh);
+          emit(0, k, GD.mean, W[0 * 3 + k] * dp[0] + W[1 * 3 + k] * dp[1] + W[2 * 3 + k] * dp[2]);
       }
       if (GD.log_scale || GD.quat) {
         const float qw0 = J.quat[g], qx0 = J.quat[n + g], qy0 = J.quat[2 * n + g], qz0 = J.quat[3 * n + g];
@@ -180,7 +198,7 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
           for (int k = 0; k < 3; ++k) GM[i * 3 + k] = 2.f * (GS[i * 3 + 0] * M[0 * 3 + k] + GS[i * 3 + 1] * M[1 * 3 + k] + GS[i * 3 + 2] * M[2 * 3 + k]);
         if (GD.log_scale) {
           for (int k = 0; k < 3; ++k)
-            store_grad(GD.log_scale + k * n + g, s[k] * (GM[0 * 3 + k] * Rq[0 * 3 + k] + GM[1 * 3 + k] * Rq[1 * 3 + k] + GM[2 * 3 + k] * Rq[2 * 3 + k]), sh);
+            emit(1, k, GD.log_scale, s[k] * (GM[0 * 3 + k] * Rq[0 * 3 + k] + GM[1 * 3 + k] * Rq[1 * 3 + k] + GM[2 * 3 + k] * Rq[2 * 3 + k]));
         }
         if (GD.quat) {
           float GR[9];
@@ -188,15 +206,15 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
             for (int k = 0; k < 3; ++k) GR[i * 3 + k] = GM[i * 3 + k] * s[k];
           float dq[4];
           rot_backward(qw0, qx0, qy0, qz0, GR, dq);
-          for (int k = 0; k < 4; ++k) store_grad(GD.quat + k * n + g, dq[k], sh);
+          for (int k = 0; k < 4; ++k) emit(2, k, GD.quat, dq[k]);
         }
       }
       if (GD.opac) {
         const float op = 1.0f / (1.0f + __expf(-J.opac[g]));
-        store_grad(GD.opac + g, gi[5] * op * (1.f - op), sh);
+        emit(3, 0, GD.opac, gi[5] * op * (1.f - op));
       }
       if (GD.rgb) {
-        for (int k = 0; k < 3; ++k) store_grad(GD.rgb + k * n + g, gi[7 + k], sh);
+        for (int k = 0; k < 3; ++k) emit(4, k, GD.rgb, gi[7 + k]);
       }
     }
     if (want_pose && pr != nullptr) {
@@ -204,6 +222,31 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
       quat_to_rot(pr[0], pr[1], pr[2], pr[3], Rd);
       pose_contrib(p, Sc, Rd, pr + 4, dp, G, acc);
     }
+  }
+  if (kAdam && g < n) {
+    float pv[14], mv[14], vv[14];
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int k = 0; k < (q == 2 ? 4 : q == 3 ? 1 : 3); ++k) {
+        const int j2 = kSlot0[q] + k;
+        const int64_t idx = (int64_t)k * n + g;
+        pv[j2] = params[q][idx];
+        mv[j2] = adam.m[r][q][idx];
+        vv[j2] = adam.v[r][q][idx];
+      }
+#pragma unroll
+    for (int q = 0; q < 5; ++q)
+#pragma unroll
+      for (int k = 0; k < (q == 2 ? 4 : q == 3 ? 1 : 3); ++k) {
+        const int j2 = kSlot0[q] + k;
+        const int64_t idx = (int64_t)k * n + g;
+        adam_update(pv[j2], mv[j2], vv[j2], gv[j2], adam.lr[r][q], adam.beta1, adam.beta2, adam.eps, adam.bc1,
+                    adam.bc2);
+        params[q][idx] = pv[j2];
+        adam.m[r][q][idx] = mv[j2];
+        adam.v[r][q][idx] = vv[j2];
+      }
   }
   if (want_pose) {
     // fixed-order block reduction: wave sums, then the 4 waves in order
@@ -259,10 +302,16 @@ void launch_project(const JobDev* jobs, const int32_t* blk_off, int R, int nblk,
 }
 void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int nblk, const float* pose,
                         const int32_t* radius, const float* aux, float* g2d, const GradDev* grads, int want_gauss,
-                        float* pose_part, int want_pose, float* pose_grad, hipStream_t s) {
-  if (nblk > 0)
-    hipLaunchKernelGGL(k_project_bwd, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius,
-                       reinterpret_cast<const float4*>(aux), g2d, grads, want_gauss, pose_part, want_pose);
+                        float* pose_part, int want_pose, float* pose_grad, hipStream_t s, const GaussAdamArgs* adam) {
+  if (nblk > 0) {
+    if (adam)
+      hipLaunchKernelGGL(k_project_bwd<true>, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius,
+                         reinterpret_cast<const float4*>(aux), g2d, grads, 1, pose_part, want_pose, *adam);
+    else
+      hipLaunchKernelGGL(k_project_bwd<false>, dim3(nblk), dim3(256), 0, s, jobs, blk_off, R, pose, radius,
+                         reinterpret_cast<const float4*>(aux), g2d, grads, want_gauss, pose_part, want_pose,
+                         GaussAdamArgs{});
+  }
   if (want_pose)
     hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, (const float*)pose_part, pose_grad, 0);
 }

@@ -129,6 +129,16 @@ class ls_adam_group(C.Structure):
                 ("n", C.c_int64), ("lr", C.c_float)]
 
 
+class ls_adam_array(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("v", C.c_void_p), ("lr", C.c_float)]
+
+
+class ls_gaussian_adam(C.Structure):
+    _fields_ = [("mean", ls_adam_array), ("log_scale", ls_adam_array), ("quat", ls_adam_array),
+                ("opacity_logit", ls_adam_array), ("rgb", ls_adam_array)]
+
+
+LS_ADAM_FUSED_MAX_RENDERS = 16  # renders one ls_render_bwd_project_adam call steps
 LS_ISOTROPIC_WORK_FLOATS = 256  # scratch floats of ls_loss_isotropic
 LS_OVERLAP_NOALLOC_MAX_POINTS = 524288  # points per set taken by ls_overlap_ratio_noalloc
 LS_OVERLAP_NOALLOC_BYTES = 40 << 20     # its static per-device scratch array
@@ -152,6 +162,9 @@ _PROTOS = {
                                         C.POINTER(ls_image_grad), C.c_uint32, _P]),
     "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, C.c_uint32,
                                           _P]),
+    "ls_render_bwd_project_adam": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins),
+                                               C.POINTER(ls_gaussian_adam), C.c_int32, C.c_float, C.c_float,
+                                               C.c_float, _P, _P]),
     "ls_render_stats": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), C.POINTER(ls_image), _P, _P]),
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
     "ls_loss_tracking": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, C.POINTER(ls_loss_params), _P, _P, _P, _P, _P,
@@ -262,6 +275,11 @@ def ls_render_bwd_tiles(h, pose, proj, bins, bg, fwd, up, flags, stream):
 
 def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, flags, stream):
     return _call("ls_render_bwd_project", h, pose, C.byref(proj), C.byref(bins), grads, pose_grad, flags, stream)
+
+
+def ls_render_bwd_project_adam(h, pose, proj, bins, adam, step, beta1, beta2, eps, pose_grad, stream):
+    return _call("ls_render_bwd_project_adam", h, pose, C.byref(proj), C.byref(bins), adam, step, beta1, beta2, eps,
+                 pose_grad, stream)
 
 
 def ls_render_stats(h, proj, bins, fwd, stats, stream):

@@ -212,6 +212,27 @@ class RenderBatch:
         L.ls_render_bwd_project(self.h, _ptr(pose), self.proj, self.bins, garr, _ptr(pose_grad),
                                 L.BWD_POSE_ONLY if pose_only else 0, _stream())
 
+    def render_bwd_project_adam(self, adam, step: int, pose=None, pose_grad=None, beta1=0.9, beta2=0.999,
+                                eps=1e-8):
+        """render_bwd_project with the Adam step fused: adam is one
+        (moments, rates) entry per render, each a dict name -> (m, v, lr) over
+        mean, log_scale, quat, opacity_logit and rgb (m, v device tensors
+        shaped like the parameter); the batch's Gaussian sets are updated in
+        place.  The pose gradient is accumulated into pose_grad as usual."""
+        self._check_pose(pose)
+        self._check_dev(pose_grad, 7 * self.R, name="pose_grad")
+        if len(adam) != self.R:
+            raise ValueError("need one Adam state per render")
+        arr = (L.ls_gaussian_adam * self.R)()
+        for r, (st, gs) in enumerate(zip(adam, self.gsets)):
+            for name, ref in zip(("mean", "log_scale", "quat", "opacity_logit", "rgb"), gs.tensors()):
+                m, v, lr = st[name]
+                self._check_dev(m, ref.numel(), name="moment")
+                self._check_dev(v, ref.numel(), name="moment")
+                setattr(arr[r], name, L.ls_adam_array(m.data_ptr(), v.data_ptr(), float(lr)))
+        L.ls_render_bwd_project_adam(self.h, _ptr(pose), self.proj, self.bins, arr, int(step), beta1, beta2, eps,
+                                     _ptr(pose_grad), _stream())
+
     def render_stats(self):
         """(entries evaluated, entries composited) of the last forward (syncs)."""
         st = torch.zeros(2, dtype=torch.int64, device=self.device)

@@ -314,6 +314,84 @@ def test_adam_matches_oracle(gpu):
         np.testing.assert_allclose(d[0].cpu().numpy(), rf[0].numpy(), rtol=1e-5, atol=1e-5)
 
 
+def test_fused_backward_adam_matches_separate_steps(gpu):
+    """Three renders of their own Gaussian sets (some Gaussians behind the
+    camera, so culled), four mapping iterations against fixed targets:
+    ls_render_bwd_project_adam updates the parameters and moments as
+    ls_render_bwd_project into gradient arrays followed by ls_adam does, to
+    the float-atomic ordering of the tile backward (each side sums a
+    Gaussian's per-tile contributions in its own order; given the same
+    gradient both apply the same Adam arithmetic), and accumulates the same
+    pose gradients; culled Gaussians step like the others; renders sharing a
+    Gaussian set are refused."""
+    from paper_2408_10154_amd import lib as L
+    from paper_2408_10154_amd.render import adam
+
+    jobs, poses = _three_scenes()
+    for g, _, _ in jobs:
+        g["mean"][2, ::9] = -np.abs(g["mean"][2, ::9])  # every ninth Gaussian behind the camera
+    pose = torch.as_tensor(np.stack(poses), device="cuda").contiguous()
+    names = ("mean", "log_scale", "quat", "opacity_logit", "rgb")
+    lrs = dict(mean=1e-3, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, rgb=2.5e-3)
+    sides = []
+    for _ in range(2):
+        b = _batch(jobs)
+        b.project(pose)
+        b.bin_sort()
+        b.render_fwd()
+        sides.append(b)
+    tgt = [(sides[0].rgb.clone() * 0.9 + 0.05, sides[0].depth.clone() * 1.02)]
+    a, f = sides
+    grads = [g.zeros_like() for g in a.gsets]
+    mom_a = [[(torch.zeros_like(t), torch.zeros_like(t)) for t in g.tensors()] for g in a.gsets]
+    mom_f = [{n: (torch.zeros_like(t), torch.zeros_like(t), lrs[n]) for n, t in zip(names, g.tensors())}
+             for g in f.gsets]
+    pg = [torch.zeros_like(pose), torch.zeros_like(pose)]
+    for step in range(1, 5):
+        for i, b in enumerate(sides):
+            b.project(pose)
+            b.bin_sort()
+            b.render_fwd()
+            loss = torch.zeros(b.R, device="cuda")
+            g_rgb, g_depth, scale = torch.zeros_like(b.rgb), torch.zeros_like(b.depth), torch.zeros(b.R, device="cuda")
+            b.loss_l1(tgt[0][0], tgt[0][1], loss, g_rgb, g_depth, scale)
+            b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=scale)
+            if i == 0:
+                b.render_bwd_project(grads=grads, pose=pose, pose_grad=pg[0])
+                groups = []
+                for g, gr, mm in zip(b.gsets, grads, mom_a):
+                    for n, t, tg, (m, v) in zip(names, g.tensors(), gr.tensors(), mm):
+                        groups.append((t, tg, m, v, lrs[n]))
+                adam(groups, step)
+            else:
+                b.render_bwd_project_adam(mom_f, step, pose=pose, pose_grad=pg[1])
+    torch.cuda.synchronize()
+    for ga, gf, ma, mf in zip(a.gsets, f.gsets, mom_a, mom_f):
+        for n, ta, tf, (m1, v1) in zip(names, ga.tensors(), gf.tensors(), ma):
+            m1, v1, mf0, vf0 = (x.cpu().numpy() for x in (m1, v1, mf[n][0], mf[n][1]))
+            np.testing.assert_allclose(tf.cpu().numpy(), ta.cpu().numpy(), rtol=1e-6, atol=1e-7, err_msg=n)
+            np.testing.assert_allclose(mf0, m1, rtol=1e-4, atol=1e-5 * np.abs(m1).max(), err_msg=n)
+            np.testing.assert_allclose(vf0, v1, rtol=1e-4, atol=1e-5 * np.abs(v1).max(), err_msg=n)
+            culled = (np.asarray(jobs[0][0]["mean"])[2] < 0) if n == "mean" and ga is a.gsets[0] else None
+            if culled is not None:  # zero gradients: the moments decay exactly alike on both sides
+                np.testing.assert_array_equal(mf0[:, culled], m1[:, culled])
+    np.testing.assert_allclose(pg[1].cpu().numpy(), pg[0].cpu().numpy(), rtol=1e-4,
+                               atol=1e-5 * float(pg[0].abs().max()))
+    moved = [float((t - torch.as_tensor(jobs[0][0][n], device="cuda")).abs().max()) for n, t in
+             zip(names, f.gsets[0].tensors())]
+    assert min(moved) > 0  # every array took steps
+    # a batch whose renders share one Gaussian set is refused
+    from paper_2408_10154_amd.render import GaussianSet, RenderBatch
+
+    gs = GaussianSet.from_numpy(jobs[0][0])
+    shared = RenderBatch([(gs, jobs[0][1], jobs[0][2]), (gs, jobs[0][1], jobs[0][2])])
+    shared.project()
+    shared.bin_sort()
+    st = {n: (torch.zeros_like(t), torch.zeros_like(t), 1e-3) for n, t in zip(names, gs.tensors())}
+    with pytest.raises(L.LsError):
+        shared.render_bwd_project_adam([st, st], 1)
+
+
 @pytest.mark.parametrize("compact", ["0", "1"])
 @pytest.mark.parametrize("frac", [0.0, 0.37, 1.0])
 def test_bin_sort_overflow_stays_within_capacity(gpu, monkeypatch, frac, compact):
