@@ -77,10 +77,9 @@ def algorithmic_bytes(n: int, inst: int, px: int, tiles: int) -> dict:
         "fwd": 44 * inst + 28 * px,                       # record gather, image out
         "loss": 56 * px,                                  # images and targets in, gradients out
         "bwd": 44 * inst + 44 * px + 40 * n,              # record gather, image state in, 2D gradients out
-        # projection backward with the Adam step fused: 2D gradients 40, parameters 56 in and out,
-        # moments 112 in and out (the gradients never go to memory)
+        # projection backward with the Adam steps of the Gaussians and the pose fused: 2D gradients
+        # 40, parameters 56 in and out, moments 112 in and out (the gradients never go to memory)
         "bwd_project_adam": 376 * n,
-        "adam": 28 * 7,                                   # the pose: p, g, m, v read; p, m, v written
     }
 
 
@@ -531,7 +530,7 @@ def main():
     grads = gs.zeros_like()
     pose_grad = torch.zeros_like(pose)
     lr = dict(mean=1e-3, log_scale=5e-3, quat=1e-3, opacity_logit=5e-2, rgb=2.5e-3)
-    # render loop: the Gaussians' Adam step fused into the projection backward, the pose's by ls_adam
+    # render loop: the Adam steps of the Gaussians and the pose fused into the projection backward
     mom = {name: (torch.zeros_like(getattr(gs, name)), torch.zeros_like(getattr(gs, name)), lr[name])
            for name in GaussianSet.FIELDS}
     pm, pv = torch.zeros_like(pose), torch.zeros_like(pose)
@@ -548,7 +547,7 @@ def main():
     g_depth = torch.zeros_like(b.depth)
     g_scale = torch.zeros(1, device="cuda")
     stream = torch.cuda.current_stream()
-    kinds = ("project", "bin_sort", "fwd", "loss", "bwd", "bwd_project_adam", "adam")
+    kinds = ("project", "bin_sort", "fwd", "loss", "bwd", "bwd_project_adam")
     ev = {k: [] for k in kinds}
     step_no = [0]
     sp = L.C.c_void_p(stream.cuda_stream)
@@ -569,8 +568,8 @@ def main():
         run("loss", lambda: b.loss_l1(tgt_rgb, tgt_depth, loss, g_rgb, g_depth, g_scale))
         run("bwd", lambda: b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=g_scale))
         step_no[0] += 1
-        run("bwd_project_adam", lambda: b.render_bwd_project_adam([mom], step_no[0], pose=pose, pose_grad=pose_grad))
-        run("adam", lambda: adam(pose_groups, step_no[0]))
+        run("bwd_project_adam", lambda: b.render_bwd_project_adam([mom], step_no[0], pose=pose, pose_grad=pose_grad,
+                                                                  pose_adam=(pm, pv, 2e-3, 1e-2)))
 
     for _ in range(args.warmup):
         step("")

@@ -235,6 +235,15 @@ typedef struct {
   ls_adam_array mean, log_scale, quat, opacity_logit, rgb;
 } ls_gaussian_adam;
 
+/* Adam state of the renders' pose corrections: device [R][7] moments and
+ * the rates of the quaternion and translation parts. */
+typedef struct {
+  float* m;
+  float* v;
+  float lr_rot;
+  float lr_trans;
+} ls_pose_adam;
+
 #define LS_ADAM_FUSED_MAX_RENDERS 16
 
 /* Backward of ls_project + ls_render_fwd (= ls_render_bwd_tiles followed by
@@ -495,13 +504,16 @@ ls_status ls_adam(const ls_adam_group* groups, int32_t ngroups, int32_t step, fl
  *   adam:      host [R], one per render (R <= LS_ADAM_FUSED_MAX_RENDERS);
  *              renders may not share a Gaussian array (a shared set's
  *              gradient is only complete after all of its renders)
- *   pose_grad: device [R][7], accumulated, or NULL; needs `pose` (the pose
- *              takes its own step, e.g. with ls_adam)
+ *   pose_grad: device [R][7], accumulated, or NULL; needs `pose`
+ *   pose_adam: NULL, or the poses' Adam state: then each render's pose takes
+ *              the same step in the pose reduction (pose updated in place,
+ *              pose_grad, required, consumed and zeroed), as ls_adam over
+ *              pose_grad would
  * Errors: LS_ERR_INVALID (NULL state, too many renders, shared arrays, step
- * < 1, bad constants). */
-ls_status ls_render_bwd_project_adam(const ls_batch* b, const float* pose, const ls_projected* p,
-                                     const ls_bins* bins, const ls_gaussian_adam* adam, int32_t step, float beta1,
-                                     float beta2, float eps, float* pose_grad, hipStream_t s);
+ * < 1, bad constants, pose_adam without pose and pose_grad). */
+ls_status ls_render_bwd_project_adam(const ls_batch* b, float* pose, const ls_projected* p, const ls_bins* bins,
+                                     const ls_gaussian_adam* adam, const ls_pose_adam* pose_adam, int32_t step,
+                                     float beta1, float beta2, float eps, float* pose_grad, hipStream_t s);
 
 /* Fills `count` int32 words at `ptr` with `value` (a kernel, never a memset
  * node, so it is safe inside captured graphs). */

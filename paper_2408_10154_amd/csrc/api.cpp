@@ -415,6 +415,7 @@ int64_t ls_struct_size(const char* name) {
       {"ls_submap_adjust", sizeof(ls_submap_adjust)},
       {"ls_prune_array", sizeof(ls_prune_array)},
       {"ls_adam_array", sizeof(ls_adam_array)},     {"ls_gaussian_adam", sizeof(ls_gaussian_adam)},
+      {"ls_pose_adam", sizeof(ls_pose_adam)},
   };
   for (const Entry& e : table)
     if (std::strcmp(e.n, name) == 0) return (int64_t)e.s;
@@ -556,9 +557,9 @@ ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_p
   return hip_check("ls_render_bwd_project");
 }
 
-ls_status ls_render_bwd_project_adam(const ls_batch* b, const float* pose, const ls_projected* p,
-                                     const ls_bins* bins, const ls_gaussian_adam* adam, int32_t step, float beta1,
-                                     float beta2, float eps, float* pose_grad, hipStream_t s) {
+ls_status ls_render_bwd_project_adam(const ls_batch* b, float* pose, const ls_projected* p, const ls_bins* bins,
+                                     const ls_gaussian_adam* adam, const ls_pose_adam* pose_adam, int32_t step,
+                                     float beta1, float beta2, float eps, float* pose_grad, hipStream_t s) {
   if (!b) return fail(LS_ERR_INVALID, "NULL batch");
   ls_status st;
   if ((st = check_projected(p, true)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
@@ -566,6 +567,9 @@ ls_status ls_render_bwd_project_adam(const ls_batch* b, const float* pose, const
   if (b->R > LS_ADAM_FUSED_MAX_RENDERS) return fail(LS_ERR_INVALID, "at most %d renders", LS_ADAM_FUSED_MAX_RENDERS);
   if (step < 1) return fail(LS_ERR_INVALID, "Adam step counts from 1");
   if (pose_grad && !pose) return fail(LS_ERR_INVALID, "pose_grad needs the pose it is taken at");
+  if (pose_adam && (!pose_grad || !pose_adam->m || !pose_adam->v || !std::isfinite(pose_adam->lr_rot) ||
+                    !std::isfinite(pose_adam->lr_trans)))
+    return fail(LS_ERR_INVALID, "the pose step needs pose, pose_grad, moments and finite rates");
   if (!(beta1 >= 0.f && beta1 < 1.f) || !(beta2 >= 0.f && beta2 < 1.f) || !(eps > 0.f))
     return fail(LS_ERR_INVALID, "bad Adam constants");
   GaussAdamArgs a{};
@@ -594,6 +598,13 @@ ls_status ls_render_bwd_project_adam(const ls_batch* b, const float* pose, const
   a.eps = eps;
   a.bc1 = (float)(1.0 / (1.0 - std::pow((double)beta1, step)));
   a.bc2 = (float)(1.0 / (1.0 - std::pow((double)beta2, step)));
+  if (pose_adam) {
+    a.pose = pose;
+    a.pose_m = pose_adam->m;
+    a.pose_v = pose_adam->v;
+    a.lr_rot = pose_adam->lr_rot;
+    a.lr_trans = pose_adam->lr_trans;
+  }
   const Layout L = layout_of(b, bins->capacity);
   launch_project_bwd(b->jobs_d, b->blk_off_d, b->R, b->nblk_items, pose, p->radius, p->aux,
                      at<float>(bins->work, L.g2d), nullptr, 1, at<float>(bins->work, L.pose_part),

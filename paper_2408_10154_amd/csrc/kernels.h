@@ -37,6 +37,11 @@ struct GaussAdamArgs {
   float* v[kAdamRenders][5];
   float lr[kAdamRenders][5];
   float beta1, beta2, eps, bc1, bc2;
+  // optional pose step in the pose reduction: [R][7] pose and moments (NULL: none)
+  float* pose;
+  float* pose_m;
+  float* pose_v;
+  float lr_rot, lr_trans;
 };
 
 // adam (or NULL): instead of accumulating the Gaussian gradients into grads,

@@ -268,8 +268,11 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
 // Per render: sum the partials in order (per 256-item block of the render,
 // or per tile when by_tile is set), chain dL/dR_d to the quaternion,
 // accumulate into pose_grad [R][7].  One wave per render.
+// With step.pose_m set, each render's pose then takes one Adam step from the
+// accumulated gradient (as ls_adam over pose_grad), which is consumed.
 __global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const float* __restrict__ pose,
-                              const float* __restrict__ pose_part, float* __restrict__ pose_grad, int by_tile) {
+                              const float* __restrict__ pose_part, float* __restrict__ pose_grad, int by_tile,
+                              GaussAdamArgs step) {
   const int r = blockIdx.x;
   if (r >= R) return;
   const JobDev& J = jobs[r];
@@ -288,6 +291,18 @@ __global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const floa
     float* out = pose_grad + 7 * r;
     for (int k = 0; k < 4; ++k) out[k] += dq[k];
     for (int k = 0; k < 3; ++k) out[4 + k] += acc[9 + k];
+    if (step.pose_m) {
+      for (int k = 0; k < 7; ++k) {
+        const int i = 7 * r + k;
+        float p = step.pose[i], m = step.pose_m[i], v = step.pose_v[i];
+        adam_update(p, m, v, out[k], k < 4 ? step.lr_rot : step.lr_trans, step.beta1, step.beta2, step.eps, step.bc1,
+                    step.bc2);
+        step.pose[i] = p;
+        step.pose_m[i] = m;
+        step.pose_v[i] = v;
+        out[k] = 0.f;
+      }
+    }
   }
 }
 
@@ -313,7 +328,8 @@ void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int n
                          GaussAdamArgs{});
   }
   if (want_pose)
-    hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, (const float*)pose_part, pose_grad, 0);
+    hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, (const float*)pose_part, pose_grad, 0,
+                       adam ? *adam : GaussAdamArgs{});
 }
 
 // Pose reduction by tile partials (as k_pose_reduce with by_tile) followed
@@ -349,6 +365,6 @@ void launch_pose_reduce_adam(const JobDev* jobs, int R, const float* tile_part, 
 
 void launch_pose_reduce_tiles(const JobDev* jobs, int R, const float* pose, const float* tile_part, float* pose_grad,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, tile_part, pose_grad, 1);
+  hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, tile_part, pose_grad, 1, GaussAdamArgs{});
 }
 }  // namespace ls

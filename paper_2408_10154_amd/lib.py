@@ -138,6 +138,10 @@ class ls_gaussian_adam(C.Structure):
                 ("opacity_logit", ls_adam_array), ("rgb", ls_adam_array)]
 
 
+class ls_pose_adam(C.Structure):
+    _fields_ = [("m", C.c_void_p), ("v", C.c_void_p), ("lr_rot", C.c_float), ("lr_trans", C.c_float)]
+
+
 LS_ADAM_FUSED_MAX_RENDERS = 16  # renders one ls_render_bwd_project_adam call steps
 LS_ISOTROPIC_WORK_FLOATS = 256  # scratch floats of ls_loss_isotropic
 LS_OVERLAP_NOALLOC_MAX_POINTS = 524288  # points per set taken by ls_overlap_ratio_noalloc
@@ -163,8 +167,8 @@ _PROTOS = {
     "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, C.c_uint32,
                                           _P]),
     "ls_render_bwd_project_adam": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins),
-                                               C.POINTER(ls_gaussian_adam), C.c_int32, C.c_float, C.c_float,
-                                               C.c_float, _P, _P]),
+                                               C.POINTER(ls_gaussian_adam), C.POINTER(ls_pose_adam), C.c_int32,
+                                               C.c_float, C.c_float, C.c_float, _P, _P]),
     "ls_render_stats": (C.c_int32, [_P, C.POINTER(ls_projected), C.POINTER(ls_bins), C.POINTER(ls_image), _P, _P]),
     "ls_loss_l1": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, _P, _P, _P, _P, _P]),
     "ls_loss_tracking": (C.c_int32, [_P, C.POINTER(ls_image), _P, _P, C.POINTER(ls_loss_params), _P, _P, _P, _P, _P,
@@ -277,9 +281,9 @@ def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, flags, stream):
     return _call("ls_render_bwd_project", h, pose, C.byref(proj), C.byref(bins), grads, pose_grad, flags, stream)
 
 
-def ls_render_bwd_project_adam(h, pose, proj, bins, adam, step, beta1, beta2, eps, pose_grad, stream):
-    return _call("ls_render_bwd_project_adam", h, pose, C.byref(proj), C.byref(bins), adam, step, beta1, beta2, eps,
-                 pose_grad, stream)
+def ls_render_bwd_project_adam(h, pose, proj, bins, adam, pose_adam, step, beta1, beta2, eps, pose_grad, stream):
+    return _call("ls_render_bwd_project_adam", h, pose, C.byref(proj), C.byref(bins), adam, pose_adam, step, beta1,
+                 beta2, eps, pose_grad, stream)
 
 
 def ls_render_stats(h, proj, bins, fwd, stats, stream):

@@ -212,15 +212,23 @@ class RenderBatch:
         L.ls_render_bwd_project(self.h, _ptr(pose), self.proj, self.bins, garr, _ptr(pose_grad),
                                 L.BWD_POSE_ONLY if pose_only else 0, _stream())
 
-    def render_bwd_project_adam(self, adam, step: int, pose=None, pose_grad=None, beta1=0.9, beta2=0.999,
-                                eps=1e-8):
+    def render_bwd_project_adam(self, adam, step: int, pose=None, pose_grad=None, pose_adam=None, beta1=0.9,
+                                beta2=0.999, eps=1e-8):
         """render_bwd_project with the Adam step fused: adam is one
         (moments, rates) entry per render, each a dict name -> (m, v, lr) over
         mean, log_scale, quat, opacity_logit and rgb (m, v device tensors
         shaped like the parameter); the batch's Gaussian sets are updated in
-        place.  The pose gradient is accumulated into pose_grad as usual."""
+        place.  The pose gradient is accumulated into pose_grad; with
+        pose_adam = (m, v, lr_rot, lr_trans) ([R, 7] moments) the poses take
+        their step too (pose_grad consumed)."""
         self._check_pose(pose)
         self._check_dev(pose_grad, 7 * self.R, name="pose_grad")
+        pa = None
+        if pose_adam is not None:
+            pm, pv, lr_rot, lr_trans = pose_adam
+            self._check_dev(pm, 7 * self.R, name="pose moment")
+            self._check_dev(pv, 7 * self.R, name="pose moment")
+            pa = C.byref(L.ls_pose_adam(pm.data_ptr(), pv.data_ptr(), float(lr_rot), float(lr_trans)))
         if len(adam) != self.R:
             raise ValueError("need one Adam state per render")
         arr = (L.ls_gaussian_adam * self.R)()
@@ -230,7 +238,7 @@ class RenderBatch:
                 self._check_dev(m, ref.numel(), name="moment")
                 self._check_dev(v, ref.numel(), name="moment")
                 setattr(arr[r], name, L.ls_adam_array(m.data_ptr(), v.data_ptr(), float(lr)))
-        L.ls_render_bwd_project_adam(self.h, _ptr(pose), self.proj, self.bins, arr, int(step), beta1, beta2, eps,
+        L.ls_render_bwd_project_adam(self.h, _ptr(pose), self.proj, self.bins, arr, pa, int(step), beta1, beta2, eps,
                                      _ptr(pose_grad), _stream())
 
     def render_stats(self):

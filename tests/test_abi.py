@@ -43,7 +43,7 @@ def test_binding_covers_the_header():
 
 @pytest.mark.parametrize("name", ["ls_prune_array", "ls_loss_params", "ls_mapping_params", "ls_submap_adjust", "ls_pair", "ls_reg_params", "ls_reg_result", "ls_server_params", "ls_server_stats", "ls_gaussians", "ls_intrinsics", "ls_render_job", "ls_batch_info", "ls_projected",
                                   "ls_bins", "ls_image", "ls_image_grad", "ls_gaussian_grads", "ls_adam_group",
-                                  "ls_adam_array", "ls_gaussian_adam"])
+                                  "ls_adam_array", "ls_gaussian_adam", "ls_pose_adam"])
 def test_struct_layouts_match(name):
     lib = L.load()
     assert lib.ls_struct_size(name.encode()) == C.sizeof(getattr(L, name))
@@ -64,7 +64,7 @@ def test_invalid_arguments_are_rejected_without_a_device():
     grp = (L.ls_adam_group * 1)()
     assert lib.ls_adam(grp, 1, 0, 0.9, 0.999, 1e-8, 0, None) == L.LS_ERR_INVALID  # step 0
     assert lib.ls_fill_i32(None, 4, 0, None) == L.LS_ERR_INVALID
-    assert lib.ls_render_bwd_project_adam(None, None, None, None, None, 1, 0.9, 0.999, 1e-8, None,
+    assert lib.ls_render_bwd_project_adam(None, None, None, None, None, None, 1, 0.9, 0.999, 1e-8, None,
                                           None) == L.LS_ERR_INVALID
     assert lib.ls_loss_isotropic(None, -1, 1.0, None, None, None, None) == L.LS_ERR_INVALID
     assert lib.ls_loss_isotropic(None, 4, 1.0, None, None, None, None) == L.LS_ERR_INVALID  # NULL arrays

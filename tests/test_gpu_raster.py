@@ -380,6 +380,32 @@ def test_fused_backward_adam_matches_separate_steps(gpu):
     moved = [float((t - torch.as_tensor(jobs[0][0][n], device="cuda")).abs().max()) for n, t in
              zip(names, f.gsets[0].tensors())]
     assert min(moved) > 0  # every array took steps
+    # one more iteration in which the poses step too: fused into the pose
+    # reduction on one side, ls_adam over the accumulated gradient on the other
+    poses2 = [pose.clone(), pose.clone()]
+    pmv = [(torch.zeros_like(pose), torch.zeros_like(pose)) for _ in range(2)]
+    for i, b in enumerate(sides):
+        b.project(poses2[i])
+        b.bin_sort()
+        b.render_fwd()
+        loss = torch.zeros(b.R, device="cuda")
+        g_rgb, g_depth, scale = torch.zeros_like(b.rgb), torch.zeros_like(b.depth), torch.zeros(b.R, device="cuda")
+        b.loss_l1(tgt[0][0], tgt[0][1], loss, g_rgb, g_depth, scale)
+        b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=scale)
+        pg[i].zero_()
+        if i == 0:
+            b.render_bwd_project(grads=grads, pose=poses2[0], pose_grad=pg[0])
+            for r in range(b.R):  # per render: quaternion and translation groups, as the bench steps a pose
+                adam([(poses2[0][r, :4], pg[0][r, :4], pmv[0][0][r, :4], pmv[0][1][r, :4], 2e-3),
+                      (poses2[0][r, 4:], pg[0][r, 4:], pmv[0][0][r, 4:], pmv[0][1][r, 4:], 1e-2)], 5)
+        else:
+            b.render_bwd_project_adam(mom_f, 5, pose=poses2[1], pose_grad=pg[1],
+                                      pose_adam=(pmv[1][0], pmv[1][1], 2e-3, 1e-2))
+    torch.cuda.synchronize()
+    assert float(pg[1].abs().max()) == 0.0  # consumed by the fused step
+    # against ls_adam steps of the same gradient (up to its float-atomic order)
+    np.testing.assert_allclose(poses2[1].cpu().numpy(), poses2[0].cpu().numpy(), rtol=0, atol=1e-6)
+    assert float((poses2[1] - pose).abs().max()) > 0  # the poses moved
     # a batch whose renders share one Gaussian set is refused
     from paper_2408_10154_amd.render import GaussianSet, RenderBatch
 
