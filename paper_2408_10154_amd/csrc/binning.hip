@@ -302,18 +302,47 @@ __global__ __launch_bounds__(kSortThreads) void k_depth_keys_compact(const float
   __syncthreads();
   uint32_t run = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   if (blockIdx.x == 0 && threadIdx.x == 0) *nkeep = (int32_t)(wtot[0] + wtot[1] + wtot[2] + wtot[3]);
-  __syncthreads();
-  for (int i = 0; i < rounds; ++i) {
+  // every round's keep flags first; per wave a ballot gives each lane its rank
+  // and the wave's count; one barrier, then each lane's place follows from
+  // the counts of the earlier rounds and waves (item order kept)
+  __shared__ uint32_t wcnt[kSortItems][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint64_t bal[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
-    const bool keep = k < M && tiles[k] > 0;
-    uint32_t tot;
-    const uint32_t x = block_excl_scan(keep ? 1u : 0u, wsum, &tot);
-    if (keep) {
-      keys[run + x] = __float_as_uint(rec[k * 3 + 1].z);
-      vals[run + x] = (uint32_t)k;
-    }
-    run += tot;
+    const bool keep = i < rounds && k < M && tiles[k] > 0;
+    bal[i] = __ballot(keep);
+    if (i < rounds && lane == 0) wcnt[i][w] = (uint32_t)__popcll(bal[i]);
   }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if (i >= rounds) break;
+    uint32_t pre = 0;
+    for (int u = 0; u < w; ++u) pre += wcnt[i][u];
+    if ((bal[i] >> lane) & 1ull) {
+      const uint32_t pos = run + pre + (uint32_t)__popcll(bal[i] & lt);
+      const int64_t k = base + i * kSortThreads + threadIdx.x;
+      keys[pos] = __float_as_uint(rec[k * 3 + 1].z);
+      vals[pos] = (uint32_t)k;
+    }
+    run += (wcnt[i][0] + wcnt[i][1]) + (wcnt[i][2] + wcnt[i][3]);
+  }
+}
+
+// Inclusive prefix sum over the 64 lanes (DPP: shifts within 16-lane rows,
+// then the row ends broadcast to the later rows); 0 is the identity.
+__device__ __forceinline__ uint32_t wave_incl_sum(uint32_t v) {
+  int x = (int)v;
+  x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xF, 0xF, false);  // row_shr:1
+  x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xF, 0xF, false);  // row_shr:2
+  x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xF, 0xF, false);  // row_shr:4
+  x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xF, 0xF, false);  // row_shr:8
+  x += __builtin_amdgcn_update_dpp(0, x, 0x142, 0xA, 0xF, false);  // row_bcast:15 -> rows 1, 3
+  x += __builtin_amdgcn_update_dpp(0, x, 0x143, 0xC, 0xF, false);  // row_bcast:31 -> rows 2, 3
+  return (uint32_t)x;
 }
 
 // Items in the depth order: M, or the kept count when the items were
@@ -330,6 +359,10 @@ __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __re
   __shared__ uint32_t ws[4];
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
   const int64_t n = order_len(M, n_dev);
+  if (base >= n) {  // no item here
+    if (threadIdx.x == 0) bsum[blockIdx.x] = 0;
+    return;
+  }
   uint32_t s = 0;
   for (int i = 0; i < rounds; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
@@ -357,6 +390,7 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
   __shared__ uint64_t wtot[4];
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
   const int64_t n = order_len(M, n_dev);
+  if (blockIdx.x != 0 && base >= n) return;  // no item here (block 0 writes the counts)
   // the offset of this block (and, for block 0, the total over all blocks)
   const int upto = blockIdx.x == 0 ? nbd : (int)blockIdx.x;
   uint64_t before = 0, total = 0;
@@ -376,19 +410,38 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
   __syncthreads();
   uint32_t run = wsum[0] + wsum[1] + wsum[2] + wsum[3];
   const uint64_t I64 = wtot[0] + wtot[1] + wtot[2] + wtot[3];
-  __syncthreads();
-  for (int i = 0; i < rounds; ++i) {
+  // every round's counts first, an inclusive scan per wave and round (DPP),
+  // the wave totals to LDS, one barrier; then each lane's offset follows from
+  // the totals of the earlier rounds and waves
+  __shared__ uint32_t wt[kSortItems][4];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  uint32_t c[kSortItems], x[kSortItems];
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
     const int64_t k = base + i * kSortThreads + threadIdx.x;
-    const uint32_t c = k < n ? (uint32_t)tiles[order[k]] : 0u;
-    uint32_t tot;
-    const uint32_t x = block_excl_scan(c, wsum, &tot);
+    c[i] = (i < rounds && k < n) ? (uint32_t)tiles[order[k]] : 0u;
+  }
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if (i >= rounds) break;
+    const uint32_t incl = wave_incl_sum(c[i]);
+    x[i] = incl - c[i];
+    if (lane == 63) wt[i][w] = incl;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int i = 0; i < kSortItems; ++i) {
+    if (i >= rounds) break;
+    uint32_t pre = 0;
+    for (int u = 0; u < w; ++u) pre += wt[i][u];
+    const int64_t k = base + i * kSortThreads + threadIdx.x;
     if (k < n) {
-      const int64_t o = (int64_t)run + x;
+      const int64_t o = (int64_t)run + pre + x[i];
       offs[k] = (uint32_t)o;
-      for (int64_t m = (o + kEmitSpan - 1) / kEmitSpan; m < nspan && m * kEmitSpan < o + c; ++m)
+      for (int64_t m = (o + kEmitSpan - 1) / kEmitSpan; m < nspan && m * kEmitSpan < o + c[i]; ++m)
         first[m] = (uint32_t)k;
     }
-    run += tot;
+    run += (wt[i][0] + wt[i][1]) + (wt[i][2] + wt[i][3]);
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     const int64_t I = (int64_t)I64;
@@ -491,38 +544,57 @@ __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, c
 }
 
 // [start, end) of each tile's run in the sorted instance keys, for every one
-// of the T tiles, empty tiles [0, 0): the thread at the start of a run also
-// clears the tiles between the previous run's tile and its own (the first
-// thread those before the first run, the last thread those after the last
-// run); with no instances, thread t clears tile t.  The grid covers
-// max(capacity, T) threads.
+// of the T tiles, empty tiles [0, 0).  A thread takes 4 consecutive keys
+// (one 16-byte load, and its neighbours' edge keys); at the start of a run it
+// also clears the tiles between the previous run's tile and its own (the
+// first key those before the first run, the last key those after the last
+// run).  With no instances, thread t clears tiles 4t..4t+3.  The grid covers
+// ceil(max(capacity, T) / 4) threads (keys not 16-byte aligned are read one
+// by one).
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, const int32_t* __restrict__ count,
                               int32_t* __restrict__ range, int T) {
-  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t k0 = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
   const int64_t n = count[0];
   if (n == 0) {
-    if (k < T) {
-      range[2 * k] = 0;
-      range[2 * k + 1] = 0;
-    }
-    return;
-  }
-  if (k >= n) return;
-  const int64_t t = keys[k];
-  if (k == 0 || keys[k - 1] != (uint32_t)t) {
-    for (int64_t u = k == 0 ? 0 : (int64_t)keys[k - 1] + 1; u < t; ++u) {
+    for (int64_t u = k0; u < k0 + 4 && u < T; ++u) {
       range[2 * u] = 0;
       range[2 * u + 1] = 0;
     }
-    range[2 * t] = (int32_t)k;
+    return;
   }
-  if (k == n - 1 || keys[k + 1] != (uint32_t)t) {
-    range[2 * t + 1] = (int32_t)(k + 1);
-    if (k == n - 1)
-      for (int64_t u = t + 1; u < T; ++u) {
+  if (k0 >= n) return;
+  uint32_t kk[6];  // keys k0 - 1 .. k0 + 4 (valid where 0 <= index < n)
+  kk[0] = k0 > 0 ? keys[k0 - 1] : 0u;
+  if (k0 + 4 <= n && (reinterpret_cast<uintptr_t>(keys) & 15) == 0) {
+    const uint4 q = *reinterpret_cast<const uint4*>(keys + k0);
+    kk[1] = q.x;
+    kk[2] = q.y;
+    kk[3] = q.z;
+    kk[4] = q.w;
+  } else {
+    for (int j = 0; j < 4; ++j) kk[1 + j] = k0 + j < n ? keys[k0 + j] : 0u;
+  }
+  kk[5] = k0 + 4 < n ? keys[k0 + 4] : 0u;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) {
+    const int64_t k = k0 + j;
+    if (k >= n) break;
+    const int64_t t = kk[1 + j];
+    if (k == 0 || kk[j] != (uint32_t)t) {
+      for (int64_t u = k == 0 ? 0 : (int64_t)kk[j] + 1; u < t; ++u) {
         range[2 * u] = 0;
         range[2 * u + 1] = 0;
       }
+      range[2 * t] = (int32_t)k;
+    }
+    if (k == n - 1 || kk[2 + j] != (uint32_t)t) {
+      range[2 * t + 1] = (int32_t)(k + 1);
+      if (k == n - 1)
+        for (int64_t u = t + 1; u < T; ++u) {
+          range[2 * u] = 0;
+          range[2 * u + 1] = 0;
+        }
+    }
   }
 }
 
@@ -624,7 +696,7 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
     std::swap(ek, ok);
     std::swap(ev, ov);
   }
-  const int64_t nr = std::max<int64_t>(cap, T);
+  const int64_t nr = (std::max<int64_t>(cap, T) + 3) / 4;  // threads of 4 keys (or tiles)
   if (nr > 0)
     hipLaunchKernelGGL(k_tile_ranges, dim3((unsigned)((nr + 255) / 256)), dim3(256), 0, s, (const uint32_t*)tile_of,
                        (const int32_t*)count, range, T);
