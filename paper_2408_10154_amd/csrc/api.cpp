@@ -82,8 +82,10 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.dv0 = take(4 * M);
   L.dk1 = take(4 * M);
   L.dv1 = take(4 * M);
-  L.hist = take(4 * std::max<int64_t>({(int64_t)(1 << kDepthDigitBits) * nbd, (int64_t)(1 << kTileDigitBits) * nbt,
-                                        emit_spans(cap), 256}));  // digit histograms, or the first item of each span
+  // digit histograms; after the depth sort, the first tile pass's histogram
+  // followed by the first item of each emission span
+  L.hist = take(4 * std::max<int64_t>({(int64_t)(1 << kDepthDigitBits) * nbd,
+                                        (int64_t)(1 << kTileDigitBits) * nbt + emit_spans(cap), 256}));
   L.bsum = take(4 * (nbd + 8 + kMaxSortBins + 8));  // block sums, then the digit totals
   L.tk = take(4 * cap);
   L.tv = take(4 * cap);

@@ -24,6 +24,13 @@ __device__ __forceinline__ int sort_count(const int32_t* n_dev, int64_t n_static
   return (int)n;
 }
 
+// Sort blocks that hold keys (n keys, rounds x 256 per block): the histogram
+// columns of later blocks are neither written nor read (a capacity sized for
+// the worst case leaves most blocks of a pass idle).
+__device__ __forceinline__ int active_blocks(int n, int rounds) {
+  return (int)(((int64_t)n + (int64_t)rounds * kSortThreads - 1) / ((int64_t)rounds * kSortThreads));
+}
+
 // Digit histogram of one sort block's keys (kSortItems registers per thread,
 // rounds of them valid, nb keys in all) into LDS h, then to
 // hist[d * nblocks + block] (digit-major).  Equal digits within a wave are
@@ -54,8 +61,9 @@ __device__ __forceinline__ void block_digit_hist(const uint32_t (&key)[kSortItem
 }
 
 // Per-block digit histogram of kBits-bit digits, stored digit-major:
-// hist[d * nblocks + block].  Every key of the block is loaded before any is
-// counted, so the block waits for memory once, not once per round.
+// hist[d * nblocks + block], for the blocks that hold keys.  Every key of the
+// block is loaded before any is counted, so the block waits for memory once,
+// not once per round.
 template <int kBits>
 __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __restrict__ keys, const int32_t* n_dev,
                                                             int64_t n_static, int64_t cap, int shift,
@@ -63,9 +71,10 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_hist(const uint32_t* __re
   constexpr int kBins = 1 << kBits;
   __shared__ uint32_t h[kBins];
   const int n = sort_count(n_dev, n_static, cap);
-  for (int i = threadIdx.x; i < kBins; i += kSortThreads) h[i] = 0;
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
-  const int nb = base < n ? (int)min((int64_t)rounds * kSortThreads, (int64_t)n - base) : 0;
+  if (base >= n) return;  // uniform for the block: no keys, no column
+  for (int i = threadIdx.x; i < kBins; i += kSortThreads) h[i] = 0;
+  const int nb = (int)min((int64_t)rounds * kSortThreads, (int64_t)n - base);
   uint32_t key[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
@@ -126,11 +135,14 @@ __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t* wsum, 
 }
 
 // Exclusive scan of each row of a [rows][len] array in place, one 256-thread
-// block per row; row totals go to totals[row].
-__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, int64_t len,
-                                                   uint32_t* __restrict__ totals) {
+// block per row; row totals go to totals[row].  Only the columns of the sort
+// blocks that hold keys are scanned (n keys, rounds x 256 per block).
+__global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, int64_t stride,
+                                                   uint32_t* __restrict__ totals, const int32_t* n_dev,
+                                                   int64_t n_static, int64_t cap, int rounds) {
   __shared__ uint32_t wsum[4];
-  uint32_t* row = data + (int64_t)blockIdx.x * len;
+  uint32_t* row = data + (int64_t)blockIdx.x * stride;
+  const int64_t len = min(stride, (int64_t)active_blocks(sort_count(n_dev, n_static, cap), rounds));
   const int64_t per = (len + 255) / 256;
   const int64_t b = threadIdx.x * per;
   const int64_t e = min(b + per, len);
@@ -176,6 +188,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
   const int64_t bbase = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (bbase >= n) return;  // uniform for the block
   const int nb = (int)min((int64_t)rounds * kSortThreads, (int64_t)n - bbase);
+  const int nact = active_blocks(n, rounds);  // blocks with histogram columns
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   uint32_t key[kSortItems], val[kSortItems];
 #pragma unroll
@@ -193,7 +206,7 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
       const int d = tid * kPer + k;
       const uint32_t here = hist[(int64_t)d * nblocks + blockIdx.x];
       tot[k] = digit_total[d];
-      const uint32_t next = (int)blockIdx.x + 1 < nblocks ? hist[(int64_t)d * nblocks + blockIdx.x + 1] : tot[k];
+      const uint32_t next = (int)blockIdx.x + 1 < nact ? hist[(int64_t)d * nblocks + blockIdx.x + 1] : tot[k];
       cnt[k] = next - here;
       gsum += tot[k];
       lsum += cnt[k];
@@ -377,7 +390,7 @@ __global__ __launch_bounds__(kSortThreads) void k_count_sum(const uint32_t* __re
 // Exclusive offsets of every depth-sorted item: block offset (the sum of the
 // preceding block sums, formed here rather than by a scan launch) plus the
 // in-block prefix, 16 rounds of 256 items in order.  The item whose instance
-// range holds instance m * kEmitSpan (m < nspan) is recorded in first[m].
+// range holds instance m * span (m < nspan) is recorded in first[m].
 // Block 0 also writes count = {min(I, cap), I > cap, min(I, INT32_MAX), 0}.
 __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __restrict__ order,
                                                           const int32_t* __restrict__ tiles, int64_t M,
@@ -385,7 +398,7 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
                                                           int nbd,
                                                           uint32_t* __restrict__ offs, int32_t* __restrict__ count,
                                                           int64_t cap, int rounds, uint32_t* __restrict__ first,
-                                                          int64_t nspan) {
+                                                          int64_t span, int64_t nspan) {
   __shared__ uint32_t wsum[4];
   __shared__ uint64_t wtot[4];
   const int64_t base = (int64_t)blockIdx.x * rounds * kSortThreads;
@@ -438,7 +451,7 @@ __global__ __launch_bounds__(kSortThreads) void k_offsets(const uint32_t* __rest
     if (k < n) {
       const int64_t o = (int64_t)run + pre + x[i];
       offs[k] = (uint32_t)o;
-      for (int64_t m = (o + kEmitSpan - 1) / kEmitSpan; m < nspan && m * kEmitSpan < o + c[i]; ++m)
+      for (int64_t m = (o + span - 1) / span; m < nspan && m * span < o + c[i]; ++m)
         first[m] = (uint32_t)k;
     }
     run += (wt[i][0] + wt[i][1]) + (wt[i][2] + wt[i][3]);
@@ -465,8 +478,8 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 }
 
 // Emission of the tile instances in depth order, one wave per span of
-// kEmitSpan consecutive instances (so every wave has the same work, however
-// many tiles its items cover).  The wave takes the items from the span's first
+// consecutive instances (so every wave has the same work, however many tiles
+// its items cover).  The wave takes the items from the span's first
 // one on, 64 at a time, lane l item kb + l: its instance offset, its tile
 // rectangle and the key of the rectangle's first tile.  It fills the span 64
 // instances at a time, lane l writing instance W0 + l, so every store is one
@@ -477,23 +490,32 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // positions before the first start keep the previous owner (at first, lane 0:
 // the item that holds the span's first instance).  Within its owner's
 // rectangle, instance q lies in row q / width (row by row, as the tiles are
-// counted).  Instances at or beyond the capacity are not written.
-__global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
+// counted).  Instances at or beyond the capacity are not written.  The
+// kEmitWaves spans of a block are the positions of one block of the first
+// tile radix pass, whose digit histogram the block counts as it writes (LDS) and stores
+// digit-major in hist[d * gridDim.x + block], as the histogram kernel would.
+__global__ __launch_bounds__(64 * kEmitWaves) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
                                               int R, const uint32_t* __restrict__ order,
                                               const float4* __restrict__ rec, const int32_t* __restrict__ radius,
                                               const int32_t* __restrict__ tiles, int64_t M_all, const int32_t* n_dev,
                                               const uint32_t* __restrict__ offs, const int32_t* __restrict__ count,
-                                              const uint32_t* __restrict__ first, int64_t nspan,
-                                              uint32_t* __restrict__ kout, int32_t* __restrict__ vout) {
-  __shared__ int marks[4][64];
+                                              const uint32_t* __restrict__ first, int64_t span_len, int64_t nspan,
+                                              uint32_t* __restrict__ kout, int32_t* __restrict__ vout,
+                                              uint32_t* __restrict__ hist) {
+  static_assert(kTileDigitBits == 8 && 64 * kEmitWaves >= 256, "a histogram bin per thread of the first 256");
+  __shared__ int marks[kEmitWaves][64];
+  __shared__ uint32_t h[256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t span = (int64_t)blockIdx.x * 4 + w;
   const int64_t I = count[0];  // already clamped to the capacity
+  if ((int64_t)blockIdx.x * kEmitWaves * span_len >= I) return;  // uniform: no instance, no histogram column
+  if (threadIdx.x < 256) h[threadIdx.x] = 0u;
+  __syncthreads();
+  const int64_t span = (int64_t)blockIdx.x * kEmitWaves + w;
   const int64_t M = order_len(M_all, n_dev);
-  if (span >= nspan || span * kEmitSpan >= I) return;  // uniform for the wave
-  const int64_t iend = min((span + 1) * kEmitSpan, I);
-  int64_t kb = (int64_t)first[span];
-  int64_t W0 = span * kEmitSpan;
+  const bool work = span < nspan && span * span_len < I;  // uniform for the wave
+  const int64_t iend = work ? min((span + 1) * span_len, I) : 0;
+  int64_t kb = work ? (int64_t)first[span] : M;
+  int64_t W0 = span * span_len;
   while (W0 < iend && kb < M) {
     const int64_t k = kb + lane;
     const int last = (int)min((int64_t)63, M - 1 - kb);  // last lane with an item
@@ -533,14 +555,18 @@ __global__ __launch_bounds__(256) void k_emit(const JobDev* __restrict__ jobs, c
         int dy = (int)((float)q * o_inv);
         if ((dy + 1) * o_wdt <= q) ++dy;
         else if (dy * o_wdt > q) --dy;
-        kout[i] = (uint32_t)(o_key + dy * o_stride + q);
+        const uint32_t key = (uint32_t)(o_key + dy * o_stride + q);
+        kout[i] = key;
         vout[i] = (int32_t)o_it;
+        atomicAdd(&h[key & 255u], 1u);
       }
       __builtin_amdgcn_wave_barrier();
       W0 = min(W0 + 64, cend);
     }
     kb += 64;
   }
+  __syncthreads();
+  if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
 // [start, end) of each tile's run in the sorted instance keys, for every one
@@ -616,7 +642,8 @@ static void radix_pass(const uint32_t* kin, const uint32_t* vin, uint32_t* kout,
   if (!hist_done)
     hipLaunchKernelGGL(k_sort_hist<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, n_dev, n_static, cap, shift,
                        hist, nblocks, rounds);
-  hipLaunchKernelGGL(k_scan_rows, dim3(1 << kBits), dim3(256), 0, s, hist, (int64_t)nblocks, digit_total);
+  hipLaunchKernelGGL(k_scan_rows, dim3(1 << kBits), dim3(256), 0, s, hist, (int64_t)nblocks, digit_total, n_dev,
+                     n_static, cap, rounds);
   hipLaunchKernelGGL(k_sort_scatter<kBits>, dim3(nblocks), dim3(kSortThreads), 0, s, kin, vin, kout, vout, n_dev,
                      n_static, cap, shift, (const uint32_t*)hist, nblocks, (const uint32_t*)digit_total, rounds);
 }
@@ -675,24 +702,27 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   uint32_t* offs = ka;  // the free key buffer holds the per-item offsets
   hipLaunchKernelGGL(k_count_sum, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const int32_t*)nkeep, rd,
                      bsum);
-  const int64_t nspan = emit_spans(cap);
-  uint32_t* first = hist;  // free between the depth sort and the tile sort
+  const int rt = sort_rounds(cap), nbt = (int)sort_blocks(cap);
+  const int64_t span = emit_span(cap), nspan = emit_spans(cap);
+  // the emission spans of block b are the positions of tile-sort block b
+  // (kEmitWaves spans per block: nbt blocks cover the spans)
+  uint32_t* first = hist + (int64_t)(1 << kTileDigitBits) * nbt;  // after the first tile pass's histogram
   hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const int32_t*)nkeep,
                      (const uint32_t*)bsum, nbd,
-                     offs, count, cap, rd, first, nspan);
+                     offs, count, cap, rd, first, span, nspan);
   // emission lands in the buffer that, after tile_passes ping-pongs, is the output
   uint32_t* ek = (tile_passes & 1) ? tk : tile_of;
   uint32_t* ev = (tile_passes & 1) ? tv : reinterpret_cast<uint32_t*>(item);
   uint32_t* ok = (tile_passes & 1) ? tile_of : tk;
   uint32_t* ov = (tile_passes & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
-  if (nspan > 0 && M > 0)
-    hipLaunchKernelGGL(k_emit, dim3((unsigned)((nspan + 3) / 4)), dim3(256), 0, s, jobs, item_off_d, R, order, rec4,
-                       radius, tiles, M, (const int32_t*)nkeep, (const uint32_t*)offs, (const int32_t*)count,
-                       (const uint32_t*)first, nspan,
-                       ek, reinterpret_cast<int32_t*>(ev));
-  const int rt = sort_rounds(cap), nbt = (int)sort_blocks(cap);
+  const bool emitted = nbt > 0 && M > 0;
+  if (emitted)
+    hipLaunchKernelGGL(k_emit, dim3((unsigned)nbt), dim3(64 * kEmitWaves), 0, s, jobs, item_off_d, R, order, rec4, radius, tiles,
+                       M, (const int32_t*)nkeep, (const uint32_t*)offs, (const int32_t*)count,
+                       (const uint32_t*)first, span, nspan, ek, reinterpret_cast<int32_t*>(ev), hist);
   for (int p = 0; p < tile_passes && nbt > 0; ++p) {
-    radix_pass<kTileDigitBits>(ek, ev, ok, ov, count, 0, cap, kTileDigitBits * p, hist, digit_base, nbt, rt, s);
+    radix_pass<kTileDigitBits>(ek, ev, ok, ov, count, 0, cap, kTileDigitBits * p, hist, digit_base, nbt, rt, s,
+                               p == 0 && emitted);
     std::swap(ek, ok);
     std::swap(ev, ov);
   }

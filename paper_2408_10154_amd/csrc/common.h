@@ -34,10 +34,15 @@ __host__ __device__ inline int64_t sort_blocks(int64_t n) {
   const int64_t per = (int64_t)sort_rounds(n) * kSortThreads;
   return (n + per - 1) / per;
 }
-// Tile instances emitted per wave; the first item of every span is recorded
-// while the item offsets are formed (in the sort histogram buffer, free then).
-constexpr int kEmitSpan = 512;
-__host__ __device__ inline int64_t emit_spans(int64_t cap) { return (cap + kEmitSpan - 1) / kEmitSpan; }
+// Tile instances emitted per wave: an eighth of a tile-sort block, so the
+// kEmitWaves waves of an emission block fill exactly the positions of one
+// block of the first tile pass and can count its digits.  The first item of
+// every span is recorded while the item offsets are formed.
+constexpr int kEmitWaves = 8;
+__host__ __device__ inline int64_t emit_span(int64_t cap) {
+  return (int64_t)sort_rounds(cap) * (kSortThreads / kEmitWaves);
+}
+__host__ __device__ inline int64_t emit_spans(int64_t cap) { return (cap + emit_span(cap) - 1) / emit_span(cap); }
 constexpr int kGrad2D = 10;         // du dv dA dB dC dop dz dr dg db
 constexpr int kPoseAcc = 12;        // dL/dR (9, row-major) and dL/dt (3)
 constexpr int kAuxFloats = 12;      // per item: camera-space mean (3), covariance (6), 0 x3
