@@ -270,21 +270,52 @@ __global__ __launch_bounds__(256) void k_project_bwd(const JobDev* __restrict__ 
 // accumulate into pose_grad [R][7].  One wave per render.
 // With step.pose_m set, each render's pose then takes one Adam step from the
 // accumulated gradient (as ls_adam over pose_grad), which is consumed.
-__global__ void k_pose_reduce(const JobDev* __restrict__ jobs, int R, const float* __restrict__ pose,
-                              const float* __restrict__ pose_part, float* __restrict__ pose_grad, int by_tile,
-                              GaussAdamArgs step) {
+constexpr int kPoseSumThreads = 256;
+
+// Sum of the kPoseAcc-float rows part[first .. first + nb) over a block of
+// kPoseSumThreads threads in a fixed order: strided per-thread sums (each
+// row three 16-byte loads, four rows in flight per thread), wave sums, then
+// the four waves in order.  Thread 0 returns the totals.
+__device__ __forceinline__ void block_pose_sum(const float* __restrict__ part, int first, int nb,
+                                               float (&acc)[kPoseAcc]) {
+  static_assert(kPoseAcc == 12, "a row is three float4");
+  __shared__ float ws[kPoseSumThreads / 64][kPoseAcc];
+  const float4* p4 = reinterpret_cast<const float4*>(part);
+#pragma unroll
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
+  auto add = [&](const float4* row) {
+    const float4 x = row[0], y = row[1], z = row[2];
+    acc[0] += x.x; acc[1] += x.y; acc[2] += x.z; acc[3] += x.w;
+    acc[4] += y.x; acc[5] += y.y; acc[6] += y.z; acc[7] += y.w;
+    acc[8] += z.x; acc[9] += z.y; acc[10] += z.z; acc[11] += z.w;
+  };
+#pragma unroll 4
+  for (int b = threadIdx.x; b < nb; b += kPoseSumThreads) add(p4 + 3 * (int64_t)(first + b));
+#pragma unroll
+  for (int k = 0; k < kPoseAcc; ++k) acc[k] = wave_sum(acc[k]);
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0)
+#pragma unroll
+    for (int k = 0; k < kPoseAcc; ++k) ws[w][k] = acc[k];
+  __syncthreads();
+  if (threadIdx.x == 0)
+#pragma unroll
+    for (int k = 0; k < kPoseAcc; ++k) acc[k] = (ws[0][k] + ws[1][k]) + (ws[2][k] + ws[3][k]);
+}
+
+__global__ __launch_bounds__(kPoseSumThreads) void k_pose_reduce(const JobDev* __restrict__ jobs, int R,
+                                                                 const float* __restrict__ pose,
+                                                                 const float* __restrict__ pose_part,
+                                                                 float* __restrict__ pose_grad, int by_tile,
+                                                                 GaussAdamArgs step) {
   const int r = blockIdx.x;
   if (r >= R) return;
   const JobDev& J = jobs[r];
   const int first = by_tile ? J.tile_off : J.blk_off;
   const int nb = by_tile ? J.TX * J.TY : (J.n + 255) / 256;
-  const int lane = threadIdx.x;
   float acc[kPoseAcc];
-  for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
-  for (int b = lane; b < nb; b += 64)
-    for (int k = 0; k < kPoseAcc; ++k) acc[k] += pose_part[(int64_t)(first + b) * kPoseAcc + k];
-  for (int k = 0; k < kPoseAcc; ++k) acc[k] = wave_sum(acc[k]);
-  if (lane == 0) {
+  block_pose_sum(pose_part, first, nb, acc);
+  if (threadIdx.x == 0) {
     const float* pr = pose + 7 * r;
     float dq[4];
     rot_backward(pr[0], pr[1], pr[2], pr[3], acc, dq);
@@ -328,26 +359,24 @@ void launch_project_bwd(const JobDev* jobs, const int32_t* blk_off, int R, int n
                          GaussAdamArgs{});
   }
   if (want_pose)
-    hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, (const float*)pose_part, pose_grad, 0,
-                       adam ? *adam : GaussAdamArgs{});
+    hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(kPoseSumThreads), 0, s, jobs, R, pose, (const float*)pose_part,
+                       pose_grad, 0, adam ? *adam : GaussAdamArgs{});
 }
 
 // Pose reduction by tile partials (as k_pose_reduce with by_tile) followed
 // by the render's Adam step; block 0 also folds the overflow count into the
 // sticky flag.
-__global__ void k_pose_reduce_adam(const JobDev* __restrict__ jobs, int R, const float* __restrict__ tile_part,
-                                   PoseAdamArgs a, const int32_t* __restrict__ count, int32_t* __restrict__ sticky) {
+__global__ __launch_bounds__(kPoseSumThreads) void k_pose_reduce_adam(const JobDev* __restrict__ jobs, int R,
+                                                                      const float* __restrict__ tile_part,
+                                                                      PoseAdamArgs a,
+                                                                      const int32_t* __restrict__ count,
+                                                                      int32_t* __restrict__ sticky) {
   const int r = blockIdx.x;
   if (r >= R) return;
   const JobDev& J = jobs[r];
-  const int first = J.tile_off, nb = J.TX * J.TY;
-  const int lane = threadIdx.x;
   float acc[kPoseAcc];
-  for (int k = 0; k < kPoseAcc; ++k) acc[k] = 0.f;
-  for (int b = lane; b < nb; b += 64)
-    for (int k = 0; k < kPoseAcc; ++k) acc[k] += tile_part[(int64_t)(first + b) * kPoseAcc + k];
-  for (int k = 0; k < kPoseAcc; ++k) acc[k] = wave_sum(acc[k]);
-  if (lane == 0) {
+  block_pose_sum(tile_part, J.tile_off, J.TX * J.TY, acc);
+  if (threadIdx.x == 0) {
     const float* pr = a.pose + 7 * r;
     float dq[4], g[7];
     rot_backward(pr[0], pr[1], pr[2], pr[3], acc, dq);
@@ -360,11 +389,13 @@ __global__ void k_pose_reduce_adam(const JobDev* __restrict__ jobs, int R, const
 
 void launch_pose_reduce_adam(const JobDev* jobs, int R, const float* tile_part, const PoseAdamArgs& a,
                              const int32_t* count, int32_t* sticky, hipStream_t s) {
-  if (R > 0) hipLaunchKernelGGL(k_pose_reduce_adam, dim3(R), dim3(64), 0, s, jobs, R, tile_part, a, count, sticky);
+  if (R > 0)
+    hipLaunchKernelGGL(k_pose_reduce_adam, dim3(R), dim3(kPoseSumThreads), 0, s, jobs, R, tile_part, a, count, sticky);
 }
 
 void launch_pose_reduce_tiles(const JobDev* jobs, int R, const float* pose, const float* tile_part, float* pose_grad,
                               hipStream_t s) {
-  hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(64), 0, s, jobs, R, pose, tile_part, pose_grad, 1, GaussAdamArgs{});
+  hipLaunchKernelGGL(k_pose_reduce, dim3(R), dim3(kPoseSumThreads), 0, s, jobs, R, pose, tile_part, pose_grad, 1,
+                     GaussAdamArgs{});
 }
 }  // namespace ls
