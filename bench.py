@@ -75,8 +75,10 @@ def algorithmic_bytes(n: int, inst: int, px: int, tiles: int) -> dict:
         "project": 88 * n,                                # parameters 56 in, record 32 out
         "bin_sort": 28 * n + 44 * inst + 8 * tiles,       # scan 8 + emit read 20; emit 12, sort 24, ranges 8
         "fwd": 44 * inst + 28 * px,                       # record gather, image out
-        "loss": 56 * px,                                  # images and targets in, gradients out
-        "bwd": 44 * inst + 44 * px + 40 * n,              # record gather, image state in, 2D gradients out
+        # the L1 gradient is formed inside the backward, which also writes each tile's loss
+        # partial; "loss" is the per-render sum of those partials
+        "loss": 8 * tiles,
+        "bwd": 44 * inst + 60 * px + 40 * n + 8 * tiles,  # records, image state + images + targets, 2D grads
         # projection backward with the Adam steps of the Gaussians and the pose fused: 2D gradients
         # 40, parameters 56 in and out, moments 112 in and out (the gradients never go to memory)
         "bwd_project_adam": 376 * n,
@@ -547,7 +549,9 @@ def main():
     g_depth = torch.zeros_like(b.depth)
     g_scale = torch.zeros(1, device="cuda")
     stream = torch.cuda.current_stream()
-    kinds = ("project", "bin_sort", "fwd", "loss", "bwd", "bwd_project_adam")
+    # 1 / |Omega| of the fixed targets, once (ls_loss_l1's grad_scale)
+    b.loss_l1(tgt_rgb, tgt_depth, loss, g_rgb, g_depth, g_scale)
+    kinds = ("project", "bin_sort", "fwd", "bwd", "loss", "bwd_project_adam")
     ev = {k: [] for k in kinds}
     step_no = [0]
     sp = L.C.c_void_p(stream.cuda_stream)
@@ -565,8 +569,8 @@ def main():
         run("project", lambda: b.project(pose))
         run("bin_sort", lambda: L.ls_bin_sort(b.h, b.proj, b.bins, sp))
         run("fwd", lambda: b.render_fwd())
-        run("loss", lambda: b.loss_l1(tgt_rgb, tgt_depth, loss, g_rgb, g_depth, g_scale))
-        run("bwd", lambda: b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=g_scale))
+        run("bwd", lambda: b.render_bwd_tiles_l1(tgt_rgb, tgt_depth, g_scale))
+        run("loss", lambda: b.loss_l1_tiles(loss))
         step_no[0] += 1
         run("bwd_project_adam", lambda: b.render_bwd_project_adam([mom], step_no[0], pose=pose, pose_grad=pose_grad,
                                                                   pose_adam=(pm, pv, 2e-3, 1e-2)))

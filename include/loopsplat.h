@@ -279,6 +279,32 @@ ls_status ls_render_bwd_tiles(const ls_batch* b, const float* pose, const ls_pro
                               const float* bg, const ls_image* fwd, const ls_image_grad* up, uint32_t flags,
                               hipStream_t s);
 
+/* ls_loss_l1 followed by ls_render_bwd_tiles, fused (Sec. 3.2 loss, as
+ * ls_loss_l1 defines it): the per-pixel gradient, sign(x - x*) on Omega
+ * times inv_count[r] for each colour channel and the depth (0 outside Omega),
+ * is formed inside the compositing backward from the forward images and the
+ * targets, so no gradient images are written or read.  Each tile also stores
+ * its sum of the loss terms and its count of pixels in Omega in the bins
+ * workspace, from which ls_loss_l1_tiles forms the loss.
+ *   fwd        the forward's images: rgb, depth, T_final and n_last are read
+ *   tgt_rgb, tgt_depth: device targets in the batch's image layout
+ *   inv_count  device [R]: 1 / |Omega| per render, as ls_loss_l1 writes it to
+ *              grad_scale for the same targets (it depends on them only)
+ *   flags      0 (full mode, as ls_render_bwd_tiles) or LS_BWD_POSE_ONLY
+ * The Gaussian and pose gradients equal those of ls_loss_l1 +
+ * ls_render_bwd_tiles bit for bit in pose-only mode and up to the order of
+ * the float atomics in full mode.  Errors: LS_ERR_INVALID (missing images,
+ * targets or inv_count, unknown flags). */
+ls_status ls_render_bwd_tiles_l1(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                                 const float* bg, const ls_image* fwd, const float* tgt_rgb, const float* tgt_depth,
+                                 const float* inv_count, uint32_t flags, hipStream_t s);
+
+/* The L1 loss of the last ls_render_bwd_tiles_l1 on these bins: loss (device
+ * [R], written) = (1/|Omega|) sum over Omega of the per-pixel terms, as
+ * ls_loss_l1 computes it but summed tile by tile (equal to its value up to
+ * FP32 rounding); 0 for a render with no pixel in Omega. */
+ls_status ls_loss_l1_tiles(const ls_batch* b, const ls_bins* bins, float* loss, hipStream_t s);
+
 /* Second half of ls_render_bwd: chains the accumulated image-space gradients
  * through the EWA projection to the Gaussian parameters and the pose (full
  * mode), or sums the per-tile pose partials of each render (LS_BWD_POSE_ONLY;

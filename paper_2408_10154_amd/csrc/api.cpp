@@ -64,7 +64,7 @@ ls_status overlap_check_args(const float* p_mean, int32_t np, const float* q_mea
 namespace {
 
 struct Layout {
-  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, queues, total;
+  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, loss_part, queues, total;
 };
 
 Layout layout_of(const ls_batch* b, int64_t cap) {
@@ -92,6 +92,7 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.g2d = take(4 * (size_t)kGrad2D * M);
   L.tile_part = take(4 * (size_t)kPoseAcc * std::max(b->T, 1));
   L.pose_part = take(4 * (size_t)kPoseAcc * std::max(b->nblk_items, 1));
+  L.loss_part = take(8 * (size_t)std::max(b->T, 1));  // per tile {L1 sum, pixels in Omega}
   L.queues = take(kTileQueueBytes);
   L.total = off;
   return L;
@@ -367,7 +368,7 @@ ls_status render_bwd_pose_l1(const ls_batch* b, const float* pose, const ls_proj
     return fail(LS_ERR_INVALID, "forward images or 1 / |Omega| missing");
   const Layout L = layout_of(b, bins->capacity);
   const float zero[3] = {0.f, 0.f, 0.f};
-  const L1Targets l1{fwd->rgb, fwd->depth, tgt_rgb, tgt_depth};
+  const L1Targets l1{fwd->rgb, fwd->depth, tgt_rgb, tgt_depth, nullptr};
   launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range, zero,
                        fwd->T_final, fwd->n_last, nullptr, nullptr, nullptr, scale, at<float>(bins->work, L.g2d),
                        at<float>(bins->work, L.tile_part), 1, at<char>(bins->work, L.queues), s, &l1);
@@ -510,6 +511,35 @@ ls_status ls_render_bwd_tiles(const ls_batch* b, const float* pose, const ls_pro
                        at<float>(bins->work, L.g2d), at<float>(bins->work, L.tile_part),
                        (flags & LS_BWD_POSE_ONLY) ? 1 : 0, at<char>(bins->work, L.queues), s);
   return hip_check("ls_render_bwd_tiles");
+}
+
+ls_status ls_render_bwd_tiles_l1(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,
+                                 const float* bg, const ls_image* fwd, const float* tgt_rgb, const float* tgt_depth,
+                                 const float* inv_count, uint32_t flags, hipStream_t s) {
+  if (!b) return fail(LS_ERR_INVALID, "NULL batch");
+  ls_status st;
+  if ((st = check_projected(p, true)) || (st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  if (!fwd || !fwd->T_final || !fwd->n_last || !fwd->rgb || !fwd->depth)
+    return fail(LS_ERR_INVALID, "forward images (rgb, depth, T_final, n_last) missing");
+  if (!tgt_rgb || !tgt_depth || !inv_count) return fail(LS_ERR_INVALID, "targets or 1 / |Omega| missing");
+  if (flags & ~LS_BWD_POSE_ONLY) return fail(LS_ERR_INVALID, "unknown backward flags");
+  const Layout L = layout_of(b, bins->capacity);
+  const float zero[3] = {0.f, 0.f, 0.f};
+  const L1Targets l1{fwd->rgb, fwd->depth, tgt_rgb, tgt_depth, at<float>(bins->work, L.loss_part)};
+  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range,
+                       bg ? bg : zero, fwd->T_final, fwd->n_last, nullptr, nullptr, nullptr, inv_count,
+                       at<float>(bins->work, L.g2d), at<float>(bins->work, L.tile_part),
+                       (flags & LS_BWD_POSE_ONLY) ? 1 : 0, at<char>(bins->work, L.queues), s, &l1);
+  return hip_check("ls_render_bwd_tiles_l1");
+}
+
+ls_status ls_loss_l1_tiles(const ls_batch* b, const ls_bins* bins, float* loss, hipStream_t s) {
+  if (!b || !loss) return fail(LS_ERR_INVALID, "NULL batch or loss");
+  ls_status st;
+  if ((st = check_bins(b, bins)) || (st = ensure_device(b))) return st;
+  const Layout L = layout_of(b, bins->capacity);
+  launch_tile_loss_reduce(b->jobs_d, b->R, at<float>(bins->work, L.loss_part), loss, s);
+  return hip_check("ls_loss_l1_tiles");
 }
 
 ls_status ls_render_bwd_project(const ls_batch* b, const float* pose, const ls_projected* p, const ls_bins* bins,

@@ -467,6 +467,7 @@ __device__ __forceinline__ void bwd_apply(const BwdEval& e, float4 col, float z,
 struct BwdPixel {
   float T, gR, gG, gB, gD, acc;
   int nl;
+  float lsum, lcnt;  // the pixel's L1 terms and 1 when it lies in Omega (L1 targets only), else 0
 };
 
 __device__ __forceinline__ float l1_sign(float d) { return d > 0.f ? 1.f : (d < 0.f ? -1.f : 0.f); }
@@ -475,7 +476,7 @@ __device__ __forceinline__ BwdPixel bwd_pixel(const TileCtx& c, const JobDev& J,
                                               const float* fwd_T, const int32_t* fwd_n, const float* up_rgb,
                                               const float* up_depth, const float* up_alpha, const float* up_scale,
                                               const L1Targets& l1) {
-  BwdPixel p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0};
+  BwdPixel p{1.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0, 0.f, 0.f};
   if (c.inside) {
     const int64_t hw = (int64_t)J.W * J.H;
     const int64_t ci = 3 * J.pix_off + (int64_t)c.y * J.W + c.x;
@@ -486,10 +487,16 @@ __device__ __forceinline__ BwdPixel bwd_pixel(const TileCtx& c, const JobDev& J,
       const float* trgb = l1.tgt_rgb ? l1.tgt_rgb + ci : J.tgt_rgb + q;
       const float td = l1.tgt_depth ? l1.tgt_depth[c.pix] : J.tgt_depth[q];
       const bool valid = td > 0.f;
-      p.gR = sc * (valid ? l1_sign(l1.pred_rgb[ci] - trgb[0]) : 0.f);
-      p.gG = sc * (valid ? l1_sign(l1.pred_rgb[ci + hw] - trgb[hw]) : 0.f);
-      p.gB = sc * (valid ? l1_sign(l1.pred_rgb[ci + 2 * hw] - trgb[2 * hw]) : 0.f);
-      p.gD = sc * (valid ? l1_sign(l1.pred_depth[c.pix] - td) : 0.f);
+      const float d0 = l1.pred_rgb[ci] - trgb[0], d1 = l1.pred_rgb[ci + hw] - trgb[hw];
+      const float d2 = l1.pred_rgb[ci + 2 * hw] - trgb[2 * hw], dd = l1.pred_depth[c.pix] - td;
+      p.gR = sc * (valid ? l1_sign(d0) : 0.f);
+      p.gG = sc * (valid ? l1_sign(d1) : 0.f);
+      p.gB = sc * (valid ? l1_sign(d2) : 0.f);
+      p.gD = sc * (valid ? l1_sign(dd) : 0.f);
+      if (valid) {  // summed as the loss kernel sums a pixel: depth, then the channels in order
+        p.lsum = ((fabsf(dd) + fabsf(d0)) + fabsf(d1)) + fabsf(d2);
+        p.lcnt = 1.f;
+      }
     }
     if (up_rgb) { p.gR = sc * up_rgb[ci]; p.gG = sc * up_rgb[ci + hw]; p.gB = sc * up_rgb[ci + 2 * hw]; }
     if (up_depth) p.gD = sc * up_depth[c.pix];
@@ -538,6 +545,24 @@ __device__ __forceinline__ void stage_chunk(int lane, int cnt, int chunk, int st
   }
 }
 
+// The tile's L1 loss partial (L1 targets with loss_part): each wave's sums to
+// LDS before the caller's next barrier (tile_loss_put), and after it threads 0
+// and 1 write {sum, count} over the four waves in order (tile_loss_get).
+__device__ __forceinline__ void tile_loss_put(const L1Targets& l1, const BwdPixel& px, float (*sl)[4]) {
+  if (!l1.loss_part) return;
+  const float s = wave_sum(px.lsum), n = wave_sum(px.lcnt);
+  if ((threadIdx.x & 63) == 0) {
+    sl[0][threadIdx.x >> 6] = s;
+    sl[1][threadIdx.x >> 6] = n;
+  }
+}
+__device__ __forceinline__ void tile_loss_get(const L1Targets& l1, float (*sl)[4], int tile) {
+  if (l1.loss_part && threadIdx.x < 2) {
+    const float* v = sl[threadIdx.x];
+    l1.loss_part[2 * (int64_t)tile + threadIdx.x] = (v[0] + v[1]) + (v[2] + v[3]);
+  }
+}
+
 // Full mode: the ten per-pixel terms of each entry are summed over each
 // wave's 64 lanes (wave_sums), the four wave sums of the block over LDS in a
 // fixed order, and the ten gradients formed from them are added to the item's
@@ -553,8 +578,9 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
                                                           const float* __restrict__ up_depth,
                                                           const float* __restrict__ up_alpha,
                                                           const float* __restrict__ up_scale,
-                                                          float* __restrict__ g2d, int tile) {
+                                                          float* __restrict__ g2d, const L1Targets& l1, int tile) {
   __shared__ float4 s0[kBwdChunk], s1[kBwdChunk], s2[kBwdChunk];
+  __shared__ float sloss[2][4];
   __shared__ int32_t sit[kBwdChunk];
   __shared__ uint32_t smask[kBwdChunk];
   __shared__ uint8_t slist[4][kBwdChunk];
@@ -569,12 +595,13 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wval = wave_value<kGrad2D>(lane);  // the value whose wave sum this lane stores, or -1
   const int tx0 = c.x0, ty0 = c.y0;
-  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale,
-                          L1Targets{nullptr, nullptr, nullptr, nullptr});
+  BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, l1);
+  tile_loss_put(l1, px, sloss);
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
   __syncthreads();
   if (px.nl > 0) atomicMax(&bmax[w], px.nl);
   __syncthreads();
+  tile_loss_get(l1, sloss, tile);
   const int smax = max(max(bmax[0], bmax[1]), max(bmax[2], bmax[3]));
   const int last = min(start + smax, end);  // exclusive end of the entries any pixel visited
 
@@ -688,11 +715,11 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
                                                           const float* __restrict__ up_depth,
                                                           const float* __restrict__ up_alpha,
                                                           const float* __restrict__ up_scale,
-                                                          float* __restrict__ g2d) {
+                                                          float* __restrict__ g2d, L1Targets l1) {
   const int tile = xcd_remap(blockIdx.x, T_total);
   if (tile >= T_total) return;
   composite_bwd_tile(jobs, tile_off, R, T_total, rec, items, range, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth,
-                     up_alpha, up_scale, g2d, tile);
+                     up_alpha, up_scale, g2d, l1, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDev* __restrict__ jobs,
@@ -700,7 +727,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDe
     const int32_t* __restrict__ items, const int32_t* __restrict__ range, float bg0, float bg1, float bg2,
     const float* __restrict__ fwd_T, const int32_t* __restrict__ fwd_n, const float* __restrict__ up_rgb,
     const float* __restrict__ up_depth, const float* __restrict__ up_alpha, const float* __restrict__ up_scale,
-    float* __restrict__ g2d, TileQueue* __restrict__ queue, int nstatic) {
+    float* __restrict__ g2d, TileQueue* __restrict__ queue, int nstatic, L1Targets l1) {
   __shared__ int s_tile;
   bool first = true;
   uint32_t dead = 0;
@@ -708,7 +735,7 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDe
     const int tile = claim_tile(queue, T_total, nstatic, first, dead, &s_tile);
     if (tile < 0) break;
     composite_bwd_tile(jobs, tile_off, R, T_total, rec, items, range, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth,
-                       up_alpha, up_scale, g2d, tile);
+                       up_alpha, up_scale, g2d, l1, tile);
   }
   release_queue(queue);
 }
@@ -761,11 +788,14 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wval = wave_value<kPoseRow>(lane);
   const int tx0 = c.x0, ty0 = c.y0;
+  __shared__ float sloss[2][4];
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, l1);
+  tile_loss_put(l1, px, sloss);
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
   __syncthreads();
   if (px.nl > 0) atomicMax(&bmax[w], px.nl);
   __syncthreads();
+  tile_loss_get(l1, sloss, tile);
   const int smax = max(max(bmax[0], bmax[1]), max(bmax[2], bmax[3]));
   const int last = min(start + smax, end);
 
@@ -1067,7 +1097,7 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
                           const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
                           float* tile_part, int pose_only, void* queues, hipStream_t s, const L1Targets* l1) {
   if (T <= 0) return;
-  const L1Targets l1v = l1 ? *l1 : L1Targets{nullptr, nullptr, nullptr, nullptr};
+  const L1Targets l1v = l1 ? *l1 : L1Targets{nullptr, nullptr, nullptr, nullptr, nullptr};
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const float4* aux4 = reinterpret_cast<const float4*>(aux);
   if (pose_only) {
@@ -1085,10 +1115,10 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
     if (g.on)
       hipLaunchKernelGGL(k_composite_bwd_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4,
                          items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d,
-                         reinterpret_cast<TileQueue*>(queues) + 0, g.nstatic);
+                         reinterpret_cast<TileQueue*>(queues) + 0, g.nstatic, l1v);
     else
       hipLaunchKernelGGL(k_composite_bwd, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, items, range,
-                         bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d);
+                         bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d, l1v);
   }
 }
 }  // namespace ls

@@ -80,13 +80,20 @@ constexpr size_t kTileQueueBytes = 2 * 9 * 128;
 // instead of read from a loss kernel's gradient images: on pixels with a
 // target depth, sign(rendered - target) per colour channel and for depth,
 // times the render's 1 / |Omega| (up_scale); 0 elsewhere.  Targets in the
-// batch's image layout, or NULL: each render's own (JobDev.tgt_*).
+// batch's image layout, or NULL: each render's own (JobDev.tgt_*).  With
+// loss_part, each tile also writes {sum over its pixels in Omega of the L1
+// terms (|D - D*| + sum_c |C_c - C*_c|), number of those pixels}.
 struct L1Targets {
   const float* pred_rgb;    // forward colour [3][P]; NULL: off
   const float* pred_depth;  // forward depth [P]
   const float* tgt_rgb;
   const float* tgt_depth;
+  float* loss_part;         // [T][2], or NULL
 };
+
+// Per-render L1 loss from the tile partials: loss[r] = sum / count over the
+// render's tiles in a fixed order (0 when the render has no pixel in Omega).
+void launch_tile_loss_reduce(const JobDev* jobs, int R, const float* loss_part, float* loss, hipStream_t s);
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,

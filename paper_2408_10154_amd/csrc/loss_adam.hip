@@ -163,6 +163,38 @@ __global__ void k_loss_reduce(const int32_t* __restrict__ pblk_off, int R, const
   }
 }
 
+// Per-render L1 loss from the per-tile partials {sum, count} that the
+// compositing backward wrote with L1 targets: one 256-thread block per render,
+// strided per-thread sums, wave sums, then the four waves in order.
+__global__ __launch_bounds__(256) void k_tile_loss_reduce(const JobDev* __restrict__ jobs, int R,
+                                                          const float* __restrict__ part, float* __restrict__ loss) {
+  __shared__ float ws[2][4];
+  const int r = blockIdx.x;
+  if (r >= R) return;
+  const JobDev& J = jobs[r];
+  const int first = J.tile_off, nt = J.TX * J.TY;
+  const float2* p2 = reinterpret_cast<const float2*>(part);
+  float s = 0.f, c = 0.f;
+#pragma unroll 4
+  for (int t = threadIdx.x; t < nt; t += 256) {
+    const float2 v = p2[first + t];
+    s += v.x;
+    c += v.y;
+  }
+  s = wave_sum(s);
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) {
+    ws[0][threadIdx.x >> 6] = s;
+    ws[1][threadIdx.x >> 6] = c;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float ts = (ws[0][0] + ws[0][1]) + (ws[0][2] + ws[0][3]);
+    const float tc = (ws[1][0] + ws[1][1]) + (ws[1][2] + ws[1][3]);
+    loss[r] = tc > 0.f ? ts / tc : 0.f;
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Tracking loss with masks (Eq. 2 and the supplement's tracking-loss
 // details).  The inlier mask needs, per render, the median of the depth
@@ -417,6 +449,10 @@ void launch_loss_track(const JobDev* jobs, const int32_t* pblk_off_d, int R, int
                        g_depth, part, expo, epart);
   hipLaunchKernelGGL(k_loss_reduce, dim3(R), dim3(64), 0, s, pblk_off_d, R, (const float*)part, loss, scale,
                      (const float*)epart, egrad);
+}
+
+void launch_tile_loss_reduce(const JobDev* jobs, int R, const float* loss_part, float* loss, hipStream_t s) {
+  if (R > 0) hipLaunchKernelGGL(k_tile_loss_reduce, dim3(R), dim3(256), 0, s, jobs, R, loss_part, loss);
 }
 
 void launch_adam(const ls_adam_group* g, int ng, float beta1, float beta2, float eps, float bc1, float bc2,

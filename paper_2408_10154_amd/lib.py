@@ -164,6 +164,9 @@ _PROTOS = {
                                   C.POINTER(ls_image_grad), _P, _P, _P]),
     "ls_render_bwd_tiles": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, C.POINTER(ls_image),
                                         C.POINTER(ls_image_grad), C.c_uint32, _P]),
+    "ls_render_bwd_tiles_l1": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P,
+                                           C.POINTER(ls_image), _P, _P, _P, C.c_uint32, _P]),
+    "ls_loss_l1_tiles": (C.c_int32, [_P, C.POINTER(ls_bins), _P, _P]),
     "ls_render_bwd_project": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins), _P, _P, C.c_uint32,
                                           _P]),
     "ls_render_bwd_project_adam": (C.c_int32, [_P, _P, C.POINTER(ls_projected), C.POINTER(ls_bins),
@@ -275,6 +278,15 @@ def ls_render_bwd(h, pose, proj, bins, bg, fwd, up, grads, pose_grad, stream):
 def ls_render_bwd_tiles(h, pose, proj, bins, bg, fwd, up, flags, stream):
     return _call("ls_render_bwd_tiles", h, pose, C.byref(proj), C.byref(bins), bg, C.byref(fwd), C.byref(up), flags,
                  stream)
+
+
+def ls_render_bwd_tiles_l1(h, pose, proj, bins, bg, fwd, tgt_rgb, tgt_depth, inv_count, flags, stream):
+    return _call("ls_render_bwd_tiles_l1", h, pose, C.byref(proj), C.byref(bins), bg, C.byref(fwd), tgt_rgb,
+                 tgt_depth, inv_count, flags, stream)
+
+
+def ls_loss_l1_tiles(h, bins, loss, stream):
+    return _call("ls_loss_l1_tiles", h, C.byref(bins), loss, stream)
 
 
 def ls_render_bwd_project(h, pose, proj, bins, grads, pose_grad, flags, stream):

@@ -201,6 +201,26 @@ class RenderBatch:
         L.ls_render_bwd_tiles(self.h, _ptr(pose), self.proj, self.bins, bgc, self.image, up,
                               L.BWD_POSE_ONLY if pose_only else 0, _stream())
 
+    def render_bwd_tiles_l1(self, tgt_rgb, tgt_depth, inv_count, bg=None, pose=None, pose_only=False):
+        """loss_l1 + render_bwd_tiles fused: the L1 gradient is formed inside
+        the backward from the batch's images and the targets; inv_count is
+        loss_l1's grad_scale for the same targets.  loss_l1_tiles() gives the
+        loss afterwards."""
+        self._check_pose(pose)
+        self._check_dev(tgt_rgb, 3 * self.P, name="tgt_rgb")
+        self._check_dev(tgt_depth, self.P, name="tgt_depth")
+        self._check_dev(inv_count, self.R, name="inv_count")
+        bgc = (C.c_float * 3)(*bg) if bg is not None else None
+        L.ls_render_bwd_tiles_l1(self.h, _ptr(pose), self.proj, self.bins, bgc, self.image, _ptr(tgt_rgb),
+                                 _ptr(tgt_depth), _ptr(inv_count), L.BWD_POSE_ONLY if pose_only else 0, _stream())
+
+    def loss_l1_tiles(self, loss=None):
+        """The L1 loss per render of the last render_bwd_tiles_l1."""
+        loss = torch.zeros(self.R, dtype=torch.float32, device=self.device) if loss is None else loss
+        self._check_dev(loss, self.R, name="loss")
+        L.ls_loss_l1_tiles(self.h, self.bins, _ptr(loss), _stream())
+        return loss
+
     def render_bwd_project(self, grads=None, pose=None, pose_grad=None, pose_only=False):
         self._check_pose(pose)
         self._check_dev(pose_grad, 7 * self.R, name="pose_grad")

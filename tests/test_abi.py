@@ -66,6 +66,8 @@ def test_invalid_arguments_are_rejected_without_a_device():
     assert lib.ls_fill_i32(None, 4, 0, None) == L.LS_ERR_INVALID
     assert lib.ls_render_bwd_project_adam(None, None, None, None, None, None, 1, 0.9, 0.999, 1e-8, None,
                                           None) == L.LS_ERR_INVALID
+    assert lib.ls_render_bwd_tiles_l1(None, None, None, None, None, None, None, None, None, 0, None) == L.LS_ERR_INVALID
+    assert lib.ls_loss_l1_tiles(None, None, None, None) == L.LS_ERR_INVALID
     assert lib.ls_loss_isotropic(None, -1, 1.0, None, None, None, None) == L.LS_ERR_INVALID
     assert lib.ls_loss_isotropic(None, 4, 1.0, None, None, None, None) == L.LS_ERR_INVALID  # NULL arrays
     sub = L.ls_submap_adjust(0, 0, None, None, None, (C.c_float * 12)(2, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 0))

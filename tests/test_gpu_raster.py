@@ -843,3 +843,48 @@ def test_gpu_gradients_match_gpu_finite_differences(gpu):
                 accepted[name] += 1
         print(f"{n} Gaussians: accepted finite-difference samples per group:", accepted)
         assert all(v >= 3 for v in accepted.values()), accepted
+
+
+@pytest.mark.parametrize("pose_only", [False, True])
+def test_fused_l1_backward_matches_loss_then_backward(gpu, pose_only):
+    """ls_render_bwd_tiles_l1 (the Sec. 3.2 L1 gradient formed inside the
+    compositing backward) against ls_loss_l1 + ls_render_bwd_tiles on three
+    ragged renders whose targets lack depth on every seventh pixel (outside
+    Omega): the same per-pixel gradients, so pose-only partials and pose
+    gradients are bit-identical and full-mode Gaussian gradients agree to the
+    float-atomic order; the tile-summed loss equals ls_loss_l1's to FP32
+    rounding."""
+    jobs, poses = _three_scenes()
+    pose = torch.as_tensor(np.stack(poses), device="cuda").contiguous()
+    b = _batch(jobs)
+    b.project(pose)
+    b.bin_sort()
+    b.render_fwd()
+    tgt_rgb = (b.rgb * 0.9 + 0.05).contiguous()
+    tgt_depth = (b.depth * 1.02).contiguous()
+    tgt_depth[::7] = 0.0
+    loss, g_rgb, g_depth, scale = b.loss_l1(tgt_rgb, tgt_depth)
+    out = []
+    for fused in (False, True):
+        grads = None if pose_only else [g.zeros_like() for g in b.gsets]
+        pg = torch.zeros_like(pose)
+        if fused:
+            b.render_bwd_tiles_l1(tgt_rgb, tgt_depth, scale, pose=pose, pose_only=pose_only)
+            lt = b.loss_l1_tiles()
+        else:
+            b.render_bwd_tiles(up_rgb=g_rgb, up_depth=g_depth, scale=scale, pose=pose, pose_only=pose_only)
+            lt = loss
+        b.render_bwd_project(grads=grads, pose=pose, pose_grad=pg, pose_only=pose_only)
+        torch.cuda.synchronize()
+        out.append((grads, pg.cpu().numpy(), lt.cpu().numpy()))
+    (ga, pa, la), (gf, pf, lf) = out
+    np.testing.assert_allclose(lf, la, rtol=2e-6)
+    assert (la > 0).all()
+    if pose_only:
+        np.testing.assert_array_equal(pf, pa)
+        return
+    np.testing.assert_allclose(pf, pa, rtol=1e-4, atol=1e-5 * np.abs(pa).max())
+    for x, y in zip(ga, gf):
+        for n, ta, tf in zip(("mean", "log_scale", "quat", "opacity_logit", "rgb"), x.tensors(), y.tensors()):
+            a_, f_ = ta.cpu().numpy(), tf.cpu().numpy()
+            np.testing.assert_allclose(f_, a_, rtol=1e-4, atol=1e-5 * max(np.abs(a_).max(), 1e-30), err_msg=n)
