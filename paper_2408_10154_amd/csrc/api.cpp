@@ -283,7 +283,7 @@ static ls_status batch_host(const ls_render_job* jobs, int32_t R, ls_batch** out
   b->nblk_ssim = b->sblk_off[R];
   int bits = 0;
   while (bits < 32 && ((int64_t)1 << bits) < (int64_t)b->T) ++bits;
-  b->tile_passes = (bits + kTileDigitBits - 1) / kTileDigitBits;
+  b->tile_bits = bits;
   *out = b;
   return LS_OK;
 }
@@ -476,7 +476,7 @@ ls_status ls_bin_sort(const ls_batch* b, const ls_projected* p, const ls_bins* b
     launch_fill_i32(bins->range, 2 * (int64_t)b->T, 0, s);
     return hip_check("ls_bin_sort");
   }
-  launch_bin_sort(b->jobs_d, b->item_off_d, b->R, b->M, b->T, b->tile_passes, p->rec, p->radius, p->tiles,
+  launch_bin_sort(b->jobs_d, b->item_off_d, b->R, b->M, b->T, b->tile_bits, p->rec, p->radius, p->tiles,
                   bins->capacity, bins->tile_of, bins->item, bins->range, bins->count, at<uint32_t>(w, L.dk0),
                   at<uint32_t>(w, L.dv0), at<uint32_t>(w, L.dk1), at<uint32_t>(w, L.dv1), at<uint32_t>(w, L.hist),
                   at<uint32_t>(w, L.bsum), at<uint32_t>(w, L.tk), at<uint32_t>(w, L.tv), s);

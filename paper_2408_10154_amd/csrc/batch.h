@@ -16,7 +16,7 @@ struct ls_batch {
   int nblk_items = 0;
   int nblk_pix = 0;
   int nblk_ssim = 0;  // mapping-loss SSIM blocks (3 channels x 32x32 tiles per render)
-  int tile_passes = 0;
+  int tile_bits = 0;  // bits of the largest tile key
   int device = 0;
   std::vector<JobDev> jobs_h;
   std::vector<int64_t> item_off, pix_off;

@@ -177,8 +177,8 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
                                                                int shift, const uint32_t* __restrict__ hist, int nblocks,
                                                                const uint32_t* __restrict__ digit_total, int rounds) {
   constexpr int kBins = 1 << kBits;
-  constexpr int kPer = kBins / kSortThreads;  // digits per thread in the set-up
-  static_assert(kBins % kSortThreads == 0, "digit count must be a multiple of the block size");
+  constexpr int kPer = kBins >= kSortThreads ? kBins / kSortThreads : 1;  // digits per thread in the set-up
+  static_assert(kBins % kSortThreads == 0 || kSortThreads % kBins == 0, "digits and threads must divide");
   __shared__ uint32_t base[kBins];   // running local position of each digit
   __shared__ uint32_t delta[kBins];  // global minus local start of each digit's run (mod 2^32)
   __shared__ uint32_t wcnt[4][kBins];
@@ -199,30 +199,37 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
     val[r] = ok ? vin[bbase + i] : 0u;
   }
   {
-    uint32_t tot[kPer], cnt[kPer];
+    // threads 0 .. kBins / kPer - 1 hold kPer digits each (fewer digits than
+    // threads: the other threads add zeros to the scans)
+    const bool has = tid * kPer < kBins;
+    uint32_t tot[kPer], cnt[kPer], here[kPer];
     uint32_t gsum = 0, lsum = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int d = tid * kPer + k;
-      const uint32_t here = hist[(int64_t)d * nblocks + blockIdx.x];
-      tot[k] = digit_total[d];
-      const uint32_t next = (int)blockIdx.x + 1 < nact ? hist[(int64_t)d * nblocks + blockIdx.x + 1] : tot[k];
-      cnt[k] = next - here;
+      tot[k] = cnt[k] = here[k] = 0u;
+      if (has) {
+        here[k] = hist[(int64_t)d * nblocks + blockIdx.x];
+        tot[k] = digit_total[d];
+        const uint32_t next = (int)blockIdx.x + 1 < nact ? hist[(int64_t)d * nblocks + blockIdx.x + 1] : tot[k];
+        cnt[k] = next - here[k];
+      }
       gsum += tot[k];
       lsum += cnt[k];
-      delta[d] = here;
     }
     uint32_t all;
     uint32_t grun = block_excl_scan(gsum, wsum, &all);
     uint32_t lrun = block_excl_scan(lsum, wsum, &all);
+    if (has) {
 #pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const int d = tid * kPer + k;
-      base[d] = lrun;
-      delta[d] = grun + delta[d] - lrun;
-      grun += tot[k];
-      lrun += cnt[k];
-      wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0u;
+      for (int k = 0; k < kPer; ++k) {
+        const int d = tid * kPer + k;
+        base[d] = lrun;
+        delta[d] = grun + here[k] - lrun;
+        grun += tot[k];
+        lrun += cnt[k];
+        wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0u;
+      }
     }
   }
   __syncthreads();
@@ -492,8 +499,9 @@ __device__ __forceinline__ int wave_incl_max(int v) {
 // rectangle, instance q lies in row q / width (row by row, as the tiles are
 // counted).  Instances at or beyond the capacity are not written.  The
 // kEmitWaves spans of a block are the positions of one block of the first
-// tile radix pass, whose digit histogram the block counts as it writes (LDS) and stores
-// digit-major in hist[d * gridDim.x + block], as the histogram kernel would.
+// tile radix pass, whose histogram of the keys' low `dbits` bits the block
+// counts as it writes (LDS) and stores digit-major in
+// hist[d * gridDim.x + block], as the histogram kernel would.
 __global__ __launch_bounds__(64 * kEmitWaves) void k_emit(const JobDev* __restrict__ jobs, const int64_t* __restrict__ item_off,
                                               int R, const uint32_t* __restrict__ order,
                                               const float4* __restrict__ rec, const int32_t* __restrict__ radius,
@@ -501,8 +509,9 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit(const JobDev* __restri
                                               const uint32_t* __restrict__ offs, const int32_t* __restrict__ count,
                                               const uint32_t* __restrict__ first, int64_t span_len, int64_t nspan,
                                               uint32_t* __restrict__ kout, int32_t* __restrict__ vout,
-                                              uint32_t* __restrict__ hist) {
-  static_assert(kTileDigitBits == 8 && 64 * kEmitWaves >= 256, "a histogram bin per thread of the first 256");
+                                              uint32_t* __restrict__ hist, int dbits) {
+  static_assert(kTileDigitBits <= 8 && 64 * kEmitWaves >= 256, "a histogram bin per thread of the first 256");
+  const uint32_t dmask = (1u << dbits) - 1u;
   __shared__ int marks[kEmitWaves][64];
   __shared__ uint32_t h[256];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -558,7 +567,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit(const JobDev* __restri
         const uint32_t key = (uint32_t)(o_key + dy * o_stride + q);
         kout[i] = key;
         vout[i] = (int32_t)o_it;
-        atomicAdd(&h[key & 255u], 1u);
+        atomicAdd(&h[key & dmask], 1u);
       }
       __builtin_amdgcn_wave_barrier();
       W0 = min(W0 + 64, cend);
@@ -566,7 +575,7 @@ __global__ __launch_bounds__(64 * kEmitWaves) void k_emit(const JobDev* __restri
     kb += 64;
   }
   __syncthreads();
-  if (threadIdx.x < 256) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
+  if (threadIdx.x <= dmask) hist[(int64_t)threadIdx.x * gridDim.x + blockIdx.x] = h[threadIdx.x];
 }
 
 // [start, end) of each tile's run in the sorted instance keys, for every one
@@ -672,12 +681,13 @@ static bool compact_items(int64_t M) {
   return M >= (int64_t)1 << 20;
 }
 
-void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_passes,
+void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64_t M, int T, int tile_bits,
                      const float* rec, const int32_t* radius, const int32_t* tiles, int64_t cap, uint32_t* tile_of,
                      int32_t* item, int32_t* range, int32_t* count, uint32_t* dk0, uint32_t* dv0, uint32_t* dk1,
                      uint32_t* dv1, uint32_t* hist, uint32_t* bsum, uint32_t* tk, uint32_t* tv, hipStream_t s) {
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
   const int rd = sort_rounds(M), nbd = (int)sort_blocks(M);
+  const int npass = tile_passes(tile_bits), tbits = tile_digit_bits(tile_bits);
   uint32_t* digit_base = bsum + nbd + 8;  // digit totals (up to kMaxSortBins) after the block sums
   // large batches sort only the items with tiles; the kept count sits in a
   // spare word after the block sums
@@ -710,19 +720,24 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
   hipLaunchKernelGGL(k_offsets, dim3(nbd), dim3(kSortThreads), 0, s, order, tiles, M, (const int32_t*)nkeep,
                      (const uint32_t*)bsum, nbd,
                      offs, count, cap, rd, first, span, nspan);
-  // emission lands in the buffer that, after tile_passes ping-pongs, is the output
-  uint32_t* ek = (tile_passes & 1) ? tk : tile_of;
-  uint32_t* ev = (tile_passes & 1) ? tv : reinterpret_cast<uint32_t*>(item);
-  uint32_t* ok = (tile_passes & 1) ? tile_of : tk;
-  uint32_t* ov = (tile_passes & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
+  // emission lands in the buffer that, after npass ping-pongs, is the output
+  uint32_t* ek = (npass & 1) ? tk : tile_of;
+  uint32_t* ev = (npass & 1) ? tv : reinterpret_cast<uint32_t*>(item);
+  uint32_t* ok = (npass & 1) ? tile_of : tk;
+  uint32_t* ov = (npass & 1) ? reinterpret_cast<uint32_t*>(item) : tv;
   const bool emitted = nbt > 0 && M > 0;
   if (emitted)
     hipLaunchKernelGGL(k_emit, dim3((unsigned)nbt), dim3(64 * kEmitWaves), 0, s, jobs, item_off_d, R, order, rec4, radius, tiles,
                        M, (const int32_t*)nkeep, (const uint32_t*)offs, (const int32_t*)count,
-                       (const uint32_t*)first, span, nspan, ek, reinterpret_cast<int32_t*>(ev), hist);
-  for (int p = 0; p < tile_passes && nbt > 0; ++p) {
-    radix_pass<kTileDigitBits>(ek, ev, ok, ov, count, 0, cap, kTileDigitBits * p, hist, digit_base, nbt, rt, s,
-                               p == 0 && emitted);
+                       (const uint32_t*)first, span, nspan, ek, reinterpret_cast<int32_t*>(ev), hist, tbits);
+  for (int p = 0; p < npass && nbt > 0; ++p) {
+    const bool hd = p == 0 && emitted;
+    if (tbits == 6)
+      radix_pass<6>(ek, ev, ok, ov, count, 0, cap, 6 * p, hist, digit_base, nbt, rt, s, hd);
+    else if (tbits == 7)
+      radix_pass<7>(ek, ev, ok, ov, count, 0, cap, 7 * p, hist, digit_base, nbt, rt, s, hd);
+    else
+      radix_pass<8>(ek, ev, ok, ov, count, 0, cap, 8 * p, hist, digit_base, nbt, rt, s, hd);
     std::swap(ek, ok);
     std::swap(ev, ov);
   }

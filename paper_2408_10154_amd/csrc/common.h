@@ -16,7 +16,7 @@ constexpr int kSortThreads = 256;   // radix sort block
 // measured 3 % slower on the render loop: the 2048-bin histograms, row scans
 // and scatter set-up cost more than the pass they save.
 constexpr int kDepthDigitBits = 8;  // depth keys: 4 passes over 32 bits
-constexpr int kTileDigitBits = 8;   // tile keys: ceil(bits / 8) passes
+constexpr int kTileDigitBits = 8;   // tile keys: ceil(bits / 8) passes of at most 8 bits
 constexpr int kMaxSortBins = 1 << (kDepthDigitBits > kTileDigitBits ? kDepthDigitBits : kTileDigitBits);
 constexpr int kSortItems = 16;      // most items per thread per sort block
 constexpr int kSortTile = kSortThreads * kSortItems;
@@ -34,6 +34,19 @@ __host__ __device__ inline int64_t sort_blocks(int64_t n) {
   const int64_t per = (int64_t)sort_rounds(n) * kSortThreads;
   return (n + per - 1) / per;
 }
+// Digit width of the tile-key passes for keys of `bits` bits: as many passes
+// as 8-bit digits need, the bits split evenly between them, rounded up to 6,
+// 7 or 8 (12-bit keys: two 6-bit passes).  Fewer bins per pass give each sort
+// block longer runs of equal digits to count and to write.
+__host__ __device__ inline int tile_digit_bits(int bits) {
+  const int passes = bits <= 0 ? 1 : (bits + kTileDigitBits - 1) / kTileDigitBits;
+  const int w = (bits + passes - 1) / passes;
+  return w < 6 ? 6 : (w > kTileDigitBits ? kTileDigitBits : w);
+}
+__host__ __device__ inline int tile_passes(int bits) {
+  return bits <= 0 ? 0 : (bits + tile_digit_bits(bits) - 1) / tile_digit_bits(bits);
+}
+
 // Tile instances emitted per wave: an eighth of a tile-sort block, so the
 // kEmitWaves waves of an emission block fill exactly the positions of one
 // block of the first tile pass and can count its digits.  The first item of
