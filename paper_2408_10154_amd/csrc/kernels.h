@@ -216,6 +216,32 @@ __device__ inline void or_flag(const int32_t* count, int32_t* sticky) {
   }
 }
 
+// Joint registration on the device (one T = T_{P->Q} per pair shared by its
+// views, optimised by Adam in double precision).  Per view: its keyframe's
+// rotation, translation and unit quaternion, the pair and whether it is a
+// keyframe of Q; per pair: T (unnormalised quaternion, translation), its
+// moments and its views [first, first + count).
+struct JointView {
+  double Rc[9], tc[3], qc[4];
+  int32_t pair, reverse;
+};
+struct JointPair {
+  double T[7], m[7], v[7];
+  int32_t first, count;
+};
+struct JointAdam {
+  double lr_rot, lr_trans, beta1, beta2, eps, bc1, bc2;  // bc = 1 / (1 - beta^step)
+};
+// pose[r] = the camera-frame correction Delta of view r under its pair's T:
+// C^-1 T^-1 C for a keyframe of P, C^-1 T C for one of Q.
+void launch_joint_poses(const JointView* views, int R, const JointPair* pairs, float* pose, hipStream_t s);
+// One Adam step of every pair's T from its views' pose gradients (chained
+// through the Jacobian of T -> Delta by central differences of that smooth
+// map in double precision), then the views' new corrections; the pose
+// gradients are cleared.
+void launch_joint_step(const JointView* views, JointPair* pairs, int npairs, float* pose_grad, float* pose,
+                       const JointAdam& a, hipStream_t s);
+
 // One iteration's end in pose-only registration: per render, the tile
 // partials reduced to its pose gradient (as launch_pose_reduce_tiles) and
 // its Adam step (pose_adam_view) in one launch; render 0 also updates the

@@ -29,6 +29,115 @@ __global__ void k_or_flag(const int32_t* __restrict__ count, int32_t* __restrict
   if (threadIdx.x == 0) or_flag(count, sticky);
 }
 
+// ---------------------------------------------------------------- joint mode
+
+__device__ __forceinline__ void quat_mul_d(const double* a, const double* b, double* o) {
+  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
+  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
+  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
+  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
+}
+
+// Delta (7 values: unit quaternion, translation) of one view under T.
+__device__ void joint_delta_d(const double* T7, const JointView& jv, double* d7) {
+  const double n = sqrt(T7[0] * T7[0] + T7[1] * T7[1] + T7[2] * T7[2] + T7[3] * T7[3]);
+  const double w = T7[0] / n, x = T7[1] / n, y = T7[2] / n, z = T7[3] / n;
+  const double q[4] = {w, x, y, z}, qi[4] = {w, -x, -y, -z};
+  const double Rt[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z),     2 * (x * z + w * y),
+                        2 * (x * y + w * z),     1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                        2 * (x * z - w * y),     2 * (y * z + w * x),     1 - 2 * (x * x + y * y)};
+  const double qci[4] = {jv.qc[0], -jv.qc[1], -jv.qc[2], -jv.qc[3]};
+  double tmp[4];
+  quat_mul_d(qci, jv.reverse ? q : qi, tmp);
+  quat_mul_d(tmp, jv.qc, d7);
+  double v[3];
+  for (int i = 0; i < 3; ++i) {
+    if (jv.reverse)  // Rt tc + t - tc
+      v[i] = Rt[i * 3 + 0] * jv.tc[0] + Rt[i * 3 + 1] * jv.tc[1] + Rt[i * 3 + 2] * jv.tc[2] + T7[4 + i] - jv.tc[i];
+    else  // Rt^T (tc - t) - tc
+      v[i] = Rt[0 * 3 + i] * (jv.tc[0] - T7[4]) + Rt[1 * 3 + i] * (jv.tc[1] - T7[5]) +
+             Rt[2 * 3 + i] * (jv.tc[2] - T7[6]) - jv.tc[i];
+  }
+  for (int i = 0; i < 3; ++i) d7[4 + i] = jv.Rc[0 * 3 + i] * v[0] + jv.Rc[1 * 3 + i] * v[1] + jv.Rc[2 * 3 + i] * v[2];
+}
+
+__global__ void k_joint_poses(const JointView* __restrict__ views, int R, const JointPair* __restrict__ pairs,
+                              float* __restrict__ pose) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= R) return;
+  double d[7];
+  joint_delta_d(pairs[views[r].pair].T, views[r], d);
+  for (int k = 0; k < 7; ++k) pose[7 * r + k] = (float)d[k];
+}
+
+constexpr int kJointChunk = 32;  // views per round of the gradient (kJointChunk x 7 tasks <= block)
+
+// One block per pair.  Rounds of up to kJointChunk views: task (view, k)
+// forms sum_i dDelta_i/dT_k g_i by central differences (h = 1e-7); threads
+// 0..6 add the round's tasks of their k in view order.  Thread k then takes
+// the Adam step of T_k; the pose gradients are cleared and each view gets its
+// correction under the new T.
+__global__ __launch_bounds__(256) void k_joint_step(const JointView* __restrict__ views, JointPair* __restrict__ pairs,
+                                                    float* __restrict__ pose_grad, float* __restrict__ pose,
+                                                    JointAdam a) {
+  __shared__ double part[kJointChunk][7];
+  __shared__ double Tn[7];
+  JointPair& P = pairs[blockIdx.x];
+  const int first = P.first, count = P.count;
+  double T[7];
+  for (int k = 0; k < 7; ++k) T[k] = P.T[k];
+  double g = 0.0;  // thread k < 7: dL/dT_k
+  for (int v0 = 0; v0 < count; v0 += kJointChunk) {
+    const int nv = min(kJointChunk, count - v0);
+    for (int t = threadIdx.x; t < 7 * nv; t += blockDim.x) {
+      const int v = t / 7, k = t - 7 * v, r = first + v0 + v;
+      constexpr double h = 1e-7;
+      double Tp[7], Tm[7], dp[7], dm[7];
+      for (int i = 0; i < 7; ++i) Tp[i] = Tm[i] = T[i];
+      Tp[k] += h;
+      Tm[k] -= h;
+      joint_delta_d(Tp, views[r], dp);
+      joint_delta_d(Tm, views[r], dm);
+      double c = 0.0;
+      for (int i = 0; i < 7; ++i) c += (dp[i] - dm[i]) / (2 * h) * (double)pose_grad[7 * r + i];
+      part[v][k] = c;
+    }
+    __syncthreads();
+    if (threadIdx.x < 7)
+      for (int v = 0; v < nv; ++v) g += part[v][threadIdx.x];
+    __syncthreads();
+  }
+  if (threadIdx.x < 7) {
+    const int k = threadIdx.x;
+    double m = P.m[k], v = P.v[k];
+    m = a.beta1 * m + (1.0 - a.beta1) * g;
+    v = a.beta2 * v + (1.0 - a.beta2) * g * g;
+    const double lr = k < 4 ? a.lr_rot : a.lr_trans;
+    const double t = T[k] - lr * (m * a.bc1) / (sqrt(v * a.bc2) + a.eps);
+    P.m[k] = m;
+    P.v[k] = v;
+    P.T[k] = t;
+    Tn[k] = t;
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < 7 * count; i += blockDim.x) pose_grad[7 * first + i] = 0.f;
+  for (int v = threadIdx.x; v < count; v += blockDim.x) {
+    const int r = first + v;
+    double d[7];
+    joint_delta_d(Tn, views[r], d);
+    for (int k = 0; k < 7; ++k) pose[7 * r + k] = (float)d[k];
+  }
+}
+
+void launch_joint_poses(const JointView* views, int R, const JointPair* pairs, float* pose, hipStream_t s) {
+  if (R > 0) hipLaunchKernelGGL(k_joint_poses, dim3((R + 63) / 64), dim3(64), 0, s, views, R, pairs, pose);
+}
+
+void launch_joint_step(const JointView* views, JointPair* pairs, int npairs, float* pose_grad, float* pose,
+                       const JointAdam& a, hipStream_t s) {
+  if (npairs > 0) hipLaunchKernelGGL(k_joint_step, dim3(npairs), dim3(256), 0, s, views, pairs, pose_grad, pose, a);
+}
+
 void launch_pose_init(float* pose, float* m, float* v, ViewOpt* opt, int R, hipStream_t s) {
   const int n = 7 * R;
   hipLaunchKernelGGL(k_pose_init, dim3((n + 255) / 256), dim3(256), 0, s, pose, m, v, opt, R);

@@ -46,13 +46,6 @@ void rigid_mul(const double* A, const double* B, double* out) {
   std::memcpy(out, o, sizeof(o));
 }
 
-static void quat_mul(const double* a, const double* b, double* o) {
-  o[0] = a[0] * b[0] - a[1] * b[1] - a[2] * b[2] - a[3] * b[3];
-  o[1] = a[0] * b[1] + a[1] * b[0] + a[2] * b[3] - a[3] * b[2];
-  o[2] = a[0] * b[2] - a[1] * b[3] + a[2] * b[0] + a[3] * b[1];
-  o[3] = a[0] * b[3] + a[1] * b[2] - a[2] * b[1] + a[3] * b[0];
-}
-
 // Unit quaternion of a rotation (row-major), largest-diagonal branch.
 static void quat_of_rot(const double* R, double* q) {
   const double tr = R[0] + R[4] + R[8];
@@ -71,33 +64,6 @@ static void quat_of_rot(const double* R, double* q) {
   }
   const double n = std::sqrt(q[0] * q[0] + q[1] * q[1] + q[2] * q[2] + q[3] * q[3]);
   for (int k = 0; k < 4; ++k) q[k] /= n;
-}
-
-// Joint registration: the camera-frame correction of a view implied by one
-// shared T = T_{P->Q} (7 values, unnormalised quaternion and translation):
-// Delta = C^-1 T^-1 C for a keyframe of P, C^-1 T C for one of Q.
-void joint_delta(const double* T7, const double* c2w, bool reverse, double* d7) {
-  const double n = std::sqrt(T7[0] * T7[0] + T7[1] * T7[1] + T7[2] * T7[2] + T7[3] * T7[3]);
-  const double q[4] = {T7[0] / n, T7[1] / n, T7[2] / n, T7[3] / n};
-  const double qi[4] = {q[0], -q[1], -q[2], -q[3]};
-  double Rc[9], qc[4], Rt[9];
-  for (int i = 0; i < 3; ++i)
-    for (int j = 0; j < 3; ++j) Rc[i * 3 + j] = c2w[i * 4 + j];
-  quat_of_rot(Rc, qc);
-  const double qci[4] = {qc[0], -qc[1], -qc[2], -qc[3]};
-  rot_of_quat(q, Rt);
-  const double tc[3] = {c2w[3], c2w[7], c2w[11]};
-  double tmp[4], v[3];
-  quat_mul(qci, reverse ? q : qi, tmp);
-  quat_mul(tmp, qc, d7);
-  for (int i = 0; i < 3; ++i) {
-    if (reverse)  // Rt tc + t - tc
-      v[i] = Rt[i * 3 + 0] * tc[0] + Rt[i * 3 + 1] * tc[1] + Rt[i * 3 + 2] * tc[2] + T7[4 + i] - tc[i];
-    else  // Rt^T (tc - t) - tc
-      v[i] = Rt[0 * 3 + i] * (tc[0] - T7[4]) + Rt[1 * 3 + i] * (tc[1] - T7[5]) + Rt[2 * 3 + i] * (tc[2] - T7[6]) -
-             tc[i];
-  }
-  for (int i = 0; i < 3; ++i) d7[4 + i] = Rc[0 * 3 + i] * v[0] + Rc[1 * 3 + i] * v[1] + Rc[2 * 3 + i] * v[2];
 }
 
 // E = C Delta^-1 C^-1 for a keyframe c2w C and its optimised correction Delta.
@@ -275,6 +241,7 @@ RegEngine::Layout RegEngine::layout(int64_t cap) const {
   L.count = take(16);
   L.sticky = take(8);
   L.expo = pairs[0].prm.exposure ? take(4 * (8 * (size_t)R + 2 * (size_t)batch->nblk_pix)) : 0;
+  L.joint = pairs[0].prm.joint ? take(sizeof(JointView) * (size_t)R + sizeof(JointPair) * pairs.size()) : 0;
   L.zero_end = off;  // everything above starts at zero
   L.tile_of = take(4 * (size_t)cap);
   L.item = take(4 * (size_t)cap);
@@ -358,11 +325,34 @@ ls_status RegEngine::bind(void* work, size_t work_bytes, int64_t cap, hipStream_
   launch_pose_init(pose, adam_m, adam_v, opt, R, s);
   fused_l1 = fused_l1_allowed(pairs[0].prm);
   if (fused_l1 && (st = batch_valid_inv(batch, tgt_depth, scale, s))) return st;  // constant over the iterations
-  joint_T.assign(7 * pairs.size(), 0.0);
-  for (size_t p = 0; p < pairs.size(); ++p) joint_T[7 * p] = 1.0;
-  joint_m.assign(7 * pairs.size(), 0.0);
-  joint_v.assign(7 * pairs.size(), 0.0);
   joint_step = 0;
+  joint_T.assign(7 * pairs.size(), 0.0);
+  if (pairs[0].prm.joint) {  // T = identity, zero moments; each view's rotation as a unit quaternion
+    jviews = reinterpret_cast<JointView*>(a + L.joint);
+    jpairs = reinterpret_cast<JointPair*>(a + L.joint + sizeof(JointView) * (size_t)R);
+    jviews_h.assign(R, JointView{});
+    jpairs_h.assign(pairs.size(), JointPair{});
+    for (int r = 0; r < R; ++r) {
+      JointView& jv = jviews_h[r];
+      for (int i = 0; i < 3; ++i) {
+        for (int j = 0; j < 3; ++j) jv.Rc[i * 3 + j] = views[r].c2w[i * 4 + j];
+        jv.tc[i] = views[r].c2w[i * 4 + 3];
+      }
+      quat_of_rot(jv.Rc, jv.qc);
+      jv.pair = views[r].pair;
+      jv.reverse = views[r].reverse ? 1 : 0;
+    }
+    for (size_t p = 0; p < pairs.size(); ++p) {
+      jpairs_h[p].T[0] = 1.0;
+      jpairs_h[p].first = first_view[p];
+      jpairs_h[p].count = first_view[p + 1] - first_view[p];
+    }
+    if (hipMemcpyAsync(jviews, jviews_h.data(), sizeof(JointView) * R, hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(jpairs, jpairs_h.data(), sizeof(JointPair) * pairs.size(), hipMemcpyHostToDevice, s) !=
+            hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+      return LS_ERR_HIP;
+    launch_joint_poses(jviews, R, jpairs, pose, s);
+  }
   return hip_ok();
 }
 
@@ -409,25 +399,12 @@ ls_status RegEngine::step(hipStream_t s) {
 
 // Joint registration: uploads every view's correction implied by its pair's
 // shared T.
-ls_status RegEngine::upload_joint_poses(hipStream_t s) {
-  joint_pose_h.assign(7 * (size_t)R, 0.f);
-  for (int r = 0; r < R; ++r) {
-    double d[7];
-    joint_delta(&joint_T[7 * (size_t)views[r].pair], views[r].c2w, views[r].reverse, d);
-    for (int k = 0; k < 7; ++k) joint_pose_h[7 * (size_t)r + k] = (float)d[k];
-  }
-  return hipMemcpyAsync(pose, joint_pose_h.data(), 28 * (size_t)R, hipMemcpyHostToDevice, s) == hipSuccess
-             ? LS_OK
-             : LS_ERR_HIP;
-}
-
 // One joint iteration: the views' pose gradients from the pose-only
-// backward, chained to each pair's T through the Jacobian of the map
-// T -> Delta (central differences of that smooth map in double precision),
-// summed over the pair's views, then an Adam step on T on the host.
+// backward, then on the device every pair's Adam step of T (chained through
+// the Jacobian of T -> Delta) and the views' new corrections.  No host
+// synchronisation.
 ls_status RegEngine::step_joint(hipStream_t s) {
   ls_status st;
-  if ((st = upload_joint_poses(s))) return st;
   const ls_image_grad up{g_rgb, g_depth, nullptr, scale};
   if ((st = ls_project(batch, pose, &proj, s)) || (st = ls_bin_sort(batch, &proj, &bins, s))) return st;
   launch_or_flag(count, sticky, s);
@@ -435,40 +412,23 @@ ls_status RegEngine::step_joint(hipStream_t s) {
       (st = ls_render_bwd_tiles(batch, pose, &proj, &bins, nullptr, &img, &up, LS_BWD_POSE_ONLY, s)) ||
       (st = ls_render_bwd_project(batch, pose, &proj, &bins, nullptr, pose_grad, LS_BWD_POSE_ONLY, s)))
     return st;
-  std::vector<float> gh(7 * (size_t)R);
-  if (hipMemcpyAsync(gh.data(), pose_grad, 28 * (size_t)R, hipMemcpyDeviceToHost, s) != hipSuccess ||
-      hipMemsetAsync(pose_grad, 0, 28 * (size_t)R, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-    return LS_ERR_HIP;
   ++joint_step;
   const ls_reg_params& pm = pairs[0].prm;
-  const double bc1 = 1.0 / (1.0 - std::pow((double)pm.beta1, joint_step));
-  const double bc2 = 1.0 / (1.0 - std::pow((double)pm.beta2, joint_step));
-  for (size_t p = 0; p < pairs.size(); ++p) {
-    double* T = &joint_T[7 * p];
-    double g[7] = {0, 0, 0, 0, 0, 0, 0};
-    for (int r = first_view[p]; r < first_view[p + 1]; ++r) {
-      for (int k = 0; k < 7; ++k) {
-        constexpr double h = 1e-7;
-        double Tp[7], Tm[7], dp[7], dm[7];
-        std::memcpy(Tp, T, sizeof(Tp));
-        std::memcpy(Tm, T, sizeof(Tm));
-        Tp[k] += h;
-        Tm[k] -= h;
-        joint_delta(Tp, views[r].c2w, views[r].reverse, dp);
-        joint_delta(Tm, views[r].c2w, views[r].reverse, dm);
-        for (int i = 0; i < 7; ++i) g[k] += (dp[i] - dm[i]) / (2 * h) * gh[7 * (size_t)r + i];
-      }
-    }
-    for (int k = 0; k < 7; ++k) {
-      double& m = joint_m[7 * p + k];
-      double& v = joint_v[7 * p + k];
-      m = pm.beta1 * m + (1.0 - pm.beta1) * g[k];
-      v = pm.beta2 * v + (1.0 - pm.beta2) * g[k] * g[k];
-      const double lr = k < 4 ? pm.lr_rot : pm.lr_trans;
-      T[k] -= lr * (m * bc1) / (std::sqrt(v * bc2) + pm.adam_eps);
-    }
-  }
+  const JointAdam ja{pm.lr_rot, pm.lr_trans, pm.beta1, pm.beta2, pm.adam_eps,
+                     1.0 / (1.0 - std::pow((double)pm.beta1, joint_step)),
+                     1.0 / (1.0 - std::pow((double)pm.beta2, joint_step))};
+  launch_joint_step(jviews, jpairs, (int)pairs.size(), pose_grad, pose, ja, s);
   return hip_ok();
+}
+
+ls_status RegEngine::read_joint_T(hipStream_t s) {
+  std::vector<JointPair> h(pairs.size());
+  if (hipMemcpyAsync(h.data(), jpairs, sizeof(JointPair) * pairs.size(), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return LS_ERR_HIP;
+  for (size_t p = 0; p < pairs.size(); ++p)
+    for (int k = 0; k < 7; ++k) joint_T[7 * p + k] = h[p].T[k];
+  return LS_OK;
 }
 
 // Residual of each view at its final pose: the unmasked colour + depth L1,
@@ -685,7 +645,7 @@ ls_status ls_register_pair(const ls_pair* pair, const ls_reg_params* prm, void* 
   if (prm->joint) {
     for (; done < prm->iters; ++done)
       if ((st = e.step_joint(s))) return finish(st);
-    if ((st = e.upload_joint_poses(s))) return finish(st);  // the final forward sees the final T
+    if ((st = e.read_joint_T(s))) return finish(st);  // the last step left the final T's corrections in pose
   }
   while (done < prm->iters) {
     const int k = prm->exit_patience > 0 ? std::min(kCheckEvery, prm->iters - done) : prm->iters - done;

@@ -42,11 +42,14 @@ class RegEngine {
   ls_status readback(std::vector<float>& pose_h, std::vector<float>& loss_h, int32_t* overflow, hipStream_t s);
   ls_status fuse_pair(int p, const std::vector<float>& pose_h, const std::vector<float>& loss_h, ls_reg_result* out);
   ls_status read_exposure(int p, ls_reg_result* out, hipStream_t s);
-  // joint registration (one T per pair, optimised on the host)
+  // joint registration (one T per pair, optimised on the device)
   ls_status step_joint(hipStream_t s);
-  ls_status upload_joint_poses(hipStream_t s);
-  std::vector<double> joint_T, joint_m, joint_v;  // [pairs][7]
-  std::vector<float> joint_pose_h;               // staging of the uploaded corrections
+  ls_status read_joint_T(hipStream_t s);  // device T of every pair -> joint_T
+  std::vector<double> joint_T;            // [pairs][7], after read_joint_T
+  JointView* jviews = nullptr;            // device, [R]
+  JointPair* jpairs = nullptr;            // device, [pairs]
+  std::vector<JointView> jviews_h;        // staging of the uploads
+  std::vector<JointPair> jpairs_h;
   int joint_step = 0;
   void release();
 
@@ -77,7 +80,7 @@ class RegEngine {
  private:
   struct Layout {
     size_t tables, rec, rad, til, aux, rgb, dep, alp, Tf, nl, trgb, tdep, grgb, gdep, scale, loss, pose, pg, m, v,
-        opt, range, count, sticky, expo, zero_end, tile_of, item, work, total;
+        opt, range, count, sticky, expo, joint, zero_end, tile_of, item, work, total;
   };
   Layout layout(int64_t capacity) const;
   static ls_status hip_ok();
@@ -87,7 +90,6 @@ void rot_of_quat(const double* q, double* R);
 void rigid_inv(const double* A, double* out);
 void rigid_mul(const double* A, const double* B, double* out);
 void view_estimate(const double* c2w, const float* pose7, double* E);
-void joint_delta(const double* T7, const double* c2w, bool reverse, double* d7);
 int fuse_estimates(const double* est, const double* resid, const int32_t* rev, int n, double* out);
 ls_status validate_pair(const ls_pair* p, const ls_reg_params* prm);
 // Whether the iterations may take the fused L1 backward (LS_FUSED_L1=0 in the

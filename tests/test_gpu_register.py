@@ -341,9 +341,9 @@ def test_server_with_exposure_matches_the_plain_path_bitwise(gpu):
 
 def test_joint_registration_tiny_pair_matches_oracle(gpu):
     """One transform shared by both views (plain L1), 100 Adam steps: the GPU
-    (rendering and backward on the device, the 7-parameter chain and Adam on
-    the host) agrees with the oracle's joint registration and recovers the
-    known transform."""
+    (rendering, backward, the 7-parameter chain and the Adam step of T all on
+    the device, in double for the chain and the step) agrees with the oracle's
+    joint registration and recovers the known transform."""
     from paper_2408_10154_amd import register as REG
 
     d = synth.registration_pair(4, 1500, 1500, shared_frac=1.0, views_p=1, views_q=1, width=64, height=48, f=45,
