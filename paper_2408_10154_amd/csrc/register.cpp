@@ -397,8 +397,6 @@ ls_status RegEngine::step(hipStream_t s) {
   return hip_ok();
 }
 
-// Joint registration: uploads every view's correction implied by its pair's
-// shared T.
 // One joint iteration: the views' pose gradients from the pose-only
 // backward, then on the device every pair's Adam step of T (chained through
 // the Jacobian of T -> Delta) and the views' new corrections.  No host
