@@ -64,7 +64,7 @@ ls_status overlap_check_args(const float* p_mean, int32_t np, const float* q_mea
 namespace {
 
 struct Layout {
-  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, loss_part, queues, total;
+  size_t dk0, dv0, dk1, dv1, hist, bsum, tk, tv, g2d, tile_part, pose_part, loss_part, used, queues, total;
 };
 
 Layout layout_of(const ls_batch* b, int64_t cap) {
@@ -93,6 +93,7 @@ Layout layout_of(const ls_batch* b, int64_t cap) {
   L.tile_part = take(4 * (size_t)kPoseAcc * std::max(b->T, 1));
   L.pose_part = take(4 * (size_t)kPoseAcc * std::max(b->nblk_items, 1));
   L.loss_part = take(8 * (size_t)std::max(b->T, 1));  // per tile {L1 sum, pixels in Omega}
+  L.used = take(8 * 4 * (size_t)used_slots(cap, b->T));  // per band a row of "used" bits, 64 entries a word
   L.queues = take(kTileQueueBytes);
   L.total = off;
   return L;
@@ -369,7 +370,8 @@ ls_status render_bwd_pose_l1(const ls_batch* b, const float* pose, const ls_proj
   const Layout L = layout_of(b, bins->capacity);
   const float zero[3] = {0.f, 0.f, 0.f};
   const L1Targets l1{fwd->rgb, fwd->depth, tgt_rgb, tgt_depth, nullptr};
-  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range, zero,
+  launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range,
+                       at<uint64_t>(bins->work, L.used), used_slots(bins->capacity, b->T), zero,
                        fwd->T_final, fwd->n_last, nullptr, nullptr, nullptr, scale, at<float>(bins->work, L.g2d),
                        at<float>(bins->work, L.tile_part), 1, at<char>(bins->work, L.queues), s, &l1);
   return hip_check("pose-only backward with the L1 gradient");
@@ -491,8 +493,10 @@ ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins*
   if (!out || !out->rgb || !out->depth || !out->alpha || !out->T_final || !out->n_last)
     return fail(LS_ERR_INVALID, "ls_image has NULL members");
   const float zero[3] = {0.f, 0.f, 0.f};
+  const Layout L = layout_of(b, bins->capacity);
   launch_composite_fwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, bins->item, bins->range, bg ? bg : zero,
-                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, s);
+                       out->rgb, out->depth, out->alpha, out->T_final, out->n_last, at<uint64_t>(bins->work, L.used),
+                       used_slots(bins->capacity, b->T), s);
   return hip_check("ls_render_fwd");
 }
 
@@ -507,6 +511,7 @@ ls_status ls_render_bwd_tiles(const ls_batch* b, const float* pose, const ls_pro
   const Layout L = layout_of(b, bins->capacity);
   const float zero[3] = {0.f, 0.f, 0.f};
   launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range,
+                       at<uint64_t>(bins->work, L.used), used_slots(bins->capacity, b->T),
                        bg ? bg : zero, fwd->T_final, fwd->n_last, up->rgb, up->depth, up->alpha, up->scale,
                        at<float>(bins->work, L.g2d), at<float>(bins->work, L.tile_part),
                        (flags & LS_BWD_POSE_ONLY) ? 1 : 0, at<char>(bins->work, L.queues), s);
@@ -527,6 +532,7 @@ ls_status ls_render_bwd_tiles_l1(const ls_batch* b, const float* pose, const ls_
   const float zero[3] = {0.f, 0.f, 0.f};
   const L1Targets l1{fwd->rgb, fwd->depth, tgt_rgb, tgt_depth, at<float>(bins->work, L.loss_part)};
   launch_composite_bwd(b->jobs_d, b->tile_off_d, b->R, b->T, p->rec, p->aux, pose, bins->item, bins->range,
+                       at<uint64_t>(bins->work, L.used), used_slots(bins->capacity, b->T),
                        bg ? bg : zero, fwd->T_final, fwd->n_last, nullptr, nullptr, nullptr, inv_count,
                        at<float>(bins->work, L.g2d), at<float>(bins->work, L.tile_part),
                        (flags & LS_BWD_POSE_ONLY) ? 1 : 0, at<char>(bins->work, L.queues), s, &l1);

@@ -230,7 +230,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const JobDev* __restrict__ jobs, const int32_t* __restrict__ tile_off, int R, int T_total,
     const float4* __restrict__ rec, const int32_t* __restrict__ items, const int32_t* __restrict__ range, float bg0,
     float bg1, float bg2, float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_alpha,
-    float* __restrict__ out_T, int32_t* __restrict__ out_n) {
+    float* __restrict__ out_T, int32_t* __restrict__ out_n, uint64_t* __restrict__ used, int64_t ustride) {
   __shared__ float4 s0[64], s1[64], s2[64];
   __shared__ int32_t spos[64];
   const int unit = xcd_remap(blockIdx.x, 4 * T_total);
@@ -251,8 +251,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
   int nlast = end - start;
   uint64_t alive = __ballot(inside);
-  for (int chunk = start; chunk < end && alive != 0ull; chunk += 64) {
+  // chunk k of the tile's list keeps its "used" bits in slot (start / 64) +
+  // tile + k of the band's row: the slots of successive tiles never overlap
+  int64_t slot = (int64_t)(start >> 6) + tile;
+  for (int chunk = start; chunk < end && alive != 0ull; chunk += 64, ++slot) {
     const int e = chunk + lane;
+    uint64_t usedm = 0ull;  // bit j: some pixel of the band composited its j-th staged entry
     bool in = false;
     float4 r0 = make_float4(0.f, 0.f, 0.f, 0.f), r1 = r0, r2 = r0;  // this lane's record
     if (e < end) {
@@ -266,8 +270,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       }
     }
     const uint64_t bal = __ballot(in);
+    const int pos = __popcll(bal & lt);
     if (in) {
-      const int pos = __popcll(bal & lt);
       s0[pos] = r0;
       s1[pos] = r1;
       s2[pos] = r2;
@@ -295,6 +299,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
         cb += wgt * col.z;
         dd += wgt * b.z;
         T = u ? Tn : T;
+        usedm |= 1ull << j;
       }
     };
     // Records are read one entry ahead into two alternating register sets
@@ -316,6 +321,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       step(jj, aB, bB, cB);
       ++jj;
     }
+    // the entries of this chunk that some pixel of the band composited
+    // (bit l: entry chunk + l): exactly the (entry, band) pairs in which the
+    // backward has an active lane
+    const uint64_t um = __ballot(in && ((usedm >> pos) & 1ull));
+    if (lane == 0) used[band * ustride + slot] = um;
     __builtin_amdgcn_wave_barrier();
   }
   if (!inside) return;
@@ -510,21 +520,33 @@ __device__ __forceinline__ BwdPixel bwd_pixel(const TileCtx& c, const JobDev& J,
 
 // Wave 0 stages a chunk of the tile's list (records and item ids) and builds,
 // for each of the four wave bands, the list-ordered positions of the entries
-// that can reach it and that some pixel of the band visited (list position
-// below the band's largest entry count, bmax: the forward stopped every pixel
-// of the band before the others).
+// that some pixel of the band composited in the forward (its "used" bits:
+// per band row, 64 entries per slot, slot (start / 64) + tile + k for the
+// entries from start + 64 k on; list positions at or beyond the band's
+// largest entry count bmax were never walked there and are dropped).
 template <int kChunk>
-__device__ __forceinline__ void stage_chunk(int lane, int cnt, int chunk, int start, const int* bmax,
-                                            const int32_t* items, const float4* rec, int tx0, int ty0, float4* s0,
-                                            float4* s1, float4* s2, int32_t* sit, uint32_t* smask,
-                                            uint8_t (*slist)[kChunk], uint32_t* swc) {
+__device__ __forceinline__ void stage_chunk(int lane, int cnt, int chunk, int start, int tile, const int* bmax,
+                                            const int32_t* items, const float4* rec, const uint64_t* used,
+                                            int64_t ustride, float4* s0, float4* s1, float4* s2, int32_t* sit,
+                                            uint32_t* smask, uint8_t (*slist)[kChunk], uint32_t* swc) {
+  // the chunk's bits of each band (bit l: entry chunk + l), from one or two slots
+  const int rel = chunk - start, sh = rel & 63;
+  const int64_t slot = (int64_t)(start >> 6) + tile + (rel >> 6);
+  uint64_t ub[4];
+#pragma unroll
+  for (int b2 = 0; b2 < 4; ++b2) {
+    const uint64_t w0 = used[b2 * ustride + slot];
+    const uint64_t w1 = sh ? used[b2 * ustride + slot + 1] : 0ull;
+    ub[b2] = sh ? (w0 >> sh) | (w1 << (64 - sh)) : w0;
+  }
   uint32_t m = 0;
   const bool valid = lane < cnt;
   if (valid) {
     const int64_t it = items[chunk + lane];
     float4 a = rec[it * 3 + 0], b = rec[it * 3 + 1];
     const int k = chunk + lane - start;
-    m = wave_mask(a, b, tx0, ty0);
+#pragma unroll
+    for (int b2 = 0; b2 < 4; ++b2) m |= (uint32_t)((ub[b2] >> lane) & 1ull) << b2;
 #pragma unroll
     for (int b2 = 0; b2 < 4; ++b2)
       if (k >= bmax[b2]) m &= ~(1u << b2);
@@ -571,8 +593,10 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
                                                           const int32_t* __restrict__ items,
-                                                          const int32_t* __restrict__ range, float bg0, float bg1,
-                                                          float bg2, const float* __restrict__ fwd_T,
+                                                          const int32_t* __restrict__ range,
+                                                          const uint64_t* __restrict__ used, int64_t ustride,
+                                                          float bg0, float bg1, float bg2,
+                                                          const float* __restrict__ fwd_T,
                                                           const int32_t* __restrict__ fwd_n,
                                                           const float* __restrict__ up_rgb,
                                                           const float* __restrict__ up_depth,
@@ -594,7 +618,6 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wval = wave_value<kGrad2D>(lane);  // the value whose wave sum this lane stores, or -1
-  const int tx0 = c.x0, ty0 = c.y0;
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, l1);
   tile_loss_put(l1, px, sloss);
   if (threadIdx.x < 4) bmax[threadIdx.x] = 0;
@@ -609,7 +632,8 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
     const int chunk = max(start, chunk_end - kBwdChunk);
     const int cnt = chunk_end - chunk;
     if (w == 0)
-      stage_chunk<kBwdChunk>(lane, cnt, chunk, start, bmax, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist, swc);
+      stage_chunk<kBwdChunk>(lane, cnt, chunk, start, tile, bmax, items, rec, used, ustride, s0, s1, s2, sit, smask,
+                             slist, swc);
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     // the band's list in a register; lanes past its end hold 0, so the
@@ -708,8 +732,10 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
                                                           const int32_t* __restrict__ tile_off, int R, int T_total,
                                                           const float4* __restrict__ rec,
                                                           const int32_t* __restrict__ items,
-                                                          const int32_t* __restrict__ range, float bg0, float bg1,
-                                                          float bg2, const float* __restrict__ fwd_T,
+                                                          const int32_t* __restrict__ range,
+                                                          const uint64_t* __restrict__ used, int64_t ustride,
+                                                          float bg0, float bg1, float bg2,
+                                                          const float* __restrict__ fwd_T,
                                                           const int32_t* __restrict__ fwd_n,
                                                           const float* __restrict__ up_rgb,
                                                           const float* __restrict__ up_depth,
@@ -718,24 +744,25 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd(const JobDev* __restri
                                                           float* __restrict__ g2d, L1Targets l1) {
   const int tile = xcd_remap(blockIdx.x, T_total);
   if (tile >= T_total) return;
-  composite_bwd_tile(jobs, tile_off, R, T_total, rec, items, range, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth,
-                     up_alpha, up_scale, g2d, l1, tile);
+  composite_bwd_tile(jobs, tile_off, R, T_total, rec, items, range, used, ustride, bg0, bg1, bg2, fwd_T, fwd_n,
+                     up_rgb, up_depth, up_alpha, up_scale, g2d, l1, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void k_composite_bwd_persistent(const JobDev* __restrict__ jobs,
     const int32_t* __restrict__ tile_off, int R, int T_total, const float4* __restrict__ rec,
-    const int32_t* __restrict__ items, const int32_t* __restrict__ range, float bg0, float bg1, float bg2,
-    const float* __restrict__ fwd_T, const int32_t* __restrict__ fwd_n, const float* __restrict__ up_rgb,
-    const float* __restrict__ up_depth, const float* __restrict__ up_alpha, const float* __restrict__ up_scale,
-    float* __restrict__ g2d, TileQueue* __restrict__ queue, int nstatic, L1Targets l1) {
+    const int32_t* __restrict__ items, const int32_t* __restrict__ range, const uint64_t* __restrict__ used,
+    int64_t ustride, float bg0, float bg1, float bg2, const float* __restrict__ fwd_T,
+    const int32_t* __restrict__ fwd_n, const float* __restrict__ up_rgb, const float* __restrict__ up_depth,
+    const float* __restrict__ up_alpha, const float* __restrict__ up_scale, float* __restrict__ g2d,
+    TileQueue* __restrict__ queue, int nstatic, L1Targets l1) {
   __shared__ int s_tile;
   bool first = true;
   uint32_t dead = 0;
   for (;;) {
     const int tile = claim_tile(queue, T_total, nstatic, first, dead, &s_tile);
     if (tile < 0) break;
-    composite_bwd_tile(jobs, tile_off, R, T_total, rec, items, range, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth,
-                       up_alpha, up_scale, g2d, l1, tile);
+    composite_bwd_tile(jobs, tile_off, R, T_total, rec, items, range, used, ustride, bg0, bg1, bg2, fwd_T, fwd_n,
+                       up_rgb, up_depth, up_alpha, up_scale, g2d, l1, tile);
   }
   release_queue(queue);
 }
@@ -761,8 +788,10 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
                                                                const float4* __restrict__ aux,
                                                                const float* __restrict__ pose,
                                                                const int32_t* __restrict__ items,
-                                                               const int32_t* __restrict__ range, float bg0,
-                                                               float bg1, float bg2, const float* __restrict__ fwd_T,
+                                                               const int32_t* __restrict__ range,
+                                                               const uint64_t* __restrict__ used, int64_t ustride,
+                                                               float bg0, float bg1, float bg2,
+                                                               const float* __restrict__ fwd_T,
                                                                const int32_t* __restrict__ fwd_n,
                                                                const float* __restrict__ up_rgb,
                                                                const float* __restrict__ up_depth,
@@ -787,7 +816,6 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
   const float fx = (float)c.x + 0.5f, fy = (float)c.y + 0.5f;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wval = wave_value<kPoseRow>(lane);
-  const int tx0 = c.x0, ty0 = c.y0;
   __shared__ float sloss[2][4];
   BwdPixel px = bwd_pixel(c, J, bg0, bg1, bg2, fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, l1);
   tile_loss_put(l1, px, sloss);
@@ -805,8 +833,8 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
     const int chunk = max(start, chunk_end - kPoseChunk);
     const int cnt = chunk_end - chunk;
     if (w == 0)
-      stage_chunk<kPoseChunk>(lane, cnt, chunk, start, bmax, items, rec, tx0, ty0, s0, s1, s2, sit, smask, slist,
-                              swc);
+      stage_chunk<kPoseChunk>(lane, cnt, chunk, start, tile, bmax, items, rec, used, ustride, s0, s1, s2, sit, smask,
+                              slist, swc);
     __syncthreads();
     const int cw = __builtin_amdgcn_readfirstlane((int)swc[w]);
     // the band's list in a register; lanes past its end hold 0, so the
@@ -930,8 +958,10 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose(const JobDev* __r
                                                                const float4* __restrict__ aux,
                                                                const float* __restrict__ pose,
                                                                const int32_t* __restrict__ items,
-                                                               const int32_t* __restrict__ range, float bg0,
-                                                               float bg1, float bg2, const float* __restrict__ fwd_T,
+                                                               const int32_t* __restrict__ range,
+                                                               const uint64_t* __restrict__ used, int64_t ustride,
+                                                               float bg0, float bg1, float bg2,
+                                                               const float* __restrict__ fwd_T,
                                                                const int32_t* __restrict__ fwd_n,
                                                                const float* __restrict__ up_rgb,
                                                                const float* __restrict__ up_depth,
@@ -940,14 +970,15 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose(const JobDev* __r
                                                                float* __restrict__ tile_part, L1Targets l1) {
   const int tile = xcd_remap(blockIdx.x, T_total);
   if (tile >= T_total) return;
-  composite_bwd_pose_tile(jobs, tile_off, R, T_total, rec, aux, pose, items, range, bg0, bg1, bg2, fwd_T, fwd_n,
-                          up_rgb, up_depth, up_alpha, up_scale, tile_part, l1, tile);
+  composite_bwd_pose_tile(jobs, tile_off, R, T_total, rec, aux, pose, items, range, used, ustride, bg0, bg1, bg2,
+                          fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, tile_part, l1, tile);
 }
 
 __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose_persistent(const JobDev* __restrict__ jobs,
     const int32_t* __restrict__ tile_off, int R, int T_total, const float4* __restrict__ rec,
     const float4* __restrict__ aux, const float* __restrict__ pose, const int32_t* __restrict__ items,
-    const int32_t* __restrict__ range, float bg0, float bg1, float bg2, const float* __restrict__ fwd_T,
+    const int32_t* __restrict__ range, const uint64_t* __restrict__ used, int64_t ustride, float bg0, float bg1,
+    float bg2, const float* __restrict__ fwd_T,
     const int32_t* __restrict__ fwd_n, const float* __restrict__ up_rgb, const float* __restrict__ up_depth,
     const float* __restrict__ up_alpha, const float* __restrict__ up_scale, float* __restrict__ tile_part,
     TileQueue* __restrict__ queue, int nstatic, L1Targets l1) {
@@ -957,8 +988,8 @@ __global__ __launch_bounds__(kBlock) void k_composite_bwd_pose_persistent(const 
   for (;;) {
     const int tile = claim_tile(queue, T_total, nstatic, first, dead, &s_tile);
     if (tile < 0) break;
-    composite_bwd_pose_tile(jobs, tile_off, R, T_total, rec, aux, pose, items, range, bg0, bg1, bg2, fwd_T, fwd_n,
-                            up_rgb, up_depth, up_alpha, up_scale, tile_part, l1, tile);
+    composite_bwd_pose_tile(jobs, tile_off, R, T_total, rec, aux, pose, items, range, used, ustride, bg0, bg1, bg2,
+                            fwd_T, fwd_n, up_rgb, up_depth, up_alpha, up_scale, tile_part, l1, tile);
   }
   release_queue(queue);
 }
@@ -1081,21 +1112,24 @@ static PersistentGrid persistent_grid(int which, const void* kernel, int T) {
 
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
-                          float* alpha, float* Tf, int32_t* nl, hipStream_t s) {
+                          float* alpha, float* Tf, int32_t* nl, uint64_t* used, int64_t ustride,
+                          hipStream_t s) {
   if (T <= 0) return;
   // always one block per band: a band is short, and claiming tiles from the
   // queues cost more than it balanced (registration iteration A/B: 1.3 %
   // slower persistent)
   hipLaunchKernelGGL(k_composite_fwd_band, dim3(xcd_grid(4 * T)), dim3(64), 0, s, jobs, tile_off, R, T,
                      reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], rgb, depth, alpha, Tf,
-                     nl);
+                     nl, used, ustride);
 }
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,
-                          const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
-                          const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
-                          float* tile_part, int pose_only, void* queues, hipStream_t s, const L1Targets* l1) {
+                          const uint64_t* used, int64_t ustride, const float* bg, const float* Tf,
+                          const int32_t* nl,
+                          const float* up_rgb, const float* up_depth, const float* up_alpha, const float* up_scale,
+                          float* g2d, float* tile_part, int pose_only, void* queues, hipStream_t s,
+                          const L1Targets* l1) {
   if (T <= 0) return;
   const L1Targets l1v = l1 ? *l1 : L1Targets{nullptr, nullptr, nullptr, nullptr, nullptr};
   const float4* rec4 = reinterpret_cast<const float4*>(rec);
@@ -1104,21 +1138,22 @@ void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, in
     const PersistentGrid g = persistent_grid(1, reinterpret_cast<const void*>(k_composite_bwd_pose_persistent), T);
     if (g.on)
       hipLaunchKernelGGL(k_composite_bwd_pose_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T,
-                         rec4, aux4, pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha,
-                         up_scale, tile_part, reinterpret_cast<TileQueue*>(queues) + 1, g.nstatic, l1v);
+                         rec4, aux4, pose, items, range, used, ustride, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth,
+                         up_alpha, up_scale, tile_part, reinterpret_cast<TileQueue*>(queues) + 1, g.nstatic, l1v);
     else
       hipLaunchKernelGGL(k_composite_bwd_pose, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, aux4,
-                         pose, items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
-                         tile_part, l1v);
+                         pose, items, range, used, ustride, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha,
+                         up_scale, tile_part, l1v);
   } else {
     const PersistentGrid g = persistent_grid(0, reinterpret_cast<const void*>(k_composite_bwd_persistent), T);
     if (g.on)
       hipLaunchKernelGGL(k_composite_bwd_persistent, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4,
-                         items, range, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d,
-                         reinterpret_cast<TileQueue*>(queues) + 0, g.nstatic, l1v);
+                         items, range, used, ustride, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale,
+                         g2d, reinterpret_cast<TileQueue*>(queues) + 0, g.nstatic, l1v);
     else
       hipLaunchKernelGGL(k_composite_bwd, dim3(g.blocks), dim3(kBlock), 0, s, jobs, tile_off, R, T, rec4, items, range,
-                         bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d, l1v);
+                         used, ustride, bg[0], bg[1], bg[2], Tf, nl, up_rgb, up_depth, up_alpha, up_scale, g2d,
+                         l1v);
   }
 }
 }  // namespace ls

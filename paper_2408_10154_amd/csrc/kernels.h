@@ -67,9 +67,15 @@ void launch_bin_sort(const JobDev* jobs, const int64_t* item_off_d, int R, int64
 int launch_radix_sort_pairs(uint32_t* k0, uint32_t* v0, uint32_t* k1, uint32_t* v1, int64_t n, int bits,
                             uint32_t* hist, uint32_t* digit_total, hipStream_t s);
 
+// used: 4 rows (one per band) of ustride = used_slots(capacity, T) 64-bit
+// words; the forward sets bit l of slot (start / 64) + tile + k of row q when
+// some pixel of band q composited list entry start + 64 k + l of the tile
+// (chunks a band never walked keep old bits: the backward reads only
+// positions below the band's largest n_last).
+inline int64_t used_slots(int64_t cap, int T) { return cap / 64 + T + 2; }
 void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const int32_t* items, const int32_t* range, const float* bg, float* rgb, float* depth,
-                          float* alpha, float* Tf, int32_t* nl, hipStream_t s);
+                          float* alpha, float* Tf, int32_t* nl, uint64_t* used, int64_t ustride, hipStream_t s);
 
 // Backward compositing (persistent when a launch has many tiles per resident
 // block); queues = kTileQueueBytes of zero-initialised workspace (left zeroed
@@ -96,9 +102,12 @@ struct L1Targets {
 // render's tiles in a fixed order (0 when the render has no pixel in Omega).
 void launch_tile_loss_reduce(const JobDev* jobs, int R, const float* loss_part, float* loss, hipStream_t s);
 
+// used, ustride: the flags the forward wrote for the same bins: the backward
+// walks only the entries some pixel of the band composited.
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,
                           const float* aux, const float* pose, const int32_t* items, const int32_t* range,
-                          const float* bg, const float* Tf, const int32_t* nl, const float* up_rgb,
+                          const uint64_t* used, int64_t ustride, const float* bg, const float* Tf, const int32_t* nl,
+                          const float* up_rgb,
                           const float* up_depth, const float* up_alpha, const float* up_scale, float* g2d,
                           float* tile_part, int pose_only, void* queues, hipStream_t s,
                           const L1Targets* l1 = nullptr);
