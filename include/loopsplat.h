@@ -199,7 +199,10 @@ typedef struct {
  * o exp(-sigma)); entries with sigma < 0 or alpha < 1/255 are skipped; the
  * loop stops before the entry that would take T below 1e-4; otherwise
  * w = alpha T, C += w c, D += w z, T *= 1 - alpha.  rgb gets + T bg.
- * bg: host float[3] or NULL (zero). */
+ * bg: host float[3] or NULL (zero).  It also records in bins->work which
+ * list entries each 8x8 band of a tile composited; the backward calls read
+ * those records, so `fwd` passed to them must be this call's output on the
+ * same bins (no ls_render_fwd or ls_bin_sort on them in between). */
 ls_status ls_render_fwd(const ls_batch* b, const ls_projected* p, const ls_bins* bins, const float* bg,
                         const ls_image* out, hipStream_t s);
 
@@ -248,9 +251,10 @@ typedef struct {
 
 /* Backward of ls_project + ls_render_fwd (= ls_render_bwd_tiles followed by
  * ls_render_bwd_project).  Recomputes the per-pixel transmittance back to
- * front from T_final / n_last (no per-pixel lists are stored), reduces the
- * per-Gaussian image-space gradients within each tile, then chains them
- * through the projection.
+ * front from T_final / n_last (no per-pixel lists are stored), walking only
+ * the list entries the last ls_render_fwd on these bins composited in each
+ * band (fwd must be that call's output), reduces the per-Gaussian image-space
+ * gradients within each tile, then chains them through the projection.
  *   grads:     host array [R] of per-render outputs, or NULL (pose only).
  *              Jobs sharing a Gaussian set may share output arrays.
  *   pose_grad: device [R][7], accumulated, or NULL; needs `pose`.
