@@ -442,8 +442,10 @@ constexpr int kPartStride = 4 * kWaveSlots + 1;         // floats per entry: 4 w
 // sigma >= 0 and alpha >= 1/255.  bwd_apply (entries some lane of the wave
 // composited), branch-free: where act, T is recovered, acc updated, and
 // wgt = alpha T, ds = dL/dsigma and dop = dL/d(opacity) are set (both zero
-// while the 0.99 clamp is active); elsewhere T and acc are unchanged and
-// wgt = ds = dop = 0 (selected, never formed from products with exp(-sigma)).
+// while the 0.99 clamp is active).  Elsewhere the step runs with alpha = 0,
+// which leaves T (times 1 / 1) and acc (plus 0) unchanged and gives wgt = 0,
+// and with G and exp(-sigma) selected to 0, which gives ds = dop = 0: three
+// selects instead of one per output.
 struct BwdEval {
   float ex, G, al;  // exp(-sigma), o exp(-sigma), alpha
   bool act;
@@ -461,15 +463,16 @@ __device__ __forceinline__ BwdEval bwd_eval(bool visited, float4 a, float4 b, fl
 
 __device__ __forceinline__ void bwd_apply(const BwdEval& e, float4 col, float z, float gR, float gG, float gB,
                                           float gD, float& T, float& acc, float& wgt, float& ds, float& dop) {
-  const float om = 1.f - e.al;
-  T = e.act ? T * __builtin_amdgcn_rcpf(om) : T;
-  wgt = e.act ? e.al * T : 0.f;
+  const float al = e.act ? e.al : 0.f;
+  T = T * __builtin_amdgcn_rcpf(1.f - al);
+  wgt = al * T;
   const float v = col.x * gR + col.y * gG + col.z * gB + z * gD;
-  const float dal = T * (v - acc);
-  acc = e.act ? e.al * v + om * acc : acc;
+  const float d = v - acc;
+  const float dal = T * d;
+  acc = fmaf(al, d, acc);  // alpha v + (1 - alpha) acc
   const bool grad = e.act && e.G < LS_ALPHA_MAX;  // dL/dG = dal; no gradient through an active clamp
-  ds = grad ? -dal * e.G : 0.f;
-  dop = grad ? dal * e.ex : 0.f;
+  ds = -dal * (grad ? e.G : 0.f);
+  dop = dal * (grad ? e.ex : 0.f);
 }
 
 // Per-pixel state shared by both backward kernels: upstream gradients (scaled),
@@ -643,29 +646,27 @@ __device__ __forceinline__ void composite_bwd_tile(const JobDev* __restrict__ jo
       float* pj = part + j * kPartStride + w * kWaveSlots + max(wval, 0);  // written only where wval >= 0
       const int k = chunk + j - start;  // list position
       const float dx = fx - a.x, dy = fy - a.y;
+      // every staged entry has an active lane (the forward's bits), so the
+      // step runs unconditionally; inactive lanes contribute exact zeros
       const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
-      if (__ballot(e.act) != 0ull) {
-        float wgt, ds, dop;
-        bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
-        // per-pixel terms whose sums give the ten gradients; the conic factors
-        // of dL/du, dL/dv and the halves of dL/dA, dL/dC are applied once per
-        // entry after the sums
-        float g[kGrad2D];
-        g[0] = ds * dx;
-        g[1] = ds * dy;
-        g[2] = g[0] * dx;
-        g[3] = g[0] * dy;
-        g[4] = g[1] * dy;
-        g[5] = dop;
-        g[6] = wgt * px.gD;
-        g[7] = wgt * px.gR;
-        g[8] = wgt * px.gG;
-        g[9] = wgt * px.gB;
-        const float out = wave_sums<kGrad2D>(g, lane);
-        if (wval >= 0) *pj = out;
-      } else if (wval >= 0) {
-        *pj = 0.f;
-      }
+      float wgt, ds, dop;
+      bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
+      // per-pixel terms whose sums give the ten gradients; the conic factors
+      // of dL/du, dL/dv and the halves of dL/dA, dL/dC are applied once per
+      // entry after the sums
+      float g[kGrad2D];
+      g[0] = ds * dx;
+      g[1] = ds * dy;
+      g[2] = g[0] * dx;
+      g[3] = g[0] * dy;
+      g[4] = g[1] * dy;
+      g[5] = dop;
+      g[6] = wgt * px.gD;
+      g[7] = wgt * px.gR;
+      g[8] = wgt * px.gG;
+      g[9] = wgt * px.gB;
+      const float out = wave_sums<kGrad2D>(g, lane);
+      if (wval >= 0) *pj = out;
     };
     // records read one entry ahead into alternating register sets (as in the forward)
     int jA = (int)__builtin_amdgcn_readlane(myj, cw > 0 ? cw - 1 : 0), jB = 0;
@@ -844,21 +845,19 @@ __device__ __forceinline__ void composite_bwd_pose_tile(const JobDev* __restrict
       float* pj = part + j * kPoseStride + w * kPoseSlots + max(wval, 0);  // written only where wval >= 0
       const int k = chunk + j - start;
       const float dx = fx - a.x, dy = fy - a.y;
+      // unconditional, as in the full-mode kernel
       const BwdEval e = bwd_eval(k < px.nl, a, b, dx, dy);
-      float out = 0.f;
-      if (__ballot(e.act) != 0ull) {
-        float wgt, ds, dop;
-        bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
-        // as in the full-mode kernel: conic factors and halves after the sums
-        float g[kPoseRow];
-        g[0] = ds * dx;
-        g[1] = ds * dy;
-        g[2] = g[0] * dx;
-        g[3] = g[0] * dy;
-        g[4] = g[1] * dy;
-        g[5] = wgt * px.gD;
-        out = wave_sums<kPoseRow>(g, lane);
-      }
+      float wgt, ds, dop;
+      bwd_apply(e, col, b.z, px.gR, px.gG, px.gB, px.gD, px.T, px.acc, wgt, ds, dop);
+      // as in the full-mode kernel: conic factors and halves after the sums
+      float g[kPoseRow];
+      g[0] = ds * dx;
+      g[1] = ds * dy;
+      g[2] = g[0] * dx;
+      g[3] = g[0] * dy;
+      g[4] = g[1] * dy;
+      g[5] = wgt * px.gD;
+      const float out = wave_sums<kPoseRow>(g, lane);
       if (wval >= 0) *pj = out;
     };
     // records read one entry ahead into alternating register sets (as in the forward)
