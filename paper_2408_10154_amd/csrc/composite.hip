@@ -109,6 +109,28 @@ __device__ __forceinline__ uint32_t wave_mask(float4 a, float4 b, int tile_x0, i
   return m;
 }
 
+// The rows of one 8x8 band (pixel centres from (bx0, by0), 1 px apart) that
+// the Gaussian's alpha >= 1/255 support can reach, as a mask of whole rows
+// (bit 8 r + c for every column c of a reached row r): the support's y-extent
+// over the band's column strip (strip_extent, widened as in wave_mask) holds
+// every pixel centre the support contains, so a row whose centre lies outside
+// it holds no pixel that composites the entry.
+__device__ __forceinline__ uint64_t band_rows(float4 a, float4 b, float bx0, float by0) {
+  const float o = b.y;
+  if (!(o >= LS_ALPHA_MIN)) return 0ull;
+  const float A = a.z, B = a.w, C = b.x;
+  const float dq = A * C - B * B;
+  if (!(dq > 0.f)) return ~0ull;
+  const float smax = __logf(o * (1.0f / LS_ALPHA_MIN)) * 1.001f + 1e-4f;
+  const float hx = sqrtf(fmaxf(2.f * smax * C / dq, 0.f)) * 1.001f + 0.02f;
+  const float hy = sqrtf(fmaxf(2.f * smax * A / dq, 0.f)) * 1.001f + 0.02f;
+  float ylo, yhi;
+  if (!strip_extent(a.x, a.y, A, B, C, dq, smax, hx, hy, bx0, bx0 + 7.f, ylo, yhi)) return 0ull;
+  const int r0 = (int)fmaxf(ceilf(ylo - by0), 0.f), r1 = (int)fminf(floorf(yhi - by0), 7.f);
+  if (r0 > r1) return 0ull;
+  return (~0ull >> (8 * (7 - r1))) & (~0ull << (8 * r0));
+}
+
 // Tile queues of the persistent compositing kernels (in the bins workspace:
 // zero on first use, re-zeroed by every launch).  The tiles are cut into 8
 // contiguous ranges; block b runs on XCD b % 8 under round-robin dispatch and
@@ -230,7 +252,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
     const JobDev* __restrict__ jobs, const int32_t* __restrict__ tile_off, int R, int T_total,
     const float4* __restrict__ rec, const int32_t* __restrict__ items, const int32_t* __restrict__ range, float bg0,
     float bg1, float bg2, float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_alpha,
-    float* __restrict__ out_T, int32_t* __restrict__ out_n, uint64_t* __restrict__ used, int64_t ustride) {
+    float* __restrict__ out_T, int32_t* __restrict__ out_n, uint64_t* __restrict__ used, int64_t ustride,
+    int cover) {
   __shared__ float4 s0[64], s1[64], s2[64];
   __shared__ int32_t spos[64];
   const int unit = xcd_remap(blockIdx.x, 4 * T_total);
@@ -246,11 +269,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
   const bool inside = x < J.W && y < J.H;
   const int start = range[2 * tile], end = range[2 * tile + 1];
   const float fx = (float)x + 0.5f, fy = (float)y + 0.5f;
+  const float bx0 = (float)(tx0 + 8 * (band & 1)) + 0.5f, by0 = (float)(ty0 + 8 * (band >> 1)) + 0.5f;
   const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 
   float T = 1.f, cr = 0.f, cg = 0.f, cb = 0.f, dd = 0.f;
   int nlast = end - start;
-  uint64_t alive = __ballot(inside);
+  uint64_t alive = __ballot(inside);  // lane l is pixel (l & 7, l >> 3) of the band: bit l of band_rows
   // chunk k of the tile's list keeps its "used" bits in slot (start / 64) +
   // tile + k of the band's row: the slots of successive tiles never overlap
   int64_t slot = (int64_t)(start >> 6) + tile;
@@ -263,7 +287,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const int64_t it = items[e];
       r0 = rec[it * 3 + 0];
       r1 = rec[it * 3 + 1];
-      in = (wave_mask(r0, r1, tx0, ty0) >> band) & 1u;
+      if (cover)  // some row the entry can reach holds a pixel still compositing
+        in = (band_rows(r0, r1, bx0, by0) & alive) != 0ull;
+      else
+        in = (wave_mask(r0, r1, tx0, ty0) >> band) & 1u;
       if (in) {
         stage_conic(r0, r1);
         r2 = rec[it * 3 + 2];
@@ -1117,9 +1144,13 @@ void launch_composite_fwd(const JobDev* jobs, const int32_t* tile_off, int R, in
   // always one block per band: a band is short, and claiming tiles from the
   // queues cost more than it balanced (registration iteration A/B: 1.3 %
   // slower persistent)
+  // LS_COVER=0 (read at every launch; for tests and measurements): stage by
+  // the band rectangle test alone, whatever pixels have stopped
+  const char* cv = std::getenv("LS_COVER");
+  const int cover = (cv && cv[0] == '0' && cv[1] == '\0') ? 0 : 1;
   hipLaunchKernelGGL(k_composite_fwd_band, dim3(xcd_grid(4 * T)), dim3(64), 0, s, jobs, tile_off, R, T,
                      reinterpret_cast<const float4*>(rec), items, range, bg[0], bg[1], bg[2], rgb, depth, alpha, Tf,
-                     nl, used, ustride);
+                     nl, used, ustride, cover);
 }
 
 void launch_composite_bwd(const JobDev* jobs, const int32_t* tile_off, int R, int T, const float* rec,

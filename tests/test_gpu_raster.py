@@ -888,3 +888,39 @@ def test_fused_l1_backward_matches_loss_then_backward(gpu, pose_only):
         for n, ta, tf in zip(("mean", "log_scale", "quat", "opacity_logit", "rgb"), x.tensors(), y.tensors()):
             a_, f_ = ta.cpu().numpy(), tf.cpu().numpy()
             np.testing.assert_allclose(f_, a_, rtol=1e-4, atol=1e-5 * max(np.abs(a_).max(), 1e-30), err_msg=n)
+
+
+@pytest.mark.parametrize("which", ["three_renders", "room_200k"])
+def test_forward_cover_skip_is_bitwise_neutral(gpu, monkeypatch, which):
+    """The forward stages an entry for a band by the pixels its alpha >= 1/255
+    support reaches (per-row intervals) and skips it once all of those pixels
+    have stopped.  Against LS_COVER=0 (the band rectangle test, every staged
+    entry walked) the images, T_final and n_last are bit-identical, and so
+    are the pose-only backward's gradients (deterministic, and it walks only
+    the entries the forward marked as composited), on three ragged renders
+    and on the 200k-Gaussian 1200x680 render-loop scene."""
+    from paper_2408_10154_amd.render import GaussianSet, RenderBatch
+
+    if which == "three_renders":
+        jobs, poses = _three_scenes()
+        b = _batch(jobs)
+    else:
+        s = synth.scene_room_volume(seed=1, n=200_000)
+        b = RenderBatch([(GaussianSet.from_numpy(s["gauss"]), s["cam"], s["w2c"])], auto_grow=True)
+        poses = [s["target_pose"]]
+    pose = torch.as_tensor(np.stack(poses), device="cuda").contiguous()
+    out = {}
+    for mode in ("0", "1"):
+        monkeypatch.setenv("LS_COVER", mode)
+        b.project(pose)
+        b.bin_sort()
+        b.render_fwd()
+        g = torch.Generator(device="cpu").manual_seed(3)
+        up_rgb = torch.randn(b.rgb.numel(), generator=g).to("cuda")
+        up_depth = torch.randn(b.depth.numel(), generator=g).to("cuda")
+        pg = torch.zeros_like(pose)
+        b.render_bwd(up_rgb=up_rgb, up_depth=up_depth, grads=None, pose=pose, pose_grad=pg)
+        torch.cuda.synchronize()
+        out[mode] = [t.cpu().numpy().copy() for t in (b.rgb, b.depth, b.alpha, b.T_final, b.n_last, pg)]
+    for name, x0, x1 in zip(("rgb", "depth", "alpha", "T_final", "n_last", "pose_grad"), out["0"], out["1"]):
+        np.testing.assert_array_equal(x1, x0, err_msg=name)
