@@ -158,6 +158,55 @@ def test_bin_sort_bit_exact_long_tile_lists(gpu, monkeypatch, n_items, seed, com
     np.testing.assert_array_equal(b.range.cpu().numpy().reshape(-1, 2), np.asarray(ranges).reshape(-1, 2))
 
 
+@pytest.mark.parametrize("views,digit_bits", [(2, 6), (4, 7), (16, 8)])
+def test_bin_sort_bit_exact_across_tile_digit_widths(gpu, views, digit_bits):
+    """Batches of 640x480 renders (1,200 tiles each) whose tile keys take 12,
+    13 and 15 bits, so the tile passes run on 6-, 7- and 8-bit digits: the
+    lists, ranges and counts equal the oracle's per-render bin sort (tile
+    keys offset by each render's first tile), with equal-depth runs, culled
+    items and items on the image border."""
+    rng = np.random.default_rng(40 + views)
+    per, exp_t, exp_i = [], [], []
+    jobs = []
+    for r in range(views):
+        s = synth.scene_tiny(70 + r, 600, 640, 480, 500.0)
+        jobs.append((s["gauss"], s["cam"], s["w2c"]))
+    b = _batch(jobs, capacity=600 * views * 60)
+    bits = int(np.ceil(np.log2(b.T)))
+    assert {12: 6, 13: 7, 14: 7, 15: 8, 16: 8}[bits] == digit_bits
+    for r, (g, cam, w2c) in enumerate(jobs):
+        camo = U.oracle_camera(cam)
+        n = 600
+        u = rng.uniform(-30.0, 670.0, n).astype(np.float32)
+        v = rng.uniform(-30.0, 510.0, n).astype(np.float32)
+        rad = rng.integers(1, 48, n).astype(np.int64)
+        rad[rng.random(n) < 0.05] = 0
+        z = rng.uniform(0.5, 9.0, n).astype(np.float32)
+        z[50:150] = np.float32(3.0)
+        x0, x1, y0, y1 = R.tile_rect_f32(u, v, rad, camo)
+        tl = np.where(rad > 0, np.maximum(x1 - x0, 0) * np.maximum(y1 - y0, 0), 0)
+        rad = np.where(tl > 0, rad, 0)
+        rc = np.zeros((n, 12), np.float32)
+        rc[:, 0], rc[:, 1], rc[:, 6] = u, v, z
+        rc[:, 2], rc[:, 4], rc[:, 5] = 0.01, 0.01, 0.5
+        per.append((rc, rad.astype(np.int32), tl.astype(np.int32)))
+        t, i, _ = R.bin_sort(u, v, z, rad, camo)
+        exp_t.append(np.asarray(t) + int(b.tile_off[r]))
+        exp_i.append(np.asarray(i) + int(b.item_off[r]))
+    _load_records(b, per)
+    b.bin_sort()
+    exp_t, exp_i = np.concatenate(exp_t), np.concatenate(exp_i)
+    n = b.instances()
+    assert n == len(exp_t) and int(b.count[1].item()) == 0
+    np.testing.assert_array_equal(b.tile_of[:n].cpu().numpy().astype(np.int64), exp_t)
+    np.testing.assert_array_equal(b.item[:n].cpu().numpy().astype(np.int64), exp_i)
+    rng_ = b.range.cpu().numpy().reshape(-1, 2)
+    starts = np.searchsorted(exp_t, np.arange(b.T), side="left")
+    ends = np.searchsorted(exp_t, np.arange(b.T), side="right")
+    expect = np.where((ends > starts)[:, None], np.stack([starts, ends], 1), 0)
+    np.testing.assert_array_equal(rng_, expect)
+
+
 def test_render_fwd_same_inputs(gpu):
     jobs, poses = _three_scenes()
     b = _batch(jobs)
