@@ -895,14 +895,17 @@ def test_gpu_gradients_match_gpu_finite_differences(gpu):
 
 
 @pytest.mark.parametrize("pose_only", [False, True])
-def test_fused_l1_backward_matches_loss_then_backward(gpu, pose_only):
+@pytest.mark.parametrize("empty_render", [False, True])
+def test_fused_l1_backward_matches_loss_then_backward(gpu, pose_only, empty_render):
     """ls_render_bwd_tiles_l1 (the Sec. 3.2 L1 gradient formed inside the
     compositing backward) against ls_loss_l1 + ls_render_bwd_tiles on three
     ragged renders whose targets lack depth on every seventh pixel (outside
     Omega): the same per-pixel gradients, so pose-only partials and pose
     gradients are bit-identical and full-mode Gaussian gradients agree to the
     float-atomic order; the tile-summed loss equals ls_loss_l1's to FP32
-    rounding."""
+    rounding.  With empty_render the second render's targets have no depth
+    at all (an empty Omega): its loss is exactly 0 on both paths and its pose
+    gets no gradient."""
     jobs, poses = _three_scenes()
     pose = torch.as_tensor(np.stack(poses), device="cuda").contiguous()
     b = _batch(jobs)
@@ -912,6 +915,8 @@ def test_fused_l1_backward_matches_loss_then_backward(gpu, pose_only):
     tgt_rgb = (b.rgb * 0.9 + 0.05).contiguous()
     tgt_depth = (b.depth * 1.02).contiguous()
     tgt_depth[::7] = 0.0
+    if empty_render:
+        tgt_depth[int(b.pix_off[1]):int(b.pix_off[2])] = 0.0
     loss, g_rgb, g_depth, scale = b.loss_l1(tgt_rgb, tgt_depth)
     out = []
     for fused in (False, True):
@@ -928,7 +933,12 @@ def test_fused_l1_backward_matches_loss_then_backward(gpu, pose_only):
         out.append((grads, pg.cpu().numpy(), lt.cpu().numpy()))
     (ga, pa, la), (gf, pf, lf) = out
     np.testing.assert_allclose(lf, la, rtol=2e-6)
-    assert (la > 0).all()
+    if empty_render:
+        assert la[1] == 0.0 and lf[1] == 0.0 and float(scale[1].item()) == 0.0
+        assert (pf[1] == 0.0).all() and (pa[1] == 0.0).all()
+        assert la[0] > 0 and la[2] > 0
+    else:
+        assert (la > 0).all()
     if pose_only:
         np.testing.assert_array_equal(pf, pa)
         return
