@@ -152,10 +152,27 @@ constexpr float kLog2e = 1.44269504088896340736f;
 constexpr float kLn2 = 0.69314718055994530942f;
 constexpr float kTwoLn2 = 1.38629436111989061883f;
 
+// The staged record also carries, in its free slot b.w, the bits of the
+// bound on sigma log2(e) within which the splat is composited: alpha =
+// opacity 2^(-sigma log2 e) >= 1/255 with sigma >= 0 holds exactly when
+// 0 <= sigma log2(e) <= log2(255 opacity), i.e. when the bits of sigma log2(e)
+// (a float >= +0, so ordered like its bits; a negative sigma has the sign bit
+// and fails) are below those of log2(255 opacity) plus one.  One unsigned
+// compare per pixel and entry replaces the two tests; below opacity 1/255
+// the bound is 0 and nothing passes.
 __device__ __forceinline__ void stage_conic(float4& a, float4& b) {
   a.z *= kHalfLog2e;
   a.w *= kLog2e;
   b.x *= kHalfLog2e;
+  const float t = __builtin_amdgcn_logf(b.y * (1.0f / LS_ALPHA_MIN));
+  b.w = __uint_as_float(t >= 0.f ? __float_as_uint(t) + 1u : 0u);
+}
+
+// Whether a staged splat (b from stage_conic) is composited at a pixel whose
+// sigma log2(e) is sl: alpha >= 1/255 and sigma >= 0, the test of both the
+// forward and the backward.
+__device__ __forceinline__ bool composited(float sl, const float4& b) {
+  return __float_as_uint(sl) < __float_as_uint(b.w);
 }
 
 // sigma log2(e) at pixel offset (dx, dy) from a staged conic, as

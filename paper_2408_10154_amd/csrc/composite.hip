@@ -311,7 +311,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
       const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
       const float Tn = T * (1.f - al);
-      const uint64_t hit = alive & __ballot(sl >= 0.f) & __ballot(al >= LS_ALPHA_MIN);
+      const uint64_t hit = alive & __ballot(composited(sl, b));
       const uint64_t stop = hit & __ballot(Tn < LS_T_STOP);
       const uint64_t use = hit & ~stop;
       if (stop != 0ull) {
@@ -484,7 +484,7 @@ __device__ __forceinline__ BwdEval bwd_eval(bool visited, float4 a, float4 b, fl
   e.ex = __builtin_amdgcn_exp2f(-sl);
   e.G = b.y * e.ex;
   e.al = fminf(LS_ALPHA_MAX, e.G);
-  e.act = visited && sl >= 0.f && e.al >= LS_ALPHA_MIN;
+  e.act = visited && composited(sl, b);
   return e;
 }
 
@@ -1060,9 +1060,7 @@ __global__ __launch_bounds__(kBlock) void k_render_stats(const JobDev* __restric
       const float4 b = s1[j];
       const float dx = fx - a.x, dy = fy - a.y;
       const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
-      if (sl < 0.f) continue;
-      const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
-      if (al >= LS_ALPHA_MIN) ++comp;
+      if (composited(sl, b)) ++comp;
     }
     __syncthreads();
   }
