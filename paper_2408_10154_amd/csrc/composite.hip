@@ -310,7 +310,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       const float dx = fx - a.x, dy = fy - a.y;
       const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
       const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
-      const float Tn = T * (1.f - al);
+      // the weight alpha T, and T (1 - alpha) as T - alpha T in one FMA
+      const float w = al * T, Tn = __builtin_fmaf(-al, T, T);
       const uint64_t hit = alive & __ballot(composited(sl, b));
       const uint64_t stop = hit & __ballot(Tn < LS_T_STOP);
       const uint64_t use = hit & ~stop;
@@ -320,7 +321,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       }
       if (use != 0ull) {
         const bool u = __builtin_amdgcn_inverse_ballot_w64(use);
-        const float wgt = u ? al * T : 0.f;  // 0 adds an exact zero below
+        const float wgt = u ? w : 0.f;  // 0 adds an exact zero below
         cr += wgt * col.x;
         cg += wgt * col.y;
         cb += wgt * col.z;
