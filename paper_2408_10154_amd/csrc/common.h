@@ -154,12 +154,14 @@ constexpr float kTwoLn2 = 1.38629436111989061883f;
 
 // The staged record also carries, in its free slot b.w, the bits of the
 // bound on sigma log2(e) within which the splat is composited: alpha =
-// opacity 2^(-sigma log2 e) >= 1/255 with sigma >= 0 holds exactly when
+// opacity 2^(-sigma log2 e) >= 1/255 with sigma >= 0 holds (in exact
+// arithmetic; in FP32 up to a few ulps of the threshold) when
 // 0 <= sigma log2(e) <= log2(255 opacity), i.e. when the bits of sigma log2(e)
 // (a float >= +0, so ordered like its bits; a negative sigma has the sign bit
 // and fails) are below those of log2(255 opacity) plus one.  One unsigned
-// compare per pixel and entry replaces the two tests; below opacity 1/255
-// the bound is 0 and nothing passes.
+// compare per pixel and entry replaces the two tests, and forward and
+// backward take the same decisions from the same staged bound; below
+// opacity 1/255 the bound is 0 and nothing passes.
 __device__ __forceinline__ void stage_conic(float4& a, float4& b) {
   a.z *= kHalfLog2e;
   a.w *= kLog2e;
