@@ -254,7 +254,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
     float bg1, float bg2, float* __restrict__ out_rgb, float* __restrict__ out_depth, float* __restrict__ out_alpha,
     float* __restrict__ out_T, int32_t* __restrict__ out_n, uint64_t* __restrict__ used, int64_t ustride,
     int cover) {
-  __shared__ float4 s0[64], s1[64], s2[64];
+  // one entry of padding: the walk reads entry j + 1 ahead without a clamp
+  __shared__ float4 s0[65], s1[65], s2[65];
   __shared__ int32_t spos[64];
   const int unit = xcd_remap(blockIdx.x, 4 * T_total);
   if (unit >= 4 * T_total) return;
@@ -305,7 +306,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       spos[pos] = e - start;
     }
     __builtin_amdgcn_wave_barrier();
-    const int cw = __popcll(bal);
+    int cwe = alive != 0ull ? __popcll(bal) : 0;
     auto step = [&](int j, const float4& a, const float4& b, const float4& col) {
       const float dx = fx - a.x, dy = fy - a.y;
       const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
@@ -318,6 +319,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       if (stop != 0ull) {
         if (__builtin_amdgcn_inverse_ballot_w64(stop)) nlast = spos[j];
         alive &= ~stop;
+        if (alive == 0ull) cwe = 0;  // every pixel stopped: the walk ends after this step
       }
       if (use != 0ull) {
         const bool u = __builtin_amdgcn_inverse_ballot_w64(use);
@@ -332,20 +334,20 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
     };
     // Records are read one entry ahead into two alternating register sets
     // (the loop unrolled by hand, so no copies), so the LDS latency of the
-    // next entry overlaps the arithmetic of this one.  With no entries, entry
-    // 0 is read and never used.
+    // next entry overlaps the arithmetic of this one; the read past the last
+    // staged entry (at most entry 64, the padding) is never used.  The walk
+    // ends at cwe: the staged count, or 0 once every pixel has stopped (set
+    // where pixels stop, so a step that stops none tests nothing).
     float4 aA = s0[0], bA = s1[0], cA = s2[0], aB, bB, cB;
-    for (int jj = 0; jj < cw && alive != 0ull;) {
-      const int jn = jj + 1 < cw ? jj + 1 : jj;
-      aB = s0[jn];
-      bB = s1[jn];
-      cB = s2[jn];
+    for (int jj = 0; jj < cwe;) {
+      aB = s0[jj + 1];
+      bB = s1[jj + 1];
+      cB = s2[jj + 1];
       step(jj, aA, bA, cA);
-      if (++jj >= cw || alive == 0ull) break;
-      const int jm = jj + 1 < cw ? jj + 1 : jj;
-      aA = s0[jm];
-      bA = s1[jm];
-      cA = s2[jm];
+      if (++jj >= cwe) break;
+      aA = s0[jj + 1];
+      bA = s1[jj + 1];
+      cA = s2[jj + 1];
       step(jj, aB, bB, cB);
       ++jj;
     }
