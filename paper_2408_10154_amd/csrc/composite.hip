@@ -306,8 +306,11 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       spos[pos] = e - start;
     }
     __builtin_amdgcn_wave_barrier();
-    int cwe = alive != 0ull ? __popcll(bal) : 0;
-    auto step = [&](int j, const float4& a, const float4& b, const float4& col) {
+    const int cw = __popcll(bal);
+    // one step at staged entry j; returns whether every pixel has now stopped
+    // (decided only where pixels stop, so a step that stops none tests nothing)
+    auto step = [&](int j, const float4& a, const float4& b, const float4& col) -> bool {
+      bool ended = false;
       const float dx = fx - a.x, dy = fy - a.y;
       const float sl = falloff_log2(a.z, a.w, b.x, dx, dy);
       const float al = fminf(LS_ALPHA_MAX, b.y * __builtin_amdgcn_exp2f(-sl));
@@ -319,7 +322,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
       if (stop != 0ull) {
         if (__builtin_amdgcn_inverse_ballot_w64(stop)) nlast = spos[j];
         alive &= ~stop;
-        if (alive == 0ull) cwe = 0;  // every pixel stopped: the walk ends after this step
+        ended = alive == 0ull;
       }
       if (use != 0ull) {
         const bool u = __builtin_amdgcn_inverse_ballot_w64(use);
@@ -329,26 +332,26 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(8))) void k_
         cb += wgt * col.z;
         dd += wgt * b.z;
         T = u ? Tn : T;
-        usedm |= 1ull << j;
+        // usedm |= 1 << j in one scalar instruction (a register-only bit set)
+        asm volatile("s_bitset1_b64 %0, %1" : "+s"(usedm) : "s"(j));
       }
+      return ended;
     };
     // Records are read one entry ahead into two alternating register sets
     // (the loop unrolled by hand, so no copies), so the LDS latency of the
     // next entry overlaps the arithmetic of this one; the read past the last
     // staged entry (at most entry 64, the padding) is never used.  The walk
-    // ends at cwe: the staged count, or 0 once every pixel has stopped (set
-    // where pixels stop, so a step that stops none tests nothing).
+    // ends after the staged entries or once every pixel has stopped.
     float4 aA = s0[0], bA = s1[0], cA = s2[0], aB, bB, cB;
-    for (int jj = 0; jj < cwe;) {
+    for (int jj = 0; jj < cw;) {
       aB = s0[jj + 1];
       bB = s1[jj + 1];
       cB = s2[jj + 1];
-      step(jj, aA, bA, cA);
-      if (++jj >= cwe) break;
+      if (step(jj, aA, bA, cA) || ++jj >= cw) break;
       aA = s0[jj + 1];
       bA = s1[jj + 1];
       cA = s2[jj + 1];
-      step(jj, aB, bB, cB);
+      if (step(jj, aB, bB, cB)) break;
       ++jj;
     }
     // the entries of this chunk that some pixel of the band composited
