@@ -154,19 +154,22 @@ __global__ __launch_bounds__(256) void k_scan_rows(uint32_t* __restrict__ data, 
   if (threadIdx.x == 0) totals[blockIdx.x] = tot;
 }
 
-// Stable scatter of one kBits-bit digit pass.  Each block loads all its
-// items at once, then
-//  - turns the digit totals into global digit bases (a block-wide scan,
-//    cheaper than a launch of its own) plus its scanned row entries, and its
-//    own digit counts (differences of neighbouring row entries) into local
-//    digit bases;
-//  - takes its items in rounds of 256 in index order and places each in LDS
-//    at its digit's running local base + the count of equal digits in earlier
-//    waves of the round + its rank among equal digits in its own wave (ballot
-//    matching).  Only the one leader lane per (wave, digit) present writes a
-//    count, adds it to the base and clears it again, so a round costs work in
-//    proportion to its items, not to the number of digits;
-//  - writes the block's items out in LDS order: item i of digit d goes to
+// Stable scatter of one kBits-bit digit pass.  The block's keys (rounds x
+// 256 consecutive positions) are split into four consecutive quarters, one
+// per wave, each taken 64 at a time in order:
+//  - every wave ranks its own keys alone: per 64 keys, a ballot match gives
+//    each key its rank among equal digits, and the wave's running count of
+//    that digit (its own LDS row) the number of earlier ones; the leader of
+//    each digit present adds the group's count.  No barrier until the wave
+//    has ranked all its keys;
+//  - one thread per digit then turns the four wave counts into the digit's
+//    place in LDS order (digits ascending, then waves in order) and its
+//    global run start (the scanned histogram entry plus the digit totals'
+//    block-wide scan);
+//  - each key goes to LDS at its wave's base for its digit plus its rank, so
+//    LDS holds the block's keys ordered by digit and, within a digit, by
+//    position: the pass is stable;
+//  - the block writes its keys out in LDS order: item i of digit d goes to
 //    global base(d) - local base(d) + i, so neighbouring threads write
 //    neighbouring addresses along each digit's run.
 template <int kBits>
@@ -179,40 +182,66 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
   constexpr int kBins = 1 << kBits;
   constexpr int kPer = kBins >= kSortThreads ? kBins / kSortThreads : 1;  // digits per thread in the set-up
   static_assert(kBins % kSortThreads == 0 || kSortThreads % kBins == 0, "digits and threads must divide");
-  __shared__ uint32_t base[kBins];   // running local position of each digit
-  __shared__ uint32_t delta[kBins];  // global minus local start of each digit's run (mod 2^32)
-  __shared__ uint32_t wcnt[4][kBins];
+  static_assert(kSortThreads == 256, "four waves per block");
+  __shared__ uint32_t wcnt[4][kBins];  // per wave: running count of each digit, then the wave's LDS base for it
+  __shared__ uint32_t delta[kBins];    // global minus local start of each digit's run (mod 2^32)
   __shared__ uint32_t wsum[4];
   __shared__ uint32_t sk[kSortTile], sv[kSortTile];
   const int n = sort_count(n_dev, n_static, cap);
   const int64_t bbase = (int64_t)blockIdx.x * rounds * kSortThreads;
   if (bbase >= n) return;  // uniform for the block
   const int nb = (int)min((int64_t)rounds * kSortThreads, (int64_t)n - bbase);
-  const int nact = active_blocks(n, rounds);  // blocks with histogram columns
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  uint32_t key[kSortItems], val[kSortItems];
+  const int wpos = w * rounds * 64;  // the wave's first position in the block
+  uint32_t key[kSortItems], val[kSortItems], rk[kSortItems];
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    const int i = r * kSortThreads + tid;
+    const int i = wpos + r * 64 + lane;
     const bool ok = r < rounds && i < nb;
     key[r] = ok ? kin[bbase + i] : 0u;
     val[r] = ok ? vin[bbase + i] : 0u;
+    rk[r] = 0u;
   }
+  for (int d = lane; d < kBins; d += 64) wcnt[w][d] = 0u;
+  __builtin_amdgcn_wave_barrier();
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+  for (int r = 0; r < kSortItems; ++r) {
+    if (r < rounds && wpos + r * 64 < nb) {  // uniform for the wave; a guard, not a break, so the loop unrolls
+      const bool valid = wpos + r * 64 + lane < nb;
+      const uint32_t d = (key[r] >> shift) & (uint32_t)(kBins - 1);
+      uint64_t peers = __ballot(valid);
+#pragma unroll
+      for (int b = 0; b < kBits; ++b) {
+        const bool bit = (d >> b) & 1u;
+        const uint64_t m = __ballot(bit);
+        peers &= bit ? m : ~m;
+      }
+      const uint32_t rank = (uint32_t)__popcll(peers & lt);
+      const uint32_t before = valid ? wcnt[w][d] : 0u;
+      rk[r] = before + rank;
+      if (valid && rank == 0) wcnt[w][d] = before + (uint32_t)__popcll(peers);
+      __builtin_amdgcn_wave_barrier();
+    }
+  }
+  __syncthreads();
   {
     // threads 0 .. kBins / kPer - 1 hold kPer digits each (fewer digits than
     // threads: the other threads add zeros to the scans)
     const bool has = tid * kPer < kBins;
-    uint32_t tot[kPer], cnt[kPer], here[kPer];
+    uint32_t tot[kPer], cnt[kPer], here[kPer], c0[kPer], c1[kPer], c2[kPer];
     uint32_t gsum = 0, lsum = 0;
 #pragma unroll
     for (int k = 0; k < kPer; ++k) {
       const int d = tid * kPer + k;
-      tot[k] = cnt[k] = here[k] = 0u;
+      tot[k] = cnt[k] = here[k] = c0[k] = c1[k] = c2[k] = 0u;
       if (has) {
+        c0[k] = wcnt[0][d];
+        c1[k] = wcnt[1][d];
+        c2[k] = wcnt[2][d];
+        cnt[k] = c0[k] + c1[k] + c2[k] + wcnt[3][d];
         here[k] = hist[(int64_t)d * nblocks + blockIdx.x];
         tot[k] = digit_total[d];
-        const uint32_t next = (int)blockIdx.x + 1 < nact ? hist[(int64_t)d * nblocks + blockIdx.x + 1] : tot[k];
-        cnt[k] = next - here[k];
       }
       gsum += tot[k];
       lsum += cnt[k];
@@ -224,49 +253,27 @@ __global__ __launch_bounds__(kSortThreads) void k_sort_scatter(const uint32_t* _
 #pragma unroll
       for (int k = 0; k < kPer; ++k) {
         const int d = tid * kPer + k;
-        base[d] = lrun;
         delta[d] = grun + here[k] - lrun;
+        wcnt[0][d] = lrun;
+        wcnt[1][d] = lrun + c0[k];
+        wcnt[2][d] = lrun + c0[k] + c1[k];
+        wcnt[3][d] = lrun + c0[k] + c1[k] + c2[k];
         grun += tot[k];
         lrun += cnt[k];
-        wcnt[0][d] = wcnt[1][d] = wcnt[2][d] = wcnt[3][d] = 0u;
       }
     }
   }
   __syncthreads();
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
   for (int r = 0; r < kSortItems; ++r) {
-    if (r < rounds && r * kSortThreads < nb) {  // uniform; a guard, not a break, so the loop unrolls
-      const bool valid = r * kSortThreads + tid < nb;
+    if (r < rounds && wpos + r * 64 + lane < nb) {
       const uint32_t d = (key[r] >> shift) & (uint32_t)(kBins - 1);
-      uint64_t peers = __ballot(valid);
-#pragma unroll
-      for (int b = 0; b < kBits; ++b) {
-        const bool bit = (d >> b) & 1u;
-        const uint64_t m = __ballot(bit);
-        peers &= bit ? m : ~m;
-      }
-      const uint32_t rank = (uint32_t)__popcll(peers & lt);
-      const bool leader = valid && rank == 0;
-      const uint32_t c = (uint32_t)__popcll(peers);
-      if (leader) wcnt[w][d] = c;
-      __syncthreads();
-      if (valid) {
-        uint32_t pos = base[d] + rank;
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          if (k < w) pos += wcnt[k][d];
-        sk[pos] = key[r];
-        sv[pos] = val[r];
-      }
-      __syncthreads();
-      if (leader) {
-        atomicAdd(&base[d], c);
-        wcnt[w][d] = 0u;
-      }
-      __syncthreads();
+      const uint32_t pos = wcnt[w][d] + rk[r];
+      sk[pos] = key[r];
+      sv[pos] = val[r];
     }
   }
+  __syncthreads();
   for (int i = tid; i < nb; i += kSortThreads) {
     const uint32_t k = sk[i];
     const uint32_t pos = delta[(k >> shift) & (uint32_t)(kBins - 1)] + (uint32_t)i;
